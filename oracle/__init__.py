@@ -1,0 +1,33 @@
+"""CPU FP64 oracle for the purified-MPS Lindblad step.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import anything from this package.
+The GPU library never calls it and shares no code with it; the only shared
+module is ``workload`` (seeded inputs, no arithmetic of the method).
+
+Three levels, each a plain NumPy/LAPACK implementation in float64/complex128:
+
+* ``oracle.dense``  -- Oracle-D: dense density matrix, RK4 on the Lindblad
+  equation (paper Eq. lindblad, RK4 stages of Sec. 3.1.1).
+  Oracle-K: the dense second-order Kraus map and its purified form
+  (paper Sec. 5.2, Kraus maps U, U', first/second-order schemes).
+* ``oracle.tt``     -- quantics tensor trains: TT-SVD of dense vectors and
+  per-mode operators, MPO algebra (sum, product, dagger, compression) and the
+  stacked Kraus-family MPO (paper Sec. 2.1-2.2, Sec. 5.1 matrix addition).
+* ``oracle.mps``    -- Oracle-M: the purified-MPS step (zip-up apply,
+  purification truncation, truncated-SVD back-sweep, renormalisation) and
+  observables by transfer matrices.
+
+Pins (``tests/test_oracle_*.py``, marked ``not gpu``): closed forms for a
+coherent state and a Fock state under loss, RK4 order 4 / Kraus order 2
+convergence, Taylor-2 propagator for the jump-free rank-1 case, identity for
+H = 0 and no jumps, the two-photon-pumped even-cat steady state, trace and
+positivity invariants, exact polynomial MPO ranks (paper Table I, exact row),
+and brute-force agreement of the MPS step with the dense Kraus map on small
+Hilbert spaces.
+
+Parity unpinned: the zip-up truncation inside Oracle-M is not compared to
+any closed form when it is active (it is an approximation with no exact
+target); it is pinned only in the regime where it is inactive (brute force)
+and by the invariants.
+"""

@@ -1,0 +1,176 @@
+"""Oracle-M: the purified-MPS second-order Kraus step on the CPU (complex128).
+
+State: X = A_1 ... A_L with A_i[chi_{i-1}, 2, chi_i], chi_0 = 1 and chi_L the
+purification rank (paper Sec. 4.1 purification rho = Psi Psi^dag, Sec. 4.2-4.3:
+the purification tensor sits at the end of the chain, here as the open right
+bond of the last quantics site).  Between steps X is right-canonical with the
+orthogonality centre on site 1.
+
+One step (paper Sec. 5.2 with the compression of Sec. 5.1):
+  S1  zip-up application of the stacked Kraus MPO W (paper Sec. 3.1.1 cites
+      zip-up for MPO.MPS): for i = 1..L-1, T = C_{i-1} A_i W_i reshaped
+      (chi' 2) x (chi_i w_i), truncated SVD T = U S V^dag with (tol/10, chi),
+      new site U, carry C_i = S V^dag.
+  S2  at the last site the columns are (purification mu, Kraus index): the SVD
+      keeps k <= chi_mu by (tol, chi_mu); new last site U S, V^dag dropped
+      (a unitary on the purification index leaves X X^dag unchanged).
+  S3  right-to-left truncated-SVD sweep with (tol, chi): A_i -> V^dag, U S is
+      absorbed into A_{i-1}.
+  S4  tau = ||A_1||_F^2 (= Tr of the step's output); A_1 /= sqrt(tau).
+Truncation rule: keep the smallest k >= 1 whose discarded squared singular
+values sum to at most tol^2 times the total, then cap.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .tt import keep_rank, mode_blocks, reverse_chain, svd, vector_to_mps
+
+
+@dataclass
+class StepInfo:
+    tau: float = 1.0
+    zip_bonds: list = field(default_factory=list)
+    bonds: list = field(default_factory=list)
+    chi_mu: int = 1
+    discarded: list = field(default_factory=list)
+
+
+def product_state(vectors, bits, site_order, tol: float = 1e-14) -> list[np.ndarray]:
+    """MPS of a product of per-mode amplitude vectors in the given site order,
+    with a purification bond of size 1; not yet canonical."""
+    blocks = mode_blocks(site_order, len(bits))
+    sites: list = [None] * len(site_order)
+    for m, (start, length, msb) in enumerate(blocks):
+        cores = vector_to_mps(np.asarray(vectors[m], complex), tol)
+        sites[start:start + length] = cores if msb else reverse_chain(cores)
+    return sites
+
+
+def right_canonicalize(sites, tol: float = 0.0, cap: int | None = None):
+    """Right-to-left SVD sweep; returns (sites, norm^2) with the centre on site 1
+    normalised to unit Frobenius norm."""
+    s = [x.copy() for x in sites]
+    for i in range(len(s) - 1, 0, -1):
+        l, d, r = s[i].shape
+        u, sv, vh = svd(s[i].reshape(l, d * r))
+        k = keep_rank(sv, tol, cap) if tol > 0 or cap is not None else \
+            int(np.sum(sv > 0)) or 1
+        s[i] = vh[:k].reshape(k, d, r)
+        s[i - 1] = np.einsum('asb,bk->ask', s[i - 1], u[:, :k] * sv[None, :k])
+    nrm2 = float(np.vdot(s[0], s[0]).real)
+    s[0] = s[0] / np.sqrt(nrm2)
+    return s, nrm2
+
+
+def zipup(sites, W, tol_zip: float, chi_zip: int, tol: float, chi_mu: int, info: StepInfo):
+    """S1 + S2: apply the stacked Kraus MPO W by zip-up."""
+    L = len(sites)
+    out = []
+    C = np.ones((1, 1, 1), complex)          # C[a', a, u]
+    for i in range(L):
+        A = sites[i]                         # A[a, s, b]
+        w = W[i]                             # w[u, s', s, v]
+        T = np.einsum('xau,asb,uzsv->xzbv', C, A, w, optimize=True)
+        ap, _, b, v = T.shape
+        M = T.reshape(ap * 2, b * v)
+        u, s, vh = svd(M)
+        if i < L - 1:
+            k = keep_rank(s, tol_zip, chi_zip)
+            out.append(u[:, :k].reshape(ap, 2, k))
+            C = (s[:k, None] * vh[:k]).reshape(k, b, v)
+            info.zip_bonds.append(k)
+        else:
+            k = keep_rank(s, tol, chi_mu)
+            out.append((u[:, :k] * s[None, :k]).reshape(ap, 2, k))
+            info.chi_mu = k
+            total = float(np.sum(s ** 2))
+            info.discarded.append(float(np.sum(s[k:] ** 2)) / total if total > 0 else 0.0)
+    return out
+
+
+def back_sweep(sites, tol: float, chi: int, info: StepInfo):
+    """S3: right-to-left truncated SVDs; leaves sites 2..L right-orthonormal."""
+    s = list(sites)
+    bonds = [0] * (len(s) - 1)
+    for i in range(len(s) - 1, 0, -1):
+        l, d, r = s[i].shape
+        u, sv, vh = svd(s[i].reshape(l, d * r))
+        k = keep_rank(sv, tol, chi)
+        s[i] = vh[:k].reshape(k, d, r)
+        s[i - 1] = np.einsum('asb,bk->ask', s[i - 1], u[:, :k] * sv[None, :k])
+        bonds[i - 1] = k
+        total = float(np.sum(sv ** 2))
+        info.discarded.append(float(np.sum(sv[k:] ** 2)) / total if total > 0 else 0.0)
+    info.bonds = bonds
+    return s
+
+
+def k2_step(sites, W, tol: float, chi: int, chi_mu: int,
+            tol_zip: float | None = None, chi_zip: int | None = None):
+    """One purified-MPS Kraus step (S1-S4).  Returns (sites', StepInfo)."""
+    info = StepInfo()
+    tz = tol / 10.0 if tol_zip is None else tol_zip
+    cz = chi if chi_zip is None else chi_zip
+    s = zipup(sites, W, tz, cz, tol, chi_mu, info)
+    s = back_sweep(s, tol, chi, info)
+    tau = float(np.vdot(s[0], s[0]).real)
+    s[0] = s[0] / np.sqrt(tau)
+    info.tau = tau
+    return s, info
+
+
+# ---------------------------------------------------------------------------
+# observables by transfer matrices
+# ---------------------------------------------------------------------------
+
+def expect(sites, O) -> complex:
+    """Tr(O rho) = sum_mu <X_mu|O|X_mu> (O an MPO with unit boundary dims)."""
+    E = np.ones((1, 1, 1), complex)          # E[a*, u, a]
+    for A, w in zip(sites, O):
+        E = np.einsum('xua,xzb,uzsv,asc->bvc', E, A.conj(), w, A, optimize=True)
+    return complex(np.einsum('bvb->', E))
+
+
+def gram(sites, other=None) -> np.ndarray:
+    """(X^dag Y)_{mu nu} over the physical indices (Y = X by default)."""
+    Y = sites if other is None else other
+    E = np.ones((1, 1), complex)
+    for A, B in zip(sites, Y):
+        E = np.einsum('xa,xsb,asc->bc', E, A.conj(), B, optimize=True)
+    return E
+
+
+def trace(sites) -> float:
+    return float(np.trace(gram(sites)).real)
+
+
+def purity(sites) -> float:
+    g = gram(sites)
+    return float(np.sum(np.abs(g) ** 2) / np.trace(g).real ** 2)
+
+
+def rho_distance2(x1, x2) -> float:
+    """||X1 X1^dag - X2 X2^dag||_F^2 from overlaps with open purification legs."""
+    a = np.sum(np.abs(gram(x1)) ** 2)
+    b = np.sum(np.abs(gram(x2)) ** 2)
+    c = np.sum(np.abs(gram(x1, x2)) ** 2)
+    return float(a + b - 2 * c)
+
+
+def to_dense(sites, bits, site_order) -> np.ndarray:
+    """X as a D x chi_mu matrix, mode 0 most significant (small sizes only)."""
+    t = sites[0]
+    for A in sites[1:]:
+        t = np.tensordot(t, A, axes=([t.ndim - 1], [0]))
+    t = t.reshape(t.shape[1:])               # (s1, ..., sL, mu)
+    L = len(site_order)
+    std = sorted(range(L), key=lambda i: (site_order[i][0], site_order[i][1]))
+    t = t.transpose(std + [L])
+    return t.reshape(1 << L, -1)
+
+
+def bond_dims(sites) -> list[int]:
+    return [A.shape[2] for A in sites[:-1]]

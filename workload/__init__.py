@@ -1,0 +1,258 @@
+"""Seeded synthetic workloads shared by the tests, the benchmark and the oracle.
+
+This module holds *inputs only*: physical parameters of the studied models,
+operator descriptions as plain data (sums of products of named single-mode
+factors), seeded random numbers and initial-state amplitudes.  It contains
+none of the method's arithmetic (no MPO/MPS construction, no time stepping,
+no factorisation); the oracle and the GPU library each interpret these
+descriptions with their own code.
+
+Operator description
+--------------------
+An operator is a list of terms ``(coef, factors)`` where ``factors`` maps a
+mode index to a factor ``(kind, args)``.  Kinds (matching ``lb_factor_kind``
+in ``include/lindblad.h``):
+
+* ``"ID"``                      identity
+* ``("A_POW", p)``              a^p,           <n|a^p|n'> = d(n+p,n') sqrt(n'!/n!)
+* ``("ADAG_POW", p)``           (a^dagger)^p
+* ``("ADAG_A", p, q)``          (a^dagger)^p a^q (normal ordered)
+* ``("NUM_POW", p)``            diag(n^p), n = 0..N-1
+* ``("CHARGE_POW", p, off)``    diag((n-off)^p)   (charge basis, offset binary)
+* ``("SHIFT", k)``              (T_k)_{n,n'} = d(n+k, n'), open boundary
+
+The quantics index of a mode with R bits is n = sum_i 2^(R-i) sigma_i with
+sigma_1 the most significant bit (paper, Sec. 2.1, quantics encoding).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEED = 20261203
+
+# --------------------------------------------------------------------------
+# model descriptions
+# --------------------------------------------------------------------------
+
+
+@dataclass
+class Model:
+    """A Lindblad problem: H(t) = H0 + f(t) H1, jumps L_k, initial product state."""
+
+    name: str
+    bits: list[int]                      # R per mode (N = 2^R)
+    H0: list = field(default_factory=list)
+    H1: list = field(default_factory=list)     # optional drive operator
+    drive: list = field(default_factory=list)  # f(t) = sum c cos(w t + phi): (c, w, phi)
+    jumps: list = field(default_factory=list)  # list of operator descriptions
+    init: list = field(default_factory=list)   # per-mode dense amplitude vectors
+    dt: float = 1e-3
+    steps: int = 100
+    chi: int = 16
+    chi_mu: int = 4
+    tol: float = 1e-8
+
+    @property
+    def n_modes(self) -> int:
+        return len(self.bits)
+
+    @property
+    def dims(self) -> list[int]:
+        return [1 << r for r in self.bits]
+
+    def site_order(self) -> list[tuple[int, int]]:
+        """Default site order: (mode, bit) with bit 0 = most significant digit.
+
+        One mode: [sigma_R ... sigma_1] then the purification bond.
+        Two modes: [a: sigma_R ... sigma_1][b: sigma_1 ... sigma_R], so both
+        most significant digits face the inter-mode bond (paper, Sec. 4.3).
+        """
+        return default_site_order(self.bits)
+
+
+def default_site_order(bits: list[int]) -> list[tuple[int, int]]:
+    order: list[tuple[int, int]] = []
+    for m, r in enumerate(bits):
+        if m == 0:
+            order += [(0, b) for b in reversed(range(r))]
+        else:
+            order += [(m, b) for b in range(r)]
+    return order
+
+
+def coherent_amplitudes(n_levels: int, alpha: complex) -> np.ndarray:
+    """c_n = exp(-|alpha|^2/2) alpha^n / sqrt(n!), n < N, renormalised."""
+    n = np.arange(n_levels)
+    logmag = -0.5 * abs(alpha) ** 2 + n * math.log(abs(alpha) if alpha != 0 else 1.0) \
+        - 0.5 * np.array([math.lgamma(k + 1.0) for k in n])
+    c = np.exp(logmag).astype(complex)
+    if alpha == 0:
+        c[:] = 0.0
+        c[0] = 1.0
+    else:
+        c *= np.exp(1j * np.angle(alpha) * n)
+    return c / np.linalg.norm(c)
+
+
+def fock_amplitudes(n_levels: int, m: int) -> np.ndarray:
+    c = np.zeros(n_levels, complex)
+    c[m] = 1.0
+    return c
+
+
+def vacuum(n_levels: int) -> np.ndarray:
+    return fock_amplitudes(n_levels, 0)
+
+
+# ---- the five workloads -----------------------------------------------------
+
+def model_coherent_loss(R: int = 4, delta: float = 1.0, kappa: float = 1.0,
+                        alpha: complex = 2.0, dt: float = 0.01, steps: int = 100,
+                        chi: int = 16, chi_mu: int = 4) -> Model:
+    """Single mode, H = Delta a^dag a, L = sqrt(kappa) a, coherent start."""
+    return Model(
+        name="coherent-loss",
+        bits=[R],
+        H0=[(delta, {0: ("NUM_POW", 1)})],
+        jumps=[[(math.sqrt(kappa), {0: ("A_POW", 1)})]],
+        init=[coherent_amplitudes(1 << R, alpha)],
+        dt=dt, steps=steps, chi=chi, chi_mu=chi_mu)
+
+
+def model_two_photon_cat(R: int = 8, alpha2: float = 8.0, kappa2: float = 1.0,
+                         kappa1: float = 1e-3, dt: float = 5e-5, steps: int = 5000,
+                         chi: int = 64, chi_mu: int = 8) -> Model:
+    """H = 0, L2 = sqrt(k2)(a^2 - alpha^2), L1 = sqrt(k1) a, vacuum start."""
+    s2 = math.sqrt(kappa2)
+    jumps = [[(s2, {0: ("A_POW", 2)}), (-s2 * alpha2, {0: "ID"})]]
+    if kappa1 > 0:
+        jumps.append([(math.sqrt(kappa1), {0: ("A_POW", 1)})])
+    return Model(name="two-photon-cat", bits=[R], H0=[], jumps=jumps,
+                 init=[vacuum(1 << R)], dt=dt, steps=steps, chi=chi, chi_mu=chi_mu)
+
+
+def model_cat_buffer(Ra: int = 8, Rb: int = 8, alpha2: float = 8.0, g2: float = 1.0,
+                     kappa_b: float = 10.0, kappa_a: float = 1e-3, dt: float = 2.5e-5,
+                     steps: int = 200, chi: int = 128, chi_mu: int = 16) -> Model:
+    """Cat mode a + lossy buffer b (paper Sec. 5, Eq. cb):
+    H = g2 (a^dag^2 b + a^2 b^dag) + eps_d (b + b^dag), eps_d = -alpha^2 g2,
+    L_b = sqrt(kappa_b) b, L_a = sqrt(kappa_a) a; vacuum x vacuum start."""
+    eps_d = -alpha2 * g2
+    H0 = [(g2, {0: ("ADAG_POW", 2), 1: ("A_POW", 1)}),
+          (g2, {0: ("A_POW", 2), 1: ("ADAG_POW", 1)}),
+          (eps_d, {1: ("A_POW", 1)}),
+          (eps_d, {1: ("ADAG_POW", 1)})]
+    jumps = [[(math.sqrt(kappa_b), {1: ("A_POW", 1)})]]
+    if kappa_a > 0:
+        jumps.append([(math.sqrt(kappa_a), {0: ("A_POW", 1)})])
+    return Model(name="cat-buffer", bits=[Ra, Rb], H0=H0, jumps=jumps,
+                 init=[vacuum(1 << Ra), vacuum(1 << Rb)], dt=dt, steps=steps,
+                 chi=chi, chi_mu=chi_mu)
+
+
+def model_transmon_resonator(Rt: int = 10, Rr: int = 12, ej_over_ec: float = 50.0,
+                             ng: float = 0.25, omega_r: float = 30.0, g: float = 0.5,
+                             eps: float = 2.0, omega_d: float = 30.0, kappa: float = 0.05,
+                             dt: float = 1.5e-7, steps: int = 200, chi: int = 256,
+                             chi_mu: int = 32, init_t: np.ndarray | None = None) -> Model:
+    """Transmon in the charge basis (offset binary, n = q - 2^(Rt-1)) coupled to a
+    resonator (paper Sec. 6, Eq. transmon_cavity with the readout drive written
+    as eps cos(w_d t)(a + a^dag)); E_C = 1 units.
+
+    H0 = 4 (n - ng)^2 - E_J cos(phi) + w_r a^dag a + i g n (a^dag - a)
+    H1 = eps (a + a^dag),  f(t) = cos(w_d t),  L = sqrt(kappa) a.
+    cos(phi) = (T_1 + T_-1)/2 with open shifts.
+    """
+    off = 1 << (Rt - 1)
+    ej = ej_over_ec
+    H0 = [(4.0, {0: ("CHARGE_POW", 2, off)}),
+          (-8.0 * ng, {0: ("CHARGE_POW", 1, off)}),
+          (4.0 * ng * ng, {0: "ID"}),
+          (-0.5 * ej, {0: ("SHIFT", 1)}),
+          (-0.5 * ej, {0: ("SHIFT", -1)}),
+          (omega_r, {1: ("NUM_POW", 1)}),
+          (1j * g, {0: ("CHARGE_POW", 1, off), 1: ("ADAG_POW", 1)}),
+          (-1j * g, {0: ("CHARGE_POW", 1, off), 1: ("A_POW", 1)})]
+    H1 = [(eps, {1: ("A_POW", 1)}), (eps, {1: ("ADAG_POW", 1)})]
+    jumps = [[(math.sqrt(kappa), {1: ("A_POW", 1)})]]
+    Nt = 1 << Rt
+    if init_t is None:
+        init_t = np.zeros(Nt, complex)
+        init_t[off] = 1.0          # charge state n = 0
+    return Model(name="transmon-resonator", bits=[Rt, Rr], H0=H0, H1=H1,
+                 drive=[(1.0, omega_d, 0.0)], jumps=jumps,
+                 init=[init_t, vacuum(1 << Rr)], dt=dt, steps=steps, chi=chi,
+                 chi_mu=chi_mu)
+
+
+# --------------------------------------------------------------------------
+# synthetic saturated state (timing workloads)
+# --------------------------------------------------------------------------
+
+def saturated_bonds(n_sites: int, chi_mu: int, chi: int, d: int = 2) -> list[int]:
+    """Bond dims b_0..b_L with b_i = min(d^i, d^(L-i) chi_mu, chi), b_0 = 1, b_L = chi_mu."""
+    b = [min(d ** i, d ** (n_sites - i) * chi_mu, chi) for i in range(n_sites + 1)]
+    b[0] = 1
+    b[-1] = chi_mu
+    return b
+
+
+def synthetic_mps(n_sites: int, chi_mu: int, chi: int, decay: float = 0.93,
+                  seed: int = SEED) -> list[np.ndarray]:
+    """Raw (not canonical) random site tensors A_i[b_{i-1}, 2, b_i].
+
+    Entries are i.i.d. complex Gaussian from PCG64(seed); the right bond
+    index j of every site is scaled by decay^j so that after canonicalisation
+    the Schmidt spectra decay roughly geometrically and a 1e-8 tolerance keeps
+    the caps.  Canonicalisation and normalisation are the consumer's job.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    b = saturated_bonds(n_sites, chi_mu, chi)
+    sites = []
+    for i in range(n_sites):
+        g = (rng.standard_normal((b[i], 2, b[i + 1]))
+             + 1j * rng.standard_normal((b[i], 2, b[i + 1]))) / math.sqrt(2.0)
+        g *= (decay ** np.arange(b[i + 1]))[None, None, :]
+        sites.append(np.ascontiguousarray(g))
+    return sites
+
+
+def random_matrix(m: int, n: int, seed: int = SEED, spectrum: np.ndarray | None = None):
+    """Seeded complex Gaussian m x n matrix; with ``spectrum`` given, the matrix
+    U diag(spectrum) V^H built from seeded random unitaries (Haar via QR)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    g = (rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))) / math.sqrt(2.0)
+    if spectrum is None:
+        return g
+    k = len(spectrum)
+    qa, ra = np.linalg.qr((rng.standard_normal((m, k)) + 1j * rng.standard_normal((m, k))))
+    qb, rb = np.linalg.qr((rng.standard_normal((n, k)) + 1j * rng.standard_normal((n, k))))
+    qa = qa * (np.diag(ra) / np.abs(np.diag(ra)))[None, :]
+    qb = qb * (np.diag(rb) / np.abs(np.diag(rb)))[None, :]
+    return (qa * np.asarray(spectrum)[None, :]) @ qb.conj().T
+
+
+def serving_requests(n: int = 512, seed: int = SEED) -> list[dict]:
+    """Parameter-sweep solve requests: uniform over the three model families with
+    the parameter ranges of the serving workload; arrival order is the list order."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(n):
+        fam = int(rng.integers(0, 3))
+        if fam == 0:
+            out.append(dict(family="two-photon-cat", R=int(rng.integers(6, 9)),
+                            alpha2=float(rng.uniform(2, 16)),
+                            chi=int(rng.choice([32, 64])), chi_mu=8, steps=100))
+        elif fam == 1:
+            out.append(dict(family="cat-buffer", R=int(rng.integers(6, 9)),
+                            alpha2=float(rng.uniform(4, 12)),
+                            chi=int(rng.choice([32, 64, 128])), chi_mu=16, steps=100))
+        else:
+            out.append(dict(family="transmon-resonator", Rt=int(rng.integers(6, 11)),
+                            Rr=int(rng.integers(6, 13)), eps=float(rng.uniform(0, 5)),
+                            ng=float(rng.uniform(0, 0.5)),
+                            chi=int(rng.choice([32, 64, 128, 256])), chi_mu=32, steps=100))
+    return out
