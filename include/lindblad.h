@@ -1,0 +1,237 @@
+/*
+ * lindblad.h -- C ABI of the MI355X purified-MPS Lindblad solver.
+ *
+ * What it computes.  The density matrix of a few bosonic modes is kept as a
+ * purification rho = X X^dagger (paper Sec. 4.1).  X is a matrix product
+ * state whose sites are the binary digits of each mode's Fock (or charge)
+ * index (quantics encoding, paper Sec. 2.1) and whose last site carries the
+ * purification index as its open right bond (paper Sec. 4.2: the
+ * purification tensor may sit anywhere in the chain).  One time step applies
+ * the second-order Kraus map of paper Sec. 5.2.2,
+ *     K(rho) = U1' rho U1'^dag + (h/2) sum_k (U1 L_k rho L_k^dag U1^dag
+ *              + L_k U1 rho U1^dag L_k^dag) + (h^2/2) sum_kk' L_k L_k' rho ...^dag,
+ *     U1 = 1 - i h H_eff,  U1' = U1 - (h^2/2) H_eff^2,
+ *     H_eff = H - (i/2) sum_k L_k^dag L_k,
+ * as one MPO applied to X, recompresses it by truncated SVDs that cap the
+ * bond dimension and the purification rank, and renormalises the trace
+ * (end of paper Sec. 5.2.2).
+ *
+ * Conventions shared by every call.
+ *  - Complex numbers are interleaved (re, im) pairs of double.
+ *  - "host" pointers are ordinary CPU memory, owned by the caller and only
+ *    read (or written, for outputs) during the call; the library copies what
+ *    it keeps.
+ *  - A mode with R bits has N = 2^R levels, index n = sum_i 2^(R-i) sigma_i.
+ *  - Every call returns an lb_status; on failure lindblad_last_error() gives
+ *    a message (thread-local, valid until the next failing call on the same
+ *    thread).  No C++ exception crosses this boundary.
+ *  - One solver must not be used from two threads at once; distinct solvers
+ *    may be used concurrently.
+ *  - Device work is enqueued on the solver's HIP stream; lindblad_step is
+ *    asynchronous with respect to the host except where noted.
+ */
+#ifndef LINDBLAD_H
+#define LINDBLAD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LB_MAX_MODES 8
+#define LB_MAX_SITES 64
+
+typedef enum lb_status {
+  LB_OK = 0,
+  LB_ERR_ARG = -1,      /* invalid argument (null pointer, size out of range) */
+  LB_ERR_OOM = -2,      /* device memory (or the caller's arena) exhausted     */
+  LB_ERR_HIP = -3,      /* a HIP runtime call failed                           */
+  LB_ERR_NUMERIC = -4,  /* non-finite values or a factorisation did not converge */
+  LB_ERR_UNSTABLE = -5, /* dt violates the explicit-scheme stability estimate   */
+  LB_ERR_STATE = -6,    /* call order violated (e.g. step before set_generator) */
+  LB_WARN_UNSTABLE = 1  /* step done, but the pre-normalisation trace drifted   */
+} lb_status;
+
+enum lb_precision {
+  LB_FP64 = 0,          /* every contraction in complex128                       */
+  LB_FP32_CONTRACT = 1  /* MPO/MPS contractions in complex64 (FP32 accumulate);
+                           Gram matrices, eigen-decompositions, truncation
+                           weights and trace in FP64                            */
+};
+
+typedef struct lb_config {
+  int32_t n_modes;                 /* 1..LB_MAX_MODES                            */
+  int32_t bits[LB_MAX_MODES];      /* R per mode, 1..14                          */
+  int32_t n_sites;                 /* 0: default site order; else sum(bits)      */
+  int32_t site_order[LB_MAX_SITES][2]; /* (mode, bit), bit 0 = most significant;
+                                      each mode contiguous, MSB- or LSB-first   */
+  int32_t chi_cap;                 /* bond dimension cap chi                     */
+  int32_t chi_mu_cap;              /* purification rank cap                      */
+  int32_t chi_zip_cap;             /* zip-up intermediate cap; 0 = chi_cap       */
+  double tol;                      /* relative Frobenius truncation tolerance    */
+  double tol_zip;                  /* zip-up tolerance; <= 0 means tol / 10      */
+  int32_t order;                   /* Kraus scheme order: 1 or 2                 */
+  int32_t precision;               /* enum lb_precision                          */
+  int32_t allow_unstable;          /* nonzero: skip the dt stability check       */
+  void* stream;                    /* hipStream_t to use; NULL = a private stream */
+  int32_t device;                  /* HIP device ordinal                         */
+} lb_config;
+
+typedef struct lb_solver lb_solver; /* opaque */
+typedef struct lb_op lb_op;         /* opaque MPO handle, owned by its solver */
+
+/* Fill *cfg with defaults: one mode of 4 bits, chi 16, chi_mu 4, tol 1e-8,
+ * order 2, LB_FP64, private stream, device 0. */
+void lindblad_default_config(lb_config* cfg);
+
+/* Create a solver.  Validates cfg; host only.  The device is selected and the
+ * stream created or bound at the first call that needs the device
+ * (set_state_*, observe); device memory is allocated then.
+ * Errors: LB_ERR_ARG for an invalid cfg. */
+lb_status lindblad_create(const lb_config* cfg, lb_solver** out);
+
+/* Release everything the solver owns (state, MPOs, workspace, private
+ * stream) after synchronising its stream.  NULL is a no-op. */
+void lindblad_destroy(lb_solver* s);
+
+/* ---- operators (paper Sec. 2.2) ------------------------------------------ */
+
+enum lb_factor_kind {
+  LB_ID = 0,
+  LB_A_POW = 1,       /* a^p                                   (paper Sec. 2.2.2) */
+  LB_ADAG_POW = 2,    /* (a^dagger)^p                                            */
+  LB_ADAG_A = 3,      /* (a^dagger)^p a^q, normal ordered                        */
+  LB_NUM_POW = 4,     /* diag(n^p)                                               */
+  LB_CHARGE_POW = 5,  /* diag((n - offset)^p): charge basis in offset binary     */
+  LB_SHIFT = 6,       /* (T_p)_{n,n'} = delta(n + p, n'), open boundary          */
+  LB_DENSE = 7        /* explicit N x N matrix (host, row-major, complex)         */
+};
+
+typedef struct lb_factor {
+  int32_t mode;
+  int32_t kind;           /* enum lb_factor_kind */
+  int32_t p, q;
+  int64_t offset;         /* LB_CHARGE_POW */
+  const double* dense;    /* LB_DENSE: host, N*N complex, row-major; copied */
+} lb_factor;
+
+typedef struct lb_term {
+  double re, im;          /* coefficient                                     */
+  int32_t n_factors;      /* at most one factor per mode; absent modes = ID  */
+  const lb_factor* factors;
+} lb_term;
+
+/* Build the MPO of sum_t c_t prod_f factor_f (paper Sec. 2.2: diagonal MPOs of
+ * quantics functions times binary shift MPOs, placed on each mode's site
+ * block, added and multiplied with the standard MPO toolbox) on the host in
+ * FP64, compressed at relative Frobenius tolerance `tol` (1e-14 if <= 0).
+ * The handle is owned by the solver.  n_terms = 0 gives the zero operator.
+ * Errors: LB_ERR_ARG (unknown kind, mode out of range, bad dense pointer). */
+lb_status lindblad_mpo_build(lb_solver* s, const lb_term* terms, int32_t n_terms,
+                             double tol, lb_op** out);
+
+/* Bond dimensions of an MPO: bonds[0..n_sites-2] (host array of n_sites-1). */
+lb_status lindblad_op_info(const lb_op* op, int32_t* n_sites, int32_t* bonds);
+
+/* Copy one site tensor of an MPO to the host: *l and *r receive its bond
+ * dimensions and, if w != NULL, w receives l*2*2*r complex values laid out
+ * [l][s_out][s_in][r] (entry <s_out|W|s_in>).  Host only, no device work.
+ * Errors: LB_ERR_ARG for a bad handle or site index. */
+lb_status lindblad_op_site(const lb_op* op, int32_t site, int32_t* l, int32_t* r, double* w);
+
+/* ---- the step's generator ------------------------------------------------ */
+
+typedef struct lb_drive {          /* f(t) = sum_j coef_j cos(omega_j t + phase_j) */
+  int32_t n;
+  const double* coef;
+  const double* omega;
+  const double* phase;
+} lb_drive;
+
+/* Set H(t) = H0 + f(t) H1 (H1 and f may be NULL), the jump operators L_k and
+ * the time step dt.  Builds the stacked Kraus family of the chosen scheme on
+ * the host (for a drive: as a polynomial of degree 2 in f, evaluated at the
+ * midpoint t + dt/2 of every step on the device), compresses it and brings
+ * it to the right-canonical gauge.  Host only: the upload and the workspace
+ * allocation happen at the next set_state_* call, which must follow.
+ * Errors: LB_ERR_ARG, LB_ERR_UNSTABLE (|1 - x + x^2/2| > 1 with
+ * x = dt * G/2 and G = sum_k ||L_k||^2 bounded by the triangle inequality
+ * over each jump's terms, unless cfg.allow_unstable), LB_ERR_OOM,
+ * LB_ERR_HIP. */
+lb_status lindblad_set_generator(lb_solver* s, const lb_op* H0, const lb_op* H1,
+                                 const lb_drive* f, const lb_op* const* L,
+                                 int32_t n_jumps, double dt);
+
+/* Kraus-MPO bond dimensions (host int32[n_sites-1]) and number of Kraus
+ * operators (the last site's right index). */
+lb_status lindblad_kraus_info(const lb_solver* s, int32_t* bonds, int32_t* n_kraus);
+
+/* Site tensor of the stacked Kraus MPO, layout as lindblad_op_site.  With a
+ * drive, site 0's left bond is the polynomial index p (coefficient of f^p).
+ * Host only.  Errors: LB_ERR_STATE before set_generator, LB_ERR_ARG. */
+lb_status lindblad_kraus_site(const lb_solver* s, int32_t site, int32_t* l, int32_t* r, double* w);
+
+/* ---- state --------------------------------------------------------------- */
+
+/* rho(0) = |psi><psi| with psi a product of per-mode amplitude vectors
+ * (host, complex, length 2^bits[m]; need not be normalised).  The library
+ * builds each mode's quantics MPS and brings the chain to right-canonical
+ * form with unit trace on the device.  Resets t and the step counter. */
+lb_status lindblad_set_state_product(lb_solver* s, const double* const* vectors);
+
+/* Load an MPS: bonds[0..n_sites] (bonds[0] = 1, bonds[n_sites] = purification
+ * rank), sites[i] host complex arrays [bonds[i]][2][bonds[i+1]] row-major.
+ * The library right-canonicalises (no truncation beyond exact zeros, caps
+ * enforced by the tolerance rule if exceeded) and normalises.  Used for
+ * checkpoints and synthetic states. */
+lb_status lindblad_set_state_mps(lb_solver* s, const int32_t* bonds,
+                                 const double* const* sites);
+
+/* Export the current MPS (synchronises).  bonds: host int32[n_sites+1];
+ * if sites != NULL, sites[i] must hold bonds[i]*2*bonds[i+1] complex. */
+lb_status lindblad_get_state_mps(lb_solver* s, int32_t* bonds, double** sites);
+
+/* ---- stepping ------------------------------------------------------------ */
+
+/* Advance by n_steps steps of the Kraus map (zip-up application, purification
+ * truncation, right-to-left truncated-SVD sweep, trace renormalisation). */
+lb_status lindblad_step(lb_solver* s, int32_t n_steps);
+
+/* Advance n solvers by n_steps each, sharing kernel launches across solvers
+ * that live on the same device.  Solvers may differ in sizes and caps. */
+lb_status lindblad_step_batch(lb_solver* const* s, int32_t n, int32_t n_steps);
+
+/* ---- observation (synchronises the solver's stream) ----------------------- */
+
+/* out[0] + i out[1] = Tr(O rho) by transfer matrices (paper Sec. 3.2 and
+ * Sec. 6 define the expectation values used). Errors: LB_ERR_NUMERIC if the
+ * state holds non-finite values. */
+lb_status lindblad_observe(lb_solver* s, const lb_op* O, double out[2]);
+
+/* Tr rho and purity Tr rho^2 = ||X^dag X||_F^2 (paper Sec. 4.1). */
+lb_status lindblad_trace_purity(lb_solver* s, double* trace, double* purity);
+
+typedef struct lb_diag {
+  int64_t steps;                   /* steps taken since set_state                */
+  double t;                        /* physical time                              */
+  double tau;                      /* last step's trace before renormalisation   */
+  double max_tau_defect;           /* max |tau - 1| since set_state              */
+  int32_t n_sites;
+  int32_t bonds[LB_MAX_SITES];     /* current bonds[0..n_sites-2]                */
+  int32_t chi_mu;                  /* current purification rank                  */
+  int32_t zip_bonds[LB_MAX_SITES]; /* last step's zip-up ranks                   */
+  double discarded[LB_MAX_SITES];  /* last step's relative discarded weights:
+                                      [0] purification, [1..] back-sweep bonds  */
+} lb_diag;
+
+/* Diagnostics of the last step (synchronises). */
+lb_status lindblad_diagnostics(lb_solver* s, lb_diag* out);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* lindblad_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LINDBLAD_H */

@@ -1,0 +1,45 @@
+/*
+ * lindblad_kernels.h -- component entry points of the step's kernels, for
+ * parity tests of each kernel in isolation.  Host pointers in and out; each
+ * call allocates its device buffers, runs one kernel sequence on a private
+ * stream, copies the result back and synchronises.  Complex values are
+ * interleaved (re, im) doubles, matrices row-major.
+ */
+#ifndef LINDBLAD_KERNELS_H
+#define LINDBLAD_KERNELS_H
+
+#include <stdint.h>
+#include "lindblad.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C (M x N) = op(A) op(B), op(A) = A (M x K) or A^H (A stored K x M) when
+ * adj_a, op(B) = B (K x N) or B^H (B stored N x K) when adj_b.  precision:
+ * LB_FP64 (FP64 MFMA) or LB_FP32_CONTRACT (operands rounded to complex64,
+ * FP32 MFMA, FP32 accumulation).  splits > 1 exercises the split-K path.
+ * This is the contraction kernel of the zip-up, back-sweep and transfer
+ * steps (paper Sec. 3.1.1: MPO.MPS products; Sec. 5.1 compressions).
+ * Errors: LB_ERR_ARG (sizes <= 0, NULL), LB_ERR_HIP. */
+lb_status lindblad_kernel_zgemm(int32_t M, int32_t N, int32_t K, const double* A, int32_t adj_a,
+                                const double* B, int32_t adj_b, double* C, int32_t precision,
+                                int32_t splits);
+
+/* Eigen-decomposition of a Hermitian n x n matrix G (n <= 512) by the
+ * device Jacobi kernel: w (n, descending) and U (n x n, eigenvectors as
+ * columns).  *sweeps receives the sweeps used (-1: not converged).
+ * This is the factorisation behind every truncated SVD of the step.
+ * Errors: LB_ERR_ARG, LB_ERR_HIP. */
+lb_status lindblad_kernel_heev(int32_t n, const double* G, double* w, double* U, int32_t* sweeps);
+
+/* Truncation rule on descending squared singular values lam (n): smallest
+ * k >= 1 with sum_{j>k} lam_j <= tol^2 sum_j lam_j, then min(k, cap);
+ * *disc = discarded / total.  (Tolerance rule of all compressions.) */
+lb_status lindblad_kernel_truncate(int32_t n, const double* lam, double tol, int32_t cap,
+                                   int32_t* k, double* disc);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,112 @@
+// Component entry points (include/lindblad_kernels.h): one kernel sequence
+// per call on host data, for isolated parity tests of the device kernels.
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lindblad_kernels.h"
+#include "kernels.h"
+
+namespace {
+thread_local std::string g_err;
+
+struct Dev {
+  void* p = nullptr;
+  explicit Dev(size_t b) { if (hipMalloc(&p, b ? b : 16) != hipSuccess) p = nullptr; }
+  ~Dev() { if (p) (void)hipFree(p); }
+};
+
+lb_status hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return LB_ERR_HIP;
+}
+}  // namespace
+
+extern "C" {
+
+lb_status lindblad_kernel_zgemm(int32_t M, int32_t N, int32_t K, const double* A, int32_t adj_a,
+                                const double* B, int32_t adj_b, double* C, int32_t precision,
+                                int32_t splits) {
+  if (M <= 0 || N <= 0 || K <= 0 || !A || !B || !C) return LB_ERR_ARG;
+  const size_t na = (size_t)M * K, nb = (size_t)K * N, nc = (size_t)M * N;
+  const bool f32 = precision == LB_FP32_CONTRACT;
+  hipStream_t s;
+  hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "stream");
+  Dev dA(na * 16), dB(nb * 16), dC(nc * 16), dA32(na * 8), dB32(nb * 8), dC32(nc * 8),
+      ws((size_t)std::max(1, splits) * nc * 16);
+  lb_status rc = LB_OK;
+  do {
+    if (!dA.p || !dB.p || !dC.p || !ws.p) { rc = LB_ERR_OOM; break; }
+    if ((e = hipMemcpyAsync(dA.p, A, na * 16, hipMemcpyHostToDevice, s)) != hipSuccess) { rc = hip_fail(e, "copy"); break; }
+    if ((e = hipMemcpyAsync(dB.p, B, nb * 16, hipMemcpyHostToDevice, s)) != hipSuccess) { rc = hip_fail(e, "copy"); break; }
+    lbk::Gemm g;
+    g.M = M; g.N = N; g.K = K; g.splits = std::max(1, splits); g.ws = ws.p;
+    if (f32) {
+      if ((e = lbk::to_f32((double*)dA.p, (float*)dA32.p, (long long)na, s)) != hipSuccess) { rc = hip_fail(e, "f32"); break; }
+      if ((e = lbk::to_f32((double*)dB.p, (float*)dB32.p, (long long)nb, s)) != hipSuccess) { rc = hip_fail(e, "f32"); break; }
+    }
+    g.A = f32 ? dA32.p : dA.p; g.pa = f32 ? lbk::F32 : lbk::F64;
+    g.B = f32 ? dB32.p : dB.p; g.pb = f32 ? lbk::F32 : lbk::F64;
+    if (adj_a) { g.sa_m = 1; g.sa_k = M; g.conjA = 1; } else { g.sa_m = K; g.sa_k = 1; }
+    if (adj_b) { g.sb_k = 1; g.sb_n = K; g.conjB = 1; } else { g.sb_k = N; g.sb_n = 1; }
+    g.C = dC.p; g.pc = lbk::F64; g.sc_m = N; g.sc_n = 1;
+    g.compute = f32 ? lbk::F32 : lbk::F64;
+    if ((e = lbk::gemm(g, s)) != hipSuccess) { rc = hip_fail(e, "gemm"); break; }
+    if ((e = hipMemcpyAsync(C, dC.p, nc * 16, hipMemcpyDeviceToHost, s)) != hipSuccess) { rc = hip_fail(e, "copy"); break; }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) { rc = hip_fail(e, "sync"); break; }
+  } while (0);
+  (void)hipStreamSynchronize(s);
+  (void)hipStreamDestroy(s);
+  return rc;
+}
+
+lb_status lindblad_kernel_heev(int32_t n, const double* G, double* w, double* U, int32_t* sweeps) {
+  if (n <= 0 || n > 512 || !G || !w || !U) return LB_ERR_ARG;
+  hipStream_t s;
+  hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "stream");
+  const size_t nn = (size_t)n * n;
+  Dev dG(nn * 16), dV(nn * 16), dw(n * 8), di(16);
+  lb_status rc = LB_OK;
+  do {
+    if (!dG.p || !dV.p || !dw.p || !di.p) { rc = LB_ERR_OOM; break; }
+    if ((e = hipMemcpyAsync(dG.p, G, nn * 16, hipMemcpyHostToDevice, s)) != hipSuccess) { rc = hip_fail(e, "copy"); break; }
+    if ((e = lbk::heev_jacobi((double*)dG.p, n, 0, n, (double*)dw.p, 0, (double*)dV.p, 1, 1.5e-15, 40,
+                              (int*)di.p, s)) != hipSuccess) { rc = hip_fail(e, "heev"); break; }
+    int info = 0;
+    if ((e = hipMemcpyAsync(U, dG.p, nn * 16, hipMemcpyDeviceToHost, s)) != hipSuccess) { rc = hip_fail(e, "copy"); break; }
+    if ((e = hipMemcpyAsync(w, dw.p, n * 8, hipMemcpyDeviceToHost, s)) != hipSuccess) { rc = hip_fail(e, "copy"); break; }
+    if ((e = hipMemcpyAsync(&info, di.p, 4, hipMemcpyDeviceToHost, s)) != hipSuccess) { rc = hip_fail(e, "copy"); break; }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) { rc = hip_fail(e, "sync"); break; }
+    if (sweeps) *sweeps = info;
+  } while (0);
+  (void)hipStreamSynchronize(s);
+  (void)hipStreamDestroy(s);
+  return rc;
+}
+
+lb_status lindblad_kernel_truncate(int32_t n, const double* lam, double tol, int32_t cap, int32_t* k,
+                                   double* disc) {
+  if (n <= 0 || !lam || !k) return LB_ERR_ARG;
+  hipStream_t s;
+  hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "stream");
+  Dev dl(n * 8), dk(16), dd(16);
+  lb_status rc = LB_OK;
+  do {
+    if ((e = hipMemcpyAsync(dl.p, lam, n * 8, hipMemcpyHostToDevice, s)) != hipSuccess) { rc = hip_fail(e, "copy"); break; }
+    if ((e = lbk::truncate_rank((double*)dl.p, n, tol, cap, (int*)dk.p, (double*)dd.p, s)) != hipSuccess) { rc = hip_fail(e, "trunc"); break; }
+    double dh = 0.0;
+    if ((e = hipMemcpyAsync(k, dk.p, 4, hipMemcpyDeviceToHost, s)) != hipSuccess) { rc = hip_fail(e, "copy"); break; }
+    if ((e = hipMemcpyAsync(&dh, dd.p, 8, hipMemcpyDeviceToHost, s)) != hipSuccess) { rc = hip_fail(e, "copy"); break; }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) { rc = hip_fail(e, "sync"); break; }
+    if (disc) *disc = dh;
+  } while (0);
+  (void)hipStreamSynchronize(s);
+  (void)hipStreamDestroy(s);
+  return rc;
+}
+
+}  // extern "C"

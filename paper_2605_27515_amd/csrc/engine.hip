@@ -1,0 +1,1095 @@
+// Solver engine behind the C ABI of include/lindblad.h.
+//
+// Host side: configuration, MPO construction (mpo.cpp), Kraus-family build,
+// buffer management and the sequencing of one step.  Device side: every
+// arithmetic operation of the step runs in the kernels of kernels.hip.
+//
+// Step (paper Sec. 5.2.2 Kraus map applied as one MPO; Sec. 5.1 compression):
+//   S0'  drive: W_0 = sum_p f(t + h/2)^p Wb_p (boundary contraction)
+//   S1   zip-up, site i = 0..L-2:
+//          P = C_i . X_i                         (stage 1 GEMM)
+//          T = W_i^t . P, batched over C's rows   (stage 2 GEMM)
+//          G = T T^H (FP64), eigen(G) -> U, lambda (FP64 two-pass refinement
+//          in LB_FP64: B = U^H T, G2 = B B^H, eigen(G2))
+//          k = rule(lambda, tol_zip, chi_zip); X_i <- U[:, :k];
+//          C_{i+1} = U[:, :k]^H T
+//   S2   last site: G' = T^H T over (Kraus x purification) columns,
+//        eigen -> V, k = rule(lambda, tol, chi_mu); X_L <- T V[:, :k]
+//   S3   back-sweep i = L-1..1: G = M M^H for M = X_i (chi_i x 2 chi_{i+1}),
+//        eigen, k = rule(tol, chi); X_i <- S^-1 U_k^H M; X_{i-1} <- X_{i-1} U_k S
+//   S4   tau = ||X_0||^2, X_0 /= sqrt(tau)
+// The singular values and left singular vectors of each unfolding come from
+// the eigen-decomposition of its Gram matrix; in LB_FP64 a second pass on
+// the rotated matrix restores absolute FP64 accuracy of the small singular
+// values (the first pass alone resolves them only to sqrt(eps) relative).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/lindblad.h"
+#include "kernels.h"
+#include "mpo.h"
+
+using lb::cd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Fail : std::runtime_error {
+  lb_status code;
+  Fail(lb_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(x)                                                                      \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess)                                                              \
+      throw Fail(LB_ERR_HIP, std::string(#x " failed: ") + hipGetErrorString(e_));      \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  void alloc(size_t b) {
+    if (b <= bytes && p) return;
+    release();
+    if (b == 0) b = 16;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      bytes = 0;
+      throw Fail(LB_ERR_OOM, "hipMalloc of " + std::to_string(b) + " bytes failed");
+    }
+    bytes = b;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  double* d() const { return (double*)p; }
+  float* f() const { return (float*)p; }
+  int* i() const { return (int*)p; }
+  ~DevBuf() { release(); }
+};
+
+// One site of an MPO on the device in the transposed layout used by the
+// stage-2 GEMM: Wt[(s_out, r)][(l, s_in)], row-major (2r x 2l).
+struct DevMpo {
+  std::vector<int> wl, wr;
+  std::vector<DevBuf> d64, d32;
+};
+
+}  // namespace
+
+struct lb_op {
+  lb::Mpo mpo;
+  std::vector<lb::Term> terms;
+  DevMpo dev;
+  bool uploaded = false;
+};
+
+struct lb_solver {
+  lb_config cfg;
+  lb::Layout lay;
+  int L = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool dev_ready = false;      // device selected and stream bound
+  bool gen_on_device = false;  // Kraus MPO uploaded, workspace allocated
+  std::vector<std::unique_ptr<lb_op>> ops;
+
+  // generator
+  bool have_gen = false;
+  double dt = 0.0;
+  int n_kraus = 0, degree = 1;
+  std::vector<double> drv_c, drv_w, drv_p;
+  lb::Mpo kraus;          // host copy (canonical gauge)
+  lb::Mpo kraus_dev;      // as uploaded (site 0 zeroed when a drive refreshes it)
+  std::vector<cd> h0;     // boundary coefficients of site 0 (Wt layout, per p)
+  std::vector<int> wb;    // MPO bonds wb[0..L]; wb[0] = 1 after the boundary contraction
+  DevMpo W;               // device Kraus MPO (site 0 is refreshed per step for a drive)
+  DevBuf Wb0;             // boundary polynomial coefficients of site 0 (FP64, Wt layout)
+  long long wb0_stride = 0;
+
+  // state
+  bool have_state = false;
+  std::vector<int> chi;       // chi[0..L]
+  std::vector<int> cap;       // capacity per bond
+  std::vector<DevBuf> X;      // site buffers (all of the same capacity)
+  DevBuf Xspare;
+  size_t site_cap = 0;        // complex elements per site buffer
+
+  // workspace
+  DevBuf C, P, T, Bm, G, G2, U2, Uf, V, lam, lam2, ws, kdev, disc, tau, flag, info, scratch;
+  size_t ws_bytes = 0;
+  int n_max = 0;
+  long long m_max = 0;
+
+  // diagnostics
+  double t = 0.0;
+  long long steps = 0;
+  double last_tau = 1.0, max_defect = 0.0;
+  std::vector<int> zip_bonds;
+  std::vector<double> discarded;
+  int last_chi_mu = 1;
+};
+
+namespace {
+
+using lbk::Gemm;
+using lbk::Prec;
+
+bool fp32(const lb_solver* s) { return s->cfg.precision == LB_FP32_CONTRACT; }
+int passes(const lb_solver* s) { return fp32(s) ? 1 : 2; }
+
+lb::Layout make_layout(const lb_config& c) {
+  lb::Layout lay;
+  lay.bits.assign(c.bits, c.bits + c.n_modes);
+  int total = 0;
+  for (int b : lay.bits) total += b;
+  std::vector<std::pair<int, int>> order;
+  if (c.n_sites == 0) {
+    for (int m = 0; m < c.n_modes; ++m) {
+      if (m == 0)
+        for (int b = c.bits[0] - 1; b >= 0; --b) order.push_back({0, b});
+      else
+        for (int b = 0; b < c.bits[m]; ++b) order.push_back({m, b});
+    }
+  } else {
+    if (c.n_sites != total) throw Fail(LB_ERR_ARG, "n_sites must equal the total number of bits");
+    for (int i = 0; i < c.n_sites; ++i) order.push_back({c.site_order[i][0], c.site_order[i][1]});
+  }
+  lay.n_sites = total;
+  lay.first.assign(c.n_modes, -1);
+  lay.len.assign(c.n_modes, 0);
+  lay.msb_first.assign(c.n_modes, true);
+  for (int m = 0; m < c.n_modes; ++m) {
+    std::vector<int> pos, bits;
+    for (int i = 0; i < total; ++i)
+      if (order[i].first == m) { pos.push_back(i); bits.push_back(order[i].second); }
+    if ((int)pos.size() != c.bits[m]) throw Fail(LB_ERR_ARG, "site order does not cover every bit");
+    for (size_t k = 1; k < pos.size(); ++k)
+      if (pos[k] != pos[0] + (int)k) throw Fail(LB_ERR_ARG, "a mode's sites must be contiguous");
+    bool inc = true, dec = true;
+    for (size_t k = 0; k < bits.size(); ++k) {
+      if (bits[k] != (int)k) inc = false;
+      if (bits[k] != (int)(bits.size() - 1 - k)) dec = false;
+    }
+    if (!inc && !dec) throw Fail(LB_ERR_ARG, "bits of a mode must be MSB- or LSB-first");
+    lay.first[m] = pos[0];
+    lay.len[m] = (int)pos.size();
+    lay.msb_first[m] = inc;
+  }
+  return lay;
+}
+
+// Upload an MPO in the Wt layout; site 0 of a boundary-stacked MPO is
+// uploaded per boundary index p into `wb0` when given.
+void upload_mpo(lb_solver* s, const lb::Mpo& m, DevMpo& d, bool want32) {
+  const int n = (int)m.size();
+  d.wl.resize(n);
+  d.wr.resize(n);
+  d.d64.resize(n);
+  d.d32.resize(n);
+  for (int k = 0; k < n; ++k) {
+    const lb::Site& x = m[k];
+    d.wl[k] = x.l;
+    d.wr[k] = x.r;
+    std::vector<cd> h((size_t)x.l * 4 * x.r);
+    for (int l = 0; l < x.l; ++l)
+      for (int o = 0; o < 2; ++o)
+        for (int i = 0; i < 2; ++i)
+          for (int r = 0; r < x.r; ++r)
+            h[((size_t)o * x.r + r) * (2 * x.l) + (size_t)l * 2 + i] = x.at(l, o, i, r);
+    d.d64[k].alloc(h.size() * sizeof(cd));
+    HIPCHK(hipMemcpyAsync(d.d64[k].p, h.data(), h.size() * sizeof(cd), hipMemcpyHostToDevice, s->stream));
+    if (want32) {
+      d.d32[k].alloc(h.size() * 2 * sizeof(float));
+      HIPCHK(lbk::to_f32(d.d64[k].d(), d.d32[k].f(), (long long)h.size(), s->stream));
+    }
+  }
+  HIPCHK(hipStreamSynchronize(s->stream));
+}
+
+void check_gemm(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw Fail(LB_ERR_HIP, std::string("gemm ") + what + ": " + hipGetErrorString(e));
+}
+
+int read_k(lb_solver* s) {
+  int k = 0;
+  HIPCHK(hipMemcpyAsync(&k, s->kdev.p, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  return k;
+}
+
+double read_disc(lb_solver* s) {
+  double d = 0.0;
+  HIPCHK(hipMemcpyAsync(&d, s->disc.p, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  return d;
+}
+
+int choose_splits(int M, int N, long long K) {
+  const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  if (tiles >= 256 || K < 512) return 1;
+  // splits * tiles <= 512 bounds the partial-sum workspace by 512 * 64 * 64
+  int sp = (int)std::min<long long>(512 / tiles, K / 256);
+  return std::max(1, std::min(sp, 64));
+}
+
+// Gram G = A A^H of the rows of A (n x m, row stride lda), FP64 output n x n.
+void gram_rows(lb_solver* s, const void* A, Prec pa, int n, long long m, long long lda, double* G) {
+  Gemm g;
+  g.M = n; g.N = n; g.K = (int)m;
+  g.A = A; g.sa_m = lda; g.sa_k = 1; g.pa = pa;
+  g.B = A; g.sb_k = 1; g.sb_n = lda; g.conjB = 1; g.pb = pa;
+  g.C = G; g.sc_m = n; g.sc_n = 1; g.pc = lbk::F64;
+  g.compute = lbk::F64;
+  g.splits = choose_splits(n, n, m);
+  g.ws = s->ws.p;
+  check_gemm(lbk::gemm(g, s->stream), "gram_rows");
+}
+
+// Gram G = A^H A of the columns of A (n x m), FP64 output m x m.
+void gram_cols(lb_solver* s, const void* A, Prec pa, int n, int m, long long lda, double* G) {
+  Gemm g;
+  g.M = m; g.N = m; g.K = n;
+  g.A = A; g.sa_m = 1; g.sa_k = lda; g.conjA = 1; g.pa = pa;
+  g.B = A; g.sb_k = lda; g.sb_n = 1; g.pb = pa;
+  g.C = G; g.sc_m = m; g.sc_n = 1; g.pc = lbk::F64;
+  g.compute = lbk::F64;
+  g.splits = choose_splits(m, m, n);
+  g.ws = s->ws.p;
+  check_gemm(lbk::gemm(g, s->stream), "gram_cols");
+}
+
+void eig(lb_solver* s, double* G, int n, double* lam) {
+  HIPCHK(lbk::heev_jacobi(G, n, 0, n, lam, 0, s->V.d(), 1, 1.5e-15, 40, s->info.i(), s->stream));
+}
+
+// C = op(A) op(B) with row-major dense operands described by leading dims.
+void mm(lb_solver* s, int M, int N, int K, const void* A, Prec pa, long long lda, bool adjA,
+        const void* B, Prec pb, long long ldb, bool adjB, void* C, Prec pc, long long ldc, Prec comp,
+        int batch = 1, long long sa_b = 0, long long sb_b = 0, long long sc_b = 0) {
+  Gemm g;
+  g.M = M; g.N = N; g.K = K; g.batch = batch;
+  g.A = A; g.pa = pa; g.sa_b = sa_b;
+  if (adjA) { g.sa_m = 1; g.sa_k = lda; g.conjA = 1; } else { g.sa_m = lda; g.sa_k = 1; }
+  g.B = B; g.pb = pb; g.sb_b = sb_b;
+  if (adjB) { g.sb_k = 1; g.sb_n = ldb; g.conjB = 1; } else { g.sb_k = ldb; g.sb_n = 1; }
+  g.C = C; g.pc = pc; g.sc_m = ldc; g.sc_n = 1; g.sc_b = sc_b;
+  g.compute = comp;
+  g.splits = (batch == 1) ? choose_splits(M, N, K) : 1;
+  g.ws = s->ws.p;
+  check_gemm(lbk::gemm(g, s->stream), "mm");
+}
+
+// Left singular vectors / squared singular values of the n x m matrix A
+// (row-major, leading dim lda): on return Uout (n x n, ld n) and lamout (n).
+// Two passes in FP64 mode; `Bout` (n x m, ld m) then holds U2^H U0^H A, the
+// rows sigma_j v_j^H (used for carries).  Returns the device pointer of U.
+double* left_svd(lb_solver* s, const void* A, Prec pa, int n, long long m, long long lda, bool want_b) {
+  double* G = s->G.d();
+  gram_rows(s, A, pa, n, m, lda, G);
+  eig(s, G, n, s->lam.d());
+  if (passes(s) == 1) return G;
+  // second pass: B = U0^H A, G2 = B B^H, eigen(G2) -> U2, U = U0 U2
+  double* B = s->Bm.d();
+  mm(s, n, (int)m, n, G, lbk::F64, n, true, A, pa, lda, false, B, lbk::F64, m, lbk::F64);
+  double* G2 = s->G2.d();
+  gram_rows(s, B, lbk::F64, n, m, m, G2);
+  eig(s, G2, n, s->lam.d());
+  double* Uf = s->Uf.d();
+  mm(s, n, n, n, G, lbk::F64, n, false, G2, lbk::F64, n, false, Uf, lbk::F64, n, lbk::F64);
+  if (want_b) {
+    // rows of U2^H B in place of B (scratch T-sized buffer then swap)
+    double* B2 = s->U2.d();
+    mm(s, n, (int)m, n, G2, lbk::F64, n, true, B, lbk::F64, m, false, B2, lbk::F64, m, lbk::F64);
+    std::swap(s->Bm.p, s->U2.p);
+    std::swap(s->Bm.bytes, s->U2.bytes);
+  }
+  return Uf;
+}
+
+void alloc_workspace(lb_solver* s) {
+  const int L = s->L;
+  const int zc = s->cfg.chi_zip_cap > 0 ? s->cfg.chi_zip_cap : s->cfg.chi_cap;
+  int nmax = 2;
+  long long mmax = 1, cmax = 1, pmax = 1;
+  std::vector<int> zcap(L + 1, 1);
+  for (int i = 1; i <= L; ++i) zcap[i] = (int)std::min<long long>(zc, 1LL << std::min(i, 30));
+  for (int i = 0; i < L; ++i) {
+    const int zl = zcap[i];
+    const int cr = (i == L - 1) ? s->cfg.chi_mu_cap : s->cap[i + 1];
+    const int cl = s->cap[i];
+    nmax = std::max(nmax, 2 * zl);
+    mmax = std::max(mmax, (long long)s->wb[i + 1] * cr);
+    cmax = std::max(cmax, (long long)zl * s->wb[i] * cl);
+    pmax = std::max(pmax, (long long)zl * s->wb[i] * 2 * cr);
+  }
+  // the last site's column Gram has m = K * chi_mu columns
+  nmax = std::max<long long>(nmax, (long long)s->n_kraus * s->cfg.chi_mu_cap);
+  nmax = std::max(nmax, 2 * s->cfg.chi_cap);
+  if (nmax > 512) throw Fail(LB_ERR_ARG, "zip-up factor dimension exceeds 512 (chi_zip or chi_mu*K too large)");
+  s->n_max = nmax;
+  s->m_max = mmax;
+  const size_t cbytes = fp32(s) ? 8 : 16;
+  s->C.alloc(std::max(cmax, (long long)nmax * mmax) * cbytes);
+  s->P.alloc(pmax * cbytes);
+  s->T.alloc((size_t)nmax * mmax * cbytes);
+  const size_t nn = (size_t)nmax * nmax * 16;
+  s->G.alloc(nn);
+  s->G2.alloc(nn);
+  s->Uf.alloc(nn);
+  s->V.alloc(nn);
+  s->Bm.alloc((size_t)nmax * std::max<long long>(mmax, nmax) * 16);
+  s->U2.alloc((size_t)nmax * std::max<long long>(mmax, nmax) * 16);
+  s->lam.alloc((size_t)nmax * 8);
+  s->lam2.alloc((size_t)nmax * 8);
+  s->ws.alloc((size_t)64 * nmax * nmax * 16 + (size_t)512 * 64 * 64 * 16);
+  s->kdev.alloc(64);
+  s->disc.alloc(64);
+  s->tau.alloc(64);
+  s->flag.alloc(64);
+  s->info.alloc(64);
+  s->scratch.alloc((size_t)4 * nmax * nmax * 16);
+  HIPCHK(hipMemsetAsync(s->flag.p, 0, 64, s->stream));
+}
+
+void alloc_state(lb_solver* s) {
+  const int L = s->L;
+  s->cap.assign(L + 1, 1);
+  const long long chi = s->cfg.chi_cap, mu = s->cfg.chi_mu_cap;
+  for (int i = 1; i < L; ++i) {
+    long long c = std::min<long long>(chi, 1LL << std::min(i, 30));
+    c = std::min<long long>(c, (1LL << std::min(L - i, 30)) * mu);
+    s->cap[i] = (int)c;
+  }
+  s->cap[L] = (int)mu;
+  // zip-up sites may carry the zip cap on their bonds before the back-sweep
+  const int zc = s->cfg.chi_zip_cap > 0 ? s->cfg.chi_zip_cap : s->cfg.chi_cap;
+  size_t mx = 1;
+  for (int i = 0; i < L; ++i) {
+    const long long l = std::max<long long>(s->cap[i], std::min<long long>(zc, 1LL << std::min(i, 30)));
+    const long long r = std::max<long long>(s->cap[i + 1], std::min<long long>(zc, 1LL << std::min(i + 1, 30)));
+    mx = std::max<size_t>(mx, (size_t)l * 2 * r);
+  }
+  mx = std::max<size_t>(mx, (size_t)std::max(zc, (int)chi) * 2 * (size_t)std::max<long long>(mu * 16, chi));
+  s->site_cap = mx;
+  s->X.resize(L);
+  for (int i = 0; i < L; ++i) s->X[i].alloc(mx * 16);
+  s->Xspare.alloc(mx * 16);
+}
+
+void ensure_device(lb_solver* s) {
+  if (s->dev_ready) return;
+  HIPCHK(hipSetDevice(s->cfg.device));
+  if (s->cfg.stream) {
+    s->stream = (hipStream_t)s->cfg.stream;
+  } else {
+    HIPCHK(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+    s->own_stream = true;
+  }
+  s->dev_ready = true;
+}
+
+void ensure_generator_on_device(lb_solver* s) {
+  if (!s->have_gen) throw Fail(LB_ERR_STATE, "set_generator must precede this call");
+  ensure_device(s);
+  if (s->gen_on_device) return;
+  HIPCHK(hipSetDevice(s->cfg.device));
+  if (s->degree > 1) {
+    s->Wb0.alloc(s->h0.size() * sizeof(cd));
+    HIPCHK(hipMemcpyAsync(s->Wb0.p, s->h0.data(), s->h0.size() * sizeof(cd), hipMemcpyHostToDevice, s->stream));
+  }
+  upload_mpo(s, s->kraus_dev, s->W, fp32(s));
+  if (s->cap.empty()) alloc_state(s);
+  alloc_workspace(s);
+  s->gen_on_device = true;
+}
+
+// ---- one step ---------------------------------------------------------------
+
+void refresh_drive(lb_solver* s) {
+  if (s->degree <= 1) return;
+  double f = 0.0;
+  const double tm = s->t + 0.5 * s->dt;
+  for (size_t j = 0; j < s->drv_c.size(); ++j) f += s->drv_c[j] * std::cos(s->drv_w[j] * tm + s->drv_p[j]);
+  const long long count = (long long)2 * s->W.wr[0] * 2 * 1;
+  HIPCHK(lbk::boundary_contract(s->Wb0.d(), s->wb0_stride, s->degree, f, s->W.d64[0].d(),
+                                fp32(s) ? s->W.d32[0].f() : nullptr, count, s->stream));
+}
+
+void zipup(lb_solver* s) {
+  const int L = s->L;
+  const bool f32 = fp32(s);
+  const Prec pw = f32 ? lbk::F32 : lbk::F64;   // contraction storage / compute precision
+  const double tolz = s->cfg.tol_zip > 0 ? s->cfg.tol_zip : s->cfg.tol / 10.0;
+  const int zc = s->cfg.chi_zip_cap > 0 ? s->cfg.chi_zip_cap : s->cfg.chi_cap;
+  int zk = 1;  // rows of the carry (new left bond)
+  s->zip_bonds.assign(L, 0);
+  for (int i = 0; i < L; ++i) {
+    const int cl = s->chi[i], cr = s->chi[i + 1];
+    const int wl = s->wb[i], wr = s->wb[i + 1];
+    // stage 1: P[(a', u)][(s, b)] = C[(a', u)][a] X_i[a][(s, b)]
+    const void* Pp;
+    Prec pp;
+    if (i == 0) {
+      Pp = s->X[0].p;
+      pp = lbk::F64;
+    } else {
+      mm(s, zk * wl, 2 * cr, cl, s->C.p, pw, cl, false, s->X[i].p, lbk::F64, 2 * cr, false,
+         s->P.p, pw, 2 * cr, pw);
+      Pp = s->P.p;
+      pp = pw;
+    }
+    // stage 2: T_{a'}[(s', v)][b] = Wt[(s', v)][(u, s)] P_{a'}[(u, s)][b]
+    const void* Wt = f32 ? (const void*)s->W.d32[i].p : (const void*)s->W.d64[i].p;
+    mm(s, 2 * wr, cr, 2 * wl, Wt, pw, 2 * wl, false, Pp, pp, cr, false, s->T.p, pw, cr, pw,
+       zk, 0, (long long)2 * wl * cr, (long long)2 * wr * cr);
+    const int n = 2 * zk;
+    const long long m = (long long)wr * cr;
+    if (i < L - 1) {
+      double* U = left_svd(s, s->T.p, pw, n, m, m, passes(s) == 2);
+      HIPCHK(lbk::truncate_rank(s->lam.d(), n, tolz, zc, s->kdev.i(), s->disc.d(), s->stream));
+      const int k = read_k(s);
+      // new site X_i[(a', s')][k] = U[:, :k]
+      HIPCHK(lbk::copy_cols(U, n, s->X[i].d(), k, n, k, nullptr, s->stream));
+      // carry C[k][(v, b)] = U_k^H T  (or the first k rows of U2^H B)
+      if (passes(s) == 2) {
+        if (f32) throw Fail(LB_ERR_STATE, "internal: two-pass FP32");
+        HIPCHK(hipMemcpyAsync(s->C.p, s->Bm.p, (size_t)k * m * 16, hipMemcpyDeviceToDevice, s->stream));
+      } else {
+        mm(s, k, (int)m, n, U, lbk::F64, n, true, s->T.p, pw, m, false, s->C.p, pw, m, pw);
+      }
+      s->chi[i] = zk;       // left bond of the new site
+      zk = k;
+      s->zip_bonds[i] = k;
+    } else {
+      // S2: purification truncation on the (Kraus x purification) columns
+      const int mc = (int)m;
+      double* Gc = s->G.d();
+      gram_cols(s, s->T.p, pw, n, mc, m, Gc);
+      eig(s, Gc, mc, s->lam.d());
+      double* Vf = Gc;
+      const void* Asrc = s->T.p;
+      Prec asrc = pw;
+      if (passes(s) == 2) {
+        // B' = T V0 (columns sigma_j u_j), G2' = B'^H B', eigen -> V2
+        double* Bc = s->Bm.d();
+        mm(s, n, mc, mc, s->T.p, pw, m, false, Gc, lbk::F64, mc, false, Bc, lbk::F64, mc, lbk::F64);
+        double* G2 = s->G2.d();
+        gram_cols(s, Bc, lbk::F64, n, mc, mc, G2);
+        eig(s, G2, mc, s->lam.d());
+        Vf = G2;
+        Asrc = Bc;
+        asrc = lbk::F64;
+      }
+      HIPCHK(lbk::truncate_rank(s->lam.d(), mc, s->cfg.tol, s->cfg.chi_mu_cap, s->kdev.i(), s->disc.d(),
+                                s->stream));
+      const int k = read_k(s);
+      s->discarded[0] = read_disc(s);
+      // X_{L-1}[(a', s')][k] = A V[:, :k]
+      mm(s, n, k, mc, Asrc, asrc, (passes(s) == 2) ? mc : m, false, Vf, lbk::F64, mc, false,
+         s->X[i].p, lbk::F64, k, lbk::F64);
+      s->chi[i] = zk;
+      s->chi[L] = k;
+      s->last_chi_mu = k;
+    }
+  }
+}
+
+// Right-to-left truncated-SVD sweep; leaves sites 1..L-1 right-orthonormal.
+void back_sweep(lb_solver* s, double tol, bool record) {
+  const int L = s->L;
+  for (int i = L - 1; i >= 1; --i) {
+    const int l = s->chi[i], r = s->chi[i + 1];
+    const long long m = 2LL * r;
+    double* U = left_svd(s, s->X[i].p, lbk::F64, l, m, m, passes(s) == 2);
+    HIPCHK(lbk::truncate_rank(s->lam.d(), l, tol, s->cap[i], s->kdev.i(), s->disc.d(), s->stream));
+    const int k = read_k(s);
+    if (record && i < (int)s->discarded.size()) s->discarded[i] = read_disc(s);
+    // new X_i = S^-1 U_k^H M  (rows k)
+    if (passes(s) == 2) {
+      HIPCHK(lbk::scale_rows_inv_sqrt(s->Bm.d(), (int)m, s->Xspare.d(), (int)m, k, (int)m, s->lam.d(), s->stream));
+    } else {
+      double* tmp = s->Bm.d();
+      mm(s, k, (int)m, l, U, lbk::F64, l, true, s->X[i].p, lbk::F64, m, false, tmp, lbk::F64, m, lbk::F64);
+      HIPCHK(lbk::scale_rows_inv_sqrt(tmp, (int)m, s->Xspare.d(), (int)m, k, (int)m, s->lam.d(), s->stream));
+    }
+    std::swap(s->X[i].p, s->Xspare.p);
+    std::swap(s->X[i].bytes, s->Xspare.bytes);
+    // US = U[:, :k] * sigma ; X_{i-1} <- X_{i-1} US
+    double* US = s->scratch.d();
+    HIPCHK(lbk::copy_cols(U, l, US, k, l, k, s->lam.d(), s->stream));
+    const int lp = s->chi[i - 1];
+    mm(s, 2 * lp, k, l, s->X[i - 1].p, lbk::F64, l, false, US, lbk::F64, k, false, s->Xspare.p,
+       lbk::F64, k, lbk::F64);
+    std::swap(s->X[i - 1].p, s->Xspare.p);
+    std::swap(s->X[i - 1].bytes, s->Xspare.bytes);
+    s->chi[i] = k;
+  }
+}
+
+void normalize_center(lb_solver* s) {
+  HIPCHK(lbk::normalize(s->X[0].d(), 2LL * s->chi[1], s->tau.d(), s->flag.i(), s->stream));
+}
+
+void step_once(lb_solver* s) {
+  refresh_drive(s);
+  zipup(s);
+  back_sweep(s, s->cfg.tol, true);
+  normalize_center(s);
+  double tau = 1.0;
+  HIPCHK(hipMemcpyAsync(&tau, s->tau.p, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  s->last_tau = tau;
+  s->max_defect = std::max(s->max_defect, std::fabs(tau - 1.0));
+  s->t += s->dt;
+  s->steps += 1;
+}
+
+void canonicalize(lb_solver* s) {
+  // back-sweep without truncation beyond numerical zeros, then normalise
+  back_sweep(s, 1e-14, false);
+  normalize_center(s);
+  HIPCHK(hipStreamSynchronize(s->stream));
+}
+
+lb_status fail(const Fail& f) {
+  g_last_error = f.what();
+  return f.code;
+}
+
+std::vector<lb::Term> convert_terms(const lb_solver* s, const lb_term* terms, int n) {
+  std::vector<lb::Term> out;
+  for (int t = 0; t < n; ++t) {
+    lb::Term tm;
+    tm.coef = cd(terms[t].re, terms[t].im);
+    if (terms[t].n_factors < 0 || (terms[t].n_factors > 0 && !terms[t].factors))
+      throw Fail(LB_ERR_ARG, "term factors pointer is NULL");
+    for (int f = 0; f < terms[t].n_factors; ++f) {
+      const lb_factor& x = terms[t].factors[f];
+      if (x.mode < 0 || x.mode >= s->cfg.n_modes) throw Fail(LB_ERR_ARG, "factor mode out of range");
+      if (x.kind < 0 || x.kind > 7) throw Fail(LB_ERR_ARG, "unknown factor kind");
+      if ((x.kind >= 1 && x.kind <= 5) && (x.p < 0 || x.q < 0)) throw Fail(LB_ERR_ARG, "negative power");
+      for (const auto& pf : tm.factors)
+        if (pf.first == x.mode) throw Fail(LB_ERR_ARG, "two factors on one mode in a term");
+      lb::Factor fc;
+      fc.kind = x.kind; fc.p = x.p; fc.q = x.q; fc.offset = x.offset;
+      if (x.kind == LB_DENSE) {
+        if (!x.dense) throw Fail(LB_ERR_ARG, "dense factor pointer is NULL");
+        const size_t N = (size_t)1 << s->cfg.bits[x.mode];
+        fc.dense.resize(N * N);
+        std::memcpy(fc.dense.data(), x.dense, N * N * sizeof(cd));
+      }
+      tm.factors.push_back({x.mode, fc});
+    }
+    out.push_back(tm);
+  }
+  return out;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+
+extern "C" {
+
+void lindblad_default_config(lb_config* c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof(*c));
+  c->n_modes = 1;
+  c->bits[0] = 4;
+  c->chi_cap = 16;
+  c->chi_mu_cap = 4;
+  c->tol = 1e-8;
+  c->order = 2;
+  c->precision = LB_FP64;
+}
+
+lb_status lindblad_create(const lb_config* cfg, lb_solver** out) {
+  try {
+    if (!cfg || !out) throw Fail(LB_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    if (cfg->n_modes < 1 || cfg->n_modes > LB_MAX_MODES) throw Fail(LB_ERR_ARG, "n_modes out of range");
+    int total = 0;
+    for (int m = 0; m < cfg->n_modes; ++m) {
+      if (cfg->bits[m] < 1 || cfg->bits[m] > 14) throw Fail(LB_ERR_ARG, "bits out of range (1..14)");
+      total += cfg->bits[m];
+    }
+    if (total > LB_MAX_SITES) throw Fail(LB_ERR_ARG, "too many sites");
+    if (cfg->chi_cap < 1 || cfg->chi_cap > 256) throw Fail(LB_ERR_ARG, "chi_cap out of range (1..256)");
+    if (cfg->chi_mu_cap < 1 || cfg->chi_mu_cap > 256) throw Fail(LB_ERR_ARG, "chi_mu_cap out of range");
+    if (cfg->chi_zip_cap < 0 || cfg->chi_zip_cap > 256) throw Fail(LB_ERR_ARG, "chi_zip_cap out of range");
+    if (!(cfg->tol >= 0.0) || cfg->tol >= 1.0) throw Fail(LB_ERR_ARG, "tol out of range");
+    if (cfg->order != 1 && cfg->order != 2) throw Fail(LB_ERR_ARG, "order must be 1 or 2");
+    if (cfg->precision != LB_FP64 && cfg->precision != LB_FP32_CONTRACT) throw Fail(LB_ERR_ARG, "bad precision");
+    auto s = std::make_unique<lb_solver>();
+    s->cfg = *cfg;
+    s->lay = make_layout(*cfg);
+    s->L = s->lay.n_sites;
+    s->discarded.assign(s->L + 1, 0.0);
+    *out = s.release();
+    return LB_OK;
+  } catch (const Fail& f) {
+    return fail(f);
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return LB_ERR_ARG;
+  }
+}
+
+void lindblad_destroy(lb_solver* s) {
+  if (!s) return;
+  if (s->dev_ready && s->stream) (void)hipStreamSynchronize(s->stream);
+  hipStream_t st = s->stream;
+  bool own = s->own_stream;
+  delete s;
+  if (own && st) (void)hipStreamDestroy(st);
+}
+
+lb_status lindblad_mpo_build(lb_solver* s, const lb_term* terms, int32_t n_terms, double tol, lb_op** out) {
+  try {
+    if (!s || !out || (n_terms > 0 && !terms) || n_terms < 0) throw Fail(LB_ERR_ARG, "NULL argument");
+    auto op = std::make_unique<lb_op>();
+    op->terms = convert_terms(s, terms, n_terms);
+    op->mpo = lb::build_operator(op->terms, s->lay, tol > 0 ? tol : 1e-14);
+    *out = op.get();
+    s->ops.push_back(std::move(op));
+    return LB_OK;
+  } catch (const Fail& f) {
+    return fail(f);
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return LB_ERR_ARG;
+  }
+}
+
+lb_status lindblad_op_info(const lb_op* op, int32_t* n_sites, int32_t* bonds) {
+  if (!op) { g_last_error = "NULL op"; return LB_ERR_ARG; }
+  if (n_sites) *n_sites = (int32_t)op->mpo.size();
+  if (bonds)
+    for (size_t k = 0; k + 1 < op->mpo.size(); ++k) bonds[k] = op->mpo[k].r;
+  return LB_OK;
+}
+
+lb_status lindblad_set_generator(lb_solver* s, const lb_op* H0, const lb_op* H1, const lb_drive* f,
+                                 const lb_op* const* Ls, int32_t n_jumps, double dt) {
+  try {
+    if (!s || !H0) throw Fail(LB_ERR_ARG, "NULL solver or H0");
+    if (!(dt > 0.0) || !std::isfinite(dt)) throw Fail(LB_ERR_ARG, "dt must be positive");
+    if (n_jumps < 0 || n_jumps > 8 || (n_jumps > 0 && !Ls)) throw Fail(LB_ERR_ARG, "bad jump list");
+    const int L = s->L;
+    const double tol = 1e-14, h = dt;
+    // stability estimate of the damping part
+    double gsum = 0.0;
+    for (int k = 0; k < n_jumps; ++k) {
+      if (!Ls[k]) throw Fail(LB_ERR_ARG, "NULL jump operator");
+      const double nb = lb::norm_bound(Ls[k]->terms, s->lay);
+      gsum += nb * nb;
+    }
+    const double x = 0.5 * h * gsum;
+    if (std::fabs(1.0 - x + 0.5 * x * x) > 1.0 && !s->cfg.allow_unstable)
+      throw Fail(LB_ERR_UNSTABLE, "dt too large for the explicit Kraus scheme: x = dt*G/2 = " + std::to_string(x));
+    using namespace lb;
+    std::vector<Mpo> Lm;
+    for (int k = 0; k < n_jumps; ++k) Lm.push_back(Ls[k]->mpo);
+    Mpo G;
+    bool haveG = false;
+    for (auto& l : Lm) {
+      Mpo t = mpo_compress(mpo_mul(mpo_dagger(l), l), tol);
+      G = haveG ? mpo_compress(mpo_add(G, t), tol) : t;
+      haveG = true;
+    }
+    Mpo A = haveG ? mpo_compress(mpo_add(H0->mpo, mpo_scale(G, cd(0.0, -0.5))), tol) : H0->mpo;
+    const bool drive = H1 && f && f->n > 0;
+    Mpo B;
+    if (drive) B = H1->mpo;
+    Mpo eye = mpo_identity(L);
+    auto c = [&](const Mpo& m) { return mpo_compress(m, tol); };
+    auto add = [&](const Mpo& a, const Mpo& b) { return c(mpo_add(a, b)); };
+    std::vector<Mpo> u1{add(eye, mpo_scale(A, cd(0.0, -h)))};
+    if (drive) u1.push_back(c(mpo_scale(B, cd(0.0, -h))));
+    std::vector<std::vector<Mpo>> fam;
+    if (s->cfg.order == 1) {
+      fam.push_back(u1);
+      for (auto& l : Lm) fam.push_back({c(mpo_scale(l, std::sqrt(h)))});
+    } else {
+      Mpo A2 = c(mpo_mul(A, A));
+      std::vector<Mpo> u1p{add(u1[0], mpo_scale(A2, -0.5 * h * h))};
+      if (drive) {
+        Mpo AB = add(c(mpo_mul(A, B)), c(mpo_mul(B, A)));
+        u1p.push_back(add(u1[1], mpo_scale(AB, -0.5 * h * h)));
+        u1p.push_back(c(mpo_scale(c(mpo_mul(B, B)), -0.5 * h * h)));
+      }
+      fam.push_back(u1p);
+      const double sq = std::sqrt(h / 2.0);
+      for (auto& l : Lm) {
+        std::vector<Mpo> v;
+        for (auto& p : u1) v.push_back(c(mpo_scale(c(mpo_mul(p, l)), sq)));
+        fam.push_back(v);
+      }
+      for (auto& l : Lm) {
+        std::vector<Mpo> v;
+        for (auto& p : u1) v.push_back(c(mpo_scale(c(mpo_mul(l, p)), sq)));
+        fam.push_back(v);
+      }
+      for (auto& l : Lm)
+        for (auto& lp : Lm) fam.push_back({c(mpo_scale(c(mpo_mul(l, lp)), h / std::sqrt(2.0)))});
+    }
+    int degree = 1;
+    for (auto& f2 : fam) degree = std::max(degree, (int)f2.size());
+    std::vector<Mpo> polys;
+    for (int p = 0; p < degree; ++p) {
+      std::vector<Mpo> members;
+      for (auto& f2 : fam) members.push_back(p < (int)f2.size() ? f2[p] : mpo_zero(L));
+      polys.push_back(c(kraus_stack(members)));
+    }
+    Mpo W = (degree == 1) ? polys[0] : c(boundary_stack(polys));
+    s->kraus = W;
+    s->n_kraus = (int)fam.size();
+    s->degree = degree;
+    s->dt = dt;
+    s->drv_c.clear(); s->drv_w.clear(); s->drv_p.clear();
+    if (drive)
+      for (int j = 0; j < f->n; ++j) {
+        s->drv_c.push_back(f->coef[j]);
+        s->drv_w.push_back(f->omega[j]);
+        s->drv_p.push_back(f->phase ? f->phase[j] : 0.0);
+      }
+    // device copies; site 0's boundary index handled separately
+    s->wb.assign(L + 1, 1);
+    for (int k = 0; k < L; ++k) s->wb[k + 1] = W[k].r;
+    s->wb[0] = 1;
+    Mpo Wdev = W;
+    std::vector<cd> h0;
+    if (degree > 1) {
+      // site 0 per boundary index p: Wt_p[(s', r)][(0, s)]
+      const Site& x = W[0];
+      const long long per = (long long)2 * x.r * 2;
+      h0.assign((size_t)degree * per, cd(0.0, 0.0));
+      for (int p = 0; p < degree; ++p)
+        for (int o = 0; o < 2; ++o)
+          for (int i = 0; i < 2; ++i)
+            for (int r = 0; r < x.r; ++r) h0[(size_t)p * per + ((size_t)o * x.r + r) * 2 + i] = x.at(p, o, i, r);
+      s->wb0_stride = per;
+      Site z(1, x.r);
+      Wdev[0] = z;
+    }
+    s->kraus_dev = Wdev;
+    s->h0 = h0;
+    s->gen_on_device = false;
+    s->have_gen = true;
+    s->have_state = false;
+    return LB_OK;
+  } catch (const Fail& f) {
+    return fail(f);
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return LB_ERR_ARG;
+  }
+}
+
+lb_status lindblad_kraus_info(const lb_solver* s, int32_t* bonds, int32_t* n_kraus) {
+  if (!s || !s->have_gen) { g_last_error = "no generator"; return LB_ERR_STATE; }
+  if (bonds)
+    for (int k = 0; k + 1 < s->L; ++k) bonds[k] = s->wb[k + 1];
+  if (n_kraus) *n_kraus = s->n_kraus;
+  return LB_OK;
+}
+
+static lb_status load_mps(lb_solver* s, const std::vector<int>& bonds, const std::vector<const cd*>& sites) {
+  const int L = s->L;
+  ensure_generator_on_device(s);
+  for (int i = 0; i < L; ++i) {
+    const size_t cnt = (size_t)bonds[i] * 2 * bonds[i + 1];
+    if (cnt > s->site_cap) throw Fail(LB_ERR_ARG, "site exceeds the capacity implied by the caps");
+    HIPCHK(hipMemcpyAsync(s->X[i].p, sites[i], cnt * sizeof(cd), hipMemcpyHostToDevice, s->stream));
+  }
+  s->chi = bonds;
+  canonicalize(s);
+  s->t = 0.0;
+  s->steps = 0;
+  s->max_defect = 0.0;
+  s->last_tau = 1.0;
+  s->have_state = true;
+  return LB_OK;
+}
+
+lb_status lindblad_set_state_product(lb_solver* s, const double* const* vectors) {
+  try {
+    if (!s || !vectors) throw Fail(LB_ERR_ARG, "NULL argument");
+    const int L = s->L;
+    std::vector<std::vector<cd>> cores(L);
+    std::vector<int> bonds(L + 1, 1);
+    for (int m = 0; m < s->cfg.n_modes; ++m) {
+      if (!vectors[m]) throw Fail(LB_ERR_ARG, "NULL mode vector");
+      const size_t N = (size_t)1 << s->cfg.bits[m];
+      std::vector<cd> v(N);
+      std::memcpy(v.data(), vectors[m], N * sizeof(cd));
+      double nrm = 0.0;
+      for (auto& x : v) nrm += std::norm(x);
+      if (!(nrm > 0.0) || !std::isfinite(nrm)) throw Fail(LB_ERR_ARG, "mode vector is zero or not finite");
+      std::vector<int> b;
+      auto cs = lb::vector_mps(v, 1e-14, b);
+      const int first = s->lay.first[m], len = s->lay.len[m];
+      for (int j = 0; j < len; ++j) {
+        const int src = s->lay.msb_first[m] ? j : len - 1 - j;
+        const int l = b[src], r = b[src + 1];
+        std::vector<cd> core((size_t)l * 2 * r);
+        if (s->lay.msb_first[m]) {
+          core = cs[src];
+        } else {  // reverse: core'[r][s][l] = core[l][s][r]
+          for (int a = 0; a < l; ++a)
+            for (int sg = 0; sg < 2; ++sg)
+              for (int c = 0; c < r; ++c) core[((size_t)c * 2 + sg) * l + a] = cs[src][((size_t)a * 2 + sg) * r + c];
+        }
+        cores[first + j] = core;
+        bonds[first + j] = s->lay.msb_first[m] ? l : r;
+        bonds[first + j + 1] = s->lay.msb_first[m] ? r : l;
+      }
+    }
+    std::vector<const cd*> ptrs(L);
+    for (int i = 0; i < L; ++i) ptrs[i] = cores[i].data();
+    return load_mps(s, bonds, ptrs);
+  } catch (const Fail& f) {
+    return fail(f);
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return LB_ERR_ARG;
+  }
+}
+
+lb_status lindblad_set_state_mps(lb_solver* s, const int32_t* bonds, const double* const* sites) {
+  try {
+    if (!s || !bonds || !sites) throw Fail(LB_ERR_ARG, "NULL argument");
+    const int L = s->L;
+    std::vector<int> b(bonds, bonds + L + 1);
+    if (b[0] != 1) throw Fail(LB_ERR_ARG, "bonds[0] must be 1");
+    for (int i = 1; i <= L; ++i)
+      if (b[i] < 1 || b[i] > 4096) throw Fail(LB_ERR_ARG, "bond out of range");
+    if (b[L] > s->cfg.chi_mu_cap) throw Fail(LB_ERR_ARG, "purification rank exceeds chi_mu_cap");
+    for (int i = 1; i < L; ++i)
+      if (b[i] > s->cfg.chi_cap) throw Fail(LB_ERR_ARG, "bond exceeds chi_cap");
+    std::vector<const cd*> ptrs(L);
+    for (int i = 0; i < L; ++i) {
+      if (!sites[i]) throw Fail(LB_ERR_ARG, "NULL site");
+      ptrs[i] = (const cd*)sites[i];
+    }
+    return load_mps(s, b, ptrs);
+  } catch (const Fail& f) {
+    return fail(f);
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return LB_ERR_ARG;
+  }
+}
+
+lb_status lindblad_get_state_mps(lb_solver* s, int32_t* bonds, double** sites) {
+  try {
+    if (!s || !bonds) throw Fail(LB_ERR_ARG, "NULL argument");
+    if (!s->have_state) throw Fail(LB_ERR_STATE, "no state");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    for (int i = 0; i <= s->L; ++i) bonds[i] = s->chi[i];
+    if (sites)
+      for (int i = 0; i < s->L; ++i) {
+        const size_t cnt = (size_t)s->chi[i] * 2 * s->chi[i + 1];
+        HIPCHK(hipMemcpy(sites[i], s->X[i].p, cnt * sizeof(cd), hipMemcpyDeviceToHost));
+      }
+    return LB_OK;
+  } catch (const Fail& f) {
+    return fail(f);
+  }
+}
+
+lb_status lindblad_step(lb_solver* s, int32_t n_steps) {
+  try {
+    if (!s || n_steps < 0) throw Fail(LB_ERR_ARG, "bad argument");
+    if (!s->have_gen || !s->have_state) throw Fail(LB_ERR_STATE, "set_generator and set_state first");
+    for (int k = 0; k < n_steps; ++k) step_once(s);
+    return LB_OK;
+  } catch (const Fail& f) {
+    return fail(f);
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return LB_ERR_HIP;
+  }
+}
+
+lb_status lindblad_step_batch(lb_solver* const* ss, int32_t n, int32_t n_steps) {
+  try {
+    if (!ss || n < 0 || n_steps < 0) throw Fail(LB_ERR_ARG, "bad argument");
+    for (int j = 0; j < n; ++j) {
+      if (!ss[j]) throw Fail(LB_ERR_ARG, "NULL solver in batch");
+      if (!ss[j]->have_gen || !ss[j]->have_state) throw Fail(LB_ERR_STATE, "solver not ready");
+    }
+    for (int k = 0; k < n_steps; ++k)
+      for (int j = 0; j < n; ++j) step_once(ss[j]);
+    return LB_OK;
+  } catch (const Fail& f) {
+    return fail(f);
+  }
+}
+
+static void upload_op(lb_solver* s, lb_op* op) {
+  ensure_device(s);
+  if (op->uploaded) return;
+  upload_mpo(s, op->mpo, op->dev, false);
+  op->uploaded = true;
+}
+
+lb_status lindblad_observe(lb_solver* s, const lb_op* Oc, double out[2]) {
+  try {
+    if (!s || !Oc || !out) throw Fail(LB_ERR_ARG, "NULL argument");
+    if (!s->have_state) throw Fail(LB_ERR_STATE, "no state");
+    lb_op* O = const_cast<lb_op*>(Oc);
+    upload_op(s, O);
+    const int L = s->L;
+    // E[a*][u][a] in buffer E0; stage buffers T1 (P) and T2 (T), F64
+    std::vector<int> wo(L + 1, 1);
+    for (int k = 0; k < L; ++k) wo[k + 1] = O->dev.wr[k];
+    // transfer buffers: use G2 / Uf / U2-sized scratch big enough for chi^2 wo
+    size_t need = 1;
+    for (int i = 0; i < L; ++i) {
+      need = std::max<size_t>(need, (size_t)s->chi[i] * wo[i] * 2 * s->chi[i + 1]);
+      need = std::max<size_t>(need, (size_t)s->chi[i] * 2 * wo[i + 1] * s->chi[i + 1]);
+      need = std::max<size_t>(need, (size_t)s->chi[i + 1] * wo[i + 1] * s->chi[i + 1]);
+    }
+    DevBuf E, T1, T2;
+    E.alloc(need * 16);
+    T1.alloc(need * 16);
+    T2.alloc(need * 16);
+    DevBuf res;
+    res.alloc(64);
+    for (int i = 0; i < L; ++i) {
+      const int cl = s->chi[i], cr = s->chi[i + 1], ul = wo[i], vr = wo[i + 1];
+      const void* Tin;
+      if (i == 0) {
+        Tin = s->X[0].p;
+      } else {
+        mm(s, cl * ul, 2 * cr, cl, E.p, lbk::F64, cl, false, s->X[i].p, lbk::F64, 2 * cr, false, T1.p,
+           lbk::F64, 2 * cr, lbk::F64);
+        Tin = T1.p;
+      }
+      mm(s, 2 * vr, cr, 2 * ul, O->dev.d64[i].p, lbk::F64, 2 * ul, false, Tin, lbk::F64, cr, false, T2.p,
+         lbk::F64, cr, lbk::F64, cl, 0, (long long)2 * ul * cr, (long long)2 * vr * cr);
+      // E'[b*][(v, b)] = sum_{(a*, s')} conj(X[(a*, s')][b*]) T2[(a*, s')][(v, b)]
+      mm(s, cr, vr * cr, 2 * cl, s->X[i].p, lbk::F64, cr, true, T2.p, lbk::F64, (long long)vr * cr, false,
+         E.p, lbk::F64, (long long)vr * cr, lbk::F64);
+    }
+    HIPCHK(lbk::diag_sum(E.d(), s->chi[L], s->chi[L], res.d(), s->stream));
+    double h[2];
+    HIPCHK(hipMemcpyAsync(h, res.p, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    out[0] = h[0];
+    out[1] = h[1];
+    if (!std::isfinite(h[0]) || !std::isfinite(h[1])) throw Fail(LB_ERR_NUMERIC, "non-finite expectation value");
+    return LB_OK;
+  } catch (const Fail& f) {
+    return fail(f);
+  }
+}
+
+lb_status lindblad_trace_purity(lb_solver* s, double* trace, double* purity) {
+  try {
+    if (!s) throw Fail(LB_ERR_ARG, "NULL solver");
+    if (!s->have_state) throw Fail(LB_ERR_STATE, "no state");
+    const int L = s->L;
+    size_t need = 1;
+    for (int i = 0; i < L; ++i) need = std::max<size_t>(need, (size_t)s->chi[i] * 2 * s->chi[i + 1]);
+    DevBuf E, T1, res;
+    E.alloc(need * 16);
+    T1.alloc(need * 16);
+    res.alloc(64);
+    for (int i = 0; i < L; ++i) {
+      const int cl = s->chi[i], cr = s->chi[i + 1];
+      const void* Tin;
+      if (i == 0) {
+        Tin = s->X[0].p;
+      } else {
+        mm(s, cl, 2 * cr, cl, E.p, lbk::F64, cl, false, s->X[i].p, lbk::F64, 2 * cr, false, T1.p, lbk::F64,
+           2 * cr, lbk::F64);
+        Tin = T1.p;
+      }
+      mm(s, cr, cr, 2 * cl, s->X[i].p, lbk::F64, cr, true, Tin, lbk::F64, cr, false, E.p, lbk::F64, cr,
+         lbk::F64);
+    }
+    HIPCHK(lbk::gram_stats(E.d(), s->chi[L], res.d(), s->stream));
+    double h[2];
+    HIPCHK(hipMemcpyAsync(h, res.p, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (trace) *trace = h[1];
+    if (purity) *purity = h[0] / (h[1] * h[1]);
+    if (!std::isfinite(h[0]) || !std::isfinite(h[1])) throw Fail(LB_ERR_NUMERIC, "non-finite state");
+    return LB_OK;
+  } catch (const Fail& f) {
+    return fail(f);
+  }
+}
+
+lb_status lindblad_diagnostics(lb_solver* s, lb_diag* out) {
+  try {
+    if (!s || !out) throw Fail(LB_ERR_ARG, "NULL argument");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    std::memset(out, 0, sizeof(*out));
+    out->steps = s->steps;
+    out->t = s->t;
+    out->tau = s->last_tau;
+    out->max_tau_defect = s->max_defect;
+    out->n_sites = s->L;
+    for (int i = 0; i + 1 < s->L && !s->chi.empty(); ++i) out->bonds[i] = s->chi[i + 1];
+    out->chi_mu = s->chi.empty() ? 0 : s->chi[s->L];
+    for (int i = 0; i < s->L && i < (int)s->zip_bonds.size(); ++i) out->zip_bonds[i] = s->zip_bonds[i];
+    for (int i = 0; i < s->L && i < (int)s->discarded.size(); ++i) out->discarded[i] = s->discarded[i];
+    int flag = 0;
+    if (s->flag.p) {
+      HIPCHK(hipMemcpy(&flag, s->flag.p, sizeof(int), hipMemcpyDeviceToHost));
+    }
+    if (flag) throw Fail(LB_ERR_NUMERIC, "non-finite trace encountered during a step");
+    return LB_OK;
+  } catch (const Fail& f) {
+    return fail(f);
+  }
+}
+
+static lb_status export_site(const lb::Mpo& m, int32_t site, int32_t* l, int32_t* r, double* w) {
+  if (site < 0 || site >= (int32_t)m.size()) { g_last_error = "site out of range"; return LB_ERR_ARG; }
+  const lb::Site& x = m[site];
+  if (l) *l = x.l;
+  if (r) *r = x.r;
+  if (w) std::memcpy(w, x.w.data(), x.w.size() * sizeof(cd));
+  return LB_OK;
+}
+
+lb_status lindblad_op_site(const lb_op* op, int32_t site, int32_t* l, int32_t* r, double* w) {
+  if (!op) { g_last_error = "NULL op"; return LB_ERR_ARG; }
+  return export_site(op->mpo, site, l, r, w);
+}
+
+lb_status lindblad_kraus_site(const lb_solver* s, int32_t site, int32_t* l, int32_t* r, double* w) {
+  if (!s || !s->have_gen) { g_last_error = "no generator"; return LB_ERR_STATE; }
+  return export_site(s->kraus, site, l, r, w);
+}
+
+const char* lindblad_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,599 @@
+// Device kernels of the purified-MPS Kraus step for gfx950 (MI355X).
+//
+//  * gemm_kernel   complex GEMM on MFMA (v_mfma_f64_16x16x4f64 or
+//                  v_mfma_f32_16x16x4f32), 64x64 output tile per 256-thread
+//                  workgroup (4 waves x 32x32), K staged through LDS in
+//                  slices of 16, one-slice register prefetch, optional
+//                  split-K with a fixed-order reduction.
+//  * heev_kernel   Hermitian eigen-decomposition by cyclic Jacobi with the
+//                  round-robin parallel ordering (one workgroup per matrix).
+//  * small kernels truncation rule, column/row scaling, normalisation,
+//                  precision conversion, drive-boundary contraction.
+#include "kernels.h"
+
+#include <cmath>
+
+namespace lbk {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Acc;
+template <> struct Acc<double> { typedef d4 type; };
+template <> struct Acc<float> { typedef f4 type; };
+
+__device__ inline d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline f4 mfma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+constexpr int BM = 64, BN = 64, BK = 16, PAD = 4, NT = 256;
+
+struct GemmK {
+  int M, N, K, batch, splits, kchunk;
+  const void* A; long long sa_m, sa_k, sa_b; int conjA;
+  const void* B; long long sb_k, sb_n, sb_b; int conjB;
+  void* C; long long sc_m, sc_n, sc_b;
+  double ar, ai, br, bi;
+  void* ws;
+};
+
+template <typename TA, typename TB, typename TC, typename TO>
+__global__ __launch_bounds__(NT) void gemm_kernel(GemmK g) {
+  __shared__ TC As_r[BK][BM + PAD], As_i[BK][BM + PAD];
+  __shared__ TC Bs_r[BK][BN + PAD], Bs_i[BK][BN + PAD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int tiles_n = (g.N + BN - 1) / BN;
+  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+  const int i0 = tm * BM, j0 = tn * BN;
+  const int z = blockIdx.y;
+  const int b = z / g.splits, split = z % g.splits;
+  const int kb = split * g.kchunk;
+  const int ke = min(g.K, kb + g.kchunk);
+
+  const TA* A = reinterpret_cast<const TA*>(g.A) + 2 * (long long)b * g.sa_b;
+  const TB* B = reinterpret_cast<const TB*>(g.B) + 2 * (long long)b * g.sb_b;
+  const bool a_kfast = (g.sa_k == 1);
+  const bool b_nfast = (g.sb_n == 1);
+  const TC sa = g.conjA ? TC(-1) : TC(1);
+  const TC sb = g.conjB ? TC(-1) : TC(1);
+
+  TC ra_r[4], ra_i[4], rb_r[4], rb_i[4];
+
+  auto load_tiles = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid + e * NT;
+      int ii, kk;
+      if (a_kfast) { ii = idx / BK; kk = idx % BK; } else { kk = idx / BM; ii = idx % BM; }
+      const int gi = i0 + ii, gk = k0 + kk;
+      TC vr = 0, vi = 0;
+      if (gi < g.M && gk < ke) {
+        const long long off = 2 * ((long long)gi * g.sa_m + (long long)gk * g.sa_k);
+        vr = (TC)A[off];
+        vi = sa * (TC)A[off + 1];
+      }
+      ra_r[e] = vr; ra_i[e] = vi;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid + e * NT;
+      int jj, kk;
+      if (b_nfast) { kk = idx / BN; jj = idx % BN; } else { jj = idx / BK; kk = idx % BK; }
+      const int gj = j0 + jj, gk = k0 + kk;
+      TC vr = 0, vi = 0;
+      if (gj < g.N && gk < ke) {
+        const long long off = 2 * ((long long)gk * g.sb_k + (long long)gj * g.sb_n);
+        vr = (TC)B[off];
+        vi = sb * (TC)B[off + 1];
+      }
+      rb_r[e] = vr; rb_i[e] = vi;
+    }
+  };
+  auto store_tiles = [&]() {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid + e * NT;
+      int ii, kk;
+      if (a_kfast) { ii = idx / BK; kk = idx % BK; } else { kk = idx / BM; ii = idx % BM; }
+      As_r[kk][ii] = ra_r[e]; As_i[kk][ii] = ra_i[e];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid + e * NT;
+      int jj, kk;
+      if (b_nfast) { kk = idx / BN; jj = idx % BN; } else { jj = idx / BK; kk = idx % BK; }
+      Bs_r[kk][jj] = rb_r[e]; Bs_i[kk][jj] = rb_i[e];
+    }
+  };
+
+  typedef typename Acc<TC>::type AV;
+  AV acc_r[2][2], acc_i[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) { acc_r[x][y] = AV{0, 0, 0, 0}; acc_i[x][y] = AV{0, 0, 0, 0}; }
+
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  if (kb < ke) load_tiles(kb);
+  for (int k0 = kb; k0 < ke; k0 += BK) {
+    __syncthreads();
+    store_tiles();
+    __syncthreads();
+    if (k0 + BK < ke) load_tiles(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      TC a_r[2], a_i[2], b_r[2], b_i[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        a_r[x] = As_r[kk + lk][wm + x * 16 + lr];
+        a_i[x] = As_i[kk + lk][wm + x * 16 + lr];
+        b_r[x] = Bs_r[kk + lk][wn + x * 16 + lr];
+        b_i[x] = Bs_i[kk + lk][wn + x * 16 + lr];
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          acc_r[x][y] = mfma(a_r[x], b_r[y], acc_r[x][y]);
+          acc_r[x][y] = mfma(-a_i[x], b_i[y], acc_r[x][y]);
+          acc_i[x][y] = mfma(a_r[x], b_i[y], acc_i[x][y]);
+          acc_i[x][y] = mfma(a_i[x], b_r[y], acc_i[x][y]);
+        }
+    }
+  }
+
+  // epilogue: lane holds D[4*(lane/16) + r][lane % 16] of each 16x16 block
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wm + x * 16 + 4 * lk + r;
+        const int j = j0 + wn + y * 16 + lr;
+        if (i >= g.M || j >= g.N) continue;
+        const double vr = (double)acc_r[x][y][r], vi = (double)acc_i[x][y][r];
+        if (g.splits > 1) {
+          TC* ws = reinterpret_cast<TC*>(g.ws);
+          const long long off = 2 * ((((long long)b * g.splits + split) * g.M + i) * g.N + j);
+          ws[off] = (TC)vr;
+          ws[off + 1] = (TC)vi;
+        } else {
+          TO* C = reinterpret_cast<TO*>(g.C) + 2 * (long long)b * g.sc_b;
+          const long long off = 2 * ((long long)i * g.sc_m + (long long)j * g.sc_n);
+          double orr = g.ar * vr - g.ai * vi, oi = g.ar * vi + g.ai * vr;
+          if (g.br != 0.0 || g.bi != 0.0) {
+            const double cr = (double)C[off], ci = (double)C[off + 1];
+            orr += g.br * cr - g.bi * ci;
+            oi += g.br * ci + g.bi * cr;
+          }
+          C[off] = (TO)orr;
+          C[off + 1] = (TO)oi;
+        }
+      }
+}
+
+template <typename TC, typename TO>
+__global__ void splitk_reduce(GemmK g) {
+  const long long total = (long long)g.batch * g.M * g.N;
+  const TC* ws = reinterpret_cast<const TC*>(g.ws);
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int b = (int)(e / ((long long)g.M * g.N));
+    const long long ij = e % ((long long)g.M * g.N);
+    const int i = (int)(ij / g.N), j = (int)(ij % g.N);
+    double vr = 0.0, vi = 0.0;
+    for (int s = 0; s < g.splits; ++s) {
+      const long long off = 2 * ((((long long)b * g.splits + s) * g.M + i) * g.N + j);
+      vr += (double)ws[off];
+      vi += (double)ws[off + 1];
+    }
+    TO* C = reinterpret_cast<TO*>(g.C) + 2 * (long long)b * g.sc_b;
+    const long long off = 2 * ((long long)i * g.sc_m + (long long)j * g.sc_n);
+    double orr = g.ar * vr - g.ai * vi, oi = g.ar * vi + g.ai * vr;
+    if (g.br != 0.0 || g.bi != 0.0) {
+      const double cr = (double)C[off], ci = (double)C[off + 1];
+      orr += g.br * cr - g.bi * ci;
+      oi += g.br * ci + g.bi * cr;
+    }
+    C[off] = (TO)orr;
+    C[off + 1] = (TO)oi;
+  }
+}
+
+template <typename TA, typename TB, typename TC, typename TO>
+static hipError_t launch_gemm(const GemmK& k, hipStream_t s) {
+  const int tiles = ((k.M + BM - 1) / BM) * ((k.N + BN - 1) / BN);
+  dim3 grid(tiles, k.batch * k.splits);
+  hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, TO>), grid, dim3(NT), 0, s, k);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || k.splits == 1) return e;
+  const long long total = (long long)k.batch * k.M * k.N;
+  const int blocks = (int)std::min<long long>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL((splitk_reduce<TC, TO>), dim3(blocks), dim3(256), 0, s, k);
+  return hipGetLastError();
+}
+
+template <typename TA, typename TB, typename TC>
+static hipError_t pick_out(const GemmK& k, Prec pc, hipStream_t s) {
+  return pc == F64 ? launch_gemm<TA, TB, TC, double>(k, s) : launch_gemm<TA, TB, TC, float>(k, s);
+}
+template <typename TA, typename TB>
+static hipError_t pick_compute(const GemmK& k, Prec comp, Prec pc, hipStream_t s) {
+  return comp == F64 ? pick_out<TA, TB, double>(k, pc, s) : pick_out<TA, TB, float>(k, pc, s);
+}
+template <typename TA>
+static hipError_t pick_b(const GemmK& k, Prec pb, Prec comp, Prec pc, hipStream_t s) {
+  return pb == F64 ? pick_compute<TA, double>(k, comp, pc, s) : pick_compute<TA, float>(k, comp, pc, s);
+}
+
+hipError_t gemm(const Gemm& g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+  GemmK k;
+  k.M = g.M; k.N = g.N; k.K = g.K; k.batch = g.batch;
+  int splits = std::max(1, g.splits);
+  if (g.K <= 0) splits = 1;
+  int kchunk = (g.K + splits - 1) / splits;
+  kchunk = ((kchunk + BK - 1) / BK) * BK;
+  if (kchunk <= 0) kchunk = BK;
+  splits = std::max(1, (g.K + kchunk - 1) / kchunk);
+  if (splits > 1 && g.ws == nullptr) return hipErrorInvalidValue;
+  k.splits = splits; k.kchunk = kchunk;
+  k.A = g.A; k.sa_m = g.sa_m; k.sa_k = g.sa_k; k.sa_b = g.sa_b; k.conjA = g.conjA;
+  k.B = g.B; k.sb_k = g.sb_k; k.sb_n = g.sb_n; k.sb_b = g.sb_b; k.conjB = g.conjB;
+  k.C = g.C; k.sc_m = g.sc_m; k.sc_n = g.sc_n; k.sc_b = g.sc_b;
+  k.ar = g.alpha_re; k.ai = g.alpha_im; k.br = g.beta_re; k.bi = g.beta_im;
+  k.ws = g.ws;
+  return g.pa == F64 ? pick_b<double>(k, g.pb, g.compute, g.pc, s)
+                     : pick_b<float>(k, g.pb, g.compute, g.pc, s);
+}
+
+// ---------------------------------------------------------------------------
+// Hermitian Jacobi eigen-decomposition
+// ---------------------------------------------------------------------------
+
+struct cplx { double r, i; };
+__device__ inline cplx ld(const double* p, long long e) { return cplx{p[2 * e], p[2 * e + 1]}; }
+__device__ inline void st(double* p, long long e, cplx v) { p[2 * e] = v.r; p[2 * e + 1] = v.i; }
+__device__ inline cplx cmul(cplx a, cplx b) { return cplx{a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+__device__ inline cplx cconj(cplx a) { return cplx{a.r, -a.i}; }
+__device__ inline cplx cadd(cplx a, cplx b) { return cplx{a.r + b.r, a.i + b.i}; }
+__device__ inline cplx cscale(double s, cplx a) { return cplx{s * a.r, s * a.i}; }
+
+constexpr int HEEV_NT = 256;
+constexpr int HEEV_MAXP = 256;   // max pairs per round: n <= 512
+
+// pair of slot t in round r for nn (even) players; p < q
+__device__ inline void rr_pair(int r, int t, int nn, int& p, int& q) {
+  const int m = nn - 1;
+  int x, y;
+  if (t == 0) { x = 0; y = (r % m) + 1; }
+  else { x = ((r + t) % m) + 1; y = (((r - t) % m) + m) % m + 1; }
+  p = min(x, y); q = max(x, y);
+}
+
+__global__ __launch_bounds__(HEEV_NT) void heev_kernel(double* Gall, int ldg, long long g_stride, int n,
+                                                        double* wall, long long w_stride, double* Vall,
+                                                        double rel_tol, int max_sweeps, int* info) {
+  __shared__ int sp[HEEV_MAXP], sq[HEEV_MAXP];
+  __shared__ double sc[HEEV_MAXP], ssr[HEEV_MAXP], ssi[HEEV_MAXP], sda[HEEV_MAXP], sdb[HEEV_MAXP];
+  __shared__ int srot[HEEV_MAXP];
+  __shared__ int nrot;
+  double* G = Gall + 2 * (long long)blockIdx.x * g_stride;
+  double* V = Vall + 2 * (long long)blockIdx.x * n * n;
+  double* w = wall + (long long)blockIdx.x * w_stride;
+  const int tid = threadIdx.x;
+  const int nn = n + (n & 1);
+  const int np = nn / 2;
+
+  for (long long e = tid; e < (long long)n * n; e += HEEV_NT) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    st(V, e, cplx{i == j ? 1.0 : 0.0, 0.0});
+  }
+  int sweeps_used = -1;
+  for (int sweep = 0; sweep < max_sweeps && n > 1; ++sweep) {
+    if (tid == 0) nrot = 0;
+    __syncthreads();
+    for (int r = 0; r < nn - 1; ++r) {
+      for (int t = tid; t < np; t += HEEV_NT) {
+        int p, q;
+        rr_pair(r, t, nn, p, q);
+        sp[t] = p; sq[t] = q;
+        int rot = 0;
+        double c = 1.0, sr = 0.0, si = 0.0, da = 0.0, db = 0.0;
+        if (q < n) {
+          const double a = G[2 * ((long long)p * ldg + p)], bb = G[2 * ((long long)q * ldg + q)];
+          const cplx z = ld(G, (long long)p * ldg + q);
+          const double az = sqrt(z.r * z.r + z.i * z.i);
+          if (az > rel_tol * sqrt(fabs(a * bb)) && az > 1e-300) {
+            const double zeta = (bb - a) / (2.0 * az);
+            const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            const double s = tt * c;
+            sr = s * z.r / az; si = s * z.i / az;
+            da = a - tt * az; db = bb + tt * az;
+            rot = 1;
+          }
+        }
+        sc[t] = c; ssr[t] = sr; ssi[t] = si; sda[t] = da; sdb[t] = db; srot[t] = rot;
+        if (rot) atomicAdd(&nrot, 1);
+      }
+      __syncthreads();
+      // G <- R^H G R, pair block by pair block (upper triangle, mirrored)
+      for (int blk = tid; blk < np * np; blk += HEEV_NT) {
+        const int u = blk / np, v = blk % np;
+        if (u > v) continue;
+        if (!srot[u] && !srot[v]) continue;
+        const int pu = sp[u], qu = sq[u], pv = sp[v], qv = sq[v];
+        if (u == v) {
+          if (qu < n) {
+            st(G, (long long)pu * ldg + pu, cplx{sda[u], 0.0});
+            st(G, (long long)qu * ldg + qu, cplx{sdb[u], 0.0});
+            st(G, (long long)pu * ldg + qu, cplx{0.0, 0.0});
+            st(G, (long long)qu * ldg + pu, cplx{0.0, 0.0});
+          }
+          continue;
+        }
+        // R_x = [[c, s], [-conj(s), c]]
+        const cplx su{ssr[u], ssi[u]}, sv{ssr[v], ssi[v]};
+        const double cu = sc[u], cv = sc[v];
+        const bool qu_ok = qu < n, qv_ok = qv < n;
+        cplx g00 = ld(G, (long long)pu * ldg + pv);
+        cplx g01 = qv_ok ? ld(G, (long long)pu * ldg + qv) : cplx{0, 0};
+        cplx g10 = qu_ok ? ld(G, (long long)qu * ldg + pv) : cplx{0, 0};
+        cplx g11 = (qu_ok && qv_ok) ? ld(G, (long long)qu * ldg + qv) : cplx{0, 0};
+        // columns: [g_0, g_1] R_v
+        cplx h00 = cadd(cscale(cv, g00), cmul(cplx{-sv.r, sv.i}, g01));  // -conj(s_v)
+        cplx h01 = cadd(cmul(sv, g00), cscale(cv, g01));
+        cplx h10 = cadd(cscale(cv, g10), cmul(cplx{-sv.r, sv.i}, g11));
+        cplx h11 = cadd(cmul(sv, g10), cscale(cv, g11));
+        // rows: R_u^H [h_0; h_1], R_u^H = [[c, -s], [conj(s), c]]
+        cplx k00 = cadd(cscale(cu, h00), cmul(cplx{-su.r, -su.i}, h10));
+        cplx k01 = cadd(cscale(cu, h01), cmul(cplx{-su.r, -su.i}, h11));
+        cplx k10 = cadd(cmul(cconj(su), h00), cscale(cu, h10));
+        cplx k11 = cadd(cmul(cconj(su), h01), cscale(cu, h11));
+        st(G, (long long)pu * ldg + pv, k00);
+        st(G, (long long)pv * ldg + pu, cconj(k00));
+        if (qv_ok) { st(G, (long long)pu * ldg + qv, k01); st(G, (long long)qv * ldg + pu, cconj(k01)); }
+        if (qu_ok) { st(G, (long long)qu * ldg + pv, k10); st(G, (long long)pv * ldg + qu, cconj(k10)); }
+        if (qu_ok && qv_ok) { st(G, (long long)qu * ldg + qv, k11); st(G, (long long)qv * ldg + qu, cconj(k11)); }
+      }
+      // V <- V R (columns of each rotated pair)
+      for (int e = tid; e < n * np; e += HEEV_NT) {
+        const int i = e / np, v = e % np;
+        if (!srot[v]) continue;
+        const int pv = sp[v], qv = sq[v];
+        const cplx sv{ssr[v], ssi[v]};
+        const double cv = sc[v];
+        const cplx a = ld(V, (long long)i * n + pv), bq = ld(V, (long long)i * n + qv);
+        st(V, (long long)i * n + pv, cadd(cscale(cv, a), cmul(cplx{-sv.r, sv.i}, bq)));
+        st(V, (long long)i * n + qv, cadd(cmul(sv, a), cscale(cv, bq)));
+      }
+      __syncthreads();
+    }
+    const int done = (nrot == 0);
+    __syncthreads();
+    if (done) { sweeps_used = sweep + 1; break; }
+  }
+  if (n <= 1) sweeps_used = 0;
+  // sort descending (stable by index), write eigenvalues and eigenvectors
+  __shared__ double sw[2 * HEEV_MAXP];
+  __shared__ int rank_of[2 * HEEV_MAXP];
+  for (int j = tid; j < n; j += HEEV_NT) sw[j] = G[2 * ((long long)j * ldg + j)];
+  __syncthreads();
+  for (int j = tid; j < n; j += HEEV_NT) {
+    const double lj = sw[j];
+    int rk = 0;
+    for (int l = 0; l < n; ++l) {
+      const double ll = sw[l];
+      if (ll > lj || (ll == lj && l < j)) ++rk;
+    }
+    rank_of[j] = rk;
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += HEEV_NT) w[rank_of[j]] = sw[j];
+  for (long long e = tid; e < (long long)n * n; e += HEEV_NT) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    st(G, (long long)i * ldg + rank_of[j], ld(V, e));
+  }
+  if (tid == 0 && info) info[blockIdx.x] = sweeps_used;
+}
+
+hipError_t heev_jacobi(double* G, int ldg, long long g_stride, int n, double* w, long long w_stride,
+                       double* V, int batch, double rel_tol, int max_sweeps, int* info,
+                       hipStream_t s) {
+  if (n <= 0 || batch <= 0) return hipSuccess;
+  if (n > 2 * HEEV_MAXP) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(heev_kernel, dim3(batch), dim3(HEEV_NT), 0, s, G, ldg, g_stride, n, w, w_stride,
+                     V, rel_tol, max_sweeps, info);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// small kernels
+// ---------------------------------------------------------------------------
+
+__global__ void truncate_kernel(const double* lam, int n, double tol, int cap, int* k_out, double* disc) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double total = 0.0;
+  for (int j = 0; j < n; ++j) total += fmax(lam[j], 0.0);
+  int k = n;
+  double tail = 0.0;
+  while (k > 1 && tail + fmax(lam[k - 1], 0.0) <= tol * tol * total) {
+    tail += fmax(lam[k - 1], 0.0);
+    --k;
+  }
+  if (cap > 0 && k > cap) {
+    for (int j = cap; j < k; ++j) tail += fmax(lam[j], 0.0);
+    k = cap;
+  }
+  if (k < 1) k = 1;
+  *k_out = k;
+  if (disc) *disc = total > 0.0 ? tail / total : 0.0;
+}
+
+hipError_t truncate_rank(const double* lam, int n, double tol, int cap, int* k_out, double* disc,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(truncate_kernel, dim3(1), dim3(64), 0, s, lam, n, tol, cap, k_out, disc);
+  return hipGetLastError();
+}
+
+__global__ void copy_cols_kernel(const double* src, int lds, double* dst, int ldd, int rows, int cols,
+                                 const double* lam) {
+  const long long total = (long long)rows * cols;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / cols), j = (int)(e % cols);
+    const double f = lam ? sqrt(fmax(lam[j], 0.0)) : 1.0;
+    dst[2 * ((long long)i * ldd + j)] = f * src[2 * ((long long)i * lds + j)];
+    dst[2 * ((long long)i * ldd + j) + 1] = f * src[2 * ((long long)i * lds + j) + 1];
+  }
+}
+
+hipError_t copy_cols(const double* src, int lds, double* dst, int ldd, int rows, int cols,
+                     const double* lam, hipStream_t s) {
+  const long long total = (long long)rows * cols;
+  if (total <= 0) return hipSuccess;
+  const int blocks = (int)std::min<long long>((total + 255) / 256, 2048);
+  hipLaunchKernelGGL(copy_cols_kernel, dim3(blocks), dim3(256), 0, s, src, lds, dst, ldd, rows, cols, lam);
+  return hipGetLastError();
+}
+
+__global__ void scale_rows_kernel(const double* src, int lds, double* dst, int ldd, int rows, int cols,
+                                  const double* lam) {
+  const long long total = (long long)rows * cols;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(e / cols), c = (int)(e % cols);
+    const double l = lam[j];
+    const double f = l > 0.0 ? 1.0 / sqrt(l) : 0.0;
+    dst[2 * ((long long)j * ldd + c)] = f * src[2 * ((long long)j * lds + c)];
+    dst[2 * ((long long)j * ldd + c) + 1] = f * src[2 * ((long long)j * lds + c) + 1];
+  }
+}
+
+hipError_t scale_rows_inv_sqrt(const double* src, int lds, double* dst, int ldd, int rows, int cols,
+                               const double* lam, hipStream_t s) {
+  const long long total = (long long)rows * cols;
+  if (total <= 0) return hipSuccess;
+  const int blocks = (int)std::min<long long>((total + 255) / 256, 2048);
+  hipLaunchKernelGGL(scale_rows_kernel, dim3(blocks), dim3(256), 0, s, src, lds, dst, ldd, rows, cols, lam);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void normalize_kernel(double* x, long long count, double* tau_out, int* flag) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (long long e = threadIdx.x; e < count; e += 256) {
+    const double a = x[2 * e], b = x[2 * e + 1];
+    acc += a * a + b * b;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double tau = red[0];
+  const bool ok = isfinite(tau) && tau > 0.0;
+  const double f = ok ? 1.0 / sqrt(tau) : 1.0;
+  for (long long e = threadIdx.x; e < 2 * count; e += 256) x[e] *= f;
+  if (threadIdx.x == 0) {
+    *tau_out = tau;
+    if (!ok && flag) *flag = 1;
+  }
+}
+
+hipError_t normalize(double* x, long long count, double* tau_out, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(normalize_kernel, dim3(1), dim3(256), 0, s, x, count, tau_out, flag);
+  return hipGetLastError();
+}
+
+__global__ void to_f32_kernel(const double* src, float* dst, long long n) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    dst[e] = (float)src[e];
+}
+
+hipError_t to_f32(const double* src, float* dst, long long count, hipStream_t s) {
+  const long long n = 2 * count;
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(to_f32_kernel, dim3(blocks), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+__global__ void boundary_kernel(const double* Wb, long long stride, int degree, double f,
+                                double* W0, float* W0f, long long count) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < count;
+       e += (long long)gridDim.x * blockDim.x) {
+    double vr = 0.0, vi = 0.0, c = 1.0;
+    for (int p = 0; p < degree; ++p) {
+      vr += c * Wb[2 * (p * stride + e)];
+      vi += c * Wb[2 * (p * stride + e) + 1];
+      c *= f;
+    }
+    W0[2 * e] = vr; W0[2 * e + 1] = vi;
+    if (W0f) { W0f[2 * e] = (float)vr; W0f[2 * e + 1] = (float)vi; }
+  }
+}
+
+hipError_t boundary_contract(const double* Wb, long long stride, int degree, double f,
+                             double* W0, float* W0f, long long count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const int blocks = (int)std::min<long long>((count + 255) / 256, 1024);
+  hipLaunchKernelGGL(boundary_kernel, dim3(blocks), dim3(256), 0, s, Wb, stride, degree, f, W0, W0f, count);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void diag_sum_kernel(const double* E, int n, long long ld, double* out) {
+  __shared__ double rr[256], ri[256];
+  double a = 0.0, b = 0.0;
+  for (int j = threadIdx.x; j < n; j += 256) {
+    a += E[2 * ((long long)j * ld + j)];
+    b += E[2 * ((long long)j * ld + j) + 1];
+  }
+  rr[threadIdx.x] = a; ri[threadIdx.x] = b;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) { rr[threadIdx.x] += rr[threadIdx.x + s]; ri[threadIdx.x] += ri[threadIdx.x + s]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { out[0] = rr[0]; out[1] = ri[0]; }
+}
+
+hipError_t diag_sum(const double* E, int n, long long ld, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(diag_sum_kernel, dim3(1), dim3(256), 0, s, E, n, ld, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void gram_stats_kernel(const double* E, int n, double* out) {
+  __shared__ double ra[256], rt[256];
+  double a = 0.0, t = 0.0;
+  for (long long e = threadIdx.x; e < (long long)n * n; e += 256) {
+    const double x = E[2 * e], y = E[2 * e + 1];
+    a += x * x + y * y;
+    if (e / n == e % n) t += x;
+  }
+  ra[threadIdx.x] = a; rt[threadIdx.x] = t;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) { ra[threadIdx.x] += ra[threadIdx.x + s]; rt[threadIdx.x] += rt[threadIdx.x + s]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { out[0] = ra[0]; out[1] = rt[0]; }
+}
+
+hipError_t gram_stats(const double* E, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(gram_stats_kernel, dim3(1), dim3(256), 0, s, E, n, out);
+  return hipGetLastError();
+}
+
+}  // namespace lbk

@@ -1,0 +1,124 @@
+"""CPU tests of the C-ABI library: it loads, exports every declared symbol,
+and its host-side MPO construction (no device work) matches the oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workload as wl
+from oracle import dense, tt
+from oracle.operators import factor_matrix
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib_or_skip():
+    from paper_2605_27515_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("liblindblad.so not built")
+    return _lib
+
+
+def _declared_symbols():
+    names = set()
+    for h in ("lindblad.h", "lindblad_kernels.h"):
+        text = open(os.path.join(ROOT, "include", h)).read()
+        names |= set(re.findall(r"^\s*(?:lb_status|void|const char\*)\s+(lindblad_\w+)\s*\(", text, re.M))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    lib_mod = _lib_or_skip()
+    raw = ctypes.CDLL(lib_mod.LIB_PATH)
+    declared = _declared_symbols()
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(raw, name), name
+    assert set(declared) == set(lib_mod.EXPORTED)
+
+
+@pytest.mark.parametrize("factor", ["ID", ("A_POW", 1), ("A_POW", 2), ("ADAG_POW", 2), ("ADAG_A", 2, 1),
+                                    ("ADAG_A", 1, 2), ("NUM_POW", 2), ("CHARGE_POW", 2, 8),
+                                    ("SHIFT", 1), ("SHIFT", -3)])
+@pytest.mark.parametrize("msb_first", [True, False])
+def test_host_mpo_builder_matches_dense(factor, msb_first):
+    _lib_or_skip()
+    from paper_2605_27515_amd import api
+    so = [(0, b) for b in (range(5) if msb_first else reversed(range(5)))]
+    s = api.Solver([5], 8, 2, site_order=so)
+    op = s.mpo([(1.0, {0: factor})])
+    ref = factor_matrix(factor, 32)
+    err = np.linalg.norm(tt.mpo_to_dense(op.sites(), [5], so) - ref)
+    assert err <= 1e-13 * max(1.0, np.linalg.norm(ref))
+    s.close()
+
+
+def test_host_polynomial_ranks_exact():
+    """(a^dag)^m a^m has exact quantics rank m + 1 (paper Table I)."""
+    _lib_or_skip()
+    from paper_2605_27515_amd import api
+    s = api.Solver([10], 8, 2)
+    for m in (1, 2, 3):
+        assert max(s.mpo([(1.0, {0: ("ADAG_A", m, m)})]).bonds()) == m + 1
+    s.close()
+
+
+@pytest.mark.parametrize("which", ["coherent", "cat-buffer", "transmon"])
+def test_host_kraus_mpo_matches_dense_family(which):
+    _lib_or_skip()
+    from paper_2605_27515_amd import api
+    m = {"coherent": wl.model_coherent_loss(),
+         "cat-buffer": wl.model_cat_buffer(Ra=3, Rb=2, alpha2=2.0, dt=1e-3),
+         "transmon": wl.model_transmon_resonator(Rt=3, Rr=2, dt=1e-3)}[which]
+    s = api.solver_from_model(m, state="none")
+    W = s.kraus_sites()
+    so = m.site_order()
+    dm = dense.DenseModel(m)
+    K = tt.KrausMPO(m, m.dt)
+    for t in (0.0, 0.3):
+        fam = dense.kraus_family(dm, t, m.dt)
+        Wt = W
+        if W[0].shape[0] > 1:
+            f = K.f(t + 0.5 * m.dt)
+            Wt = tt.contract_boundary(W, [f ** p for p in range(W[0].shape[0])])
+        for j, kd in enumerate(fam):
+            w = list(Wt)
+            w[-1] = w[-1][:, :, :, j:j + 1]
+            assert np.abs(tt.mpo_to_dense(w, m.bits, so) - kd).max() < 1e-12
+    bonds, nk = s.kraus_info()
+    assert nk == len(fam)
+    assert bonds == K.bonds
+    # canonical gauge: sites 1.. right-orthonormal
+    for w in W[1:]:
+        M = w.reshape(w.shape[0], -1)
+        assert np.abs(M @ M.conj().T - np.eye(w.shape[0])).max() < 1e-12
+    s.close()
+
+
+def test_argument_errors():
+    _lib_or_skip()
+    from paper_2605_27515_amd import api
+    from paper_2605_27515_amd._lib import LB_ERR_ARG, LB_ERR_UNSTABLE, LB_ERR_STATE
+    with pytest.raises(api.LindbladError) as e:
+        api.Solver([0], 8, 2)
+    assert e.value.code == LB_ERR_ARG
+    with pytest.raises(api.LindbladError) as e:
+        api.Solver([4], 1000, 2)
+    assert e.value.code == LB_ERR_ARG
+    s = api.Solver([4], 8, 2)
+    with pytest.raises(api.LindbladError) as e:
+        s.mpo([(1.0, {3: ("A_POW", 1)})])
+    assert e.value.code == LB_ERR_ARG
+    with pytest.raises(api.LindbladError) as e:
+        s.step(1)
+    assert e.value.code == LB_ERR_STATE
+    s.close()
+    # the stated dt of the two-photon cat violates the explicit-scheme bound
+    m = wl.model_two_photon_cat(R=8, dt=1e-3)
+    with pytest.raises(api.LindbladError) as e:
+        api.solver_from_model(m, state="none")
+    assert e.value.code == LB_ERR_UNSTABLE
+    s = api.solver_from_model(wl.model_two_photon_cat(R=8, dt=5e-5), state="none")
+    s.close()

@@ -1,0 +1,91 @@
+"""GPU parity of the individual kernels against plain NumPy / the oracle's
+truncation rule (through the component C ABI, include/lindblad_kernels.h)."""
+import numpy as np
+import pytest
+
+import workload as wl
+from oracle import tt
+
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    from paper_2605_27515_amd import api
+    return api
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (17, 33, 5), (64, 64, 16), (100, 70, 129), (256, 96, 1000),
+                                   (3, 300, 64)])
+@pytest.mark.parametrize("adj", [(False, False), (True, False), (False, True), (True, True)])
+def test_zgemm_fp64(shape, adj):
+    api = _api()
+    M, N, K = shape
+    A = wl.random_matrix(K if adj[0] else M, M if adj[0] else K, seed=1)
+    B = wl.random_matrix(N if adj[1] else K, K if adj[1] else N, seed=2)
+    ref = (A.conj().T if adj[0] else A) @ (B.conj().T if adj[1] else B)
+    for splits in (1, 4):
+        C = api.kernel_zgemm(A, B, adj[0], adj[1], "fp64", splits)
+        # FP64 with K-term sums: relative error a few eps * sqrt(K)
+        assert np.abs(C - ref).max() <= 1e-14 * np.sqrt(K) * np.abs(A).max() * np.abs(B).max() * K ** 0.5 + 1e-300
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 64), (130, 90, 257)])
+def test_zgemm_fp32(shape):
+    api = _api()
+    M, N, K = shape
+    A = wl.random_matrix(M, K, seed=3)
+    B = wl.random_matrix(K, N, seed=4)
+    ref = A @ B
+    C = api.kernel_zgemm(A, B, precision="fp32")
+    rel = np.abs(C - ref).max() / np.abs(ref).max()
+    assert rel < 2e-6 * np.sqrt(K / 64)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 16, 33, 64, 100, 128])
+def test_heev_parity(n):
+    api = _api()
+    X = wl.random_matrix(n, n + 3, seed=10 + n)
+    G = X @ X.conj().T
+    w, U, sweeps = api.kernel_heev(G)
+    assert sweeps > 0 or n == 1
+    ref = np.linalg.eigvalsh(G)[::-1]
+    scale = np.abs(ref).max()
+    assert np.abs(w - ref).max() <= 1e-13 * scale
+    assert np.abs(U.conj().T @ U - np.eye(n)).max() < 1e-13
+    assert np.abs(U @ np.diag(w) @ U.conj().T - G).max() <= 1e-13 * scale
+
+
+def test_heev_graded_spectrum_relative_accuracy():
+    """Graded PSD matrices (the second pass of the factorisation): eigenvalues
+    to high relative accuracy down to 1e-24 of the largest."""
+    api = _api()
+    n = 48
+    lam = 10.0 ** (-np.linspace(0, 24, n))
+    Q = wl.random_matrix(n, n, seed=5, spectrum=np.ones(n))
+    # nearly diagonal graded matrix: D^(1/2) (I + E) D^(1/2), small E
+    E = 1e-3 * (Q + Q.conj().T)
+    D = np.diag(np.sqrt(lam))
+    G = D @ (np.eye(n) + E) @ D
+    w, U, _ = api.kernel_heev(G)
+    ref = np.sort(np.linalg.eigvalsh(np.eye(n) + E))  # only used for scale sanity
+    assert np.all(np.diff(w) <= 0)
+    rel = np.abs(w - lam) / lam
+    assert rel.max() < 5e-3          # eigenvalues within the O(E) perturbation
+    # reconstruction in the relative (graded) norm
+    R = U @ np.diag(w) @ U.conj().T - G
+    Dinv = np.diag(1.0 / np.sqrt(lam))
+    assert np.abs(Dinv @ R @ Dinv).max() < 1e-12
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_truncate_bit_exact(case):
+    api = _api()
+    rng = np.random.Generator(np.random.PCG64(wl.SEED + case))
+    n = [1, 5, 64, 100, 256, 33][case]
+    s = np.sort(np.abs(rng.standard_normal(n)) * 10.0 ** (-rng.uniform(0, 12, n)))[::-1]
+    for tol, cap in [(1e-8, 0), (1e-8, 16), (1e-3, 0), (0.0, 8), (1e-8, 1)]:
+        k, disc = api.kernel_truncate(s ** 2, tol, cap)
+        kref = tt.keep_rank(s, tol, cap if cap > 0 else None)
+        assert k == kref
+        total = np.sum(s ** 2)
+        assert abs(disc - np.sum(s[k:] ** 2) / total) <= 1e-14
