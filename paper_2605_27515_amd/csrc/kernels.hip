@@ -149,14 +149,17 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmK g) {
     }
   }
 
-  // epilogue: lane holds D[4*(lane/16) + r][lane % 16] of each 16x16 block
+  // epilogue.  Output layout of each 16x16 block (measured on gfx950):
+  //   v_mfma_f32_16x16x4f32: register r of lane l holds D[4*(l/16) + r][l%16]
+  //   v_mfma_f64_16x16x4f64: register r of lane l holds D[4*r + l/16][l%16]
+  constexpr bool f64acc = sizeof(TC) == 8;
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = i0 + wm + x * 16 + 4 * lk + r;
+        const int i = i0 + wm + x * 16 + (f64acc ? 4 * r + lk : 4 * lk + r);
         const int j = j0 + wn + y * 16 + lr;
         if (i >= g.M || j >= g.N) continue;
         const double vr = (double)acc_r[x][y][r], vi = (double)acc_i[x][y][r];
