@@ -26,12 +26,14 @@ lb_status lindblad_kernel_zgemm(int32_t M, int32_t N, int32_t K, const double* A
                                 const double* B, int32_t adj_b, double* C, int32_t precision,
                                 int32_t splits);
 
-/* Eigen-decomposition of a Hermitian n x n matrix G (n <= 512) by the
- * device Jacobi kernel: w (n, descending) and U (n x n, eigenvectors as
- * columns).  *sweeps receives the sweeps used (-1: not converged).
- * This is the factorisation behind every truncated SVD of the step.
- * Errors: LB_ERR_ARG, LB_ERR_HIP. */
-lb_status lindblad_kernel_heev(int32_t n, const double* G, double* w, double* U, int32_t* sweeps);
+/* Eigen-decomposition of a Hermitian n x n matrix G (n <= 512): w (n,
+ * descending) and U (n x n, eigenvectors as columns).  method 0: cyclic
+ * Jacobi (relative accuracy; *sweeps = sweeps used, -1 if not converged);
+ * method 1: Householder tridiagonalisation + bisection + inverse iteration
+ * (absolute accuracy; *sweeps = 0).  These are the factorisations behind
+ * every truncated SVD of the step.  Errors: LB_ERR_ARG, LB_ERR_HIP. */
+lb_status lindblad_kernel_heev(int32_t n, const double* G, double* w, double* U, int32_t* sweeps,
+                               int32_t method);
 
 /* Truncation rule on descending squared singular values lam (n): smallest
  * k >= 1 with sum_{j>k} lam_j <= tol^2 sum_j lam_j, then min(k, cap);

@@ -105,7 +105,7 @@ def load() -> C.CDLL:
     dp = C.POINTER(C.c_double)
     lib.lindblad_kernel_zgemm.argtypes = [C.c_int32, C.c_int32, C.c_int32, dp, C.c_int32, dp, C.c_int32,
                                           dp, C.c_int32, C.c_int32]
-    lib.lindblad_kernel_heev.argtypes = [C.c_int32, dp, dp, dp, C.POINTER(C.c_int32)]
+    lib.lindblad_kernel_heev.argtypes = [C.c_int32, dp, dp, dp, C.POINTER(C.c_int32), C.c_int32]
     lib.lindblad_kernel_truncate.argtypes = [C.c_int32, dp, C.c_double, C.c_int32, C.POINTER(C.c_int32), dp]
     lib.lindblad_last_error.argtypes = []
     lib.lindblad_last_error.restype = C.c_char_p

@@ -253,14 +253,15 @@ def kernel_zgemm(A: np.ndarray, B: np.ndarray, adj_a: bool = False, adj_b: bool 
     return C_
 
 
-def kernel_heev(G: np.ndarray):
+def kernel_heev(G: np.ndarray, method: str = "jacobi"):
     G = np.ascontiguousarray(G, np.complex128)
     n = G.shape[0]
     w = np.zeros(n)
     U = np.zeros((n, n), np.complex128)
     sw = C.c_int32()
     _check(L.load().lindblad_kernel_heev(n, _dptr(G.view(np.float64)), _dptr(w),
-                                         _dptr(U.view(np.float64)), C.byref(sw)), "kernel_heev")
+                                         _dptr(U.view(np.float64)), C.byref(sw),
+                                         1 if method == "tridiag" else 0), "kernel_heev")
     return w, U, sw.value
 
 

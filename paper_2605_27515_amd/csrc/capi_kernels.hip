@@ -62,21 +62,32 @@ lb_status lindblad_kernel_zgemm(int32_t M, int32_t N, int32_t K, const double* A
   return rc;
 }
 
-lb_status lindblad_kernel_heev(int32_t n, const double* G, double* w, double* U, int32_t* sweeps) {
+lb_status lindblad_kernel_heev(int32_t n, const double* G, double* w, double* U, int32_t* sweeps,
+                               int32_t method) {
   if (n <= 0 || n > 512 || !G || !w || !U) return LB_ERR_ARG;
   hipStream_t s;
   hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
   if (e != hipSuccess) return hip_fail(e, "stream");
   const size_t nn = (size_t)n * n;
-  Dev dG(nn * 16), dV(nn * 16), dw(n * 8), di(16);
+  Dev dG(nn * 16), dV(nn * 16), dw(n * 8), di(16), dwork(lbk::heev_tridiag_work_doubles(n) * 8);
   lb_status rc = LB_OK;
   do {
-    if (!dG.p || !dV.p || !dw.p || !di.p) { rc = LB_ERR_OOM; break; }
+    if (!dG.p || !dV.p || !dw.p || !di.p || !dwork.p) { rc = LB_ERR_OOM; break; }
     if ((e = hipMemcpyAsync(dG.p, G, nn * 16, hipMemcpyHostToDevice, s)) != hipSuccess) { rc = hip_fail(e, "copy"); break; }
-    if ((e = lbk::heev_jacobi((double*)dG.p, n, 0, n, (double*)dw.p, 0, (double*)dV.p, 1, 1.5e-15, 40,
-                              (int*)di.p, s)) != hipSuccess) { rc = hip_fail(e, "heev"); break; }
+    if ((e = hipMemsetAsync(di.p, 0, 16, s)) != hipSuccess) { rc = hip_fail(e, "memset"); break; }
+    if (method == 1) {
+      if ((e = lbk::heev_tridiag((double*)dG.p, n, n, (double*)dw.p, (double*)dV.p, n, n, (double*)dwork.p, s)) != hipSuccess) { rc = hip_fail(e, "heev_tridiag"); break; }
+      // same clean-up as the solver: two Newton-Schulz polar steps (G is scratch now)
+      Dev dT(nn * 16);
+      if (!dT.p) { rc = LB_ERR_OOM; break; }
+      if ((e = lbk::orthonormalize_columns((double*)dV.p, n, n, n, (double*)dG.p, (double*)dT.p, 2, s)) != hipSuccess) { rc = hip_fail(e, "orthonormalize"); break; }
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) { rc = hip_fail(e, "sync"); break; }
+    } else {
+      if ((e = lbk::heev_jacobi((double*)dG.p, n, 0, n, (double*)dw.p, 0, (double*)dV.p, 1, 1.5e-15, 40,
+                                (int*)di.p, s)) != hipSuccess) { rc = hip_fail(e, "heev"); break; }
+    }
     int info = 0;
-    if ((e = hipMemcpyAsync(U, dG.p, nn * 16, hipMemcpyDeviceToHost, s)) != hipSuccess) { rc = hip_fail(e, "copy"); break; }
+    if ((e = hipMemcpyAsync(U, method == 1 ? dV.p : dG.p, nn * 16, hipMemcpyDeviceToHost, s)) != hipSuccess) { rc = hip_fail(e, "copy"); break; }
     if ((e = hipMemcpyAsync(w, dw.p, n * 8, hipMemcpyDeviceToHost, s)) != hipSuccess) { rc = hip_fail(e, "copy"); break; }
     if ((e = hipMemcpyAsync(&info, di.p, 4, hipMemcpyDeviceToHost, s)) != hipSuccess) { rc = hip_fail(e, "copy"); break; }
     if ((e = hipStreamSynchronize(s)) != hipSuccess) { rc = hip_fail(e, "sync"); break; }

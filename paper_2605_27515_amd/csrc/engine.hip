@@ -136,7 +136,7 @@ struct lb_solver {
   size_t site_cap = 0;        // complex elements per site buffer
 
   // workspace
-  DevBuf C, P, T, Bm, G, G2, U2, Uf, V, lam, lam2, ws, kdev, disc, tau, flag, info, scratch;
+  DevBuf C, P, T, Bm, G, G2, U2, Uf, U0, V, lam, lam2, ws, kdev, disc, tau, flag, info, scratch, ework;
   size_t ws_bytes = 0;
   int n_max = 0;
   long long m_max = 0;
@@ -279,14 +279,29 @@ void gram_cols(lb_solver* s, const void* A, Prec pa, int n, int m, long long lda
   check_gemm(lbk::gemm(g, s->stream), "gram_cols");
 }
 
-void eig(lb_solver* s, double* G, int n, double* lam) {
+void mm(lb_solver* s, int M, int N, int K, const void* A, Prec pa, long long lda, bool adjA,
+        const void* B, Prec pb, long long ldb, bool adjB, void* C, Prec pc, long long ldc, Prec comp,
+        int batch = 1, long long sa_b = 0, long long sb_b = 0, long long sc_b = 0);
+
+// Jacobi (relative accuracy; second pass of LB_FP64): eigenvectors in G.
+void eig_jacobi(lb_solver* s, double* G, int n, double* lam) {
   HIPCHK(lbk::heev_jacobi(G, n, 0, n, lam, 0, s->V.d(), 1, 1.5e-15, 40, s->info.i(), s->stream));
+}
+
+// Tridiagonal route (absolute accuracy): G destroyed, all eigenvalues in
+// lam, the eigenvectors of the kvec largest in U (ld n), made orthonormal to
+// rounding by two Newton-Schulz polar steps U <- U (3I - U^H U)/2 (inverse
+// iteration leaves eps ||G|| / gap of mutual overlap between vectors).
+void eig_trid(lb_solver* s, double* G, int n, double* lam, double* U, int kvec) {
+  kvec = std::min(kvec, n);
+  HIPCHK(lbk::heev_tridiag(G, n, n, lam, U, n, kvec, s->ework.d(), s->stream));
+  HIPCHK(lbk::orthonormalize_columns(U, n, n, kvec, s->scratch.d(), s->U2.d(), 2, s->stream));
 }
 
 // C = op(A) op(B) with row-major dense operands described by leading dims.
 void mm(lb_solver* s, int M, int N, int K, const void* A, Prec pa, long long lda, bool adjA,
         const void* B, Prec pb, long long ldb, bool adjB, void* C, Prec pc, long long ldc, Prec comp,
-        int batch = 1, long long sa_b = 0, long long sb_b = 0, long long sc_b = 0) {
+        int batch, long long sa_b, long long sb_b, long long sc_b) {
   Gemm g;
   g.M = M; g.N = N; g.K = K; g.batch = batch;
   g.A = A; g.pa = pa; g.sa_b = sa_b;
@@ -301,24 +316,34 @@ void mm(lb_solver* s, int M, int N, int K, const void* A, Prec pa, long long lda
 }
 
 // Left singular vectors / squared singular values of the n x m matrix A
-// (row-major, leading dim lda): on return Uout (n x n, ld n) and lamout (n).
-// Two passes in FP64 mode; `Bout` (n x m, ld m) then holds U2^H U0^H A, the
-// rows sigma_j v_j^H (used for carries).  Returns the device pointer of U.
-double* left_svd(lb_solver* s, const void* A, Prec pa, int n, long long m, long long lda, bool want_b) {
+// (row-major, leading dim lda).  Returns the device pointer of U (n x n, ld
+// n; the first kvec columns are valid) and leaves the eigenvalues in s->lam.
+// LB_FP64 runs two passes: the tridiagonal route gives U0 (all n vectors),
+// one Newton-Schulz step makes it unitary to rounding, then B = U0^H A,
+// G2 = B B^H is nearly diagonal with graded rows and Jacobi with a relative
+// threshold restores absolute FP64 accuracy of the small singular values.
+// `Bout` then holds U2^H B = rows sigma_j v_j^H (used for carries).
+double* left_svd(lb_solver* s, const void* A, Prec pa, int n, long long m, long long lda, bool want_b,
+                 int kvec) {
   double* G = s->G.d();
   gram_rows(s, A, pa, n, m, lda, G);
-  eig(s, G, n, s->lam.d());
-  if (passes(s) == 1) return G;
-  // second pass: B = U0^H A, G2 = B B^H, eigen(G2) -> U2, U = U0 U2
+  double* U0 = s->U0.d();
+  if (passes(s) == 1) {
+    eig_trid(s, G, n, s->lam.d(), U0, kvec);
+    return U0;
+  }
+  eig_trid(s, G, n, s->lam.d(), U0, n);
+  double* U0o = s->Uf.d();
+  HIPCHK(lbk::copy_cols(U0, n, U0o, n, n, n, nullptr, s->stream));
+  // second pass: B = U0^H A, G2 = B B^H, Jacobi(G2) -> U2, U = U0 U2
   double* B = s->Bm.d();
-  mm(s, n, (int)m, n, G, lbk::F64, n, true, A, pa, lda, false, B, lbk::F64, m, lbk::F64);
+  mm(s, n, (int)m, n, U0o, lbk::F64, n, true, A, pa, lda, false, B, lbk::F64, m, lbk::F64);
   double* G2 = s->G2.d();
   gram_rows(s, B, lbk::F64, n, m, m, G2);
-  eig(s, G2, n, s->lam.d());
-  double* Uf = s->Uf.d();
-  mm(s, n, n, n, G, lbk::F64, n, false, G2, lbk::F64, n, false, Uf, lbk::F64, n, lbk::F64);
+  eig_jacobi(s, G2, n, s->lam.d());
+  double* Uf = s->U0.d();
+  mm(s, n, n, n, U0o, lbk::F64, n, false, G2, lbk::F64, n, false, Uf, lbk::F64, n, lbk::F64);
   if (want_b) {
-    // rows of U2^H B in place of B (scratch T-sized buffer then swap)
     double* B2 = s->U2.d();
     mm(s, n, (int)m, n, G2, lbk::F64, n, true, B, lbk::F64, m, false, B2, lbk::F64, m, lbk::F64);
     std::swap(s->Bm.p, s->U2.p);
@@ -357,7 +382,9 @@ void alloc_workspace(lb_solver* s) {
   s->G.alloc(nn);
   s->G2.alloc(nn);
   s->Uf.alloc(nn);
+  s->U0.alloc(nn);
   s->V.alloc(nn);
+  s->ework.alloc(lbk::heev_tridiag_work_doubles(nmax) * sizeof(double));
   s->Bm.alloc((size_t)nmax * std::max<long long>(mmax, nmax) * 16);
   s->U2.alloc((size_t)nmax * std::max<long long>(mmax, nmax) * 16);
   s->lam.alloc((size_t)nmax * 8);
@@ -466,7 +493,7 @@ void zipup(lb_solver* s) {
     const int n = 2 * zk;
     const long long m = (long long)wr * cr;
     if (i < L - 1) {
-      double* U = left_svd(s, s->T.p, pw, n, m, m, passes(s) == 2);
+      double* U = left_svd(s, s->T.p, pw, n, m, m, passes(s) == 2, zc);
       HIPCHK(lbk::truncate_rank(s->lam.d(), n, tolz, zc, s->kdev.i(), s->disc.d(), s->stream));
       const int k = read_k(s);
       // new site X_i[(a', s')][k] = U[:, :k]
@@ -486,17 +513,19 @@ void zipup(lb_solver* s) {
       const int mc = (int)m;
       double* Gc = s->G.d();
       gram_cols(s, s->T.p, pw, n, mc, m, Gc);
-      eig(s, Gc, mc, s->lam.d());
-      double* Vf = Gc;
+      double* V0 = s->U0.d();
+      eig_trid(s, Gc, mc, s->lam.d(), V0, passes(s) == 2 ? mc : std::min(mc, s->cfg.chi_mu_cap));
+      double* Vf = V0;
       const void* Asrc = s->T.p;
       Prec asrc = pw;
       if (passes(s) == 2) {
-        // B' = T V0 (columns sigma_j u_j), G2' = B'^H B', eigen -> V2
+        // B' = T V0 (columns sigma_j u_j), G2' = B'^H B', Jacobi -> V2
+        double* V0o = V0;
         double* Bc = s->Bm.d();
-        mm(s, n, mc, mc, s->T.p, pw, m, false, Gc, lbk::F64, mc, false, Bc, lbk::F64, mc, lbk::F64);
+        mm(s, n, mc, mc, s->T.p, pw, m, false, V0o, lbk::F64, mc, false, Bc, lbk::F64, mc, lbk::F64);
         double* G2 = s->G2.d();
         gram_cols(s, Bc, lbk::F64, n, mc, mc, G2);
-        eig(s, G2, mc, s->lam.d());
+        eig_jacobi(s, G2, mc, s->lam.d());
         Vf = G2;
         Asrc = Bc;
         asrc = lbk::F64;
@@ -521,7 +550,7 @@ void back_sweep(lb_solver* s, double tol, bool record) {
   for (int i = L - 1; i >= 1; --i) {
     const int l = s->chi[i], r = s->chi[i + 1];
     const long long m = 2LL * r;
-    double* U = left_svd(s, s->X[i].p, lbk::F64, l, m, m, passes(s) == 2);
+    double* U = left_svd(s, s->X[i].p, lbk::F64, l, m, m, passes(s) == 2, s->cap[i]);
     HIPCHK(lbk::truncate_rank(s->lam.d(), l, tol, s->cap[i], s->kdev.i(), s->disc.d(), s->stream));
     const int k = read_k(s);
     if (record && i < (int)s->discarded.size()) s->discarded[i] = read_disc(s);

@@ -39,6 +39,22 @@ hipError_t heev_jacobi(double* G, int ldg, long long g_stride, int n, double* w,
                        double* V, int batch, double rel_tol, int max_sweeps, int* info,
                        hipStream_t stream);
 
+// Hermitian eigen-decomposition through a real tridiagonal form (Householder
+// reduction, bisection, inverse iteration, back-transformation).  G (n x n,
+// ld ldg, n <= 512) is destroyed; w[0..n) receives all eigenvalues in
+// descending order; U (ld ldu) receives the eigenvectors of the kvec largest
+// as its first kvec columns.  `work` holds heev_tridiag_work_doubles(n).
+// Accuracy is absolute (eps * ||G||), as for any backward-stable method.
+hipError_t heev_tridiag(double* G, int ldg, int n, double* w, double* U, int ldu, int kvec, double* work,
+                        hipStream_t stream);
+size_t heev_tridiag_work_doubles(int n);
+
+// Newton-Schulz polar steps U <- U (3I - U^H U) / 2 on the first k columns
+// of U (n rows, ld ldu): removes the eps ||G|| / gap overlap left by inverse
+// iteration.  S: k*k complex scratch, T: n*k complex scratch.
+hipError_t orthonormalize_columns(double* U, int ldu, int n, int k, double* S, double* T, int iters,
+                                  hipStream_t stream);
+
 // Truncation rule on descending eigenvalues lam (= squared singular values):
 // smallest k >= 1 with sum_{j>k} lam_j <= tol^2 sum_j lam_j, then min(k, cap);
 // negative noise is clamped to zero.  Writes k to *k_out and the relative
@@ -71,6 +87,10 @@ hipError_t boundary_contract(const double* Wb, long long stride, int degree, dou
 
 // out[0] + i out[1] = sum_j E[j*ld + j] (complex128 trace of an n x n block)
 hipError_t diag_sum(const double* E, int n, long long ld, double* out, hipStream_t stream);
+
+// S <- 1.5 I - 0.5 S (n x n complex): the Newton-Schulz polar step
+// U <- U (3I - U^H U) / 2 is U . blend(U^H U).
+hipError_t newton_schulz_blend(double* S, int n, hipStream_t stream);
 
 // out[0] = sum |E|^2, out[1] = Re tr E, for an n x n complex matrix (purity).
 hipError_t gram_stats(const double* E, int n, double* out, hipStream_t stream);

@@ -594,9 +594,461 @@ __global__ __launch_bounds__(256) void gram_stats_kernel(const double* E, int n,
   if (threadIdx.x == 0) { out[0] = ra[0]; out[1] = rt[0]; }
 }
 
+__global__ void ns_blend_kernel(double* S, int n) {
+  const long long total = (long long)n * n;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    S[2 * e] = (i == j ? 1.5 : 0.0) - 0.5 * S[2 * e];
+    S[2 * e + 1] = -0.5 * S[2 * e + 1];
+  }
+}
+
+hipError_t newton_schulz_blend(double* S, int n, hipStream_t s) {
+  const long long total = (long long)n * n;
+  const int blocks = (int)std::min<long long>((total + 255) / 256, 1024);
+  hipLaunchKernelGGL(ns_blend_kernel, dim3(blocks), dim3(256), 0, s, S, n);
+  return hipGetLastError();
+}
+
 hipError_t gram_stats(const double* E, int n, double* out, hipStream_t s) {
   hipLaunchKernelGGL(gram_stats_kernel, dim3(1), dim3(256), 0, s, E, n, out);
   return hipGetLastError();
+}
+
+}  // namespace lbk
+
+// ---------------------------------------------------------------------------
+// Hermitian eigen-decomposition through a real symmetric tridiagonal form
+//   1. hetrd_kernel  Householder reduction G = Q T Q^H, T real (one workgroup;
+//                    each reflector chosen so that its beta is real)
+//   2. stebz_kernel  all eigenvalues of T by bisection with 64-point
+//                    multisection, one wave per eigenvalue
+//   3. stein_kernel  eigenvectors of T by inverse iteration, one lane per
+//                    eigenvalue (pivoted tridiagonal LU, two iterations)
+//   4. ormtr_kernel  back-transformation U = Q Z, one wave per column
+// ---------------------------------------------------------------------------
+namespace lbk {
+
+constexpr int TRD_NT = 1024;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int NT>
+__device__ inline double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x < 64) {
+    t = (threadIdx.x < NT / 64) ? red[threadIdx.x] : 0.0;
+    t = wave_sum(t);
+    if (threadIdx.x == 0) red[NT / 64] = t;
+  }
+  __syncthreads();
+  t = red[NT / 64];
+  __syncthreads();
+  return t;
+}
+
+// G (n x n, ld ldg, Hermitian, full storage) is destroyed.  Outputs: d[n],
+// e[n-1] (real tridiagonal), tau[n-1] (complex) and the reflector vectors as
+// rows of Vt (n x n, row j holds v_j on columns j+1..n-1, v_j[j+1] = 1).
+__global__ __launch_bounds__(TRD_NT) void hetrd_kernel(double* G, int ldg, int n, double* d, double* e,
+                                                       double* tau, double* Vt) {
+  __shared__ double vr[512], vi[512], yr[512], yi[512], wr[512], wi[512];
+  __shared__ double red[32];
+  __shared__ double sc[4];
+  const int tid = threadIdx.x;
+  for (int j = 0; j < n - 1; ++j) {
+    const int m = n - j - 1;
+    const int r0 = j + 1;
+    // 1. reflector from x = G[j+1:, j]
+    double part = 0.0;
+    for (int i = 1 + tid; i < m; i += TRD_NT) {
+      const double a = G[2 * ((long long)(r0 + i) * ldg + j)], b = G[2 * ((long long)(r0 + i) * ldg + j) + 1];
+      part += a * a + b * b;
+    }
+    const double xn2 = block_sum<TRD_NT>(part, red);
+    if (tid == 0) {
+      const double ar = G[2 * ((long long)r0 * ldg + j)], ai = G[2 * ((long long)r0 * ldg + j) + 1];
+      double tr, ti, beta, s_r, s_i;
+      if (xn2 == 0.0 && ai == 0.0) {
+        tr = 0.0; ti = 0.0; beta = ar; s_r = 0.0; s_i = 0.0;
+      } else {
+        beta = -copysign(sqrt(ar * ar + ai * ai + xn2), ar);
+        tr = (beta - ar) / beta; ti = -ai / beta;
+        // scale = 1 / (alpha - beta)
+        const double pr = ar - beta, pi = ai, den = pr * pr + pi * pi;
+        s_r = pr / den; s_i = -pi / den;
+      }
+      d[j] = G[2 * ((long long)j * ldg + j)];
+      e[j] = beta;
+      tau[2 * j] = tr; tau[2 * j + 1] = ti;
+      sc[0] = tr; sc[1] = ti; sc[2] = s_r; sc[3] = s_i;
+    }
+    __syncthreads();
+    const double tr = sc[0], ti = sc[1], s_r = sc[2], s_i = sc[3];
+    for (int i = tid; i < m; i += TRD_NT) {
+      double a, b;
+      if (i == 0) { a = 1.0; b = 0.0; }
+      else {
+        const double xr = G[2 * ((long long)(r0 + i) * ldg + j)], xi = G[2 * ((long long)(r0 + i) * ldg + j) + 1];
+        a = xr * s_r - xi * s_i; b = xr * s_i + xi * s_r;
+      }
+      vr[i] = a; vi[i] = b;
+      Vt[2 * ((long long)j * n + r0 + i)] = a;
+      Vt[2 * ((long long)j * n + r0 + i) + 1] = b;
+    }
+    __syncthreads();
+    if (tr == 0.0 && ti == 0.0) continue;
+    // 2. y = B v with B = G[j+1:, j+1:] Hermitian: y_r = sum_c conj(B[c][r]) v_c
+    const int half = (m + 1) / 2;
+    for (int rr = tid; rr < 2 * m; rr += TRD_NT) {
+      const int r = rr % m, part2 = rr / m;
+      const int c0 = part2 ? half : 0, c1 = part2 ? m : half;
+      double ar = 0.0, ai = 0.0;
+      for (int c = c0; c < c1; ++c) {
+        const double br = G[2 * ((long long)(r0 + c) * ldg + r0 + r)], bi = -G[2 * ((long long)(r0 + c) * ldg + r0 + r) + 1];
+        ar += br * vr[c] - bi * vi[c];
+        ai += br * vi[c] + bi * vr[c];
+      }
+      if (part2) { wr[r] = ar; wi[r] = ai; } else { yr[r] = ar; yi[r] = ai; }
+    }
+    __syncthreads();
+    for (int r = tid; r < m; r += TRD_NT) { yr[r] += wr[r]; yi[r] += wi[r]; }
+    __syncthreads();
+    // 3. s = Re(v^H y)
+    double sp = 0.0;
+    for (int r = tid; r < m; r += TRD_NT) sp += vr[r] * yr[r] + vi[r] * yi[r];
+    const double s = block_sum<TRD_NT>(sp, red);
+    // 4. w = tau y - (|tau|^2 / 2) s v
+    const double h = 0.5 * (tr * tr + ti * ti) * s;
+    for (int r = tid; r < m; r += TRD_NT) {
+      wr[r] = tr * yr[r] - ti * yi[r] - h * vr[r];
+      wi[r] = tr * yi[r] + ti * yr[r] - h * vi[r];
+    }
+    __syncthreads();
+    // 5. B -= w v^H + v w^H
+    for (long long q = tid; q < (long long)m * m; q += TRD_NT) {
+      const int r = (int)(q / m), c = (int)(q % m);
+      const long long off = 2 * ((long long)(r0 + r) * ldg + r0 + c);
+      // w_r conj(v_c) + v_r conj(w_c)
+      const double ur = wr[r] * vr[c] + wi[r] * vi[c] + vr[r] * wr[c] + vi[r] * wi[c];
+      const double ui = wi[r] * vr[c] - wr[r] * vi[c] + vi[r] * wr[c] - vr[r] * wi[c];
+      G[off] -= ur;
+      G[off + 1] -= ui;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) d[n - 1] = G[2 * ((long long)(n - 1) * ldg + n - 1)];
+}
+
+__device__ inline int sturm_count(const double* sd, const double* se2, int n, double x, double pivmin) {
+  int c = 0;
+  double q = sd[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  if (q < 0.0) ++c;
+  for (int i = 1; i < n; ++i) {
+    q = (sd[i] - x) - se2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0.0) ++c;
+  }
+  return c;
+}
+
+// w[j] (j < kmax) = j-th largest eigenvalue of the tridiagonal (d, e).
+__global__ __launch_bounds__(256) void stebz_kernel(const double* d, const double* e, int n, double* w, int kmax) {
+  __shared__ double sd[512], se2[512];
+  __shared__ double bnd[2];
+  for (int i = threadIdx.x; i < n; i += 256) {
+    sd[i] = d[i];
+    se2[i] = (i < n - 1) ? e[i] * e[i] : 0.0;
+  }
+  if (threadIdx.x == 0) {
+    double lo = 1e300, hi = -1e300, emax = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0);
+      lo = fmin(lo, d[i] - r);
+      hi = fmax(hi, d[i] + r);
+      if (i < n - 1) emax = fmax(emax, e[i] * e[i]);
+    }
+    const double span = fmax(fabs(lo), fabs(hi));
+    bnd[0] = lo - 4.0 * 2.2e-16 * span - 1e-300;
+    bnd[1] = hi + 4.0 * 2.2e-16 * span + 1e-300;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= kmax) return;
+  double emax = 0.0;
+  for (int i = lane; i < n - 1; i += 64) emax = fmax(emax, se2[i]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) emax = fmax(emax, __shfl_xor(emax, o, 64));
+  const double pivmin = 1e-290 * fmax(1.0, emax);
+  const int target = n - 1 - j;   // eigenvalue mu_target (ascending index)
+  double lo = bnd[0], hi = bnd[1];
+  for (int it = 0; it < 40; ++it) {
+    const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+    const int c = sturm_count(sd, se2, n, x, pivmin);
+    const unsigned long long mask = __ballot(c >= target + 1);
+    const int first = mask ? __ffsll((long long)mask) - 1 : 64;
+    const double nlo = (first == 0) ? lo : lo + (hi - lo) * (double)first / 65.0;
+    const double nhi = (first == 64) ? hi : lo + (hi - lo) * (double)(first + 1) / 65.0;
+    const bool done = (nhi - nlo) <= 2.0 * 2.2e-16 * fmax(fabs(nlo), fabs(nhi)) + 1e-300 ||
+                      (nlo == lo && nhi == hi);
+    lo = nlo; hi = nhi;
+    if (done) break;
+  }
+  if (lane == 0) w[j] = 0.5 * (lo + hi);
+}
+
+__device__ inline double hash_unit(unsigned int a, unsigned int b) {
+  unsigned int h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u;
+  h ^= h >> 15; h *= 0x2C1B3C6Du; h ^= h >> 12; h *= 0x297A2D39u; h ^= h >> 15;
+  return ((double)(h & 0xFFFFFF) / 16777216.0) * 2.0 - 1.0;
+}
+
+// Z[i*ldz + j] (j < k): unit eigenvector of the tridiagonal for w[j].
+// scratch: 6 * n * kpad doubles, kpad = k rounded up to 64.
+__global__ __launch_bounds__(64) void stein_kernel(const double* d, const double* e, int n, const double* w,
+                                                   int k, double* Z, int ldz, double* scr, int kpad) {
+  __shared__ double sd[512], se[512];
+  for (int i = threadIdx.x; i < n; i += 64) { sd[i] = d[i]; se[i] = (i < n - 1) ? e[i] : 0.0; }
+  __syncthreads();
+  const int j = blockIdx.x * 64 + threadIdx.x;
+  if (j >= k) return;
+  double tnorm = 0.0;
+  for (int i = 0; i < n; ++i) tnorm = fmax(tnorm, fabs(sd[i]) + fabs(se[i]) + (i > 0 ? fabs(se[i - 1]) : 0.0));
+  const double tiny = fmax(tnorm, 1e-300) * 2.2e-16;
+  const double lam = w[j];
+  double* U0 = scr + 0LL * n * kpad;
+  double* U1 = scr + 1LL * n * kpad;
+  double* U2 = scr + 2LL * n * kpad;
+  double* LM = scr + 3LL * n * kpad;
+  double* PV = scr + 4LL * n * kpad;
+  double* ZZ = scr + 5LL * n * kpad;
+#define IX(i) ((long long)(i) * kpad + j)
+  // pivoted LU of T - lam I
+  double a = sd[0] - lam, b = (n > 1) ? se[0] : 0.0;
+  for (int i = 0; i < n - 1; ++i) {
+    const double c = se[i];
+    const double an = sd[i + 1] - lam;
+    const double bn = (i + 1 < n - 1) ? se[i + 1] : 0.0;
+    if (fabs(a) >= fabs(c)) {
+      const double aa = (a == 0.0) ? tiny : a;
+      const double mult = c / aa;
+      U0[IX(i)] = aa; U1[IX(i)] = b; U2[IX(i)] = 0.0; LM[IX(i)] = mult; PV[IX(i)] = 0.0;
+      a = an - mult * b;
+      b = bn;
+    } else {
+      const double mult = a / c;
+      U0[IX(i)] = c; U1[IX(i)] = an; U2[IX(i)] = bn; LM[IX(i)] = mult; PV[IX(i)] = 1.0;
+      a = b - mult * an;
+      b = -mult * bn;
+    }
+  }
+  U0[IX(n - 1)] = a;
+  for (int i = 0; i < n; ++i) {
+    double u = U0[IX(i)];
+    if (fabs(u) < tiny) U0[IX(i)] = copysign(tiny, u == 0.0 ? 1.0 : u);
+    ZZ[IX(i)] = hash_unit((unsigned)i, (unsigned)j);
+  }
+  for (int iter = 0; iter < 2; ++iter) {
+    // forward: apply the row exchanges and multipliers
+    double cur = ZZ[IX(0)];
+    for (int i = 0; i < n - 1; ++i) {
+      double nxt = ZZ[IX(i + 1)];
+      if (PV[IX(i)] != 0.0) { const double t = cur; cur = nxt; nxt = t; }
+      nxt -= LM[IX(i)] * cur;
+      ZZ[IX(i)] = cur;
+      cur = nxt;
+    }
+    ZZ[IX(n - 1)] = cur;
+    // backward substitution with the upper factor (bandwidth 3)
+    double z1 = 0.0, z2 = 0.0, nrm = 0.0, big = 0.0;
+    for (int i = n - 1; i >= 0; --i) {
+      const double z = (ZZ[IX(i)] - U1[IX(i)] * z1 - U2[IX(i)] * z2) / U0[IX(i)];
+      ZZ[IX(i)] = z;
+      z2 = z1; z1 = z;
+      big = fmax(big, fabs(z));
+    }
+    const double inv = (big > 0.0) ? 1.0 / big : 1.0;
+    for (int i = 0; i < n; ++i) { const double z = ZZ[IX(i)] * inv; nrm += z * z; ZZ[IX(i)] = z; }
+    const double s = 1.0 / sqrt(fmax(nrm, 1e-300));
+    for (int i = 0; i < n; ++i) ZZ[IX(i)] *= s;
+    // deterministic sign: largest-magnitude component positive
+  }
+  double big = 0.0, sg = 1.0;
+  for (int i = 0; i < n; ++i) { const double z = ZZ[IX(i)]; if (fabs(z) > big) { big = fabs(z); sg = z < 0 ? -1.0 : 1.0; } }
+  for (int i = 0; i < n; ++i) Z[(long long)i * ldz + j] = sg * ZZ[IX(i)];
+#undef IX
+}
+
+// U[:, j] = Q z_j for j < k: Q = H_0 H_1 ... H_{n-2}, H_i = I - tau_i v_i v_i^H
+// acting on rows i+1..n-1 (v_i is row i of Vt).  U complex (ld ldu), Z real.
+__global__ __launch_bounds__(256) void ormtr_kernel(const double* Vt, const double* tau, int n, const double* Z,
+                                                    int ldz, int k, double* U, int ldu) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= k) return;
+  constexpr int MAXQ = 8;   // n <= 512
+  double ur[MAXQ], ui[MAXQ];
+#pragma unroll
+  for (int q = 0; q < MAXQ; ++q) {
+    const int r = lane + 64 * q;
+    ur[q] = (r < n) ? Z[(long long)r * ldz + j] : 0.0;
+    ui[q] = 0.0;
+  }
+  for (int i = n - 2; i >= 0; --i) {
+    const double tr = tau[2 * i], ti = tau[2 * i + 1];
+    if (tr == 0.0 && ti == 0.0) continue;
+    const double* v = Vt + 2LL * i * n;
+    double dr = 0.0, di = 0.0;
+#pragma unroll
+    for (int q = 0; q < MAXQ; ++q) {
+      const int r = lane + 64 * q;
+      if (r > i && r < n) {
+        const double a = v[2 * r], b = v[2 * r + 1];
+        dr += a * ur[q] + b * ui[q];          // conj(v) u
+        di += a * ui[q] - b * ur[q];
+      }
+    }
+    dr = wave_sum(dr);
+    di = wave_sum(di);
+    // u -= tau v (v^H u)
+    const double fr = tr * dr - ti * di, fi = tr * di + ti * dr;
+#pragma unroll
+    for (int q = 0; q < MAXQ; ++q) {
+      const int r = lane + 64 * q;
+      if (r > i && r < n) {
+        const double a = v[2 * r], b = v[2 * r + 1];
+        ur[q] -= a * fr - b * fi;
+        ui[q] -= a * fi + b * fr;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < MAXQ; ++q) {
+    const int r = lane + 64 * q;
+    if (r < n) {
+      U[2 * ((long long)r * ldu + j)] = ur[q];
+      U[2 * ((long long)r * ldu + j) + 1] = ui[q];
+    }
+  }
+}
+
+// Orthonormalise, within every cluster of eigenvalues closer than
+// gap_rel * max|w| (w descending, j < k), the columns of the real n x k block
+// Z (ld ldz) by classical Gram-Schmidt applied twice, one vector after the
+// other.  Inverse iteration gives independent vectors inside a cluster but
+// not orthogonal ones.  One workgroup.
+__global__ __launch_bounds__(256) void cluster_cgs2_kernel(double* Z, int ldz, int n, const double* w, int k,
+                                                           double gap_rel) {
+  __shared__ double red[32];
+  __shared__ double dots[512];
+  __shared__ int bounds[2];
+  double wmax = 0.0;
+  for (int j = 0; j < k; ++j) wmax = fmax(wmax, fabs(w[j]));
+  const double gap = gap_rel * fmax(wmax, 1e-300);
+  int start = 0;
+  while (start < k) {
+    if (threadIdx.x == 0) {
+      int end = start + 1;
+      while (end < k && fabs(w[end - 1] - w[end]) <= gap) ++end;
+      bounds[0] = start;
+      bounds[1] = end;
+    }
+    __syncthreads();
+    const int cs = bounds[0], ce = bounds[1];
+    __syncthreads();
+    for (int i = cs; i < ce; ++i) {
+      for (int pass = 0; pass < 2; ++pass) {
+        // dots of column i with columns cs..i-1 (one wave per dot)
+        const int nprev = i - cs;
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        for (int p0 = 0; p0 < nprev; p0 += 4) {
+          const int p = p0 + wave;
+          double acc = 0.0;
+          if (p < nprev)
+            for (int r = lane; r < n; r += 64) acc += Z[(long long)r * ldz + cs + p] * Z[(long long)r * ldz + i];
+          acc = wave_sum(acc);
+          if (lane == 0 && p < nprev) dots[p] = acc;
+        }
+        __syncthreads();
+        for (int r = threadIdx.x; r < n; r += 256) {
+          double v = Z[(long long)r * ldz + i];
+          for (int p = 0; p < nprev; ++p) v -= dots[p] * Z[(long long)r * ldz + cs + p];
+          Z[(long long)r * ldz + i] = v;
+        }
+        __syncthreads();
+      }
+      double part = 0.0;
+      for (int r = threadIdx.x; r < n; r += 256) {
+        const double v = Z[(long long)r * ldz + i];
+        part += v * v;
+      }
+      const double nrm = block_sum<256>(part, red);
+      const double f = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
+      for (int r = threadIdx.x; r < n; r += 256) Z[(long long)r * ldz + i] *= f;
+      __syncthreads();
+    }
+    start = ce;
+  }
+}
+
+hipError_t heev_tridiag(double* G, int ldg, int n, double* w, double* U, int ldu, int kvec, double* work,
+                        hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (n > 512 || kvec > n) return hipErrorInvalidValue;
+  // work layout: d[n] e[n] tau[2n] Vt[2n*n] Z[n*n] scr[6*n*kpad]
+  double* d = work;
+  double* e = d + n;
+  double* tau = e + n;
+  double* Vt = tau + 2 * n;
+  double* Z = Vt + 2LL * n * n;
+  double* scr = Z + (long long)n * n;
+  const int kpad = ((kvec + 63) / 64) * 64;
+  hipLaunchKernelGGL(hetrd_kernel, dim3(1), dim3(TRD_NT), 0, s, G, ldg, n, d, e, tau, Vt);
+  hipLaunchKernelGGL(stebz_kernel, dim3((n + 3) / 4), dim3(256), 0, s, d, e, n, w, n);
+  if (kvec > 0) {
+    hipLaunchKernelGGL(stein_kernel, dim3((kvec + 63) / 64), dim3(64), 0, s, d, e, n, w, kvec, Z, n, scr, kpad);
+    hipLaunchKernelGGL(cluster_cgs2_kernel, dim3(1), dim3(256), 0, s, Z, n, n, w, kvec, 1e-12);
+    hipLaunchKernelGGL(ormtr_kernel, dim3((kvec + 3) / 4), dim3(256), 0, s, Vt, tau, n, Z, n, kvec, U, ldu);
+  }
+  return hipGetLastError();
+}
+
+size_t heev_tridiag_work_doubles(int n) {
+  const size_t kpad = ((size_t)(n + 63) / 64) * 64;
+  return (size_t)4 * n + 2 * (size_t)n * n + (size_t)n * n + 6 * (size_t)n * kpad + 64;
+}
+
+hipError_t orthonormalize_columns(double* U, int ldu, int n, int k, double* S, double* T, int iters,
+                                  hipStream_t s) {
+  for (int it = 0; it < iters; ++it) {
+    Gemm g;
+    g.M = k; g.N = k; g.K = n;
+    g.A = U; g.sa_m = 1; g.sa_k = ldu; g.conjA = 1;
+    g.B = U; g.sb_k = ldu; g.sb_n = 1;
+    g.C = S; g.sc_m = k; g.sc_n = 1;
+    hipError_t e = gemm(g, s);
+    if (e != hipSuccess) return e;
+    if ((e = newton_schulz_blend(S, k, s)) != hipSuccess) return e;
+    Gemm h;
+    h.M = n; h.N = k; h.K = k;
+    h.A = U; h.sa_m = ldu; h.sa_k = 1;
+    h.B = S; h.sb_k = k; h.sb_n = 1;
+    h.C = T; h.sc_m = k; h.sc_n = 1;
+    if ((e = gemm(h, s)) != hipSuccess) return e;
+    if ((e = copy_cols(T, k, U, ldu, n, k, nullptr, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace lbk

@@ -41,18 +41,38 @@ def test_zgemm_fp32(shape):
     assert rel < 2e-6 * np.sqrt(K / 64)
 
 
-@pytest.mark.parametrize("n", [1, 2, 7, 16, 33, 64, 100, 128])
-def test_heev_parity(n):
+@pytest.mark.parametrize("method", ["jacobi", "tridiag"])
+@pytest.mark.parametrize("n", [1, 2, 7, 16, 33, 64, 100, 128, 256])
+def test_heev_parity(n, method):
     api = _api()
+    if method == "jacobi" and n > 128:
+        pytest.skip("single-workgroup Jacobi is only used on second-pass sizes")
     X = wl.random_matrix(n, n + 3, seed=10 + n)
     G = X @ X.conj().T
-    w, U, sweeps = api.kernel_heev(G)
-    assert sweeps > 0 or n == 1
+    w, U, sweeps = api.kernel_heev(G, method)
+    assert sweeps > 0 or n == 1 or method == "tridiag"
     ref = np.linalg.eigvalsh(G)[::-1]
     scale = np.abs(ref).max()
     assert np.abs(w - ref).max() <= 1e-13 * scale
     assert np.abs(U.conj().T @ U - np.eye(n)).max() < 1e-13
-    assert np.abs(U @ np.diag(w) @ U.conj().T - G).max() <= 1e-13 * scale
+    assert np.abs(U @ np.diag(w) @ U.conj().T - G).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("n", [40, 200])
+def test_heev_tridiag_graded_and_clustered(n):
+    """Geometric spectrum (as in the zip-up Gram matrices) with an exactly
+    degenerate pair and a zero block: absolute accuracy eps ||G||."""
+    api = _api()
+    lam = 0.9 ** np.arange(n)
+    lam[3] = lam[2]                       # exact degeneracy
+    lam[-5:] = 0.0                        # rank deficiency
+    G = wl.random_matrix(n, n, seed=7, spectrum=np.sqrt(lam))
+    G = G @ G.conj().T
+    w, U, _ = api.kernel_heev(G, "tridiag")
+    ref = np.sort(lam)[::-1]
+    assert np.abs(w - ref).max() <= 1e-13
+    assert np.abs(U.conj().T @ U - np.eye(n)).max() < 1e-13
+    assert np.abs(G @ U - U * w).max() <= 1e-12
 
 
 def test_heev_graded_spectrum_relative_accuracy():
