@@ -1,0 +1,171 @@
+#!/usr/bin/env python
+"""Benchmark of the purified-MPS Kraus step on one MI355X.
+
+Workload (the chi = 128 configuration): cat mode + lossy buffer, two modes of
+2^8 Fock levels each (16 quantics sites), H = g2 (a^dag^2 b + a^2 b^dag)
++ eps_d (b + b^dag) with alpha^2 = 8, jumps sqrt(10) b and sqrt(1e-3) a
+(9 Kraus operators), bond cap chi = 128, purification cap chi_mu = 16,
+tol = 1e-8, dt = 2.5e-5; the state is a seeded synthetic MPS saturated at
+the caps (bonds min(2^i, 2^(16-i) 16, 128), Schmidt spectra decaying
+geometrically), so every step runs at the full chi = 128 cost.
+
+One step = zip-up application of the stacked Kraus MPO, purification
+truncation, right-to-left truncated-SVD sweep and trace renormalisation.
+The timed form computes the MPO/MPS contractions in complex64 (FP32 MFMA,
+FP32 accumulation) and every Gram matrix, factorisation, truncation weight
+and trace in FP64.  A few steps of the plain FP64 form are timed beside it,
+and the CPU oracle (NumPy/LAPACK) on a bounded sample of the same workload.
+
+Prints one JSON line.  --gpus above 1 is not supported (one GPU).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "purified-MPS steps/s at chi=128; batched solves/s + p50/p99 vs plain FP64"
+PEAKS = {  # MI355X published dense peaks
+    ("mfma", "f32"): 157.3, ("mfma", "f64"): 78.6, ("alu", "f64"): 78.6, ("alu", "f32"): 157.3,
+    ("hbm", None): 8000.0,
+}
+ALU_CLASSES = {"hetrd", "stebz", "stein", "ormtr", "jacobi"}
+
+
+def workload():
+    import workload as wl
+    m = wl.model_cat_buffer(Ra=8, Rb=8, alpha2=8.0, dt=2.5e-5)
+    L, chi, chi_mu = 16, 128, 16
+    raw = wl.synthetic_mps(L, chi_mu, chi)
+    return m, L, chi, chi_mu, raw
+
+
+def roofline_entry(prof: dict, precision: str) -> dict:
+    name = max(prof, key=lambda k: prof[k]["ms"])
+    p = prof[name]
+    ms_per_launch = p["ms"] / max(p["launches"], 1)
+    if name in ALU_CLASSES:
+        bound, unit, dt = "alu", "TFLOP/s", "f64"
+    else:
+        bound, unit = "mfma", "TFLOP/s"
+        dt = "f32" if (precision == "fp32" and name == "gemm_contract") else "f64"
+    achieved = (p["flop"] / p["launches"]) / (ms_per_launch * 1e-3) / 1e12 if p["ms"] > 0 else 0.0
+    peak = PEAKS[(bound, dt)]
+    return {"kernel": name, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": None, "avg_launch_us": ms_per_launch * 1e3,
+            "launches": p["launches"], "flop_per_launch": p["flop"] / max(p["launches"], 1),
+            "dtype": dt}
+
+
+def gpu_run(steps: int, warmup: int, precision: str):
+    import torch
+    from paper_2605_27515_amd import api
+    m, L, chi, chi_mu, raw = workload()
+    s = api.solver_from_model(m, precision=precision, chi=chi, chi_mu=chi_mu, state="none", device=0)
+    s.set_state_mps(raw)
+    if warmup:
+        s.step(warmup)
+    s.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = s.profile_read()
+    s.profile(False)
+    d = s.diagnostics()
+    s.close()
+    return (t1 - t0), prof, d
+
+
+def cpu_baseline(budget_s: float) -> dict:
+    """The oracle as it stands, on the same workload, for a bounded sample."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle import mps, tt
+    m, L, chi, chi_mu, raw = workload()
+    K = tt.KrausMPO(m, m.dt)
+    X, _ = mps.right_canonicalize(raw, tol=1e-14)
+    X, _ = mps.k2_step(X, K.at(0.0), m.tol, chi, chi_mu)       # warm-up step
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        X, _ = mps.k2_step(X, K.at(n * m.dt), m.tol, chi, chi_mu)
+        n += 1
+        if time.perf_counter() - t0 > budget_s or n >= 50:
+            break
+    dt = time.perf_counter() - t0
+    threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    return {"value": n / dt, "unit": "steps/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n} steps of the same chi=128 cat+buffer workload (oracle NumPy/LAPACK FP64, "
+                      f"{dt:.1f} s), after one warm-up step", "host_cpus": os.cpu_count()}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--fp64-steps", type=int, default=3, help="steps of the plain FP64 form timed beside")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the method's step is a "
+              "sequential sweep per solve; independent solves shard across GPUs without communication)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    print(f"bench: {args.precision} steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
+    elapsed, prof, diag = gpu_run(args.steps, args.warmup, args.precision)
+    value = args.steps / elapsed
+    print(f"bench: {value:.3f} steps/s, bonds {diag['bonds']}, chi_mu {diag['chi_mu']}",
+          file=sys.stderr, flush=True)
+    fp64 = None
+    if args.fp64_steps > 0 and args.precision != "fp64":
+        e64, _, _ = gpu_run(args.fp64_steps, 1, "fp64")
+        fp64 = args.fp64_steps / e64
+        print(f"bench: plain fp64 {fp64:.3f} steps/s", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(args.cpu_seconds)
+        print(f"bench: cpu oracle {cpu['value']:.4f} steps/s on {cpu['cores']} threads", file=sys.stderr,
+              flush=True)
+    total_ms = sum(p["ms"] for p in prof.values())
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "cat+buffer 2x256 Fock (16 sites), alpha^2=8, 9 Kraus ops, chi=128, "
+                               "chi_mu=16, tol=1e-8, dt=2.5e-5, seeded saturated MPS",
+                   "precision": args.precision, "parallelism": "single solve, one GPU"},
+        "roofline": roofline_entry(prof, args.precision),
+        "cpu_baseline": cpu,
+        "fp64_plain_steps_per_s": fp64,
+        "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items() if v["launches"]},
+        "kernel_share": {k: v["ms"] / total_ms for k, v in prof.items() if v["launches"]} if total_ms else {},
+        "final_bonds": diag["bonds"],
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -228,6 +228,28 @@ typedef struct lb_diag {
 /* Diagnostics of the last step (synchronises). */
 lb_status lindblad_diagnostics(lb_solver* s, lb_diag* out);
 
+/* ---- live per-kernel timing ------------------------------------------------ */
+
+#define LB_PROF_CLASSES 16
+typedef struct lb_profile {
+  int32_t n;                         /* number of kernel classes reported        */
+  char name[LB_PROF_CLASSES][24];
+  int64_t launches[LB_PROF_CLASSES];
+  double ms[LB_PROF_CLASSES];        /* summed device time between HIP events
+                                        recorded on the solver's stream          */
+  double flop[LB_PROF_CLASSES];      /* summed algorithmic real flops            */
+  double bytes[LB_PROF_CLASSES];     /* summed algorithmic bytes: operands read
+                                        once plus results written once           */
+} lb_profile;
+
+/* Reset the counters and switch event timing of every kernel launch of
+ * lindblad_step on (enable != 0) or off.  Timing adds one event pair per
+ * launch.  Errors: LB_ERR_ARG. */
+lb_status lindblad_profile(lb_solver* s, int32_t enable);
+
+/* Read the counters accumulated since lindblad_profile (synchronises). */
+lb_status lindblad_profile_read(lb_solver* s, lb_profile* out);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* lindblad_last_error(void);
 

@@ -73,7 +73,10 @@ def zipup(sites, W, tol_zip: float, chi_zip: int, tol: float, chi_mu: int, info:
     for i in range(L):
         A = sites[i]                         # A[a, s, b]
         w = W[i]                             # w[u, s', s, v]
-        T = np.einsum('xau,asb,uzsv->xzbv', C, A, w, optimize=True)
+        # T[x, s', b, v] = sum_{a, u, s} C[x, a, u] A[a, s, b] w[u, s', s, v]
+        T1 = np.tensordot(C, A, axes=([1], [0]))              # [x, u, s, b]
+        T = np.tensordot(T1, w, axes=([1, 2], [0, 2]))         # [x, b, s', v]
+        T = T.transpose(0, 2, 1, 3)
         ap, _, b, v = T.shape
         M = T.reshape(ap * 2, b * v)
         u, s, vh = svd(M)
@@ -130,7 +133,11 @@ def expect(sites, O) -> complex:
     """Tr(O rho) = sum_mu <X_mu|O|X_mu> (O an MPO with unit boundary dims)."""
     E = np.ones((1, 1, 1), complex)          # E[a*, u, a]
     for A, w in zip(sites, O):
-        E = np.einsum('xua,xzb,uzsv,asc->bvc', E, A.conj(), w, A, optimize=True)
+        # E'[b*, v, c] = sum E[x, u, a] conj(A[x, z, b*]) w[u, z, s, v] A[a, s, c]
+        F = np.tensordot(E, A, axes=([2], [0]))                # [x, u, s, c]
+        F = np.tensordot(F, w, axes=([1, 2], [0, 2]))          # [x, c, z, v]
+        E = np.tensordot(A.conj(), F, axes=([0, 1], [0, 2]))   # [b*, c, v]
+        E = E.transpose(0, 2, 1)
     return complex(np.einsum('bvb->', E))
 
 
@@ -139,7 +146,8 @@ def gram(sites, other=None) -> np.ndarray:
     Y = sites if other is None else other
     E = np.ones((1, 1), complex)
     for A, B in zip(sites, Y):
-        E = np.einsum('xa,xsb,asc->bc', E, A.conj(), B, optimize=True)
+        F = np.tensordot(E, B, axes=([1], [0]))                # [x, s, c]
+        E = np.tensordot(A.conj(), F, axes=([0, 1], [0, 1]))   # [b, c]
     return E
 
 
@@ -153,7 +161,10 @@ def purity(sites) -> float:
 
 
 def rho_distance2(x1, x2) -> float:
-    """||X1 X1^dag - X2 X2^dag||_F^2 from overlaps with open purification legs."""
+    """||X1 X1^dag - X2 X2^dag||_F^2 from overlaps with open purification legs.
+
+    Each of the three terms is O(||rho||^2), so the difference carries an
+    absolute rounding floor of ~1e-15 ||rho||^2."""
     a = np.sum(np.abs(gram(x1)) ** 2)
     b = np.sum(np.abs(gram(x2)) ** 2)
     c = np.sum(np.abs(gram(x1, x2)) ** 2)

@@ -27,7 +27,7 @@ EXPORTED = ["lindblad_default_config", "lindblad_create", "lindblad_destroy",
             "lindblad_kraus_info", "lindblad_kraus_site", "lindblad_set_state_product", "lindblad_set_state_mps",
             "lindblad_get_state_mps", "lindblad_step", "lindblad_step_batch",
             "lindblad_observe", "lindblad_trace_purity", "lindblad_diagnostics",
-            "lindblad_last_error", "lindblad_kernel_zgemm", "lindblad_kernel_heev",
+            "lindblad_last_error", "lindblad_profile", "lindblad_profile_read", "lindblad_kernel_zgemm", "lindblad_kernel_heev",
             "lindblad_kernel_truncate"]
 
 
@@ -61,6 +61,11 @@ class LbDiag(C.Structure):
                 ("bonds", C.c_int32 * LB_MAX_SITES), ("chi_mu", C.c_int32),
                 ("zip_bonds", C.c_int32 * LB_MAX_SITES),
                 ("discarded", C.c_double * LB_MAX_SITES)]
+
+
+class LbProfile(C.Structure):
+    _fields_ = [("n", C.c_int32), ("name", (C.c_char * 24) * 16), ("launches", C.c_int64 * 16),
+                ("ms", C.c_double * 16), ("flop", C.c_double * 16), ("bytes", C.c_double * 16)]
 
 
 _lib = None
@@ -107,6 +112,8 @@ def load() -> C.CDLL:
                                           dp, C.c_int32, C.c_int32]
     lib.lindblad_kernel_heev.argtypes = [C.c_int32, dp, dp, dp, C.POINTER(C.c_int32), C.c_int32]
     lib.lindblad_kernel_truncate.argtypes = [C.c_int32, dp, C.c_double, C.c_int32, C.POINTER(C.c_int32), dp]
+    lib.lindblad_profile.argtypes = [vp, C.c_int32]
+    lib.lindblad_profile_read.argtypes = [vp, C.POINTER(LbProfile)]
     lib.lindblad_last_error.argtypes = []
     lib.lindblad_last_error.restype = C.c_char_p
     for name in EXPORTED:

@@ -201,6 +201,15 @@ class Solver:
                     zip_bonds=[d.zip_bonds[i] for i in range(n)],
                     discarded=[d.discarded[i] for i in range(n)])
 
+    def profile(self, enable: bool = True):
+        _check(L.load().lindblad_profile(self.h, 1 if enable else 0), "profile")
+
+    def profile_read(self) -> dict:
+        p = L.LbProfile()
+        _check(L.load().lindblad_profile_read(self.h, C.byref(p)), "profile_read")
+        return {p.name[i].value.decode(): dict(launches=int(p.launches[i]), ms=p.ms[i], flop=p.flop[i],
+                                                bytes=p.bytes[i]) for i in range(p.n)}
+
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
             L.load().lindblad_destroy(self.h)

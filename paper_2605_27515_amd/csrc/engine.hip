@@ -141,6 +141,16 @@ struct lb_solver {
   int n_max = 0;
   long long m_max = 0;
 
+  // live profiling (HIP events around every launch of the step)
+  bool prof_on = false;
+  int cls = 0;                                // class of the launches being issued
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  struct Pending { size_t a, b; int cls; double flop, bytes; };
+  std::vector<Pending> pending;
+  double p_ms[LB_PROF_CLASSES] = {0}, p_flop[LB_PROF_CLASSES] = {0}, p_bytes[LB_PROF_CLASSES] = {0};
+  long long p_n[LB_PROF_CLASSES] = {0};
+
   // diagnostics
   double t = 0.0;
   long long steps = 0;
@@ -157,6 +167,55 @@ using lbk::Prec;
 
 bool fp32(const lb_solver* s) { return s->cfg.precision == LB_FP32_CONTRACT; }
 int passes(const lb_solver* s) { return fp32(s) ? 1 : 2; }
+
+enum ProfClass { PC_CONTRACT = 0, PC_GRAM, PC_SVDGEMM, PC_HETRD, PC_STEBZ, PC_STEIN, PC_ORMTR, PC_JACOBI,
+                 PC_OTHER, PC_COUNT };
+const char* kProfNames[PC_COUNT] = {"gemm_contract", "gemm_gram", "gemm_svd", "hetrd", "stebz", "stein",
+                                    "ormtr", "jacobi", "other"};
+
+size_t prof_event(lb_solver* s) {
+  if (s->ev_used == s->ev_pool.size()) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    s->ev_pool.push_back(e);
+  }
+  return s->ev_used++;
+}
+
+// Brackets one launch (or launch sequence) with an event pair when profiling.
+struct Timed {
+  lb_solver* s;
+  int cls;
+  double flop, bytes;
+  size_t a = 0;
+  Timed(lb_solver* s_, int c, double f, double b) : s(s_), cls(c), flop(f), bytes(b) {
+    if (s->prof_on) {
+      a = prof_event(s);
+      HIPCHK(hipEventRecord(s->ev_pool[a], s->stream));
+    }
+  }
+  ~Timed() noexcept(false) {
+    if (!s->prof_on) return;
+    const size_t b = prof_event(s);
+    HIPCHK(hipEventRecord(s->ev_pool[b], s->stream));
+    s->pending.push_back({a, b, cls, flop, bytes});
+  }
+};
+
+void prof_flush(lb_solver* s) {
+  if (s->pending.empty()) { s->ev_used = 0; return; }
+  HIPCHK(hipStreamSynchronize(s->stream));
+  for (const auto& p : s->pending) {
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, s->ev_pool[p.a], s->ev_pool[p.b]));
+    s->p_ms[p.cls] += ms;
+    s->p_flop[p.cls] += p.flop;
+    s->p_bytes[p.cls] += p.bytes;
+    s->p_n[p.cls] += 1;
+  }
+  s->pending.clear();
+  s->ev_used = 0;
+}
 
 lb::Layout make_layout(const lb_config& c) {
   lb::Layout lay;
@@ -263,6 +322,7 @@ void gram_rows(lb_solver* s, const void* A, Prec pa, int n, long long m, long lo
   g.compute = lbk::F64;
   g.splits = choose_splits(n, n, m);
   g.ws = s->ws.p;
+  Timed tm(s, PC_GRAM, 8.0 * n * n * (double)m, (double)n * m * (pa == lbk::F64 ? 16 : 8) + 16.0 * n * n);
   check_gemm(lbk::gemm(g, s->stream), "gram_rows");
 }
 
@@ -276,6 +336,7 @@ void gram_cols(lb_solver* s, const void* A, Prec pa, int n, int m, long long lda
   g.compute = lbk::F64;
   g.splits = choose_splits(m, m, n);
   g.ws = s->ws.p;
+  Timed tm(s, PC_GRAM, 8.0 * m * m * (double)n, (double)n * m * (pa == lbk::F64 ? 16 : 8) + 16.0 * m * m);
   check_gemm(lbk::gemm(g, s->stream), "gram_cols");
 }
 
@@ -285,6 +346,7 @@ void mm(lb_solver* s, int M, int N, int K, const void* A, Prec pa, long long lda
 
 // Jacobi (relative accuracy; second pass of LB_FP64): eigenvectors in G.
 void eig_jacobi(lb_solver* s, double* G, int n, double* lam) {
+  Timed tm(s, PC_JACOBI, 0.0, 32.0 * n * n);
   HIPCHK(lbk::heev_jacobi(G, n, 0, n, lam, 0, s->V.d(), 1, 1.5e-15, 40, s->info.i(), s->stream));
 }
 
@@ -294,8 +356,33 @@ void eig_jacobi(lb_solver* s, double* G, int n, double* lam) {
 // iteration leaves eps ||G|| / gap of mutual overlap between vectors).
 void eig_trid(lb_solver* s, double* G, int n, double* lam, double* U, int kvec) {
   kvec = std::min(kvec, n);
-  HIPCHK(lbk::heev_tridiag(G, n, n, lam, U, n, kvec, s->ework.d(), s->stream));
-  HIPCHK(lbk::orthonormalize_columns(U, n, n, kvec, s->scratch.d(), s->U2.d(), 2, s->stream));
+  const double N = n;
+  const lbk::TridWork tw = lbk::trid_work(s->ework.d(), n, kvec);
+  {
+    // complex Hermitian Householder tridiagonalisation: 16/3 n^3 real flops;
+    // reads the matrix once, writes the reflectors and the tridiagonal
+    Timed tm(s, PC_HETRD, 16.0 / 3.0 * N * N * N, 16.0 * N * N + 8.0 * N * N + 24.0 * N);
+    HIPCHK(lbk::trid_reduce(G, n, n, tw, s->stream));
+  }
+  {
+    // bisection: 53 halvings x n Sturm steps of 5 flops, per eigenvalue
+    Timed tm(s, PC_STEBZ, 53.0 * 5.0 * N * N, 24.0 * N);
+    HIPCHK(lbk::trid_eigenvalues(n, tw, lam, s->stream));
+  }
+  {
+    // inverse iteration: factor (8n) + 2 x (forward 2n + backward 5n + norm 3n)
+    Timed tm(s, PC_STEIN, 28.0 * N * kvec, 8.0 * N * kvec + 24.0 * N);
+    HIPCHK(lbk::trid_vectors(n, tw, lam, kvec, s->stream));
+  }
+  {
+    // U = Q Z: n-1 complex reflectors of mean length n/2 on kvec vectors
+    Timed tm(s, PC_ORMTR, 8.0 * N * N * kvec, 16.0 * N * N / 2 + 8.0 * N * kvec + 16.0 * N * kvec);
+    HIPCHK(lbk::trid_backtransform(n, tw, kvec, U, n, s->stream));
+  }
+  {
+    Timed tm(s, PC_SVDGEMM, 2.0 * (8.0 * kvec * kvec * N * 2), 2.0 * 16.0 * (2.0 * N * kvec + kvec * kvec));
+    HIPCHK(lbk::orthonormalize_columns(U, n, n, kvec, s->scratch.d(), s->U2.d(), 2, s->stream));
+  }
 }
 
 // C = op(A) op(B) with row-major dense operands described by leading dims.
@@ -312,6 +399,10 @@ void mm(lb_solver* s, int M, int N, int K, const void* A, Prec pa, long long lda
   g.compute = comp;
   g.splits = (batch == 1) ? choose_splits(M, N, K) : 1;
   g.ws = s->ws.p;
+  const double ea = (pa == lbk::F64 ? 16.0 : 8.0), eb = (pb == lbk::F64 ? 16.0 : 8.0), ec = (pc == lbk::F64 ? 16.0 : 8.0);
+  const double bytes = (double)M * K * ea * (sa_b ? batch : 1) + (double)K * N * eb * (sb_b ? batch : 1) +
+                       (double)M * N * ec * batch;
+  Timed tm(s, s->cls, 8.0 * M * N * (double)K * batch, bytes);
   check_gemm(lbk::gemm(g, s->stream), "mm");
 }
 
@@ -459,6 +550,7 @@ void refresh_drive(lb_solver* s) {
   const double tm = s->t + 0.5 * s->dt;
   for (size_t j = 0; j < s->drv_c.size(); ++j) f += s->drv_c[j] * std::cos(s->drv_w[j] * tm + s->drv_p[j]);
   const long long count = (long long)2 * s->W.wr[0] * 2 * 1;
+  Timed tmr(s, PC_OTHER, 8.0 * count * s->degree, 16.0 * count * (s->degree + 1));
   HIPCHK(lbk::boundary_contract(s->Wb0.d(), s->wb0_stride, s->degree, f, s->W.d64[0].d(),
                                 fp32(s) ? s->W.d32[0].f() : nullptr, count, s->stream));
 }
@@ -475,6 +567,7 @@ void zipup(lb_solver* s) {
     const int cl = s->chi[i], cr = s->chi[i + 1];
     const int wl = s->wb[i], wr = s->wb[i + 1];
     // stage 1: P[(a', u)][(s, b)] = C[(a', u)][a] X_i[a][(s, b)]
+    s->cls = PC_CONTRACT;
     const void* Pp;
     Prec pp;
     if (i == 0) {
@@ -493,16 +586,18 @@ void zipup(lb_solver* s) {
     const int n = 2 * zk;
     const long long m = (long long)wr * cr;
     if (i < L - 1) {
+      s->cls = PC_SVDGEMM;
       double* U = left_svd(s, s->T.p, pw, n, m, m, passes(s) == 2, zc);
-      HIPCHK(lbk::truncate_rank(s->lam.d(), n, tolz, zc, s->kdev.i(), s->disc.d(), s->stream));
+      { Timed tm(s, PC_OTHER, 0.0, 8.0 * n); HIPCHK(lbk::truncate_rank(s->lam.d(), n, tolz, zc, s->kdev.i(), s->disc.d(), s->stream)); }
       const int k = read_k(s);
       // new site X_i[(a', s')][k] = U[:, :k]
-      HIPCHK(lbk::copy_cols(U, n, s->X[i].d(), k, n, k, nullptr, s->stream));
+      { Timed tm(s, PC_OTHER, 0.0, 32.0 * n * k); HIPCHK(lbk::copy_cols(U, n, s->X[i].d(), k, n, k, nullptr, s->stream)); }
       // carry C[k][(v, b)] = U_k^H T  (or the first k rows of U2^H B)
       if (passes(s) == 2) {
         if (f32) throw Fail(LB_ERR_STATE, "internal: two-pass FP32");
         HIPCHK(hipMemcpyAsync(s->C.p, s->Bm.p, (size_t)k * m * 16, hipMemcpyDeviceToDevice, s->stream));
       } else {
+        s->cls = PC_CONTRACT;
         mm(s, k, (int)m, n, U, lbk::F64, n, true, s->T.p, pw, m, false, s->C.p, pw, m, pw);
       }
       s->chi[i] = zk;       // left bond of the new site
@@ -511,6 +606,7 @@ void zipup(lb_solver* s) {
     } else {
       // S2: purification truncation on the (Kraus x purification) columns
       const int mc = (int)m;
+      s->cls = PC_SVDGEMM;
       double* Gc = s->G.d();
       gram_cols(s, s->T.p, pw, n, mc, m, Gc);
       double* V0 = s->U0.d();
@@ -530,11 +626,12 @@ void zipup(lb_solver* s) {
         Asrc = Bc;
         asrc = lbk::F64;
       }
-      HIPCHK(lbk::truncate_rank(s->lam.d(), mc, s->cfg.tol, s->cfg.chi_mu_cap, s->kdev.i(), s->disc.d(),
-                                s->stream));
+      { Timed tm(s, PC_OTHER, 0.0, 8.0 * mc); HIPCHK(lbk::truncate_rank(s->lam.d(), mc, s->cfg.tol, s->cfg.chi_mu_cap, s->kdev.i(), s->disc.d(),
+                                s->stream)); }
       const int k = read_k(s);
       s->discarded[0] = read_disc(s);
       // X_{L-1}[(a', s')][k] = A V[:, :k]
+      s->cls = PC_CONTRACT;
       mm(s, n, k, mc, Asrc, asrc, (passes(s) == 2) ? mc : m, false, Vf, lbk::F64, mc, false,
          s->X[i].p, lbk::F64, k, lbk::F64);
       s->chi[i] = zk;
@@ -550,23 +647,26 @@ void back_sweep(lb_solver* s, double tol, bool record) {
   for (int i = L - 1; i >= 1; --i) {
     const int l = s->chi[i], r = s->chi[i + 1];
     const long long m = 2LL * r;
+    s->cls = PC_SVDGEMM;
     double* U = left_svd(s, s->X[i].p, lbk::F64, l, m, m, passes(s) == 2, s->cap[i]);
-    HIPCHK(lbk::truncate_rank(s->lam.d(), l, tol, s->cap[i], s->kdev.i(), s->disc.d(), s->stream));
+    { Timed tm(s, PC_OTHER, 0.0, 8.0 * l); HIPCHK(lbk::truncate_rank(s->lam.d(), l, tol, s->cap[i], s->kdev.i(), s->disc.d(), s->stream)); }
     const int k = read_k(s);
     if (record && i < (int)s->discarded.size()) s->discarded[i] = read_disc(s);
     // new X_i = S^-1 U_k^H M  (rows k)
     if (passes(s) == 2) {
+      Timed tm(s, PC_OTHER, 0.0, 32.0 * k * m);
       HIPCHK(lbk::scale_rows_inv_sqrt(s->Bm.d(), (int)m, s->Xspare.d(), (int)m, k, (int)m, s->lam.d(), s->stream));
     } else {
       double* tmp = s->Bm.d();
       mm(s, k, (int)m, l, U, lbk::F64, l, true, s->X[i].p, lbk::F64, m, false, tmp, lbk::F64, m, lbk::F64);
+      Timed tm(s, PC_OTHER, 0.0, 32.0 * k * m);
       HIPCHK(lbk::scale_rows_inv_sqrt(tmp, (int)m, s->Xspare.d(), (int)m, k, (int)m, s->lam.d(), s->stream));
     }
     std::swap(s->X[i].p, s->Xspare.p);
     std::swap(s->X[i].bytes, s->Xspare.bytes);
     // US = U[:, :k] * sigma ; X_{i-1} <- X_{i-1} US
     double* US = s->scratch.d();
-    HIPCHK(lbk::copy_cols(U, l, US, k, l, k, s->lam.d(), s->stream));
+    { Timed tm(s, PC_OTHER, 0.0, 32.0 * l * k); HIPCHK(lbk::copy_cols(U, l, US, k, l, k, s->lam.d(), s->stream)); }
     const int lp = s->chi[i - 1];
     mm(s, 2 * lp, k, l, s->X[i - 1].p, lbk::F64, l, false, US, lbk::F64, k, false, s->Xspare.p,
        lbk::F64, k, lbk::F64);
@@ -577,7 +677,7 @@ void back_sweep(lb_solver* s, double tol, bool record) {
 }
 
 void normalize_center(lb_solver* s) {
-  HIPCHK(lbk::normalize(s->X[0].d(), 2LL * s->chi[1], s->tau.d(), s->flag.i(), s->stream));
+  { Timed tm(s, PC_OTHER, 8.0 * s->chi[1], 64.0 * s->chi[1]); HIPCHK(lbk::normalize(s->X[0].d(), 2LL * s->chi[1], s->tau.d(), s->flag.i(), s->stream)); }
 }
 
 void step_once(lb_solver* s) {
@@ -592,6 +692,7 @@ void step_once(lb_solver* s) {
   s->max_defect = std::max(s->max_defect, std::fabs(tau - 1.0));
   s->t += s->dt;
   s->steps += 1;
+  if (s->prof_on) prof_flush(s);
 }
 
 void canonicalize(lb_solver* s) {
@@ -692,6 +793,7 @@ void lindblad_destroy(lb_solver* s) {
   if (s->dev_ready && s->stream) (void)hipStreamSynchronize(s->stream);
   hipStream_t st = s->stream;
   bool own = s->own_stream;
+  for (auto e : s->ev_pool) (void)hipEventDestroy(e);
   delete s;
   if (own && st) (void)hipStreamDestroy(st);
 }
@@ -1094,6 +1196,37 @@ lb_status lindblad_diagnostics(lb_solver* s, lb_diag* out) {
       HIPCHK(hipMemcpy(&flag, s->flag.p, sizeof(int), hipMemcpyDeviceToHost));
     }
     if (flag) throw Fail(LB_ERR_NUMERIC, "non-finite trace encountered during a step");
+    return LB_OK;
+  } catch (const Fail& f) {
+    return fail(f);
+  }
+}
+
+lb_status lindblad_profile(lb_solver* s, int32_t enable) {
+  try {
+    if (!s) throw Fail(LB_ERR_ARG, "NULL solver");
+    if (s->dev_ready) prof_flush(s);
+    for (int c = 0; c < LB_PROF_CLASSES; ++c) { s->p_ms[c] = 0; s->p_flop[c] = 0; s->p_bytes[c] = 0; s->p_n[c] = 0; }
+    s->prof_on = enable != 0;
+    return LB_OK;
+  } catch (const Fail& f) {
+    return fail(f);
+  }
+}
+
+lb_status lindblad_profile_read(lb_solver* s, lb_profile* out) {
+  try {
+    if (!s || !out) throw Fail(LB_ERR_ARG, "NULL argument");
+    if (s->dev_ready) prof_flush(s);
+    std::memset(out, 0, sizeof(*out));
+    out->n = PC_COUNT;
+    for (int c = 0; c < PC_COUNT; ++c) {
+      std::strncpy(out->name[c], kProfNames[c], 23);
+      out->launches[c] = s->p_n[c];
+      out->ms[c] = s->p_ms[c];
+      out->flop[c] = s->p_flop[c];
+      out->bytes[c] = s->p_bytes[c];
+    }
     return LB_OK;
   } catch (const Fail& f) {
     return fail(f);

@@ -49,6 +49,17 @@ hipError_t heev_tridiag(double* G, int ldg, int n, double* w, double* U, int ldu
                         hipStream_t stream);
 size_t heev_tridiag_work_doubles(int n);
 
+// The same four stages, callable one by one (for per-stage timing).
+struct TridWork {
+  double *d, *e, *tau, *Vt, *Z, *scr;
+  int kpad;
+};
+TridWork trid_work(double* work, int n, int kvec);
+hipError_t trid_reduce(double* G, int ldg, int n, const TridWork& t, hipStream_t stream);
+hipError_t trid_eigenvalues(int n, const TridWork& t, double* w, hipStream_t stream);
+hipError_t trid_vectors(int n, const TridWork& t, const double* w, int kvec, hipStream_t stream);
+hipError_t trid_backtransform(int n, const TridWork& t, int kvec, double* U, int ldu, hipStream_t stream);
+
 // Newton-Schulz polar steps U <- U (3I - U^H U) / 2 on the first k columns
 // of U (n rows, ld ldu): removes the eps ||G|| / gap overlap left by inverse
 // iteration.  S: k*k complex scratch, T: n*k complex scratch.

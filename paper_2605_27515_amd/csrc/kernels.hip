@@ -1002,26 +1002,54 @@ __global__ __launch_bounds__(256) void cluster_cgs2_kernel(double* Z, int ldz, i
   }
 }
 
+TridWork trid_work(double* work, int n, int kvec) {
+  TridWork t;
+  t.d = work;
+  t.e = t.d + n;
+  t.tau = t.e + n;
+  t.Vt = t.tau + 2 * n;
+  t.Z = t.Vt + 2LL * n * n;
+  t.scr = t.Z + (long long)n * n;
+  t.kpad = ((std::max(kvec, 1) + 63) / 64) * 64;
+  return t;
+}
+
+hipError_t trid_reduce(double* G, int ldg, int n, const TridWork& t, hipStream_t s) {
+  hipLaunchKernelGGL(hetrd_kernel, dim3(1), dim3(TRD_NT), 0, s, G, ldg, n, t.d, t.e, t.tau, t.Vt);
+  return hipGetLastError();
+}
+
+hipError_t trid_eigenvalues(int n, const TridWork& t, double* w, hipStream_t s) {
+  hipLaunchKernelGGL(stebz_kernel, dim3((n + 3) / 4), dim3(256), 0, s, t.d, t.e, n, w, n);
+  return hipGetLastError();
+}
+
+hipError_t trid_vectors(int n, const TridWork& t, const double* w, int kvec, hipStream_t s) {
+  if (kvec <= 0) return hipSuccess;
+  hipLaunchKernelGGL(stein_kernel, dim3((kvec + 63) / 64), dim3(64), 0, s, t.d, t.e, n, w, kvec, t.Z, n,
+                     t.scr, t.kpad);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(cluster_cgs2_kernel, dim3(1), dim3(256), 0, s, t.Z, n, n, w, kvec, 1e-12);
+  return hipGetLastError();
+}
+
+hipError_t trid_backtransform(int n, const TridWork& t, int kvec, double* U, int ldu, hipStream_t s) {
+  if (kvec <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ormtr_kernel, dim3((kvec + 3) / 4), dim3(256), 0, s, t.Vt, t.tau, n, t.Z, n, kvec, U, ldu);
+  return hipGetLastError();
+}
+
 hipError_t heev_tridiag(double* G, int ldg, int n, double* w, double* U, int ldu, int kvec, double* work,
                         hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (n > 512 || kvec > n) return hipErrorInvalidValue;
-  // work layout: d[n] e[n] tau[2n] Vt[2n*n] Z[n*n] scr[6*n*kpad]
-  double* d = work;
-  double* e = d + n;
-  double* tau = e + n;
-  double* Vt = tau + 2 * n;
-  double* Z = Vt + 2LL * n * n;
-  double* scr = Z + (long long)n * n;
-  const int kpad = ((kvec + 63) / 64) * 64;
-  hipLaunchKernelGGL(hetrd_kernel, dim3(1), dim3(TRD_NT), 0, s, G, ldg, n, d, e, tau, Vt);
-  hipLaunchKernelGGL(stebz_kernel, dim3((n + 3) / 4), dim3(256), 0, s, d, e, n, w, n);
-  if (kvec > 0) {
-    hipLaunchKernelGGL(stein_kernel, dim3((kvec + 63) / 64), dim3(64), 0, s, d, e, n, w, kvec, Z, n, scr, kpad);
-    hipLaunchKernelGGL(cluster_cgs2_kernel, dim3(1), dim3(256), 0, s, Z, n, n, w, kvec, 1e-12);
-    hipLaunchKernelGGL(ormtr_kernel, dim3((kvec + 3) / 4), dim3(256), 0, s, Vt, tau, n, Z, n, kvec, U, ldu);
-  }
-  return hipGetLastError();
+  const TridWork t = trid_work(work, n, kvec);
+  hipError_t e;
+  if ((e = trid_reduce(G, ldg, n, t, s)) != hipSuccess) return e;
+  if ((e = trid_eigenvalues(n, t, w, s)) != hipSuccess) return e;
+  if ((e = trid_vectors(n, t, w, kvec, s)) != hipSuccess) return e;
+  return trid_backtransform(n, t, kvec, U, ldu, s);
 }
 
 size_t heev_tridiag_work_doubles(int n) {

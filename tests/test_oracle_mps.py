@@ -61,7 +61,10 @@ def test_invariants_and_gauge():
     Y[-1] = np.einsum('asm,mn->asn', X[-1], q)
     O = tt.operator_mpo([(1.0, {0: ("NUM_POW", 1)}), (0.5, {1: ("A_POW", 1)})], m.bits, so)
     assert abs(mps.expect(X, O) - mps.expect(Y, O)) < 1e-13
-    assert mps.rho_distance2(X, Y) < 1e-24
+    Xd, Yd = mps.to_dense(X, m.bits, so), mps.to_dense(Y, m.bits, so)
+    assert np.abs(Xd @ Xd.conj().T - Yd @ Yd.conj().T).max() < 1e-14
+    # the overlap identity agrees within its rounding floor
+    assert abs(mps.rho_distance2(X, Y)) < 1e-14
     # dense cross-check of the rho distance identity
     Xa = mps.to_dense(X, m.bits, so)
     rho = Xa @ Xa.conj().T
@@ -77,7 +80,8 @@ def test_identity_step_leaves_state_unchanged():
     X, _ = mps.right_canonicalize(X)
     X1, info = mps.k2_step(X, K.at(0.0), 1e-8, 16, 4)
     assert abs(info.tau - 1.0) < 1e-14
-    assert mps.rho_distance2(X, X1) < 1e-28
+    A, B = mps.to_dense(X, m.bits, so), mps.to_dense(X1, m.bits, so)
+    assert np.abs(A @ A.conj().T - B @ B.conj().T).max() < 1e-15
 
 
 def test_parity_conserved_without_single_photon_loss():
