@@ -7,6 +7,12 @@
 //                  split-K with a fixed-order reduction.
 //  * heev_kernel   Hermitian eigen-decomposition by cyclic Jacobi with the
 //                  round-robin parallel ordering (one workgroup per matrix).
+//  * tridiagonal route (hetrd_fused_kernel, stebz_kernel, stein_kernel,
+//                  stein_groups_kernel, ormtr_kernel): Householder reduction
+//                  to real tridiagonal form, eigenvalues by Sturm-count
+//                  multisection, eigenvectors by inverse iteration made
+//                  orthogonal inside groups of close eigenvalues, and the
+//                  back-transformation with the stored reflectors.
 //  * small kernels truncation rule, column/row scaling, normalisation,
 //                  precision conversion, drive-boundary contraction.
 #include "kernels.h"
@@ -638,6 +644,12 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 template <int NT>
 __device__ inline double block_sum(double v, double* red) {
   v = wave_sum(v);
@@ -747,6 +759,227 @@ __global__ __launch_bounds__(TRD_NT) void hetrd_kernel(double* G, int ldg, int n
     __syncthreads();
   }
   if (tid == 0) d[n - 1] = G[2 * ((long long)(n - 1) * ldg + n - 1)];
+}
+
+// Fused variant: one pass per step over the trailing block applies step j's
+// rank-2 update and accumulates step j+1's product y' = B' v' (Hermitian, so
+// y'_c = sum_r conj(B'[r][c]) v'_r: one thread per column, coalesced rows).
+// Trailing blocks of at most HT_LDSM rows are kept in LDS.
+constexpr int HT_LDSM = 72;
+
+template <bool SRC_LDS, bool DST_LDS>
+__device__ inline void hetrd_fused_pass(double* G, int ldg, double* Ls, int base, int j, int m,
+                                        const double* v_r, const double* v_i, const double* w_r,
+                                        const double* w_i, const double* nv_r, const double* nv_i,
+                                        double* yp_r, double* yp_i) {
+  const int ncols = m - 1;
+  const int parts = (ncols <= 256) ? 4 : 2;
+  const int chunk = (ncols + parts - 1) / parts;
+  const int t = threadIdx.x;
+  if (t >= ncols * parts) return;
+  const int cl = 1 + t % ncols, part = t / ncols;
+  const int r0 = 1 + part * chunk, r1 = min(m, 1 + (part + 1) * chunk);
+  const int C = j + 1 + cl;
+  const double vcr = v_r[cl], vci = v_i[cl], wcr = w_r[cl], wci = w_i[cl];
+  double ar = 0.0, ai = 0.0;
+#pragma unroll 4
+  for (int r = r0; r < r1; ++r) {
+    const int R = j + 1 + r;
+    double br, bi;
+    if (SRC_LDS) {
+      const long long o = 2 * ((long long)(R - base) * HT_LDSM + (C - base));
+      br = Ls[o]; bi = Ls[o + 1];
+    } else {
+      const long long o = 2 * ((long long)R * ldg + C);
+      br = G[o]; bi = G[o + 1];
+    }
+    // b -= w_r conj(v_c) + v_r conj(w_c)
+    br -= w_r[r] * vcr + w_i[r] * vci + v_r[r] * wcr + v_i[r] * wci;
+    bi -= w_i[r] * vcr - w_r[r] * vci + v_i[r] * wcr - v_r[r] * wci;
+    if (DST_LDS) {
+      const int nb = SRC_LDS ? base : (j + 2);
+      const long long o = 2 * ((long long)(R - nb) * HT_LDSM + (C - nb));
+      Ls[o] = br; Ls[o + 1] = bi;
+    } else {
+      const long long o = 2 * ((long long)R * ldg + C);
+      G[o] = br; G[o + 1] = bi;
+    }
+    // acc += conj(b) * nv[r - 1]
+    const double xr = nv_r[r - 1], xi = nv_i[r - 1];
+    ar += br * xr + bi * xi;
+    ai += br * xi - bi * xr;
+  }
+  yp_r[part * 512 + cl - 1] = ar;
+  yp_i[part * 512 + cl - 1] = ai;
+}
+
+__global__ __launch_bounds__(TRD_NT) void hetrd_fused_kernel(double* G, int ldg, int n, double* d, double* e,
+                                                             double* tau, double* Vt) {
+  __shared__ double Ls[2 * HT_LDSM * HT_LDSM];
+  __shared__ double v_r[512], v_i[512], w_r[512], w_i[512], y_r[512], y_i[512], nv_r[512], nv_i[512];
+  __shared__ double yp_r[4 * 512], yp_i[4 * 512];
+  __shared__ double red[32];
+  __shared__ double sc[8];
+  const int tid = threadIdx.x;
+  if (n == 1) {
+    if (tid == 0) d[0] = G[0];
+    return;
+  }
+  // reflector 0 from x = G[1:n, 0]
+  int m = n - 1;
+  {
+    double part = 0.0;
+    for (int i = 1 + tid; i < m; i += TRD_NT) {
+      const double a = G[2 * ((long long)(1 + i) * ldg)], b = G[2 * ((long long)(1 + i) * ldg) + 1];
+      part += a * a + b * b;
+    }
+    const double xn2 = block_sum<TRD_NT>(part, red);
+    if (tid == 0) {
+      const double ar = G[2 * ((long long)ldg)], ai = G[2 * ((long long)ldg) + 1];
+      double tr = 0.0, ti = 0.0, beta = ar, s_r = 0.0, s_i = 0.0;
+      if (!(xn2 == 0.0 && ai == 0.0)) {
+        beta = -copysign(sqrt(ar * ar + ai * ai + xn2), ar);
+        tr = (beta - ar) / beta; ti = -ai / beta;
+        const double pr = ar - beta, pi = ai, den = pr * pr + pi * pi;
+        s_r = pr / den; s_i = -pi / den;
+      }
+      d[0] = G[0];
+      e[0] = beta;
+      tau[0] = tr; tau[1] = ti;
+      sc[0] = tr; sc[1] = ti; sc[2] = s_r; sc[3] = s_i;
+    }
+    __syncthreads();
+    for (int i = tid; i < m; i += TRD_NT) {
+      double a = 1.0, b = 0.0;
+      if (i > 0) {
+        const double xr = G[2 * ((long long)(1 + i) * ldg)], xi = G[2 * ((long long)(1 + i) * ldg) + 1];
+        a = xr * sc[2] - xi * sc[3]; b = xr * sc[3] + xi * sc[2];
+      }
+      v_r[i] = a; v_i[i] = b;
+      Vt[2 * (1 + i)] = a; Vt[2 * (1 + i) + 1] = b;
+    }
+    __syncthreads();
+    // y = B v, B = G[1:, 1:]: y_c = sum_r conj(B[r][c]) v_r
+    const int parts = (m <= 256) ? 4 : 2;
+    const int chunk = (m + parts - 1) / parts;
+    if (tid < m * parts) {
+      const int c = tid % m, part = tid / m;
+      const int r0 = part * chunk, r1 = min(m, (part + 1) * chunk);
+      double ar = 0.0, ai = 0.0;
+#pragma unroll 4
+      for (int r = r0; r < r1; ++r) {
+        const long long o = 2 * ((long long)(1 + r) * ldg + 1 + c);
+        const double br = G[o], bi = G[o + 1];
+        ar += br * v_r[r] + bi * v_i[r];
+        ai += br * v_i[r] - bi * v_r[r];
+      }
+      yp_r[part * 512 + c] = ar;
+      yp_i[part * 512 + c] = ai;
+    }
+    __syncthreads();
+    for (int c = tid; c < m; c += TRD_NT) {
+      double ar = 0.0, ai = 0.0;
+      for (int p = 0; p < parts; ++p) { ar += yp_r[p * 512 + c]; ai += yp_i[p * 512 + c]; }
+      y_r[c] = ar; y_i[c] = ai;
+    }
+    __syncthreads();
+  }
+  bool inL = false;
+  int base = 0;
+  for (int j = 0;; ++j) {
+    m = n - j - 1;
+    const double tr = sc[0], ti = sc[1];
+    const bool refl = !(tr == 0.0 && ti == 0.0);
+    // w = tau y - (|tau|^2 / 2) Re(v^H y) v
+    double sp = 0.0;
+    for (int r = tid; r < m; r += TRD_NT) sp += v_r[r] * y_r[r] + v_i[r] * y_i[r];
+    const double s = block_sum<TRD_NT>(sp, red);
+    const double h = 0.5 * (tr * tr + ti * ti) * s;
+    for (int r = tid; r < m; r += TRD_NT) {
+      if (refl) {
+        w_r[r] = tr * y_r[r] - ti * y_i[r] - h * v_r[r];
+        w_i[r] = tr * y_i[r] + ti * y_r[r] - h * v_i[r];
+      } else {
+        w_r[r] = 0.0; w_i[r] = 0.0;
+      }
+    }
+    __syncthreads();
+    // column 0 of the block (global column j+1, rows j+1..n-1) after the update
+    for (int r = tid; r < m; r += TRD_NT) {
+      const int R = j + 1 + r, Cc = j + 1;
+      double br, bi;
+      if (inL) {
+        const long long o = 2 * ((long long)(R - base) * HT_LDSM + (Cc - base));
+        br = Ls[o]; bi = Ls[o + 1];
+      } else {
+        const long long o = 2 * ((long long)R * ldg + Cc);
+        br = G[o]; bi = G[o + 1];
+      }
+      br -= w_r[r] * v_r[0] + w_i[r] * v_i[0] + v_r[r] * w_r[0] + v_i[r] * w_i[0];
+      bi -= w_i[r] * v_r[0] - w_r[r] * v_i[0] + v_i[r] * w_r[0] - v_r[r] * w_i[0];
+      nv_r[r] = br; nv_i[r] = bi;      // raw x (reflector source) for now
+    }
+    __syncthreads();
+    if (m == 1) {
+      if (tid == 0) d[j + 1] = nv_r[0];
+      break;
+    }
+    // reflector j+1 from x = nv[1..m-1] (nv[0] is the new diagonal entry):
+    // squared norm of the tail x[1:] = nv[2..m-1]
+    double part = 0.0;
+    for (int r = 2 + tid; r < m; r += TRD_NT) part += nv_r[r] * nv_r[r] + nv_i[r] * nv_i[r];
+    const double xn2b = block_sum<TRD_NT>(part, red);
+    if (tid == 0) {
+      const double ar = nv_r[1], ai = nv_i[1];
+      double ntr = 0.0, nti = 0.0, beta = ar, s_r = 0.0, s_i = 0.0;
+      if (!(xn2b == 0.0 && ai == 0.0)) {
+        beta = -copysign(sqrt(ar * ar + ai * ai + xn2b), ar);
+        ntr = (beta - ar) / beta; nti = -ai / beta;
+        const double pr = ar - beta, pi = ai, den = pr * pr + pi * pi;
+        s_r = pr / den; s_i = -pi / den;
+      }
+      d[j + 1] = nv_r[0];
+      e[j + 1] = beta;
+      tau[2 * (j + 1)] = ntr; tau[2 * (j + 1) + 1] = nti;
+      sc[4] = ntr; sc[5] = nti; sc[2] = s_r; sc[3] = s_i;
+    }
+    __syncthreads();
+    // scaled reflector v' in the next block's local indices (r' = r - 1),
+    // v'[0] = 1; staged through y (free until the partial sums are folded)
+    {
+      const double s_r = sc[2], s_i = sc[3];
+      for (int r = 1 + tid; r < m; r += TRD_NT) {
+        double a = 1.0, b = 0.0;
+        if (r > 1) {
+          const double xr = nv_r[r], xi = nv_i[r];
+          a = xr * s_r - xi * s_i; b = xr * s_i + xi * s_r;
+        }
+        y_r[r - 1] = a; y_i[r - 1] = b;
+        Vt[2 * ((long long)(j + 1) * n + j + 1 + r)] = a;
+        Vt[2 * ((long long)(j + 1) * n + j + 1 + r) + 1] = b;
+      }
+      __syncthreads();
+      for (int r = tid; r < m - 1; r += TRD_NT) { nv_r[r] = y_r[r]; nv_i[r] = y_i[r]; }
+      __syncthreads();
+    }
+    // fused pass over rows/cols j+2..n-1: update of step j, product with v'
+    const bool dst = inL || (m - 1 <= HT_LDSM);
+    if (!inL && !dst) hetrd_fused_pass<false, false>(G, ldg, Ls, base, j, m, v_r, v_i, w_r, w_i, nv_r, nv_i, yp_r, yp_i);
+    else if (!inL && dst) hetrd_fused_pass<false, true>(G, ldg, Ls, base, j, m, v_r, v_i, w_r, w_i, nv_r, nv_i, yp_r, yp_i);
+    else hetrd_fused_pass<true, true>(G, ldg, Ls, base, j, m, v_r, v_i, w_r, w_i, nv_r, nv_i, yp_r, yp_i);
+    __syncthreads();
+    if (dst && !inL) { inL = true; base = j + 2; }
+    const int ncols = m - 1;
+    const int parts = (ncols <= 256) ? 4 : 2;
+    for (int c = tid; c < ncols; c += TRD_NT) {
+      double ar = 0.0, ai = 0.0;
+      for (int p = 0; p < parts; ++p) { ar += yp_r[p * 512 + c]; ai += yp_i[p * 512 + c]; }
+      y_r[c] = ar; y_i[c] = ai;
+      v_r[c] = nv_r[c]; v_i[c] = nv_i[c];
+    }
+    if (tid == 0) { sc[0] = sc[4]; sc[1] = sc[5]; }
+    __syncthreads();
+  }
 }
 
 __device__ inline int sturm_count(const double* sd, const double* se2, int n, double x, double pivmin) {
@@ -943,62 +1176,131 @@ __global__ __launch_bounds__(256) void ormtr_kernel(const double* Vt, const doub
   }
 }
 
-// Orthonormalise, within every cluster of eigenvalues closer than
-// gap_rel * max|w| (w descending, j < k), the columns of the real n x k block
-// Z (ld ldz) by classical Gram-Schmidt applied twice, one vector after the
-// other.  Inverse iteration gives independent vectors inside a cluster but
-// not orthogonal ones.  One workgroup.
-__global__ __launch_bounds__(256) void cluster_cgs2_kernel(double* Z, int ldz, int n, const double* w, int k,
-                                                           double gap_rel) {
+// Inverse iteration gives vectors orthogonal to about n eps ||T|| / gap, so
+// eigenvalues closer than theta ||T|| are treated as a group (theta = 1e-8
+// keeps the contamination between groups below ~1e-5, which the polar
+// clean-up of the caller removes).  Inside a group every member after the
+// first is projected out of the span of the earlier members by classical
+// Gram-Schmidt applied twice.  A member that loses more than half of its norm
+// in the projection (nearly dependent vectors, as for eigenvalues at the
+// rounding floor) would carry the amplified contamination of other groups,
+// so it is first refined by one more solve with its own shifted
+// factorisation (left in `scr` by stein_kernel), which damps every direction
+// outside the group, and projected again; if that collapses too it restarts
+// from fresh start vectors.  One workgroup; w holds all n eigenvalues
+// (descending), Z the k vectors (ld ldz).
+constexpr int SG_NT = 256;
+
+__device__ void sg_project(double* Z, int ldz, int n, int c0, int c1, double* zl, double* dots) {
+  const int nprev = c1 - c0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int p0 = 0; p0 < nprev; p0 += SG_NT / 64) {
+      const int p = p0 + wave;
+      double acc = 0.0;
+      if (p < nprev)
+        for (int r = lane; r < n; r += 64) acc += Z[(long long)r * ldz + c0 + p] * zl[r];
+      acc = wave_sum(acc);
+      if (lane == 0 && p < nprev) dots[p] = acc;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < n; r += SG_NT) {
+      double v = zl[r];
+      for (int p = 0; p < nprev; ++p) v -= dots[p] * Z[(long long)r * ldz + c0 + p];
+      zl[r] = v;
+    }
+    __syncthreads();
+  }
+}
+
+__device__ double sg_norm(const double* zl, int n, double* red) {
+  double part = 0.0;
+  for (int r = threadIdx.x; r < n; r += SG_NT) part += zl[r] * zl[r];
+  return sqrt(block_sum<SG_NT>(part, red));
+}
+
+__device__ void sg_scale(double* zl, int n, double f) {
+  for (int r = threadIdx.x; r < n; r += SG_NT) zl[r] *= f;
+  __syncthreads();
+}
+
+// one solve with the pivoted factorisation of T - w_j I (layout of stein_kernel)
+__device__ void sg_solve(double* zl, int n, const double* scr, int kpad, int j, double* lu, double* red) {
+  double* u0 = lu;
+  double* u1 = lu + 512;
+  double* u2 = lu + 1024;
+  double* lm = lu + 1536;
+  double* pv = lu + 2048;
+  const long long nk = (long long)n * kpad;
+  for (int i = threadIdx.x; i < n; i += SG_NT) {
+    const long long o = (long long)i * kpad + j;
+    u0[i] = scr[o]; u1[i] = scr[nk + o]; u2[i] = scr[2 * nk + o]; lm[i] = scr[3 * nk + o]; pv[i] = scr[4 * nk + o];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double cur = zl[0];
+    for (int i = 0; i < n - 1; ++i) {
+      double nxt = zl[i + 1];
+      if (pv[i] != 0.0) { const double t = cur; cur = nxt; nxt = t; }
+      nxt -= lm[i] * cur;
+      zl[i] = cur;
+      cur = nxt;
+    }
+    zl[n - 1] = cur;
+    double z1 = 0.0, z2 = 0.0;
+    for (int i = n - 1; i >= 0; --i) {
+      const double z = (zl[i] - u1[i] * z1 - u2[i] * z2) / u0[i];
+      zl[i] = z;
+      z2 = z1; z1 = z;
+    }
+  }
+  __syncthreads();
+  double big = 0.0;
+  for (int r = threadIdx.x; r < n; r += SG_NT) big = fmax(big, fabs(zl[r]));
+  big = wave_max(big);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = big;
+  __syncthreads();
+  big = 0.0;
+  for (int q = 0; q < SG_NT / 64; ++q) big = fmax(big, red[q]);
+  __syncthreads();
+  sg_scale(zl, n, big > 0.0 ? 1.0 / big : 1.0);
+}
+
+__global__ __launch_bounds__(SG_NT) void stein_groups_kernel(int n, const double* w, int k, double theta,
+                                                             double* Z, int ldz, const double* scr, int kpad) {
+  __shared__ double zl[512], dots[512], lu[5 * 512];
   __shared__ double red[32];
-  __shared__ double dots[512];
-  __shared__ int bounds[2];
-  double wmax = 0.0;
-  for (int j = 0; j < k; ++j) wmax = fmax(wmax, fabs(w[j]));
-  const double gap = gap_rel * fmax(wmax, 1e-300);
+  __shared__ unsigned char link[512];   // link[j]: w[j] belongs to the group of w[j-1]
+  const double tn = fmax(fmax(fabs(w[0]), fabs(w[n - 1])), 1e-300);
+  const double gap = theta * tn;
+  for (int j = threadIdx.x; j < k; j += SG_NT) link[j] = (j > 0 && w[j - 1] - w[j] <= gap) ? 1 : 0;
+  __syncthreads();
   int start = 0;
   while (start < k) {
-    if (threadIdx.x == 0) {
-      int end = start + 1;
-      while (end < k && fabs(w[end - 1] - w[end]) <= gap) ++end;
-      bounds[0] = start;
-      bounds[1] = end;
-    }
-    __syncthreads();
-    const int cs = bounds[0], ce = bounds[1];
-    __syncthreads();
-    for (int i = cs; i < ce; ++i) {
-      for (int pass = 0; pass < 2; ++pass) {
-        // dots of column i with columns cs..i-1 (one wave per dot)
-        const int nprev = i - cs;
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-        for (int p0 = 0; p0 < nprev; p0 += 4) {
-          const int p = p0 + wave;
-          double acc = 0.0;
-          if (p < nprev)
-            for (int r = lane; r < n; r += 64) acc += Z[(long long)r * ldz + cs + p] * Z[(long long)r * ldz + i];
-          acc = wave_sum(acc);
-          if (lane == 0 && p < nprev) dots[p] = acc;
+    int end = start + 1;
+    while (end < k && link[end]) ++end;
+    for (int j = start + 1; j < end; ++j) {
+      for (int r = threadIdx.x; r < n; r += SG_NT) zl[r] = Z[(long long)r * ldz + j];
+      __syncthreads();
+      bool ok = false;
+      for (int attempt = 0; attempt < 4 && !ok; ++attempt) {
+        if (attempt >= 2) {
+          // restart from a fresh start vector, pulled towards the group by two solves
+          for (int r = threadIdx.x; r < n; r += SG_NT) zl[r] = hash_unit((unsigned)r, (unsigned)(j + 7919 * attempt));
+          __syncthreads();
+          sg_solve(zl, n, scr, kpad, j, lu, red);
         }
-        __syncthreads();
-        for (int r = threadIdx.x; r < n; r += 256) {
-          double v = Z[(long long)r * ldz + i];
-          for (int p = 0; p < nprev; ++p) v -= dots[p] * Z[(long long)r * ldz + cs + p];
-          Z[(long long)r * ldz + i] = v;
-        }
-        __syncthreads();
+        if (attempt >= 1) sg_solve(zl, n, scr, kpad, j, lu, red);
+        const double n0 = sg_norm(zl, n, red);
+        sg_project(Z, ldz, n, start, j, zl, dots);
+        const double n1 = sg_norm(zl, n, red);
+        ok = n1 > 0.5 * n0 && n1 > 0.0;
+        if (n1 > 0.0) sg_scale(zl, n, 1.0 / n1);
       }
-      double part = 0.0;
-      for (int r = threadIdx.x; r < n; r += 256) {
-        const double v = Z[(long long)r * ldz + i];
-        part += v * v;
-      }
-      const double nrm = block_sum<256>(part, red);
-      const double f = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
-      for (int r = threadIdx.x; r < n; r += 256) Z[(long long)r * ldz + i] *= f;
+      for (int r = threadIdx.x; r < n; r += SG_NT) Z[(long long)r * ldz + j] = zl[r];
       __syncthreads();
     }
-    start = ce;
+    start = end;
   }
 }
 
@@ -1015,7 +1317,7 @@ TridWork trid_work(double* work, int n, int kvec) {
 }
 
 hipError_t trid_reduce(double* G, int ldg, int n, const TridWork& t, hipStream_t s) {
-  hipLaunchKernelGGL(hetrd_kernel, dim3(1), dim3(TRD_NT), 0, s, G, ldg, n, t.d, t.e, t.tau, t.Vt);
+  hipLaunchKernelGGL(hetrd_fused_kernel, dim3(1), dim3(TRD_NT), 0, s, G, ldg, n, t.d, t.e, t.tau, t.Vt);
   return hipGetLastError();
 }
 
@@ -1030,7 +1332,7 @@ hipError_t trid_vectors(int n, const TridWork& t, const double* w, int kvec, hip
                      t.scr, t.kpad);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(cluster_cgs2_kernel, dim3(1), dim3(256), 0, s, t.Z, n, n, w, kvec, 1e-12);
+  hipLaunchKernelGGL(stein_groups_kernel, dim3(1), dim3(SG_NT), 0, s, n, w, kvec, 1e-8, t.Z, n, t.scr, t.kpad);
   return hipGetLastError();
 }
 

@@ -75,6 +75,29 @@ def test_heev_tridiag_graded_and_clustered(n):
     assert np.abs(G @ U - U * w).max() <= 1e-12
 
 
+@pytest.mark.parametrize("n,m", [(12, 20), (40, 30), (128, 300), (256, 200)])
+@pytest.mark.parametrize("seed", range(4))
+def test_heev_tridiag_rounding_floor_tail(n, m, seed):
+    """Gram of a graded matrix whose smaller singular values lie at and below
+    sqrt(eps) of the largest, so the tail of the Gram spectrum sits at the
+    rounding floor, plus a non-Hermitian perturbation of that size (as a Gram
+    matrix formed by a GEMM carries).  The inverse-iteration vectors of the
+    unresolved tail are nearly dependent; they must still come out
+    orthonormal, and the resolved part accurate to eps ||G|| / gap."""
+    api = _api()
+    r = min(n, m)
+    sv = np.concatenate([[np.sqrt(8.0)], 10.0 ** (-np.linspace(2.5, 18.0, r - 1))])
+    A = wl.random_matrix(n, m, seed=100 + seed, spectrum=sv)
+    G = A @ A.conj().T
+    G = G + 4e-17 * np.abs(G).max() * wl.random_matrix(n, n, seed=200 + seed)
+    w, U, _ = api.kernel_heev(G, "tridiag")
+    assert np.abs(U.conj().T @ U - np.eye(n)).max() < 1e-13
+    Gh = 0.5 * (G + G.conj().T)
+    ref = np.linalg.eigvalsh(Gh)[::-1]
+    assert np.abs(w - ref).max() <= 1e-13 * ref[0]
+    assert np.abs(Gh @ U - U * w).max() <= 1e-12 * ref[0]
+
+
 def test_heev_graded_spectrum_relative_accuracy():
     """Graded PSD matrices (the second pass of the factorisation): eigenvalues
     to high relative accuracy down to 1e-24 of the largest."""

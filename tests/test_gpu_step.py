@@ -1,8 +1,12 @@
 """GPU parity of the full purified-MPS step (through the C ABI) against
 Oracle-M on the same seeded inputs, and invariants at larger sizes.
 
-Tolerances: FP64 path 1e-10 relative on observables and on the
-gauge-invariant density-matrix distance; FP32-contraction path 1e-5."""
+Tolerances: FP64 path 1e-10 relative on observables and density-matrix
+elements; FP32-contraction path 1e-5.  The FP64 bound is checked at a
+truncation tolerance of 1e-12: at tol = 1e-8 a truncation decision whose tail
+sum lies within the oracle's own SVD accuracy (eps * sigma_1, i.e. ~1e-8
+relative for the singular values at the cut) of the threshold can go either
+way, and such a flip moves rho by O(tol); that case is checked at O(tol)."""
 import numpy as np
 import pytest
 
@@ -81,29 +85,32 @@ def _compare(m, steps, chi, chi_mu, precision, rtol, tol=1e-8):
     return Xo, Xg
 
 
-@pytest.mark.parametrize("precision,rtol", [("fp64", 1e-10), ("fp32", 1e-5)])
-def test_step_coherent_loss(precision, rtol):
-    _compare(wl.model_coherent_loss(), 100, 16, 4, precision, rtol)
+FORMS = [("fp64", 1e-10, 1e-12), ("fp32", 1e-5, 1e-8), ("fp64", 1e-7, 1e-8)]
 
 
-@pytest.mark.parametrize("precision,rtol", [("fp64", 1e-10), ("fp32", 1e-5)])
-def test_step_two_photon_cat(precision, rtol):
-    _compare(wl.model_two_photon_cat(R=5, alpha2=2.0, dt=1e-3), 60, 16, 8, precision, rtol)
+@pytest.mark.parametrize("precision,rtol,tol", FORMS)
+def test_step_coherent_loss(precision, rtol, tol):
+    _compare(wl.model_coherent_loss(), 100, 16, 4, precision, rtol, tol)
 
 
-@pytest.mark.parametrize("precision,rtol", [("fp64", 1e-10), ("fp32", 1e-5)])
-def test_step_cat_buffer(precision, rtol):
-    _compare(wl.model_cat_buffer(Ra=4, Rb=3, alpha2=2.0, dt=1e-3), 30, 16, 8, precision, rtol)
+@pytest.mark.parametrize("precision,rtol,tol", FORMS)
+def test_step_two_photon_cat(precision, rtol, tol):
+    _compare(wl.model_two_photon_cat(R=5, alpha2=2.0, dt=1e-3), 60, 16, 8, precision, rtol, tol)
 
 
-@pytest.mark.parametrize("precision,rtol", [("fp64", 1e-10), ("fp32", 1e-5)])
-def test_step_driven_transmon(precision, rtol):
-    _compare(wl.model_transmon_resonator(Rt=4, Rr=3, eps=2.0, dt=2e-4), 20, 16, 8, precision, rtol)
+@pytest.mark.parametrize("precision,rtol,tol", FORMS)
+def test_step_cat_buffer(precision, rtol, tol):
+    _compare(wl.model_cat_buffer(Ra=4, Rb=3, alpha2=2.0, dt=1e-3), 30, 16, 8, precision, rtol, tol)
+
+
+@pytest.mark.parametrize("precision,rtol,tol", FORMS)
+def test_step_driven_transmon(precision, rtol, tol):
+    _compare(wl.model_transmon_resonator(Rt=4, Rr=3, eps=2.0, dt=2e-4), 20, 16, 8, precision, rtol, tol)
 
 
 def test_step_caps_bind_ragged():
     """Caps below the exact ranks (truncation by cap at every bond), odd sizes."""
-    _compare(wl.model_cat_buffer(Ra=4, Rb=3, alpha2=3.0, dt=1e-3), 15, 6, 3, "fp64", 1e-10)
+    _compare(wl.model_cat_buffer(Ra=4, Rb=3, alpha2=3.0, dt=1e-3), 15, 6, 3, "fp64", 1e-10, 1e-12)
 
 
 def test_identity_generator_keeps_state():
@@ -128,8 +135,8 @@ def test_synthetic_saturated_state_sampled():
     K = tt.KrausMPO(m, m.dt)
     Xo, _ = mps.right_canonicalize(raw, tol=1e-14)
     for s_ in range(3):
-        Xo, info = mps.k2_step(Xo, K.at(s_ * m.dt), 1e-8, chi, chi_mu)
-    s = api.solver_from_model(m, chi=chi, chi_mu=chi_mu, state="none")
+        Xo, info = mps.k2_step(Xo, K.at(s_ * m.dt), 1e-12, chi, chi_mu)
+    s = api.solver_from_model(m, chi=chi, chi_mu=chi_mu, tol=1e-12, state="none")
     s.set_state_mps(raw)
     s.step(3)
     Xg = s.get_state_mps()
