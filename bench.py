@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=3, help="steps of the plain FP64 form timed beside")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the method's step is a "
@@ -126,6 +128,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     print(f"bench: {args.precision} steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
+    if args.copy_calibration:
+        src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")   # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     elapsed, prof, diag = gpu_run(args.steps, args.warmup, args.precision)
     value = args.steps / elapsed
     print(f"bench: {value:.3f} steps/s, bonds {diag['bonds']}, chi_mu {diag['chi_mu']}",
