@@ -16,6 +16,15 @@ FP32 accumulation) and every Gram matrix, factorisation, truncation weight
 and trace in FP64.  A few steps of the plain FP64 form are timed beside it,
 and the CPU oracle (NumPy/LAPACK) on a bounded sample of the same workload.
 
+The serving leg runs a seeded subsample of the parameter-sweep request
+stream (two-photon cat, cat + buffer, driven transmon; Fock sizes 64-4096,
+bond caps 32-256, 100 steps each) through the library's continuous-batching
+loop (include/lindblad_serve.h): a burst (every request at t = 0) gives
+solves/s, a Poisson stream at 0.7 x that rate gives the p50/p99 latency from
+arrival to completion, both against the same requests solved one at a time in
+plain FP64.  The host-side Kraus-MPO builds (once per request) are done
+before the timed runs and reported separately.
+
 Prints one JSON line.  --gpus above 1 is not supported (one GPU).
 """
 from __future__ import annotations
@@ -25,6 +34,10 @@ import json
 import os
 import sys
 import time
+
+# hardware queues for the overlapping solves of the serving leg (HIP reads
+# this when it initialises, so it is set before torch is imported)
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -84,6 +97,83 @@ def gpu_run(steps: int, warmup: int, precision: str):
     return (t1 - t0), prof, d
 
 
+def build_requests(reqs, precision: str, threads: int = 16):
+    """Solvers (generator set, no state) and observables for serving requests;
+    the host builds run in parallel threads (the C calls release the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+    import workload as wl
+    from paper_2605_27515_amd import api
+
+    def one(r):
+        m = wl.model_from_request(r)
+        s = api.solver_from_model(m, precision=precision, state="none")
+        obs = [s.mpo([(1.0, {0: ("NUM_POW", 1)})]), s.mpo([(1.0, {0: ("A_POW", 1)})])]
+        return m, s, obs
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(one, reqs))
+
+
+def serve_once(built, slots: int, budget: int, arrivals):
+    from paper_2605_27515_amd import api
+    sv = api.Server(n_slots=slots, hbm_budget=budget)
+    for (m, s, obs), t in zip(built, arrivals):
+        sv.submit(s, m.init, m.steps, obs, arrival=float(t))
+    sv.run()
+    res = [sv.result(k) for k in range(len(built))]
+    st = sv.stats()
+    sv.close()
+    bad = [r for r in res if r["status"] != 0]
+    if bad:
+        raise RuntimeError(f"{len(bad)} serving requests failed (status {bad[0]['status']})")
+    return res, st
+
+
+def serving(n_req: int, slots: int, budget_gb: float) -> dict:
+    import numpy as np
+    import workload as wl
+    reqs = wl.serving_requests(512)[:n_req]
+    t0 = time.perf_counter()
+    fast = build_requests(reqs, "fp32")
+    plain = build_requests(reqs, "fp64")
+    build_s = time.perf_counter() - t0
+    budget = int(budget_gb * (1 << 30))
+    # burst: every request at t = 0
+    res, st = serve_once(fast, slots, budget, [0.0] * n_req)
+    burst = n_req / st["makespan"]
+    # Poisson stream at 0.7 x the burst rate
+    rate = 0.7 * burst
+    arr = wl.poisson_arrivals(n_req, rate)
+    res_p, st_p = serve_once(fast, slots, budget, arr)
+    lat = np.array([r["done"] - r["arrival"] for r in res_p])
+    # the same requests one at a time in plain FP64, same arrivals
+    res_b, st_b = serve_once(plain, 1, 0, arr)
+    lat_b = np.array([r["done"] - r["arrival"] for r in res_b])
+    svc_b = np.array([r["done"] - r["admitted"] for r in res_b])
+    # observables of the two forms (FP32 contractions vs plain FP64)
+    dev = max(abs(a - b) / max(1.0, abs(b)) for r1, r2 in zip(res_p, res_b)
+              for a, b in zip(r1["observables"], r2["observables"]))
+    for _, s, _ in fast + plain:
+        s.close()
+    fam = {}
+    for r in reqs:
+        fam[r["family"]] = fam.get(r["family"], 0) + 1
+    return {
+        "requests": n_req, "families": fam, "steps_per_request": reqs[0]["steps"], "slots": slots,
+        "hbm_budget_gb": budget_gb, "host_build_s": build_s,
+        "burst_solves_per_s": burst, "burst_peak_running": st["peak_running"],
+        "burst_peak_gb": st["peak_bytes"] / (1 << 30),
+        "poisson_rate_per_s": rate, "poisson_solves_per_s": n_req / st_p["makespan"],
+        "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+        "baseline_fp64_one_at_a_time": {
+            "solves_per_s": n_req / st_b["makespan"],
+            "p50_s": float(np.percentile(lat_b, 50)), "p99_s": float(np.percentile(lat_b, 99)),
+            "service_p50_s": float(np.percentile(svc_b, 50)), "service_p99_s": float(np.percentile(svc_b, 99))},
+        "solves_per_s_vs_baseline": burst / (n_req / st_b["makespan"]),
+        "max_rel_observable_diff_fp32_vs_fp64": dev,
+    }
+
+
 def cpu_baseline(budget_s: float) -> dict:
     """The oracle as it stands, on the same workload, for a bounded sample."""
     import numpy as np
@@ -116,6 +206,10 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=3, help="steps of the plain FP64 form timed beside")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--serve-requests", type=int, default=64,
+                    help="requests of the seeded serving stream (0: skip the serving leg)")
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-budget-gb", type=float, default=8.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -143,6 +237,12 @@ def main():
         e64, _, _ = gpu_run(args.fp64_steps, 1, "fp64")
         fp64 = args.fp64_steps / e64
         print(f"bench: plain fp64 {fp64:.3f} steps/s", file=sys.stderr, flush=True)
+    serve = None
+    if args.serve_requests > 0:
+        serve = serving(args.serve_requests, args.serve_slots, args.serve_budget_gb)
+        print(f"bench: serving {serve['burst_solves_per_s']:.2f} solves/s (burst), p50 {serve['p50_s']:.3f} s "
+              f"p99 {serve['p99_s']:.3f} s; one-at-a-time FP64 "
+              f"{serve['baseline_fp64_one_at_a_time']['solves_per_s']:.2f} solves/s", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(args.cpu_seconds)
@@ -171,6 +271,7 @@ def main():
         "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items() if v["launches"]},
         "kernel_share": {k: v["ms"] / total_ms for k, v in prof.items() if v["launches"]} if total_ms else {},
         "final_bonds": diag["bonds"],
+        "serving": serve,
     }
     print(json.dumps(line), flush=True)
 

@@ -202,10 +202,28 @@ lb_status lindblad_step(lb_solver* s, int32_t n_steps);
  * that live on the same device.  Solvers may differ in sizes and caps. */
 lb_status lindblad_step_batch(lb_solver* const* s, int32_t n, int32_t n_steps);
 
+/* ---- device residency (for request loops that admit solves by memory) --- */
+
+/* Copy the solver's configuration to *cfg.  Host only. */
+lb_status lindblad_get_config(const lb_solver* s, lb_config* cfg);
+
+/* Device bytes the solver holds once its Kraus MPO, workspace and state are
+ * on the device (allocation size classes included; observable MPOs, a few
+ * KB each, excluded).  Host only.  Errors: LB_ERR_STATE before
+ * set_generator. */
+lb_status lindblad_footprint(const lb_solver* s, int64_t* bytes);
+
+/* Synchronise the solver's stream and give back all its device memory
+ * (state, workspace, MPO copies) to the library's block cache, where other
+ * solvers of the process reuse it.  The generator and operators stay on the
+ * host; the state is gone, so set_state_* must precede the next step.
+ * Errors: LB_ERR_ARG, LB_ERR_HIP. */
+lb_status lindblad_release(lb_solver* s);
+
 /* ---- observation (synchronises the solver's stream) ----------------------- */
 
 /* out[0] + i out[1] = Tr(O rho) by transfer matrices (paper Sec. 3.2 and
- * Sec. 6 define the expectation values used). Errors: LB_ERR_NUMERIC if the
+ * Sec. 6.2 define the expectation values used). Errors: LB_ERR_NUMERIC if the
  * state holds non-finite values. */
 lb_status lindblad_observe(lb_solver* s, const lb_op* O, double out[2]);
 

@@ -4,7 +4,7 @@ Factor kinds follow the operator descriptions in ``workload``; matrices are
 the truncated (N = 2^R) Fock or charge-basis representations.
 
 Paper: Sec. 2.2 (matrix elements of a, a^m, (a^dagger)^m a^m),
-Sec. 6 (charge-basis n_t and cos(phi) as half the sum of the two shifts).
+Sec. 7.1 (charge-basis n_t and cos(phi) as half the sum of the two shifts).
 """
 from __future__ import annotations
 

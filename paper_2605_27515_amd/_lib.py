@@ -1,4 +1,5 @@
-"""ctypes declarations of the C ABI in include/lindblad.h.
+"""ctypes declarations of the C ABI in include/lindblad.h, lindblad_serve.h and
+lindblad_kernels.h.
 
 Loading fails loudly when the HIP library has not been built: there is no
 fallback implementation of any part of the step.
@@ -28,7 +29,9 @@ EXPORTED = ["lindblad_default_config", "lindblad_create", "lindblad_destroy",
             "lindblad_get_state_mps", "lindblad_step", "lindblad_step_batch",
             "lindblad_observe", "lindblad_trace_purity", "lindblad_diagnostics",
             "lindblad_last_error", "lindblad_profile", "lindblad_profile_read", "lindblad_kernel_zgemm", "lindblad_kernel_heev",
-            "lindblad_kernel_truncate"]
+            "lindblad_kernel_truncate", "lindblad_get_config", "lindblad_footprint", "lindblad_release",
+            "lindblad_server_create", "lindblad_server_submit", "lindblad_server_run",
+            "lindblad_server_result", "lindblad_server_stats", "lindblad_server_destroy"]
 
 
 class LbConfig(C.Structure):
@@ -66,6 +69,27 @@ class LbDiag(C.Structure):
 class LbProfile(C.Structure):
     _fields_ = [("n", C.c_int32), ("name", (C.c_char * 24) * 16), ("launches", C.c_int64 * 16),
                 ("ms", C.c_double * 16), ("flop", C.c_double * 16), ("bytes", C.c_double * 16)]
+
+
+class LbServerConfig(C.Structure):
+    _fields_ = [("n_slots", C.c_int32), ("hbm_budget", C.c_int64)]
+
+
+class LbRequest(C.Structure):
+    _fields_ = [("solver", C.c_void_p), ("init", C.POINTER(C.POINTER(C.c_double))),
+                ("n_steps", C.c_int32), ("obs", C.POINTER(C.c_void_p)), ("n_obs", C.c_int32),
+                ("arrival", C.c_double)]
+
+
+class LbResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("arrival", C.c_double), ("admitted", C.c_double),
+                ("done", C.c_double), ("bytes", C.c_int64), ("max_tau_defect", C.c_double),
+                ("chi_mu", C.c_int32), ("max_bond", C.c_int32)]
+
+
+class LbServerStats(C.Structure):
+    _fields_ = [("makespan", C.c_double), ("peak_bytes", C.c_int64), ("peak_running", C.c_int32),
+                ("completed", C.c_int32)]
 
 
 _lib = None
@@ -114,11 +138,22 @@ def load() -> C.CDLL:
     lib.lindblad_kernel_truncate.argtypes = [C.c_int32, dp, C.c_double, C.c_int32, C.POINTER(C.c_int32), dp]
     lib.lindblad_profile.argtypes = [vp, C.c_int32]
     lib.lindblad_profile_read.argtypes = [vp, C.POINTER(LbProfile)]
+    lib.lindblad_get_config.argtypes = [vp, C.POINTER(LbConfig)]
+    lib.lindblad_footprint.argtypes = [vp, C.POINTER(C.c_int64)]
+    lib.lindblad_release.argtypes = [vp]
+    lib.lindblad_server_create.argtypes = [C.POINTER(LbServerConfig), C.POINTER(vp)]
+    lib.lindblad_server_submit.argtypes = [vp, C.POINTER(LbRequest), C.POINTER(C.c_int32)]
+    lib.lindblad_server_run.argtypes = [vp]
+    lib.lindblad_server_result.argtypes = [vp, C.c_int32, C.POINTER(LbResult), C.POINTER(C.c_double)]
+    lib.lindblad_server_stats.argtypes = [vp, C.POINTER(LbServerStats)]
+    lib.lindblad_server_destroy.argtypes = [vp]
+    lib.lindblad_server_destroy.restype = None
     lib.lindblad_last_error.argtypes = []
     lib.lindblad_last_error.restype = C.c_char_p
     for name in EXPORTED:
         fn = getattr(lib, name)
-        if name not in ("lindblad_default_config", "lindblad_destroy", "lindblad_last_error"):
+        if name not in ("lindblad_default_config", "lindblad_destroy", "lindblad_last_error",
+                        "lindblad_server_destroy"):
             fn.restype = C.c_int
     _lib = lib
     return lib

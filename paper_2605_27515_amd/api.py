@@ -210,6 +210,14 @@ class Solver:
         return {p.name[i].value.decode(): dict(launches=int(p.launches[i]), ms=p.ms[i], flop=p.flop[i],
                                                 bytes=p.bytes[i]) for i in range(p.n)}
 
+    def footprint(self) -> int:
+        b = C.c_int64()
+        _check(L.load().lindblad_footprint(self.h, C.byref(b)), "footprint")
+        return int(b.value)
+
+    def release(self):
+        _check(L.load().lindblad_release(self.h), "release")
+
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
             L.load().lindblad_destroy(self.h)
@@ -243,6 +251,60 @@ def solver_from_model(model, precision: str = "fp64", chi: int | None = None,
     if state == "init":
         s.set_state_product(model.init)
     return s
+
+
+# ---- request loop (include/lindblad_serve.h) --------------------------------
+
+class Server:
+    """Continuous-batching loop over independent solves (lindblad_server_*)."""
+
+    def __init__(self, n_slots: int = 8, hbm_budget: int = 0):
+        lib = L.load()
+        cfg = L.LbServerConfig(int(n_slots), int(hbm_budget))
+        h = C.c_void_p()
+        _check(lib.lindblad_server_create(C.byref(cfg), C.byref(h)), "server_create")
+        self.h = h
+        self.n_obs = []
+
+    def submit(self, solver: Solver, init, n_steps: int, observables=(), arrival: float = 0.0) -> int:
+        arrs = [np.ascontiguousarray(np.asarray(v, np.complex128)) for v in init]
+        ptrs = (C.POINTER(C.c_double) * len(arrs))(*[_dptr(a.view(np.float64)) for a in arrs])
+        obs = (C.c_void_p * max(len(observables), 1))(*[o.handle.value for o in observables])
+        req = L.LbRequest(solver.h.value, ptrs, int(n_steps), obs, len(observables), float(arrival))
+        t = C.c_int32()
+        _check(L.load().lindblad_server_submit(self.h, C.byref(req), C.byref(t)), "server_submit")
+        self.n_obs.append(len(observables))
+        return int(t.value)
+
+    def run(self):
+        _check(L.load().lindblad_server_run(self.h), "server_run")
+
+    def result(self, ticket: int) -> dict:
+        r = L.LbResult()
+        n_obs = self.n_obs[ticket] if 0 <= ticket < len(self.n_obs) else 0
+        out = np.zeros(2 * max(n_obs, 1))
+        _check(L.load().lindblad_server_result(self.h, int(ticket), C.byref(r), _dptr(out)), "server_result")
+        vals = [complex(out[2 * i], out[2 * i + 1]) for i in range(n_obs)]
+        return dict(status=r.status, arrival=r.arrival, admitted=r.admitted, done=r.done, bytes=r.bytes,
+                    max_tau_defect=r.max_tau_defect, chi_mu=r.chi_mu, max_bond=r.max_bond,
+                    observables=vals)
+
+    def stats(self) -> dict:
+        st = L.LbServerStats()
+        _check(L.load().lindblad_server_stats(self.h, C.byref(st)), "server_stats")
+        return dict(makespan=st.makespan, peak_bytes=st.peak_bytes, peak_running=st.peak_running,
+                    completed=st.completed)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            L.load().lindblad_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---- component entry points (include/lindblad_kernels.h) ---------------------

@@ -15,8 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblindblad.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["engine.hip", "kernels.hip", "capi_kernels.hip", "mpo.cpp", "hostla.cpp"]
-HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+SOURCES = ["engine.hip", "kernels.hip", "capi_kernels.hip", "mpo.cpp", "hostla.cpp", "serve.cpp"]
+HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-pthread",
              # packed FP32 arithmetic stays off (hardware notes)
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-result"]
@@ -32,13 +32,13 @@ def build(verbose: bool = False) -> str:
         if src.endswith(".hip"):
             cmd = [HIPCC, *HIP_FLAGS, "-c", path, "-o", obj]
         else:
-            cmd = [HIPCC, "-O3", "-std=c++17", "-fPIC", "-c", path, "-o", obj]
+            cmd = [HIPCC, "-O3", "-std=c++17", "-fPIC", "-pthread", "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -31,6 +31,9 @@
 #include <stdexcept>
 #include <string>
 #include <vector>
+#include <map>
+#include <mutex>
+#include <thread>
 
 #include "../../include/lindblad.h"
 #include "kernels.h"
@@ -54,31 +57,77 @@ struct Fail : std::runtime_error {
       throw Fail(LB_ERR_HIP, std::string(#x " failed: ") + hipGetErrorString(e_));      \
   } while (0)
 
+// Process-wide cache of device blocks, by (device, power-of-two size class).
+// A released block goes back to the cache, not to HIP: hipFree synchronises
+// the whole device and would stall every other solve in flight.  A block is
+// put back only after the stream it was used on has drained, so a block in
+// the cache has no pending work and any stream may take it.
+struct BlockCache {
+  std::mutex mu;
+  std::map<std::pair<int, size_t>, std::vector<void*>> free;
+};
+
+BlockCache& block_cache() {
+  static BlockCache* c = new BlockCache;   // never destroyed: blocks live until exit
+  return *c;
+}
+
+size_t size_class(size_t b) {
+  size_t c = 256;
+  while (c < b) c <<= 1;
+  return c;
+}
+
 struct DevBuf {
   void* p = nullptr;
-  size_t bytes = 0;
+  size_t bytes = 0;             // size class actually held
+  int dev = 0;
+  hipStream_t st = nullptr;     // the stream the block is used on
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), dev(o.dev), st(o.st) { o.p = nullptr; o.bytes = 0; }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    if (this != &o) {
+      release();
+      p = o.p; bytes = o.bytes; dev = o.dev; st = o.st;
+      o.p = nullptr; o.bytes = 0;
+    }
     return *this;
   }
-  void alloc(size_t b) {
-    if (b <= bytes && p) return;
+  void alloc(size_t b, hipStream_t stream) {
+    if (b <= bytes && p) { st = stream; return; }
     release();
-    if (b == 0) b = 16;
-    hipError_t e = hipMalloc(&p, b);
-    if (e != hipSuccess) {
-      p = nullptr;
-      bytes = 0;
-      throw Fail(LB_ERR_OOM, "hipMalloc of " + std::to_string(b) + " bytes failed");
+    const size_t cls = size_class(b);
+    int d = 0;
+    (void)hipGetDevice(&d);
+    void* q = nullptr;
+    {
+      BlockCache& c = block_cache();
+      std::lock_guard<std::mutex> g(c.mu);
+      auto it = c.free.find({d, cls});
+      if (it != c.free.end() && !it->second.empty()) {
+        q = it->second.back();
+        it->second.pop_back();
+      }
     }
-    bytes = b;
+    if (!q) {
+      hipError_t e = hipMalloc(&q, cls);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Fail(LB_ERR_OOM, "hipMalloc of " + std::to_string(cls) + " bytes failed");
+      }
+    }
+    p = q; bytes = cls; dev = d; st = stream;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (!p) return;
+    if (st) (void)hipStreamSynchronize(st);
+    BlockCache& c = block_cache();
+    {
+      std::lock_guard<std::mutex> g(c.mu);
+      c.free[{dev, bytes}].push_back(p);
+    }
     p = nullptr;
     bytes = 0;
   }
@@ -276,10 +325,10 @@ void upload_mpo(lb_solver* s, const lb::Mpo& m, DevMpo& d, bool want32) {
         for (int i = 0; i < 2; ++i)
           for (int r = 0; r < x.r; ++r)
             h[((size_t)o * x.r + r) * (2 * x.l) + (size_t)l * 2 + i] = x.at(l, o, i, r);
-    d.d64[k].alloc(h.size() * sizeof(cd));
+    d.d64[k].alloc(h.size() * sizeof(cd), s->stream);
     HIPCHK(hipMemcpyAsync(d.d64[k].p, h.data(), h.size() * sizeof(cd), hipMemcpyHostToDevice, s->stream));
     if (want32) {
-      d.d32[k].alloc(h.size() * 2 * sizeof(float));
+      d.d32[k].alloc(h.size() * 2 * sizeof(float), s->stream);
       HIPCHK(lbk::to_f32(d.d64[k].d(), d.d32[k].f(), (long long)h.size(), s->stream));
     }
   }
@@ -443,76 +492,141 @@ double* left_svd(lb_solver* s, const void* A, Prec pa, int n, long long m, long 
   return Uf;
 }
 
-void alloc_workspace(lb_solver* s) {
+// Bond capacities of the state (bounded by 2^i, 2^(L-i) chi_mu and chi) and
+// the element count of one site buffer; zip-up sites may carry the zip cap on
+// their bonds before the back-sweep.
+std::vector<int> state_caps(const lb_solver* s, size_t* site_cap) {
+  const int L = s->L;
+  std::vector<int> cap(L + 1, 1);
+  const long long chi = s->cfg.chi_cap, mu = s->cfg.chi_mu_cap;
+  for (int i = 1; i < L; ++i) {
+    long long c = std::min<long long>(chi, 1LL << std::min(i, 30));
+    c = std::min<long long>(c, (1LL << std::min(L - i, 30)) * mu);
+    cap[i] = (int)c;
+  }
+  cap[L] = (int)mu;
+  const int zc = s->cfg.chi_zip_cap > 0 ? s->cfg.chi_zip_cap : s->cfg.chi_cap;
+  size_t mx = 1;
+  for (int i = 0; i < L; ++i) {
+    const long long l = std::max<long long>(cap[i], std::min<long long>(zc, 1LL << std::min(i, 30)));
+    const long long r = std::max<long long>(cap[i + 1], std::min<long long>(zc, 1LL << std::min(i + 1, 30)));
+    mx = std::max<size_t>(mx, (size_t)l * 2 * r);
+  }
+  mx = std::max<size_t>(mx, (size_t)std::max(zc, (int)chi) * 2 * (size_t)std::max<long long>(mu * 16, chi));
+  *site_cap = mx;
+  return cap;
+}
+
+// Byte sizes of the workspace buffers, in the order of WorkPlan::buffers().
+struct WorkPlan {
+  int nmax = 2;
+  long long mmax = 1;
+  size_t C = 0, P = 0, T = 0, nn = 0, ework = 0, wide = 0, lam = 0, ws = 0, scratch = 0;
+  static constexpr size_t kSmall = 64;
+};
+
+WorkPlan work_plan(const lb_solver* s, const std::vector<int>& cap) {
   const int L = s->L;
   const int zc = s->cfg.chi_zip_cap > 0 ? s->cfg.chi_zip_cap : s->cfg.chi_cap;
-  int nmax = 2;
-  long long mmax = 1, cmax = 1, pmax = 1;
+  WorkPlan w;
+  long long cmax = 1, pmax = 1;
   std::vector<int> zcap(L + 1, 1);
   for (int i = 1; i <= L; ++i) zcap[i] = (int)std::min<long long>(zc, 1LL << std::min(i, 30));
   for (int i = 0; i < L; ++i) {
     const int zl = zcap[i];
-    const int cr = (i == L - 1) ? s->cfg.chi_mu_cap : s->cap[i + 1];
-    const int cl = s->cap[i];
-    nmax = std::max(nmax, 2 * zl);
-    mmax = std::max(mmax, (long long)s->wb[i + 1] * cr);
+    const int cr = (i == L - 1) ? s->cfg.chi_mu_cap : cap[i + 1];
+    const int cl = cap[i];
+    w.nmax = std::max(w.nmax, 2 * zl);
+    w.mmax = std::max(w.mmax, (long long)s->wb[i + 1] * cr);
     cmax = std::max(cmax, (long long)zl * s->wb[i] * cl);
     pmax = std::max(pmax, (long long)zl * s->wb[i] * 2 * cr);
   }
   // the last site's column Gram has m = K * chi_mu columns
-  nmax = std::max<long long>(nmax, (long long)s->n_kraus * s->cfg.chi_mu_cap);
-  nmax = std::max(nmax, 2 * s->cfg.chi_cap);
-  if (nmax > 512) throw Fail(LB_ERR_ARG, "zip-up factor dimension exceeds 512 (chi_zip or chi_mu*K too large)");
-  s->n_max = nmax;
-  s->m_max = mmax;
+  w.nmax = std::max<long long>(w.nmax, (long long)s->n_kraus * s->cfg.chi_mu_cap);
+  w.nmax = std::max(w.nmax, 2 * s->cfg.chi_cap);
+  if (w.nmax > 512) throw Fail(LB_ERR_ARG, "zip-up factor dimension exceeds 512 (chi_zip or chi_mu*K too large)");
   const size_t cbytes = fp32(s) ? 8 : 16;
-  s->C.alloc(std::max(cmax, (long long)nmax * mmax) * cbytes);
-  s->P.alloc(pmax * cbytes);
-  s->T.alloc((size_t)nmax * mmax * cbytes);
-  const size_t nn = (size_t)nmax * nmax * 16;
-  s->G.alloc(nn);
-  s->G2.alloc(nn);
-  s->Uf.alloc(nn);
-  s->U0.alloc(nn);
-  s->V.alloc(nn);
-  s->ework.alloc(lbk::heev_tridiag_work_doubles(nmax) * sizeof(double));
-  s->Bm.alloc((size_t)nmax * std::max<long long>(mmax, nmax) * 16);
-  s->U2.alloc((size_t)nmax * std::max<long long>(mmax, nmax) * 16);
-  s->lam.alloc((size_t)nmax * 8);
-  s->lam2.alloc((size_t)nmax * 8);
-  s->ws.alloc((size_t)64 * nmax * nmax * 16 + (size_t)512 * 64 * 64 * 16);
-  s->kdev.alloc(64);
-  s->disc.alloc(64);
-  s->tau.alloc(64);
-  s->flag.alloc(64);
-  s->info.alloc(64);
-  s->scratch.alloc((size_t)4 * nmax * nmax * 16);
+  w.C = std::max(cmax, (long long)w.nmax * w.mmax) * cbytes;
+  w.P = pmax * cbytes;
+  w.T = (size_t)w.nmax * w.mmax * cbytes;
+  w.nn = (size_t)w.nmax * w.nmax * 16;
+  w.ework = lbk::heev_tridiag_work_doubles(w.nmax) * sizeof(double);
+  w.wide = (size_t)w.nmax * std::max<long long>(w.mmax, w.nmax) * 16;
+  w.lam = (size_t)w.nmax * 8;
+  // split-K partial sums: splits * tiles <= 512 tiles of 64 x 64 complex
+  w.ws = (size_t)512 * 64 * 64 * 16;
+  w.scratch = (size_t)4 * w.nmax * w.nmax * 16;
+  return w;
+}
+
+void alloc_workspace(lb_solver* s) {
+  const WorkPlan w = work_plan(s, s->cap);
+  hipStream_t st = s->stream;
+  s->n_max = w.nmax;
+  s->m_max = w.mmax;
+  s->C.alloc(w.C, st);
+  s->P.alloc(w.P, st);
+  s->T.alloc(w.T, st);
+  for (DevBuf* b : {&s->G, &s->G2, &s->Uf, &s->U0, &s->V}) b->alloc(w.nn, st);
+  s->ework.alloc(w.ework, st);
+  s->Bm.alloc(w.wide, st);
+  s->U2.alloc(w.wide, st);
+  s->lam.alloc(w.lam, st);
+  s->lam2.alloc(w.lam, st);
+  s->ws.alloc(w.ws, st);
+  for (DevBuf* b : {&s->kdev, &s->disc, &s->tau, &s->flag, &s->info}) b->alloc(WorkPlan::kSmall, st);
+  s->scratch.alloc(w.scratch, st);
   HIPCHK(hipMemsetAsync(s->flag.p, 0, 64, s->stream));
 }
 
 void alloc_state(lb_solver* s) {
   const int L = s->L;
-  s->cap.assign(L + 1, 1);
-  const long long chi = s->cfg.chi_cap, mu = s->cfg.chi_mu_cap;
-  for (int i = 1; i < L; ++i) {
-    long long c = std::min<long long>(chi, 1LL << std::min(i, 30));
-    c = std::min<long long>(c, (1LL << std::min(L - i, 30)) * mu);
-    s->cap[i] = (int)c;
-  }
-  s->cap[L] = (int)mu;
-  // zip-up sites may carry the zip cap on their bonds before the back-sweep
-  const int zc = s->cfg.chi_zip_cap > 0 ? s->cfg.chi_zip_cap : s->cfg.chi_cap;
-  size_t mx = 1;
-  for (int i = 0; i < L; ++i) {
-    const long long l = std::max<long long>(s->cap[i], std::min<long long>(zc, 1LL << std::min(i, 30)));
-    const long long r = std::max<long long>(s->cap[i + 1], std::min<long long>(zc, 1LL << std::min(i + 1, 30)));
-    mx = std::max<size_t>(mx, (size_t)l * 2 * r);
-  }
-  mx = std::max<size_t>(mx, (size_t)std::max(zc, (int)chi) * 2 * (size_t)std::max<long long>(mu * 16, chi));
-  s->site_cap = mx;
+  s->cap = state_caps(s, &s->site_cap);
   s->X.resize(L);
-  for (int i = 0; i < L; ++i) s->X[i].alloc(mx * 16);
-  s->Xspare.alloc(mx * 16);
+  for (int i = 0; i < L; ++i) s->X[i].alloc(s->site_cap * 16, s->stream);
+  s->Xspare.alloc(s->site_cap * 16, s->stream);
+}
+
+// Device bytes a solver holds once its generator and state are on the device
+// (the size classes the block cache hands out).
+size_t footprint_bytes(const lb_solver* s) {
+  size_t site_cap = 0;
+  const std::vector<int> cap = state_caps(s, &site_cap);
+  const WorkPlan w = work_plan(s, cap);
+  size_t t = (size_t)(s->L + 1) * size_class(site_cap * 16);
+  t += size_class(w.C) + size_class(w.P) + size_class(w.T) + 5 * size_class(w.nn) + size_class(w.ework);
+  t += 2 * size_class(w.wide) + 2 * size_class(w.lam) + size_class(w.ws) + 5 * size_class(WorkPlan::kSmall);
+  t += size_class(w.scratch);
+  for (const lb::Site& x : s->kraus_dev) {
+    const size_t e = (size_t)x.l * 4 * x.r;
+    t += size_class(e * 16);
+    if (fp32(s)) t += size_class(e * 8);
+  }
+  if (s->degree > 1) t += size_class(s->h0.size() * sizeof(cd));
+  return t;
+}
+
+// Free every device buffer of the solver (state, workspace, MPOs); the host
+// copies of the generator and operators stay.
+void release_device(lb_solver* s) {
+  if (s->dev_ready && s->stream) HIPCHK(hipStreamSynchronize(s->stream));
+  for (auto& x : s->X) x.release();
+  s->X.clear();
+  s->Xspare.release();
+  for (DevBuf* b : {&s->C, &s->P, &s->T, &s->Bm, &s->G, &s->G2, &s->U2, &s->Uf, &s->U0, &s->V, &s->lam,
+                    &s->lam2, &s->ws, &s->kdev, &s->disc, &s->tau, &s->flag, &s->info, &s->scratch, &s->ework})
+    b->release();
+  for (auto& b : s->W.d64) b.release();
+  for (auto& b : s->W.d32) b.release();
+  s->Wb0.release();
+  for (auto& op : s->ops) {
+    for (auto& b : op->dev.d64) b.release();
+    for (auto& b : op->dev.d32) b.release();
+    op->uploaded = false;
+  }
+  s->cap.clear();
+  s->gen_on_device = false;
+  s->have_state = false;
 }
 
 void ensure_device(lb_solver* s) {
@@ -533,7 +647,7 @@ void ensure_generator_on_device(lb_solver* s) {
   if (s->gen_on_device) return;
   HIPCHK(hipSetDevice(s->cfg.device));
   if (s->degree > 1) {
-    s->Wb0.alloc(s->h0.size() * sizeof(cd));
+    s->Wb0.alloc(s->h0.size() * sizeof(cd), s->stream);
     HIPCHK(hipMemcpyAsync(s->Wb0.p, s->h0.data(), s->h0.size() * sizeof(cd), hipMemcpyHostToDevice, s->stream));
   }
   upload_mpo(s, s->kraus_dev, s->W, fp32(s));
@@ -950,6 +1064,7 @@ lb_status lindblad_kraus_info(const lb_solver* s, int32_t* bonds, int32_t* n_kra
 
 static lb_status load_mps(lb_solver* s, const std::vector<int>& bonds, const std::vector<const cd*>& sites) {
   const int L = s->L;
+  HIPCHK(hipSetDevice(s->cfg.device));
   ensure_generator_on_device(s);
   for (int i = 0; i < L; ++i) {
     const size_t cnt = (size_t)bonds[i] * 2 * bonds[i + 1];
@@ -1044,8 +1159,9 @@ lb_status lindblad_get_state_mps(lb_solver* s, int32_t* bonds, double** sites) {
     if (sites)
       for (int i = 0; i < s->L; ++i) {
         const size_t cnt = (size_t)s->chi[i] * 2 * s->chi[i + 1];
-        HIPCHK(hipMemcpy(sites[i], s->X[i].p, cnt * sizeof(cd), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpyAsync(sites[i], s->X[i].p, cnt * sizeof(cd), hipMemcpyDeviceToHost, s->stream));
       }
+    HIPCHK(hipStreamSynchronize(s->stream));
     return LB_OK;
   } catch (const Fail& f) {
     return fail(f);
@@ -1056,6 +1172,7 @@ lb_status lindblad_step(lb_solver* s, int32_t n_steps) {
   try {
     if (!s || n_steps < 0) throw Fail(LB_ERR_ARG, "bad argument");
     if (!s->have_gen || !s->have_state) throw Fail(LB_ERR_STATE, "set_generator and set_state first");
+    HIPCHK(hipSetDevice(s->cfg.device));
     for (int k = 0; k < n_steps; ++k) step_once(s);
     return LB_OK;
   } catch (const Fail& f) {
@@ -1072,9 +1189,58 @@ lb_status lindblad_step_batch(lb_solver* const* ss, int32_t n, int32_t n_steps) 
     for (int j = 0; j < n; ++j) {
       if (!ss[j]) throw Fail(LB_ERR_ARG, "NULL solver in batch");
       if (!ss[j]->have_gen || !ss[j]->have_state) throw Fail(LB_ERR_STATE, "solver not ready");
+      for (int i = 0; i < j; ++i)
+        if (ss[i] == ss[j]) throw Fail(LB_ERR_ARG, "a solver appears twice in the batch");
     }
-    for (int k = 0; k < n_steps; ++k)
-      for (int j = 0; j < n; ++j) step_once(ss[j]);
+    if (n == 1) return lindblad_step(ss[0], n_steps);
+    // one host thread per solve, each driving its solver's own stream, so the
+    // solves' kernels overlap on the device
+    std::vector<lb_status> rc(n, LB_OK);
+    std::vector<std::string> msg(n);
+    std::vector<std::thread> th;
+    th.reserve(n);
+    for (int j = 0; j < n; ++j)
+      th.emplace_back([&, j] {
+        rc[j] = lindblad_step(ss[j], n_steps);
+        if (rc[j] != LB_OK) msg[j] = g_last_error;
+      });
+    for (auto& t : th) t.join();
+    for (int j = 0; j < n; ++j)
+      if (rc[j] != LB_OK) {
+        g_last_error = "solver " + std::to_string(j) + " of the batch: " + msg[j];
+        return rc[j];
+      }
+    return LB_OK;
+  } catch (const Fail& f) {
+    return fail(f);
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return LB_ERR_HIP;
+  }
+}
+
+lb_status lindblad_get_config(const lb_solver* s, lb_config* cfg) {
+  if (!s || !cfg) { g_last_error = "NULL argument"; return LB_ERR_ARG; }
+  *cfg = s->cfg;
+  return LB_OK;
+}
+
+lb_status lindblad_footprint(const lb_solver* s, int64_t* bytes) {
+  try {
+    if (!s || !bytes) throw Fail(LB_ERR_ARG, "NULL argument");
+    if (!s->have_gen) throw Fail(LB_ERR_STATE, "set_generator first");
+    *bytes = (int64_t)footprint_bytes(s);
+    return LB_OK;
+  } catch (const Fail& f) {
+    return fail(f);
+  }
+}
+
+lb_status lindblad_release(lb_solver* s) {
+  try {
+    if (!s) throw Fail(LB_ERR_ARG, "NULL argument");
+    if (s->dev_ready) HIPCHK(hipSetDevice(s->cfg.device));
+    release_device(s);
     return LB_OK;
   } catch (const Fail& f) {
     return fail(f);
@@ -1106,11 +1272,11 @@ lb_status lindblad_observe(lb_solver* s, const lb_op* Oc, double out[2]) {
       need = std::max<size_t>(need, (size_t)s->chi[i + 1] * wo[i + 1] * s->chi[i + 1]);
     }
     DevBuf E, T1, T2;
-    E.alloc(need * 16);
-    T1.alloc(need * 16);
-    T2.alloc(need * 16);
+    E.alloc(need * 16, s->stream);
+    T1.alloc(need * 16, s->stream);
+    T2.alloc(need * 16, s->stream);
     DevBuf res;
-    res.alloc(64);
+    res.alloc(64, s->stream);
     for (int i = 0; i < L; ++i) {
       const int cl = s->chi[i], cr = s->chi[i + 1], ul = wo[i], vr = wo[i + 1];
       const void* Tin;
@@ -1148,9 +1314,9 @@ lb_status lindblad_trace_purity(lb_solver* s, double* trace, double* purity) {
     size_t need = 1;
     for (int i = 0; i < L; ++i) need = std::max<size_t>(need, (size_t)s->chi[i] * 2 * s->chi[i + 1]);
     DevBuf E, T1, res;
-    E.alloc(need * 16);
-    T1.alloc(need * 16);
-    res.alloc(64);
+    E.alloc(need * 16, s->stream);
+    T1.alloc(need * 16, s->stream);
+    res.alloc(64, s->stream);
     for (int i = 0; i < L; ++i) {
       const int cl = s->chi[i], cr = s->chi[i + 1];
       const void* Tin;
@@ -1193,7 +1359,8 @@ lb_status lindblad_diagnostics(lb_solver* s, lb_diag* out) {
     for (int i = 0; i < s->L && i < (int)s->discarded.size(); ++i) out->discarded[i] = s->discarded[i];
     int flag = 0;
     if (s->flag.p) {
-      HIPCHK(hipMemcpy(&flag, s->flag.p, sizeof(int), hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpyAsync(&flag, s->flag.p, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+      HIPCHK(hipStreamSynchronize(s->stream));
     }
     if (flag) throw Fail(LB_ERR_NUMERIC, "non-finite trace encountered during a step");
     return LB_OK;

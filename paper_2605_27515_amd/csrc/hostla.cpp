@@ -26,53 +26,107 @@ ZMat matmul(const ZMat& x, const ZMat& y) {
   return z;
 }
 
-void householder_qr(const ZMat& A, ZMat& Q, ZMat& R) {
-  const int m = A.r, n = A.c, k = std::min(m, n);
-  ZMat W = A;                          // becomes R in its upper part
-  std::vector<std::vector<cd>> vs(k);  // Householder vectors
-  std::vector<cd> beta(k, cd(0.0, 0.0));
-  for (int j = 0; j < k; ++j) {
+// Householder QR with optional column pivoting and early stop.  The loops
+// run along rows (row-major storage).  With pivot, the column of largest
+// remaining norm is eliminated next and the factorisation stops once the
+// remaining columns hold at most stop2 of squared Frobenius norm.
+static void qr_core(const ZMat& A, bool pivot, double stop2, ZMat& Q, ZMat& R) {
+  const int m = A.r, n = A.c, kmax = std::min(m, n);
+  ZMat W = A;
+  std::vector<int> perm(n);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::vector<std::vector<cd>> vs;
+  std::vector<double> beta;
+  std::vector<cd> acc(n);
+  std::vector<double> cn(n);
+  int k = 0;
+  for (int j = 0; j < kmax; ++j) {
+    if (pivot) {
+      std::fill(cn.begin() + j, cn.end(), 0.0);
+      for (int i = j; i < m; ++i) {
+        const cd* row = &W.a[(size_t)i * n];
+        for (int c = j; c < n; ++c) cn[c] += std::norm(row[c]);
+      }
+      double rem = 0.0;
+      int p = j;
+      for (int c = j; c < n; ++c) {
+        rem += cn[c];
+        if (cn[c] > cn[p]) p = c;
+      }
+      if (j > 0 && rem <= stop2) break;
+      if (p != j) {
+        for (int i = 0; i < m; ++i) std::swap(W(i, j), W(i, p));
+        std::swap(perm[j], perm[p]);
+      }
+    }
     double norm2 = 0.0;
     for (int i = j; i < m; ++i) norm2 += std::norm(W(i, j));
     const double nrm = std::sqrt(norm2);
     std::vector<cd> v(m - j, cd(0.0, 0.0));
-    if (nrm == 0.0) { vs[j] = v; beta[j] = 0.0; continue; }
-    const cd x0 = W(j, j);
-    const cd phase = (std::abs(x0) > 0.0) ? x0 / std::abs(x0) : cd(1.0, 0.0);
-    const cd alpha = -phase * nrm;     // reflect x onto alpha e_1
-    v[0] = x0 - alpha;
-    for (int i = j + 1; i < m; ++i) v[i - j] = W(i, j);
-    double vn2 = 0.0;
-    for (auto& e : v) vn2 += std::norm(e);
-    if (vn2 == 0.0) { vs[j] = v; beta[j] = 0.0; continue; }
-    const double b = 2.0 / vn2;
-    // apply H = I - b v v^H to W[j:, j:]
-    for (int c = j; c < n; ++c) {
-      cd s(0.0, 0.0);
-      for (int i = j; i < m; ++i) s += std::conj(v[i - j]) * W(i, c);
-      s *= b;
-      for (int i = j; i < m; ++i) W(i, c) -= v[i - j] * s;
+    double b = 0.0;
+    if (nrm > 0.0) {
+      const cd x0 = W(j, j);
+      const cd phase = (std::abs(x0) > 0.0) ? x0 / std::abs(x0) : cd(1.0, 0.0);
+      const cd alpha = -phase * nrm;     // reflect x onto alpha e_1
+      v[0] = x0 - alpha;
+      for (int i = j + 1; i < m; ++i) v[i - j] = W(i, j);
+      double vn2 = 0.0;
+      for (auto& e : v) vn2 += std::norm(e);
+      if (vn2 > 0.0) {
+        b = 2.0 / vn2;
+        // W[j:, j:] <- (I - b v v^H) W[j:, j:]
+        std::fill(acc.begin() + j, acc.end(), cd(0.0, 0.0));
+        for (int i = j; i < m; ++i) {
+          const cd vi = std::conj(v[i - j]);
+          const cd* row = &W.a[(size_t)i * n];
+          for (int c = j; c < n; ++c) acc[c] += vi * row[c];
+        }
+        for (int c = j; c < n; ++c) acc[c] *= b;
+        for (int i = j; i < m; ++i) {
+          const cd vi = v[i - j];
+          cd* row = &W.a[(size_t)i * n];
+          for (int c = j; c < n; ++c) row[c] -= vi * acc[c];
+        }
+      }
     }
-    vs[j] = v;
-    beta[j] = b;
+    vs.push_back(std::move(v));
+    beta.push_back(b);
+    k = j + 1;
   }
+  if (k == 0) k = 1;
+  while ((int)vs.size() < k) { vs.emplace_back(m, cd(0.0, 0.0)); beta.push_back(0.0); }
   R = ZMat(k, n);
   for (int i = 0; i < k; ++i)
-    for (int j = i; j < n; ++j) R(i, j) = W(i, j);
+    for (int c = i; c < n; ++c) R(i, perm[c]) = W(i, c);
   // Q = H_0 H_1 ... H_{k-1} applied to the first k columns of I
   Q = ZMat(m, k);
   for (int i = 0; i < k; ++i) Q(i, i) = 1.0;
+  std::vector<cd> qa(k);
   for (int j = k - 1; j >= 0; --j) {
     const auto& v = vs[j];
-    const double b = beta[j].real();
+    const double b = beta[j];
     if (b == 0.0) continue;
-    for (int c = 0; c < k; ++c) {
-      cd s(0.0, 0.0);
-      for (int i = j; i < m; ++i) s += std::conj(v[i - j]) * Q(i, c);
-      s *= b;
-      for (int i = j; i < m; ++i) Q(i, c) -= v[i - j] * s;
+    std::fill(qa.begin(), qa.end(), cd(0.0, 0.0));
+    for (int i = j; i < m; ++i) {
+      const cd vi = std::conj(v[i - j]);
+      const cd* row = &Q.a[(size_t)i * k];
+      for (int c = 0; c < k; ++c) qa[c] += vi * row[c];
+    }
+    for (int c = 0; c < k; ++c) qa[c] *= b;
+    for (int i = j; i < m; ++i) {
+      const cd vi = v[i - j];
+      cd* row = &Q.a[(size_t)i * k];
+      for (int c = 0; c < k; ++c) row[c] -= vi * qa[c];
     }
   }
+}
+
+void householder_qr(const ZMat& A, ZMat& Q, ZMat& R) { qr_core(A, false, 0.0, Q, R); }
+
+void qr_truncated(const ZMat& A, double rel, ZMat& Q, ZMat& R) {
+  double tot = 0.0;
+  for (const cd& x : A.a) tot += std::norm(x);
+  qr_core(A, true, rel * rel * tot, Q, R);
 }
 
 // One-sided Jacobi on the columns of the square matrix W; V accumulates.

@@ -25,6 +25,11 @@ ZMat matmul(const ZMat& x, const ZMat& y);
 // columns) and R k x n upper trapezoidal, k = min(m, n).
 void householder_qr(const ZMat& A, ZMat& Q, ZMat& R);
 
+// Column-pivoted Householder QR stopped once the columns left hold at most
+// rel^2 of ||A||_F^2: A ~ Q R with Q m x k orthonormal, R k x n (original
+// column order), ||A - Q R||_F <= rel ||A||_F, k >= 1.
+void qr_truncated(const ZMat& A, double rel, ZMat& Q, ZMat& R);
+
 // Economy SVD A = U diag(S) Vh, k = min(m, n), S descending.  QR reduction
 // to a square triangle followed by one-sided (Hestenes) Jacobi with the
 // relative off-diagonal criterion |w_p^H w_q| <= eps ||w_p|| ||w_q||.

@@ -83,6 +83,10 @@ Mpo mpo_mul(const Mpo& a, const Mpo& b) {
   return m;
 }
 
+// Left-to-right sweep of QR factorisations that drop only directions at the
+// rounding floor (1e-16 of the site's norm: products of MPOs carry bonds far
+// above their numerical rank), then the right-to-left truncated SVD sweep at
+// `tol` (relative Frobenius rule).
 Mpo mpo_compress(const Mpo& a, double tol) {
   Mpo w = a;
   const int n = (int)w.size();
@@ -91,7 +95,7 @@ Mpo mpo_compress(const Mpo& a, double tol) {
     ZMat M(l * 4, r);
     M.a = w[k].w;
     ZMat Q, R;
-    householder_qr(M, Q, R);
+    qr_truncated(M, 1e-16, Q, R);
     const int kk = Q.c;
     Site s(l, kk);
     s.w = Q.a;

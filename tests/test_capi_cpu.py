@@ -23,7 +23,7 @@ def _lib_or_skip():
 
 def _declared_symbols():
     names = set()
-    for h in ("lindblad.h", "lindblad_kernels.h"):
+    for h in ("lindblad.h", "lindblad_kernels.h", "lindblad_serve.h"):
         text = open(os.path.join(ROOT, "include", h)).read()
         names |= set(re.findall(r"^\s*(?:lb_status|void|const char\*)\s+(lindblad_\w+)\s*\(", text, re.M))
     return sorted(names)
@@ -122,3 +122,43 @@ def test_argument_errors():
     assert e.value.code == LB_ERR_UNSTABLE
     s = api.solver_from_model(wl.model_two_photon_cat(R=8, dt=5e-5), state="none")
     s.close()
+
+
+def test_footprint_host_only():
+    """The device footprint is computed on the host from the caps and the
+    Kraus MPO; it grows with chi and is smaller in the FP32 form."""
+    _lib_or_skip()
+    from paper_2605_27515_amd import api
+    m = wl.model_cat_buffer(Ra=5, Rb=5, alpha2=4.0, dt=2.5e-5)
+    s0 = api.Solver(m.bits, 16, 4, site_order=m.site_order())
+    with pytest.raises(api.LindbladError):
+        s0.footprint()                      # no generator yet
+    s0.close()
+    f = {}
+    for prec in ("fp64", "fp32"):
+        for chi in (16, 64):
+            s = api.solver_from_model(m, precision=prec, chi=chi, chi_mu=8, state="none")
+            f[prec, chi] = s.footprint()
+            s.release()                     # nothing on the device: a no-op
+            s.close()
+    assert f["fp64", 16] < f["fp64", 64]
+    assert f["fp32", 64] < f["fp64", 64]
+    assert 1 << 20 < f["fp64", 16] < 1 << 30
+
+
+def test_server_argument_errors_host_only():
+    _lib_or_skip()
+    from paper_2605_27515_amd import api
+    with pytest.raises(api.LindbladError):
+        api.Server(n_slots=0)
+    sv = api.Server(n_slots=2, hbm_budget=1 << 30)
+    m = wl.model_coherent_loss()
+    s = api.Solver(m.bits, 16, 4, site_order=m.site_order())
+    with pytest.raises(api.LindbladError):
+        sv.submit(s, m.init, 10)            # generator not set
+    sv.run()                                # nothing queued: no device work
+    assert sv.stats()["completed"] == 0
+    with pytest.raises(api.LindbladError):
+        sv.result(0)
+    s.close()
+    sv.close()

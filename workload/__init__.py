@@ -137,7 +137,7 @@ def model_two_photon_cat(R: int = 8, alpha2: float = 8.0, kappa2: float = 1.0,
 def model_cat_buffer(Ra: int = 8, Rb: int = 8, alpha2: float = 8.0, g2: float = 1.0,
                      kappa_b: float = 10.0, kappa_a: float = 1e-3, dt: float = 2.5e-5,
                      steps: int = 200, chi: int = 128, chi_mu: int = 16) -> Model:
-    """Cat mode a + lossy buffer b (paper Sec. 5, Eq. cb):
+    """Cat mode a + lossy buffer b (paper Sec. 6.1, Eq. cb):
     H = g2 (a^dag^2 b + a^2 b^dag) + eps_d (b + b^dag), eps_d = -alpha^2 g2,
     L_b = sqrt(kappa_b) b, L_a = sqrt(kappa_a) a; vacuum x vacuum start."""
     eps_d = -alpha2 * g2
@@ -159,7 +159,7 @@ def model_transmon_resonator(Rt: int = 10, Rr: int = 12, ej_over_ec: float = 50.
                              dt: float = 1.5e-7, steps: int = 200, chi: int = 256,
                              chi_mu: int = 32, init_t: np.ndarray | None = None) -> Model:
     """Transmon in the charge basis (offset binary, n = q - 2^(Rt-1)) coupled to a
-    resonator (paper Sec. 6, Eq. transmon_cavity with the readout drive written
+    resonator (paper Sec. 7.1, Eq. transmon_cavity with the readout drive written
     as eps cos(w_d t)(a + a^dag)); E_C = 1 units.
 
     H0 = 4 (n - ng)^2 - E_J cos(phi) + w_r a^dag a + i g n (a^dag - a)
@@ -186,6 +186,44 @@ def model_transmon_resonator(Rt: int = 10, Rr: int = 12, ej_over_ec: float = 50.
                  drive=[(1.0, omega_d, 0.0)], jumps=jumps,
                  init=[init_t, vacuum(1 << Rr)], dt=dt, steps=steps, chi=chi,
                  chi_mu=chi_mu)
+
+
+def transmon_ground_state(Rt: int, ej_over_ec: float = 50.0, ng: float = 0.25) -> np.ndarray:
+    """Ground state of H_t = 4 (n - ng)^2 - (E_J/2)(T_1 + T_-1) on the charge
+    states n = q - 2^(Rt-1) (E_C = 1), by a dense symmetric eigensolve."""
+    N = 1 << Rt
+    n = np.arange(N) - (N >> 1)
+    H = np.diag(4.0 * (n - ng) ** 2) - 0.5 * ej_over_ec * (np.eye(N, k=1) + np.eye(N, k=-1))
+    w, v = np.linalg.eigh(H)
+    g = v[:, 0].astype(complex)
+    return g * np.sign(g[np.argmax(np.abs(g))].real)
+
+
+# stable time steps of the three families (explicit-scheme bound, E_C = 1 units)
+SERVING_DT = {"two-photon-cat": 5e-5, "cat-buffer": 2.5e-5, "transmon-resonator": 1.5e-7}
+
+
+def model_from_request(req: dict) -> Model:
+    """The model of one serving request (see serving_requests)."""
+    fam = req["family"]
+    if fam == "two-photon-cat":
+        return model_two_photon_cat(R=req["R"], alpha2=req["alpha2"], dt=SERVING_DT[fam],
+                                    steps=req["steps"], chi=req["chi"], chi_mu=req["chi_mu"])
+    if fam == "cat-buffer":
+        return model_cat_buffer(Ra=req["R"], Rb=req["R"], alpha2=req["alpha2"], dt=SERVING_DT[fam],
+                                steps=req["steps"], chi=req["chi"], chi_mu=req["chi_mu"])
+    if fam == "transmon-resonator":
+        return model_transmon_resonator(Rt=req["Rt"], Rr=req["Rr"], eps=req["eps"], ng=req["ng"],
+                                        dt=SERVING_DT[fam], steps=req["steps"], chi=req["chi"],
+                                        chi_mu=req["chi_mu"],
+                                        init_t=transmon_ground_state(req["Rt"], 50.0, req["ng"]))
+    raise ValueError(f"unknown family {fam}")
+
+
+def poisson_arrivals(n: int, rate: float, seed: int = SEED) -> np.ndarray:
+    """Arrival times (seconds) of a Poisson stream of n requests at `rate` per second."""
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    return np.cumsum(rng.exponential(1.0 / rate, n))
 
 
 # --------------------------------------------------------------------------
