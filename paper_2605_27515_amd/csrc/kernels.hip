@@ -1182,31 +1182,39 @@ __global__ __launch_bounds__(256) void ormtr_kernel(const double* Vt, const doub
 // clean-up of the caller removes).  Inside a group every member after the
 // first is projected out of the span of the earlier members by classical
 // Gram-Schmidt applied twice.  A member that loses more than half of its norm
-// in the projection (nearly dependent vectors, as for eigenvalues at the
-// rounding floor) would carry the amplified contamination of other groups,
-// so it is first refined by one more solve with its own shifted
-// factorisation (left in `scr` by stein_kernel), which damps every direction
-// outside the group, and projected again; if that collapses too it restarts
-// from fresh start vectors.  One workgroup; w holds all n eigenvalues
-// (descending), Z the k vectors (ld ldz).
+// in the projection (nearly dependent vectors) would carry amplified
+// contamination of other groups, so it is first refined by one more solve
+// with its own shifted factorisation (left in `scr` by stein_kernel), which
+// damps every direction outside the group, and projected again; if that
+// collapses too it restarts from fresh start vectors.
+// Eigenvalues within 8 n eps ||T|| of zero are not resolved by the reduction
+// at all: any orthonormal basis of what the resolved vectors leave is as good
+// as another, and inverse iteration can return, for them, a vector along a
+// resolved eigenvector.  Such a member is projected out of the span of ALL
+// earlier vectors and replaced by a fresh start vector when that leaves less
+// than 1e-3 of it.  One workgroup; w holds all n eigenvalues (descending), Z
+// the k vectors (ld ldz).
 constexpr int SG_NT = 256;
 
-__device__ void sg_project(double* Z, int ldz, int n, int c0, int c1, double* zl, double* dots) {
-  const int nprev = c1 - c0;
+// z -= Z[:, cols] (Z[:, cols]^T z), twice; cols[p] = c0 + p when cols == nullptr.
+__device__ void sg_project(const double* Z, int ldz, int n, int c0, int nprev, const int* cols, double* zl,
+                           double* dots) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int pass = 0; pass < 2; ++pass) {
     for (int p0 = 0; p0 < nprev; p0 += SG_NT / 64) {
       const int p = p0 + wave;
       double acc = 0.0;
-      if (p < nprev)
-        for (int r = lane; r < n; r += 64) acc += Z[(long long)r * ldz + c0 + p] * zl[r];
+      if (p < nprev) {
+        const int c = cols ? cols[p] : c0 + p;
+        for (int r = lane; r < n; r += 64) acc += Z[(long long)r * ldz + c] * zl[r];
+      }
       acc = wave_sum(acc);
       if (lane == 0 && p < nprev) dots[p] = acc;
     }
     __syncthreads();
     for (int r = threadIdx.x; r < n; r += SG_NT) {
       double v = zl[r];
-      for (int p = 0; p < nprev; ++p) v -= dots[p] * Z[(long long)r * ldz + c0 + p];
+      for (int p = 0; p < nprev; ++p) v -= dots[p] * Z[(long long)r * ldz + (cols ? cols[p] : c0 + p)];
       zl[r] = v;
     }
     __syncthreads();
@@ -1270,37 +1278,78 @@ __global__ __launch_bounds__(SG_NT) void stein_groups_kernel(int n, const double
                                                              double* Z, int ldz, const double* scr, int kpad) {
   __shared__ double zl[512], dots[512], lu[5 * 512];
   __shared__ double red[32];
+  __shared__ int cols[512];
   __shared__ unsigned char link[512];   // link[j]: w[j] belongs to the group of w[j-1]
   const double tn = fmax(fmax(fabs(w[0]), fabs(w[n - 1])), 1e-300);
   const double gap = theta * tn;
+  const double floor_abs = 8.0 * n * 2.2e-16 * tn;
   for (int j = threadIdx.x; j < k; j += SG_NT) link[j] = (j > 0 && w[j - 1] - w[j] <= gap) ? 1 : 0;
   __syncthreads();
+  // 1. resolved members of groups, against the earlier members of their group
   int start = 0;
-  while (start < k) {
-    int end = start + 1;
-    while (end < k && link[end]) ++end;
-    for (int j = start + 1; j < end; ++j) {
-      for (int r = threadIdx.x; r < n; r += SG_NT) zl[r] = Z[(long long)r * ldz + j];
-      __syncthreads();
-      bool ok = false;
-      for (int attempt = 0; attempt < 4 && !ok; ++attempt) {
-        if (attempt >= 2) {
-          // restart from a fresh start vector, pulled towards the group by two solves
-          for (int r = threadIdx.x; r < n; r += SG_NT) zl[r] = hash_unit((unsigned)r, (unsigned)(j + 7919 * attempt));
-          __syncthreads();
-          sg_solve(zl, n, scr, kpad, j, lu, red);
-        }
-        if (attempt >= 1) sg_solve(zl, n, scr, kpad, j, lu, red);
-        const double n0 = sg_norm(zl, n, red);
-        sg_project(Z, ldz, n, start, j, zl, dots);
-        const double n1 = sg_norm(zl, n, red);
-        ok = n1 > 0.5 * n0 && n1 > 0.0;
-        if (n1 > 0.0) sg_scale(zl, n, 1.0 / n1);
+  for (int j = 1; j < k; ++j) {
+    if (!link[j]) start = j;
+    if (start == j || fabs(w[j]) <= floor_abs) continue;
+    int s0 = start;
+    while (s0 < j && fabs(w[s0]) <= floor_abs) ++s0;   // (not reached for a PSD matrix)
+    for (int r = threadIdx.x; r < n; r += SG_NT) zl[r] = Z[(long long)r * ldz + j];
+    __syncthreads();
+    bool ok = false;
+    for (int attempt = 0; attempt < 4 && !ok; ++attempt) {
+      if (attempt >= 2) {
+        // restart from a fresh start vector, pulled towards the group by two solves
+        for (int r = threadIdx.x; r < n; r += SG_NT) zl[r] = hash_unit((unsigned)r, (unsigned)(j + 7919 * attempt));
+        __syncthreads();
+        sg_solve(zl, n, scr, kpad, j, lu, red);
       }
-      for (int r = threadIdx.x; r < n; r += SG_NT) Z[(long long)r * ldz + j] = zl[r];
+      if (attempt >= 1) sg_solve(zl, n, scr, kpad, j, lu, red);
+      const double n0 = sg_norm(zl, n, red);
+      int np = 0;
+      if (threadIdx.x == 0)
+        for (int c = s0; c < j; ++c)
+          if (fabs(w[c]) > floor_abs) cols[np++] = c;
       __syncthreads();
+      np = 0;
+      for (int c = s0; c < j; ++c) np += fabs(w[c]) > floor_abs ? 1 : 0;
+      sg_project(Z, ldz, n, 0, np, cols, zl, dots);
+      const double n1 = sg_norm(zl, n, red);
+      ok = n1 > 0.5 * n0 && n1 > 0.0;
+      if (n1 > 0.0) sg_scale(zl, n, 1.0 / n1);
     }
-    start = end;
+    for (int r = threadIdx.x; r < n; r += SG_NT) Z[(long long)r * ldz + j] = zl[r];
+    __syncthreads();
+  }
+  // 2. unresolved eigenvalues: against every resolved vector and the earlier
+  //    unresolved ones
+  int nres = 0;
+  for (int c = 0; c < k; ++c) nres += fabs(w[c]) > floor_abs ? 1 : 0;
+  if (threadIdx.x == 0) {
+    int q = 0;
+    for (int c = 0; c < k; ++c)
+      if (fabs(w[c]) > floor_abs) cols[q++] = c;
+  }
+  __syncthreads();
+  int np = nres;
+  for (int j = 0; j < k; ++j) {
+    if (fabs(w[j]) > floor_abs) continue;
+    for (int r = threadIdx.x; r < n; r += SG_NT) zl[r] = Z[(long long)r * ldz + j];
+    __syncthreads();
+    bool ok = false;
+    for (int attempt = 0; attempt < 4 && !ok; ++attempt) {
+      if (attempt > 0) {
+        for (int r = threadIdx.x; r < n; r += SG_NT) zl[r] = hash_unit((unsigned)r, (unsigned)(j + 7919 * attempt));
+        __syncthreads();
+      }
+      const double n0 = sg_norm(zl, n, red);
+      sg_project(Z, ldz, n, 0, np, cols, zl, dots);
+      const double n1 = sg_norm(zl, n, red);
+      ok = n1 > 1e-3 * n0 && n1 > 0.0;
+      if (n1 > 0.0) sg_scale(zl, n, 1.0 / n1);
+    }
+    for (int r = threadIdx.x; r < n; r += SG_NT) Z[(long long)r * ldz + j] = zl[r];
+    if (threadIdx.x == 0) cols[np] = j;
+    __syncthreads();
+    ++np;
   }
 }
 

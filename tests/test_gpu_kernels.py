@@ -75,9 +75,10 @@ def test_heev_tridiag_graded_and_clustered(n):
     assert np.abs(G @ U - U * w).max() <= 1e-12
 
 
-@pytest.mark.parametrize("n,m", [(12, 20), (40, 30), (128, 300), (256, 200)])
+@pytest.mark.parametrize("n,m", [(12, 20), (16, 135), (40, 30), (128, 300), (256, 200)])
 @pytest.mark.parametrize("seed", range(4))
-def test_heev_tridiag_rounding_floor_tail(n, m, seed):
+@pytest.mark.parametrize("gram", ["numpy", "gpu"])
+def test_heev_tridiag_rounding_floor_tail(n, m, seed, gram):
     """Gram of a graded matrix whose smaller singular values lie at and below
     sqrt(eps) of the largest, so the tail of the Gram spectrum sits at the
     rounding floor, plus a non-Hermitian perturbation of that size (as a Gram
@@ -88,8 +89,12 @@ def test_heev_tridiag_rounding_floor_tail(n, m, seed):
     r = min(n, m)
     sv = np.concatenate([[np.sqrt(8.0)], 10.0 ** (-np.linspace(2.5, 18.0, r - 1))])
     A = wl.random_matrix(n, m, seed=100 + seed, spectrum=sv)
-    G = A @ A.conj().T
-    G = G + 4e-17 * np.abs(G).max() * wl.random_matrix(n, n, seed=200 + seed)
+    if gram == "numpy":
+        G = A @ A.conj().T
+        G = G + 4e-17 * np.abs(G).max() * wl.random_matrix(n, n, seed=200 + seed)
+    else:
+        # the Gram as the solver forms it (FP64 MFMA GEMM, its own rounding)
+        G = api.kernel_zgemm(A, A, False, True, "fp64", 1 + seed % 2)
     w, U, _ = api.kernel_heev(G, "tridiag")
     assert np.abs(U.conj().T @ U - np.eye(n)).max() < 1e-13
     Gh = 0.5 * (G + G.conj().T)

@@ -161,3 +161,29 @@ def test_batch_equals_alone():
         b = s.get_state_mps()
         _assert_same_rho(a, b, m, 1e-13)
         s.close()
+
+
+@pytest.mark.parametrize("k", [7, 50, 54, 63])
+def test_step_serving_requests(k):
+    """Requests of the seeded serving stream (100 steps from vacuum / the
+    transmon ground state, N up to 256) whose Gram matrices carry isolated
+    resolved eigenvalues above a tail at the rounding floor: both forms
+    against the oracle, FP64 at the tol = 1e-8 bound, FP32 observables at
+    1e-5.  FP32 density-matrix elements are held to 1e-4 of max|rho|: the
+    complex64 contractions round at 6e-8 per step and this accumulates over
+    the 100 steps (5e-6 measured on the driven transmon)."""
+    api = _api()
+    r = wl.serving_requests(512)[k]
+    m = wl.model_from_request(r)
+    print(f"serving request {k}: {r}", flush=True)
+    Xo, taus = _oracle_run(m, r["steps"], m.chi, m.chi_mu, m.tol)
+    so = m.site_order()
+    for precision, rtol in (("fp64", 1e-7), ("fp32", 1e-5)):
+        s = api.solver_from_model(m, precision=precision)
+        s.step(r["steps"])
+        for terms in _observables(m):
+            vo = mps.expect(Xo, tt.operator_mpo(terms, m.bits, so))
+            vg = s.observe(s.mpo(terms))
+            assert abs(vg - vo) <= rtol * max(1.0, abs(vo)), (precision, terms, vg, vo)
+        _assert_same_rho(Xo, s.get_state_mps(), m, rtol if precision == "fp64" else 1e-4)
+        s.close()
