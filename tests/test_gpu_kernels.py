@@ -42,7 +42,7 @@ def test_zgemm_fp32(shape):
 
 
 @pytest.mark.parametrize("method", ["jacobi", "tridiag"])
-@pytest.mark.parametrize("n", [1, 2, 7, 16, 33, 64, 100, 128, 256])
+@pytest.mark.parametrize("n", [1, 2, 7, 16, 33, 64, 100, 128, 256, 512])
 def test_heev_parity(n, method):
     api = _api()
     if method == "jacobi" and n > 128:
@@ -75,7 +75,7 @@ def test_heev_tridiag_graded_and_clustered(n):
     assert np.abs(G @ U - U * w).max() <= 1e-12
 
 
-@pytest.mark.parametrize("n,m", [(12, 20), (16, 135), (40, 30), (128, 300), (256, 200)])
+@pytest.mark.parametrize("n,m", [(12, 20), (16, 135), (40, 30), (128, 300), (256, 200), (512, 600)])
 @pytest.mark.parametrize("seed", range(4))
 @pytest.mark.parametrize("gram", ["numpy", "gpu"])
 def test_heev_tridiag_rounding_floor_tail(n, m, seed, gram):

@@ -187,3 +187,57 @@ def test_step_serving_requests(k):
             assert abs(vg - vo) <= rtol * max(1.0, abs(vo)), (precision, terms, vg, vo)
         _assert_same_rho(Xo, s.get_state_mps(), m, rtol if precision == "fp64" else 1e-4)
         s.close()
+
+
+@pytest.mark.parametrize("precision,rtol", [("fp64", 1e-7), ("fp32", 1e-5)])
+def test_bench_workload_full_size(precision, rtol):
+    """The timed workload itself: cat + buffer at 2 x 256 levels, chi = 128,
+    chi_mu = 16, on the seeded saturated state, one step in the launch
+    configuration the benchmark times, against the oracle.  Observables to
+    rtol, rho through the overlap identity, bonds equal."""
+    api = _api()
+    m = wl.model_cat_buffer(Ra=8, Rb=8, alpha2=8.0, dt=2.5e-5)
+    L, chi, chi_mu = 16, 128, 16
+    raw = wl.synthetic_mps(L, chi_mu, chi)
+    so = m.site_order()
+    K = tt.KrausMPO(m, m.dt)
+    Xo, _ = mps.right_canonicalize(raw, tol=1e-14)
+    Xo, info = mps.k2_step(Xo, K.at(0.0), m.tol, chi, chi_mu)
+    s = api.solver_from_model(m, precision=precision, chi=chi, chi_mu=chi_mu, state="none")
+    s.set_state_mps(raw)
+    s.step(1)
+    Xg = s.get_state_mps()
+    d = s.diagnostics()
+    assert d["bonds"] == info.bonds and d["chi_mu"] == info.chi_mu
+    assert abs(d["tau"] - info.tau) <= rtol
+    for terms in _observables(m) + [[(1.0, {0: ("ADAG_A", 2, 2)})]]:
+        vo = mps.expect(Xo, tt.operator_mpo(terms, m.bits, so))
+        vg = s.observe(s.mpo(terms))
+        assert abs(vg - vo) <= rtol * max(1.0, abs(vo)), (terms, vg, vo)
+    d2 = mps.rho_distance2(Xo, Xg)
+    norm2 = np.sum(np.abs(mps.gram(Xo)) ** 2)
+    assert d2 <= max(100 * rtol ** 2, 1e-14) * norm2, d2
+    s.close()
+
+
+def test_transmon_full_chain_fp32():
+    """Driven transmon at its full 10 + 12 = 22 quantics sites (charge states
+    -512..511, resonator 4096 levels), FP32 form, on a seeded state saturated
+    at chi = 64, chi_mu = 32: two steps against the oracle."""
+    api = _api()
+    m = wl.model_transmon_resonator()
+    L, chi, chi_mu = 22, 64, 32
+    raw = wl.synthetic_mps(L, chi_mu, chi)
+    Xo, taus = _oracle_run(m, 2, chi, chi_mu, m.tol, init=raw)
+    s = api.solver_from_model(m, precision="fp32", chi=chi, chi_mu=chi_mu, state="none")
+    s.set_state_mps(raw)
+    s.step(2)
+    so = m.site_order()
+    for terms in _observables(m):
+        vo = mps.expect(Xo, tt.operator_mpo(terms, m.bits, so))
+        vg = s.observe(s.mpo(terms))
+        assert abs(vg - vo) <= 1e-5 * max(1.0, abs(vo)), (terms, vg, vo)
+    tr, pur = s.trace_purity()
+    assert abs(tr - 1.0) < 1e-12 and 1.0 / chi_mu - 1e-12 <= pur <= 1.0 + 1e-12
+    assert abs(s.diagnostics()["tau"] - taus[-1]) <= 1e-5
+    s.close()
