@@ -1026,6 +1026,7 @@ __global__ __launch_bounds__(256) void stebz_kernel(const double* d, const doubl
   const double pivmin = 1e-290 * fmax(1.0, emax);
   const int target = n - 1 - j;   // eigenvalue mu_target (ascending index)
   double lo = bnd[0], hi = bnd[1];
+  const double tspan = fmax(fabs(lo), fabs(hi));
   for (int it = 0; it < 40; ++it) {
     const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
     const int c = sturm_count(sd, se2, n, x, pivmin);
@@ -1033,7 +1034,8 @@ __global__ __launch_bounds__(256) void stebz_kernel(const double* d, const doubl
     const int first = mask ? __ffsll((long long)mask) - 1 : 64;
     const double nlo = (first == 0) ? lo : lo + (hi - lo) * (double)first / 65.0;
     const double nhi = (first == 64) ? hi : lo + (hi - lo) * (double)(first + 1) / 65.0;
-    const bool done = (nhi - nlo) <= 2.0 * 2.2e-16 * fmax(fabs(nlo), fabs(nhi)) + 1e-300 ||
+    // the reduction fixes eigenvalues only to eps ||T|| absolute, so bisect no further
+    const bool done = (nhi - nlo) <= 2.0 * 2.2e-16 * fmax(fmax(fabs(nlo), fabs(nhi)), tspan) + 1e-300 ||
                       (nlo == lo && nhi == hi);
     lo = nlo; hi = nhi;
     if (done) break;
@@ -1046,6 +1048,10 @@ __device__ inline double hash_unit(unsigned int a, unsigned int b) {
   h ^= h >> 15; h *= 0x2C1B3C6Du; h ^= h >> 12; h *= 0x297A2D39u; h ^= h >> 15;
   return ((double)(h & 0xFFFFFF) / 16777216.0) * 2.0 - 1.0;
 }
+
+// Solves of inverse iteration after the first (the first starts from a hashed
+// vector and amplifies the wanted direction by ~1 / (eps ||T||)).
+constexpr int STEIN_EXTRA = 0;
 
 // Z[i*ldz + j] (j < k): unit eigenvector of the tridiagonal for w[j].
 // scratch: 6 * n * kpad doubles, kpad = k rounded up to 64.
@@ -1067,42 +1073,50 @@ __global__ __launch_bounds__(64) void stein_kernel(const double* d, const double
   double* PV = scr + 4LL * n * kpad;
   double* ZZ = scr + 5LL * n * kpad;
 #define IX(i) ((long long)(i) * kpad + j)
-  // pivoted LU of T - lam I
+  // pivoted LU of T - lam I, with the forward elimination of the start vector
+  // folded in (its rows are eliminated in the same order); pivots below
+  // eps ||T|| are replaced by +-eps ||T|| for the back substitution
   double a = sd[0] - lam, b = (n > 1) ? se[0] : 0.0;
+  double cur = hash_unit(0u, (unsigned)j);
   for (int i = 0; i < n - 1; ++i) {
     const double c = se[i];
     const double an = sd[i + 1] - lam;
     const double bn = (i + 1 < n - 1) ? se[i + 1] : 0.0;
+    double nxt = hash_unit((unsigned)(i + 1), (unsigned)j);
     if (fabs(a) >= fabs(c)) {
       const double aa = (a == 0.0) ? tiny : a;
       const double mult = c / aa;
-      U0[IX(i)] = aa; U1[IX(i)] = b; U2[IX(i)] = 0.0; LM[IX(i)] = mult; PV[IX(i)] = 0.0;
+      U0[IX(i)] = (fabs(aa) < tiny) ? copysign(tiny, aa) : aa;
+      U1[IX(i)] = b; U2[IX(i)] = 0.0; LM[IX(i)] = mult; PV[IX(i)] = 0.0;
       a = an - mult * b;
       b = bn;
     } else {
       const double mult = a / c;
-      U0[IX(i)] = c; U1[IX(i)] = an; U2[IX(i)] = bn; LM[IX(i)] = mult; PV[IX(i)] = 1.0;
+      U0[IX(i)] = (fabs(c) < tiny) ? copysign(tiny, c) : c;
+      U1[IX(i)] = an; U2[IX(i)] = bn; LM[IX(i)] = mult; PV[IX(i)] = 1.0;
       a = b - mult * an;
       b = -mult * bn;
+      const double t = cur; cur = nxt; nxt = t;
     }
+    nxt -= LM[IX(i)] * cur;
+    ZZ[IX(i)] = cur;
+    cur = nxt;
   }
-  U0[IX(n - 1)] = a;
-  for (int i = 0; i < n; ++i) {
-    double u = U0[IX(i)];
-    if (fabs(u) < tiny) U0[IX(i)] = copysign(tiny, u == 0.0 ? 1.0 : u);
-    ZZ[IX(i)] = hash_unit((unsigned)i, (unsigned)j);
-  }
-  for (int iter = 0; iter < 2; ++iter) {
-    // forward: apply the row exchanges and multipliers
-    double cur = ZZ[IX(0)];
-    for (int i = 0; i < n - 1; ++i) {
-      double nxt = ZZ[IX(i + 1)];
-      if (PV[IX(i)] != 0.0) { const double t = cur; cur = nxt; nxt = t; }
-      nxt -= LM[IX(i)] * cur;
-      ZZ[IX(i)] = cur;
-      cur = nxt;
+  U0[IX(n - 1)] = (fabs(a) < tiny) ? copysign(tiny, a == 0.0 ? 1.0 : a) : a;
+  ZZ[IX(n - 1)] = cur;
+  for (int iter = 0; iter <= STEIN_EXTRA; ++iter) {
+    if (iter > 0) {
+      // forward: the row exchanges and multipliers again
+      double cf = ZZ[IX(0)];
+      for (int i = 0; i < n - 1; ++i) {
+        double nf = ZZ[IX(i + 1)];
+        if (PV[IX(i)] != 0.0) { const double t = cf; cf = nf; nf = t; }
+        nf -= LM[IX(i)] * cf;
+        ZZ[IX(i)] = cf;
+        cf = nf;
+      }
+      ZZ[IX(n - 1)] = cf;
     }
-    ZZ[IX(n - 1)] = cur;
     // backward substitution with the upper factor (bandwidth 3)
     double z1 = 0.0, z2 = 0.0, nrm = 0.0, big = 0.0;
     for (int i = n - 1; i >= 0; --i) {
@@ -1113,10 +1127,10 @@ __global__ __launch_bounds__(64) void stein_kernel(const double* d, const double
     }
     const double inv = (big > 0.0) ? 1.0 / big : 1.0;
     for (int i = 0; i < n; ++i) { const double z = ZZ[IX(i)] * inv; nrm += z * z; ZZ[IX(i)] = z; }
-    const double s = 1.0 / sqrt(fmax(nrm, 1e-300));
-    for (int i = 0; i < n; ++i) ZZ[IX(i)] *= s;
-    // deterministic sign: largest-magnitude component positive
+    const double sc = 1.0 / sqrt(fmax(nrm, 1e-300));
+    for (int i = 0; i < n; ++i) ZZ[IX(i)] *= sc;
   }
+  // deterministic sign: largest-magnitude component positive
   double big = 0.0, sg = 1.0;
   for (int i = 0; i < n; ++i) { const double z = ZZ[IX(i)]; if (fabs(z) > big) { big = fabs(z); sg = z < 0 ? -1.0 : 1.0; } }
   for (int i = 0; i < n; ++i) Z[(long long)i * ldz + j] = sg * ZZ[IX(i)];
