@@ -400,9 +400,11 @@ void eig_jacobi(lb_solver* s, double* G, int n, double* lam) {
 }
 
 // Tridiagonal route (absolute accuracy): G destroyed, all eigenvalues in
-// lam, the eigenvectors of the kvec largest in U (ld n), made orthonormal to
-// rounding by two Newton-Schulz polar steps U <- U (3I - U^H U)/2 (inverse
-// iteration leaves eps ||G|| / gap of mutual overlap between vectors).
+// lam, the eigenvectors of the kvec largest in U (ld n), made orthonormal by
+// Newton-Schulz polar steps U <- U (3I - U^H U)/2.  Inverse iteration with the
+// grouped orthogonalisation leaves at most ~1e-5 of mutual overlap; one step
+// takes that to ~1e-10, below the FP32 form's rounding of the contractions;
+// the FP64 form (whose second pass needs U0 unitary to rounding) takes two.
 void eig_trid(lb_solver* s, double* G, int n, double* lam, double* U, int kvec) {
   kvec = std::min(kvec, n);
   const double N = n;
@@ -429,8 +431,8 @@ void eig_trid(lb_solver* s, double* G, int n, double* lam, double* U, int kvec) 
     HIPCHK(lbk::trid_backtransform(n, tw, kvec, U, n, s->stream));
   }
   {
-    Timed tm(s, PC_SVDGEMM, 2.0 * (8.0 * kvec * kvec * N * 2), 2.0 * 16.0 * (2.0 * N * kvec + kvec * kvec));
-    HIPCHK(lbk::orthonormalize_columns(U, n, n, kvec, s->scratch.d(), s->U2.d(), 2, s->stream));
+    Timed tm(s, PC_SVDGEMM, passes(s) * (8.0 * kvec * kvec * N * 2), passes(s) * 16.0 * (2.0 * N * kvec + kvec * kvec));
+    HIPCHK(lbk::orthonormalize_columns(U, n, n, kvec, s->scratch.d(), s->U2.d(), passes(s), s->stream));
   }
 }
 

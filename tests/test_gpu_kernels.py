@@ -15,7 +15,7 @@ def _api():
 
 
 @pytest.mark.parametrize("shape", [(1, 1, 1), (17, 33, 5), (64, 64, 16), (100, 70, 129), (256, 96, 1000),
-                                   (3, 300, 64)])
+                                   (3, 300, 64), (520, 530, 40)])
 @pytest.mark.parametrize("adj", [(False, False), (True, False), (False, True), (True, True)])
 def test_zgemm_fp64(shape, adj):
     api = _api()
@@ -29,7 +29,7 @@ def test_zgemm_fp64(shape, adj):
         assert np.abs(C - ref).max() <= 1e-15 * 4 * K * np.abs(A).max() * np.abs(B).max()
 
 
-@pytest.mark.parametrize("shape", [(64, 64, 64), (130, 90, 257)])
+@pytest.mark.parametrize("shape", [(64, 64, 64), (130, 90, 257), (520, 530, 40)])
 def test_zgemm_fp32(shape):
     api = _api()
     M, N, K = shape
