@@ -1057,22 +1057,31 @@ constexpr int STEIN_EXTRA = 0;
 // scratch: 6 * n * kpad doubles, kpad = k rounded up to 64.
 __global__ __launch_bounds__(64) void stein_kernel(const double* d, const double* e, int n, const double* w,
                                                    int k, double* Z, int ldz, double* scr, int kpad) {
+  // per-thread working arrays in LDS, [array][i][thread] (blockDim.x threads);
+  // the factors also go to `scr` for the refinement solves of the grouping
+  // kernel (write-only here)
+  extern __shared__ double lds[];
   __shared__ double sd[512], se[512];
-  for (int i = threadIdx.x; i < n; i += 64) { sd[i] = d[i]; se[i] = (i < n - 1) ? e[i] : 0.0; }
+  const int T = blockDim.x, t = threadIdx.x;
+  for (int i = t; i < n; i += T) { sd[i] = d[i]; se[i] = (i < n - 1) ? e[i] : 0.0; }
   __syncthreads();
-  const int j = blockIdx.x * 64 + threadIdx.x;
+  const int j = blockIdx.x * T + t;
   if (j >= k) return;
   double tnorm = 0.0;
   for (int i = 0; i < n; ++i) tnorm = fmax(tnorm, fabs(sd[i]) + fabs(se[i]) + (i > 0 ? fabs(se[i - 1]) : 0.0));
   const double tiny = fmax(tnorm, 1e-300) * 2.2e-16;
   const double lam = w[j];
-  double* U0 = scr + 0LL * n * kpad;
-  double* U1 = scr + 1LL * n * kpad;
-  double* U2 = scr + 2LL * n * kpad;
-  double* LM = scr + 3LL * n * kpad;
-  double* PV = scr + 4LL * n * kpad;
-  double* ZZ = scr + 5LL * n * kpad;
+  double* gU0 = scr + 0LL * n * kpad;
+  double* gU1 = scr + 1LL * n * kpad;
+  double* gU2 = scr + 2LL * n * kpad;
+  double* gLM = scr + 3LL * n * kpad;
+  double* gPV = scr + 4LL * n * kpad;
+  double* sU0 = lds;
+  double* sU1 = lds + (long long)n * T;
+  double* sU2 = lds + 2LL * n * T;
+  double* sZ = lds + 3LL * n * T;
 #define IX(i) ((long long)(i) * kpad + j)
+#define SX(i) ((i) * T + t)
   // pivoted LU of T - lam I, with the forward elimination of the start vector
   // folded in (its rows are eliminated in the same order); pivots below
   // eps ||T|| are replaced by +-eps ||T|| for the back substitution
@@ -1083,57 +1092,66 @@ __global__ __launch_bounds__(64) void stein_kernel(const double* d, const double
     const double an = sd[i + 1] - lam;
     const double bn = (i + 1 < n - 1) ? se[i + 1] : 0.0;
     double nxt = hash_unit((unsigned)(i + 1), (unsigned)j);
+    double u0, u1, u2, mult, pv;
     if (fabs(a) >= fabs(c)) {
       const double aa = (a == 0.0) ? tiny : a;
-      const double mult = c / aa;
-      U0[IX(i)] = (fabs(aa) < tiny) ? copysign(tiny, aa) : aa;
-      U1[IX(i)] = b; U2[IX(i)] = 0.0; LM[IX(i)] = mult; PV[IX(i)] = 0.0;
+      mult = c / aa;
+      u0 = (fabs(aa) < tiny) ? copysign(tiny, aa) : aa;
+      u1 = b; u2 = 0.0; pv = 0.0;
       a = an - mult * b;
       b = bn;
     } else {
-      const double mult = a / c;
-      U0[IX(i)] = (fabs(c) < tiny) ? copysign(tiny, c) : c;
-      U1[IX(i)] = an; U2[IX(i)] = bn; LM[IX(i)] = mult; PV[IX(i)] = 1.0;
+      mult = a / c;
+      u0 = (fabs(c) < tiny) ? copysign(tiny, c) : c;
+      u1 = an; u2 = bn; pv = 1.0;
       a = b - mult * an;
       b = -mult * bn;
-      const double t = cur; cur = nxt; nxt = t;
+      const double tt = cur; cur = nxt; nxt = tt;
     }
-    nxt -= LM[IX(i)] * cur;
-    ZZ[IX(i)] = cur;
+    sU0[SX(i)] = u0; sU1[SX(i)] = u1; sU2[SX(i)] = u2;
+    gU0[IX(i)] = u0; gU1[IX(i)] = u1; gU2[IX(i)] = u2; gLM[IX(i)] = mult; gPV[IX(i)] = pv;
+    nxt -= mult * cur;
+    sZ[SX(i)] = cur;
     cur = nxt;
   }
-  U0[IX(n - 1)] = (fabs(a) < tiny) ? copysign(tiny, a == 0.0 ? 1.0 : a) : a;
-  ZZ[IX(n - 1)] = cur;
+  {
+    const double u0 = (fabs(a) < tiny) ? copysign(tiny, a == 0.0 ? 1.0 : a) : a;
+    sU0[SX(n - 1)] = u0; sU1[SX(n - 1)] = 0.0; sU2[SX(n - 1)] = 0.0;
+    gU0[IX(n - 1)] = u0; gU1[IX(n - 1)] = 0.0; gU2[IX(n - 1)] = 0.0; gLM[IX(n - 1)] = 0.0; gPV[IX(n - 1)] = 0.0;
+  }
+  sZ[SX(n - 1)] = cur;
   for (int iter = 0; iter <= STEIN_EXTRA; ++iter) {
     if (iter > 0) {
       // forward: the row exchanges and multipliers again
-      double cf = ZZ[IX(0)];
+      double cf = sZ[SX(0)];
       for (int i = 0; i < n - 1; ++i) {
-        double nf = ZZ[IX(i + 1)];
-        if (PV[IX(i)] != 0.0) { const double t = cf; cf = nf; nf = t; }
-        nf -= LM[IX(i)] * cf;
-        ZZ[IX(i)] = cf;
+        double nf = sZ[SX(i + 1)];
+        if (gPV[IX(i)] != 0.0) { const double tt = cf; cf = nf; nf = tt; }
+        nf -= gLM[IX(i)] * cf;
+        sZ[SX(i)] = cf;
         cf = nf;
       }
-      ZZ[IX(n - 1)] = cf;
+      sZ[SX(n - 1)] = cf;
     }
     // backward substitution with the upper factor (bandwidth 3)
-    double z1 = 0.0, z2 = 0.0, nrm = 0.0, big = 0.0;
+    double z1 = 0.0, z2 = 0.0, big = 0.0;
     for (int i = n - 1; i >= 0; --i) {
-      const double z = (ZZ[IX(i)] - U1[IX(i)] * z1 - U2[IX(i)] * z2) / U0[IX(i)];
-      ZZ[IX(i)] = z;
+      const double z = (sZ[SX(i)] - sU1[SX(i)] * z1 - sU2[SX(i)] * z2) / sU0[SX(i)];
+      sZ[SX(i)] = z;
       z2 = z1; z1 = z;
       big = fmax(big, fabs(z));
     }
     const double inv = (big > 0.0) ? 1.0 / big : 1.0;
-    for (int i = 0; i < n; ++i) { const double z = ZZ[IX(i)] * inv; nrm += z * z; ZZ[IX(i)] = z; }
+    double nrm = 0.0;
+    for (int i = 0; i < n; ++i) { const double z = sZ[SX(i)] * inv; nrm += z * z; sZ[SX(i)] = z; }
     const double sc = 1.0 / sqrt(fmax(nrm, 1e-300));
-    for (int i = 0; i < n; ++i) ZZ[IX(i)] *= sc;
+    for (int i = 0; i < n; ++i) sZ[SX(i)] *= sc;
   }
   // deterministic sign: largest-magnitude component positive
   double big = 0.0, sg = 1.0;
-  for (int i = 0; i < n; ++i) { const double z = ZZ[IX(i)]; if (fabs(z) > big) { big = fabs(z); sg = z < 0 ? -1.0 : 1.0; } }
-  for (int i = 0; i < n; ++i) Z[(long long)i * ldz + j] = sg * ZZ[IX(i)];
+  for (int i = 0; i < n; ++i) { const double z = sZ[SX(i)]; if (fabs(z) > big) { big = fabs(z); sg = z < 0 ? -1.0 : 1.0; } }
+  for (int i = 0; i < n; ++i) Z[(long long)i * ldz + j] = sg * sZ[SX(i)];
+#undef SX
 #undef IX
 }
 
@@ -1391,7 +1409,11 @@ hipError_t trid_eigenvalues(int n, const TridWork& t, double* w, hipStream_t s) 
 
 hipError_t trid_vectors(int n, const TridWork& t, const double* w, int kvec, hipStream_t s) {
   if (kvec <= 0) return hipSuccess;
-  hipLaunchKernelGGL(stein_kernel, dim3((kvec + 63) / 64), dim3(64), 0, s, t.d, t.e, n, w, kvec, t.Z, n,
+  // threads per workgroup so that four n-long arrays per thread fit in 128 KB of LDS
+  int tpb = 64;
+  while (tpb > 1 && 4LL * n * tpb * 8 > 131072) tpb >>= 1;
+  const size_t lds = (size_t)4 * n * tpb * 8;
+  hipLaunchKernelGGL(stein_kernel, dim3((kvec + tpb - 1) / tpb), dim3(tpb), lds, s, t.d, t.e, n, w, kvec, t.Z, n,
                      t.scr, t.kpad);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
