@@ -1157,47 +1157,70 @@ __global__ __launch_bounds__(64) void stein_kernel(const double* d, const double
 
 // U[:, j] = Q z_j for j < k: Q = H_0 H_1 ... H_{n-2}, H_i = I - tau_i v_i v_i^H
 // acting on rows i+1..n-1 (v_i is row i of Vt).  U complex (ld ldu), Z real.
+constexpr int ORM_B = 8;   // reflectors staged through LDS at a time
+
+// One wave per vector; the reflectors are staged through LDS in blocks of
+// ORM_B by the whole workgroup, so each application reads them at LDS latency.
 __global__ __launch_bounds__(256) void ormtr_kernel(const double* Vt, const double* tau, int n, const double* Z,
                                                     int ldz, int k, double* U, int ldu) {
+  __shared__ double vs[ORM_B][2 * 512];
+  __shared__ double ts[ORM_B][2];
   const int lane = threadIdx.x & 63;
   const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (j >= k) return;
+  const bool active = j < k;
   constexpr int MAXQ = 8;   // n <= 512
   double ur[MAXQ], ui[MAXQ];
 #pragma unroll
   for (int q = 0; q < MAXQ; ++q) {
     const int r = lane + 64 * q;
-    ur[q] = (r < n) ? Z[(long long)r * ldz + j] : 0.0;
+    ur[q] = (active && r < n) ? Z[(long long)r * ldz + j] : 0.0;
     ui[q] = 0.0;
   }
-  for (int i = n - 2; i >= 0; --i) {
-    const double tr = tau[2 * i], ti = tau[2 * i + 1];
-    if (tr == 0.0 && ti == 0.0) continue;
-    const double* v = Vt + 2LL * i * n;
-    double dr = 0.0, di = 0.0;
-#pragma unroll
-    for (int q = 0; q < MAXQ; ++q) {
-      const int r = lane + 64 * q;
-      if (r > i && r < n) {
-        const double a = v[2 * r], b = v[2 * r + 1];
-        dr += a * ur[q] + b * ui[q];          // conj(v) u
-        di += a * ui[q] - b * ur[q];
-      }
+  for (int ih = n - 2; ih >= 0; ih -= ORM_B) {
+    const int nb = min(ORM_B, ih + 1);        // reflectors ih, ih-1, ..., ih-nb+1
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nb * n; idx += 256) {
+      const int b = idx / n, r = idx % n, i = ih - b;
+      const bool on = r > i;
+      vs[b][2 * r] = on ? Vt[2 * ((long long)i * n + r)] : 0.0;
+      vs[b][2 * r + 1] = on ? Vt[2 * ((long long)i * n + r) + 1] : 0.0;
     }
-    dr = wave_sum(dr);
-    di = wave_sum(di);
-    // u -= tau v (v^H u)
-    const double fr = tr * dr - ti * di, fi = tr * di + ti * dr;
+    if (threadIdx.x < nb) {
+      ts[threadIdx.x][0] = tau[2 * (ih - threadIdx.x)];
+      ts[threadIdx.x][1] = tau[2 * (ih - threadIdx.x) + 1];
+    }
+    __syncthreads();
+    if (!active) continue;
+    for (int b = 0; b < nb; ++b) {
+      const double tr = ts[b][0], ti = ts[b][1];
+      if (tr == 0.0 && ti == 0.0) continue;
+      const double* v = vs[b];
+      double dr = 0.0, di = 0.0;
 #pragma unroll
-    for (int q = 0; q < MAXQ; ++q) {
-      const int r = lane + 64 * q;
-      if (r > i && r < n) {
-        const double a = v[2 * r], b = v[2 * r + 1];
-        ur[q] -= a * fr - b * fi;
-        ui[q] -= a * fi + b * fr;
+      for (int q = 0; q < MAXQ; ++q) {
+        const int r = lane + 64 * q;
+        if (r < n) {
+          const double a = v[2 * r], bb = v[2 * r + 1];
+          dr += a * ur[q] + bb * ui[q];          // conj(v) u
+          di += a * ui[q] - bb * ur[q];
+        }
+      }
+      dr = wave_sum(dr);
+      di = wave_sum(di);
+      // u -= tau v (v^H u)
+      const double fr = tr * dr - ti * di, fi = tr * di + ti * dr;
+#pragma unroll
+      for (int q = 0; q < MAXQ; ++q) {
+        const int r = lane + 64 * q;
+        if (r < n) {
+          const double a = v[2 * r], bb = v[2 * r + 1];
+          ur[q] -= a * fr - bb * fi;
+          ui[q] -= a * fi + bb * fr;
+        }
       }
     }
   }
+  if (!active) return;
 #pragma unroll
   for (int q = 0; q < MAXQ; ++q) {
     const int r = lane + 64 * q;
