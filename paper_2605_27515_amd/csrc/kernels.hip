@@ -884,84 +884,93 @@ __global__ __launch_bounds__(TRD_NT) void hetrd_fused_kernel(double* G, int ldg,
     }
     __syncthreads();
   }
+  // Main loop.  The vector work of a step (s = Re(v^H y), w, the updated
+  // first column of the block, the next reflector and its scaling) is done by
+  // wave 0 alone with wave reductions, each lane owning the entries r = lane
+  // + 64 q; the whole workgroup meets only at the two barriers around the
+  // fused update-and-product pass.
+  __shared__ int stop;
+  const int lane = tid & 63;
+  const bool w0 = tid < 64;
   bool inL = false;
   int base = 0;
+  double tr = sc[0], ti = sc[1];          // reflector j (used by wave 0)
   for (int j = 0;; ++j) {
     m = n - j - 1;
-    const double tr = sc[0], ti = sc[1];
-    const bool refl = !(tr == 0.0 && ti == 0.0);
-    // w = tau y - (|tau|^2 / 2) Re(v^H y) v
-    double sp = 0.0;
-    for (int r = tid; r < m; r += TRD_NT) sp += v_r[r] * y_r[r] + v_i[r] * y_i[r];
-    const double s = block_sum<TRD_NT>(sp, red);
-    const double h = 0.5 * (tr * tr + ti * ti) * s;
-    for (int r = tid; r < m; r += TRD_NT) {
-      if (refl) {
-        w_r[r] = tr * y_r[r] - ti * y_i[r] - h * v_r[r];
-        w_i[r] = tr * y_i[r] + ti * y_r[r] - h * v_i[r];
-      } else {
-        w_r[r] = 0.0; w_i[r] = 0.0;
-      }
-    }
-    __syncthreads();
-    // column 0 of the block (global column j+1, rows j+1..n-1) after the update
-    for (int r = tid; r < m; r += TRD_NT) {
-      const int R = j + 1 + r, Cc = j + 1;
-      double br, bi;
-      if (inL) {
-        const long long o = 2 * ((long long)(R - base) * HT_LDSM + (Cc - base));
-        br = Ls[o]; bi = Ls[o + 1];
-      } else {
-        const long long o = 2 * ((long long)R * ldg + Cc);
-        br = G[o]; bi = G[o + 1];
-      }
-      br -= w_r[r] * v_r[0] + w_i[r] * v_i[0] + v_r[r] * w_r[0] + v_i[r] * w_i[0];
-      bi -= w_i[r] * v_r[0] - w_r[r] * v_i[0] + v_i[r] * w_r[0] - v_r[r] * w_i[0];
-      nv_r[r] = br; nv_i[r] = bi;      // raw x (reflector source) for now
-    }
-    __syncthreads();
-    if (m == 1) {
-      if (tid == 0) d[j + 1] = nv_r[0];
-      break;
-    }
-    // reflector j+1 from x = nv[1..m-1] (nv[0] is the new diagonal entry):
-    // squared norm of the tail x[1:] = nv[2..m-1]
-    double part = 0.0;
-    for (int r = 2 + tid; r < m; r += TRD_NT) part += nv_r[r] * nv_r[r] + nv_i[r] * nv_i[r];
-    const double xn2b = block_sum<TRD_NT>(part, red);
-    if (tid == 0) {
-      const double ar = nv_r[1], ai = nv_i[1];
-      double ntr = 0.0, nti = 0.0, beta = ar, s_r = 0.0, s_i = 0.0;
-      if (!(xn2b == 0.0 && ai == 0.0)) {
-        beta = -copysign(sqrt(ar * ar + ai * ai + xn2b), ar);
-        ntr = (beta - ar) / beta; nti = -ai / beta;
-        const double pr = ar - beta, pi = ai, den = pr * pr + pi * pi;
-        s_r = pr / den; s_i = -pi / den;
-      }
-      d[j + 1] = nv_r[0];
-      e[j + 1] = beta;
-      tau[2 * (j + 1)] = ntr; tau[2 * (j + 1) + 1] = nti;
-      sc[4] = ntr; sc[5] = nti; sc[2] = s_r; sc[3] = s_i;
-    }
-    __syncthreads();
-    // scaled reflector v' in the next block's local indices (r' = r - 1),
-    // v'[0] = 1; staged through y (free until the partial sums are folded)
-    {
-      const double s_r = sc[2], s_i = sc[3];
-      for (int r = 1 + tid; r < m; r += TRD_NT) {
-        double a = 1.0, b = 0.0;
-        if (r > 1) {
-          const double xr = nv_r[r], xi = nv_i[r];
-          a = xr * s_r - xi * s_i; b = xr * s_i + xi * s_r;
+    if (w0) {
+      const bool refl = !(tr == 0.0 && ti == 0.0);
+      double sp = 0.0;
+      for (int r = lane; r < m; r += 64) sp += v_r[r] * y_r[r] + v_i[r] * y_i[r];
+      const double h = 0.5 * (tr * tr + ti * ti) * wave_sum(sp);
+      // w = tau y - (|tau|^2 / 2) Re(v^H y) v
+      for (int r = lane; r < m; r += 64) {
+        if (refl) {
+          w_r[r] = tr * y_r[r] - ti * y_i[r] - h * v_r[r];
+          w_i[r] = tr * y_i[r] + ti * y_r[r] - h * v_i[r];
+        } else {
+          w_r[r] = 0.0; w_i[r] = 0.0;
         }
-        y_r[r - 1] = a; y_i[r - 1] = b;
-        Vt[2 * ((long long)(j + 1) * n + j + 1 + r)] = a;
-        Vt[2 * ((long long)(j + 1) * n + j + 1 + r) + 1] = b;
       }
-      __syncthreads();
-      for (int r = tid; r < m - 1; r += TRD_NT) { nv_r[r] = y_r[r]; nv_i[r] = y_i[r]; }
-      __syncthreads();
+      const double v0r = v_r[0], v0i = v_i[0];
+      const double w0r = refl ? tr * y_r[0] - ti * y_i[0] - h * v0r : 0.0;
+      const double w0i = refl ? tr * y_i[0] + ti * y_r[0] - h * v0i : 0.0;
+      // first column of the block (global column j+1) after step j's update,
+      // kept in y (free until the fold): x[r] for r < m
+      double f_r = 0.0, f_i = 0.0, tail = 0.0;
+      for (int r = lane; r < m; r += 64) {
+        const int R = j + 1 + r, Cc = j + 1;
+        double br, bi;
+        if (inL) {
+          const long long o = 2 * ((long long)(R - base) * HT_LDSM + (Cc - base));
+          br = Ls[o]; bi = Ls[o + 1];
+        } else {
+          const long long o = 2 * ((long long)R * ldg + Cc);
+          br = G[o]; bi = G[o + 1];
+        }
+        br -= w_r[r] * v0r + w_i[r] * v0i + v_r[r] * w0r + v_i[r] * w0i;
+        bi -= w_i[r] * v0r - w_r[r] * v0i + v_i[r] * w0r - v_r[r] * w0i;
+        y_r[r] = br; y_i[r] = bi;
+        if (r == lane) { f_r = br; f_i = bi; }
+        if (r >= 2) tail += br * br + bi * bi;
+      }
+      if (m == 1) {
+        if (lane == 0) d[j + 1] = f_r;
+      } else {
+        // reflector j+1 from x[1:] (x[0] is the new diagonal entry); every
+        // lane evaluates it from the same broadcast values
+        const double xn2 = wave_sum(tail);
+        const double dg = __shfl(f_r, 0, 64);
+        const double ar = __shfl(f_r, 1, 64), ai = __shfl(f_i, 1, 64);
+        double ntr = 0.0, nti = 0.0, beta = ar, s_r = 0.0, s_i = 0.0;
+        if (!(xn2 == 0.0 && ai == 0.0)) {
+          beta = -copysign(sqrt(ar * ar + ai * ai + xn2), ar);
+          ntr = (beta - ar) / beta; nti = -ai / beta;
+          const double pr = ar - beta, pi = ai, den = pr * pr + pi * pi;
+          s_r = pr / den; s_i = -pi / den;
+        }
+        if (lane == 0) {
+          d[j + 1] = dg;
+          e[j + 1] = beta;
+          tau[2 * (j + 1)] = ntr; tau[2 * (j + 1) + 1] = nti;
+        }
+        // scaled reflector v' in the next block's local indices (r' = r - 1)
+        for (int r = lane; r < m; r += 64) {
+          if (r < 1) continue;
+          double va = 1.0, vb = 0.0;
+          if (r > 1) {
+            const double xr = y_r[r], xi = y_i[r];
+            va = xr * s_r - xi * s_i; vb = xr * s_i + xi * s_r;
+          }
+          nv_r[r - 1] = va; nv_i[r - 1] = vb;
+          Vt[2 * ((long long)(j + 1) * n + j + 1 + r)] = va;
+          Vt[2 * ((long long)(j + 1) * n + j + 1 + r) + 1] = vb;
+        }
+        tr = ntr; ti = nti;
+      }
+      if (lane == 0) stop = (m == 1);
     }
+    __syncthreads();
+    if (stop) break;
     // fused pass over rows/cols j+2..n-1: update of step j, product with v'
     const bool dst = inL || (m - 1 <= HT_LDSM);
     if (!inL && !dst) hetrd_fused_pass<false, false>(G, ldg, Ls, base, j, m, v_r, v_i, w_r, w_i, nv_r, nv_i, yp_r, yp_i);
@@ -969,16 +978,17 @@ __global__ __launch_bounds__(TRD_NT) void hetrd_fused_kernel(double* G, int ldg,
     else hetrd_fused_pass<true, true>(G, ldg, Ls, base, j, m, v_r, v_i, w_r, w_i, nv_r, nv_i, yp_r, yp_i);
     __syncthreads();
     if (dst && !inL) { inL = true; base = j + 2; }
-    const int ncols = m - 1;
-    const int parts = (ncols <= 256) ? 4 : 2;
-    for (int c = tid; c < ncols; c += TRD_NT) {
-      double ar = 0.0, ai = 0.0;
-      for (int p = 0; p < parts; ++p) { ar += yp_r[p * 512 + c]; ai += yp_i[p * 512 + c]; }
-      y_r[c] = ar; y_i[c] = ai;
-      v_r[c] = nv_r[c]; v_i[c] = nv_i[c];
+    if (w0) {
+      // fold the partial products into y' and move v' into v
+      const int ncols = m - 1;
+      const int parts = (ncols <= 256) ? 4 : 2;
+      for (int c = lane; c < ncols; c += 64) {
+        double ar = 0.0, ai = 0.0;
+        for (int p = 0; p < parts; ++p) { ar += yp_r[p * 512 + c]; ai += yp_i[p * 512 + c]; }
+        y_r[c] = ar; y_i[c] = ai;
+        v_r[c] = nv_r[c]; v_i[c] = nv_i[c];
+      }
     }
-    if (tid == 0) { sc[0] = sc[4]; sc[1] = sc[5]; }
-    __syncthreads();
   }
 }
 
