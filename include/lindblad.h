@@ -57,7 +57,10 @@ enum lb_precision {
   LB_FP64 = 0,          /* every contraction in complex128                       */
   LB_FP32_CONTRACT = 1  /* MPO/MPS contractions in complex64 (FP32 accumulate);
                            Gram matrices, eigen-decompositions, truncation
-                           weights and trace in FP64                            */
+                           weights and trace in FP64.  The back-sweep and the
+                           purification cut run at max(tol, 1e-6) here:
+                           complex64 rounding puts noise singular values near
+                           1e-7 sigma_1                                        */
 };
 
 typedef struct lb_config {

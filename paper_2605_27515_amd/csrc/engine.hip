@@ -61,10 +61,15 @@ struct Fail : std::runtime_error {
 // A released block goes back to the cache, not to HIP: hipFree synchronises
 // the whole device and would stall every other solve in flight.  A block is
 // put back only after the stream it was used on has drained, so a block in
-// the cache has no pending work and any stream may take it.
+// the cache has no pending work and any stream may take it.  Classes up to
+// 32 MB are carved from 256 MB slabs, so a solve admitted while others run
+// rarely reaches hipMalloc.
 struct BlockCache {
   std::mutex mu;
   std::map<std::pair<int, size_t>, std::vector<void*>> free;
+  struct Slab { char* base; size_t used; };
+  std::map<int, Slab> slab;   // current slab per device
+  static constexpr size_t kSlab = (size_t)256 << 20, kSlabMax = (size_t)32 << 20;
 };
 
 BlockCache& block_cache() {
@@ -76,6 +81,39 @@ size_t size_class(size_t b) {
   size_t c = 256;
   while (c < b) c <<= 1;
   return c;
+}
+
+// A block of class `cls` on device `d` (caller holds no lock).
+void* cache_get(int d, size_t cls) {
+  BlockCache& c = block_cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  auto it = c.free.find({d, cls});
+  if (it != c.free.end() && !it->second.empty()) {
+    void* q = it->second.back();
+    it->second.pop_back();
+    return q;
+  }
+  void* q = nullptr;
+  if (cls <= BlockCache::kSlabMax) {
+    auto sl = c.slab.find(d);
+    if (sl == c.slab.end() || sl->second.used + cls > BlockCache::kSlab) {
+      void* base = nullptr;
+      if (hipMalloc(&base, BlockCache::kSlab) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+      c.slab[d] = BlockCache::Slab{(char*)base, 0};
+      sl = c.slab.find(d);
+    }
+    q = sl->second.base + sl->second.used;   // offsets stay multiples of cls (classes are powers of two)
+    sl->second.used += cls;
+    return q;
+  }
+  if (hipMalloc(&q, cls) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return q;
 }
 
 struct DevBuf {
@@ -101,23 +139,8 @@ struct DevBuf {
     const size_t cls = size_class(b);
     int d = 0;
     (void)hipGetDevice(&d);
-    void* q = nullptr;
-    {
-      BlockCache& c = block_cache();
-      std::lock_guard<std::mutex> g(c.mu);
-      auto it = c.free.find({d, cls});
-      if (it != c.free.end() && !it->second.empty()) {
-        q = it->second.back();
-        it->second.pop_back();
-      }
-    }
-    if (!q) {
-      hipError_t e = hipMalloc(&q, cls);
-      if (e != hipSuccess) {
-        (void)hipGetLastError();
-        throw Fail(LB_ERR_OOM, "hipMalloc of " + std::to_string(cls) + " bytes failed");
-      }
-    }
+    void* q = cache_get(d, cls);
+    if (!q) throw Fail(LB_ERR_OOM, "device allocation of " + std::to_string(cls) + " bytes failed");
     p = q; bytes = cls; dev = d; st = stream;
   }
   void release() {
@@ -216,6 +239,17 @@ using lbk::Prec;
 
 bool fp32(const lb_solver* s) { return s->cfg.precision == LB_FP32_CONTRACT; }
 int passes(const lb_solver* s) { return fp32(s) ? 1 : 2; }
+
+// Truncation tolerance of the back-sweep and the purification cut.  The FP32
+// form forms T in complex64, so singular values below ~1e-7 sigma_1 are
+// rounding noise there; keeping them (tol = 1e-8 would) grows the bonds to the
+// caps with noise.  These cuts sit at the orthogonality centre, where
+// truncating X at t changes rho by ~t^2, so they run at no less than 1e-6
+// (rho moves by ~1e-12, far below the complex64 rounding already in rho).  The
+// zip-up cuts a product whose right part is not orthonormal (their error
+// enters rho at first order) and keeps tol / 10.
+constexpr double kFp32TolFloor = 1e-6;
+double eff_tol(const lb_solver* s, double t) { return fp32(s) ? std::max(t, kFp32TolFloor) : t; }
 
 enum ProfClass { PC_CONTRACT = 0, PC_GRAM, PC_SVDGEMM, PC_HETRD, PC_STEBZ, PC_STEIN, PC_ORMTR, PC_JACOBI,
                  PC_OTHER, PC_COUNT };
@@ -742,7 +776,7 @@ void zipup(lb_solver* s) {
         Asrc = Bc;
         asrc = lbk::F64;
       }
-      { Timed tm(s, PC_OTHER, 0.0, 8.0 * mc); HIPCHK(lbk::truncate_rank(s->lam.d(), mc, s->cfg.tol, s->cfg.chi_mu_cap, s->kdev.i(), s->disc.d(),
+      { Timed tm(s, PC_OTHER, 0.0, 8.0 * mc); HIPCHK(lbk::truncate_rank(s->lam.d(), mc, eff_tol(s, s->cfg.tol), s->cfg.chi_mu_cap, s->kdev.i(), s->disc.d(),
                                 s->stream)); }
       const int k = read_k(s);
       s->discarded[0] = read_disc(s);
@@ -799,7 +833,7 @@ void normalize_center(lb_solver* s) {
 void step_once(lb_solver* s) {
   refresh_drive(s);
   zipup(s);
-  back_sweep(s, s->cfg.tol, true);
+  back_sweep(s, eff_tol(s, s->cfg.tol), true);
   normalize_center(s);
   double tau = 1.0;
   HIPCHK(hipMemcpyAsync(&tau, s->tau.p, sizeof(double), hipMemcpyDeviceToHost, s->stream));

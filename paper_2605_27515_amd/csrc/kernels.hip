@@ -1262,19 +1262,17 @@ __global__ __launch_bounds__(256) void ormtr_kernel(const double* Vt, const doub
 constexpr int SG_NT = 256;
 
 // z -= Z[:, cols] (Z[:, cols]^T z), twice; cols[p] = c0 + p when cols == nullptr.
+// Dots: one thread per earlier vector (rows of Z read coalesced across
+// threads); update: one thread per row.
 __device__ void sg_project(const double* Z, int ldz, int n, int c0, int nprev, const int* cols, double* zl,
                            double* dots) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int pass = 0; pass < 2; ++pass) {
-    for (int p0 = 0; p0 < nprev; p0 += SG_NT / 64) {
-      const int p = p0 + wave;
+    for (int p = threadIdx.x; p < nprev; p += SG_NT) {
+      const int c = cols ? cols[p] : c0 + p;
       double acc = 0.0;
-      if (p < nprev) {
-        const int c = cols ? cols[p] : c0 + p;
-        for (int r = lane; r < n; r += 64) acc += Z[(long long)r * ldz + c] * zl[r];
-      }
-      acc = wave_sum(acc);
-      if (lane == 0 && p < nprev) dots[p] = acc;
+#pragma unroll 4
+      for (int r = 0; r < n; ++r) acc += Z[(long long)r * ldz + c] * zl[r];
+      dots[p] = acc;
     }
     __syncthreads();
     for (int r = threadIdx.x; r < n; r += SG_NT) {
