@@ -49,6 +49,10 @@ PEAKS = {  # MI355X published dense peaks
     ("hbm", None): 8000.0,
 }
 ALU_CLASSES = {"hetrd", "stebz", "stein", "ormtr", "jacobi"}
+# HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this
+# workload, scaled by a plain 256 MiB copy (profiles/step_catbuffer_chi128_fp32_kernels.md);
+# a kernel absent here reports traffic null
+PMC_TRAFFIC_BYTES = {"hetrd": 0.858e6}
 
 
 def workload():
@@ -70,10 +74,30 @@ def roofline_entry(prof: dict, precision: str) -> dict:
         dt = "f32" if (precision == "fp32" and name == "gemm_contract") else "f64"
     achieved = (p["flop"] / p["launches"]) / (ms_per_launch * 1e-3) / 1e12 if p["ms"] > 0 else 0.0
     peak = PEAKS[(bound, dt)]
-    return {"kernel": name, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": None, "avg_launch_us": ms_per_launch * 1e3,
-            "launches": p["launches"], "flop_per_launch": p["flop"] / max(p["launches"], 1),
-            "dtype": dt}
+    out = {"kernel": name, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+           "frac": achieved / peak, "traffic": PMC_TRAFFIC_BYTES.get(name), "avg_launch_us": ms_per_launch * 1e3,
+           "launches": p["launches"], "flop_per_launch": p["flop"] / max(p["launches"], 1),
+           "dtype": dt}
+    if name in ALU_CLASSES:
+        # one workgroup per matrix: the fraction of the one CU it can occupy
+        out["frac_of_one_cu"] = achieved / (peak / 256.0)
+    return out
+
+
+def contraction_roofline(prof: dict, precision: str) -> dict:
+    """MFMA utilisation of the contraction GEMMs (MPO/MPS products and
+    carries) and of the Gram GEMMs, the kernels the dense-contraction roofline
+    applies to."""
+    out = {}
+    for name, dt in (("gemm_contract", "f32" if precision == "fp32" else "f64"), ("gemm_gram", "f64")):
+        p = prof.get(name)
+        if not p or not p["ms"]:
+            continue
+        achieved = p["flop"] / (p["ms"] * 1e-3) / 1e12
+        peak = PEAKS[("mfma", dt)]
+        out[name] = {"bound": "mfma", "dtype": dt, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "launches": p["launches"]}
+    return out
 
 
 def gpu_run(steps: int, warmup: int, precision: str):
@@ -266,6 +290,7 @@ def main():
                                "chi_mu=16, tol=1e-8, dt=2.5e-5, seeded saturated MPS",
                    "precision": args.precision, "parallelism": "single solve, one GPU"},
         "roofline": roofline_entry(prof, args.precision),
+        "roofline_contractions": contraction_roofline(prof, args.precision),
         "cpu_baseline": cpu,
         "fp64_plain_steps_per_s": fp64,
         "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items() if v["launches"]},
