@@ -6,7 +6,8 @@
  * A request is a solver whose generator is set (lindblad_set_generator) but
  * whose state is not yet on the device, the initial product state, a step
  * count and the observables wanted at the end.  lindblad_server_run admits
- * requests in arrival order as soon as (a) their arrival time has passed,
+ * requests in arrival order (equal arrival times: larger footprint first) as
+ * soon as (a) their arrival time has passed,
  * (b) one of the n_slots slots is free and (c) their device footprint
  * (lindblad_footprint) fits in what the running solves leave of hbm_budget.
  * An admitted request uploads its state, runs on its solver's own stream

@@ -1,6 +1,7 @@
 // Continuous-batching request loop over independent solves (lindblad_serve.h).
 //
-// n_slots host threads share one FIFO of requests ordered by arrival time.
+// n_slots host threads share one queue of requests ordered by arrival time
+// (ties: larger footprint first).
 // A thread takes the head of the queue once it has arrived and its device
 // footprint fits in the budget left by the running solves, then drives that
 // solve on the solver's own HIP stream: upload of the initial state, the
@@ -170,8 +171,15 @@ lb_status lindblad_server_run(lb_server* sv) {
     sv->queue.clear();
     for (int i = 0; i < (int)sv->reqs.size(); ++i)
       if (!sv->reqs[i].finished) sv->queue.push_back(i);
-    std::stable_sort(sv->queue.begin(), sv->queue.end(),
-                     [&](int a, int b) { return sv->reqs[a].arrival < sv->reqs[b].arrival; });
+    // arrival order; among requests that arrive together the larger footprint
+    // (a proxy for the longer solve) goes first, so a burst does not end on a
+    // long solve admitted last
+    std::stable_sort(sv->queue.begin(), sv->queue.end(), [&](int a, int b) {
+      const Request& x = sv->reqs[a];
+      const Request& y = sv->reqs[b];
+      if (x.arrival != y.arrival) return x.arrival < y.arrival;
+      return x.bytes > y.bytes;
+    });
     sv->head = 0;
     sv->used = 0;
     sv->running = 0;
