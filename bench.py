@@ -51,8 +51,9 @@ PEAKS = {  # MI355X published dense peaks
 ALU_CLASSES = {"hetrd", "stebz", "stein", "ormtr", "jacobi"}
 # HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this
 # workload, scaled by a plain 256 MiB copy (profiles/step_catbuffer_chi128_fp32_kernels.md);
-# a kernel absent here reports traffic null
-PMC_TRAFFIC_BYTES = {"hetrd": 0.858e6}
+# hetrd is the dispatch-weighted mean over its three instantiations.  A kernel
+# absent here reports traffic null
+PMC_TRAFFIC_BYTES = {"hetrd": 0.701e6}
 
 
 def workload():

@@ -7,7 +7,7 @@
 //                  split-K with a fixed-order reduction.
 //  * heev_kernel   Hermitian eigen-decomposition by cyclic Jacobi with the
 //                  round-robin parallel ordering (one workgroup per matrix).
-//  * tridiagonal route (hetrd_fused_kernel, stebz_kernel, stein_kernel,
+//  * tridiagonal route (hetrd_kernel, stebz_kernel, stein_kernel,
 //                  stein_groups_kernel, ormtr_kernel): Householder reduction
 //                  to real tridiagonal form, eigenvalues by Sturm-count
 //                  multisection, eigenvectors by inverse iteration made
@@ -627,27 +627,58 @@ hipError_t gram_stats(const double* E, int n, double* out, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Hermitian eigen-decomposition through a real symmetric tridiagonal form
 //   1. hetrd_kernel  Householder reduction G = Q T Q^H, T real (one workgroup;
-//                    each reflector chosen so that its beta is real)
+//                    each reflector chosen so that its beta is real; the
+//                    trailing block lives mostly in registers and LDS)
 //   2. stebz_kernel  all eigenvalues of T by bisection with 64-point
 //                    multisection, one wave per eigenvalue
 //   3. stein_kernel  eigenvectors of T by inverse iteration, one lane per
-//                    eigenvalue (pivoted tridiagonal LU, two iterations)
+//                    eigenvalue (pivoted tridiagonal LU, one solve)
 //   4. ormtr_kernel  back-transformation U = Q Z, one wave per column
 // ---------------------------------------------------------------------------
 namespace lbk {
 
-constexpr int TRD_NT = 1024;
+// Cross-lane moves inside a wave through DPP (data-parallel primitives: the
+// source lane is picked by the instruction's control word, no LDS round
+// trip).  Lanes of rows disabled by ROW_MASK receive `old`.  Callers run with
+// all 64 lanes active.
+template <int CTRL, int ROW_MASK>
+__device__ inline double dpp_f64(double old, double src) {
+  const unsigned long long o = (unsigned long long)__double_as_longlong(old);
+  const unsigned long long s = (unsigned long long)__double_as_longlong(src);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)o, (int)(unsigned)s, CTRL, ROW_MASK, 0xf, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(o >> 32), (int)(unsigned)(s >> 32), CTRL,
+                                                            ROW_MASK, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
+__device__ inline double read_lane(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Reductions over the 64 lanes of a wave, result in every lane: butterflies
+// inside quads, rotations inside rows of 16, row broadcasts 15 and 31 carry
+// the row totals into lane 63, which is read back.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_f64<0xB1, 0xF>(0.0, v);    // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E, 0xF>(0.0, v);    // quad_perm [2,3,0,1]
+  v += dpp_f64<0x124, 0xF>(0.0, v);   // row_ror:4
+  v += dpp_f64<0x128, 0xF>(0.0, v);   // row_ror:8
+  v += dpp_f64<0x142, 0xA>(0.0, v);   // row_bcast:15 into rows 1, 3
+  v += dpp_f64<0x143, 0xC>(0.0, v);   // row_bcast:31 into rows 2, 3
+  return read_lane(v, 63);
 }
 
 __device__ inline double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+  v = fmax(v, dpp_f64<0xB1, 0xF>(v, v));
+  v = fmax(v, dpp_f64<0x4E, 0xF>(v, v));
+  v = fmax(v, dpp_f64<0x124, 0xF>(v, v));
+  v = fmax(v, dpp_f64<0x128, 0xF>(v, v));
+  v = fmax(v, dpp_f64<0x142, 0xA>(v, v));
+  v = fmax(v, dpp_f64<0x143, 0xC>(v, v));
+  return read_lane(v, 63);
 }
 
 template <int NT>
@@ -668,327 +699,252 @@ __device__ inline double block_sum(double v, double* red) {
   return t;
 }
 
-// G (n x n, ld ldg, Hermitian, full storage) is destroyed.  Outputs: d[n],
-// e[n-1] (real tridiagonal), tau[n-1] (complex) and the reflector vectors as
-// rows of Vt (n x n, row j holds v_j on columns j+1..n-1, v_j[j+1] = 1).
-__global__ __launch_bounds__(TRD_NT) void hetrd_kernel(double* G, int ldg, int n, double* d, double* e,
-                                                       double* tau, double* Vt) {
-  __shared__ double vr[512], vi[512], yr[512], yi[512], wr[512], wi[512];
-  __shared__ double red[32];
-  __shared__ double sc[4];
-  const int tid = threadIdx.x;
-  for (int j = 0; j < n - 1; ++j) {
-    const int m = n - j - 1;
-    const int r0 = j + 1;
-    // 1. reflector from x = G[j+1:, j]
-    double part = 0.0;
-    for (int i = 1 + tid; i < m; i += TRD_NT) {
-      const double a = G[2 * ((long long)(r0 + i) * ldg + j)], b = G[2 * ((long long)(r0 + i) * ldg + j) + 1];
-      part += a * a + b * b;
-    }
-    const double xn2 = block_sum<TRD_NT>(part, red);
-    if (tid == 0) {
-      const double ar = G[2 * ((long long)r0 * ldg + j)], ai = G[2 * ((long long)r0 * ldg + j) + 1];
-      double tr, ti, beta, s_r, s_i;
-      if (xn2 == 0.0 && ai == 0.0) {
-        tr = 0.0; ti = 0.0; beta = ar; s_r = 0.0; s_i = 0.0;
-      } else {
-        beta = -copysign(sqrt(ar * ar + ai * ai + xn2), ar);
-        tr = (beta - ar) / beta; ti = -ai / beta;
-        // scale = 1 / (alpha - beta)
-        const double pr = ar - beta, pi = ai, den = pr * pr + pi * pi;
-        s_r = pr / den; s_i = -pi / den;
-      }
-      d[j] = G[2 * ((long long)j * ldg + j)];
-      e[j] = beta;
-      tau[2 * j] = tr; tau[2 * j + 1] = ti;
-      sc[0] = tr; sc[1] = ti; sc[2] = s_r; sc[3] = s_i;
-    }
-    __syncthreads();
-    const double tr = sc[0], ti = sc[1], s_r = sc[2], s_i = sc[3];
-    for (int i = tid; i < m; i += TRD_NT) {
-      double a, b;
-      if (i == 0) { a = 1.0; b = 0.0; }
-      else {
-        const double xr = G[2 * ((long long)(r0 + i) * ldg + j)], xi = G[2 * ((long long)(r0 + i) * ldg + j) + 1];
-        a = xr * s_r - xi * s_i; b = xr * s_i + xi * s_r;
-      }
-      vr[i] = a; vi[i] = b;
-      Vt[2 * ((long long)j * n + r0 + i)] = a;
-      Vt[2 * ((long long)j * n + r0 + i) + 1] = b;
-    }
-    __syncthreads();
-    if (tr == 0.0 && ti == 0.0) continue;
-    // 2. y = B v with B = G[j+1:, j+1:] Hermitian: y_r = sum_c conj(B[c][r]) v_c
-    const int half = (m + 1) / 2;
-    for (int rr = tid; rr < 2 * m; rr += TRD_NT) {
-      const int r = rr % m, part2 = rr / m;
-      const int c0 = part2 ? half : 0, c1 = part2 ? m : half;
-      double ar = 0.0, ai = 0.0;
-      for (int c = c0; c < c1; ++c) {
-        const double br = G[2 * ((long long)(r0 + c) * ldg + r0 + r)], bi = -G[2 * ((long long)(r0 + c) * ldg + r0 + r) + 1];
-        ar += br * vr[c] - bi * vi[c];
-        ai += br * vi[c] + bi * vr[c];
-      }
-      if (part2) { wr[r] = ar; wi[r] = ai; } else { yr[r] = ar; yi[r] = ai; }
-    }
-    __syncthreads();
-    for (int r = tid; r < m; r += TRD_NT) { yr[r] += wr[r]; yi[r] += wi[r]; }
-    __syncthreads();
-    // 3. s = Re(v^H y)
-    double sp = 0.0;
-    for (int r = tid; r < m; r += TRD_NT) sp += vr[r] * yr[r] + vi[r] * yi[r];
-    const double s = block_sum<TRD_NT>(sp, red);
-    // 4. w = tau y - (|tau|^2 / 2) s v
-    const double h = 0.5 * (tr * tr + ti * ti) * s;
-    for (int r = tid; r < m; r += TRD_NT) {
-      wr[r] = tr * yr[r] - ti * yi[r] - h * vr[r];
-      wi[r] = tr * yi[r] + ti * yr[r] - h * vi[r];
-    }
-    __syncthreads();
-    // 5. B -= w v^H + v w^H
-    for (long long q = tid; q < (long long)m * m; q += TRD_NT) {
-      const int r = (int)(q / m), c = (int)(q % m);
-      const long long off = 2 * ((long long)(r0 + r) * ldg + r0 + c);
-      // w_r conj(v_c) + v_r conj(w_c)
-      const double ur = wr[r] * vr[c] + wi[r] * vi[c] + vr[r] * wr[c] + vi[r] * wi[c];
-      const double ui = wi[r] * vr[c] - wr[r] * vi[c] + vi[r] * wr[c] - vr[r] * wi[c];
-      G[off] -= ur;
-      G[off + 1] -= ui;
-    }
-    __syncthreads();
-  }
-  if (tid == 0) d[n - 1] = G[2 * ((long long)(n - 1) * ldg + n - 1)];
+// Workgroup barrier that orders LDS only.  Used where every global address a
+// thread reads after the barrier was written, if at all, by that same thread.
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Fused variant: one pass per step over the trailing block applies step j's
-// rank-2 update and accumulates step j+1's product y' = B' v' (Hermitian, so
-// y'_c = sum_r conj(B'[r][c]) v'_r: one thread per column, coalesced rows).
-// Trailing blocks of at most HT_LDSM rows are kept in LDS.
-constexpr int HT_LDSM = 72;
+// Householder reduction of the Hermitian G (n x n, n <= 512, ld ldg complex
+// entries, full storage, destroyed) to the real tridiagonal (d, e):
+// reflector j = I - tau_j v_j v_j^H with v_j[j+1] = 1 annihilates column j
+// below the subdiagonal.  Outputs d[n], e[n-1], tau[n-1] (complex) and the
+// reflectors as rows of Vt (n x n complex, row j holds v_j on columns
+// j+1..n-1).
+//
+// One workgroup of 1024 threads.  Thread t owns column c = t % P (P = 1024 /
+// PARTS, the power of two >= n) and the rows R with (n-1-R) % PARTS == t / P;
+// its q-th row from the bottom, R = n-1-t/P-q*PARTS, sits in a register for
+// q < TRD_QR, in an LDS band for q < TRD_QR + QL and in G above that, so
+// the bottom rows of the trailing block never leave the chip (all of it for
+// n <= 128).  No thread touches another thread's entries, so the barriers
+// order LDS only.
+//
+// Step j: with y_j = B_j v_j (B_j the trailing block j+1.., from the last
+// pass), wave 0 forms w_j = tau_j y_j - (|tau_j|^2/2) Re(v_j^H y_j) v_j,
+// applies the rank-2 update B <- B - w v^H - v w^H to the block's first
+// column (handed over through LDS by the last pass), and builds reflector
+// j+1 from it.  Then one pass of all threads over rows/columns j+2.. applies
+// the rank-2 update of step j and accumulates y_{j+1} = B_{j+1} v_{j+1}
+// (Hermitian: y_c = sum_R conj(B[R][c]) v[R], a sum down the thread's own
+// column), handing column j+2 to the next step.
+constexpr int TRD_NT = 1024;
+constexpr int TRD_QR = 10;   // rows per thread in registers
 
-template <bool SRC_LDS, bool DST_LDS>
-__device__ inline void hetrd_fused_pass(double* G, int ldg, double* Ls, int base, int j, int m,
-                                        const double* v_r, const double* v_i, const double* w_r,
-                                        const double* w_i, const double* nv_r, const double* nv_i,
-                                        double* yp_r, double* yp_i) {
-  const int ncols = m - 1;
-  const int parts = (ncols <= 256) ? 4 : 2;
-  const int chunk = (ncols + parts - 1) / parts;
-  const int t = threadIdx.x;
-  if (t >= ncols * parts) return;
-  const int cl = 1 + t % ncols, part = t / ncols;
-  const int r0 = 1 + part * chunk, r1 = min(m, 1 + (part + 1) * chunk);
-  const int C = j + 1 + cl;
-  const double vcr = v_r[cl], vci = v_i[cl], wcr = w_r[cl], wci = w_i[cl];
+// LDS layout for P = 1024 / PARTS columns: vectors by global row, the
+// per-thread partial products and as many band rows per thread (QL) as fit
+// in the 160 KB of the CU.
+template <int PARTS>
+struct TrdShared {
+  static constexpr int P = TRD_NT / PARTS;
+  static constexpr int QL = (160 * 1024 - 1024 - 16 * (5 * P + TRD_NT)) / (16 * TRD_NT);
+  double2 v[2][P];            // v_j, v_{j+1} by global row
+  double2 w[P];               // w_j
+  double2 y[P];               // y_j, then the updated first column
+  double2 fc[P];              // first column of the next block after the pass
+  double2 yp[TRD_NT];         // per-thread partial sums of the product
+  double2 band[QL * TRD_NT];
+};
+
+// b -= wR conj(vC) + vR conj(wC)
+__device__ inline void trd_update(double2& b, double2 wR, double2 vR, double2 vC, double2 wC) {
+  b.x -= wR.x * vC.x + wR.y * vC.y + vR.x * wC.x + vR.y * wC.y;
+  b.y -= wR.y * vC.x - wR.x * vC.y + vR.y * wC.x - vR.x * wC.y;
+}
+
+// acc += conj(b) x
+__device__ inline void trd_acc(double& ar, double& ai, double2 b, double2 x) {
+  ar += b.x * x.x + b.y * x.y;
+  ai += b.x * x.y - b.y * x.x;
+}
+
+// Entry idx of G through a 32-bit byte offset from the (uniform) base, so a
+// load or store needs one address register (idx < 2^28 for n <= 512).
+__device__ inline double2& trd_at(double2* G, unsigned idx) {
+  return *reinterpret_cast<double2*>(reinterpret_cast<char*>(G) + idx * 16u);
+}
+
+template <int PARTS, bool FIRST>
+__device__ inline void trd_pass(double2* G, int ldg, int n, int j, TrdShared<PARTS>& sh, const double2* vc,
+                                const double2* vn, double2 (&reg)[TRD_QR], double2* vt_row) {
+  constexpr int P = TRD_NT / PARTS, QL = TrdShared<PARTS>::QL;
+  const int tid = threadIdx.x, c = tid % P, rho = tid / P;
+  const int lo = j + 2;
   double ar = 0.0, ai = 0.0;
-#pragma unroll 4
-  for (int r = r0; r < r1; ++r) {
-    const int R = j + 1 + r;
-    double br, bi;
-    if (SRC_LDS) {
-      const long long o = 2 * ((long long)(R - base) * HT_LDSM + (C - base));
-      br = Ls[o]; bi = Ls[o + 1];
-    } else {
-      const long long o = 2 * ((long long)R * ldg + C);
-      br = G[o]; bi = G[o + 1];
+  if (c >= lo && c < n) {
+    const double2 vC = FIRST ? double2{0.0, 0.0} : vc[c];
+    const double2 wC = FIRST ? double2{0.0, 0.0} : sh.w[c];
+    const int top = n - 1 - rho - lo;
+    const int qmax = top >= 0 ? top / PARTS : -1;
+    const bool fcol = (c == lo);
+    // rows above the chip-resident part: G, in place, two loads in flight
+    // (none when registers and band hold all P >= n rows)
+    if constexpr ((TRD_QR + QL) * PARTS < P) {
+      constexpr int QG = TRD_QR + QL;
+      int q = qmax;
+      for (; q >= QG + 1; q -= 2) {
+        double2 b[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) b[u] = trd_at(G, (unsigned)((n - 1 - rho - (q - u) * PARTS) * ldg + c));
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int R = n - 1 - rho - (q - u) * PARTS;
+          if (!FIRST) { trd_update(b[u], sh.w[R], vc[R], vC, wC); trd_at(G, (unsigned)(R * ldg + c)) = b[u]; }
+          trd_acc(ar, ai, b[u], vn[R]);
+          if (fcol) sh.fc[R] = b[u];
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      for (; q >= QG; --q) {
+        const int R = n - 1 - rho - q * PARTS;
+        double2 b = trd_at(G, (unsigned)(R * ldg + c));
+        if (!FIRST) { trd_update(b, sh.w[R], vc[R], vC, wC); trd_at(G, (unsigned)(R * ldg + c)) = b; }
+        trd_acc(ar, ai, b, vn[R]);
+        if (fcol) sh.fc[R] = b;
+      }
     }
-    // b -= w_r conj(v_c) + v_r conj(w_c)
-    br -= w_r[r] * vcr + w_i[r] * vci + v_r[r] * wcr + v_i[r] * wci;
-    bi -= w_i[r] * vcr - w_r[r] * vci + v_i[r] * wcr - v_r[r] * wci;
-    if (DST_LDS) {
-      const int nb = SRC_LDS ? base : (j + 2);
-      const long long o = 2 * ((long long)(R - nb) * HT_LDSM + (C - nb));
-      Ls[o] = br; Ls[o + 1] = bi;
-    } else {
-      const long long o = 2 * ((long long)R * ldg + C);
-      G[o] = br; G[o + 1] = bi;
+    // LDS band
+    for (int q = min(qmax, TRD_QR + QL - 1); q >= TRD_QR; --q) {
+      const int R = n - 1 - rho - q * PARTS;
+      double2& s = sh.band[(q - TRD_QR) * TRD_NT + tid];
+      double2 b;
+      if (FIRST) b = trd_at(G, (unsigned)(R * ldg + c));
+      else { b = s; trd_update(b, sh.w[R], vc[R], vC, wC); }
+      s = b;
+      trd_acc(ar, ai, b, vn[R]);
+      if (fcol) sh.fc[R] = b;
     }
-    // acc += conj(b) * nv[r - 1]
-    const double xr = nv_r[r - 1], xi = nv_i[r - 1];
-    ar += br * xr + bi * xi;
-    ai += br * xi - bi * xr;
+    // registers
+#pragma unroll
+    for (int q = TRD_QR - 1; q >= 0; --q) {
+      if (q <= qmax) {
+        const int R = n - 1 - rho - q * PARTS;
+        if (FIRST) reg[q] = trd_at(G, (unsigned)(R * ldg + c));
+        else trd_update(reg[q], sh.w[R], vc[R], vC, wC);
+        trd_acc(ar, ai, reg[q], vn[R]);
+        if (fcol) sh.fc[R] = reg[q];
+      }
+      // keep each row's LDS reads inside its own iteration (register pressure)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (rho == 0) vt_row[c] = vn[c];
   }
-  yp_r[part * 512 + cl - 1] = ar;
-  yp_i[part * 512 + cl - 1] = ai;
+  sh.yp[tid] = double2{ar, ai};
 }
 
-__global__ __launch_bounds__(TRD_NT) void hetrd_fused_kernel(double* G, int ldg, int n, double* d, double* e,
-                                                             double* tau, double* Vt) {
-  __shared__ double Ls[2 * HT_LDSM * HT_LDSM];
-  __shared__ double v_r[512], v_i[512], w_r[512], w_i[512], y_r[512], y_i[512], nv_r[512], nv_i[512];
-  __shared__ double yp_r[4 * 512], yp_i[4 * 512];
-  __shared__ double red[32];
-  __shared__ double sc[8];
-  const int tid = threadIdx.x;
+// Reflector from x = (alpha, x_2, ...) with xn2 = sum |x_i|^2 beyond alpha:
+// beta = -sign(Re alpha) ||x||, tau = (beta - alpha) / beta, and the scale
+// 1 / (alpha - beta) that turns x into v with v[0] = 1.  x = (real, 0...)
+// gives tau = 0 (no reflection).
+__device__ inline void trd_reflector(double2 alpha, double xn2, double& beta, double& tr, double& ti,
+                                     double2& scale) {
+  tr = 0.0; ti = 0.0; beta = alpha.x; scale = double2{0.0, 0.0};
+  if (xn2 == 0.0 && alpha.y == 0.0) return;
+  beta = -copysign(sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2), alpha.x);
+  const double ib = 1.0 / beta;
+  tr = (beta - alpha.x) * ib;
+  ti = -alpha.y * ib;
+  const double pr = alpha.x - beta, pi = alpha.y, iden = 1.0 / (pr * pr + pi * pi);
+  scale = double2{pr * iden, -pi * iden};
+}
+
+__device__ inline double2 cmul(double2 a, double2 b) { return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+
+template <int PARTS>
+__global__ __launch_bounds__(TRD_NT) void hetrd_kernel(double2* G, int ldg, int n, double* d, double* e,
+                                                       double2* tau, double2* Vt) {
+  constexpr int P = TRD_NT / PARTS;
+  __shared__ TrdShared<PARTS> sh;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const bool w0 = tid < 64;
   if (n == 1) {
-    if (tid == 0) d[0] = G[0];
+    if (tid == 0) d[0] = G[0].x;
     return;
   }
-  // reflector 0 from x = G[1:n, 0]
-  int m = n - 1;
-  {
-    double part = 0.0;
-    for (int i = 1 + tid; i < m; i += TRD_NT) {
-      const double a = G[2 * ((long long)(1 + i) * ldg)], b = G[2 * ((long long)(1 + i) * ldg) + 1];
-      part += a * a + b * b;
+  double2 reg[TRD_QR];
+  double tr = 0.0, ti = 0.0;   // tau_j, held by wave 0
+  // reflector 0 from column 0
+  if (w0) {
+    double tail = 0.0;
+    for (int R = 2 + lane; R < n; R += 64) {
+      const double2 x = G[(long long)R * ldg];
+      tail += x.x * x.x + x.y * x.y;
     }
-    const double xn2 = block_sum<TRD_NT>(part, red);
-    if (tid == 0) {
-      const double ar = G[2 * ((long long)ldg)], ai = G[2 * ((long long)ldg) + 1];
-      double tr = 0.0, ti = 0.0, beta = ar, s_r = 0.0, s_i = 0.0;
-      if (!(xn2 == 0.0 && ai == 0.0)) {
-        beta = -copysign(sqrt(ar * ar + ai * ai + xn2), ar);
-        tr = (beta - ar) / beta; ti = -ai / beta;
-        const double pr = ar - beta, pi = ai, den = pr * pr + pi * pi;
-        s_r = pr / den; s_i = -pi / den;
-      }
-      d[0] = G[0];
+    const double xn2 = wave_sum(tail);
+    const double2 alpha = G[ldg];
+    double beta;
+    double2 s;
+    trd_reflector(alpha, xn2, beta, tr, ti, s);
+    for (int R = 1 + lane; R < n; R += 64) sh.v[0][R] = (R == 1) ? double2{1.0, 0.0} : cmul(G[(long long)R * ldg], s);
+    if (lane == 0) {
+      d[0] = G[0].x;
       e[0] = beta;
-      tau[0] = tr; tau[1] = ti;
-      sc[0] = tr; sc[1] = ti; sc[2] = s_r; sc[3] = s_i;
+      tau[0] = double2{tr, ti};
     }
-    __syncthreads();
-    for (int i = tid; i < m; i += TRD_NT) {
-      double a = 1.0, b = 0.0;
-      if (i > 0) {
-        const double xr = G[2 * ((long long)(1 + i) * ldg)], xi = G[2 * ((long long)(1 + i) * ldg) + 1];
-        a = xr * sc[2] - xi * sc[3]; b = xr * sc[3] + xi * sc[2];
-      }
-      v_r[i] = a; v_i[i] = b;
-      Vt[2 * (1 + i)] = a; Vt[2 * (1 + i) + 1] = b;
-    }
-    __syncthreads();
-    // y = B v, B = G[1:, 1:]: y_c = sum_r conj(B[r][c]) v_r
-    const int parts = (m <= 256) ? 4 : 2;
-    const int chunk = (m + parts - 1) / parts;
-    if (tid < m * parts) {
-      const int c = tid % m, part = tid / m;
-      const int r0 = part * chunk, r1 = min(m, (part + 1) * chunk);
-      double ar = 0.0, ai = 0.0;
-#pragma unroll 4
-      for (int r = r0; r < r1; ++r) {
-        const long long o = 2 * ((long long)(1 + r) * ldg + 1 + c);
-        const double br = G[o], bi = G[o + 1];
-        ar += br * v_r[r] + bi * v_i[r];
-        ai += br * v_i[r] - bi * v_r[r];
-      }
-      yp_r[part * 512 + c] = ar;
-      yp_i[part * 512 + c] = ai;
-    }
-    __syncthreads();
-    for (int c = tid; c < m; c += TRD_NT) {
-      double ar = 0.0, ai = 0.0;
-      for (int p = 0; p < parts; ++p) { ar += yp_r[p * 512 + c]; ai += yp_i[p * 512 + c]; }
-      y_r[c] = ar; y_i[c] = ai;
-    }
-    __syncthreads();
   }
-  // Main loop.  The vector work of a step (s = Re(v^H y), w, the updated
-  // first column of the block, the next reflector and its scaling) is done by
-  // wave 0 alone with wave reductions, each lane owning the entries r = lane
-  // + 64 q; the whole workgroup meets only at the two barriers around the
-  // fused update-and-product pass.
-  __shared__ int stop;
-  const int lane = tid & 63;
-  const bool w0 = tid < 64;
-  bool inL = false;
-  int base = 0;
-  double tr = sc[0], ti = sc[1];          // reflector j (used by wave 0)
+  lds_barrier();
+  // y_0 = B_0 v_0 and the first column of B_0; the chip-resident rows are loaded
+  trd_pass<PARTS, true>(G, ldg, n, -1, sh, nullptr, sh.v[0], reg, Vt);
+  lds_barrier();
   for (int j = 0;; ++j) {
-    m = n - j - 1;
+    const double2* vc = sh.v[j & 1];
+    double2* vn = sh.v[(j & 1) ^ 1];
     if (w0) {
-      const bool refl = !(tr == 0.0 && ti == 0.0);
+      // y_j = sum of the partial products, s = Re(v^H y)
       double sp = 0.0;
-      for (int r = lane; r < m; r += 64) sp += v_r[r] * y_r[r] + v_i[r] * y_i[r];
+      double2 y0 = double2{0.0, 0.0};
+      for (int R = j + 1 + lane; R < n; R += 64) {
+        double2 y = double2{0.0, 0.0};
+#pragma unroll 4
+        for (int p = 0; p < PARTS; ++p) { const double2 t = sh.yp[p * P + R]; y.x += t.x; y.y += t.y; }
+        sh.y[R] = y;
+        if (R == j + 1 + lane) y0 = y;
+        const double2 v = vc[R];
+        sp += v.x * y.x + v.y * y.y;
+      }
+      const bool refl = !(tr == 0.0 && ti == 0.0);
       const double h = 0.5 * (tr * tr + ti * ti) * wave_sum(sp);
-      // w = tau y - (|tau|^2 / 2) Re(v^H y) v
-      for (int r = lane; r < m; r += 64) {
-        if (refl) {
-          w_r[r] = tr * y_r[r] - ti * y_i[r] - h * v_r[r];
-          w_i[r] = tr * y_i[r] + ti * y_r[r] - h * v_i[r];
-        } else {
-          w_r[r] = 0.0; w_i[r] = 0.0;
-        }
+      // w at the block's first row (v_j there is 1)
+      const double2 y1 = double2{read_lane(y0.x, 0), read_lane(y0.y, 0)};
+      const double2 w1 = refl ? double2{tr * y1.x - ti * y1.y - h, tr * y1.y + ti * y1.x} : double2{0.0, 0.0};
+      // w = tau y - h v, and the first column after step j's update:
+      // x = fc - w - v conj(w1)
+      double tail = 0.0;
+      double2 x0 = double2{0.0, 0.0};
+      for (int R = j + 1 + lane; R < n; R += 64) {
+        const double2 y = sh.y[R], v = vc[R], f = sh.fc[R];
+        const double2 w = refl ? double2{tr * y.x - ti * y.y - h * v.x, tr * y.y + ti * y.x - h * v.y} : double2{0.0, 0.0};
+        sh.w[R] = w;
+        const double2 x = double2{f.x - w.x - (v.x * w1.x + v.y * w1.y), f.y - w.y - (v.y * w1.x - v.x * w1.y)};
+        sh.y[R] = x;
+        if (R == j + 1 + lane) x0 = x;
+        if (R >= j + 3) tail += x.x * x.x + x.y * x.y;
       }
-      const double v0r = v_r[0], v0i = v_i[0];
-      const double w0r = refl ? tr * y_r[0] - ti * y_i[0] - h * v0r : 0.0;
-      const double w0i = refl ? tr * y_i[0] + ti * y_r[0] - h * v0i : 0.0;
-      // first column of the block (global column j+1) after step j's update,
-      // kept in y (free until the fold): x[r] for r < m
-      double f_r = 0.0, f_i = 0.0, tail = 0.0;
-      for (int r = lane; r < m; r += 64) {
-        const int R = j + 1 + r, Cc = j + 1;
-        double br, bi;
-        if (inL) {
-          const long long o = 2 * ((long long)(R - base) * HT_LDSM + (Cc - base));
-          br = Ls[o]; bi = Ls[o + 1];
-        } else {
-          const long long o = 2 * ((long long)R * ldg + Cc);
-          br = G[o]; bi = G[o + 1];
-        }
-        br -= w_r[r] * v0r + w_i[r] * v0i + v_r[r] * w0r + v_i[r] * w0i;
-        bi -= w_i[r] * v0r - w_r[r] * v0i + v_i[r] * w0r - v_r[r] * w0i;
-        y_r[r] = br; y_i[r] = bi;
-        if (r == lane) { f_r = br; f_i = bi; }
-        if (r >= 2) tail += br * br + bi * bi;
-      }
-      if (m == 1) {
-        if (lane == 0) d[j + 1] = f_r;
+      const double xn2 = wave_sum(tail);
+      const double dg = read_lane(x0.x, 0);
+      if (j == n - 2) {
+        if (lane == 0) d[j + 1] = dg;
       } else {
-        // reflector j+1 from x[1:] (x[0] is the new diagonal entry); every
-        // lane evaluates it from the same broadcast values
-        const double xn2 = wave_sum(tail);
-        const double dg = __shfl(f_r, 0, 64);
-        const double ar = __shfl(f_r, 1, 64), ai = __shfl(f_i, 1, 64);
-        double ntr = 0.0, nti = 0.0, beta = ar, s_r = 0.0, s_i = 0.0;
-        if (!(xn2 == 0.0 && ai == 0.0)) {
-          beta = -copysign(sqrt(ar * ar + ai * ai + xn2), ar);
-          ntr = (beta - ar) / beta; nti = -ai / beta;
-          const double pr = ar - beta, pi = ai, den = pr * pr + pi * pi;
-          s_r = pr / den; s_i = -pi / den;
-        }
+        const double2 alpha = double2{read_lane(x0.x, 1), read_lane(x0.y, 1)};
+        double beta;
+        double2 s;
+        trd_reflector(alpha, xn2, beta, tr, ti, s);
+        // same lane-to-row map as the loop that wrote sh.y
+        for (int R = j + 1 + lane; R < n; R += 64)
+          if (R >= j + 2) vn[R] = (R == j + 2) ? double2{1.0, 0.0} : cmul(sh.y[R], s);
         if (lane == 0) {
           d[j + 1] = dg;
           e[j + 1] = beta;
-          tau[2 * (j + 1)] = ntr; tau[2 * (j + 1) + 1] = nti;
+          tau[j + 1] = double2{tr, ti};
         }
-        // scaled reflector v' in the next block's local indices (r' = r - 1)
-        for (int r = lane; r < m; r += 64) {
-          if (r < 1) continue;
-          double va = 1.0, vb = 0.0;
-          if (r > 1) {
-            const double xr = y_r[r], xi = y_i[r];
-            va = xr * s_r - xi * s_i; vb = xr * s_i + xi * s_r;
-          }
-          nv_r[r - 1] = va; nv_i[r - 1] = vb;
-          Vt[2 * ((long long)(j + 1) * n + j + 1 + r)] = va;
-          Vt[2 * ((long long)(j + 1) * n + j + 1 + r) + 1] = vb;
-        }
-        tr = ntr; ti = nti;
-      }
-      if (lane == 0) stop = (m == 1);
-    }
-    __syncthreads();
-    if (stop) break;
-    // fused pass over rows/cols j+2..n-1: update of step j, product with v'
-    const bool dst = inL || (m - 1 <= HT_LDSM);
-    if (!inL && !dst) hetrd_fused_pass<false, false>(G, ldg, Ls, base, j, m, v_r, v_i, w_r, w_i, nv_r, nv_i, yp_r, yp_i);
-    else if (!inL && dst) hetrd_fused_pass<false, true>(G, ldg, Ls, base, j, m, v_r, v_i, w_r, w_i, nv_r, nv_i, yp_r, yp_i);
-    else hetrd_fused_pass<true, true>(G, ldg, Ls, base, j, m, v_r, v_i, w_r, w_i, nv_r, nv_i, yp_r, yp_i);
-    __syncthreads();
-    if (dst && !inL) { inL = true; base = j + 2; }
-    if (w0) {
-      // fold the partial products into y' and move v' into v
-      const int ncols = m - 1;
-      const int parts = (ncols <= 256) ? 4 : 2;
-      for (int c = lane; c < ncols; c += 64) {
-        double ar = 0.0, ai = 0.0;
-        for (int p = 0; p < parts; ++p) { ar += yp_r[p * 512 + c]; ai += yp_i[p * 512 + c]; }
-        y_r[c] = ar; y_i[c] = ai;
-        v_r[c] = nv_r[c]; v_i[c] = nv_i[c];
       }
     }
+    if (j == n - 2) break;
+    lds_barrier();
+    trd_pass<PARTS, false>(G, ldg, n, j, sh, vc, vn, reg, Vt + (long long)(j + 1) * n);
+    lds_barrier();
   }
 }
 
@@ -1429,7 +1385,15 @@ TridWork trid_work(double* work, int n, int kvec) {
 }
 
 hipError_t trid_reduce(double* G, int ldg, int n, const TridWork& t, hipStream_t s) {
-  hipLaunchKernelGGL(hetrd_fused_kernel, dim3(1), dim3(TRD_NT), 0, s, G, ldg, n, t.d, t.e, t.tau, t.Vt);
+  if (n <= 0) return hipSuccess;
+  if (n > 512 || ldg < n) return hipErrorInvalidValue;
+  double2* g2 = reinterpret_cast<double2*>(G);
+  double2* tau = reinterpret_cast<double2*>(t.tau);
+  double2* vt = reinterpret_cast<double2*>(t.Vt);
+  if (n <= 64) hipLaunchKernelGGL(hetrd_kernel<16>, dim3(1), dim3(TRD_NT), 0, s, g2, ldg, n, t.d, t.e, tau, vt);
+  else if (n <= 128) hipLaunchKernelGGL(hetrd_kernel<8>, dim3(1), dim3(TRD_NT), 0, s, g2, ldg, n, t.d, t.e, tau, vt);
+  else if (n <= 256) hipLaunchKernelGGL(hetrd_kernel<4>, dim3(1), dim3(TRD_NT), 0, s, g2, ldg, n, t.d, t.e, tau, vt);
+  else hipLaunchKernelGGL(hetrd_kernel<2>, dim3(1), dim3(TRD_NT), 0, s, g2, ldg, n, t.d, t.e, tau, vt);
   return hipGetLastError();
 }
 
