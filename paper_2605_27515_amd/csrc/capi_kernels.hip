@@ -80,7 +80,7 @@ lb_status lindblad_kernel_heev(int32_t n, const double* G, double* w, double* U,
       // same clean-up as the solver: two Newton-Schulz polar steps (G is scratch now)
       Dev dT(nn * 16);
       if (!dT.p) { rc = LB_ERR_OOM; break; }
-      if ((e = lbk::orthonormalize_columns((double*)dV.p, n, n, n, (double*)dG.p, (double*)dT.p, 2, s)) != hipSuccess) { rc = hip_fail(e, "orthonormalize"); break; }
+      if ((e = lbk::orthonormalize_columns((double*)dV.p, n, n, n, (double*)dG.p, (double*)dT.p, 2, nullptr, s)) != hipSuccess) { rc = hip_fail(e, "orthonormalize"); break; }
       if ((e = hipStreamSynchronize(s)) != hipSuccess) { rc = hip_fail(e, "sync"); break; }
     } else {
       if ((e = lbk::heev_jacobi((double*)dG.p, n, 0, n, (double*)dw.p, 0, (double*)dV.p, 1, 1.5e-15, 40,

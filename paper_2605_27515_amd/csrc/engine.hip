@@ -466,7 +466,7 @@ void eig_trid(lb_solver* s, double* G, int n, double* lam, double* U, int kvec) 
   }
   {
     Timed tm(s, PC_SVDGEMM, passes(s) * (8.0 * kvec * kvec * N * 2), passes(s) * 16.0 * (2.0 * N * kvec + kvec * kvec));
-    HIPCHK(lbk::orthonormalize_columns(U, n, n, kvec, s->scratch.d(), s->U2.d(), passes(s), s->stream));
+    HIPCHK(lbk::orthonormalize_columns(U, n, n, kvec, s->scratch.d(), s->U2.d(), passes(s), s->ws.p, s->stream));
   }
 }
 

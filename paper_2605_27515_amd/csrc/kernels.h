@@ -62,8 +62,9 @@ hipError_t trid_backtransform(int n, const TridWork& t, int kvec, double* U, int
 
 // Newton-Schulz polar steps U <- U (3I - U^H U) / 2 on the first k columns
 // of U (n rows, ld ldu): removes the eps ||G|| / gap overlap left by inverse
-// iteration.  S: k*k complex scratch, T: n*k complex scratch.
-hipError_t orthonormalize_columns(double* U, int ldu, int n, int k, double* S, double* T, int iters,
+// iteration.  S: k*k complex scratch, T: n*k complex scratch, ws: split-K
+// workspace of at least 32 * 64 * 64 complex (or nullptr: no split).
+hipError_t orthonormalize_columns(double* U, int ldu, int n, int k, double* S, double* T, int iters, void* ws,
                                   hipStream_t stream);
 
 // Truncation rule on descending eigenvalues lam (= squared singular values):

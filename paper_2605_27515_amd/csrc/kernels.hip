@@ -954,7 +954,11 @@ __device__ inline int sturm_count(const double* sd, const double* se2, int n, do
   if (fabs(q) < pivmin) q = -pivmin;
   if (q < 0.0) ++c;
   for (int i = 1; i < n; ++i) {
-    q = (sd[i] - x) - se2[i - 1] / q;
+    // e^2 / q through the hardware reciprocal refined by one Newton step
+    // (a few ulps: the count is exact for e^2 perturbed at that level)
+    const double r0 = __builtin_amdgcn_rcp(q);
+    const double r = fma(r0, fma(-q, r0, 1.0), r0);
+    q = (sd[i] - x) - se2[i - 1] * r;
     if (fabs(q) < pivmin) q = -pivmin;
     if (q < 0.0) ++c;
   }
@@ -1439,7 +1443,17 @@ size_t heev_tridiag_work_doubles(int n) {
   return (size_t)4 * n + 2 * (size_t)n * n + (size_t)n * n + 6 * (size_t)n * kpad + 64;
 }
 
-hipError_t orthonormalize_columns(double* U, int ldu, int n, int k, double* S, double* T, int iters,
+// K split so that about 32 partial tiles run (each at least 64 deep); the
+// products here have few 64 x 64 output tiles and would otherwise be one
+// long K loop on a handful of CUs.
+static int ns_splits(int M, int N, int K, const void* ws) {
+  if (!ws) return 1;
+  const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  if (tiles >= 32) return 1;
+  return std::max(1, std::min(32 / tiles, K / 64));
+}
+
+hipError_t orthonormalize_columns(double* U, int ldu, int n, int k, double* S, double* T, int iters, void* ws,
                                   hipStream_t s) {
   for (int it = 0; it < iters; ++it) {
     Gemm g;
@@ -1447,6 +1461,7 @@ hipError_t orthonormalize_columns(double* U, int ldu, int n, int k, double* S, d
     g.A = U; g.sa_m = 1; g.sa_k = ldu; g.conjA = 1;
     g.B = U; g.sb_k = ldu; g.sb_n = 1;
     g.C = S; g.sc_m = k; g.sc_n = 1;
+    g.splits = ns_splits(k, k, n, ws); g.ws = ws;
     hipError_t e = gemm(g, s);
     if (e != hipSuccess) return e;
     if ((e = newton_schulz_blend(S, k, s)) != hipSuccess) return e;
@@ -1455,6 +1470,7 @@ hipError_t orthonormalize_columns(double* U, int ldu, int n, int k, double* S, d
     h.A = U; h.sa_m = ldu; h.sa_k = 1;
     h.B = S; h.sb_k = k; h.sb_n = 1;
     h.C = T; h.sc_m = k; h.sc_n = 1;
+    h.splits = ns_splits(n, k, k, ws); h.ws = ws;
     if ((e = gemm(h, s)) != hipSuccess) return e;
     if ((e = copy_cols(T, k, U, ldu, n, k, nullptr, s)) != hipSuccess) return e;
   }
