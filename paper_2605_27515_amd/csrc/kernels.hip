@@ -948,17 +948,21 @@ __global__ __launch_bounds__(TRD_NT) void hetrd_kernel(double2* G, int ldg, int 
   }
 }
 
+// 1/q from the hardware reciprocal refined by one Newton step (a few ulps)
+__device__ inline double rcp_refined(double q) {
+  const double r0 = __builtin_amdgcn_rcp(q);
+  return fma(r0, fma(-q, r0, 1.0), r0);
+}
+
 __device__ inline int sturm_count(const double* sd, const double* se2, int n, double x, double pivmin) {
   int c = 0;
   double q = sd[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   if (q < 0.0) ++c;
   for (int i = 1; i < n; ++i) {
-    // e^2 / q through the hardware reciprocal refined by one Newton step
-    // (a few ulps: the count is exact for e^2 perturbed at that level)
-    const double r0 = __builtin_amdgcn_rcp(q);
-    const double r = fma(r0, fma(-q, r0, 1.0), r0);
-    q = (sd[i] - x) - se2[i - 1] * r;
+    // e^2 / q through the refined reciprocal (a few ulps: the count is
+    // exact for e^2 perturbed at that level)
+    q = (sd[i] - x) - se2[i - 1] * rcp_refined(q);
     if (fabs(q) < pivmin) q = -pivmin;
     if (q < 0.0) ++c;
   }
@@ -1065,20 +1069,20 @@ __global__ __launch_bounds__(64) void stein_kernel(const double* d, const double
     double u0, u1, u2, mult, pv;
     if (fabs(a) >= fabs(c)) {
       const double aa = (a == 0.0) ? tiny : a;
-      mult = c / aa;
+      mult = c * rcp_refined(aa);
       u0 = (fabs(aa) < tiny) ? copysign(tiny, aa) : aa;
       u1 = b; u2 = 0.0; pv = 0.0;
       a = an - mult * b;
       b = bn;
     } else {
-      mult = a / c;
+      mult = a * rcp_refined(c);
       u0 = (fabs(c) < tiny) ? copysign(tiny, c) : c;
       u1 = an; u2 = bn; pv = 1.0;
       a = b - mult * an;
       b = -mult * bn;
       const double tt = cur; cur = nxt; nxt = tt;
     }
-    sU0[SX(i)] = u0; sU1[SX(i)] = u1; sU2[SX(i)] = u2;
+    sU0[SX(i)] = 1.0 / u0; sU1[SX(i)] = u1; sU2[SX(i)] = u2;   // reciprocal: off the recurrence
     gU0[IX(i)] = u0; gU1[IX(i)] = u1; gU2[IX(i)] = u2; gLM[IX(i)] = mult; gPV[IX(i)] = pv;
     nxt -= mult * cur;
     sZ[SX(i)] = cur;
@@ -1086,7 +1090,7 @@ __global__ __launch_bounds__(64) void stein_kernel(const double* d, const double
   }
   {
     const double u0 = (fabs(a) < tiny) ? copysign(tiny, a == 0.0 ? 1.0 : a) : a;
-    sU0[SX(n - 1)] = u0; sU1[SX(n - 1)] = 0.0; sU2[SX(n - 1)] = 0.0;
+    sU0[SX(n - 1)] = 1.0 / u0; sU1[SX(n - 1)] = 0.0; sU2[SX(n - 1)] = 0.0;
     gU0[IX(n - 1)] = u0; gU1[IX(n - 1)] = 0.0; gU2[IX(n - 1)] = 0.0; gLM[IX(n - 1)] = 0.0; gPV[IX(n - 1)] = 0.0;
   }
   sZ[SX(n - 1)] = cur;
@@ -1106,7 +1110,7 @@ __global__ __launch_bounds__(64) void stein_kernel(const double* d, const double
     // backward substitution with the upper factor (bandwidth 3)
     double z1 = 0.0, z2 = 0.0, big = 0.0;
     for (int i = n - 1; i >= 0; --i) {
-      const double z = (sZ[SX(i)] - sU1[SX(i)] * z1 - sU2[SX(i)] * z2) / sU0[SX(i)];
+      const double z = (sZ[SX(i)] - sU1[SX(i)] * z1 - sU2[SX(i)] * z2) * sU0[SX(i)];
       sZ[SX(i)] = z;
       z2 = z1; z1 = z;
       big = fmax(big, fabs(z));
@@ -1131,12 +1135,18 @@ constexpr int ORM_B = 8;   // reflectors staged through LDS at a time
 
 // One wave per vector; the reflectors are staged through LDS in blocks of
 // ORM_B by the whole workgroup, so each application reads them at LDS latency.
+// Two buffers: the next block's loads are in flight while the waves apply
+// the current one.
+constexpr int ORM_PF = ORM_B * 512 / 256;   // staged entries per thread (n <= 512)
+
 __global__ __launch_bounds__(256) void ormtr_kernel(const double* Vt, const double* tau, int n, const double* Z,
                                                     int ldz, int k, double* U, int ldu) {
-  __shared__ double vs[ORM_B][2 * 512];
-  __shared__ double ts[ORM_B][2];
-  const int lane = threadIdx.x & 63;
-  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  __shared__ double2 vs[2][ORM_B][512];
+  __shared__ double2 ts[2][ORM_B];
+  const double2* Vt2 = reinterpret_cast<const double2*>(Vt);
+  const double2* tau2 = reinterpret_cast<const double2*>(tau);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int j = blockIdx.x * 4 + (tid >> 6);
   const bool active = j < k;
   constexpr int MAXQ = 8;   // n <= 512
   double ur[MAXQ], ui[MAXQ];
@@ -1146,49 +1156,72 @@ __global__ __launch_bounds__(256) void ormtr_kernel(const double* Vt, const doub
     ur[q] = (active && r < n) ? Z[(long long)r * ldz + j] : 0.0;
     ui[q] = 0.0;
   }
-  for (int ih = n - 2; ih >= 0; ih -= ORM_B) {
-    const int nb = min(ORM_B, ih + 1);        // reflectors ih, ih-1, ..., ih-nb+1
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < nb * n; idx += 256) {
-      const int b = idx / n, r = idx % n, i = ih - b;
-      const bool on = r > i;
-      vs[b][2 * r] = on ? Vt[2 * ((long long)i * n + r)] : 0.0;
-      vs[b][2 * r + 1] = on ? Vt[2 * ((long long)i * n + r) + 1] : 0.0;
-    }
-    if (threadIdx.x < nb) {
-      ts[threadIdx.x][0] = tau[2 * (ih - threadIdx.x)];
-      ts[threadIdx.x][1] = tau[2 * (ih - threadIdx.x) + 1];
-    }
-    __syncthreads();
-    if (!active) continue;
-    for (int b = 0; b < nb; ++b) {
-      const double tr = ts[b][0], ti = ts[b][1];
-      if (tr == 0.0 && ti == 0.0) continue;
-      const double* v = vs[b];
-      double dr = 0.0, di = 0.0;
+  // block starting at reflector ih holds ih, ih-1, ..., ih-nb+1; row b of a
+  // block is reflector ih-b on columns > ih-b (zero elsewhere)
+  double2 pf[ORM_PF];
+  double2 tpf = double2{0.0, 0.0};
+  auto fetch = [&](int ih) {
+    const int nb = min(ORM_B, ih + 1);
 #pragma unroll
-      for (int q = 0; q < MAXQ; ++q) {
-        const int r = lane + 64 * q;
-        if (r < n) {
-          const double a = v[2 * r], bb = v[2 * r + 1];
-          dr += a * ur[q] + bb * ui[q];          // conj(v) u
-          di += a * ui[q] - bb * ur[q];
-        }
-      }
-      dr = wave_sum(dr);
-      di = wave_sum(di);
-      // u -= tau v (v^H u)
-      const double fr = tr * dr - ti * di, fi = tr * di + ti * dr;
-#pragma unroll
-      for (int q = 0; q < MAXQ; ++q) {
-        const int r = lane + 64 * q;
-        if (r < n) {
-          const double a = v[2 * r], bb = v[2 * r + 1];
-          ur[q] -= a * fr - bb * fi;
-          ui[q] -= a * fi + bb * fr;
-        }
+    for (int u = 0; u < ORM_PF; ++u) {
+      const int idx = tid + u * 256;
+      pf[u] = double2{0.0, 0.0};
+      if (idx < nb * n) {
+        const int bb = idx / n, r = idx % n, i = ih - bb;
+        if (r > i) pf[u] = Vt2[(long long)i * n + r];
       }
     }
+    if (tid < nb) tpf = tau2[ih - tid];
+  };
+  auto commit = [&](int buf, int ih) {
+    const int nb = min(ORM_B, ih + 1);
+#pragma unroll
+    for (int u = 0; u < ORM_PF; ++u) {
+      const int idx = tid + u * 256;
+      if (idx < nb * n) vs[buf][idx / n][idx % n] = pf[u];
+    }
+    if (tid < nb) ts[buf][tid] = tpf;
+  };
+  fetch(n - 2);
+  commit(0, n - 2);
+  __syncthreads();
+  int buf = 0;
+  for (int ih = n - 2; ih >= 0; ih -= ORM_B, buf ^= 1) {
+    const int nb = min(ORM_B, ih + 1);
+    const int ihn = ih - ORM_B;
+    if (ihn >= 0) fetch(ihn);
+    if (active) {
+      for (int bb = 0; bb < nb; ++bb) {
+        const double tr = ts[buf][bb].x, ti = ts[buf][bb].y;
+        if (tr == 0.0 && ti == 0.0) continue;
+        const double2* v = vs[buf][bb];
+        double dr = 0.0, di = 0.0;
+#pragma unroll
+        for (int q = 0; q < MAXQ; ++q) {
+          const int r = lane + 64 * q;
+          if (r < n) {
+            const double2 a = v[r];
+            dr += a.x * ur[q] + a.y * ui[q];          // conj(v) u
+            di += a.x * ui[q] - a.y * ur[q];
+          }
+        }
+        dr = wave_sum(dr);
+        di = wave_sum(di);
+        // u -= tau v (v^H u)
+        const double fr = tr * dr - ti * di, fi = tr * di + ti * dr;
+#pragma unroll
+        for (int q = 0; q < MAXQ; ++q) {
+          const int r = lane + 64 * q;
+          if (r < n) {
+            const double2 a = v[r];
+            ur[q] -= a.x * fr - a.y * fi;
+            ui[q] -= a.x * fi + a.y * fr;
+          }
+        }
+      }
+    }
+    if (ihn >= 0) commit(buf ^ 1, ihn);
+    __syncthreads();
   }
   if (!active) return;
 #pragma unroll
