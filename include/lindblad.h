@@ -268,6 +268,11 @@ typedef struct lb_profile {
  * launch.  Errors: LB_ERR_ARG. */
 lb_status lindblad_profile(lb_solver* s, int32_t enable);
 
+/* As lindblad_profile, for the kernel classes whose bit is set in mask (bit
+ * c = entry c of lb_profile.name); mask 0 switches timing off.  Timing one
+ * class adds event pairs only around its launches.  Errors: LB_ERR_ARG. */
+lb_status lindblad_profile_mask(lb_solver* s, uint32_t mask);
+
 /* Read the counters accumulated since lindblad_profile (synchronises). */
 lb_status lindblad_profile_read(lb_solver* s, lb_profile* out);
 

@@ -201,8 +201,19 @@ class Solver:
                     zip_bonds=[d.zip_bonds[i] for i in range(n)],
                     discarded=[d.discarded[i] for i in range(n)])
 
-    def profile(self, enable: bool = True):
-        _check(L.load().lindblad_profile(self.h, 1 if enable else 0), "profile")
+    def profile(self, enable: bool = True, classes=None):
+        """Reset and switch live kernel timing on or off; `classes` limits it to
+        the named kernel classes (names as in profile_read)."""
+        if classes is None or not enable:
+            _check(L.load().lindblad_profile(self.h, 1 if enable else 0), "profile")
+            return
+        names = list(self.profile_read())
+        mask = 0
+        for c in classes:
+            if c not in names:
+                raise ValueError(f"unknown kernel class {c!r}; classes are {names}")
+            mask |= 1 << names.index(c)
+        _check(L.load().lindblad_profile_mask(self.h, mask), "profile")
 
     def profile_read(self) -> dict:
         p = L.LbProfile()

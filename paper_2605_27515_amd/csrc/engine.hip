@@ -215,6 +215,7 @@ struct lb_solver {
 
   // live profiling (HIP events around every launch of the step)
   bool prof_on = false;
+  uint32_t prof_mask = 0;   // classes timed while prof_on
   int cls = 0;                                // class of the launches being issued
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
@@ -271,14 +272,16 @@ struct Timed {
   int cls;
   double flop, bytes;
   size_t a = 0;
+  bool on = false;
   Timed(lb_solver* s_, int c, double f, double b) : s(s_), cls(c), flop(f), bytes(b) {
-    if (s->prof_on) {
+    on = s->prof_on && (s->prof_mask >> c & 1u);
+    if (on) {
       a = prof_event(s);
       HIPCHK(hipEventRecord(s->ev_pool[a], s->stream));
     }
   }
   ~Timed() noexcept(false) {
-    if (!s->prof_on) return;
+    if (!on) return;
     const size_t b = prof_event(s);
     HIPCHK(hipEventRecord(s->ev_pool[b], s->stream));
     s->pending.push_back({a, b, cls, flop, bytes});
@@ -1405,16 +1408,21 @@ lb_status lindblad_diagnostics(lb_solver* s, lb_diag* out) {
   }
 }
 
-lb_status lindblad_profile(lb_solver* s, int32_t enable) {
+lb_status lindblad_profile_mask(lb_solver* s, uint32_t mask) {
   try {
     if (!s) throw Fail(LB_ERR_ARG, "NULL solver");
     if (s->dev_ready) prof_flush(s);
     for (int c = 0; c < LB_PROF_CLASSES; ++c) { s->p_ms[c] = 0; s->p_flop[c] = 0; s->p_bytes[c] = 0; s->p_n[c] = 0; }
-    s->prof_on = enable != 0;
+    s->prof_mask = mask;
+    s->prof_on = mask != 0;
     return LB_OK;
   } catch (const Fail& f) {
     return fail(f);
   }
+}
+
+lb_status lindblad_profile(lb_solver* s, int32_t enable) {
+  return lindblad_profile_mask(s, enable != 0 ? 0xffffffffu : 0u);
 }
 
 lb_status lindblad_profile_read(lb_solver* s, lb_profile* out) {

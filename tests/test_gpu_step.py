@@ -124,6 +124,31 @@ def test_identity_generator_keeps_state():
     _assert_same_rho(X0, X1, m, 1e-13)
 
 
+def test_profile_limited_to_one_class():
+    """Live timing restricted to one kernel class records only that class;
+    the steps give the same state as untimed steps."""
+    api = _api()
+    m = wl.model_cat_buffer(Ra=4, Rb=3, alpha2=3.0, dt=1e-3)
+    a = api.solver_from_model(m, chi=16, chi_mu=4)
+    b = api.solver_from_model(m, chi=16, chi_mu=4)
+    a.profile(True, classes=["hetrd"])
+    a.step(2)
+    p = a.profile_read()
+    assert p["hetrd"]["launches"] > 0 and p["hetrd"]["ms"] > 0.0
+    assert all(v["launches"] == 0 for k, v in p.items() if k != "hetrd")
+    a.profile(True)
+    a.step(1)
+    p = a.profile_read()
+    assert p["hetrd"]["launches"] > 0 and p["gemm_contract"]["launches"] > 0
+    a.profile(False)
+    b.step(3)
+    _assert_same_rho(b.get_state_mps(), a.get_state_mps(), m, 1e-13)
+    with pytest.raises(ValueError):
+        a.profile(True, classes=["no_such_class"])
+    a.close()
+    b.close()
+
+
 def test_synthetic_saturated_state_sampled():
     """Synthetic state at the bond caps (the timing workload's structure) on
     the cat+buffer operators reduced to 2 x 5 bits: GPU vs oracle, FP64."""
