@@ -383,11 +383,13 @@ int read_k(lb_solver* s) {
   return k;
 }
 
-double read_disc(lb_solver* s) {
-  double d = 0.0;
-  HIPCHK(hipMemcpyAsync(&d, s->disc.p, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+// Rank and relative discarded weight of the last truncation, one wait.
+int read_k_disc(lb_solver* s, double* disc) {
+  int k = 0;
+  HIPCHK(hipMemcpyAsync(&k, s->kdev.p, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipMemcpyAsync(disc, s->disc.p, sizeof(double), hipMemcpyDeviceToHost, s->stream));
   HIPCHK(hipStreamSynchronize(s->stream));
-  return d;
+  return k;
 }
 
 int choose_splits(int M, int N, long long K) {
@@ -781,8 +783,7 @@ void zipup(lb_solver* s) {
       }
       { Timed tm(s, PC_OTHER, 0.0, 8.0 * mc); HIPCHK(lbk::truncate_rank(s->lam.d(), mc, eff_tol(s, s->cfg.tol), s->cfg.chi_mu_cap, s->kdev.i(), s->disc.d(),
                                 s->stream)); }
-      const int k = read_k(s);
-      s->discarded[0] = read_disc(s);
+      const int k = read_k_disc(s, &s->discarded[0]);
       // X_{L-1}[(a', s')][k] = A V[:, :k]
       s->cls = PC_CONTRACT;
       mm(s, n, k, mc, Asrc, asrc, (passes(s) == 2) ? mc : m, false, Vf, lbk::F64, mc, false,
@@ -803,8 +804,9 @@ void back_sweep(lb_solver* s, double tol, bool record) {
     s->cls = PC_SVDGEMM;
     double* U = left_svd(s, s->X[i].p, lbk::F64, l, m, m, passes(s) == 2, s->cap[i]);
     { Timed tm(s, PC_OTHER, 0.0, 8.0 * l); HIPCHK(lbk::truncate_rank(s->lam.d(), l, tol, s->cap[i], s->kdev.i(), s->disc.d(), s->stream)); }
-    const int k = read_k(s);
-    if (record && i < (int)s->discarded.size()) s->discarded[i] = read_disc(s);
+    double disc = 0.0;
+    const int k = (record && i < (int)s->discarded.size()) ? read_k_disc(s, &disc) : read_k(s);
+    if (record && i < (int)s->discarded.size()) s->discarded[i] = disc;
     // new X_i = S^-1 U_k^H M  (rows k)
     if (passes(s) == 2) {
       Timed tm(s, PC_OTHER, 0.0, 32.0 * k * m);

@@ -8,8 +8,9 @@
 //  * heev_kernel   Hermitian eigen-decomposition by cyclic Jacobi with the
 //                  round-robin parallel ordering (one workgroup per matrix).
 //  * tridiagonal route (hetrd_kernel, stebz_kernel, stein_kernel,
-//                  stein_groups_kernel, ormtr_kernel): Householder reduction
-//                  to real tridiagonal form, eigenvalues by Sturm-count
+//                  stein_groups_kernel, stein_unresolved_kernel, ormtr_kernel):
+//                  Householder reduction to real tridiagonal form,
+//                  eigenvalues by Sturm-count
 //                  multisection, eigenvectors by inverse iteration made
 //                  orthogonal inside groups of close eigenvalues, and the
 //                  back-transformation with the stored reflectors.
@@ -1330,22 +1331,24 @@ __device__ void sg_solve(double* zl, int n, const double* scr, int kpad, int j, 
   sg_scale(zl, n, big > 0.0 ? 1.0 / big : 1.0);
 }
 
+// Orthogonality inside groups of close eigenvalues (w[j-1] - w[j] <= theta
+// ||T||): member j is projected against the earlier resolved members of its
+// group.  Groups are disjoint, so workgroup g handles the group that starts
+// at eigenvalue g (if any); unresolved eigenvalues (|w| <= 8 n eps ||T||)
+// are left to stein_unresolved_kernel.
 __global__ __launch_bounds__(SG_NT) void stein_groups_kernel(int n, const double* w, int k, double theta,
                                                              double* Z, int ldz, const double* scr, int kpad) {
   __shared__ double zl[512], dots[512], lu[5 * 512];
   __shared__ double red[32];
   __shared__ int cols[512];
-  __shared__ unsigned char link[512];   // link[j]: w[j] belongs to the group of w[j-1]
   const double tn = fmax(fmax(fabs(w[0]), fabs(w[n - 1])), 1e-300);
   const double gap = theta * tn;
   const double floor_abs = 8.0 * n * 2.2e-16 * tn;
-  for (int j = threadIdx.x; j < k; j += SG_NT) link[j] = (j > 0 && w[j - 1] - w[j] <= gap) ? 1 : 0;
-  __syncthreads();
-  // 1. resolved members of groups, against the earlier members of their group
-  int start = 0;
-  for (int j = 1; j < k; ++j) {
-    if (!link[j]) start = j;
-    if (start == j || fabs(w[j]) <= floor_abs) continue;
+  auto linked = [&](int j) { return j > 0 && j < k && w[j - 1] - w[j] <= gap; };
+  const int start = blockIdx.x;
+  if (linked(start) || !linked(start + 1)) return;   // not the first of a group of two or more
+  for (int j = start + 1; linked(j); ++j) {
+    if (fabs(w[j]) <= floor_abs) continue;
     int s0 = start;
     while (s0 < j && fabs(w[s0]) <= floor_abs) ++s0;   // (not reached for a PSD matrix)
     for (int r = threadIdx.x; r < n; r += SG_NT) zl[r] = Z[(long long)r * ldz + j];
@@ -1375,10 +1378,19 @@ __global__ __launch_bounds__(SG_NT) void stein_groups_kernel(int n, const double
     for (int r = threadIdx.x; r < n; r += SG_NT) Z[(long long)r * ldz + j] = zl[r];
     __syncthreads();
   }
-  // 2. unresolved eigenvalues: against every resolved vector and the earlier
-  //    unresolved ones
+}
+
+// Unresolved eigenvalues: against every resolved vector and the earlier
+// unresolved ones (after stein_groups_kernel has finished the groups).
+__global__ __launch_bounds__(SG_NT) void stein_unresolved_kernel(int n, const double* w, int k, double* Z, int ldz) {
+  __shared__ double zl[512], dots[512];
+  __shared__ double red[32];
+  __shared__ int cols[512];
+  const double tn = fmax(fmax(fabs(w[0]), fabs(w[n - 1])), 1e-300);
+  const double floor_abs = 8.0 * n * 2.2e-16 * tn;
   int nres = 0;
   for (int c = 0; c < k; ++c) nres += fabs(w[c]) > floor_abs ? 1 : 0;
+  if (nres == k) return;
   if (threadIdx.x == 0) {
     int q = 0;
     for (int c = 0; c < k; ++c)
@@ -1449,7 +1461,9 @@ hipError_t trid_vectors(int n, const TridWork& t, const double* w, int kvec, hip
                      t.scr, t.kpad);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(stein_groups_kernel, dim3(1), dim3(SG_NT), 0, s, n, w, kvec, 1e-8, t.Z, n, t.scr, t.kpad);
+  hipLaunchKernelGGL(stein_groups_kernel, dim3(kvec), dim3(SG_NT), 0, s, n, w, kvec, 1e-8, t.Z, n, t.scr, t.kpad);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(stein_unresolved_kernel, dim3(1), dim3(SG_NT), 0, s, n, w, kvec, t.Z, n);
   return hipGetLastError();
 }
 
