@@ -400,6 +400,16 @@ int choose_splits(int M, int N, long long K) {
   return std::max(1, std::min(sp, 64));
 }
 
+// Hermitian products compute tiles on and above the diagonal only; split K
+// so that the workgroups fill the 256 CUs once (a second, partly filled round
+// costs a whole round of the MFMA-bound tiles)
+int choose_splits_herm(int N, long long K) {
+  const int t = (N + 63) / 64, tiles = t * (t + 1) / 2;
+  if (tiles >= 256 || K < 512) return 1;
+  int sp = (int)std::min<long long>(256 / tiles, K / 256);
+  return std::max(1, std::min(sp, 64));
+}
+
 // Gram G = A A^H of the rows of A (n x m, row stride lda), FP64 output n x n.
 void gram_rows(lb_solver* s, const void* A, Prec pa, int n, long long m, long long lda, double* G) {
   Gemm g;
@@ -408,7 +418,8 @@ void gram_rows(lb_solver* s, const void* A, Prec pa, int n, long long m, long lo
   g.B = A; g.sb_k = 1; g.sb_n = lda; g.conjB = 1; g.pb = pa;
   g.C = G; g.sc_m = n; g.sc_n = 1; g.pc = lbk::F64;
   g.compute = lbk::F64;
-  g.splits = choose_splits(n, n, m);
+  g.herm = 1;
+  g.splits = choose_splits_herm(n, m);
   g.ws = s->ws.p;
   Timed tm(s, PC_GRAM, 8.0 * n * n * (double)m, (double)n * m * (pa == lbk::F64 ? 16 : 8) + 16.0 * n * n);
   check_gemm(lbk::gemm(g, s->stream), "gram_rows");
@@ -422,7 +433,8 @@ void gram_cols(lb_solver* s, const void* A, Prec pa, int n, int m, long long lda
   g.B = A; g.sb_k = lda; g.sb_n = 1; g.pb = pa;
   g.C = G; g.sc_m = m; g.sc_n = 1; g.pc = lbk::F64;
   g.compute = lbk::F64;
-  g.splits = choose_splits(m, m, n);
+  g.herm = 1;
+  g.splits = choose_splits_herm(m, n);
   g.ws = s->ws.p;
   Timed tm(s, PC_GRAM, 8.0 * m * m * (double)n, (double)n * m * (pa == lbk::F64 ? 16 : 8) + 16.0 * m * m);
   check_gemm(lbk::gemm(g, s->stream), "gram_cols");

@@ -25,6 +25,10 @@ struct Gemm {
   Prec compute = F64;
   double alpha_re = 1.0, alpha_im = 0.0, beta_re = 0.0, beta_im = 0.0;
   void* ws = nullptr;
+  // herm = 1: the product is Hermitian (op(B) = op(A)^H, M == N, alpha real,
+  // beta 0); only the 64 x 64 tiles on and above the diagonal are computed
+  // and the others are written as their conjugate transposes
+  int herm = 0;
 };
 hipError_t gemm(const Gemm& g, hipStream_t stream);
 

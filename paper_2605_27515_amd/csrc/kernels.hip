@@ -39,7 +39,7 @@ __device__ inline f4 mfma(float a, float b, f4 c) {
 constexpr int BM = 64, BN = 64, BK = 16, PAD = 4, NT = 256;
 
 struct GemmK {
-  int M, N, K, batch, splits, kchunk;
+  int M, N, K, batch, splits, kchunk, herm;
   const void* A; long long sa_m, sa_k, sa_b; int conjA;
   const void* B; long long sb_k, sb_n, sb_b; int conjB;
   void* C; long long sc_m, sc_n, sc_b;
@@ -55,7 +55,14 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmK g) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int tiles_n = (g.N + BN - 1) / BN;
-  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+  int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+  if (g.herm) {
+    // tiles on and above the diagonal, row by row
+    int t = blockIdx.x;
+    tm = 0;
+    while (t >= tiles_n - tm) { t -= tiles_n - tm; ++tm; }
+    tn = tm + t;
+  }
   const int i0 = tm * BM, j0 = tn * BN;
   const int z = blockIdx.y;
   const int b = z / g.splits, split = z % g.splits;
@@ -186,6 +193,11 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmK g) {
           }
           C[off] = (TO)orr;
           C[off + 1] = (TO)oi;
+          if (g.herm && tm < tn) {
+            const long long mo = 2 * ((long long)j * g.sc_m + (long long)i * g.sc_n);
+            C[mo] = (TO)orr;
+            C[mo + 1] = (TO)(-oi);
+          }
         }
       }
 }
@@ -199,6 +211,7 @@ __global__ void splitk_reduce(GemmK g) {
     const int b = (int)(e / ((long long)g.M * g.N));
     const long long ij = e % ((long long)g.M * g.N);
     const int i = (int)(ij / g.N), j = (int)(ij % g.N);
+    if (g.herm && i / BM > j / BN) continue;   // written as the mirror of (j, i)
     double vr = 0.0, vi = 0.0;
     for (int s = 0; s < g.splits; ++s) {
       const long long off = 2 * ((((long long)b * g.splits + s) * g.M + i) * g.N + j);
@@ -215,12 +228,18 @@ __global__ void splitk_reduce(GemmK g) {
     }
     C[off] = (TO)orr;
     C[off + 1] = (TO)oi;
+    if (g.herm && i / BM < j / BN) {
+      const long long mo = 2 * ((long long)j * g.sc_m + (long long)i * g.sc_n);
+      C[mo] = (TO)orr;
+      C[mo + 1] = (TO)(-oi);
+    }
   }
 }
 
 template <typename TA, typename TB, typename TC, typename TO>
 static hipError_t launch_gemm(const GemmK& k, hipStream_t s) {
-  const int tiles = ((k.M + BM - 1) / BM) * ((k.N + BN - 1) / BN);
+  const int tn = (k.N + BN - 1) / BN;
+  const int tiles = k.herm ? tn * (tn + 1) / 2 : ((k.M + BM - 1) / BM) * tn;
   dim3 grid(tiles, k.batch * k.splits);
   hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, TO>), grid, dim3(NT), 0, s, k);
   hipError_t e = hipGetLastError();
@@ -261,6 +280,9 @@ hipError_t gemm(const Gemm& g, hipStream_t s) {
   k.C = g.C; k.sc_m = g.sc_m; k.sc_n = g.sc_n; k.sc_b = g.sc_b;
   k.ar = g.alpha_re; k.ai = g.alpha_im; k.br = g.beta_re; k.bi = g.beta_im;
   k.ws = g.ws;
+  k.herm = g.herm;
+  if (g.herm && (g.M != g.N || g.alpha_im != 0.0 || g.beta_re != 0.0 || g.beta_im != 0.0))
+    return hipErrorInvalidValue;
   return g.pa == F64 ? pick_b<double>(k, g.pb, g.compute, g.pc, s)
                      : pick_b<float>(k, g.pb, g.compute, g.pc, s);
 }
