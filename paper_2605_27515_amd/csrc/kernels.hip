@@ -37,6 +37,7 @@ __device__ inline f4 mfma(float a, float b, f4 c) {
 }
 
 constexpr int BM = 64, BN = 64, BK = 16, PAD = 4, NT = 256;
+constexpr int GEPT = BM * BK / NT;   // tile entries staged per thread
 
 struct GemmK {
   int M, N, K, batch, splits, kchunk, herm;
@@ -76,11 +77,11 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmK g) {
   const TC sa = g.conjA ? TC(-1) : TC(1);
   const TC sb = g.conjB ? TC(-1) : TC(1);
 
-  TC ra_r[4], ra_i[4], rb_r[4], rb_i[4];
+  TC ra_r[GEPT], ra_i[GEPT], rb_r[GEPT], rb_i[GEPT];
 
   auto load_tiles = [&](int k0) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < GEPT; ++e) {
       const int idx = tid + e * NT;
       int ii, kk;
       if (a_kfast) { ii = idx / BK; kk = idx % BK; } else { kk = idx / BM; ii = idx % BM; }
@@ -94,7 +95,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmK g) {
       ra_r[e] = vr; ra_i[e] = vi;
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < GEPT; ++e) {
       const int idx = tid + e * NT;
       int jj, kk;
       if (b_nfast) { kk = idx / BN; jj = idx % BN; } else { jj = idx / BK; kk = idx % BK; }
@@ -110,14 +111,14 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmK g) {
   };
   auto store_tiles = [&]() {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < GEPT; ++e) {
       const int idx = tid + e * NT;
       int ii, kk;
       if (a_kfast) { ii = idx / BK; kk = idx % BK; } else { kk = idx / BM; ii = idx % BM; }
       As_r[kk][ii] = ra_r[e]; As_i[kk][ii] = ra_i[e];
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < GEPT; ++e) {
       const int idx = tid + e * NT;
       int jj, kk;
       if (b_nfast) { kk = idx / BN; jj = idx % BN; } else { jj = idx / BK; kk = idx % BK; }
