@@ -208,7 +208,13 @@ struct lb_solver {
   size_t site_cap = 0;        // complex elements per site buffer
 
   // workspace
-  DevBuf C, P, T, Bm, G, G2, U2, Uf, U0, V, lam, lam2, ws, kdev, disc, tau, flag, info, scratch, ework;
+  DevBuf C, P, T, Bm, G, G2, U2, Uf, U0, V, lam, lam2, ws, flag, info, scratch, ework;
+  // the per-site read-backs (truncation rank, discarded weight) and tau land
+  // in pinned host memory that the kernels write through its device mapping,
+  // so a read-back is one stream wait and no copy; kept until destruction
+  struct HostIO { int32_t k; int32_t pad; double disc; double tau; };
+  HostIO* hio = nullptr;       // host view
+  HostIO* hio_dev = nullptr;   // device view of the same memory
   size_t ws_bytes = 0;
   int n_max = 0;
   long long m_max = 0;
@@ -377,19 +383,15 @@ void check_gemm(hipError_t e, const char* what) {
 }
 
 int read_k(lb_solver* s) {
-  int k = 0;
-  HIPCHK(hipMemcpyAsync(&k, s->kdev.p, sizeof(int), hipMemcpyDeviceToHost, s->stream));
   HIPCHK(hipStreamSynchronize(s->stream));
-  return k;
+  return *reinterpret_cast<volatile int32_t*>(&s->hio->k);
 }
 
 // Rank and relative discarded weight of the last truncation, one wait.
 int read_k_disc(lb_solver* s, double* disc) {
-  int k = 0;
-  HIPCHK(hipMemcpyAsync(&k, s->kdev.p, sizeof(int), hipMemcpyDeviceToHost, s->stream));
-  HIPCHK(hipMemcpyAsync(disc, s->disc.p, sizeof(double), hipMemcpyDeviceToHost, s->stream));
   HIPCHK(hipStreamSynchronize(s->stream));
-  return k;
+  *disc = *reinterpret_cast<volatile double*>(&s->hio->disc);
+  return *reinterpret_cast<volatile int32_t*>(&s->hio->k);
 }
 
 int choose_splits(int M, int N, long long K) {
@@ -627,7 +629,7 @@ void alloc_workspace(lb_solver* s) {
   s->lam.alloc(w.lam, st);
   s->lam2.alloc(w.lam, st);
   s->ws.alloc(w.ws, st);
-  for (DevBuf* b : {&s->kdev, &s->disc, &s->tau, &s->flag, &s->info}) b->alloc(WorkPlan::kSmall, st);
+  for (DevBuf* b : {&s->flag, &s->info}) b->alloc(WorkPlan::kSmall, st);
   s->scratch.alloc(w.scratch, st);
   HIPCHK(hipMemsetAsync(s->flag.p, 0, 64, s->stream));
 }
@@ -648,7 +650,7 @@ size_t footprint_bytes(const lb_solver* s) {
   const WorkPlan w = work_plan(s, cap);
   size_t t = (size_t)(s->L + 1) * size_class(site_cap * 16);
   t += size_class(w.C) + size_class(w.P) + size_class(w.T) + 5 * size_class(w.nn) + size_class(w.ework);
-  t += 2 * size_class(w.wide) + 2 * size_class(w.lam) + size_class(w.ws) + 5 * size_class(WorkPlan::kSmall);
+  t += 2 * size_class(w.wide) + 2 * size_class(w.lam) + size_class(w.ws) + 2 * size_class(WorkPlan::kSmall);
   t += size_class(w.scratch);
   for (const lb::Site& x : s->kraus_dev) {
     const size_t e = (size_t)x.l * 4 * x.r;
@@ -667,7 +669,7 @@ void release_device(lb_solver* s) {
   s->X.clear();
   s->Xspare.release();
   for (DevBuf* b : {&s->C, &s->P, &s->T, &s->Bm, &s->G, &s->G2, &s->U2, &s->Uf, &s->U0, &s->V, &s->lam,
-                    &s->lam2, &s->ws, &s->kdev, &s->disc, &s->tau, &s->flag, &s->info, &s->scratch, &s->ework})
+                    &s->lam2, &s->ws, &s->flag, &s->info, &s->scratch, &s->ework})
     b->release();
   for (auto& b : s->W.d64) b.release();
   for (auto& b : s->W.d32) b.release();
@@ -690,6 +692,10 @@ void ensure_device(lb_solver* s) {
   } else {
     HIPCHK(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
     s->own_stream = true;
+  }
+  if (!s->hio) {
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&s->hio), sizeof(lb_solver::HostIO), hipHostMallocMapped));
+    HIPCHK(hipHostGetDevicePointer(reinterpret_cast<void**>(&s->hio_dev), s->hio, 0));
   }
   s->dev_ready = true;
 }
@@ -755,7 +761,7 @@ void zipup(lb_solver* s) {
     if (i < L - 1) {
       s->cls = PC_SVDGEMM;
       double* U = left_svd(s, s->T.p, pw, n, m, m, passes(s) == 2, zc);
-      { Timed tm(s, PC_OTHER, 0.0, 8.0 * n); HIPCHK(lbk::truncate_rank(s->lam.d(), n, tolz, zc, s->kdev.i(), s->disc.d(), s->stream)); }
+      { Timed tm(s, PC_OTHER, 0.0, 8.0 * n); HIPCHK(lbk::truncate_rank(s->lam.d(), n, tolz, zc, &s->hio_dev->k, &s->hio_dev->disc, s->stream)); }
       const int k = read_k(s);
       // new site X_i[(a', s')][k] = U[:, :k]
       { Timed tm(s, PC_OTHER, 0.0, 32.0 * n * k); HIPCHK(lbk::copy_cols(U, n, s->X[i].d(), k, n, k, nullptr, s->stream)); }
@@ -793,7 +799,7 @@ void zipup(lb_solver* s) {
         Asrc = Bc;
         asrc = lbk::F64;
       }
-      { Timed tm(s, PC_OTHER, 0.0, 8.0 * mc); HIPCHK(lbk::truncate_rank(s->lam.d(), mc, eff_tol(s, s->cfg.tol), s->cfg.chi_mu_cap, s->kdev.i(), s->disc.d(),
+      { Timed tm(s, PC_OTHER, 0.0, 8.0 * mc); HIPCHK(lbk::truncate_rank(s->lam.d(), mc, eff_tol(s, s->cfg.tol), s->cfg.chi_mu_cap, &s->hio_dev->k, &s->hio_dev->disc,
                                 s->stream)); }
       const int k = read_k_disc(s, &s->discarded[0]);
       // X_{L-1}[(a', s')][k] = A V[:, :k]
@@ -815,7 +821,7 @@ void back_sweep(lb_solver* s, double tol, bool record) {
     const long long m = 2LL * r;
     s->cls = PC_SVDGEMM;
     double* U = left_svd(s, s->X[i].p, lbk::F64, l, m, m, passes(s) == 2, s->cap[i]);
-    { Timed tm(s, PC_OTHER, 0.0, 8.0 * l); HIPCHK(lbk::truncate_rank(s->lam.d(), l, tol, s->cap[i], s->kdev.i(), s->disc.d(), s->stream)); }
+    { Timed tm(s, PC_OTHER, 0.0, 8.0 * l); HIPCHK(lbk::truncate_rank(s->lam.d(), l, tol, s->cap[i], &s->hio_dev->k, &s->hio_dev->disc, s->stream)); }
     double disc = 0.0;
     const int k = (record && i < (int)s->discarded.size()) ? read_k_disc(s, &disc) : read_k(s);
     if (record && i < (int)s->discarded.size()) s->discarded[i] = disc;
@@ -844,7 +850,7 @@ void back_sweep(lb_solver* s, double tol, bool record) {
 }
 
 void normalize_center(lb_solver* s) {
-  { Timed tm(s, PC_OTHER, 8.0 * s->chi[1], 64.0 * s->chi[1]); HIPCHK(lbk::normalize(s->X[0].d(), 2LL * s->chi[1], s->tau.d(), s->flag.i(), s->stream)); }
+  { Timed tm(s, PC_OTHER, 8.0 * s->chi[1], 64.0 * s->chi[1]); HIPCHK(lbk::normalize(s->X[0].d(), 2LL * s->chi[1], &s->hio_dev->tau, s->flag.i(), s->stream)); }
 }
 
 void step_once(lb_solver* s) {
@@ -852,9 +858,8 @@ void step_once(lb_solver* s) {
   zipup(s);
   back_sweep(s, eff_tol(s, s->cfg.tol), true);
   normalize_center(s);
-  double tau = 1.0;
-  HIPCHK(hipMemcpyAsync(&tau, s->tau.p, sizeof(double), hipMemcpyDeviceToHost, s->stream));
   HIPCHK(hipStreamSynchronize(s->stream));
+  const double tau = *reinterpret_cast<volatile double*>(&s->hio->tau);
   s->last_tau = tau;
   s->max_defect = std::max(s->max_defect, std::fabs(tau - 1.0));
   s->t += s->dt;
@@ -961,6 +966,7 @@ void lindblad_destroy(lb_solver* s) {
   hipStream_t st = s->stream;
   bool own = s->own_stream;
   for (auto e : s->ev_pool) (void)hipEventDestroy(e);
+  if (s->hio) (void)hipHostFree(s->hio);
   delete s;
   if (own && st) (void)hipStreamDestroy(st);
 }
