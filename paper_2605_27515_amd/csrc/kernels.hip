@@ -675,6 +675,12 @@ __device__ inline double dpp_f64(double old, double src) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// 1/q from the hardware reciprocal refined by one Newton step (a few ulps)
+__device__ inline double rcp_refined(double q) {
+  const double r0 = __builtin_amdgcn_rcp(q);
+  return fma(r0, fma(-q, r0, 1.0), r0);
+}
+
 __device__ inline double read_lane(double v, int l) {
   const unsigned long long b = (unsigned long long)__double_as_longlong(v);
   const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
@@ -867,10 +873,11 @@ __device__ inline void trd_reflector(double2 alpha, double xn2, double& beta, do
   tr = 0.0; ti = 0.0; beta = alpha.x; scale = double2{0.0, 0.0};
   if (xn2 == 0.0 && alpha.y == 0.0) return;
   beta = -copysign(sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2), alpha.x);
-  const double ib = 1.0 / beta;
+  // the reciprocals to a few ulps keep H unitary to rounding
+  const double ib = rcp_refined(beta);
   tr = (beta - alpha.x) * ib;
   ti = -alpha.y * ib;
-  const double pr = alpha.x - beta, pi = alpha.y, iden = 1.0 / (pr * pr + pi * pi);
+  const double pr = alpha.x - beta, pi = alpha.y, iden = rcp_refined(pr * pr + pi * pi);
   scale = double2{pr * iden, -pi * iden};
 }
 
@@ -970,12 +977,6 @@ __global__ __launch_bounds__(TRD_NT) void hetrd_kernel(double2* G, int ldg, int 
     trd_pass<PARTS, false>(G, ldg, n, j, sh, vc, vn, reg, Vt + (long long)(j + 1) * n);
     lds_barrier();
   }
-}
-
-// 1/q from the hardware reciprocal refined by one Newton step (a few ulps)
-__device__ inline double rcp_refined(double q) {
-  const double r0 = __builtin_amdgcn_rcp(q);
-  return fma(r0, fma(-q, r0, 1.0), r0);
 }
 
 __device__ inline int sturm_count(const double* sd, const double* se2, int n, double x, double pivmin) {
