@@ -711,6 +711,18 @@ __device__ inline double wave_max(double v) {
   return read_lane(v, 63);
 }
 
+// Sum over aligned groups of G adjacent lanes (G = 1, 2, 4, 8, 16), result in
+// every lane of the group: butterflies inside quads, then half-row and row
+// mirrors.
+template <int G>
+__device__ inline double group_sum(double v) {
+  if constexpr (G >= 2) v += dpp_f64<0xB1, 0xF>(0.0, v);    // quad_perm [1,0,3,2]
+  if constexpr (G >= 4) v += dpp_f64<0x4E, 0xF>(0.0, v);    // quad_perm [2,3,0,1]
+  if constexpr (G >= 8) v += dpp_f64<0x141, 0xF>(0.0, v);   // row_half_mirror
+  if constexpr (G >= 16) v += dpp_f64<0x140, 0xF>(0.0, v);  // row_mirror
+  return v;
+}
+
 template <int NT>
 __device__ inline double block_sum(double v, double* red) {
   v = wave_sum(v);
@@ -744,9 +756,13 @@ __device__ inline void lds_barrier() {
 // reflectors as rows of Vt (n x n complex, row j holds v_j on columns
 // j+1..n-1).
 //
-// One workgroup of 1024 threads.  Thread t owns column c = t % P (P = 1024 /
-// PARTS, the power of two >= n) and the rows R with (n-1-R) % PARTS == t / P;
-// its q-th row from the bottom, R = n-1-t/P-q*PARTS, sits in a register for
+// One workgroup of 1024 threads.  Thread t owns one of the P = 1024 / PARTS
+// columns (the power of two >= n) and every PARTS-th row of it: column t % P
+// and row part rho = t / P, so that a wave covers 64 adjacent columns of a
+// row, or (when registers and band hold every row) column t / PARTS and rho =
+// t % PARTS, so that the parts of a column are adjacent lanes and fold their
+// products by DPP.  The rows are R with (n-1-R) % PARTS == rho; the q-th from
+// the bottom, R = n-1-rho-q*PARTS, sits in a register for
 // q < TRD_QR, in an LDS band for q < TRD_QR + QL and in G above that, so
 // the bottom rows of the trailing block never leave the chip (all of it for
 // n <= 128).  No thread touches another thread's entries, so the barriers
@@ -764,17 +780,22 @@ constexpr int TRD_NT = 1024;
 constexpr int TRD_QR = 10;   // rows per thread in registers
 
 // LDS layout for P = 1024 / PARTS columns: vectors by global row, the
-// per-thread partial products and as many band rows per thread (QL) as fit
+// folded product and as many band rows per thread (QL) as fit
 // in the 160 KB of the CU.
 template <int PARTS>
 struct TrdShared {
   static constexpr int P = TRD_NT / PARTS;
-  static constexpr int QL = (160 * 1024 - 1024 - 16 * (5 * P + TRD_NT)) / (16 * TRD_NT);
+  // interleaved: the PARTS threads of a column are adjacent lanes and fold
+  // their partial products by DPP (used when registers and band hold every
+  // row: the global rows want a wave on 64 adjacent columns of one row)
+  static constexpr int YP = (TRD_QR + 9) * PARTS >= P ? P : TRD_NT;
+  static constexpr int QL = (160 * 1024 - 1024 - 16 * (5 * P + YP)) / (16 * TRD_NT);
+  static constexpr bool INTER = YP == P;
   double2 v[2][P];            // v_j, v_{j+1} by global row
   double2 w[P];               // w_j
   double2 y[P];               // y_j, then the updated first column
   double2 fc[P];              // first column of the next block after the pass
-  double2 yp[TRD_NT];         // per-thread partial sums of the product
+  double2 yp[YP];             // the pass's product y_{j+1}: by column, or partial sums by thread
   double2 band[QL * TRD_NT];
 };
 
@@ -800,7 +821,9 @@ template <int PARTS, bool FIRST>
 __device__ inline void trd_pass(double2* G, int ldg, int n, int j, TrdShared<PARTS>& sh, const double2* vc,
                                 const double2* vn, double2 (&reg)[TRD_QR], double2* vt_row) {
   constexpr int P = TRD_NT / PARTS, QL = TrdShared<PARTS>::QL;
-  const int tid = threadIdx.x, c = tid % P, rho = tid / P;
+  constexpr bool INTER = TrdShared<PARTS>::INTER;
+  const int tid = threadIdx.x;
+  const int c = INTER ? tid / PARTS : tid % P, rho = INTER ? tid % PARTS : tid / P;
   const int lo = j + 2;
   double ar = 0.0, ai = 0.0;
   if (c >= lo && c < n) {
@@ -861,7 +884,14 @@ __device__ inline void trd_pass(double2* G, int ldg, int n, int j, TrdShared<PAR
     }
     if (rho == 0) vt_row[c] = vn[c];
   }
-  sh.yp[tid] = double2{ar, ai};
+  if constexpr (INTER) {
+    // y'_c: the PARTS partial sums of column c sit in adjacent lanes
+    ar = group_sum<PARTS>(ar);
+    ai = group_sum<PARTS>(ai);
+    if (rho == 0) sh.yp[c] = double2{ar, ai};
+  } else {
+    sh.yp[tid] = double2{ar, ai};
+  }
 }
 
 // Reflector from x = (alpha, x_2, ...) with xn2 = sum |x_i|^2 beyond alpha:
@@ -886,7 +916,6 @@ __device__ inline double2 cmul(double2 a, double2 b) { return double2{a.x * b.x 
 template <int PARTS>
 __global__ __launch_bounds__(TRD_NT) void hetrd_kernel(double2* G, int ldg, int n, double* d, double* e,
                                                        double2* tau, double2* Vt) {
-  constexpr int P = TRD_NT / PARTS;
   __shared__ TrdShared<PARTS> sh;
   const int tid = threadIdx.x, lane = tid & 63;
   const bool w0 = tid < 64;
@@ -928,8 +957,13 @@ __global__ __launch_bounds__(TRD_NT) void hetrd_kernel(double2* G, int ldg, int 
       double2 y0 = double2{0.0, 0.0};
       for (int R = j + 1 + lane; R < n; R += 64) {
         double2 y = double2{0.0, 0.0};
+        if constexpr (TrdShared<PARTS>::INTER) {
+          y = sh.yp[R];
+        } else {
+          constexpr int P = TRD_NT / PARTS;
 #pragma unroll 4
-        for (int p = 0; p < PARTS; ++p) { const double2 t = sh.yp[p * P + R]; y.x += t.x; y.y += t.y; }
+          for (int p = 0; p < PARTS; ++p) { const double2 t = sh.yp[p * P + R]; y.x += t.x; y.y += t.y; }
+        }
         sh.y[R] = y;
         if (R == j + 1 + lane) y0 = y;
         const double2 v = vc[R];
