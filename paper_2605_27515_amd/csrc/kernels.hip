@@ -77,7 +77,10 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmK g) {
   const TC sa = g.conjA ? TC(-1) : TC(1);
   const TC sb = g.conjB ? TC(-1) : TC(1);
 
-  TC ra_r[GEPT], ra_i[GEPT], rb_r[GEPT], rb_i[GEPT];
+  // raw operands of the next K slice: converted (and conjugated) only when
+  // stored to LDS, so the loads stay in flight under the current slice's MFMAs
+  TA ra_r[GEPT], ra_i[GEPT];
+  TB rb_r[GEPT], rb_i[GEPT];
 
   auto load_tiles = [&](int k0) {
 #pragma unroll
@@ -86,11 +89,11 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmK g) {
       int ii, kk;
       if (a_kfast) { ii = idx / BK; kk = idx % BK; } else { kk = idx / BM; ii = idx % BM; }
       const int gi = i0 + ii, gk = k0 + kk;
-      TC vr = 0, vi = 0;
+      TA vr = 0, vi = 0;
       if (gi < g.M && gk < ke) {
         const long long off = 2 * ((long long)gi * g.sa_m + (long long)gk * g.sa_k);
-        vr = (TC)A[off];
-        vi = sa * (TC)A[off + 1];
+        vr = A[off];
+        vi = A[off + 1];
       }
       ra_r[e] = vr; ra_i[e] = vi;
     }
@@ -100,11 +103,11 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmK g) {
       int jj, kk;
       if (b_nfast) { kk = idx / BN; jj = idx % BN; } else { jj = idx / BK; kk = idx % BK; }
       const int gj = j0 + jj, gk = k0 + kk;
-      TC vr = 0, vi = 0;
+      TB vr = 0, vi = 0;
       if (gj < g.N && gk < ke) {
         const long long off = 2 * ((long long)gk * g.sb_k + (long long)gj * g.sb_n);
-        vr = (TC)B[off];
-        vi = sb * (TC)B[off + 1];
+        vr = B[off];
+        vi = B[off + 1];
       }
       rb_r[e] = vr; rb_i[e] = vi;
     }
@@ -115,14 +118,14 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmK g) {
       const int idx = tid + e * NT;
       int ii, kk;
       if (a_kfast) { ii = idx / BK; kk = idx % BK; } else { kk = idx / BM; ii = idx % BM; }
-      As_r[kk][ii] = ra_r[e]; As_i[kk][ii] = ra_i[e];
+      As_r[kk][ii] = (TC)ra_r[e]; As_i[kk][ii] = sa * (TC)ra_i[e];
     }
 #pragma unroll
     for (int e = 0; e < GEPT; ++e) {
       const int idx = tid + e * NT;
       int jj, kk;
       if (b_nfast) { kk = idx / BN; jj = idx % BN; } else { jj = idx / BK; kk = idx % BK; }
-      Bs_r[kk][jj] = rb_r[e]; Bs_i[kk][jj] = rb_i[e];
+      Bs_r[kk][jj] = (TC)rb_r[e]; Bs_i[kk][jj] = sb * (TC)rb_i[e];
     }
   };
 
