@@ -36,8 +36,13 @@ import sys
 import time
 
 # hardware queues for the overlapping solves of the serving leg (HIP reads
-# this when it initialises, so it is set before torch is imported)
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+# this when it initialises, so it is set before torch is imported): at least
+# 16, one per slot (HIP's default is 4, which serialises the slots' streams)
+try:
+    _hwq = int(os.environ.get("GPU_MAX_HW_QUEUES", "0"))
+except ValueError:
+    _hwq = 0
+os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, max(_hwq, 16)))
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
