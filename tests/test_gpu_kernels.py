@@ -42,7 +42,7 @@ def test_zgemm_fp32(shape):
 
 
 @pytest.mark.parametrize("method", ["jacobi", "tridiag"])
-@pytest.mark.parametrize("n", [1, 2, 7, 16, 33, 64, 100, 128, 256, 512])
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 16, 33, 64, 65, 100, 128, 129, 256, 257, 300, 512])
 def test_heev_parity(n, method):
     api = _api()
     if method == "jacobi" and n > 128:
