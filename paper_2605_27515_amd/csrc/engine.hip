@@ -461,7 +461,7 @@ void eig_jacobi(lb_solver* s, double* G, int n, double* lam) {
 void eig_trid(lb_solver* s, double* G, int n, double* lam, double* U, int kvec) {
   kvec = std::min(kvec, n);
   const double N = n;
-  const lbk::TridWork tw = lbk::trid_work(s->ework.d(), n, kvec);
+  const lbk::TridWork tw = lbk::trid_work(s->ework.d(), n);
   {
     // complex Hermitian Householder tridiagonalisation: 16/3 n^3 real flops;
     // reads the matrix once, writes the reflectors and the tridiagonal

@@ -55,10 +55,9 @@ size_t heev_tridiag_work_doubles(int n);
 
 // The same four stages, callable one by one (for per-stage timing).
 struct TridWork {
-  double *d, *e, *tau, *Vt, *Z, *scr;
-  int kpad;
+  double *d, *e, *tau, *Vt, *Z;
 };
-TridWork trid_work(double* work, int n, int kvec);
+TridWork trid_work(double* work, int n);
 hipError_t trid_reduce(double* G, int ldg, int n, const TridWork& t, hipStream_t stream);
 hipError_t trid_eigenvalues(int n, const TridWork& t, double* w, hipStream_t stream);
 hipError_t trid_vectors(int n, const TridWork& t, const double* w, int kvec, hipStream_t stream);

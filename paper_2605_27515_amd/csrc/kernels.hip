@@ -1085,17 +1085,46 @@ __device__ inline double hash_unit(unsigned int a, unsigned int b) {
   return ((double)(h & 0xFFFFFF) / 16777216.0) * 2.0 - 1.0;
 }
 
-// Solves of inverse iteration after the first (the first starts from a hashed
-// vector and amplifies the wanted direction by ~1 / (eps ||T||)).
-constexpr int STEIN_EXTRA = 0;
+// One step of the pivoted LU of the tridiagonal T - lam I: (a, b) is row i's
+// diagonal and superdiagonal after the elimination so far, c = e_i the entry
+// below a, (an, bn) row i+1's diagonal and superdiagonal.  Returns row i's
+// factors (a pivot below tiny replaced by +-tiny), the multiplier and whether
+// the two rows were exchanged; leaves row i+1's reduced (a, b).
+struct SteinLu { double u0, u1, u2, mult; bool swap; };
+__device__ inline SteinLu stein_lu_step(double& a, double& b, double c, double an, double bn, double tiny) {
+  SteinLu f;
+  if (fabs(a) >= fabs(c)) {
+    const double aa = (a == 0.0) ? tiny : a;
+    f.mult = c * rcp_refined(aa);
+    f.u0 = (fabs(aa) < tiny) ? copysign(tiny, aa) : aa;
+    f.u1 = b; f.u2 = 0.0; f.swap = false;
+    a = an - f.mult * b;
+    b = bn;
+  } else {
+    f.mult = a * rcp_refined(c);
+    f.u0 = (fabs(c) < tiny) ? copysign(tiny, c) : c;
+    f.u1 = an; f.u2 = bn; f.swap = true;
+    a = b - f.mult * an;
+    b = -f.mult * bn;
+  }
+  return f;
+}
+__device__ inline double stein_last_pivot(double a, double tiny) {
+  return (fabs(a) < tiny) ? copysign(tiny, a == 0.0 ? 1.0 : a) : a;
+}
+// eps ||T||_inf of the tridiagonal (d, e): the pivot floor of the factorisation
+__device__ inline double stein_tiny(const double* sd, const double* se, int n) {
+  double tnorm = 0.0;
+  for (int i = 0; i < n; ++i) tnorm = fmax(tnorm, fabs(sd[i]) + fabs(se[i]) + (i > 0 ? fabs(se[i - 1]) : 0.0));
+  return fmax(tnorm, 1e-300) * 2.2e-16;
+}
 
-// Z[i*ldz + j] (j < k): unit eigenvector of the tridiagonal for w[j].
-// scratch: 6 * n * kpad doubles, kpad = k rounded up to 64.
+// Z[i*ldz + j] (j < k): unit eigenvector of the tridiagonal for w[j], by one
+// solve with the pivoted LU of T - w_j I from a hashed start vector (which
+// amplifies the wanted direction by ~1 / (eps ||T||)).
 __global__ __launch_bounds__(64) void stein_kernel(const double* d, const double* e, int n, const double* w,
-                                                   int k, double* Z, int ldz, double* scr, int kpad) {
-  // per-thread working arrays in LDS, [array][i][thread] (blockDim.x threads);
-  // the factors also go to `scr` for the refinement solves of the grouping
-  // kernel (write-only here)
+                                                   int k, double* Z, int ldz) {
+  // per-thread working arrays in LDS, [array][i][thread] (blockDim.x threads)
   extern __shared__ double lds[];
   __shared__ double sd[512], se[512];
   const int T = blockDim.x, t = threadIdx.x;
@@ -1103,73 +1132,31 @@ __global__ __launch_bounds__(64) void stein_kernel(const double* d, const double
   __syncthreads();
   const int j = blockIdx.x * T + t;
   if (j >= k) return;
-  double tnorm = 0.0;
-  for (int i = 0; i < n; ++i) tnorm = fmax(tnorm, fabs(sd[i]) + fabs(se[i]) + (i > 0 ? fabs(se[i - 1]) : 0.0));
-  const double tiny = fmax(tnorm, 1e-300) * 2.2e-16;
+  const double tiny = stein_tiny(sd, se, n);
   const double lam = w[j];
-  double* gU0 = scr + 0LL * n * kpad;
-  double* gU1 = scr + 1LL * n * kpad;
-  double* gU2 = scr + 2LL * n * kpad;
-  double* gLM = scr + 3LL * n * kpad;
-  double* gPV = scr + 4LL * n * kpad;
-  double* sU0 = lds;
+  double* sU0 = lds;                    // 1 / u0: the reciprocal is off the recurrence
   double* sU1 = lds + (long long)n * T;
   double* sU2 = lds + 2LL * n * T;
   double* sZ = lds + 3LL * n * T;
-#define IX(i) ((long long)(i) * kpad + j)
 #define SX(i) ((i) * T + t)
-  // pivoted LU of T - lam I, with the forward elimination of the start vector
-  // folded in (its rows are eliminated in the same order); pivots below
-  // eps ||T|| are replaced by +-eps ||T|| for the back substitution
+  // factorisation with the forward elimination of the start vector folded in
+  // (its rows are eliminated in the same order)
   double a = sd[0] - lam, b = (n > 1) ? se[0] : 0.0;
   double cur = hash_unit(0u, (unsigned)j);
   for (int i = 0; i < n - 1; ++i) {
-    const double c = se[i];
-    const double an = sd[i + 1] - lam;
     const double bn = (i + 1 < n - 1) ? se[i + 1] : 0.0;
     double nxt = hash_unit((unsigned)(i + 1), (unsigned)j);
-    double u0, u1, u2, mult, pv;
-    if (fabs(a) >= fabs(c)) {
-      const double aa = (a == 0.0) ? tiny : a;
-      mult = c * rcp_refined(aa);
-      u0 = (fabs(aa) < tiny) ? copysign(tiny, aa) : aa;
-      u1 = b; u2 = 0.0; pv = 0.0;
-      a = an - mult * b;
-      b = bn;
-    } else {
-      mult = a * rcp_refined(c);
-      u0 = (fabs(c) < tiny) ? copysign(tiny, c) : c;
-      u1 = an; u2 = bn; pv = 1.0;
-      a = b - mult * an;
-      b = -mult * bn;
-      const double tt = cur; cur = nxt; nxt = tt;
-    }
-    sU0[SX(i)] = 1.0 / u0; sU1[SX(i)] = u1; sU2[SX(i)] = u2;   // reciprocal: off the recurrence
-    gU0[IX(i)] = u0; gU1[IX(i)] = u1; gU2[IX(i)] = u2; gLM[IX(i)] = mult; gPV[IX(i)] = pv;
-    nxt -= mult * cur;
+    const SteinLu f = stein_lu_step(a, b, se[i], sd[i + 1] - lam, bn, tiny);
+    if (f.swap) { const double tt = cur; cur = nxt; nxt = tt; }
+    sU0[SX(i)] = 1.0 / f.u0; sU1[SX(i)] = f.u1; sU2[SX(i)] = f.u2;
+    nxt -= f.mult * cur;
     sZ[SX(i)] = cur;
     cur = nxt;
   }
-  {
-    const double u0 = (fabs(a) < tiny) ? copysign(tiny, a == 0.0 ? 1.0 : a) : a;
-    sU0[SX(n - 1)] = 1.0 / u0; sU1[SX(n - 1)] = 0.0; sU2[SX(n - 1)] = 0.0;
-    gU0[IX(n - 1)] = u0; gU1[IX(n - 1)] = 0.0; gU2[IX(n - 1)] = 0.0; gLM[IX(n - 1)] = 0.0; gPV[IX(n - 1)] = 0.0;
-  }
+  sU0[SX(n - 1)] = 1.0 / stein_last_pivot(a, tiny); sU1[SX(n - 1)] = 0.0; sU2[SX(n - 1)] = 0.0;
   sZ[SX(n - 1)] = cur;
-  for (int iter = 0; iter <= STEIN_EXTRA; ++iter) {
-    if (iter > 0) {
-      // forward: the row exchanges and multipliers again
-      double cf = sZ[SX(0)];
-      for (int i = 0; i < n - 1; ++i) {
-        double nf = sZ[SX(i + 1)];
-        if (gPV[IX(i)] != 0.0) { const double tt = cf; cf = nf; nf = tt; }
-        nf -= gLM[IX(i)] * cf;
-        sZ[SX(i)] = cf;
-        cf = nf;
-      }
-      sZ[SX(n - 1)] = cf;
-    }
-    // backward substitution with the upper factor (bandwidth 3)
+  // backward substitution with the upper factor (bandwidth 3), then unit norm
+  {
     double z1 = 0.0, z2 = 0.0, big = 0.0;
     for (int i = n - 1; i >= 0; --i) {
       const double z = (sZ[SX(i)] - sU1[SX(i)] * z1 - sU2[SX(i)] * z2) * sU0[SX(i)];
@@ -1188,7 +1175,6 @@ __global__ __launch_bounds__(64) void stein_kernel(const double* d, const double
   for (int i = 0; i < n; ++i) { const double z = sZ[SX(i)]; if (fabs(z) > big) { big = fabs(z); sg = z < 0 ? -1.0 : 1.0; } }
   for (int i = 0; i < n; ++i) Z[(long long)i * ldz + j] = sg * sZ[SX(i)];
 #undef SX
-#undef IX
 }
 
 // U[:, j] = Q z_j for j < k: Q = H_0 H_1 ... H_{n-2}, H_i = I - tau_i v_i v_i^H
@@ -1304,7 +1290,7 @@ __global__ __launch_bounds__(256) void ormtr_kernel(const double* Vt, const doub
 // Gram-Schmidt applied twice.  A member that loses more than half of its norm
 // in the projection (nearly dependent vectors) would carry amplified
 // contamination of other groups, so it is first refined by one more solve
-// with its own shifted factorisation (left in `scr` by stein_kernel), which
+// with its own shifted factorisation (rebuilt in sg_solve), which
 // damps every direction outside the group, and projected again; if that
 // collapses too it restarts from fresh start vectors.
 // Eigenvalues within 8 n eps ||T|| of zero are not resolved by the reduction
@@ -1350,28 +1336,29 @@ __device__ void sg_scale(double* zl, int n, double f) {
   __syncthreads();
 }
 
-// one solve with the pivoted factorisation of T - w_j I (layout of stein_kernel)
-__device__ void sg_solve(double* zl, int n, const double* scr, int kpad, int j, double* lu, double* red) {
+// One solve with the pivoted factorisation of T - lam I, rebuilt by thread 0
+// with the same steps as stein_kernel (sd, se: the tridiagonal in LDS), then
+// scaled to unit max-norm.
+__device__ void sg_solve(double* zl, int n, const double* sd, const double* se, double lam, double* lu, double* red) {
   double* u0 = lu;
   double* u1 = lu + 512;
   double* u2 = lu + 1024;
-  double* lm = lu + 1536;
-  double* pv = lu + 2048;
-  const long long nk = (long long)n * kpad;
-  for (int i = threadIdx.x; i < n; i += SG_NT) {
-    const long long o = (long long)i * kpad + j;
-    u0[i] = scr[o]; u1[i] = scr[nk + o]; u2[i] = scr[2 * nk + o]; lm[i] = scr[3 * nk + o]; pv[i] = scr[4 * nk + o];
-  }
   __syncthreads();
   if (threadIdx.x == 0) {
+    const double tiny = stein_tiny(sd, se, n);
+    double a = sd[0] - lam, b = (n > 1) ? se[0] : 0.0;
     double cur = zl[0];
     for (int i = 0; i < n - 1; ++i) {
+      const double bn = (i + 1 < n - 1) ? se[i + 1] : 0.0;
       double nxt = zl[i + 1];
-      if (pv[i] != 0.0) { const double t = cur; cur = nxt; nxt = t; }
-      nxt -= lm[i] * cur;
+      const SteinLu f = stein_lu_step(a, b, se[i], sd[i + 1] - lam, bn, tiny);
+      if (f.swap) { const double tt = cur; cur = nxt; nxt = tt; }
+      u0[i] = f.u0; u1[i] = f.u1; u2[i] = f.u2;
+      nxt -= f.mult * cur;
       zl[i] = cur;
       cur = nxt;
     }
+    u0[n - 1] = stein_last_pivot(a, tiny); u1[n - 1] = 0.0; u2[n - 1] = 0.0;
     zl[n - 1] = cur;
     double z1 = 0.0, z2 = 0.0;
     for (int i = n - 1; i >= 0; --i) {
@@ -1397,9 +1384,9 @@ __device__ void sg_solve(double* zl, int n, const double* scr, int kpad, int j, 
 // group.  Groups are disjoint, so workgroup g handles the group that starts
 // at eigenvalue g (if any); unresolved eigenvalues (|w| <= 8 n eps ||T||)
 // are left to stein_unresolved_kernel.
-__global__ __launch_bounds__(SG_NT) void stein_groups_kernel(int n, const double* w, int k, double theta,
-                                                             double* Z, int ldz, const double* scr, int kpad) {
-  __shared__ double zl[512], dots[512], lu[5 * 512];
+__global__ __launch_bounds__(SG_NT) void stein_groups_kernel(int n, const double* d, const double* e,
+                                                             const double* w, int k, double theta, double* Z, int ldz) {
+  __shared__ double zl[512], dots[512], lu[3 * 512], sd[512], se[512];
   __shared__ double red[32];
   __shared__ int cols[512];
   const double tn = fmax(fmax(fabs(w[0]), fabs(w[n - 1])), 1e-300);
@@ -1408,6 +1395,8 @@ __global__ __launch_bounds__(SG_NT) void stein_groups_kernel(int n, const double
   auto linked = [&](int j) { return j > 0 && j < k && w[j - 1] - w[j] <= gap; };
   const int start = blockIdx.x;
   if (linked(start) || !linked(start + 1)) return;   // not the first of a group of two or more
+  for (int i = threadIdx.x; i < n; i += SG_NT) { sd[i] = d[i]; se[i] = (i < n - 1) ? e[i] : 0.0; }
+  __syncthreads();
   for (int j = start + 1; linked(j); ++j) {
     if (fabs(w[j]) <= floor_abs) continue;
     int s0 = start;
@@ -1420,9 +1409,9 @@ __global__ __launch_bounds__(SG_NT) void stein_groups_kernel(int n, const double
         // restart from a fresh start vector, pulled towards the group by two solves
         for (int r = threadIdx.x; r < n; r += SG_NT) zl[r] = hash_unit((unsigned)r, (unsigned)(j + 7919 * attempt));
         __syncthreads();
-        sg_solve(zl, n, scr, kpad, j, lu, red);
+        sg_solve(zl, n, sd, se, w[j], lu, red);
       }
-      if (attempt >= 1) sg_solve(zl, n, scr, kpad, j, lu, red);
+      if (attempt >= 1) sg_solve(zl, n, sd, se, w[j], lu, red);
       const double n0 = sg_norm(zl, n, red);
       int np = 0;
       if (threadIdx.x == 0)
@@ -1482,15 +1471,13 @@ __global__ __launch_bounds__(SG_NT) void stein_unresolved_kernel(int n, const do
   }
 }
 
-TridWork trid_work(double* work, int n, int kvec) {
+TridWork trid_work(double* work, int n) {
   TridWork t;
   t.d = work;
   t.e = t.d + n;
   t.tau = t.e + n;
   t.Vt = t.tau + 2 * n;
   t.Z = t.Vt + 2LL * n * n;
-  t.scr = t.Z + (long long)n * n;
-  t.kpad = ((std::max(kvec, 1) + 63) / 64) * 64;
   return t;
 }
 
@@ -1518,11 +1505,10 @@ hipError_t trid_vectors(int n, const TridWork& t, const double* w, int kvec, hip
   int tpb = 64;
   while (tpb > 1 && 4LL * n * tpb * 8 > 131072) tpb >>= 1;
   const size_t lds = (size_t)4 * n * tpb * 8;
-  hipLaunchKernelGGL(stein_kernel, dim3((kvec + tpb - 1) / tpb), dim3(tpb), lds, s, t.d, t.e, n, w, kvec, t.Z, n,
-                     t.scr, t.kpad);
+  hipLaunchKernelGGL(stein_kernel, dim3((kvec + tpb - 1) / tpb), dim3(tpb), lds, s, t.d, t.e, n, w, kvec, t.Z, n);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(stein_groups_kernel, dim3(kvec), dim3(SG_NT), 0, s, n, w, kvec, 1e-8, t.Z, n, t.scr, t.kpad);
+  hipLaunchKernelGGL(stein_groups_kernel, dim3(kvec), dim3(SG_NT), 0, s, n, t.d, t.e, w, kvec, 1e-8, t.Z, n);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(stein_unresolved_kernel, dim3(1), dim3(SG_NT), 0, s, n, w, kvec, t.Z, n);
   return hipGetLastError();
@@ -1538,7 +1524,7 @@ hipError_t heev_tridiag(double* G, int ldg, int n, double* w, double* U, int ldu
                         hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (n > 512 || kvec > n) return hipErrorInvalidValue;
-  const TridWork t = trid_work(work, n, kvec);
+  const TridWork t = trid_work(work, n);
   hipError_t e;
   if ((e = trid_reduce(G, ldg, n, t, s)) != hipSuccess) return e;
   if ((e = trid_eigenvalues(n, t, w, s)) != hipSuccess) return e;
@@ -1547,8 +1533,7 @@ hipError_t heev_tridiag(double* G, int ldg, int n, double* w, double* U, int ldu
 }
 
 size_t heev_tridiag_work_doubles(int n) {
-  const size_t kpad = ((size_t)(n + 63) / 64) * 64;
-  return (size_t)4 * n + 2 * (size_t)n * n + (size_t)n * n + 6 * (size_t)n * kpad + 64;
+  return (size_t)4 * n + 2 * (size_t)n * n + (size_t)n * n + 64;
 }
 
 // K split so that about 32 partial tiles run (each at least 64 deep); the
