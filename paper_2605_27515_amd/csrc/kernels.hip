@@ -18,6 +18,7 @@
 //                  precision conversion, drive-boundary contraction.
 #include "kernels.h"
 
+#include <atomic>
 #include <cmath>
 
 namespace lbk {
@@ -1016,6 +1017,204 @@ __global__ __launch_bounds__(TRD_NT) void hetrd_kernel(double2* G, int ldg, int 
   }
 }
 
+// The same reduction over W workgroups for the larger orders, all of the
+// trailing block in registers.  Workgroup g owns the columns c = lc*W + g
+// (lc < LC, cyclic, so the columns retire evenly); thread (lc, rho) holds
+// rows R = q*PARTS + rho of its column, the PARTS threads of a column being
+// adjacent lanes that fold their partial products by DPP.
+//
+// One exchange per step.  The pass of step j-1 (rank-2 update of step j-1
+// fused with the product y_j = B_j v_j) leaves in every workgroup y_j on its
+// columns and row j+1 of B_j on its columns; wave 0 publishes both to `pub`
+// and raises its flag.  Once every flag is up, each workgroup gathers the
+// whole y_j and row j+1, which is column j+1 conjugated (B_j is Hermitian),
+// and redundantly forms w_j, the updated column j+1 and reflector j+1, so the
+// next pass starts without a second exchange.  Flags carry a per-launch
+// generation tag, so the sync block needs no clearing; every wait is bounded
+// (after TRM_WAIT_TICKS of the 100 MHz wall clock a workgroup raises the
+// abort word, all workgroups leave, and d is set to NaN).  The workgroups of
+// one launch must run concurrently: W of them, one CU each.
+constexpr int TRM_PARTS = 16;
+constexpr int TRM_LC = 32;
+constexpr int TRM_NT = TRM_LC * TRM_PARTS;       // 512 threads
+constexpr int TRM_WMAX = 16;
+constexpr int TRM_NMAX = TRM_WMAX * TRM_LC;      // 512
+constexpr int TRM_FLAG_STRIDE = 16;              // one 128-byte line per flag
+constexpr long long TRM_WAIT_TICKS = 200000000;  // 2 s
+// sync block in doubles: pub[2 parities][2 kinds][TRM_NMAX] complex, then
+// TRM_WMAX flags and the abort word, one line each
+constexpr size_t TRM_SYNC_DOUBLES = (size_t)2 * 2 * TRM_NMAX * 2 + (size_t)(TRM_WMAX + 1) * TRM_FLAG_STRIDE;
+
+template <int NMAX>
+struct TrmShared {
+  double2 v[2][NMAX];     // v_j, v_{j+1} by global row
+  double2 w[NMAX];        // w_j
+  double2 y[NMAX];        // gathered y_j, then the updated column j+1
+  double2 yp[TRM_LC];     // this workgroup's folded product, by local column
+  double2 fr[TRM_LC];     // this workgroup's entries of the next block's first row
+  int abort;
+};
+
+template <int W, bool FIRST>
+__device__ inline void trm_pass(const double2* G, int ldg, int n, int j, TrmShared<W * TRM_LC>& sh,
+                                const double2* vc, const double2* vn, double2 (&reg)[W * TRM_LC / TRM_PARTS],
+                                double2* vt_row) {
+  constexpr int QR = W * TRM_LC / TRM_PARTS;
+  const int tid = threadIdx.x, lc = tid / TRM_PARTS, rho = tid % TRM_PARTS, c = lc * W + blockIdx.x;
+  const int lo = j + 2;
+  double ar = 0.0, ai = 0.0;
+  double2 frow = double2{0.0, 0.0};
+  if (c >= lo && c < n) {
+    const double2 vC = FIRST ? double2{0.0, 0.0} : vc[c];
+    const double2 wC = FIRST ? double2{0.0, 0.0} : sh.w[c];
+#pragma unroll
+    for (int q = 0; q < QR; ++q) {
+      const int R = q * TRM_PARTS + rho;
+      if (R >= lo && R < n) {
+        if (FIRST) {
+          // B[R][c] = conj(B[c][R]): row c of G is contiguous in R
+          const double2 t = G[(long long)c * ldg + R];
+          reg[q] = double2{t.x, -t.y};
+        } else {
+          trd_update(reg[q], sh.w[R], vc[R], vC, wC);
+        }
+        trd_acc(ar, ai, reg[q], vn[R]);
+        if (R == lo) frow = reg[q];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (rho == 0) vt_row[c] = vn[c];
+  }
+  ar = group_sum<TRM_PARTS>(ar);
+  ai = group_sum<TRM_PARTS>(ai);
+  if (rho == 0) sh.yp[lc] = double2{ar, ai};
+  if (rho == lo % TRM_PARTS) sh.fr[lc] = frow;
+}
+
+template <int W>
+__global__ __launch_bounds__(TRM_NT) void hetrd_mc_kernel(const double2* G, int ldg, int n, double* d, double* e,
+                                                          double2* tau, double2* Vt, double2* pub,
+                                                          unsigned long long* flags, unsigned gen) {
+  constexpr int NMAX = W * TRM_LC, QR = NMAX / TRM_PARTS;
+  __shared__ TrmShared<NMAX> sh;
+  const int tid = threadIdx.x, lane = tid & 63, g = blockIdx.x;
+  const bool w0 = tid < 64, lead = (g == 0);
+  unsigned long long* abortw = flags + TRM_WMAX * TRM_FLAG_STRIDE;
+  double2 reg[QR];
+  double tr = 0.0, ti = 0.0;   // tau_j, held by wave 0
+  if (tid == 0) sh.abort = 0;
+  // reflector 0 from column 0, in every workgroup
+  if (w0) {
+    double tail = 0.0;
+    for (int R = 2 + lane; R < n; R += 64) {
+      const double2 x = G[(long long)R * ldg];
+      tail += x.x * x.x + x.y * x.y;
+    }
+    const double xn2 = wave_sum(tail);
+    const double2 alpha = G[ldg];
+    double beta;
+    double2 s;
+    trd_reflector(alpha, xn2, beta, tr, ti, s);
+    for (int R = 1 + lane; R < n; R += 64) sh.v[0][R] = (R == 1) ? double2{1.0, 0.0} : cmul(G[(long long)R * ldg], s);
+    if (lead && lane == 0) {
+      d[0] = G[0].x;
+      e[0] = beta;
+      tau[0] = double2{tr, ti};
+    }
+  }
+  __syncthreads();
+  trm_pass<W, true>(G, ldg, n, -1, sh, nullptr, sh.v[0], reg, Vt);
+  __syncthreads();
+  for (int j = 0;; ++j) {
+    const double2* vc = sh.v[j & 1];
+    double2* vn = sh.v[(j & 1) ^ 1];
+    if (w0) {
+      // publish y_j and row j+1 on this workgroup's columns, raise the flag
+      double2* py = pub + (size_t)((j & 1) * 2) * TRM_NMAX;
+      double2* pf = py + TRM_NMAX;
+      if (lane < TRM_LC) {
+        const int cc = lane * W + g;
+        if (cc > j && cc < n) { py[cc] = sh.yp[lane]; pf[cc] = sh.fr[lane]; }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      const unsigned long long tag = ((unsigned long long)gen << 32) | (unsigned)(j + 1);
+      if (lane == 0) __hip_atomic_store(&flags[g * TRM_FLAG_STRIDE], tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // wait for every workgroup's step-j data (bounded)
+      const long long t0 = (long long)wall_clock64();
+      bool abort = false;
+      for (;;) {
+        bool ok = true;
+        if (lane < W) {
+          const unsigned long long f =
+              __hip_atomic_load(&flags[lane * TRM_FLAG_STRIDE], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = (unsigned)(f >> 32) == gen && (unsigned)f >= (unsigned)(j + 1);
+        } else if (lane == W) {
+          ok = __hip_atomic_load(abortw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != (unsigned long long)gen;
+          if (!ok) abort = true;
+        }
+        if (__ballot(!ok) == 0ull) break;
+        abort = __ballot(abort) != 0ull;
+        if (!abort && (long long)wall_clock64() - t0 > TRM_WAIT_TICKS) {
+          if (lane == 0) __hip_atomic_store(abortw, (unsigned long long)gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          abort = true;
+        }
+        if (abort) break;
+        __builtin_amdgcn_s_sleep(1);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (abort) {
+        for (int R = lane; R < n; R += 64) d[R] = __builtin_nan("");
+        if (lane == 0) sh.abort = 1;
+      } else {
+        // y_j and s = Re(v^H y)
+        double sp = 0.0;
+        for (int R = j + 1 + lane; R < n; R += 64) {
+          const double2 y = py[R];
+          sh.y[R] = y;
+          const double2 v = vc[R];
+          sp += v.x * y.x + v.y * y.y;
+        }
+        const bool refl = !(tr == 0.0 && ti == 0.0);
+        const double h = 0.5 * (tr * tr + ti * ti) * wave_sum(sp);
+        const double2 y1 = sh.y[j + 1];
+        const double2 w1 = refl ? double2{tr * y1.x - ti * y1.y - h, tr * y1.y + ti * y1.x} : double2{0.0, 0.0};
+        // w = tau y - h v and column j+1 after step j's update: x = conj(row) - w - v conj(w1)
+        double tail = 0.0;
+        for (int R = j + 1 + lane; R < n; R += 64) {
+          const double2 y = sh.y[R], v = vc[R], fr = pf[R];
+          const double2 f = double2{fr.x, -fr.y};
+          const double2 w = refl ? double2{tr * y.x - ti * y.y - h * v.x, tr * y.y + ti * y.x - h * v.y} : double2{0.0, 0.0};
+          sh.w[R] = w;
+          const double2 x = double2{f.x - w.x - (v.x * w1.x + v.y * w1.y), f.y - w.y - (v.y * w1.x - v.x * w1.y)};
+          sh.y[R] = x;
+          if (R >= j + 3) tail += x.x * x.x + x.y * x.y;
+        }
+        const double xn2 = wave_sum(tail);
+        const double dg = sh.y[j + 1].x;
+        if (j == n - 2) {
+          if (lead && lane == 0) d[j + 1] = dg;
+        } else {
+          const double2 alpha = sh.y[j + 2];
+          double beta;
+          double2 s;
+          trd_reflector(alpha, xn2, beta, tr, ti, s);
+          for (int R = j + 2 + lane; R < n; R += 64) vn[R] = (R == j + 2) ? double2{1.0, 0.0} : cmul(sh.y[R], s);
+          if (lead && lane == 0) {
+            d[j + 1] = dg;
+            e[j + 1] = beta;
+            tau[j + 1] = double2{tr, ti};
+          }
+        }
+      }
+    }
+    if (j == n - 2) break;
+    __syncthreads();
+    if (sh.abort) return;
+    trm_pass<W, false>(G, ldg, n, j, sh, vc, vn, reg, Vt + (long long)(j + 1) * n);
+    __syncthreads();
+  }
+}
+
 __device__ inline int sturm_count(const double* sd, const double* se2, int n, double x, double pivmin) {
   int c = 0;
   double q = sd[0] - x;
@@ -1478,6 +1677,9 @@ TridWork trid_work(double* work, int n) {
   t.tau = t.e + n;
   t.Vt = t.tau + 2 * n;
   t.Z = t.Vt + 2LL * n * n;
+  // 128-byte aligned (the workspace itself is)
+  const size_t off = (size_t)(t.Z + (long long)n * n - work);
+  t.sync = work + ((off + 15) / 16) * 16;
   return t;
 }
 
@@ -1489,8 +1691,19 @@ hipError_t trid_reduce(double* G, int ldg, int n, const TridWork& t, hipStream_t
   double2* vt = reinterpret_cast<double2*>(t.Vt);
   if (n <= 64) hipLaunchKernelGGL(hetrd_kernel<16>, dim3(1), dim3(TRD_NT), 0, s, g2, ldg, n, t.d, t.e, tau, vt);
   else if (n <= 128) hipLaunchKernelGGL(hetrd_kernel<8>, dim3(1), dim3(TRD_NT), 0, s, g2, ldg, n, t.d, t.e, tau, vt);
-  else if (n <= 256) hipLaunchKernelGGL(hetrd_kernel<4>, dim3(1), dim3(TRD_NT), 0, s, g2, ldg, n, t.d, t.e, tau, vt);
-  else hipLaunchKernelGGL(hetrd_kernel<2>, dim3(1), dim3(TRD_NT), 0, s, g2, ldg, n, t.d, t.e, tau, vt);
+  else {
+    // launch generation tag of the multi-workgroup form (never 0)
+    static std::atomic<unsigned> next_gen{1};
+    unsigned gen = next_gen.fetch_add(1, std::memory_order_relaxed);
+    if (gen == 0) gen = next_gen.fetch_add(1, std::memory_order_relaxed);
+    double2* pub = reinterpret_cast<double2*>(t.sync);
+    auto* flags = reinterpret_cast<unsigned long long*>(t.sync + 2 * 2 * TRM_NMAX * 2);
+    if (n <= 256)
+      hipLaunchKernelGGL(hetrd_mc_kernel<8>, dim3(8), dim3(TRM_NT), 0, s, g2, ldg, n, t.d, t.e, tau, vt, pub, flags, gen);
+    else
+      hipLaunchKernelGGL(hetrd_mc_kernel<16>, dim3(16), dim3(TRM_NT), 0, s, g2, ldg, n, t.d, t.e, tau, vt, pub, flags,
+                         gen);
+  }
   return hipGetLastError();
 }
 
@@ -1533,7 +1746,7 @@ hipError_t heev_tridiag(double* G, int ldg, int n, double* w, double* U, int ldu
 }
 
 size_t heev_tridiag_work_doubles(int n) {
-  return (size_t)4 * n + 2 * (size_t)n * n + (size_t)n * n + 64;
+  return (size_t)4 * n + 2 * (size_t)n * n + (size_t)n * n + 16 + TRM_SYNC_DOUBLES + 64;
 }
 
 // K split so that about 32 partial tiles run (each at least 64 deep); the
