@@ -1019,9 +1019,11 @@ __global__ __launch_bounds__(TRD_NT) void hetrd_kernel(double2* G, int ldg, int 
 
 // The same reduction over W workgroups for the larger orders, all of the
 // trailing block in registers.  Workgroup g owns the columns c = lc*W + g
-// (lc < LC, cyclic, so the columns retire evenly); thread (lc, rho) holds
-// rows R = q*PARTS + rho of its column, the PARTS threads of a column being
-// adjacent lanes that fold their partial products by DPP.
+// (lc < 8 CPW); wave k of it holds the CPW columns lc = k + 8u (u < CPW), so
+// that every wave keeps work until the end, and lane l of a wave holds rows
+// R = 64q + l of them: each row vector entry is read from LDS by exactly one
+// lane per wave, and the columns' products fold over the wave through an LDS
+// transpose and DPP.
 //
 // One exchange per step.  The pass of step j-1 (rank-2 update of step j-1
 // fused with the product y_j = B_j v_j) leaves in every workgroup y_j on its
@@ -1034,75 +1036,162 @@ __global__ __launch_bounds__(TRD_NT) void hetrd_kernel(double2* G, int ldg, int 
 // (after TRM_WAIT_TICKS of the 100 MHz wall clock a workgroup raises the
 // abort word, all workgroups leave, and d is set to NaN).  The workgroups of
 // one launch must run concurrently: W of them, one CU each.
-constexpr int TRM_PARTS = 16;
-constexpr int TRM_LC = 32;
-constexpr int TRM_NT = TRM_LC * TRM_PARTS;       // 512 threads
-constexpr int TRM_WMAX = 16;
-constexpr int TRM_NMAX = TRM_WMAX * TRM_LC;      // 512
+constexpr int TRM_NT = 512;                      // 8 waves
+constexpr int TRM_WMAX = 32;                     // workgroups, at most
+constexpr int TRM_NMAX = 512;                    // order, at most
 constexpr int TRM_FLAG_STRIDE = 16;              // one 128-byte line per flag
 constexpr long long TRM_WAIT_TICKS = 200000000;  // 2 s
 // sync block in doubles: pub[2 parities][2 kinds][TRM_NMAX] complex, then
 // TRM_WMAX flags and the abort word, one line each
 constexpr size_t TRM_SYNC_DOUBLES = (size_t)2 * 2 * TRM_NMAX * 2 + (size_t)(TRM_WMAX + 1) * TRM_FLAG_STRIDE;
 
-template <int NMAX>
+template <int NMAX, int CPW>
 struct TrmShared {
-  double2 v[2][NMAX];     // v_j, v_{j+1} by global row
+  // row vectors by global row; entries of retired rows (below the pass's
+  // first row) and of padding rows (>= n) are kept zero, so the pass needs no
+  // row predicate
+  double2 v[2][NMAX];     // v_j, v_{j+1}
   double2 w[NMAX];        // w_j
-  double2 y[NMAX];        // gathered y_j, then the updated column j+1
-  double2 yp[TRM_LC];     // this workgroup's folded product, by local column
-  double2 fr[TRM_LC];     // this workgroup's entries of the next block's first row
+  double2 yp[8 * CPW];    // this workgroup's folded product, by local column
+  double2 fr[8 * CPW];    // this workgroup's entries of the next block's first row
+  double red[TRM_NT / 64][2 * CPW][64];   // per-wave partial products, transposed in the fold
   int abort;
 };
 
-template <int W, bool FIRST>
-__device__ inline void trm_pass(const double2* G, int ldg, int n, int j, TrmShared<W * TRM_LC>& sh,
-                                const double2* vc, const double2* vn, double2 (&reg)[W * TRM_LC / TRM_PARTS],
-                                double2* vt_row) {
-  constexpr int QR = W * TRM_LC / TRM_PARTS;
-  const int tid = threadIdx.x, lc = tid / TRM_PARTS, rho = tid % TRM_PARTS, c = lc * W + blockIdx.x;
-  const int lo = j + 2;
-  double ar = 0.0, ai = 0.0;
-  double2 frow = double2{0.0, 0.0};
-  if (c >= lo && c < n) {
-    const double2 vC = FIRST ? double2{0.0, 0.0} : vc[c];
-    const double2 wC = FIRST ? double2{0.0, 0.0} : sh.w[c];
-#pragma unroll
-    for (int q = 0; q < QR; ++q) {
-      const int R = q * TRM_PARTS + rho;
-      if (R >= lo && R < n) {
-        if (FIRST) {
-          // B[R][c] = conj(B[c][R]): row c of G is contiguous in R
-          const double2 t = G[(long long)c * ldg + R];
-          reg[q] = double2{t.x, -t.y};
-        } else {
-          trd_update(reg[q], sh.w[R], vc[R], vC, wC);
-        }
-        trd_acc(ar, ai, reg[q], vn[R]);
-        if (R == lo) frow = reg[q];
-      }
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    if (rho == 0) vt_row[c] = vn[c];
-  }
-  ar = group_sum<TRM_PARTS>(ar);
-  ai = group_sum<TRM_PARTS>(ai);
-  if (rho == 0) sh.yp[lc] = double2{ar, ai};
-  if (rho == lo % TRM_PARTS) sh.fr[lc] = frow;
+__device__ inline double2 read_lane2(double2 v, int l) { return double2{read_lane(v.x, l), read_lane(v.y, l)}; }
+
+// b -= wR conj(vC) + vR conj(wC), as fused multiply-adds
+__device__ inline void trm_update(double2& b, double2 wR, double2 vR, double2 vC, double2 wC) {
+  b.x = fma(-wR.x, vC.x, b.x); b.x = fma(-wR.y, vC.y, b.x); b.x = fma(-vR.x, wC.x, b.x); b.x = fma(-vR.y, wC.y, b.x);
+  b.y = fma(-wR.y, vC.x, b.y); b.y = fma(wR.x, vC.y, b.y); b.y = fma(-vR.y, wC.x, b.y); b.y = fma(vR.x, wC.y, b.y);
 }
 
-template <int W>
+// acc += conj(b) x, as fused multiply-adds
+__device__ inline void trm_acc(double& ar, double& ai, double2 b, double2 x) {
+  ar = fma(b.x, x.x, ar); ar = fma(b.y, x.y, ar);
+  ai = fma(b.x, x.y, ai); ai = fma(-b.y, x.x, ai);
+}
+
+template <int W, int CPW, bool FIRST>
+__device__ inline void trm_pass(const double2* G, int ldg, int n, int j, TrmShared<W * 8 * CPW, CPW>& sh,
+                                const double2* vc, const double2* vn, double2 (&reg)[CPW][W * 8 * CPW / 64],
+                                double2* vt_row) {
+  constexpr int QR = W * 8 * CPW / 64;
+  const int lane = threadIdx.x & 63, k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lo = j + 2;
+  int c[CPW];
+  bool act[CPW];
+  double2 vC[CPW], wC[CPW];
+  double ar[CPW], ai[CPW];
+#pragma unroll
+  for (int u = 0; u < CPW; ++u) {
+    c[u] = (k + 8 * u) * W + blockIdx.x;   // < NMAX: in range of the row vectors
+    act[u] = c[u] >= lo && c[u] < n;
+    ar[u] = 0.0; ai[u] = 0.0;
+    vC[u] = double2{0.0, 0.0}; wC[u] = double2{0.0, 0.0};
+  }
+  if (!FIRST) {
+    // wave-uniform column values: lane 0 reads all of them at once, the wave
+    // takes them from it
+    double2 a[CPW], b[CPW];
+#pragma unroll
+    for (int u = 0; u < CPW; ++u) { a[u] = double2{0.0, 0.0}; b[u] = double2{0.0, 0.0}; }
+    if (lane == 0) {
+#pragma unroll
+      for (int u = 0; u < CPW; ++u) { a[u] = vc[c[u]]; b[u] = sh.w[c[u]]; }
+    }
+#pragma unroll
+    for (int u = 0; u < CPW; ++u) { vC[u] = read_lane2(a[u], 0); wC[u] = read_lane2(b[u], 0); }
+  }
+  // row slices in chunks of QC: all of a chunk's vector loads are issued
+  // before its arithmetic
+  constexpr int QC = QR < 4 ? QR : 4;
+#pragma unroll
+  for (int q0 = 0; q0 < QR; q0 += QC) {
+    double2 wR[QC], vR[QC], xR[QC];
+#pragma unroll
+    for (int i = 0; i < QC; ++i) {
+      const int q = q0 + i, R = q * 64 + lane;
+      wR[i] = double2{0.0, 0.0}; vR[i] = double2{0.0, 0.0}; xR[i] = double2{0.0, 0.0};
+      if (q * 64 + 63 >= lo) {
+        if (!FIRST) { wR[i] = sh.w[R]; vR[i] = vc[R]; }
+        xR[i] = vn[R];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < QC; ++i) {
+      const int q = q0 + i, R = q * 64 + lane;
+      if (q * 64 + 63 < lo) continue;   // every row of this slice retired
+#pragma unroll
+      for (int u = 0; u < CPW; ++u) {
+        if (act[u]) {
+          if (FIRST) {
+            // B[R][c] = conj(B[c][R]): row c of G is contiguous in R; rows
+            // outside [1, n) start at zero
+            double2 t = double2{0.0, 0.0};
+            if (R >= 1 && R < n) t = G[(long long)c[u] * ldg + R];
+            reg[u][q] = double2{t.x, -t.y};
+          } else {
+            trm_update(reg[u][q], wR[i], vR[i], vC[u], wC[u]);
+          }
+          trm_acc(ar[u], ai[u], reg[u][q], xR[i]);
+        }
+      }
+    }
+  }
+  // row lo of the wave's columns, for the exchange (after the loop, so no LDS
+  // store sits between the loads and the arithmetic above)
+#pragma unroll
+  for (int q = 0; q < QR; ++q) {
+    if (q == (lo >> 6)) {
+#pragma unroll
+      for (int u = 0; u < CPW; ++u)
+        if (act[u] && lane == (lo & 63)) sh.fr[k + 8 * u] = reg[u][q];
+    }
+  }
+  // fold the NV = 2 * CPW partial sums over the wave: transpose through LDS
+  // so lane l adds NV partials of value l / (64 / NV), then DPP sums over
+  // groups of 64 / NV lanes
+  double* red = &sh.red[k][0][0];
+#pragma unroll
+  for (int u = 0; u < CPW; ++u) { red[(2 * u) * 64 + lane] = ar[u]; red[(2 * u + 1) * 64 + lane] = ai[u]; }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+  constexpr int NV = 2 * CPW, GL = 64 / NV;
+  const int val = lane / GL, seg = lane % GL;
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) t += red[val * 64 + seg * NV + i];
+  t = group_sum<GL>(t);
+  if (seg == 0) {
+    const int u = val >> 1, lc = k + 8 * u;
+    if (act[u]) reinterpret_cast<double*>(&sh.yp[lc])[val & 1] = t;
+  }
+#pragma unroll
+  for (int u = 0; u < CPW; ++u)
+    if (act[u] && lane == 0) vt_row[c[u]] = vn[c[u]];
+}
+
+template <int W, int CPW>
 __global__ __launch_bounds__(TRM_NT) void hetrd_mc_kernel(const double2* G, int ldg, int n, double* d, double* e,
                                                           double2* tau, double2* Vt, double2* pub,
                                                           unsigned long long* flags, unsigned gen) {
-  constexpr int NMAX = W * TRM_LC, QR = NMAX / TRM_PARTS;
-  __shared__ TrmShared<NMAX> sh;
+  constexpr int LC = 8 * CPW, NMAX = W * LC, QR = NMAX / 64;
+  static_assert(W <= TRM_WMAX && NMAX <= TRM_NMAX && W < 64, "sync block layout");
+  __shared__ TrmShared<NMAX, CPW> sh;
   const int tid = threadIdx.x, lane = tid & 63, g = blockIdx.x;
   const bool w0 = tid < 64, lead = (g == 0);
   unsigned long long* abortw = flags + TRM_WMAX * TRM_FLAG_STRIDE;
-  double2 reg[QR];
+  double2 reg[CPW][QR];
   double tr = 0.0, ti = 0.0;   // tau_j, held by wave 0
   if (tid == 0) sh.abort = 0;
+  for (int R = tid; R < NMAX; R += TRM_NT) {
+    sh.v[0][R] = double2{0.0, 0.0};
+    sh.v[1][R] = double2{0.0, 0.0};
+    sh.w[R] = double2{0.0, 0.0};
+  }
+  __syncthreads();
   // reflector 0 from column 0, in every workgroup
   if (w0) {
     double tail = 0.0;
@@ -1123,7 +1212,7 @@ __global__ __launch_bounds__(TRM_NT) void hetrd_mc_kernel(const double2* G, int 
     }
   }
   __syncthreads();
-  trm_pass<W, true>(G, ldg, n, -1, sh, nullptr, sh.v[0], reg, Vt);
+  trm_pass<W, CPW, true>(G, ldg, n, -1, sh, nullptr, sh.v[0], reg, Vt);
   __syncthreads();
   for (int j = 0;; ++j) {
     const double2* vc = sh.v[j & 1];
@@ -1132,7 +1221,7 @@ __global__ __launch_bounds__(TRM_NT) void hetrd_mc_kernel(const double2* G, int 
       // publish y_j and row j+1 on this workgroup's columns, raise the flag
       double2* py = pub + (size_t)((j & 1) * 2) * TRM_NMAX;
       double2* pf = py + TRM_NMAX;
-      if (lane < TRM_LC) {
+      if (lane < LC) {
         const int cc = lane * W + g;
         if (cc > j && cc < n) { py[cc] = sh.yp[lane]; pf[cc] = sh.fr[lane]; }
       }
@@ -1166,39 +1255,61 @@ __global__ __launch_bounds__(TRM_NT) void hetrd_mc_kernel(const double2* G, int 
         for (int R = lane; R < n; R += 64) d[R] = __builtin_nan("");
         if (lane == 0) sh.abort = 1;
       } else {
-        // y_j and s = Re(v^H y)
+        // gather y_j and row j+1 in one round trip; s = Re(v^H y)
+        double2 yv[QR], fv[QR];
         double sp = 0.0;
-        for (int R = j + 1 + lane; R < n; R += 64) {
-          const double2 y = py[R];
-          sh.y[R] = y;
-          const double2 v = vc[R];
-          sp += v.x * y.x + v.y * y.y;
+#pragma unroll
+        for (int q = 0; q < QR; ++q) {
+          const int R = j + 1 + lane + 64 * q;
+          yv[q] = double2{0.0, 0.0}; fv[q] = double2{0.0, 0.0};
+          if (R < n) { yv[q] = py[R]; fv[q] = pf[R]; }
+        }
+#pragma unroll
+        for (int q = 0; q < QR; ++q) {
+          const int R = j + 1 + lane + 64 * q;
+          if (R < n) { const double2 v = vc[R]; sp += v.x * yv[q].x + v.y * yv[q].y; }
         }
         const bool refl = !(tr == 0.0 && ti == 0.0);
         const double h = 0.5 * (tr * tr + ti * ti) * wave_sum(sp);
-        const double2 y1 = sh.y[j + 1];
+        const double2 y1 = read_lane2(yv[0], 0);
         const double2 w1 = refl ? double2{tr * y1.x - ti * y1.y - h, tr * y1.y + ti * y1.x} : double2{0.0, 0.0};
-        // w = tau y - h v and column j+1 after step j's update: x = conj(row) - w - v conj(w1)
+        // w = tau y - h v and column j+1 after step j's update:
+        // x = conj(row) - w - v conj(w1), kept in yv
         double tail = 0.0;
-        for (int R = j + 1 + lane; R < n; R += 64) {
-          const double2 y = sh.y[R], v = vc[R], fr = pf[R];
-          const double2 f = double2{fr.x, -fr.y};
-          const double2 w = refl ? double2{tr * y.x - ti * y.y - h * v.x, tr * y.y + ti * y.x - h * v.y} : double2{0.0, 0.0};
-          sh.w[R] = w;
-          const double2 x = double2{f.x - w.x - (v.x * w1.x + v.y * w1.y), f.y - w.y - (v.y * w1.x - v.x * w1.y)};
-          sh.y[R] = x;
-          if (R >= j + 3) tail += x.x * x.x + x.y * x.y;
+#pragma unroll
+        for (int q = 0; q < QR; ++q) {
+          const int R = j + 1 + lane + 64 * q;
+          if (R < n) {
+            const double2 y = yv[q], v = vc[R], f = double2{fv[q].x, -fv[q].y};
+            const double2 w = refl ? double2{tr * y.x - ti * y.y - h * v.x, tr * y.y + ti * y.x - h * v.y} : double2{0.0, 0.0};
+            sh.w[R] = w;
+            const double2 x = double2{f.x - w.x - (v.x * w1.x + v.y * w1.y), f.y - w.y - (v.y * w1.x - v.x * w1.y)};
+            yv[q] = x;
+            if (R >= j + 3) tail += x.x * x.x + x.y * x.y;
+          }
         }
         const double xn2 = wave_sum(tail);
-        const double dg = sh.y[j + 1].x;
+        const double dg = read_lane(yv[0].x, 0);
         if (j == n - 2) {
           if (lead && lane == 0) d[j + 1] = dg;
         } else {
-          const double2 alpha = sh.y[j + 2];
+          const double2 alpha = read_lane2(yv[0], 1);
           double beta;
           double2 s;
           trd_reflector(alpha, xn2, beta, tr, ti, s);
-          for (int R = j + 2 + lane; R < n; R += 64) vn[R] = (R == j + 2) ? double2{1.0, 0.0} : cmul(sh.y[R], s);
+#pragma unroll
+          for (int q = 0; q < QR; ++q) {
+            const int R = j + 1 + lane + 64 * q;
+            if (R >= j + 2 && R < n) vn[R] = (R == j + 2) ? double2{1.0, 0.0} : cmul(yv[q], s);
+          }
+          // row j+1 retires: zero it in w and v_j, and the two rows below
+          // j+2 in v_{j+1} (left there by v_{j-1})
+          if (lane == 0) {
+            sh.w[j + 1] = double2{0.0, 0.0};
+            sh.v[j & 1][j + 1] = double2{0.0, 0.0};
+            if (j >= 1) vn[j] = double2{0.0, 0.0};
+            vn[j + 1] = double2{0.0, 0.0};
+          }
           if (lead && lane == 0) {
             d[j + 1] = dg;
             e[j + 1] = beta;
@@ -1210,7 +1321,7 @@ __global__ __launch_bounds__(TRM_NT) void hetrd_mc_kernel(const double2* G, int 
     if (j == n - 2) break;
     __syncthreads();
     if (sh.abort) return;
-    trm_pass<W, false>(G, ldg, n, j, sh, vc, vn, reg, Vt + (long long)(j + 1) * n);
+    trm_pass<W, CPW, false>(G, ldg, n, j, sh, vc, vn, reg, Vt + (long long)(j + 1) * n);
     __syncthreads();
   }
 }
@@ -1699,10 +1810,11 @@ hipError_t trid_reduce(double* G, int ldg, int n, const TridWork& t, hipStream_t
     double2* pub = reinterpret_cast<double2*>(t.sync);
     auto* flags = reinterpret_cast<unsigned long long*>(t.sync + 2 * 2 * TRM_NMAX * 2);
     if (n <= 256)
-      hipLaunchKernelGGL(hetrd_mc_kernel<8>, dim3(8), dim3(TRM_NT), 0, s, g2, ldg, n, t.d, t.e, tau, vt, pub, flags, gen);
+      hipLaunchKernelGGL((hetrd_mc_kernel<16, 2>), dim3(16), dim3(TRM_NT), 0, s, g2, ldg, n, t.d, t.e, tau, vt, pub,
+                         flags, gen);
     else
-      hipLaunchKernelGGL(hetrd_mc_kernel<16>, dim3(16), dim3(TRM_NT), 0, s, g2, ldg, n, t.d, t.e, tau, vt, pub, flags,
-                         gen);
+      hipLaunchKernelGGL((hetrd_mc_kernel<32, 2>), dim3(32), dim3(TRM_NT), 0, s, g2, ldg, n, t.d, t.e, tau, vt, pub,
+                         flags, gen);
   }
   return hipGetLastError();
 }
