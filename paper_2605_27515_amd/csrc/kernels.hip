@@ -1489,24 +1489,25 @@ __global__ __launch_bounds__(64) void stein_kernel(const double* d, const double
 
 // U[:, j] = Q z_j for j < k: Q = H_0 H_1 ... H_{n-2}, H_i = I - tau_i v_i v_i^H
 // acting on rows i+1..n-1 (v_i is row i of Vt).  U complex (ld ldu), Z real.
-constexpr int ORM_B = 8;   // reflectors staged through LDS at a time
-
+//
 // One wave per vector; the reflectors are staged through LDS in blocks of
-// ORM_B by the whole workgroup, so each application reads them at LDS latency.
-// Two buffers: the next block's loads are in flight while the waves apply
-// the current one.
-constexpr int ORM_PF = ORM_B * 512 / 256;   // staged entries per thread (n <= 512)
-
+// ORM_B = 4096 / NMAX (n <= NMAX) by the whole workgroup, so each application
+// reads them at LDS latency.  Two buffers: the next block's loads are in
+// flight while the waves apply the current one, and a block holds enough
+// applications to cover their latency.
+template <int NMAX>
 __global__ __launch_bounds__(256) void ormtr_kernel(const double* Vt, const double* tau, int n, const double* Z,
                                                     int ldz, int k, double* U, int ldu) {
-  __shared__ double2 vs[2][ORM_B][512];
+  constexpr int ORM_B = 4096 / NMAX;             // reflectors per staged block
+  constexpr int ORM_PF = ORM_B * NMAX / 256;     // staged entries per thread
+  __shared__ double2 vs[2][ORM_B][NMAX];
   __shared__ double2 ts[2][ORM_B];
   const double2* Vt2 = reinterpret_cast<const double2*>(Vt);
   const double2* tau2 = reinterpret_cast<const double2*>(tau);
   const int tid = threadIdx.x, lane = tid & 63;
   const int j = blockIdx.x * 4 + (tid >> 6);
   const bool active = j < k;
-  constexpr int MAXQ = 8;   // n <= 512
+  constexpr int MAXQ = NMAX / 64;
   double ur[MAXQ], ui[MAXQ];
 #pragma unroll
   for (int q = 0; q < MAXQ; ++q) {
@@ -1841,7 +1842,11 @@ hipError_t trid_vectors(int n, const TridWork& t, const double* w, int kvec, hip
 
 hipError_t trid_backtransform(int n, const TridWork& t, int kvec, double* U, int ldu, hipStream_t s) {
   if (kvec <= 0) return hipSuccess;
-  hipLaunchKernelGGL(ormtr_kernel, dim3((kvec + 3) / 4), dim3(256), 0, s, t.Vt, t.tau, n, t.Z, n, kvec, U, ldu);
+  const dim3 grid((kvec + 3) / 4);
+  if (n <= 64) hipLaunchKernelGGL(ormtr_kernel<64>, grid, dim3(256), 0, s, t.Vt, t.tau, n, t.Z, n, kvec, U, ldu);
+  else if (n <= 128) hipLaunchKernelGGL(ormtr_kernel<128>, grid, dim3(256), 0, s, t.Vt, t.tau, n, t.Z, n, kvec, U, ldu);
+  else if (n <= 256) hipLaunchKernelGGL(ormtr_kernel<256>, grid, dim3(256), 0, s, t.Vt, t.tau, n, t.Z, n, kvec, U, ldu);
+  else hipLaunchKernelGGL(ormtr_kernel<512>, grid, dim3(256), 0, s, t.Vt, t.tau, n, t.Z, n, kvec, U, ldu);
   return hipGetLastError();
 }
 
