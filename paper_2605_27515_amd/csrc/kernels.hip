@@ -793,11 +793,10 @@ struct TrdShared {
   // their partial products by DPP (used when registers and band hold every
   // row: the global rows want a wave on 64 adjacent columns of one row)
   static constexpr int YP = (TRD_QR + 9) * PARTS >= P ? P : TRD_NT;
-  static constexpr int QL = (160 * 1024 - 1024 - 16 * (5 * P + YP)) / (16 * TRD_NT);
+  static constexpr int QL = (160 * 1024 - 1024 - 16 * (4 * P + YP)) / (16 * TRD_NT);
   static constexpr bool INTER = YP == P;
   double2 v[2][P];            // v_j, v_{j+1} by global row
   double2 w[P];               // w_j
-  double2 y[P];               // y_j, then the updated first column
   double2 fc[P];              // first column of the next block after the pass
   double2 yp[YP];             // the pass's product y_{j+1}: by column, or partial sums by thread
   double2 band[QL * TRD_NT];
@@ -956,53 +955,62 @@ __global__ __launch_bounds__(TRD_NT) void hetrd_kernel(double2* G, int ldg, int 
     const double2* vc = sh.v[j & 1];
     double2* vn = sh.v[(j & 1) ^ 1];
     if (w0) {
+      // rows j+1.. of the block, QW per lane at compile-time positions
+      constexpr int P = TRD_NT / PARTS, QW = (P + 63) / 64;
+      double2 yv[QW], xv[QW];
       // y_j = sum of the partial products, s = Re(v^H y)
       double sp = 0.0;
-      double2 y0 = double2{0.0, 0.0};
-      for (int R = j + 1 + lane; R < n; R += 64) {
+#pragma unroll
+      for (int q = 0; q < QW; ++q) {
+        const int R = j + 1 + lane + 64 * q;
         double2 y = double2{0.0, 0.0};
-        if constexpr (TrdShared<PARTS>::INTER) {
-          y = sh.yp[R];
-        } else {
-          constexpr int P = TRD_NT / PARTS;
+        if (R < n) {
+          if constexpr (TrdShared<PARTS>::INTER) {
+            y = sh.yp[R];
+          } else {
 #pragma unroll 4
-          for (int p = 0; p < PARTS; ++p) { const double2 t = sh.yp[p * P + R]; y.x += t.x; y.y += t.y; }
+            for (int p = 0; p < PARTS; ++p) { const double2 t = sh.yp[p * P + R]; y.x += t.x; y.y += t.y; }
+          }
+          const double2 v = vc[R];
+          sp += v.x * y.x + v.y * y.y;
         }
-        sh.y[R] = y;
-        if (R == j + 1 + lane) y0 = y;
-        const double2 v = vc[R];
-        sp += v.x * y.x + v.y * y.y;
+        yv[q] = y;
       }
       const bool refl = !(tr == 0.0 && ti == 0.0);
       const double h = 0.5 * (tr * tr + ti * ti) * wave_sum(sp);
       // w at the block's first row (v_j there is 1)
-      const double2 y1 = double2{read_lane(y0.x, 0), read_lane(y0.y, 0)};
+      const double2 y1 = double2{read_lane(yv[0].x, 0), read_lane(yv[0].y, 0)};
       const double2 w1 = refl ? double2{tr * y1.x - ti * y1.y - h, tr * y1.y + ti * y1.x} : double2{0.0, 0.0};
       // w = tau y - h v, and the first column after step j's update:
       // x = fc - w - v conj(w1)
       double tail = 0.0;
-      double2 x0 = double2{0.0, 0.0};
-      for (int R = j + 1 + lane; R < n; R += 64) {
-        const double2 y = sh.y[R], v = vc[R], f = sh.fc[R];
-        const double2 w = refl ? double2{tr * y.x - ti * y.y - h * v.x, tr * y.y + ti * y.x - h * v.y} : double2{0.0, 0.0};
-        sh.w[R] = w;
-        const double2 x = double2{f.x - w.x - (v.x * w1.x + v.y * w1.y), f.y - w.y - (v.y * w1.x - v.x * w1.y)};
-        sh.y[R] = x;
-        if (R == j + 1 + lane) x0 = x;
-        if (R >= j + 3) tail += x.x * x.x + x.y * x.y;
+#pragma unroll
+      for (int q = 0; q < QW; ++q) {
+        const int R = j + 1 + lane + 64 * q;
+        xv[q] = double2{0.0, 0.0};
+        if (R < n) {
+          const double2 y = yv[q], v = vc[R], f = sh.fc[R];
+          const double2 w = refl ? double2{tr * y.x - ti * y.y - h * v.x, tr * y.y + ti * y.x - h * v.y} : double2{0.0, 0.0};
+          sh.w[R] = w;
+          const double2 x = double2{f.x - w.x - (v.x * w1.x + v.y * w1.y), f.y - w.y - (v.y * w1.x - v.x * w1.y)};
+          xv[q] = x;
+          if (R >= j + 3) tail += x.x * x.x + x.y * x.y;
+        }
       }
       const double xn2 = wave_sum(tail);
-      const double dg = read_lane(x0.x, 0);
+      const double dg = read_lane(xv[0].x, 0);
       if (j == n - 2) {
         if (lane == 0) d[j + 1] = dg;
       } else {
-        const double2 alpha = double2{read_lane(x0.x, 1), read_lane(x0.y, 1)};
+        const double2 alpha = double2{read_lane(xv[0].x, 1), read_lane(xv[0].y, 1)};
         double beta;
         double2 s;
         trd_reflector(alpha, xn2, beta, tr, ti, s);
-        // same lane-to-row map as the loop that wrote sh.y
-        for (int R = j + 1 + lane; R < n; R += 64)
-          if (R >= j + 2) vn[R] = (R == j + 2) ? double2{1.0, 0.0} : cmul(sh.y[R], s);
+#pragma unroll
+        for (int q = 0; q < QW; ++q) {
+          const int R = j + 1 + lane + 64 * q;
+          if (R >= j + 2 && R < n) vn[R] = (R == j + 2) ? double2{1.0, 0.0} : cmul(xv[q], s);
+        }
         if (lane == 0) {
           d[j + 1] = dg;
           e[j + 1] = beta;
