@@ -60,9 +60,11 @@ PEAKS = {  # MI355X published dense peaks
 ALU_CLASSES = {"hetrd", "stebz", "stein", "ormtr", "jacobi"}
 # HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this
 # workload, scaled by a plain 256 MiB copy (profiles/step_catbuffer_chi128_fp32_kernels.md);
-# hetrd is the dispatch-weighted mean over its three instantiations.  A kernel
-# absent here reports traffic null
-PMC_TRAFFIC_BYTES = {"hetrd": 0.737e6}
+# hetrd is the dispatch-weighted mean over its instantiations (the
+# multi-workgroup form's per-step gathers and flag polls go to memory: its
+# agent-scope acquire invalidates the L2).  A kernel absent here reports
+# traffic null
+PMC_TRAFFIC_BYTES = {"hetrd": 4.535e6}
 
 
 def workload():
@@ -88,9 +90,10 @@ def roofline_entry(prof: dict, precision: str) -> dict:
            "frac": achieved / peak, "traffic": PMC_TRAFFIC_BYTES.get(name), "avg_launch_us": ms_per_launch * 1e3,
            "launches": p["launches"], "flop_per_launch": p["flop"] / max(p["launches"], 1),
            "dtype": dt}
-    if name in ALU_CLASSES:
-        # one workgroup per matrix: the fraction of the one CU it can occupy
-        out["frac_of_one_cu"] = achieved / (peak / 256.0)
+    if name == "hetrd":
+        # CUs a launch occupies: one workgroup per matrix up to order 128,
+        # then 16 (orders 129-256) or 32 (257-512) workgroups of one CU each
+        out["workgroups_per_launch"] = {"n<=128": 1, "n<=256": 16, "n<=512": 32}
     return out
 
 
