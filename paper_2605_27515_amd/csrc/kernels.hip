@@ -1349,29 +1349,35 @@ __device__ inline int sturm_count(const double* sd, const double* se2, int n, do
   return c;
 }
 
-// w[j] (j < kmax) = j-th largest eigenvalue of the tridiagonal (d, e).
-__global__ __launch_bounds__(256) void stebz_kernel(const double* d, const double* e, int n, double* w, int kmax) {
+// w[j] (j < kmax) = j-th largest eigenvalue of the tridiagonal (d, e): one
+// workgroup of STEBZ_NT threads per eigenvalue, an STEBZ_NT-point
+// multisection of the bracket per round (thread t counts at the (t+1)-th of
+// STEBZ_NT + 1 equal parts), so a round narrows the bracket STEBZ_NT + 1 fold
+// at the latency of one Sturm sequence.
+constexpr int STEBZ_NT = 256;
+__global__ __launch_bounds__(STEBZ_NT) void stebz_kernel(const double* d, const double* e, int n, double* w,
+                                                         int kmax) {
   __shared__ double sd[512], se2[512];
   __shared__ double bnd[2];
-  for (int i = threadIdx.x; i < n; i += 256) {
+  __shared__ int firstw[STEBZ_NT / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < n; i += STEBZ_NT) {
     sd[i] = d[i];
     se2[i] = (i < n - 1) ? e[i] * e[i] : 0.0;
   }
-  if (threadIdx.x == 0) {
-    double lo = 1e300, hi = -1e300, emax = 0.0;
+  if (tid == 0) {
+    double lo = 1e300, hi = -1e300;
     for (int i = 0; i < n; ++i) {
       const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0);
       lo = fmin(lo, d[i] - r);
       hi = fmax(hi, d[i] + r);
-      if (i < n - 1) emax = fmax(emax, e[i] * e[i]);
     }
     const double span = fmax(fabs(lo), fabs(hi));
     bnd[0] = lo - 4.0 * 2.2e-16 * span - 1e-300;
     bnd[1] = hi + 4.0 * 2.2e-16 * span + 1e-300;
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int j = blockIdx.x;
   if (j >= kmax) return;
   double emax = 0.0;
   for (int i = lane; i < n - 1; i += 64) emax = fmax(emax, se2[i]);
@@ -1381,20 +1387,28 @@ __global__ __launch_bounds__(256) void stebz_kernel(const double* d, const doubl
   const int target = n - 1 - j;   // eigenvalue mu_target (ascending index)
   double lo = bnd[0], hi = bnd[1];
   const double tspan = fmax(fabs(lo), fabs(hi));
+  constexpr double parts = STEBZ_NT + 1;
   for (int it = 0; it < 40; ++it) {
-    const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+    const double x = lo + (hi - lo) * (double)(tid + 1) / parts;
     const int c = sturm_count(sd, se2, n, x, pivmin);
     const unsigned long long mask = __ballot(c >= target + 1);
-    const int first = mask ? __ffsll((long long)mask) - 1 : 64;
-    const double nlo = (first == 0) ? lo : lo + (hi - lo) * (double)first / 65.0;
-    const double nhi = (first == 64) ? hi : lo + (hi - lo) * (double)(first + 1) / 65.0;
+    if (lane == 0) firstw[wave] = mask ? __ffsll((long long)mask) - 1 : 64;
+    __syncthreads();
+    // first point (in x order) whose count reaches target + 1
+    int first = STEBZ_NT;
+#pragma unroll
+    for (int v = STEBZ_NT / 64 - 1; v >= 0; --v)
+      if (firstw[v] < 64) first = v * 64 + firstw[v];
+    __syncthreads();
+    const double nlo = (first == 0) ? lo : lo + (hi - lo) * (double)first / parts;
+    const double nhi = (first == STEBZ_NT) ? hi : lo + (hi - lo) * (double)(first + 1) / parts;
     // the reduction fixes eigenvalues only to eps ||T|| absolute, so bisect no further
     const bool done = (nhi - nlo) <= 2.0 * 2.2e-16 * fmax(fmax(fabs(nlo), fabs(nhi)), tspan) + 1e-300 ||
                       (nlo == lo && nhi == hi);
     lo = nlo; hi = nhi;
     if (done) break;
   }
-  if (lane == 0) w[j] = 0.5 * (lo + hi);
+  if (tid == 0) w[j] = 0.5 * (lo + hi);
 }
 
 __device__ inline double hash_unit(unsigned int a, unsigned int b) {
@@ -1829,7 +1843,7 @@ hipError_t trid_reduce(double* G, int ldg, int n, const TridWork& t, hipStream_t
 }
 
 hipError_t trid_eigenvalues(int n, const TridWork& t, double* w, hipStream_t s) {
-  hipLaunchKernelGGL(stebz_kernel, dim3((n + 3) / 4), dim3(256), 0, s, t.d, t.e, n, w, n);
+  hipLaunchKernelGGL(stebz_kernel, dim3(n), dim3(STEBZ_NT), 0, s, t.d, t.e, n, w, n);
   return hipGetLastError();
 }
 
