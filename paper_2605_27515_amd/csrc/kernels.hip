@@ -1424,32 +1424,42 @@ __device__ inline double hash_unit(unsigned int a, unsigned int b) {
 // the two rows were exchanged; leaves row i+1's reduced (a, b).
 struct SteinLu { double u0, u1, u2, mult; bool swap; };
 __device__ inline SteinLu stein_lu_step(double& a, double& b, double c, double an, double bn, double tiny) {
+  // branch-free: the lanes of a wave take different pivots
   SteinLu f;
-  if (fabs(a) >= fabs(c)) {
-    const double aa = (a == 0.0) ? tiny : a;
-    f.mult = c * rcp_refined(aa);
-    f.u0 = (fabs(aa) < tiny) ? copysign(tiny, aa) : aa;
-    f.u1 = b; f.u2 = 0.0; f.swap = false;
-    a = an - f.mult * b;
-    b = bn;
-  } else {
-    f.mult = a * rcp_refined(c);
-    f.u0 = (fabs(c) < tiny) ? copysign(tiny, c) : c;
-    f.u1 = an; f.u2 = bn; f.swap = true;
-    a = b - f.mult * an;
-    b = -f.mult * bn;
-  }
+  const bool sw = fabs(a) < fabs(c);
+  const double aa = (a == 0.0) ? tiny : a;
+  const double den = sw ? c : aa, num = sw ? a : c;
+  f.mult = num * rcp_refined(den);
+  f.u0 = (fabs(den) < tiny) ? copysign(tiny, den) : den;
+  f.u1 = sw ? an : b;
+  f.u2 = sw ? bn : 0.0;
+  f.swap = sw;
+  const double na = sw ? b - f.mult * an : an - f.mult * b;
+  b = sw ? -f.mult * bn : bn;
+  a = na;
   return f;
 }
 __device__ inline double stein_last_pivot(double a, double tiny) {
   return (fabs(a) < tiny) ? copysign(tiny, a == 0.0 ? 1.0 : a) : a;
 }
 // eps ||T||_inf of the tridiagonal (d, e): the pivot floor of the factorisation
+__device__ inline double stein_row_norm(const double* sd, const double* se, int i) {
+  return fabs(sd[i]) + fabs(se[i]) + (i > 0 ? fabs(se[i - 1]) : 0.0);
+}
 __device__ inline double stein_tiny(const double* sd, const double* se, int n) {
   double tnorm = 0.0;
-  for (int i = 0; i < n; ++i) tnorm = fmax(tnorm, fabs(sd[i]) + fabs(se[i]) + (i > 0 ? fabs(se[i - 1]) : 0.0));
+  for (int i = 0; i < n; ++i) tnorm = fmax(tnorm, stein_row_norm(sd, se, i));
   return fmax(tnorm, 1e-300) * 2.2e-16;
 }
+// the same by the T (a power of two <= 64) threads of a one-wave workgroup
+// together (a maximum: the same value in any order)
+__device__ inline double stein_tiny_wave(const double* sd, const double* se, int n, int T) {
+  double tnorm = 0.0;
+  for (int i = threadIdx.x; i < n; i += T) tnorm = fmax(tnorm, stein_row_norm(sd, se, i));
+  for (int o = T >> 1; o > 0; o >>= 1) tnorm = fmax(tnorm, __shfl_xor(tnorm, o, T));
+  return fmax(tnorm, 1e-300) * 2.2e-16;
+}
+
 
 // Z[i*ldz + j] (j < k): unit eigenvector of the tridiagonal for w[j], by one
 // solve with the pivoted LU of T - w_j I from a hashed start vector (which
@@ -1458,13 +1468,19 @@ __global__ __launch_bounds__(64) void stein_kernel(const double* d, const double
                                                    int k, double* Z, int ldz) {
   // per-thread working arrays in LDS, [array][i][thread] (blockDim.x threads)
   extern __shared__ double lds[];
-  __shared__ double sd[512], se[512];
+  __shared__ double sd[512], se[512], rs[512];
   const int T = blockDim.x, t = threadIdx.x;
-  for (int i = t; i < n; i += T) { sd[i] = d[i]; se[i] = (i < n - 1) ? e[i] : 0.0; }
+  // rs: one pseudo-random vector; eigenvector j starts from it rotated by j
+#pragma unroll 8
+  for (int i = t; i < n; i += T) {
+    sd[i] = d[i];
+    se[i] = (i < n - 1) ? e[i] : 0.0;
+    rs[i] = hash_unit((unsigned)i, 0x5BD1E995u);
+  }
   __syncthreads();
+  const double tiny = stein_tiny_wave(sd, se, n, T);
   const int j = blockIdx.x * T + t;
   if (j >= k) return;
-  const double tiny = stein_tiny(sd, se, n);
   const double lam = w[j];
   double* sU0 = lds;                    // 1 / u0: the reciprocal is off the recurrence
   double* sU1 = lds + (long long)n * T;
@@ -1474,38 +1490,44 @@ __global__ __launch_bounds__(64) void stein_kernel(const double* d, const double
   // factorisation with the forward elimination of the start vector folded in
   // (its rows are eliminated in the same order)
   double a = sd[0] - lam, b = (n > 1) ? se[0] : 0.0;
-  double cur = hash_unit(0u, (unsigned)j);
+  int ri = j % n;
+  double cur = rs[ri];
+#pragma unroll 2
   for (int i = 0; i < n - 1; ++i) {
-    const double bn = (i + 1 < n - 1) ? se[i + 1] : 0.0;
-    double nxt = hash_unit((unsigned)(i + 1), (unsigned)j);
-    const SteinLu f = stein_lu_step(a, b, se[i], sd[i + 1] - lam, bn, tiny);
-    if (f.swap) { const double tt = cur; cur = nxt; nxt = tt; }
-    sU0[SX(i)] = 1.0 / f.u0; sU1[SX(i)] = f.u1; sU2[SX(i)] = f.u2;
-    nxt -= f.mult * cur;
-    sZ[SX(i)] = cur;
-    cur = nxt;
+    ri = (ri + 1 == n) ? 0 : ri + 1;
+    const double nxt = rs[ri];
+    // se[n - 1] = 0: row i+1's superdiagonal without a bound test
+    const SteinLu f = stein_lu_step(a, b, se[i], sd[i + 1] - lam, se[i + 1], tiny);
+    const double lo_ = f.swap ? nxt : cur, hi_ = f.swap ? cur : nxt;
+    sU0[SX(i)] = rcp_refined(f.u0); sU1[SX(i)] = f.u1; sU2[SX(i)] = f.u2;
+    sZ[SX(i)] = lo_;
+    cur = hi_ - f.mult * lo_;
   }
-  sU0[SX(n - 1)] = 1.0 / stein_last_pivot(a, tiny); sU1[SX(n - 1)] = 0.0; sU2[SX(n - 1)] = 0.0;
+  sU0[SX(n - 1)] = rcp_refined(stein_last_pivot(a, tiny)); sU1[SX(n - 1)] = 0.0; sU2[SX(n - 1)] = 0.0;
   sZ[SX(n - 1)] = cur;
-  // backward substitution with the upper factor (bandwidth 3), then unit norm
+  // backward substitution with the upper factor (bandwidth 3), then unit
+  // norm and the sign that makes the largest-magnitude component positive
+  double zmax = 0.0, zmin = 0.0;
   {
-    double z1 = 0.0, z2 = 0.0, big = 0.0;
+    double z1 = 0.0, z2 = 0.0;
+#pragma unroll 4
     for (int i = n - 1; i >= 0; --i) {
-      const double z = (sZ[SX(i)] - sU1[SX(i)] * z1 - sU2[SX(i)] * z2) * sU0[SX(i)];
+      const double z = (sZ[SX(i)] - sU2[SX(i)] * z2 - sU1[SX(i)] * z1) * sU0[SX(i)];
       sZ[SX(i)] = z;
       z2 = z1; z1 = z;
-      big = fmax(big, fabs(z));
+      zmax = fmax(zmax, z);
+      zmin = fmin(zmin, z);
     }
-    const double inv = (big > 0.0) ? 1.0 / big : 1.0;
-    double nrm = 0.0;
-    for (int i = 0; i < n; ++i) { const double z = sZ[SX(i)] * inv; nrm += z * z; sZ[SX(i)] = z; }
-    const double sc = 1.0 / sqrt(fmax(nrm, 1e-300));
-    for (int i = 0; i < n; ++i) sZ[SX(i)] *= sc;
   }
-  // deterministic sign: largest-magnitude component positive
-  double big = 0.0, sg = 1.0;
-  for (int i = 0; i < n; ++i) { const double z = sZ[SX(i)]; if (fabs(z) > big) { big = fabs(z); sg = z < 0 ? -1.0 : 1.0; } }
-  for (int i = 0; i < n; ++i) Z[(long long)i * ldz + j] = sg * sZ[SX(i)];
+  // the largest-magnitude component is made positive (a positive one on a tie)
+  const double big = fmax(zmax, -zmin), zbig = (zmax >= -zmin) ? 1.0 : -1.0;
+  const double inv = (big > 0.0) ? 1.0 / big : 1.0;
+  double nrm = 0.0;
+#pragma unroll 8
+  for (int i = 0; i < n; ++i) { const double z = sZ[SX(i)] * inv; nrm += z * z; }
+  const double sc = (zbig < 0.0 ? -inv : inv) / sqrt(fmax(nrm, 1e-300));
+#pragma unroll 8
+  for (int i = 0; i < n; ++i) Z[(long long)i * ldz + j] = sZ[SX(i)] * sc;
 #undef SX
 }
 
