@@ -1035,23 +1035,43 @@ __global__ __launch_bounds__(TRD_NT) void hetrd_kernel(double2* G, int ldg, int 
 //
 // One exchange per step.  The pass of step j-1 (rank-2 update of step j-1
 // fused with the product y_j = B_j v_j) leaves in every workgroup y_j on its
-// columns and row j+1 of B_j on its columns; wave 0 publishes both to `pub`
-// and raises its flag.  Once every flag is up, each workgroup gathers the
-// whole y_j and row j+1, which is column j+1 conjugated (B_j is Hermitian),
-// and redundantly forms w_j, the updated column j+1 and reflector j+1, so the
-// next pass starts without a second exchange.  Flags carry a per-launch
-// generation tag, so the sync block needs no clearing; every wait is bounded
-// (after TRM_WAIT_TICKS of the 100 MHz wall clock a workgroup raises the
-// abort word, all workgroups leave, and d is set to NaN).  The workgroups of
-// one launch must run concurrently: W of them, one CU each.
+// columns and row j+1 of B_j on its columns; wave 0 posts both to step j's
+// mailbox slots, each double by a 64-bit relaxed agent-scope atomic store
+// over a sentinel that no computation yields.  Each workgroup then gathers
+// the whole y_j and row j+1 (column j+1 conjugated: B_j is Hermitian) by
+// polling those slots with relaxed atomic loads until no sentinel is left:
+// a slot is written once per launch, so a value other than the sentinel is
+// the posted one (coherence of a single location), and no fence or flag is
+// needed.  It then redundantly forms w_j, the updated column j+1 and
+// reflector j+1, so the next pass starts without a second exchange.  Every
+// wait is bounded (after TRM_WAIT_TICKS of the 100 MHz wall clock a
+// workgroup raises the generation-tagged abort word, all workgroups leave,
+// and d is set to NaN).  The workgroups of one launch must run concurrently:
+// W of them, one CU each.
 constexpr int TRM_NT = 512;                      // 8 waves
 constexpr int TRM_WMAX = 32;                     // workgroups, at most
 constexpr int TRM_NMAX = 512;                    // order, at most
-constexpr int TRM_FLAG_STRIDE = 16;              // one 128-byte line per flag
 constexpr long long TRM_WAIT_TICKS = 200000000;  // 2 s
-// sync block in doubles: pub[2 parities][2 kinds][TRM_NMAX] complex, then
-// TRM_WMAX flags and the abort word, one line each
-constexpr size_t TRM_SYNC_DOUBLES = (size_t)2 * 2 * TRM_NMAX * 2 + (size_t)(TRM_WMAX + 1) * TRM_FLAG_STRIDE;
+// sync block in doubles: the abort word (one 128-byte line), then the
+// mailboxes Y[n][n] and F[n][n] (complex, step-major): slot [j][c] receives
+// y_j[c] and row j+1 of B_j at column c, each double posted once per launch
+// over the sentinel that trm_clear_kernel writes before the launch
+__host__ __device__ constexpr size_t trm_sync_doubles(int n) { return 16 + (size_t)4 * n * n; }
+constexpr unsigned long long TRM_EMPTY = ~0ull;  // sentinel: a NaN no computation yields
+
+__device__ inline void trm_post(double* p, double x) {
+  unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  if (b == TRM_EMPTY) b = 0x7FF8000000000000ull;   // keep the sentinel unique
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline unsigned long long trm_peek(const double* p) {
+  return __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void trm_clear_kernel(unsigned long long* p, long long count) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
+    p[i] = TRM_EMPTY;
+}
 
 template <int NMAX, int CPW>
 struct TrmShared {
@@ -1183,14 +1203,13 @@ __device__ inline void trm_pass(const double2* G, int ldg, int n, int j, TrmShar
 
 template <int W, int CPW>
 __global__ __launch_bounds__(TRM_NT) void hetrd_mc_kernel(const double2* G, int ldg, int n, double* d, double* e,
-                                                          double2* tau, double2* Vt, double2* pub,
-                                                          unsigned long long* flags, unsigned gen) {
+                                                          double2* tau, double2* Vt, double* mail,
+                                                          unsigned long long* abortw, unsigned gen) {
   constexpr int LC = 8 * CPW, NMAX = W * LC, QR = NMAX / 64;
-  static_assert(W <= TRM_WMAX && NMAX <= TRM_NMAX && W < 64, "sync block layout");
+  static_assert(W <= TRM_WMAX && NMAX <= TRM_NMAX, "sync block layout");
   __shared__ TrmShared<NMAX, CPW> sh;
   const int tid = threadIdx.x, lane = tid & 63, g = blockIdx.x;
   const bool w0 = tid < 64, lead = (g == 0);
-  unsigned long long* abortw = flags + TRM_WMAX * TRM_FLAG_STRIDE;
   double2 reg[CPW][QR];
   double tr = 0.0, ti = 0.0;   // tau_j, held by wave 0
   if (tid == 0) sh.abort = 0;
@@ -1226,30 +1245,45 @@ __global__ __launch_bounds__(TRM_NT) void hetrd_mc_kernel(const double2* G, int 
     const double2* vc = sh.v[j & 1];
     double2* vn = sh.v[(j & 1) ^ 1];
     if (w0) {
-      // publish y_j and row j+1 on this workgroup's columns, raise the flag
-      double2* py = pub + (size_t)((j & 1) * 2) * TRM_NMAX;
-      double2* pf = py + TRM_NMAX;
+      // post y_j and row j+1 on this workgroup's columns to step j's slots
+      double* my = mail + (size_t)2 * j * n;
+      double* mf = my + (size_t)2 * n * n;
       if (lane < LC) {
         const int cc = lane * W + g;
-        if (cc > j && cc < n) { py[cc] = sh.yp[lane]; pf[cc] = sh.fr[lane]; }
+        if (cc > j && cc < n) {
+          const double2 a = sh.yp[lane], b = sh.fr[lane];
+          trm_post(&my[2 * cc], a.x); trm_post(&my[2 * cc + 1], a.y);
+          trm_post(&mf[2 * cc], b.x); trm_post(&mf[2 * cc + 1], b.y);
+        }
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      const unsigned long long tag = ((unsigned long long)gen << 32) | (unsigned)(j + 1);
-      if (lane == 0) __hip_atomic_store(&flags[g * TRM_FLAG_STRIDE], tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      // wait for every workgroup's step-j data (bounded)
+      // gather y_j and row j+1 (rows j+1.. at compile-time positions): every
+      // double is polled until it is no longer the sentinel (bounded wait)
+      double2 yv[QR], fv[QR];
+      unsigned pending = 0;
+#pragma unroll
+      for (int q = 0; q < QR; ++q) {
+        yv[q] = double2{0.0, 0.0}; fv[q] = double2{0.0, 0.0};
+        if (j + 1 + lane + 64 * q < n) pending |= 1u << q;
+      }
       const long long t0 = (long long)wall_clock64();
       bool abort = false;
       for (;;) {
-        bool ok = true;
-        if (lane < W) {
-          const unsigned long long f =
-              __hip_atomic_load(&flags[lane * TRM_FLAG_STRIDE], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          ok = (unsigned)(f >> 32) == gen && (unsigned)f >= (unsigned)(j + 1);
-        } else if (lane == W) {
-          ok = __hip_atomic_load(abortw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != (unsigned long long)gen;
-          if (!ok) abort = true;
+#pragma unroll
+        for (int q = 0; q < QR; ++q) {
+          if (pending & (1u << q)) {
+            const int R = j + 1 + lane + 64 * q;
+            const unsigned long long a0 = trm_peek(&my[2 * R]), a1 = trm_peek(&my[2 * R + 1]);
+            const unsigned long long b0 = trm_peek(&mf[2 * R]), b1 = trm_peek(&mf[2 * R + 1]);
+            if (a0 != TRM_EMPTY && a1 != TRM_EMPTY && b0 != TRM_EMPTY && b1 != TRM_EMPTY) {
+              yv[q] = double2{__longlong_as_double((long long)a0), __longlong_as_double((long long)a1)};
+              fv[q] = double2{__longlong_as_double((long long)b0), __longlong_as_double((long long)b1)};
+              pending &= ~(1u << q);
+            }
+          }
         }
-        if (__ballot(!ok) == 0ull) break;
+        if (__ballot(pending != 0) == 0ull) break;
+        if (lane == 0)
+          abort = __hip_atomic_load(abortw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned long long)gen;
         abort = __ballot(abort) != 0ull;
         if (!abort && (long long)wall_clock64() - t0 > TRM_WAIT_TICKS) {
           if (lane == 0) __hip_atomic_store(abortw, (unsigned long long)gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1258,20 +1292,12 @@ __global__ __launch_bounds__(TRM_NT) void hetrd_mc_kernel(const double2* G, int 
         if (abort) break;
         __builtin_amdgcn_s_sleep(1);
       }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       if (abort) {
         for (int R = lane; R < n; R += 64) d[R] = __builtin_nan("");
         if (lane == 0) sh.abort = 1;
       } else {
-        // gather y_j and row j+1 in one round trip; s = Re(v^H y)
-        double2 yv[QR], fv[QR];
+        // s = Re(v^H y)
         double sp = 0.0;
-#pragma unroll
-        for (int q = 0; q < QR; ++q) {
-          const int R = j + 1 + lane + 64 * q;
-          yv[q] = double2{0.0, 0.0}; fv[q] = double2{0.0, 0.0};
-          if (R < n) { yv[q] = py[R]; fv[q] = pf[R]; }
-        }
 #pragma unroll
         for (int q = 0; q < QR; ++q) {
           const int R = j + 1 + lane + 64 * q;
@@ -1852,14 +1878,20 @@ hipError_t trid_reduce(double* G, int ldg, int n, const TridWork& t, hipStream_t
     static std::atomic<unsigned> next_gen{1};
     unsigned gen = next_gen.fetch_add(1, std::memory_order_relaxed);
     if (gen == 0) gen = next_gen.fetch_add(1, std::memory_order_relaxed);
-    double2* pub = reinterpret_cast<double2*>(t.sync);
-    auto* flags = reinterpret_cast<unsigned long long*>(t.sync + 2 * 2 * TRM_NMAX * 2);
+    auto* abortw = reinterpret_cast<unsigned long long*>(t.sync);
+    double* mail = t.sync + 16;
+    // the mailboxes start at the sentinel (a fill kernel: no memset node)
+    const long long cnt = (long long)4 * n * n;
+    hipLaunchKernelGGL(trm_clear_kernel, dim3((unsigned)std::min<long long>((cnt + 255) / 256, 1024)), dim3(256), 0, s,
+                       reinterpret_cast<unsigned long long*>(mail), cnt);
+    hipError_t ce = hipGetLastError();
+    if (ce != hipSuccess) return ce;
     if (n <= 256)
-      hipLaunchKernelGGL((hetrd_mc_kernel<16, 2>), dim3(16), dim3(TRM_NT), 0, s, g2, ldg, n, t.d, t.e, tau, vt, pub,
-                         flags, gen);
+      hipLaunchKernelGGL((hetrd_mc_kernel<16, 2>), dim3(16), dim3(TRM_NT), 0, s, g2, ldg, n, t.d, t.e, tau, vt, mail,
+                         abortw, gen);
     else
-      hipLaunchKernelGGL((hetrd_mc_kernel<32, 2>), dim3(32), dim3(TRM_NT), 0, s, g2, ldg, n, t.d, t.e, tau, vt, pub,
-                         flags, gen);
+      hipLaunchKernelGGL((hetrd_mc_kernel<32, 2>), dim3(32), dim3(TRM_NT), 0, s, g2, ldg, n, t.d, t.e, tau, vt, mail,
+                         abortw, gen);
   }
   return hipGetLastError();
 }
@@ -1907,7 +1939,7 @@ hipError_t heev_tridiag(double* G, int ldg, int n, double* w, double* U, int ldu
 }
 
 size_t heev_tridiag_work_doubles(int n) {
-  return (size_t)4 * n + 2 * (size_t)n * n + (size_t)n * n + 16 + TRM_SYNC_DOUBLES + 64;
+  return (size_t)4 * n + 2 * (size_t)n * n + (size_t)n * n + 16 + trm_sync_doubles(n) + 64;
 }
 
 // K split so that about 32 partial tiles run (each at least 64 deep); the
