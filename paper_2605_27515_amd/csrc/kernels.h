@@ -55,7 +55,7 @@ size_t heev_tridiag_work_doubles(int n);
 
 // The same four stages, callable one by one (for per-stage timing).
 struct TridWork {
-  double *d, *e, *tau, *Vt, *Z, *sync;
+  double *d, *e, *tau, *Vt, *Z, *wy, *sync;
 };
 TridWork trid_work(double* work, int n);
 hipError_t trid_reduce(double* G, int ldg, int n, const TridWork& t, hipStream_t stream);

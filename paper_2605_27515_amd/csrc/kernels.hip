@@ -7,8 +7,8 @@
 //                  split-K with a fixed-order reduction.
 //  * heev_kernel   Hermitian eigen-decomposition by cyclic Jacobi with the
 //                  round-robin parallel ordering (one workgroup per matrix).
-//  * tridiagonal route (hetrd_kernel, stebz_kernel, stein_kernel,
-//                  stein_groups_kernel, stein_unresolved_kernel, ormtr_kernel):
+//  * tridiagonal route (hetrd_kernel / hetrd_mc_kernel, stebz_kernel, stein_kernel,
+//                  stein_groups_kernel, stein_unresolved_kernel, orm_t_kernel + ormtr_wy_kernel):
 //                  Householder reduction to real tridiagonal form,
 //                  eigenvalues by Sturm-count
 //                  multisection, eigenvectors by inverse iteration made
@@ -661,7 +661,8 @@ hipError_t gram_stats(const double* E, int n, double* out, hipStream_t s) {
 //                    multisection, one wave per eigenvalue
 //   3. stein_kernel  eigenvectors of T by inverse iteration, one lane per
 //                    eigenvalue (pivoted tridiagonal LU, one solve)
-//   4. ormtr_kernel  back-transformation U = Q Z, one wave per column
+//   4. ormtr_wy_kernel  back-transformation U = Q Z, one wave per column,
+//                    reflectors in blocks of the compact WY form (orm_t_kernel)
 // ---------------------------------------------------------------------------
 namespace lbk {
 
@@ -1559,102 +1560,219 @@ __global__ __launch_bounds__(64) void stein_kernel(const double* d, const double
 
 // U[:, j] = Q z_j for j < k: Q = H_0 H_1 ... H_{n-2}, H_i = I - tau_i v_i v_i^H
 // acting on rows i+1..n-1 (v_i is row i of Vt).  U complex (ld ldu), Z real.
-//
-// One wave per vector; the reflectors are staged through LDS in blocks of
-// ORM_B = 4096 / NMAX (n <= NMAX) by the whole workgroup, so each application
-// reads them at LDS latency.  Two buffers: the next block's loads are in
-// flight while the waves apply the current one, and a block holds enough
-// applications to cover their latency.
-template <int NMAX>
-__global__ __launch_bounds__(256) void ormtr_kernel(const double* Vt, const double* tau, int n, const double* Z,
-                                                    int ldz, int k, double* U, int ldu) {
-  constexpr int ORM_B = 4096 / NMAX;             // reflectors per staged block
-  constexpr int ORM_PF = ORM_B * NMAX / 256;     // staged entries per thread
-  __shared__ double2 vs[2][ORM_B][NMAX];
-  __shared__ double2 ts[2][ORM_B];
+// One wave per vector; the reflectors are staged through LDS in blocks, two
+// buffers (the next block loads while the current one is applied).
+// The reflectors are applied B at a time in the compact WY form.  Block bi holds reflectors lo..hi (hi = n-2-bi B,
+// lo = max(hi-B+1, 0)), applied to a vector together as
+// P = H_lo H_{lo+1} ... H_hi = I - V T V^H, V = [v_lo .. v_hi] (column p is
+// v_{lo+p}) and T upper triangular with T_pp = tau_{lo+p} and
+// T[0:p, p] = -tau_{lo+p} T[0:p, 0:p] (V[:, 0:p]^H v_{lo+p}) (the forward
+// accumulation of a product of reflectors; a zero tau gives a zero column).
+// orm_t_kernel forms every block's T (one workgroup per block, Tw[bi] is
+// B x B complex, row-major); ormtr_wy_kernel applies P u = u - V (T (V^H u)):
+// the B dot products of a block fold over the wave together, by one
+// transposed reduction, instead of two wave sums per reflector.
+__host__ __device__ constexpr int orm_wy_b(int nmax) { return nmax <= 256 ? 16 : 8; }
+// doubles of the T factors of all blocks, for any n <= 512
+__host__ __device__ constexpr size_t orm_wy_doubles(int n) { return (size_t)2 * 16 * (n + 16); }
+
+template <int B, int NMAX>
+__global__ __launch_bounds__(256) void orm_t_kernel(const double* Vt, const double* tau, int n, double* Tw) {
+  __shared__ double2 vs[B][NMAX];
+  __shared__ double2 S[B][B];
+  __shared__ double2 T[B][B];
   const double2* Vt2 = reinterpret_cast<const double2*>(Vt);
   const double2* tau2 = reinterpret_cast<const double2*>(tau);
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int j = blockIdx.x * 4 + (tid >> 6);
-  const bool active = j < k;
-  constexpr int MAXQ = NMAX / 64;
-  double ur[MAXQ], ui[MAXQ];
+  const int tid = threadIdx.x, bi = blockIdx.x;
+  const int hi = n - 2 - bi * B, lo = max(hi - B + 1, 0), nb = hi - lo + 1;
+  for (int idx = tid; idx < B * NMAX; idx += 256) {
+    const int q = idx / NMAX, r = idx % NMAX, i = lo + q;
+    vs[q][r] = (q < nb && r > i && r < n) ? Vt2[(long long)i * n + r] : double2{0.0, 0.0};
+  }
+  __syncthreads();
+  // S[p][q] = v_p^H v_q for p < q; the start row is rotated by q so that the
+  // threads of one p read different banks
+  for (int pq = tid; pq < B * B; pq += 256) {
+    const int p = pq / B, q = pq % B;
+    double sr = 0.0, si = 0.0;
+    if (p < q && q < nb) {
+      int r = (2 * q) % n;
+      for (int c = 0; c < n; ++c) {
+        const double2 a = vs[p][r], b = vs[q][r];
+        sr += a.x * b.x + a.y * b.y;
+        si += a.x * b.y - a.y * b.x;
+        r = (r + 1 == n) ? 0 : r + 1;
+      }
+    }
+    S[p][q] = double2{sr, si};
+  }
+  __syncthreads();
+  // the forward recurrence, column by column; lane i owns row i of T
+  if (tid < 64) {
+    const int i = tid;
+    for (int p = 0; p < B; ++p) {
+      const double2 tp = (p < nb) ? tau2[lo + p] : double2{0.0, 0.0};
+      double wr = 0.0, wi = 0.0;
+      if (i < p)
+        for (int q = i; q < p; ++q) {
+          const double2 t = T[i][q], sq = S[q][p];
+          wr += t.x * sq.x - t.y * sq.y;
+          wi += t.x * sq.y + t.y * sq.x;
+        }
+      if (i < B) T[i][p] = (i < p) ? double2{-(tp.x * wr - tp.y * wi), -(tp.x * wi + tp.y * wr)}
+                                   : (i == p ? tp : double2{0.0, 0.0});
+    }
+    if (i < B) {
+      double2* out = reinterpret_cast<double2*>(Tw) + (size_t)bi * B * B + (size_t)i * B;
+      for (int p = 0; p < B; ++p) out[p] = T[i][p];
+    }
+  }
+}
+
+// Sum over the 64 lanes of NV values at once (NV a power of two <= 64): at
+// stage s lanes l and l ^ 2^s swap halves of their remaining values, the one
+// with bit s set keeping the upper half, so after log2 NV stages a lane holds
+// one value, summed over 2^(log2 NV) lanes; the remaining stages are plain
+// sums.  Returns the total of value index sum_s bit_s(l) * NV / 2^(s+1).
+// Stages 0 and 1 use DPP quad permutes, the others lane shuffles.  All 64
+// lanes active.
+template <int NV, int S>
+__device__ inline void wave_reduce_many_stage(double (&v)[NV], int lane) {
+  constexpr int h = NV >> (S + 1);
+  if constexpr (h >= 1) {
+    const bool up = (lane >> S) & 1;
 #pragma unroll
-  for (int q = 0; q < MAXQ; ++q) {
+    for (int i = 0; i < h; ++i) {
+      const double send = up ? v[i] : v[i + h];
+      const double keep = up ? v[i + h] : v[i];
+      double recv;
+      if constexpr (S == 0) recv = dpp_f64<0xB1, 0xF>(0.0, send);        // quad_perm [1,0,3,2]: lane ^ 1
+      else if constexpr (S == 1) recv = dpp_f64<0x4E, 0xF>(0.0, send);   // quad_perm [2,3,0,1]: lane ^ 2
+      else recv = __shfl_xor(send, 1 << S, 64);
+      v[i] = keep + recv;
+    }
+    wave_reduce_many_stage<NV, S + 1>(v, lane);
+  }
+}
+template <int NV>
+__device__ inline double wave_reduce_many(double (&v)[NV], int lane) {
+  wave_reduce_many_stage<NV, 0>(v, lane);
+  double t = v[0];
+#pragma unroll
+  for (int s = 0; s < 6; ++s)
+    if ((NV >> s) <= 1) t += __shfl_xor(t, 1 << s, 64);
+  return t;
+}
+template <int NV>
+__device__ inline int wave_reduce_many_index(int lane) {
+  int idx = 0;
+#pragma unroll
+  for (int s = 0; (NV >> (s + 1)) >= 1; ++s) idx += ((lane >> s) & 1) * (NV >> (s + 1));
+  return idx;
+}
+
+template <int B, int NMAX>
+__global__ __launch_bounds__(256) void ormtr_wy_kernel(const double* Vt, const double* Tw, int n, const double* Z,
+                                                       int ldz, int k, double* U, int ldu) {
+  constexpr int PF = B * NMAX / 256;   // staged V entries per thread
+  constexpr int QW = NMAX / 64;        // rows per lane
+  constexpr int NV = 2 * B;            // values folded per block
+  __shared__ double2 vs[2][B][NMAX];
+  __shared__ double2 ts[2][B][B];
+  __shared__ double xs[4][NV];
+  __shared__ double2 ys[4][B];
+  const double2* Vt2 = reinterpret_cast<const double2*>(Vt);
+  const double2* Tw2 = reinterpret_cast<const double2*>(Tw);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int j = blockIdx.x * 4 + wave;
+  const bool active = j < k;
+  double ur[QW], ui[QW];
+#pragma unroll
+  for (int q = 0; q < QW; ++q) {
     const int r = lane + 64 * q;
     ur[q] = (active && r < n) ? Z[(long long)r * ldz + j] : 0.0;
     ui[q] = 0.0;
   }
-  // block starting at reflector ih holds ih, ih-1, ..., ih-nb+1; row b of a
-  // block is reflector ih-b on columns > ih-b (zero elsewhere)
-  double2 pf[ORM_PF];
+  const int nblk = (n - 1 + B - 1) / B;
+  double2 pf[PF];
   double2 tpf = double2{0.0, 0.0};
-  auto fetch = [&](int ih) {
-    const int nb = min(ORM_B, ih + 1);
+  auto fetch = [&](int bi) {
+    const int hi = n - 2 - bi * B, lo = max(hi - B + 1, 0), nb = hi - lo + 1;
 #pragma unroll
-    for (int u = 0; u < ORM_PF; ++u) {
-      const int idx = tid + u * 256;
-      pf[u] = double2{0.0, 0.0};
-      if (idx < nb * n) {
-        const int bb = idx / n, r = idx % n, i = ih - bb;
-        if (r > i) pf[u] = Vt2[(long long)i * n + r];
-      }
+    for (int u = 0; u < PF; ++u) {
+      const int idx = tid + u * 256, q = idx / NMAX, r = idx % NMAX, i = lo + q;
+      pf[u] = (q < nb && r > i && r < n) ? Vt2[(long long)i * n + r] : double2{0.0, 0.0};
     }
-    if (tid < nb) tpf = tau2[ih - tid];
+    if (tid < B * B) tpf = Tw2[(size_t)bi * B * B + tid];
   };
-  auto commit = [&](int buf, int ih) {
-    const int nb = min(ORM_B, ih + 1);
+  auto commit = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < ORM_PF; ++u) {
+    for (int u = 0; u < PF; ++u) {
       const int idx = tid + u * 256;
-      if (idx < nb * n) vs[buf][idx / n][idx % n] = pf[u];
+      vs[buf][idx / NMAX][idx % NMAX] = pf[u];
     }
-    if (tid < nb) ts[buf][tid] = tpf;
+    if (tid < B * B) ts[buf][tid / B][tid % B] = tpf;
   };
-  fetch(n - 2);
-  commit(0, n - 2);
+  if (nblk > 0) {
+    fetch(0);
+    commit(0);
+  }
   __syncthreads();
-  int buf = 0;
-  for (int ih = n - 2; ih >= 0; ih -= ORM_B, buf ^= 1) {
-    const int nb = min(ORM_B, ih + 1);
-    const int ihn = ih - ORM_B;
-    if (ihn >= 0) fetch(ihn);
+  const int vidx = wave_reduce_many_index<NV>(lane);
+  for (int bi = 0, buf = 0; bi < nblk; ++bi, buf ^= 1) {
+    if (bi + 1 < nblk) fetch(bi + 1);
     if (active) {
-      for (int bb = 0; bb < nb; ++bb) {
-        const double tr = ts[buf][bb].x, ti = ts[buf][bb].y;
-        if (tr == 0.0 && ti == 0.0) continue;
-        const double2* v = vs[buf][bb];
-        double dr = 0.0, di = 0.0;
+      // x = V^H u, NV partial sums per lane
+      double xv[NV];
 #pragma unroll
-        for (int q = 0; q < MAXQ; ++q) {
-          const int r = lane + 64 * q;
-          if (r < n) {
-            const double2 a = v[r];
-            dr += a.x * ur[q] + a.y * ui[q];          // conj(v) u
-            di += a.x * ui[q] - a.y * ur[q];
-          }
+      for (int i = 0; i < NV; ++i) xv[i] = 0.0;
+#pragma unroll
+      for (int p = 0; p < B; ++p) {
+#pragma unroll
+        for (int q = 0; q < QW; ++q) {
+          const double2 a = vs[buf][p][lane + 64 * q];
+          xv[2 * p] = fma(a.x, ur[q], fma(a.y, ui[q], xv[2 * p]));
+          xv[2 * p + 1] = fma(a.x, ui[q], fma(-a.y, ur[q], xv[2 * p + 1]));
         }
-        dr = wave_sum(dr);
-        di = wave_sum(di);
-        // u -= tau v (v^H u)
-        const double fr = tr * dr - ti * di, fi = tr * di + ti * dr;
+      }
+      const double xt = wave_reduce_many<NV>(xv, lane);
+      if (lane < NV) xs[wave][vidx] = xt;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+      // y = T x, lane p forms y_p
+      if (lane < B) {
+        const int p = lane;
+        double yr = 0.0, yi = 0.0;
+        for (int q = p; q < B; ++q) {
+          const double2 t = ts[buf][p][q];
+          const double xr = xs[wave][2 * q], xi = xs[wave][2 * q + 1];
+          yr += t.x * xr - t.y * xi;
+          yi += t.x * xi + t.y * xr;
+        }
+        ys[wave][p] = double2{yr, yi};
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+      // u -= V y
 #pragma unroll
-        for (int q = 0; q < MAXQ; ++q) {
-          const int r = lane + 64 * q;
-          if (r < n) {
-            const double2 a = v[r];
-            ur[q] -= a.x * fr - a.y * fi;
-            ui[q] -= a.x * fi + a.y * fr;
-          }
+      for (int p = 0; p < B; ++p) {
+        const double2 y = ys[wave][p];
+#pragma unroll
+        for (int q = 0; q < QW; ++q) {
+          const double2 a = vs[buf][p][lane + 64 * q];
+          ur[q] -= a.x * y.x - a.y * y.y;
+          ui[q] -= a.x * y.y + a.y * y.x;
         }
       }
     }
-    if (ihn >= 0) commit(buf ^ 1, ihn);
+    if (bi + 1 < nblk) commit(buf ^ 1);
     __syncthreads();
   }
   if (!active) return;
 #pragma unroll
-  for (int q = 0; q < MAXQ; ++q) {
+  for (int q = 0; q < QW; ++q) {
     const int r = lane + 64 * q;
     if (r < n) {
       U[2 * ((long long)r * ldu + j)] = ur[q];
@@ -1859,8 +1977,9 @@ TridWork trid_work(double* work, int n) {
   t.tau = t.e + n;
   t.Vt = t.tau + 2 * n;
   t.Z = t.Vt + 2LL * n * n;
+  t.wy = t.Z + (long long)n * n;
   // 128-byte aligned (the workspace itself is)
-  const size_t off = (size_t)(t.Z + (long long)n * n - work);
+  const size_t off = (size_t)(t.wy + orm_wy_doubles(n) - work);
   t.sync = work + ((off + 15) / 16) * 16;
   return t;
 }
@@ -1919,10 +2038,21 @@ hipError_t trid_vectors(int n, const TridWork& t, const double* w, int kvec, hip
 hipError_t trid_backtransform(int n, const TridWork& t, int kvec, double* U, int ldu, hipStream_t s) {
   if (kvec <= 0) return hipSuccess;
   const dim3 grid((kvec + 3) / 4);
-  if (n <= 64) hipLaunchKernelGGL(ormtr_kernel<64>, grid, dim3(256), 0, s, t.Vt, t.tau, n, t.Z, n, kvec, U, ldu);
-  else if (n <= 128) hipLaunchKernelGGL(ormtr_kernel<128>, grid, dim3(256), 0, s, t.Vt, t.tau, n, t.Z, n, kvec, U, ldu);
-  else if (n <= 256) hipLaunchKernelGGL(ormtr_kernel<256>, grid, dim3(256), 0, s, t.Vt, t.tau, n, t.Z, n, kvec, U, ldu);
-  else hipLaunchKernelGGL(ormtr_kernel<512>, grid, dim3(256), 0, s, t.Vt, t.tau, n, t.Z, n, kvec, U, ldu);
+  const int B = orm_wy_b(n <= 256 ? 256 : 512);
+  const int nblk = (n - 1 + B - 1) / B;
+  if (nblk > 0) {
+    if (n <= 256) hipLaunchKernelGGL((orm_t_kernel<16, 256>), dim3(nblk), dim3(256), 0, s, t.Vt, t.tau, n, t.wy);
+    else hipLaunchKernelGGL((orm_t_kernel<8, 512>), dim3(nblk), dim3(256), 0, s, t.Vt, t.tau, n, t.wy);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (n <= 64)
+    hipLaunchKernelGGL((ormtr_wy_kernel<16, 64>), grid, dim3(256), 0, s, t.Vt, t.wy, n, t.Z, n, kvec, U, ldu);
+  else if (n <= 128)
+    hipLaunchKernelGGL((ormtr_wy_kernel<16, 128>), grid, dim3(256), 0, s, t.Vt, t.wy, n, t.Z, n, kvec, U, ldu);
+  else if (n <= 256)
+    hipLaunchKernelGGL((ormtr_wy_kernel<16, 256>), grid, dim3(256), 0, s, t.Vt, t.wy, n, t.Z, n, kvec, U, ldu);
+  else hipLaunchKernelGGL((ormtr_wy_kernel<8, 512>), grid, dim3(256), 0, s, t.Vt, t.wy, n, t.Z, n, kvec, U, ldu);
   return hipGetLastError();
 }
 
@@ -1939,7 +2069,7 @@ hipError_t heev_tridiag(double* G, int ldg, int n, double* w, double* U, int ldu
 }
 
 size_t heev_tridiag_work_doubles(int n) {
-  return (size_t)4 * n + 2 * (size_t)n * n + (size_t)n * n + 16 + trm_sync_doubles(n) + 64;
+  return (size_t)4 * n + 2 * (size_t)n * n + (size_t)n * n + orm_wy_doubles(n) + 16 + trm_sync_doubles(n) + 64;
 }
 
 // K split so that about 32 partial tiles run (each at least 64 deep); the
