@@ -76,7 +76,16 @@ lb_status lindblad_kernel_heev(int32_t n, const double* G, double* w, double* U,
     if ((e = hipMemcpyAsync(dG.p, G, nn * 16, hipMemcpyHostToDevice, s)) != hipSuccess) { rc = hip_fail(e, "copy"); break; }
     if ((e = hipMemsetAsync(di.p, 0, 16, s)) != hipSuccess) { rc = hip_fail(e, "memset"); break; }
     if (method == 1) {
-      if ((e = lbk::heev_tridiag((double*)dG.p, n, n, (double*)dw.p, (double*)dV.p, n, n, (double*)dwork.p, s)) != hipSuccess) { rc = hip_fail(e, "heev_tridiag"); break; }
+      // the reduction's workgroups must be resident together: take them from
+      // the device's budget until the stream has drained
+      int dev = 0;
+      (void)hipGetDevice(&dev);
+      const int held = lbk::reserve_device_cus(dev, lbk::trid_coresident_workgroups(n));
+      e = lbk::heev_tridiag((double*)dG.p, n, n, (double*)dw.p, (double*)dV.p, n, n, (double*)dwork.p, s);
+      const hipError_t es = hipStreamSynchronize(s);
+      lbk::release_device_cus(dev, held);
+      if (e == hipSuccess) e = es;
+      if (e != hipSuccess) { rc = hip_fail(e, "heev_tridiag"); break; }
       // same clean-up as the solver: two Newton-Schulz polar steps (G is scratch now)
       Dev dT(nn * 16);
       if (!dT.p) { rc = LB_ERR_OOM; break; }

@@ -32,6 +32,7 @@
 #include <string>
 #include <vector>
 #include <map>
+#include <condition_variable>
 #include <mutex>
 #include <thread>
 
@@ -178,6 +179,7 @@ struct lb_op {
 
 struct lb_solver {
   lb_config cfg;
+  int held_cus = 0;             // CUs reserved for a multi-workgroup reduction in flight
   lb::Layout lay;
   int L = 0;
   hipStream_t stream = nullptr;
@@ -382,14 +384,61 @@ void check_gemm(hipError_t e, const char* what) {
   if (e != hipSuccess) throw Fail(LB_ERR_HIP, std::string("gemm ") + what + ": " + hipGetErrorString(e));
 }
 
+// Process-wide budget of CUs per device for the multi-workgroup reduction,
+// whose workgroups spin on each other and so must all be resident at once.
+// A solver reserves a launch's workgroups (one CU each at most) before
+// enqueueing it and gives them back after its next stream wait (the
+// truncation rank read-back that follows every eigen-decomposition), so the
+// reductions in flight on all streams never need more CUs than the device
+// has and each one's workgroups can always be placed together.  A solver
+// holds at most one reservation, and never waits for the budget while
+// holding one, so the budget cannot deadlock.
+struct CuBudget {
+  std::mutex mu;
+  std::condition_variable cv;
+  int total = -1, avail = 0;
+};
+CuBudget& cu_budget(int dev) {
+  static CuBudget b[64];
+  return b[dev & 63];
+}
+thread_local lb_solver* tl_cu_holder = nullptr;
+
+void release_cus(lb_solver* s) {
+  if (s->held_cus <= 0) return;
+  lbk::release_device_cus(s->cfg.device, s->held_cus);
+  s->held_cus = 0;
+  if (tl_cu_holder == s) tl_cu_holder = nullptr;
+}
+
+void reserve_cus(lb_solver* s, int w) {
+  if (w <= 0) return;
+  if (s->held_cus > 0) {   // not expected: every reservation is followed by a read-back
+    HIPCHK(hipStreamSynchronize(s->stream));
+    release_cus(s);
+  }
+  s->held_cus = lbk::reserve_device_cus(s->cfg.device, w);
+  tl_cu_holder = s;
+}
+
+// On an error path: wait for the solver's stream and give its CUs back.
+void release_cus_on_error() {
+  lb_solver* s = tl_cu_holder;
+  if (!s) return;
+  (void)hipStreamSynchronize(s->stream);
+  release_cus(s);
+}
+
 int read_k(lb_solver* s) {
   HIPCHK(hipStreamSynchronize(s->stream));
+  release_cus(s);
   return *reinterpret_cast<volatile int32_t*>(&s->hio->k);
 }
 
 // Rank and relative discarded weight of the last truncation, one wait.
 int read_k_disc(lb_solver* s, double* disc) {
   HIPCHK(hipStreamSynchronize(s->stream));
+  release_cus(s);
   *disc = *reinterpret_cast<volatile double*>(&s->hio->disc);
   return *reinterpret_cast<volatile int32_t*>(&s->hio->k);
 }
@@ -466,6 +515,7 @@ void eig_trid(lb_solver* s, double* G, int n, double* lam, double* U, int kvec) 
     // complex Hermitian Householder tridiagonalisation: 16/3 n^3 real flops;
     // reads the matrix once, writes the reflectors and the tridiagonal
     Timed tm(s, PC_HETRD, 16.0 / 3.0 * N * N * N, 16.0 * N * N + 8.0 * N * N + 24.0 * N);
+    reserve_cus(s, lbk::trid_coresident_workgroups(n));
     HIPCHK(lbk::trid_reduce(G, n, n, tw, s->stream));
   }
   {
@@ -875,6 +925,7 @@ void canonicalize(lb_solver* s) {
 }
 
 lb_status fail(const Fail& f) {
+  release_cus_on_error();
   g_last_error = f.what();
   return f.code;
 }
@@ -913,6 +964,33 @@ std::vector<lb::Term> convert_terms(const lb_solver* s, const lb_term* terms, in
 // ============================================================================
 // C ABI
 // ============================================================================
+
+namespace lbk {
+int reserve_device_cus(int device, int w) {
+  if (w <= 0) return 0;
+  CuBudget& b = cu_budget(device);
+  std::unique_lock<std::mutex> lk(b.mu);
+  if (b.total < 0) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 1;
+    b.total = b.avail = cus;
+  }
+  w = std::min(w, b.total);
+  b.cv.wait(lk, [&] { return b.avail >= w; });
+  b.avail -= w;
+  return w;
+}
+
+void release_device_cus(int device, int w) {
+  if (w <= 0) return;
+  CuBudget& b = cu_budget(device);
+  {
+    std::lock_guard<std::mutex> g(b.mu);
+    b.avail += w;
+  }
+  b.cv.notify_all();
+}
+}  // namespace lbk
 
 extern "C" {
 
@@ -955,6 +1033,7 @@ lb_status lindblad_create(const lb_config* cfg, lb_solver** out) {
   } catch (const Fail& f) {
     return fail(f);
   } catch (const std::exception& e) {
+    release_cus_on_error();
     g_last_error = e.what();
     return LB_ERR_ARG;
   }
@@ -983,6 +1062,7 @@ lb_status lindblad_mpo_build(lb_solver* s, const lb_term* terms, int32_t n_terms
   } catch (const Fail& f) {
     return fail(f);
   } catch (const std::exception& e) {
+    release_cus_on_error();
     g_last_error = e.what();
     return LB_ERR_ARG;
   }
@@ -1108,6 +1188,7 @@ lb_status lindblad_set_generator(lb_solver* s, const lb_op* H0, const lb_op* H1,
   } catch (const Fail& f) {
     return fail(f);
   } catch (const std::exception& e) {
+    release_cus_on_error();
     g_last_error = e.what();
     return LB_ERR_ARG;
   }
@@ -1179,6 +1260,7 @@ lb_status lindblad_set_state_product(lb_solver* s, const double* const* vectors)
   } catch (const Fail& f) {
     return fail(f);
   } catch (const std::exception& e) {
+    release_cus_on_error();
     g_last_error = e.what();
     return LB_ERR_ARG;
   }
@@ -1204,6 +1286,7 @@ lb_status lindblad_set_state_mps(lb_solver* s, const int32_t* bonds, const doubl
   } catch (const Fail& f) {
     return fail(f);
   } catch (const std::exception& e) {
+    release_cus_on_error();
     g_last_error = e.what();
     return LB_ERR_ARG;
   }
@@ -1237,6 +1320,7 @@ lb_status lindblad_step(lb_solver* s, int32_t n_steps) {
   } catch (const Fail& f) {
     return fail(f);
   } catch (const std::exception& e) {
+    release_cus_on_error();
     g_last_error = e.what();
     return LB_ERR_HIP;
   }
@@ -1273,6 +1357,7 @@ lb_status lindblad_step_batch(lb_solver* const* ss, int32_t n, int32_t n_steps) 
   } catch (const Fail& f) {
     return fail(f);
   } catch (const std::exception& e) {
+    release_cus_on_error();
     g_last_error = e.what();
     return LB_ERR_HIP;
   }

@@ -59,6 +59,17 @@ struct TridWork {
 };
 TridWork trid_work(double* work, int n);
 hipError_t trid_reduce(double* G, int ldg, int n, const TridWork& t, hipStream_t stream);
+// Workgroups of one trid_reduce launch of order n that spin on each other and
+// so must be resident together, one CU each at most (0: a single workgroup).
+// Reductions in flight at once on several streams must not need more CUs
+// than the device has; the solver keeps a process-wide budget for that.
+int trid_coresident_workgroups(int n);
+// Process-wide budget of those CUs per device: reserve_device_cus blocks
+// until w CUs (at most the device's count) are free, takes them and returns
+// how many it took; release_device_cus gives them back once the launch that
+// needed them has completed (after a wait on its stream).
+int reserve_device_cus(int device, int w);
+void release_device_cus(int device, int w);
 hipError_t trid_eigenvalues(int n, const TridWork& t, double* w, hipStream_t stream);
 hipError_t trid_vectors(int n, const TridWork& t, const double* w, int kvec, hipStream_t stream);
 hipError_t trid_backtransform(int n, const TridWork& t, int kvec, double* U, int ldu, hipStream_t stream);

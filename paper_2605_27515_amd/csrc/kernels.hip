@@ -1984,6 +1984,8 @@ TridWork trid_work(double* work, int n) {
   return t;
 }
 
+int trid_coresident_workgroups(int n) { return n <= 128 ? 0 : (n <= 256 ? 16 : 32); }
+
 hipError_t trid_reduce(double* G, int ldg, int n, const TridWork& t, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (n > 512 || ldg < n) return hipErrorInvalidValue;
