@@ -266,3 +266,37 @@ def test_transmon_full_chain_fp32():
     assert abs(tr - 1.0) < 1e-12 and 1.0 / chi_mu - 1e-12 <= pur <= 1.0 + 1e-12
     assert abs(s.diagnostics()["tau"] - taus[-1]) <= 1e-5
     s.close()
+
+
+def test_batch_of_large_reductions_equals_alone():
+    """Nine driven-transmon solves at chi = 256 stepped together: their zip-up
+    Gram matrices (order 512) are reduced by 32 co-resident workgroups each,
+    more than the device's CUs for all nine at once, so the solver's CU
+    budget has to hold some back.  Every solve of the batch must equal the
+    same solve stepped alone."""
+    api = _api()
+    m = wl.model_transmon_resonator()
+    L, chi, chi_mu = 22, 256, 32
+    raw = wl.synthetic_mps(L, chi_mu, chi)
+    terms = _observables(m)
+    print("large-reduction batch: alone", flush=True)
+    s = api.solver_from_model(m, precision="fp32", chi=chi, chi_mu=chi_mu, state="none")
+    s.set_state_mps(raw)
+    s.step(1)
+    ref = [s.observe(s.mpo(t)) for t in terms]
+    ref_tp = s.trace_purity()
+    s.close()
+    print("large-reduction batch: nine together", flush=True)
+    ss = []
+    for _ in range(9):
+        x = api.solver_from_model(m, precision="fp32", chi=chi, chi_mu=chi_mu, state="none")
+        x.set_state_mps(raw)
+        ss.append(x)
+    api.step_batch(ss, 1)
+    for x in ss:
+        for t, v in zip(terms, ref):
+            g = x.observe(x.mpo(t))
+            assert np.isfinite(g) and abs(g - v) <= 1e-12 * max(1.0, abs(v)), (t, g, v)
+        tp = x.trace_purity()
+        assert abs(tp[0] - ref_tp[0]) <= 1e-12 and abs(tp[1] - ref_tp[1]) <= 1e-12
+        x.close()
