@@ -35,9 +35,11 @@ lb_status lindblad_kernel_zgemm(int32_t M, int32_t N, int32_t K, const double* A
 lb_status lindblad_kernel_heev(int32_t n, const double* G, double* w, double* U, int32_t* sweeps,
                                int32_t method);
 
-/* Truncation rule on descending squared singular values lam (n): smallest
- * k >= 1 with sum_{j>k} lam_j <= tol^2 sum_j lam_j, then min(k, cap);
- * *disc = discarded / total.  (Tolerance rule of all compressions.) */
+/* Truncation rule on descending squared singular values lam (n <= 512, the
+ * largest factorisation order): smallest k >= 1 with
+ * sum_{j>k} lam_j <= tol^2 sum_j lam_j, then min(k, cap); *disc =
+ * discarded / total.  (Tolerance rule of all compressions.)  Errors:
+ * LB_ERR_ARG (n outside 1..512 or a NULL pointer), LB_ERR_HIP. */
 lb_status lindblad_kernel_truncate(int32_t n, const double* lam, double tol, int32_t cap,
                                    int32_t* k, double* disc);
 

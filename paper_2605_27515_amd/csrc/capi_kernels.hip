@@ -109,7 +109,7 @@ lb_status lindblad_kernel_heev(int32_t n, const double* G, double* w, double* U,
 
 lb_status lindblad_kernel_truncate(int32_t n, const double* lam, double tol, int32_t cap, int32_t* k,
                                    double* disc) {
-  if (n <= 0 || !lam || !k) return LB_ERR_ARG;
+  if (n <= 0 || n > 512 || !lam || !k) return LB_ERR_ARG;
   hipStream_t s;
   hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
   if (e != hipSuccess) return hip_fail(e, "stream");

@@ -458,17 +458,23 @@ hipError_t heev_jacobi(double* G, int ldg, long long g_stride, int n, double* w,
 // ---------------------------------------------------------------------------
 
 __global__ void truncate_kernel(const double* lam, int n, double tol, int cap, int* k_out, double* disc) {
+  // the eigenvalues are staged in LDS by all threads; the sums stay serial,
+  // in index order, so the decision is that of the plain rule
+  __shared__ double sl[512];
+  for (int j = threadIdx.x; j < n; j += blockDim.x) sl[j] = fmax(lam[j], 0.0);
+  __syncthreads();
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double* lam_ = sl;
   double total = 0.0;
-  for (int j = 0; j < n; ++j) total += fmax(lam[j], 0.0);
+  for (int j = 0; j < n; ++j) total += lam_[j];
   int k = n;
   double tail = 0.0;
-  while (k > 1 && tail + fmax(lam[k - 1], 0.0) <= tol * tol * total) {
-    tail += fmax(lam[k - 1], 0.0);
+  while (k > 1 && tail + lam_[k - 1] <= tol * tol * total) {
+    tail += lam_[k - 1];
     --k;
   }
   if (cap > 0 && k > cap) {
-    for (int j = cap; j < k; ++j) tail += fmax(lam[j], 0.0);
+    for (int j = cap; j < k; ++j) tail += lam_[j];
     k = cap;
   }
   if (k < 1) k = 1;
@@ -478,6 +484,7 @@ __global__ void truncate_kernel(const double* lam, int n, double tol, int cap, i
 
 hipError_t truncate_rank(const double* lam, int n, double tol, int cap, int* k_out, double* disc,
                          hipStream_t s) {
+  if (n < 1 || n > 512) return hipErrorInvalidValue;   // the kernel stages lam in 4 KB of LDS
   hipLaunchKernelGGL(truncate_kernel, dim3(1), dim3(64), 0, s, lam, n, tol, cap, k_out, disc);
   return hipGetLastError();
 }
@@ -1385,20 +1392,26 @@ constexpr int STEBZ_NT = 256;
 __global__ __launch_bounds__(STEBZ_NT) void stebz_kernel(const double* d, const double* e, int n, double* w,
                                                          int kmax) {
   __shared__ double sd[512], se2[512];
-  __shared__ double bnd[2];
+  __shared__ double bnd[2], blo[STEBZ_NT / 64], bhi[STEBZ_NT / 64];
   __shared__ int firstw[STEBZ_NT / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // Gershgorin bounds (minimum and maximum: the same in any order)
+  double glo = 1e300, ghi = -1e300;
   for (int i = tid; i < n; i += STEBZ_NT) {
-    sd[i] = d[i];
+    const double di = d[i];
+    sd[i] = di;
     se2[i] = (i < n - 1) ? e[i] * e[i] : 0.0;
+    const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0);
+    glo = fmin(glo, di - r);
+    ghi = fmax(ghi, di + r);
   }
+  glo = -wave_max(-glo);
+  ghi = wave_max(ghi);
+  if (lane == 0) { blo[wave] = glo; bhi[wave] = ghi; }
+  __syncthreads();
   if (tid == 0) {
-    double lo = 1e300, hi = -1e300;
-    for (int i = 0; i < n; ++i) {
-      const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0);
-      lo = fmin(lo, d[i] - r);
-      hi = fmax(hi, d[i] + r);
-    }
+    double lo = blo[0], hi = bhi[0];
+    for (int v = 1; v < STEBZ_NT / 64; ++v) { lo = fmin(lo, blo[v]); hi = fmax(hi, bhi[v]); }
     const double span = fmax(fabs(lo), fabs(hi));
     bnd[0] = lo - 4.0 * 2.2e-16 * span - 1e-300;
     bnd[1] = hi + 4.0 * 2.2e-16 * span + 1e-300;
