@@ -1038,8 +1038,8 @@ __global__ __launch_bounds__(TRD_NT) void hetrd_kernel(double2* G, int ldg, int 
 // (lc < 8 CPW); wave k of it holds the CPW columns lc = k + 8u (u < CPW), so
 // that every wave keeps work until the end, and lane l of a wave holds rows
 // R = 64q + l of them: each row vector entry is read from LDS by exactly one
-// lane per wave, and the columns' products fold over the wave through an LDS
-// transpose and DPP.
+// lane per wave, and the columns' products fold over the wave together by
+// one transposed reduction.
 //
 // One exchange per step.  The pass of step j-1 (rank-2 update of step j-1
 // fused with the product y_j = B_j v_j) leaves in every workgroup y_j on its
@@ -1081,6 +1081,48 @@ __global__ void trm_clear_kernel(unsigned long long* p, long long count) {
     p[i] = TRM_EMPTY;
 }
 
+// Sum over the 64 lanes of NV values at once (NV a power of two <= 64): at
+// stage s lanes l and l ^ 2^s swap halves of their remaining values, the one
+// with bit s set keeping the upper half, so after log2 NV stages a lane holds
+// one value, summed over 2^(log2 NV) lanes; the remaining stages are plain
+// sums.  Returns the total of value index sum_s bit_s(l) * NV / 2^(s+1).
+// Stages 0 and 1 use DPP quad permutes, the others lane shuffles.  All 64
+// lanes active.
+template <int NV, int S>
+__device__ inline void wave_reduce_many_stage(double (&v)[NV], int lane) {
+  constexpr int h = NV >> (S + 1);
+  if constexpr (h >= 1) {
+    const bool up = (lane >> S) & 1;
+#pragma unroll
+    for (int i = 0; i < h; ++i) {
+      const double send = up ? v[i] : v[i + h];
+      const double keep = up ? v[i + h] : v[i];
+      double recv;
+      if constexpr (S == 0) recv = dpp_f64<0xB1, 0xF>(0.0, send);        // quad_perm [1,0,3,2]: lane ^ 1
+      else if constexpr (S == 1) recv = dpp_f64<0x4E, 0xF>(0.0, send);   // quad_perm [2,3,0,1]: lane ^ 2
+      else recv = __shfl_xor(send, 1 << S, 64);
+      v[i] = keep + recv;
+    }
+    wave_reduce_many_stage<NV, S + 1>(v, lane);
+  }
+}
+template <int NV>
+__device__ inline double wave_reduce_many(double (&v)[NV], int lane) {
+  wave_reduce_many_stage<NV, 0>(v, lane);
+  double t = v[0];
+#pragma unroll
+  for (int s = 0; s < 6; ++s)
+    if ((NV >> s) <= 1) t += __shfl_xor(t, 1 << s, 64);
+  return t;
+}
+template <int NV>
+__device__ inline int wave_reduce_many_index(int lane) {
+  int idx = 0;
+#pragma unroll
+  for (int s = 0; (NV >> (s + 1)) >= 1; ++s) idx += ((lane >> s) & 1) * (NV >> (s + 1));
+  return idx;
+}
+
 template <int NMAX, int CPW>
 struct TrmShared {
   // row vectors by global row; entries of retired rows (below the pass's
@@ -1090,7 +1132,6 @@ struct TrmShared {
   double2 w[NMAX];        // w_j
   double2 yp[8 * CPW];    // this workgroup's folded product, by local column
   double2 fr[8 * CPW];    // this workgroup's entries of the next block's first row
-  double red[TRM_NT / 64][2 * CPW][64];   // per-wave partial products, transposed in the fold
   int abort;
 };
 
@@ -1185,23 +1226,15 @@ __device__ inline void trm_pass(const double2* G, int ldg, int n, int j, TrmShar
         if (act[u] && lane == (lo & 63)) sh.fr[k + 8 * u] = reg[u][q];
     }
   }
-  // fold the NV = 2 * CPW partial sums over the wave: transpose through LDS
-  // so lane l adds NV partials of value l / (64 / NV), then DPP sums over
-  // groups of 64 / NV lanes
-  double* red = &sh.red[k][0][0];
+  // fold the NV = 2 * CPW partial sums over the wave together (a transposed
+  // reduction: lane l ends with the total of value wave_reduce_many_index(l))
+  constexpr int NV = 2 * CPW;
+  double pv[NV];
 #pragma unroll
-  for (int u = 0; u < CPW; ++u) { red[(2 * u) * 64 + lane] = ar[u]; red[(2 * u + 1) * 64 + lane] = ai[u]; }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-  constexpr int NV = 2 * CPW, GL = 64 / NV;
-  const int val = lane / GL, seg = lane % GL;
-  double t = 0.0;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) t += red[val * 64 + seg * NV + i];
-  t = group_sum<GL>(t);
-  if (seg == 0) {
-    const int u = val >> 1, lc = k + 8 * u;
+  for (int u = 0; u < CPW; ++u) { pv[2 * u] = ar[u]; pv[2 * u + 1] = ai[u]; }
+  const double t = wave_reduce_many<NV>(pv, lane);
+  if (lane < NV) {
+    const int val = wave_reduce_many_index<NV>(lane), u = val >> 1, lc = k + 8 * u;
     if (act[u]) reinterpret_cast<double*>(&sh.yp[lc])[val & 1] = t;
   }
 #pragma unroll
@@ -1640,48 +1673,6 @@ __global__ __launch_bounds__(256) void orm_t_kernel(const double* Vt, const doub
       for (int p = 0; p < B; ++p) out[p] = T[i][p];
     }
   }
-}
-
-// Sum over the 64 lanes of NV values at once (NV a power of two <= 64): at
-// stage s lanes l and l ^ 2^s swap halves of their remaining values, the one
-// with bit s set keeping the upper half, so after log2 NV stages a lane holds
-// one value, summed over 2^(log2 NV) lanes; the remaining stages are plain
-// sums.  Returns the total of value index sum_s bit_s(l) * NV / 2^(s+1).
-// Stages 0 and 1 use DPP quad permutes, the others lane shuffles.  All 64
-// lanes active.
-template <int NV, int S>
-__device__ inline void wave_reduce_many_stage(double (&v)[NV], int lane) {
-  constexpr int h = NV >> (S + 1);
-  if constexpr (h >= 1) {
-    const bool up = (lane >> S) & 1;
-#pragma unroll
-    for (int i = 0; i < h; ++i) {
-      const double send = up ? v[i] : v[i + h];
-      const double keep = up ? v[i + h] : v[i];
-      double recv;
-      if constexpr (S == 0) recv = dpp_f64<0xB1, 0xF>(0.0, send);        // quad_perm [1,0,3,2]: lane ^ 1
-      else if constexpr (S == 1) recv = dpp_f64<0x4E, 0xF>(0.0, send);   // quad_perm [2,3,0,1]: lane ^ 2
-      else recv = __shfl_xor(send, 1 << S, 64);
-      v[i] = keep + recv;
-    }
-    wave_reduce_many_stage<NV, S + 1>(v, lane);
-  }
-}
-template <int NV>
-__device__ inline double wave_reduce_many(double (&v)[NV], int lane) {
-  wave_reduce_many_stage<NV, 0>(v, lane);
-  double t = v[0];
-#pragma unroll
-  for (int s = 0; s < 6; ++s)
-    if ((NV >> s) <= 1) t += __shfl_xor(t, 1 << s, 64);
-  return t;
-}
-template <int NV>
-__device__ inline int wave_reduce_many_index(int lane) {
-  int idx = 0;
-#pragma unroll
-  for (int s = 0; (NV >> (s + 1)) >= 1; ++s) idx += ((lane >> s) & 1) * (NV >> (s + 1));
-  return idx;
 }
 
 template <int B, int NMAX>
