@@ -761,24 +761,20 @@ __device__ inline void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Householder reduction of the Hermitian G (n x n, n <= 512, ld ldg complex
-// entries, full storage, destroyed) to the real tridiagonal (d, e):
-// reflector j = I - tau_j v_j v_j^H with v_j[j+1] = 1 annihilates column j
-// below the subdiagonal.  Outputs d[n], e[n-1], tau[n-1] (complex) and the
-// reflectors as rows of Vt (n x n complex, row j holds v_j on columns
-// j+1..n-1).
+// Householder reduction of the Hermitian G (n x n, ld ldg complex entries,
+// full storage, read only) to the real tridiagonal (d, e): reflector
+// j = I - tau_j v_j v_j^H with v_j[j+1] = 1 annihilates column j below the
+// subdiagonal.  Outputs d[n], e[n-1], tau[n-1] (complex) and the reflectors
+// as rows of Vt (n x n complex, row j holds v_j on columns j+1..n-1).
 //
-// One workgroup of 1024 threads.  Thread t owns one of the P = 1024 / PARTS
-// columns (the power of two >= n) and every PARTS-th row of it: column t % P
-// and row part rho = t / P, so that a wave covers 64 adjacent columns of a
-// row, or (when registers and band hold every row) column t / PARTS and rho =
-// t % PARTS, so that the parts of a column are adjacent lanes and fold their
-// products by DPP.  The rows are R with (n-1-R) % PARTS == rho; the q-th from
-// the bottom, R = n-1-rho-q*PARTS, sits in a register for
-// q < TRD_QR, in an LDS band for q < TRD_QR + QL and in G above that, so
-// the bottom rows of the trailing block never leave the chip (all of it for
-// n <= 128).  No thread touches another thread's entries, so the barriers
-// order LDS only.
+// hetrd_kernel: one workgroup of 1024 threads, n <= P = 1024 / PARTS (PARTS =
+// 16 for n <= 64, 8 for n <= 128).  Thread t owns column t / PARTS and row
+// part rho = t % PARTS of it (the PARTS threads of a column are adjacent
+// lanes and fold their products by DPP); the rows are R with
+// (n-1-R) % PARTS == rho, the q-th from the bottom, R = n-1-rho-q*PARTS, in a
+// register for q < TRD_QR and in an LDS band above, so the whole trailing
+// block stays on chip.  No thread touches another thread's entries, so the
+// barriers order LDS only.
 //
 // Step j: with y_j = B_j v_j (B_j the trailing block j+1.., from the last
 // pass), wave 0 forms w_j = tau_j y_j - (|tau_j|^2/2) Re(v_j^H y_j) v_j,
@@ -792,22 +788,17 @@ constexpr int TRD_NT = 1024;
 constexpr int TRD_QR = 10;   // rows per thread in registers
 
 // LDS layout for P = 1024 / PARTS columns: vectors by global row, the
-// folded product and as many band rows per thread (QL) as fit
-// in the 160 KB of the CU.
+// folded product and the band rows of every thread (QL of them).
 template <int PARTS>
 struct TrdShared {
   static constexpr int P = TRD_NT / PARTS;
-  // interleaved: the PARTS threads of a column are adjacent lanes and fold
-  // their partial products by DPP (used when registers and band hold every
-  // row: the global rows want a wave on 64 adjacent columns of one row)
-  static constexpr int YP = (TRD_QR + 9) * PARTS >= P ? P : TRD_NT;
-  static constexpr int QL = (160 * 1024 - 1024 - 16 * (4 * P + YP)) / (16 * TRD_NT);
-  static constexpr bool INTER = YP == P;
+  static constexpr int QL = P / PARTS > TRD_QR ? P / PARTS - TRD_QR : 0;   // band rows per thread
+  static_assert(QL * TRD_NT * 16 + 5 * P * 16 <= 160 * 1024, "block on chip");
   double2 v[2][P];            // v_j, v_{j+1} by global row
   double2 w[P];               // w_j
   double2 fc[P];              // first column of the next block after the pass
-  double2 yp[YP];             // the pass's product y_{j+1}: by column, or partial sums by thread
-  double2 band[QL * TRD_NT];
+  double2 yp[P];              // the pass's product y_{j+1}, by column
+  double2 band[(QL > 0 ? QL : 1) * TRD_NT];
 };
 
 // b -= wR conj(vC) + vR conj(wC)
@@ -822,19 +813,12 @@ __device__ inline void trd_acc(double& ar, double& ai, double2 b, double2 x) {
   ai += b.x * x.y - b.y * x.x;
 }
 
-// Entry idx of G through a 32-bit byte offset from the (uniform) base, so a
-// load or store needs one address register (idx < 2^28 for n <= 512).
-__device__ inline double2& trd_at(double2* G, unsigned idx) {
-  return *reinterpret_cast<double2*>(reinterpret_cast<char*>(G) + idx * 16u);
-}
-
 template <int PARTS, bool FIRST>
-__device__ inline void trd_pass(double2* G, int ldg, int n, int j, TrdShared<PARTS>& sh, const double2* vc,
+__device__ inline void trd_pass(const double2* G, int ldg, int n, int j, TrdShared<PARTS>& sh, const double2* vc,
                                 const double2* vn, double2 (&reg)[TRD_QR], double2* vt_row) {
-  constexpr int P = TRD_NT / PARTS, QL = TrdShared<PARTS>::QL;
-  constexpr bool INTER = TrdShared<PARTS>::INTER;
+  constexpr int QL = TrdShared<PARTS>::QL;
   const int tid = threadIdx.x;
-  const int c = INTER ? tid / PARTS : tid % P, rho = INTER ? tid % PARTS : tid / P;
+  const int c = tid / PARTS, rho = tid % PARTS;
   const int lo = j + 2;
   double ar = 0.0, ai = 0.0;
   if (c >= lo && c < n) {
@@ -843,38 +827,12 @@ __device__ inline void trd_pass(double2* G, int ldg, int n, int j, TrdShared<PAR
     const int top = n - 1 - rho - lo;
     const int qmax = top >= 0 ? top / PARTS : -1;
     const bool fcol = (c == lo);
-    // rows above the chip-resident part: G, in place, two loads in flight
-    // (none when registers and band hold all P >= n rows)
-    if constexpr ((TRD_QR + QL) * PARTS < P) {
-      constexpr int QG = TRD_QR + QL;
-      int q = qmax;
-      for (; q >= QG + 1; q -= 2) {
-        double2 b[2];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) b[u] = trd_at(G, (unsigned)((n - 1 - rho - (q - u) * PARTS) * ldg + c));
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int R = n - 1 - rho - (q - u) * PARTS;
-          if (!FIRST) { trd_update(b[u], sh.w[R], vc[R], vC, wC); trd_at(G, (unsigned)(R * ldg + c)) = b[u]; }
-          trd_acc(ar, ai, b[u], vn[R]);
-          if (fcol) sh.fc[R] = b[u];
-          __builtin_amdgcn_sched_barrier(0);
-        }
-      }
-      for (; q >= QG; --q) {
-        const int R = n - 1 - rho - q * PARTS;
-        double2 b = trd_at(G, (unsigned)(R * ldg + c));
-        if (!FIRST) { trd_update(b, sh.w[R], vc[R], vC, wC); trd_at(G, (unsigned)(R * ldg + c)) = b; }
-        trd_acc(ar, ai, b, vn[R]);
-        if (fcol) sh.fc[R] = b;
-      }
-    }
     // LDS band
     for (int q = min(qmax, TRD_QR + QL - 1); q >= TRD_QR; --q) {
       const int R = n - 1 - rho - q * PARTS;
       double2& s = sh.band[(q - TRD_QR) * TRD_NT + tid];
       double2 b;
-      if (FIRST) b = trd_at(G, (unsigned)(R * ldg + c));
+      if (FIRST) b = G[(long long)R * ldg + c];
       else { b = s; trd_update(b, sh.w[R], vc[R], vC, wC); }
       s = b;
       trd_acc(ar, ai, b, vn[R]);
@@ -885,7 +843,7 @@ __device__ inline void trd_pass(double2* G, int ldg, int n, int j, TrdShared<PAR
     for (int q = TRD_QR - 1; q >= 0; --q) {
       if (q <= qmax) {
         const int R = n - 1 - rho - q * PARTS;
-        if (FIRST) reg[q] = trd_at(G, (unsigned)(R * ldg + c));
+        if (FIRST) reg[q] = G[(long long)R * ldg + c];
         else trd_update(reg[q], sh.w[R], vc[R], vC, wC);
         trd_acc(ar, ai, reg[q], vn[R]);
         if (fcol) sh.fc[R] = reg[q];
@@ -895,14 +853,10 @@ __device__ inline void trd_pass(double2* G, int ldg, int n, int j, TrdShared<PAR
     }
     if (rho == 0) vt_row[c] = vn[c];
   }
-  if constexpr (INTER) {
-    // y'_c: the PARTS partial sums of column c sit in adjacent lanes
-    ar = group_sum<PARTS>(ar);
-    ai = group_sum<PARTS>(ai);
-    if (rho == 0) sh.yp[c] = double2{ar, ai};
-  } else {
-    sh.yp[tid] = double2{ar, ai};
-  }
+  // y'_c: the PARTS partial sums of column c sit in adjacent lanes
+  ar = group_sum<PARTS>(ar);
+  ai = group_sum<PARTS>(ai);
+  if (rho == 0) sh.yp[c] = double2{ar, ai};
 }
 
 // Reflector from x = (alpha, x_2, ...) with xn2 = sum |x_i|^2 beyond alpha:
@@ -925,8 +879,9 @@ __device__ inline void trd_reflector(double2 alpha, double xn2, double& beta, do
 __device__ inline double2 cmul(double2 a, double2 b) { return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 
 template <int PARTS>
-__global__ __launch_bounds__(TRD_NT) void hetrd_kernel(double2* G, int ldg, int n, double* d, double* e,
+__global__ __launch_bounds__(TRD_NT) void hetrd_kernel(const double2* G, int ldg, int n, double* d, double* e,
                                                        double2* tau, double2* Vt) {
+  static_assert(PARTS == 8 || PARTS == 16, "orders up to 128");
   __shared__ TrdShared<PARTS> sh;
   const int tid = threadIdx.x, lane = tid & 63;
   const bool w0 = tid < 64;
@@ -973,12 +928,7 @@ __global__ __launch_bounds__(TRD_NT) void hetrd_kernel(double2* G, int ldg, int 
         const int R = j + 1 + lane + 64 * q;
         double2 y = double2{0.0, 0.0};
         if (R < n) {
-          if constexpr (TrdShared<PARTS>::INTER) {
-            y = sh.yp[R];
-          } else {
-#pragma unroll 4
-            for (int p = 0; p < PARTS; ++p) { const double2 t = sh.yp[p * P + R]; y.x += t.x; y.y += t.y; }
-          }
+          y = sh.yp[R];
           const double2 v = vc[R];
           sp += v.x * y.x + v.y * y.y;
         }
