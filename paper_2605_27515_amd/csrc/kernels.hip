@@ -1573,55 +1573,65 @@ __host__ __device__ constexpr int orm_wy_b(int nmax) { return nmax <= 256 ? 16 :
 __host__ __device__ constexpr size_t orm_wy_doubles(int n) { return (size_t)2 * 16 * (n + 16); }
 
 template <int B, int NMAX>
-__global__ __launch_bounds__(256) void orm_t_kernel(const double* Vt, const double* tau, int n, double* Tw) {
+__global__ __launch_bounds__(512) void orm_t_kernel(const double* Vt, const double* tau, int n, double* Tw) {
+  static_assert(B * B <= 256, "one thread per (row, column) pair in the recurrence");
   __shared__ double2 vs[B][NMAX];
-  __shared__ double2 S[B][B];
+  __shared__ double2 S2[2][B][B];
   __shared__ double2 T[B][B];
   const double2* Vt2 = reinterpret_cast<const double2*>(Vt);
   const double2* tau2 = reinterpret_cast<const double2*>(tau);
   const int tid = threadIdx.x, bi = blockIdx.x;
   const int hi = n - 2 - bi * B, lo = max(hi - B + 1, 0), nb = hi - lo + 1;
-  for (int idx = tid; idx < B * NMAX; idx += 256) {
+  for (int idx = tid; idx < B * NMAX; idx += 512) {
     const int q = idx / NMAX, r = idx % NMAX, i = lo + q;
     vs[q][r] = (q < nb && r > i && r < n) ? Vt2[(long long)i * n + r] : double2{0.0, 0.0};
   }
+  if (tid < B * B) T[tid / B][tid % B] = double2{0.0, 0.0};
   __syncthreads();
-  // S[p][q] = v_p^H v_q for p < q; the start row is rotated by q so that the
-  // threads of one p read different banks
-  for (int pq = tid; pq < B * B; pq += 256) {
-    const int p = pq / B, q = pq % B;
+  // S[p][q] = v_p^H v_q for p < q, each dot in two halves of the rows (the
+  // start row of a half rotated by q so that threads of one p read
+  // different banks); S = half 0 + half 1
+  {
+    const int half = tid >> 8, pq = tid & 255, p = pq / B, q = pq % B;
     double sr = 0.0, si = 0.0;
-    if (p < q && q < nb) {
-      int r = (2 * q) % n;
-      for (int c = 0; c < n; ++c) {
+    if (pq < B * B && p < q && q < nb) {
+      const int r0 = half * (n / 2), len = half ? n - n / 2 : n / 2;
+      int r = r0 + (len > 0 ? (2 * q) % len : 0);
+      for (int c = 0; c < len; ++c) {
         const double2 a = vs[p][r], b = vs[q][r];
         sr += a.x * b.x + a.y * b.y;
         si += a.x * b.y - a.y * b.x;
-        r = (r + 1 == n) ? 0 : r + 1;
+        r = (r + 1 == r0 + len) ? r0 : r + 1;
       }
     }
-    S[p][q] = double2{sr, si};
+    if (pq < B * B) S2[half][p][q] = double2{sr, si};
   }
   __syncthreads();
-  // the forward recurrence, column by column; lane i owns row i of T
-  if (tid < 64) {
-    const int i = tid;
-    for (int p = 0; p < B; ++p) {
-      const double2 tp = (p < nb) ? tau2[lo + p] : double2{0.0, 0.0};
-      double wr = 0.0, wi = 0.0;
-      if (i < p)
-        for (int q = i; q < p; ++q) {
-          const double2 t = T[i][q], sq = S[q][p];
-          wr += t.x * sq.x - t.y * sq.y;
-          wi += t.x * sq.y + t.y * sq.x;
-        }
-      if (i < B) T[i][p] = (i < p) ? double2{-(tp.x * wr - tp.y * wi), -(tp.x * wi + tp.y * wr)}
-                                   : (i == p ? tp : double2{0.0, 0.0});
+  // the forward recurrence column by column: thread (i, q) forms
+  // T[i][q] S[q][p] and the B threads of row i (adjacent lanes) sum them
+  const int i = tid / B, q = tid % B;
+  for (int p = 0; p < B; ++p) {
+    const double2 tp = (p < nb) ? tau2[lo + p] : double2{0.0, 0.0};
+    double pr = 0.0, pi = 0.0;
+    if (tid < B * B && i < p && q >= i && q < p) {
+      const double2 t = T[i][q], a = S2[0][q][p], b = S2[1][q][p];
+      const double2 sq = double2{a.x + b.x, a.y + b.y};
+      pr = t.x * sq.x - t.y * sq.y;
+      pi = t.x * sq.y + t.y * sq.x;
     }
-    if (i < B) {
-      double2* out = reinterpret_cast<double2*>(Tw) + (size_t)bi * B * B + (size_t)i * B;
-      for (int p = 0; p < B; ++p) out[p] = T[i][p];
+    if (tid < 256) {   // whole waves, so the DPP sums see every lane
+      pr = group_sum<B>(pr);
+      pi = group_sum<B>(pi);
     }
+    if (tid < B * B && q == 0) {
+      if (i < p) T[i][p] = double2{-(tp.x * pr - tp.y * pi), -(tp.x * pi + tp.y * pr)};
+      else if (i == p) T[p][p] = tp;
+    }
+    __syncthreads();
+  }
+  if (tid < B * B) {
+    double2* out = reinterpret_cast<double2*>(Tw) + (size_t)bi * B * B;
+    out[tid] = T[tid / B][tid % B];
   }
 }
 
@@ -1997,8 +2007,10 @@ hipError_t trid_backtransform(int n, const TridWork& t, int kvec, double* U, int
   const int B = orm_wy_b(n <= 256 ? 256 : 512);
   const int nblk = (n - 1 + B - 1) / B;
   if (nblk > 0) {
-    if (n <= 256) hipLaunchKernelGGL((orm_t_kernel<16, 256>), dim3(nblk), dim3(256), 0, s, t.Vt, t.tau, n, t.wy);
-    else hipLaunchKernelGGL((orm_t_kernel<8, 512>), dim3(nblk), dim3(256), 0, s, t.Vt, t.tau, n, t.wy);
+    if (n <= 64) hipLaunchKernelGGL((orm_t_kernel<16, 64>), dim3(nblk), dim3(512), 0, s, t.Vt, t.tau, n, t.wy);
+    else if (n <= 128) hipLaunchKernelGGL((orm_t_kernel<16, 128>), dim3(nblk), dim3(512), 0, s, t.Vt, t.tau, n, t.wy);
+    else if (n <= 256) hipLaunchKernelGGL((orm_t_kernel<16, 256>), dim3(nblk), dim3(512), 0, s, t.Vt, t.tau, n, t.wy);
+    else hipLaunchKernelGGL((orm_t_kernel<8, 512>), dim3(nblk), dim3(512), 0, s, t.Vt, t.tau, n, t.wy);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
