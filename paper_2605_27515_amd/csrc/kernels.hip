@@ -1704,17 +1704,25 @@ __global__ __launch_bounds__(256) void ormtr_wy_kernel(const double* Vt, const d
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-      // y = T x, lane p forms y_p
-      if (lane < B) {
-        const int p = lane;
+      // y = T x: the B^2 products spread over the wave (LPP lanes per row p,
+      // QPL columns each), summed over the row's lanes by DPP
+      {
+        constexpr int LPP = 64 / B, QPL = B / LPP;
+        const int p = lane / LPP, q0 = (lane % LPP) * QPL;
         double yr = 0.0, yi = 0.0;
-        for (int q = p; q < B; ++q) {
-          const double2 t = ts[buf][p][q];
-          const double xr = xs[wave][2 * q], xi = xs[wave][2 * q + 1];
-          yr += t.x * xr - t.y * xi;
-          yi += t.x * xi + t.y * xr;
+#pragma unroll
+        for (int u = 0; u < QPL; ++u) {
+          const int q = q0 + u;
+          if (q >= p) {
+            const double2 t = ts[buf][p][q];
+            const double xr = xs[wave][2 * q], xi = xs[wave][2 * q + 1];
+            yr += t.x * xr - t.y * xi;
+            yi += t.x * xi + t.y * xr;
+          }
         }
-        ys[wave][p] = double2{yr, yi};
+        yr = group_sum<LPP>(yr);
+        yi = group_sum<LPP>(yi);
+        if (lane % LPP == 0) ys[wave][p] = double2{yr, yi};
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
       __builtin_amdgcn_wave_barrier();
