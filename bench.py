@@ -61,10 +61,9 @@ ALU_CLASSES = {"hetrd", "stebz", "stein", "ormtr", "jacobi"}
 # HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this
 # workload, scaled by a plain 256 MiB copy (profiles/step_catbuffer_chi128_fp32_kernels.md);
 # hetrd is the dispatch-weighted mean over its instantiations (the
-# multi-workgroup form's per-step gathers and flag polls go to memory: its
-# agent-scope acquire invalidates the L2).  A kernel absent here reports
-# traffic null
-PMC_TRAFFIC_BYTES = {"hetrd": 4.535e6}
+# multi-workgroup form polls its mailboxes with agent-scope atomic loads,
+# which go to memory).  A kernel absent here reports traffic null
+PMC_TRAFFIC_BYTES = {"hetrd": 4.692e6}
 
 
 def workload():
