@@ -35,6 +35,15 @@ lb_status lindblad_kernel_zgemm(int32_t M, int32_t N, int32_t K, const double* A
 lb_status lindblad_kernel_heev(int32_t n, const double* G, double* w, double* U, int32_t* sweeps,
                                int32_t method);
 
+/* Bound of the waits of the multi-workgroup Householder reduction (orders
+ * 129..512), whose workgroups wait on each other's posted values every step,
+ * in ticks of the GPU's 100 MHz wall clock; ticks <= 0 restores the default
+ * (2 s).  When a wait runs out, every workgroup of the launch leaves and the
+ * tridiagonal's diagonal is NaN, so the eigenvalues come out NaN.  Process
+ * wide; for tests of that path (a bound of a few ticks forces it).  Never
+ * fails. */
+lb_status lindblad_kernel_set_wait_limit(int64_t ticks);
+
 /* Truncation rule on descending squared singular values lam (n <= 512, the
  * largest factorisation order): smallest k >= 1 with
  * sum_{j>k} lam_j <= tol^2 sum_j lam_j, then min(k, cap); *disc =

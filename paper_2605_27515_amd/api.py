@@ -347,6 +347,12 @@ def kernel_heev(G: np.ndarray, method: str = "jacobi"):
     return w, U, sw.value
 
 
+def kernel_set_wait_limit(ticks: int):
+    """Bound (100 MHz wall-clock ticks; <= 0: default 2 s) of the waits of the
+    multi-workgroup Householder reduction (include/lindblad_kernels.h)."""
+    _check(L.load().lindblad_kernel_set_wait_limit(int(ticks)), "kernel_set_wait_limit")
+
+
 def kernel_truncate(lam: np.ndarray, tol: float, cap: int):
     lam = np.ascontiguousarray(lam, np.float64)
     k = C.c_int32()

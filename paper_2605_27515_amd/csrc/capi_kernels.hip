@@ -107,6 +107,11 @@ lb_status lindblad_kernel_heev(int32_t n, const double* G, double* w, double* U,
   return rc;
 }
 
+lb_status lindblad_kernel_set_wait_limit(int64_t ticks) {
+  lbk::trid_set_wait_ticks((long long)ticks);
+  return LB_OK;
+}
+
 lb_status lindblad_kernel_truncate(int32_t n, const double* lam, double tol, int32_t cap, int32_t* k,
                                    double* disc) {
   if (n <= 0 || n > 512 || !lam || !k) return LB_ERR_ARG;

@@ -64,6 +64,10 @@ hipError_t trid_reduce(double* G, int ldg, int n, const TridWork& t, hipStream_t
 // Reductions in flight at once on several streams must not need more CUs
 // than the device has; the solver keeps a process-wide budget for that.
 int trid_coresident_workgroups(int n);
+// Bound of those workgroups' waits on each other, in ticks of the 100 MHz
+// wall clock (<= 0: the default, 2 s).  When a wait runs out, every
+// workgroup leaves and d is NaN.  For tests of that path.
+void trid_set_wait_ticks(long long ticks);
 // Process-wide budget of those CUs per device: reserve_device_cus blocks
 // until w CUs (at most the device's count) are free, takes them and returns
 // how many it took; release_device_cus gives them back once the launch that

@@ -1002,14 +1002,17 @@ __global__ __launch_bounds__(TRD_NT) void hetrd_kernel(const double2* G, int ldg
 // the posted one (coherence of a single location), and no fence or flag is
 // needed.  It then redundantly forms w_j, the updated column j+1 and
 // reflector j+1, so the next pass starts without a second exchange.  Every
-// wait is bounded (after TRM_WAIT_TICKS of the 100 MHz wall clock a
+// wait is bounded (after wait_ticks of the 100 MHz wall clock, 2 s unless a
+// test lowers it, a
 // workgroup raises the generation-tagged abort word, all workgroups leave,
 // and d is set to NaN).  The workgroups of one launch must run concurrently:
 // W of them, one CU each.
 constexpr int TRM_NT = 512;                      // 8 waves
 constexpr int TRM_WMAX = 32;                     // workgroups, at most
 constexpr int TRM_NMAX = 512;                    // order, at most
-constexpr long long TRM_WAIT_TICKS = 200000000;  // 2 s
+constexpr long long TRM_WAIT_TICKS = 200000000;  // 2 s (the default bound)
+// bound of the waits, in wall-clock ticks; tests of the time-out path lower it
+static std::atomic<long long> g_trm_wait_ticks{TRM_WAIT_TICKS};
 // sync block in doubles: the abort word (one 128-byte line), then the
 // mailboxes Y[n][n] and F[n][n] (complex, step-major): slot [j][c] receives
 // y_j[c] and row j+1 of B_j at column c, each double posted once per launch
@@ -1195,7 +1198,8 @@ __device__ inline void trm_pass(const double2* G, int ldg, int n, int j, TrmShar
 template <int W, int CPW>
 __global__ __launch_bounds__(TRM_NT) void hetrd_mc_kernel(const double2* G, int ldg, int n, double* d, double* e,
                                                           double2* tau, double2* Vt, double* mail,
-                                                          unsigned long long* abortw, unsigned gen) {
+                                                          unsigned long long* abortw, unsigned gen,
+                                                          long long wait_ticks) {
   constexpr int LC = 8 * CPW, NMAX = W * LC, QR = NMAX / 64;
   static_assert(W <= TRM_WMAX && NMAX <= TRM_NMAX, "sync block layout");
   __shared__ TrmShared<NMAX, CPW> sh;
@@ -1276,7 +1280,7 @@ __global__ __launch_bounds__(TRM_NT) void hetrd_mc_kernel(const double2* G, int 
         if (lane == 0)
           abort = __hip_atomic_load(abortw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned long long)gen;
         abort = __ballot(abort) != 0ull;
-        if (!abort && (long long)wall_clock64() - t0 > TRM_WAIT_TICKS) {
+        if (!abort && (long long)wall_clock64() - t0 > wait_ticks) {
           if (lane == 0) __hip_atomic_store(abortw, (unsigned long long)gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           abort = true;
         }
@@ -1378,26 +1382,31 @@ __global__ __launch_bounds__(STEBZ_NT) void stebz_kernel(const double* d, const 
   __shared__ double bnd[2], blo[STEBZ_NT / 64], bhi[STEBZ_NT / 64];
   __shared__ int firstw[STEBZ_NT / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // Gershgorin bounds (minimum and maximum: the same in any order)
+  // Gershgorin bounds (minimum and maximum: the same in any order); a
+  // non-finite entry of T is flagged (fmin and fmax would drop a NaN)
   double glo = 1e300, ghi = -1e300;
+  bool bad = false;
   for (int i = tid; i < n; i += STEBZ_NT) {
     const double di = d[i];
     sd[i] = di;
     se2[i] = (i < n - 1) ? e[i] * e[i] : 0.0;
     const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0);
+    bad |= !isfinite(di) || !isfinite(r);
     glo = fmin(glo, di - r);
     ghi = fmax(ghi, di + r);
   }
   glo = -wave_max(-glo);
   ghi = wave_max(ghi);
-  if (lane == 0) { blo[wave] = glo; bhi[wave] = ghi; }
+  const bool wbad = __ballot(bad) != 0ull;
+  if (lane == 0) { blo[wave] = glo; bhi[wave] = ghi; firstw[wave] = wbad ? 1 : 0; }
   __syncthreads();
   if (tid == 0) {
     double lo = blo[0], hi = bhi[0];
-    for (int v = 1; v < STEBZ_NT / 64; ++v) { lo = fmin(lo, blo[v]); hi = fmax(hi, bhi[v]); }
+    bool anybad = firstw[0] != 0;
+    for (int v = 1; v < STEBZ_NT / 64; ++v) { lo = fmin(lo, blo[v]); hi = fmax(hi, bhi[v]); anybad |= firstw[v] != 0; }
     const double span = fmax(fabs(lo), fabs(hi));
-    bnd[0] = lo - 4.0 * 2.2e-16 * span - 1e-300;
-    bnd[1] = hi + 4.0 * 2.2e-16 * span + 1e-300;
+    bnd[0] = anybad ? __builtin_nan("") : lo - 4.0 * 2.2e-16 * span - 1e-300;
+    bnd[1] = anybad ? __builtin_nan("") : hi + 4.0 * 2.2e-16 * span + 1e-300;
   }
   __syncthreads();
   const int j = blockIdx.x;
@@ -1409,6 +1418,10 @@ __global__ __launch_bounds__(STEBZ_NT) void stebz_kernel(const double* d, const 
   const double pivmin = 1e-290 * fmax(1.0, emax);
   const int target = n - 1 - j;   // eigenvalue mu_target (ascending index)
   double lo = bnd[0], hi = bnd[1];
+  if (lo != lo) {   // T not finite: the eigenvalues are NaN
+    if (tid == 0) w[j] = lo;
+    return;
+  }
   const double tspan = fmax(fabs(lo), fabs(hi));
   constexpr double parts = STEBZ_NT + 1;
   for (int it = 0; it < 40; ++it) {
@@ -1958,6 +1971,10 @@ TridWork trid_work(double* work, int n) {
 
 int trid_coresident_workgroups(int n) { return n <= 128 ? 0 : (n <= 256 ? 16 : 32); }
 
+void trid_set_wait_ticks(long long ticks) {
+  g_trm_wait_ticks.store(ticks > 0 ? ticks : TRM_WAIT_TICKS, std::memory_order_relaxed);
+}
+
 hipError_t trid_reduce(double* G, int ldg, int n, const TridWork& t, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (n > 512 || ldg < n) return hipErrorInvalidValue;
@@ -1979,12 +1996,13 @@ hipError_t trid_reduce(double* G, int ldg, int n, const TridWork& t, hipStream_t
                        reinterpret_cast<unsigned long long*>(mail), cnt);
     hipError_t ce = hipGetLastError();
     if (ce != hipSuccess) return ce;
+    const long long ticks = g_trm_wait_ticks.load(std::memory_order_relaxed);
     if (n <= 256)
       hipLaunchKernelGGL((hetrd_mc_kernel<16, 2>), dim3(16), dim3(TRM_NT), 0, s, g2, ldg, n, t.d, t.e, tau, vt, mail,
-                         abortw, gen);
+                         abortw, gen, ticks);
     else
       hipLaunchKernelGGL((hetrd_mc_kernel<32, 2>), dim3(32), dim3(TRM_NT), 0, s, g2, ldg, n, t.d, t.e, tau, vt, mail,
-                         abortw, gen);
+                         abortw, gen, ticks);
   }
   return hipGetLastError();
 }

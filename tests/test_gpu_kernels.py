@@ -137,3 +137,25 @@ def test_truncate_bit_exact(case):
         assert k == kref
         total = np.sum(s ** 2)
         assert abs(disc - np.sum(s[k:] ** 2) / total) <= 1e-14
+
+
+def test_reduction_wait_timeout_leaves_cleanly():
+    """The waits of the multi-workgroup Householder reduction (order 300 here:
+    32 workgroups) are bounded: with a bound of one wall-clock tick they run
+    out, every workgroup leaves, and the eigenvalues come out NaN; with the
+    default bound restored the same call is right again."""
+    api = _api()
+    rng = np.random.Generator(np.random.PCG64(wl.SEED + 300))
+    n = 300
+    X = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    G = X @ X.conj().T / n
+    print("reduction wait time-out, n = 300", flush=True)
+    try:
+        api.kernel_set_wait_limit(1)
+        w, _, _ = api.kernel_heev(G, method="tridiag")
+        assert np.isnan(w).any()
+    finally:
+        api.kernel_set_wait_limit(0)
+    w, U, _ = api.kernel_heev(G, method="tridiag")
+    ref = np.linalg.eigvalsh(G)[::-1]
+    assert np.abs(w - ref).max() <= 1e-10 * np.abs(ref).max()
