@@ -240,6 +240,79 @@ def cpu_baseline(budget_s: float) -> dict:
                       f"{dt:.1f} s), after one warm-up step", "host_cpus": os.cpu_count()}
 
 
+def zgate_main(args) -> None:
+    """Cat-qubit Z gate at the paper's scan point N_a = 2^8, N_b = 2^4,
+    |alpha|^2 = N_a / 3 (paper Sec. 6.2): the whole gate, timed, and its
+    phase-flip probability against the leading-order law pi / (40 |alpha|^3)."""
+    import math
+    import torch
+    import workload as wl
+    from paper_2605_27515_amd import api
+    m, z = wl.model_cat_zgate(Ra=8, Rb=4, dt_max=args.zgate_dt, chi=args.zgate_chi, chi_mu=16)
+    print(f"bench: cat Z gate, {m.steps} steps of dt={m.dt:.3e}, {args.precision}", file=sys.stderr, flush=True)
+    w = api.solver_from_model(m, precision=args.precision, device=0)
+    if args.warmup:
+        w.step(args.warmup)
+    w.profile(True)
+    w.step(PROFILE_STEPS)
+    prof = w.profile_read()
+    w.profile(False)
+    w.close()
+    s = api.solver_from_model(m, precision=args.precision, device=0)
+    parity = s.mpo(wl.parity_operator(0, m.dims[0]))
+    chunk = 2000
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < m.steps:
+        n = min(chunk, m.steps - done)
+        s.step(n)
+        done += n
+        torch.cuda.synchronize()
+        print(f"bench: {done}/{m.steps} steps, {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    elapsed = time.perf_counter() - t0
+    p = s.observe(parity).real
+    tr, pur = s.trace_purity()
+    diag = s.diagnostics()
+    s.close()
+    p_z = 0.5 * (1.0 + p)
+    law = math.pi / (40.0 * z.alpha2 ** 1.5)
+    cpu = None
+    if not args.no_cpu:
+        from threadpoolctl import threadpool_info
+        from oracle import mps, tt
+        K = tt.KrausMPO(m, m.dt)
+        X, _ = mps.right_canonicalize(mps.product_state(m.init, m.bits, m.site_order()), tol=1e-14)
+        n = 0
+        c0 = time.perf_counter()
+        while time.perf_counter() - c0 < args.cpu_seconds and n < m.steps:
+            X, _ = mps.k2_step(X, K.at(n * m.dt), m.tol, m.chi, m.chi_mu)
+            n += 1
+        cdt = time.perf_counter() - c0
+        threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+        cpu = {"value": n / cdt, "unit": "steps/s", "cores": int(threads), "kind": "oracle",
+               "sample": f"the first {n} steps of the same gate from the even cat (oracle NumPy/LAPACK FP64, "
+                         f"{cdt:.1f} s)", "host_cpus": os.cpu_count()}
+    total_ms = sum(v["ms"] for v in prof.values())
+    line = {
+        "metric": "cat Z gate: purified-MPS steps/s over the whole gate; phase-flip probability",
+        "value": m.steps / elapsed, "unit": "steps/s", "n_gpus": 1, "steps": m.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / m.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64" if args.precision == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": f"cat Z gate: memory 2^8 Fock, buffer 2^4 (12 sites), |alpha|^2={z.alpha2:.3f}, "
+                               f"g2=1, kappa_b=10, eps_Z={z.eps_z}, theta=pi, T_Z={z.t_gate:.4f}, dt={m.dt:.4e}, "
+                               f"4 Kraus ops, chi cap {m.chi}, chi_mu cap {m.chi_mu}, tol {m.tol}, even-cat start",
+                   "precision": args.precision, "parallelism": "single solve, one GPU"},
+        "gate_seconds": elapsed,
+        "p_z": p_z, "p_z_law": law, "p_z_over_law": p_z / law, "final_parity": p,
+        "trace": tr, "purity": pur, "final_bonds": diag["bonds"], "final_chi_mu": diag["chi_mu"],
+        "roofline_profiled_steps": roofline_entry(prof, args.precision) if total_ms else None,
+        "kernel_ms_per_step": {k: v["ms"] / PROFILE_STEPS for k, v in prof.items() if v["launches"]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,6 +326,10 @@ def main():
                     help="requests of the seeded serving stream (0: skip the serving leg)")
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
+    ap.add_argument("--workload", choices=["chi128", "cat-zgate"], default="chi128",
+                    help="chi128: the step benchmark (default); cat-zgate: the whole cat-qubit Z gate")
+    ap.add_argument("--zgate-dt", type=float, default=2e-4, help="largest time step of the Z-gate run")
+    ap.add_argument("--zgate-chi", type=int, default=128, help="bond cap of the Z-gate run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -264,6 +341,9 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "cat-zgate":
+        zgate_main(args)
+        return
     print(f"bench: {args.precision} steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
     if args.copy_calibration:
         src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")   # 256 MiB

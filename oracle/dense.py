@@ -120,6 +120,18 @@ def k2_step_rho(dm: DenseModel, rho: np.ndarray, t: float, h: float, order: int 
     return out / tau, tau
 
 
+def kraus_evolve(dm: DenseModel, rho: np.ndarray, h: float, n_steps: int, order: int = 2,
+                 t0: float = 0.0) -> np.ndarray:
+    """n_steps Kraus steps with trace renormalisation after each (Sec. 5.2.2).
+    Without a drive the Kraus operators do not depend on t and are formed once."""
+    fam = None if dm.H1 is not None else kraus_family(dm, t0, h, order)
+    for s in range(n_steps):
+        f = fam if fam is not None else kraus_family(dm, t0 + s * h, h, order)
+        out = kraus_apply_rho(f, rho)
+        rho = out / np.trace(out).real
+    return rho
+
+
 def k2_step_purified(dm: DenseModel, X: np.ndarray, t: float, h: float,
                      chi_mu: int, tol: float, order: int = 2):
     """Purified form: X (D x r) -> [A_1 X | A_2 X | ...], SVD, keep U S[:, :k].

@@ -174,3 +174,36 @@ def test_explicit_stability_reading():
     dm = dense.DenseModel(m)
     assert dense.stability_factor(dm, 1e-3)["damping"] > 1.0
     assert dense.stability_factor(dm, 5e-5)["damping"] < 1.0
+
+
+def _zgate_pz(case, order=2):
+    m, z = wl.model_cat_zgate(**case)
+    dm = dense.DenseModel(m)
+    rho = dense.kraus_evolve(dm, _rho(dm.psi0), m.dt, m.steps, order)
+    par = dense_operator(wl.parity_operator(0, m.dims[0]), m.dims)
+    return (1.0 + np.trace(par @ rho).real) / 2.0
+
+
+def test_cat_zgate_phase_flip_law(golden_dir):
+    """Z gate on a cat qubit (paper Sec. 6.2): with g2 = 1, kappa_b = 10,
+    eps_Z = 0.04, theta = pi and no memory loss, the phase-flip probability
+    is p_Z = pi / (40 |alpha|^3) (paper Eq. pZ).  That is the leading order
+    of the buffer-elimination theory; the Kraus scheme on a converged Fock
+    truncation (2^5 memory levels for |alpha|^2 <= 32/3) lands 7 % above it
+    at |alpha|^2 = 16/3 and 32/3, with the alpha^-3 law holding to 0.5 %.
+    A wrong drive amplitude, gate time or dissipator moves either figure
+    well outside these bounds.  The stored value the GPU runs are compared
+    with is recomputed here."""
+    with open(os.path.join(golden_dir, "zgate_dense.json")) as f:
+        g = json.load(f)
+    case = {k: g[k] for k in ("Ra", "Rb", "alpha2", "dt_max")}
+    p_hi = _zgate_pz(case)
+    assert abs(p_hi - g["p_z"]) <= 1e-12
+    p_lo = _zgate_pz(dict(case, alpha2=16.0 / 3.0))
+
+    def law(a2):
+        return math.pi / (40.0 * a2 ** 1.5)
+
+    r_hi, r_lo = p_hi / law(32.0 / 3.0), p_lo / law(16.0 / 3.0)
+    assert 1.0 <= r_hi < 1.10 and 1.0 <= r_lo < 1.10, (r_hi, r_lo)
+    assert abs(r_hi / r_lo - 1.0) < 0.005, (r_hi, r_lo)

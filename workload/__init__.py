@@ -20,6 +20,7 @@ in ``include/lindblad.h``):
 * ``("NUM_POW", p)``            diag(n^p), n = 0..N-1
 * ``("CHARGE_POW", p, off)``    diag((n-off)^p)   (charge basis, offset binary)
 * ``("SHIFT", k)``              (T_k)_{n,n'} = d(n+k, n'), open boundary
+* ``("DENSE", M)``              an explicit N x N complex matrix
 
 The quantics index of a mode with R bits is n = sum_i 2^(R-i) sigma_i with
 sigma_1 the most significant bit (paper, Sec. 2.1, quantics encoding).
@@ -151,6 +152,53 @@ def model_cat_buffer(Ra: int = 8, Rb: int = 8, alpha2: float = 8.0, g2: float = 
     return Model(name="cat-buffer", bits=[Ra, Rb], H0=H0, jumps=jumps,
                  init=[vacuum(1 << Ra), vacuum(1 << Rb)], dt=dt, steps=steps,
                  chi=chi, chi_mu=chi_mu)
+
+
+def even_cat_amplitudes(n_levels: int, alpha: float) -> np.ndarray:
+    """(|alpha> + |-alpha>) / norm over the first n_levels Fock states."""
+    c = coherent_amplitudes(n_levels, alpha) + coherent_amplitudes(n_levels, -alpha)
+    return c / np.linalg.norm(c)
+
+
+@dataclass
+class ZGate:
+    """Parameters of the cat-qubit Z gate (paper Sec. 6.2): gate angle theta,
+    memory drive eps_Z, gate time T_Z = theta / (4 alpha eps_Z)."""
+    alpha2: float
+    g2: float
+    kappa_b: float
+    eps_z: float
+    theta: float
+    t_gate: float
+
+
+def model_cat_zgate(Ra: int = 8, Rb: int = 4, alpha2: float | None = None, g2: float = 1.0,
+                    kappa_b: float = 10.0, theta: float = math.pi, dt_max: float = 2e-4,
+                    chi: int = 64, chi_mu: int = 16) -> tuple[Model, ZGate]:
+    """Z gate on a cat qubit (paper Sec. 6.1-6.2): the cat + buffer generator
+    with kappa_a = 0 plus the memory drive H_Z = eps_Z (a + a^dag),
+    eps_Z = (1/10) 4 g2^2 / kappa_b, for the time T_Z that turns the even cat
+    |+> into the odd cat |-> (theta = pi).  The cat size follows the paper's
+    scan, |alpha|^2 = N_a / 3, unless given.  Start: even cat x buffer vacuum.
+    The step count is the smallest with dt <= dt_max, so steps * dt = T_Z."""
+    Na = 1 << Ra
+    if alpha2 is None:
+        alpha2 = Na / 3.0
+    alpha = math.sqrt(alpha2)
+    eps_z = 0.1 * 4.0 * g2 * g2 / kappa_b
+    t_gate = theta / (4.0 * alpha * eps_z)
+    steps = max(1, math.ceil(t_gate / dt_max - 1e-9))
+    m = model_cat_buffer(Ra=Ra, Rb=Rb, alpha2=alpha2, g2=g2, kappa_b=kappa_b, kappa_a=0.0,
+                         dt=t_gate / steps, steps=steps, chi=chi, chi_mu=chi_mu)
+    m.name = "cat-zgate"
+    m.H0 = m.H0 + [(eps_z, {0: ("A_POW", 1)}), (eps_z, {0: ("ADAG_POW", 1)})]
+    m.init = [even_cat_amplitudes(Na, alpha), vacuum(1 << Rb)]
+    return m, ZGate(alpha2=alpha2, g2=g2, kappa_b=kappa_b, eps_z=eps_z, theta=theta, t_gate=t_gate)
+
+
+def parity_operator(mode: int, n_levels: int) -> list:
+    """Photon-number parity (-1)^n of one mode, as an explicit diagonal factor."""
+    return [(1.0, {mode: ("DENSE", np.diag((-1.0) ** np.arange(n_levels)).astype(complex))})]
 
 
 def model_transmon_resonator(Rt: int = 10, Rr: int = 12, ej_over_ec: float = 50.0,
