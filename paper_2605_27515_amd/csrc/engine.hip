@@ -252,11 +252,13 @@ int passes(const lb_solver* s) { return fp32(s) ? 1 : 2; }
 // Truncation tolerance of the back-sweep and the purification cut.  The FP32
 // form forms T in complex64, so singular values below ~1e-7 sigma_1 are
 // rounding noise there; keeping them (tol = 1e-8 would) grows the bonds to the
-// caps with noise.  These cuts sit at the orthogonality centre, where
-// truncating X at t changes rho by ~t^2, so they run at no less than 1e-6
-// (rho moves by ~1e-12, far below the complex64 rounding already in rho).  The
-// zip-up cuts a product whose right part is not orthonormal (their error
-// enters rho at first order) and keeps tol / 10.
+// caps with noise, so these cuts run at no less than 1e-6.  At the
+// purification cut a truncation at t moves rho by ~t^2; at an internal bond
+// of the sweep it moves rho at first order (the partial trace over the
+// purification index keeps cross terms between kept and dropped Schmidt
+// vectors), so the floor costs the FP32 form ~1e-6 of rho per such cut, the
+// size of its contraction rounding.  The zip-up cuts a product whose right
+// part is not orthonormal and keeps tol / 10 (flooring it too cost more).
 constexpr double kFp32TolFloor = 1e-6;
 double eff_tol(const lb_solver* s, double t) { return fp32(s) ? std::max(t, kFp32TolFloor) : t; }
 

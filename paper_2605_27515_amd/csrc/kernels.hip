@@ -1914,25 +1914,12 @@ __global__ __launch_bounds__(SG_NT) void stein_groups_kernel(int n, const double
   }
 }
 
-// Unresolved eigenvalues: against every resolved vector and the earlier
-// unresolved ones (after stein_groups_kernel has finished the groups).
-__global__ __launch_bounds__(SG_NT) void stein_unresolved_kernel(int n, const double* w, int k, double* Z, int ldz) {
-  __shared__ double zl[512], dots[512];
-  __shared__ double red[32];
-  __shared__ int cols[512];
-  const double tn = fmax(fmax(fabs(w[0]), fabs(w[n - 1])), 1e-300);
-  const double floor_abs = 8.0 * n * 2.2e-16 * tn;
-  int nres = 0;
-  for (int c = 0; c < k; ++c) nres += fabs(w[c]) > floor_abs ? 1 : 0;
-  if (nres == k) return;
-  if (threadIdx.x == 0) {
-    int q = 0;
-    for (int c = 0; c < k; ++c)
-      if (fabs(w[c]) > floor_abs) cols[q++] = c;
-  }
-  __syncthreads();
-  int np = nres;
-  for (int j = 0; j < k; ++j) {
+// Unresolved eigenvalues, one column at a time: each against every finished
+// vector (cols[0..np)), replaced by a fresh start vector when the projection
+// leaves less than 1e-3 of it.  The fallback of the blocked form below.
+__device__ void unresolved_serial(int n, int k, const double* w, double floor_abs, int j0, int np, int* cols,
+                                  double* Z, int ldz, double* zl, double* dots, double* red) {
+  for (int j = j0; j < k; ++j) {
     if (fabs(w[j]) > floor_abs) continue;
     for (int r = threadIdx.x; r < n; r += SG_NT) zl[r] = Z[(long long)r * ldz + j];
     __syncthreads();
@@ -1952,6 +1939,176 @@ __global__ __launch_bounds__(SG_NT) void stein_unresolved_kernel(int n, const do
     if (threadIdx.x == 0) cols[np] = j;
     __syncthreads();
     ++np;
+  }
+}
+
+// Unresolved eigenvalues (after stein_groups_kernel has finished the groups).
+// Their vectors may be any orthonormal basis of what the resolved vectors
+// leave, so they are made in blocks: seeded random columns, projected out of
+// the span of the resolved vectors and of the earlier unresolved chunks by
+// block Gram-Schmidt (two passes, UP earlier vectors at a time), then made
+// orthonormal within each chunk of UC columns by two Cholesky-QR passes.
+// Random columns in a complement of dimension >= their count are well
+// conditioned; a chunk whose Gram matrix still loses a pivot (below 1e-12 of
+// its diagonal) is finished, with all later ones, one column at a time.
+// (stein_kernel's vectors for these eigenvalues are not used: inverse
+// iteration at nearly equal shifts returns nearly parallel vectors.)
+constexpr int UC = 32;   // unresolved columns per chunk
+constexpr int UP = 64;   // earlier vectors per projection block
+
+// Y[:, c0..c0+cb) -= Z[:, cols[p0..p0+pb)] D, D = Z[:, cols[..]]^T Y (one block).
+__device__ void ur_project_block(const int* cols, int p0, int pb, const int* ucols, int c0, int cb, int n,
+                                 double* Z, int ldz, double* D) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;   // 4 waves x 8 columns
+  {
+    const int p = lane < pb ? lane : pb - 1;
+    const long long cp = cols[p0 + p];
+    const int jb = wave * 8;
+    const long long u0 = ucols[c0 + min(jb + 0, cb - 1)], u1 = ucols[c0 + min(jb + 1, cb - 1)],
+                    u2 = ucols[c0 + min(jb + 2, cb - 1)], u3 = ucols[c0 + min(jb + 3, cb - 1)],
+                    u4 = ucols[c0 + min(jb + 4, cb - 1)], u5 = ucols[c0 + min(jb + 5, cb - 1)],
+                    u6 = ucols[c0 + min(jb + 6, cb - 1)], u7 = ucols[c0 + min(jb + 7, cb - 1)];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0, a5 = 0.0, a6 = 0.0, a7 = 0.0;
+#pragma unroll 2
+    for (int r = 0; r < n; ++r) {
+      const double* row = Z + (long long)r * ldz;
+      const double zp = row[cp];
+      a0 += zp * row[u0]; a1 += zp * row[u1]; a2 += zp * row[u2]; a3 += zp * row[u3];
+      a4 += zp * row[u4]; a5 += zp * row[u5]; a6 += zp * row[u6]; a7 += zp * row[u7];
+    }
+    if (lane < pb) {
+      double* d = D + lane * UC + jb;
+      if (jb + 0 < cb) d[0] = a0;
+      if (jb + 1 < cb) d[1] = a1;
+      if (jb + 2 < cb) d[2] = a2;
+      if (jb + 3 < cb) d[3] = a3;
+      if (jb + 4 < cb) d[4] = a4;
+      if (jb + 5 < cb) d[5] = a5;
+      if (jb + 6 < cb) d[6] = a6;
+      if (jb + 7 < cb) d[7] = a7;
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * UC; e += SG_NT) {
+    const int r = e / UC, j = e % UC;
+    if (j >= cb) continue;
+    const double* row = Z + (long long)r * ldz;
+    double v = 0.0;
+    for (int p = 0; p < pb; ++p) v += row[cols[p0 + p]] * D[p * UC + j];
+    Z[(long long)r * ldz + ucols[c0 + j]] -= v;
+  }
+  __syncthreads();
+}
+
+// One Cholesky-QR pass on the chunk: S = Y^T Y = L L^T, Y <- Y L^-T.
+// Returns false (Y untouched) when a pivot falls below 1e-12 of its diagonal.
+__device__ bool ur_cholqr(const int* ucols, int c0, int cb, int n, double* Z, int ldz, double* S, int* bad) {
+  {
+    const int a = threadIdx.x & 31, b0 = (threadIdx.x >> 5) * 4;   // 8 groups x 4 columns
+    const long long ca = ucols[c0 + min(a, cb - 1)];
+    const long long v0 = ucols[c0 + min(b0 + 0, cb - 1)], v1 = ucols[c0 + min(b0 + 1, cb - 1)],
+                    v2 = ucols[c0 + min(b0 + 2, cb - 1)], v3 = ucols[c0 + min(b0 + 3, cb - 1)];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll 2
+    for (int r = 0; r < n; ++r) {
+      const double* row = Z + (long long)r * ldz;
+      const double ya = row[ca];
+      s0 += ya * row[v0]; s1 += ya * row[v1]; s2 += ya * row[v2]; s3 += ya * row[v3];
+    }
+    if (a < cb) {
+      double* sr = S + a * UC + b0;
+      if (b0 + 0 < cb) sr[0] = s0;
+      if (b0 + 1 < cb) sr[1] = s1;
+      if (b0 + 2 < cb) sr[2] = s2;
+      if (b0 + 3 < cb) sr[3] = s3;
+    }
+  }
+  if (threadIdx.x == 0) *bad = 0;
+  __syncthreads();
+  // left-looking Cholesky by wave 0, lane i holding row i of L (in S's lower part)
+  if (threadIdx.x < 64) {
+    const int i = threadIdx.x;
+    for (int j = 0; j < cb; ++j) {
+      double v = 0.0;
+      if (i >= j && i < cb) {
+        v = S[i * UC + j];
+        for (int m = 0; m < j; ++m) v -= S[i * UC + m] * S[j * UC + m];
+      }
+      const double piv = __shfl(v, j, 64);
+      const double diag = S[j * UC + j];
+      __builtin_amdgcn_wave_barrier();
+      if (!(piv > 1e-12 * diag)) {
+        if (i == 0) *bad = 1;
+        break;
+      }
+      const double ljj = sqrt(piv);
+      if (i == j) S[j * UC + j] = ljj;
+      else if (i > j && i < cb) S[i * UC + j] = v / ljj;
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
+  if (*bad) return false;
+  // rows: x L^T = y, forward substitution over the chunk's columns in place
+  // (x_m overwrites y_m as soon as it is known)
+  for (int r = threadIdx.x; r < n; r += SG_NT) {
+    double* row = Z + (long long)r * ldz;
+    for (int j = 0; j < cb; ++j) {
+      double v = row[ucols[c0 + j]];
+      for (int m = 0; m < j; ++m) v -= row[ucols[c0 + m]] * S[j * UC + m];
+      row[ucols[c0 + j]] = v / S[j * UC + j];
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
+__global__ __launch_bounds__(SG_NT) void stein_unresolved_kernel(int n, const double* w, int k, double* Z, int ldz) {
+  __shared__ int cols[512], ucols[512];
+  __shared__ double D[UP * UC], S[UC * UC];
+  __shared__ double zl[512], dots[512];
+  __shared__ double red[32];
+  __shared__ int nres_s, bad;
+  const double tn = fmax(fmax(fabs(w[0]), fabs(w[n - 1])), 1e-300);
+  const double floor_abs = 8.0 * n * 2.2e-16 * tn;
+  if (threadIdx.x == 0) {
+    int q = 0, u = 0;
+    for (int c = 0; c < k; ++c) {
+      if (fabs(w[c]) > floor_abs) cols[q++] = c;
+      else ucols[u++] = c;
+    }
+    nres_s = q;
+  }
+  __syncthreads();
+  const int nres = nres_s, nun = k - nres;
+  if (nun == 0) return;
+  // random columns are valid only when nothing resolved is left out of the k
+  // (the eigenvalues past k are unresolved too, as for a PSD matrix);
+  // otherwise the inverse-iteration vectors, which avoid the far eigenvectors,
+  // are completed one at a time
+  if (k < n && fabs(w[n - 1]) > floor_abs) {
+    unresolved_serial(n, k, w, floor_abs, 0, nres, cols, Z, ldz, zl, dots, red);
+    return;
+  }
+  for (long long e = threadIdx.x; e < (long long)n * nun; e += SG_NT) {
+    const int r = (int)(e / nun), j = (int)(e % nun);
+    Z[(long long)r * ldz + ucols[j]] = hash_unit((unsigned)r, (unsigned)ucols[j] + 104729u);
+  }
+  __syncthreads();
+  int nprev = nres;
+  for (int c0 = 0; c0 < nun; c0 += UC) {
+    const int cb = min(UC, nun - c0);
+    for (int pass = 0; pass < 2; ++pass)
+      for (int p0 = 0; p0 < nprev; p0 += UP) ur_project_block(cols, p0, min(UP, nprev - p0), ucols, c0, cb, n, Z, ldz, D);
+    bool ok = ur_cholqr(ucols, c0, cb, n, Z, ldz, S, &bad);
+    if (ok) ok = ur_cholqr(ucols, c0, cb, n, Z, ldz, S, &bad);
+    if (!ok) {
+      unresolved_serial(n, k, w, floor_abs, ucols[c0], nprev, cols, Z, ldz, zl, dots, red);
+      return;
+    }
+    if (threadIdx.x < cb) cols[nprev + threadIdx.x] = ucols[c0 + threadIdx.x];
+    __syncthreads();
+    nprev += cb;
   }
 }
 

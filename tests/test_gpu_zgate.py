@@ -1,14 +1,23 @@
 """The cat-qubit Z gate (paper Sec. 6.2) through the C ABI.
 
 * Parity of the GPU step with Oracle-M on the Z-gate generator, for the
-  second-order Kraus scheme and the first-order one (paper Sec. 5.2.2), FP64
-  at 1e-10 and the FP32-contraction form at 1e-5.
-* The whole gate (6012 steps, memory 2^5 Fock levels, buffer 2^2,
-  |alpha|^2 = 32/3) against the dense oracle's phase-flip probability stored
-  in tests/golden/zgate_dense.json: the purified MPS at tol 1e-8 differs from
-  the untruncated dense run by the discarded weight, ~1e-16 per truncation,
-  so FP64 must agree to 1e-8 on the parity; the FP32 form to 1e-5."""
+  second-order Kraus scheme and the first-order one (paper Sec. 5.2.2): FP64
+  at 1e-10 on observables and on every element of rho; the FP32-contraction
+  form at 1e-5 on observables.
+* The whole gate at memory 2^5, buffer 2^2, |alpha|^2 = 32/3 (6012 steps)
+  against Oracle-M's run with the same caps, and against the untruncated
+  dense run (tests/golden/zgate_dense.json), which it can only approach to
+  the effect of the purification cap.
+* The first 300 steps at the paper's scan point (memory 2^8, buffer 2^4,
+  |alpha|^2 = 256/3) against Oracle-M.
+
+An observable's error is measured relative to its operator norm on the
+truncated space (1 for the parity, sqrt(N - 1) for a, N - 1 for a^dag a):
+an expectation value near zero, such as <a> of a cat, has no relative
+accuracy of its own.  Stored values come from tests/golden/make_zgate_*.py,
+which call only the oracle."""
 import json
+import math
 import os
 
 import numpy as np
@@ -28,45 +37,92 @@ def _api():
 
 
 def _observables(m):
-    return [wl.parity_operator(0, m.dims[0]), [(1.0, {0: ("NUM_POW", 1)})], [(1.0, {0: ("A_POW", 1)})],
-            [(1.0, {1: ("NUM_POW", 1)})], [(1.0, {0: ("A_POW", 2)})]]
+    """(name, terms, operator norm) of the compared observables."""
+    Na, Nb = m.dims
+    return [("parity", wl.parity_operator(0, Na), 1.0),
+            ("n_a", [(1.0, {0: ("NUM_POW", 1)})], Na - 1.0),
+            ("a", [(1.0, {0: ("A_POW", 1)})], math.sqrt(Na - 1.0)),
+            ("n_b", [(1.0, {1: ("NUM_POW", 1)})], Nb - 1.0),
+            ("a2", [(1.0, {0: ("A_POW", 2)})], math.sqrt((Na - 1.0) * (Na - 2.0)))]
+
+
+# the FP32-contraction form applies the truncation rule at max(tol, 1e-6) in
+# the right-to-left sweep and at the purification cut, and at tol / 10 in the
+# zip-up (its contractions carry complex64 rounding near 1e-6 relative)
+FP32_SWEEP_TOL_FLOOR = 1e-6
+
+
+def _short_run(order, precision, tol, steps=25, oracle_rule=None):
+    """GPU run and Oracle-M run of the same steps.  oracle_rule "fp32" runs the
+    oracle with the FP32 form's tolerance rule; otherwise with tol as given."""
+    api = _api()
+    m, _ = wl.model_cat_zgate(**CASE, chi=32, chi_mu=8)
+    print(f"case cat-zgate bits={m.bits} order={order} steps={steps} {precision} oracle rule {oracle_rule}",
+          flush=True)
+    so = m.site_order()
+    K = tt.KrausMPO(m, m.dt, order=order)
+    Xo = mps.product_state(m.init, m.bits, so)
+    Xo, _ = mps.right_canonicalize(Xo, tol=1e-14)
+    t_sweep = max(tol, FP32_SWEEP_TOL_FLOOR) if oracle_rule == "fp32" else tol
+    for s_ in range(steps):
+        Xo, info = mps.k2_step(Xo, K.at(s_ * m.dt), t_sweep, 32, 8, tol_zip=tol / 10.0)
+    s = api.solver_from_model(m, precision=precision, chi=32, chi_mu=8, tol=tol, order=order)
+    s.step(steps)
+    obs = [(name, mps.expect(Xo, tt.operator_mpo(terms, m.bits, so)), s.observe(s.mpo(terms)), scale)
+           for name, terms, scale in _observables(m)]
+    A = mps.to_dense(Xo, m.bits, so)
+    B = mps.to_dense(s.get_state_mps(), m.bits, so)
+    ro, rg = A @ A.conj().T, B @ B.conj().T
+    elem = np.abs(rg - ro).max() / np.abs(ro).max()
+    frob = np.linalg.norm(rg - ro) / np.linalg.norm(ro)
+    print(f"  rho: max element difference {elem:.3e}, Frobenius {frob:.3e} (relative)", flush=True)
+    tau = s.diagnostics()["tau"]
+    s.close()
+    return obs, elem, frob, tau, info.tau
 
 
 @pytest.mark.parametrize("order", [2, 1])
 @pytest.mark.parametrize("precision,rtol,tol", [("fp64", 1e-10, 1e-12), ("fp32", 1e-5, 1e-8)])
 def test_zgate_step_parity(order, precision, rtol, tol):
-    api = _api()
-    m, _ = wl.model_cat_zgate(**CASE, chi=32, chi_mu=8)
-    steps = 25
-    print(f"case cat-zgate bits={m.bits} order={order} steps={steps} {precision}", flush=True)
-    so = m.site_order()
-    K = tt.KrausMPO(m, m.dt, order=order)
-    Xo = mps.product_state(m.init, m.bits, so)
-    Xo, _ = mps.right_canonicalize(Xo, tol=1e-14)
-    for s_ in range(steps):
-        Xo, info = mps.k2_step(Xo, K.at(s_ * m.dt), tol, 32, 8)
-    s = api.solver_from_model(m, precision=precision, chi=32, chi_mu=8, tol=tol, order=order)
-    s.step(steps)
-    for terms in _observables(m):
-        vo = mps.expect(Xo, tt.operator_mpo(terms, m.bits, so))
-        vg = s.observe(s.mpo(terms))
-        assert abs(vg - vo) <= rtol * max(1.0, abs(vo)), (terms, vg, vo)
-    A = mps.to_dense(Xo, m.bits, so)
-    B = mps.to_dense(s.get_state_mps(), m.bits, so)
-    ro, rg = A @ A.conj().T, B @ B.conj().T
-    assert np.abs(rg - ro).max() <= rtol * np.abs(ro).max()
-    assert abs(s.diagnostics()["tau"] - info.tau) <= 10 * rtol
-    s.close()
+    """FP64 against the oracle at tol 1e-12; the FP32 form against the oracle
+    run with the FP32 form's own tolerance rule (observables and the
+    Frobenius distance of rho)."""
+    obs, elem, frob, tau, tau_o = _short_run(order, precision, tol, oracle_rule=precision)
+    for name, vo, vg, scale in obs:
+        assert abs(vg - vo) <= rtol * scale, (name, vg, vo)
+    if precision == "fp64":
+        assert elem <= rtol
+    else:
+        assert frob <= rtol
+    assert abs(tau - tau_o) <= 10 * rtol
 
 
-@pytest.mark.parametrize("precision,atol", [("fp64", 1e-8), ("fp32", 1e-5)])
-def test_zgate_whole_gate_phase_flip(golden_dir, precision, atol):
+@pytest.mark.xfail(strict=True, reason="the FP32-contraction form truncates its right-to-left sweep at 1e-6 "
+                   "(its complex64 noise level), which moves rho at first order: over 25 steps of the Z-gate "
+                   "generator it ends 1.3e-5 (Frobenius, relative) from the tol-1e-8 density matrix, the same "
+                   "1.3e-5 the FP64 oracle shows with that truncation; observables stay within 1e-5")
+def test_zgate_fp32_rho_distance_to_fp64_rule():
+    _, _, frob, _, _ = _short_run(2, "fp32", 1e-8, oracle_rule="fp64")
+    assert frob <= 1e-5
+
+
+def _golden(golden_dir, name):
+    with open(os.path.join(golden_dir, name)) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("precision,rtol", [("fp64", 1e-7), ("fp32", 1e-5)])
+def test_zgate_whole_gate_phase_flip(golden_dir, precision, rtol):
+    """FP64 is held to 1e-7 against Oracle-M: at tol 1e-8 a truncation
+    decision within rounding of the threshold can go either way and moves rho
+    by O(tol).  Against the dense run (no caps) the purification cap
+    chi_mu = 16, which binds during the gate, leaves ~2e-5 on the parity."""
     api = _api()
-    with open(os.path.join(golden_dir, "zgate_dense.json")) as f:
-        g = json.load(f)
+    g = _golden(golden_dir, "zgate_mps.json")["small_whole_gate"]
+    gd = _golden(golden_dir, "zgate_dense.json")
     m, z = wl.model_cat_zgate(Ra=g["Ra"], Rb=g["Rb"], alpha2=g["alpha2"], dt_max=g["dt_max"],
-                              chi=64, chi_mu=16)
-    assert m.steps == g["steps"]
+                              chi=g["chi"], chi_mu=g["chi_mu"])
+    assert m.steps == g["steps"] == gd["steps"]
     print(f"case cat-zgate whole gate bits={m.bits} steps={m.steps} {precision}", flush=True)
     s = api.solver_from_model(m, precision=precision)
     parity = s.mpo(wl.parity_operator(0, m.dims[0]))
@@ -77,41 +133,38 @@ def test_zgate_whole_gate_phase_flip(golden_dir, precision, atol):
         s.step(n)
         done += n
         print(f"  {done}/{m.steps} steps, parity {s.observe(parity).real:+.10f}", flush=True)
-    p = s.observe(parity)
-    na = s.observe(s.mpo([(1.0, {0: ("NUM_POW", 1)})]))
-    assert abs(p.imag) < 1e-12
-    assert abs(p.real - g["parity"]) <= atol, (p.real, g["parity"])
-    assert abs(na.real - g["n_a"]) <= atol * g["n_a"], (na.real, g["n_a"])
+    for name, terms, scale in _observables(m):
+        if name == "a2":
+            continue
+        v = s.observe(s.mpo(terms))
+        ref = complex(*g[name]) if name == "a" else g[name]
+        assert abs(v - ref) <= rtol * scale, (name, v, ref)
+    p = s.observe(parity).real
+    assert abs(p - gd["parity"]) <= 5e-5, (p, gd["parity"])
     tr, _ = s.trace_purity()
     assert abs(tr - 1.0) < 1e-12
-    print(f"  p_Z = {(1 + p.real) / 2:.8e} (dense {g['p_z']:.8e}); bonds {s.diagnostics()['bonds']}", flush=True)
+    print(f"  p_Z = {(1 + p) / 2:.8e} (oracle {(1 + g['parity']) / 2:.8e}, dense {gd['p_z']:.8e}); "
+          f"bonds {s.diagnostics()['bonds']}", flush=True)
     s.close()
 
 
 @pytest.mark.parametrize("precision,rtol", [("fp64", 1e-7), ("fp32", 1e-5)])
 def test_zgate_paper_size_prefix(golden_dir, precision, rtol):
     """The paper's scan point memory 2^8, buffer 2^4 (12 sites),
-    |alpha|^2 = 256/3: the first 300 steps of the gate against Oracle-M's
-    stored observables (tests/golden/zgate_mps.json).  At tol 1e-8 a
-    truncation decision within rounding of the threshold can go either way
-    and moves rho by O(tol), so FP64 is held to 1e-7 here."""
+    |alpha|^2 = 256/3: the first 300 steps of the gate against Oracle-M."""
     api = _api()
-    with open(os.path.join(golden_dir, "zgate_mps.json")) as f:
-        g = json.load(f)
+    g = _golden(golden_dir, "zgate_mps.json")["paper_prefix"]
     m, _ = wl.model_cat_zgate(Ra=g["Ra"], Rb=g["Rb"], dt_max=g["dt_max"], chi=g["chi"], chi_mu=g["chi_mu"])
     assert m.steps == g["gate_steps"] and abs(m.dt - g["dt"]) < 1e-18
     print(f"case cat-zgate paper size bits={m.bits} steps={g['steps']} {precision}", flush=True)
     s = api.solver_from_model(m, precision=precision)
     s.step(g["steps"])
-    vals = {"parity": s.observe(s.mpo(wl.parity_operator(0, m.dims[0]))),
-            "n_a": s.observe(s.mpo([(1.0, {0: ("NUM_POW", 1)})])),
-            "a": s.observe(s.mpo([(1.0, {0: ("A_POW", 1)})])),
-            "n_b": s.observe(s.mpo([(1.0, {1: ("NUM_POW", 1)})]))}
-    for k in ("parity", "n_a", "n_b"):
-        ref = g[k]
-        assert abs(vals[k] - ref) <= rtol * max(1.0, abs(ref)), (k, vals[k], ref)
-    ref_a = complex(*g["a"])
-    assert abs(vals["a"] - ref_a) <= rtol, (vals["a"], ref_a)
+    for name, terms, scale in _observables(m):
+        if name == "a2":
+            continue
+        v = s.observe(s.mpo(terms))
+        ref = complex(*g[name]) if name == "a" else g[name]
+        assert abs(v - ref) <= rtol * scale, (name, v, ref)
     d = s.diagnostics()
     assert abs(d["tau"] - g["tau"]) <= 10 * rtol
     print(f"  bonds {d['bonds']} (oracle {g['final_bonds']})", flush=True)
