@@ -1945,8 +1945,9 @@ __device__ void unresolved_serial(int n, int k, const double* w, double floor_ab
 // Unresolved eigenvalues (after stein_groups_kernel has finished the groups).
 // Their vectors may be any orthonormal basis of what the resolved vectors
 // leave, so they are made in blocks: seeded random columns, projected out of
-// the span of the resolved vectors and of the earlier unresolved chunks by
-// block Gram-Schmidt (two passes, UP earlier vectors at a time), then made
+// the span of the resolved vectors (stein_unresolved_project_kernel, one
+// workgroup per column) and of the earlier unresolved chunks by block
+// Gram-Schmidt (two passes, UP earlier vectors at a time), then made
 // orthonormal within each chunk of UC columns by two Cholesky-QR passes.
 // Random columns in a complement of dimension >= their count are well
 // conditioned; a chunk whose Gram matrix still loses a pivot (below 1e-12 of
@@ -2063,6 +2064,59 @@ __device__ bool ur_cholqr(const int* ucols, int c0, int cb, int n, double* Z, in
   return true;
 }
 
+// First part of the blocked form, one workgroup per kept column (those of
+// resolved eigenvalues leave at once): the column gets its seeded random
+// vector, projected out of the span of the resolved vectors twice (classical
+// Gram-Schmidt against the whole set, the vector held in LDS).  Workgroups
+// read only resolved columns and write only their own.
+__global__ __launch_bounds__(SG_NT) void stein_unresolved_project_kernel(int n, const double* w, int k, double* Z,
+                                                                         int ldz) {
+  __shared__ int cols[512];
+  __shared__ double yl[512], d[512];
+  __shared__ int nres_s;
+  const double tn = fmax(fmax(fabs(w[0]), fabs(w[n - 1])), 1e-300);
+  const double floor_abs = 8.0 * n * 2.2e-16 * tn;
+  const int j = blockIdx.x;
+  if (j >= k || fabs(w[j]) > floor_abs) return;
+  if (k < n && fabs(w[n - 1]) > floor_abs) return;   // completed one column at a time instead
+  if (threadIdx.x == 0) {
+    int q = 0;
+    for (int c = 0; c < k; ++c)
+      if (fabs(w[c]) > floor_abs) cols[q++] = c;
+    nres_s = q;
+  }
+  for (int r = threadIdx.x; r < n; r += SG_NT) yl[r] = hash_unit((unsigned)r, (unsigned)j + 104729u);
+  __syncthreads();
+  const int nres = nres_s;
+  for (int pass = 0; pass < 2 && nres > 0; ++pass) {
+    for (int p = threadIdx.x; p < nres; p += SG_NT) {
+      const long long c = cols[p];
+      double a0 = 0.0, a1 = 0.0;
+      int r = 0;
+      for (; r + 1 < n; r += 2) {
+        a0 += Z[(long long)r * ldz + c] * yl[r];
+        a1 += Z[(long long)(r + 1) * ldz + c] * yl[r + 1];
+      }
+      if (r < n) a0 += Z[(long long)r * ldz + c] * yl[r];
+      d[p] = a0 + a1;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < n; r += SG_NT) {
+      const double* row = Z + (long long)r * ldz;
+      double v0 = 0.0, v1 = 0.0;
+      int p = 0;
+      for (; p + 1 < nres; p += 2) {
+        v0 += row[cols[p]] * d[p];
+        v1 += row[cols[p + 1]] * d[p + 1];
+      }
+      if (p < nres) v0 += row[cols[p]] * d[p];
+      yl[r] -= v0 + v1;
+    }
+    __syncthreads();
+  }
+  for (int r = threadIdx.x; r < n; r += SG_NT) Z[(long long)r * ldz + j] = yl[r];
+}
+
 __global__ __launch_bounds__(SG_NT) void stein_unresolved_kernel(int n, const double* w, int k, double* Z, int ldz) {
   __shared__ int cols[512], ucols[512];
   __shared__ double D[UP * UC], S[UC * UC];
@@ -2090,16 +2144,14 @@ __global__ __launch_bounds__(SG_NT) void stein_unresolved_kernel(int n, const do
     unresolved_serial(n, k, w, floor_abs, 0, nres, cols, Z, ldz, zl, dots, red);
     return;
   }
-  for (long long e = threadIdx.x; e < (long long)n * nun; e += SG_NT) {
-    const int r = (int)(e / nun), j = (int)(e % nun);
-    Z[(long long)r * ldz + ucols[j]] = hash_unit((unsigned)r, (unsigned)ucols[j] + 104729u);
-  }
-  __syncthreads();
+  // stein_unresolved_project_kernel has filled the unresolved columns and
+  // projected them out of the resolved ones; here only the earlier
+  // unresolved chunks (cols[nres..nprev)) remain to be projected out
   int nprev = nres;
   for (int c0 = 0; c0 < nun; c0 += UC) {
     const int cb = min(UC, nun - c0);
     for (int pass = 0; pass < 2; ++pass)
-      for (int p0 = 0; p0 < nprev; p0 += UP) ur_project_block(cols, p0, min(UP, nprev - p0), ucols, c0, cb, n, Z, ldz, D);
+      for (int p0 = nres; p0 < nprev; p0 += UP) ur_project_block(cols, p0, min(UP, nprev - p0), ucols, c0, cb, n, Z, ldz, D);
     bool ok = ur_cholqr(ucols, c0, cb, n, Z, ldz, S, &bad);
     if (ok) ok = ur_cholqr(ucols, c0, cb, n, Z, ldz, S, &bad);
     if (!ok) {
@@ -2179,6 +2231,8 @@ hipError_t trid_vectors(int n, const TridWork& t, const double* w, int kvec, hip
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(stein_groups_kernel, dim3(kvec), dim3(SG_NT), 0, s, n, t.d, t.e, w, kvec, 1e-8, t.Z, n);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(stein_unresolved_project_kernel, dim3(kvec), dim3(SG_NT), 0, s, n, w, kvec, t.Z, n);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(stein_unresolved_kernel, dim3(1), dim3(SG_NT), 0, s, n, w, kvec, t.Z, n);
   return hipGetLastError();
