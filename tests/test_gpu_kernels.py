@@ -159,3 +159,25 @@ def test_reduction_wait_timeout_leaves_cleanly():
     w, U, _ = api.kernel_heev(G, method="tridiag")
     ref = np.linalg.eigvalsh(G)[::-1]
     assert np.abs(w - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n,rank,negative", [(300, 10, 0), (200, 12, 5), (64, 3, 0), (512, 40, 8)])
+def test_heev_tridiag_low_rank_unresolved_block(n, rank, negative):
+    """A Hermitian matrix of small rank, some of it negative: all but `rank`
+    eigenvalues sit at the rounding floor, below what the reduction resolves,
+    so their vectors come from the blocked completion (random columns made
+    orthogonal to the resolved vectors, then Cholesky-QR in chunks of 32):
+    the whole basis must still be orthonormal and every eigenpair's residual
+    at the eps ||G|| level."""
+    api = _api()
+    rng = np.random.Generator(np.random.PCG64(wl.SEED + n + rank))
+    X = rng.standard_normal((n, rank)) + 1j * rng.standard_normal((n, rank))
+    sign = np.ones(rank)
+    sign[:negative] = -1.0
+    G = (X * sign) @ X.conj().T / n
+    w, U, _ = api.kernel_heev(G, "tridiag")
+    ref = np.linalg.eigvalsh(G)[::-1]
+    scale = np.abs(ref).max()
+    assert np.abs(w - ref).max() <= 1e-13 * scale
+    assert np.abs(U.conj().T @ U - np.eye(n)).max() < 1e-13
+    assert np.abs(G @ U - U * w).max() <= 1e-12 * scale
