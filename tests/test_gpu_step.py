@@ -108,6 +108,13 @@ def test_step_driven_transmon(precision, rtol, tol):
     _compare(wl.model_transmon_resonator(Rt=4, Rr=3, eps=2.0, dt=2e-4), 20, 16, 8, precision, rtol, tol)
 
 
+@pytest.mark.parametrize("precision,rtol,tol", FORMS)
+def test_step_transmon_eigenbasis(precision, rtol, tol):
+    """The driven transmon in its own eigenbasis (16 of the states of
+    |n| <= 40), its terms given as explicit matrices, + resonator 2^3."""
+    _compare(wl.model_transmon_eigen(Rt=4, Rr=3, n_cut=40, dt=2e-4), 20, 16, 8, precision, rtol, tol)
+
+
 def test_step_caps_bind_ragged():
     """Caps below the exact ranks (truncation by cap at every bond), odd sizes."""
     _compare(wl.model_cat_buffer(Ra=4, Rb=3, alpha2=3.0, dt=1e-3), 15, 6, 3, "fp64", 1e-10, 1e-12)

@@ -207,3 +207,29 @@ def test_cat_zgate_phase_flip_law(golden_dir):
     r_hi, r_lo = p_hi / law(32.0 / 3.0), p_lo / law(16.0 / 3.0)
     assert 1.0 <= r_hi < 1.10 and 1.0 <= r_lo < 1.10, (r_hi, r_lo)
     assert abs(r_hi / r_lo - 1.0) < 0.005, (r_hi, r_lo)
+
+
+def test_transmon_eigenbasis_reproduces_charge_basis():
+    """The driven transmon + resonator written in the transmon's own
+    eigenbasis (paper Sec. 7.2: diagonalise in the charge basis, keep the
+    lowest 2^R states, the charge operator as [n]_ab) evolves like the
+    charge-basis model it comes from: 16 of 32 eigenstates, resonator 2^2,
+    2000 steps of the dense second-order Kraus map.  What the dropped upper
+    levels carry is far below the bound; a wrong matrix element, a missing
+    offset charge or a scale error in either term moves <a> by far more."""
+    Rc, Rk, Rr = 5, 4, 2
+    charges = np.arange(-(1 << (Rc - 1)), 1 << (Rc - 1))
+    mc = wl.model_transmon_resonator(Rt=Rc, Rr=Rr, init_t=wl.transmon_ground_state(Rc, 50.0, 0.25))
+    me = wl.model_transmon_eigen(Rt=Rk, Rr=Rr, charges=charges)
+    h, steps = 1e-5, 2000
+    vals = []
+    for m in (mc, me):
+        dm = dense.DenseModel(m)
+        rho = dense.kraus_evolve(dm, _rho(dm.psi0), h, steps)
+        a = dense_operator([(1.0, {1: ("A_POW", 1)})], m.dims)
+        n = dense_operator([(1.0, {1: ("NUM_POW", 1)})], m.dims)
+        vals.append((np.trace(a @ rho), np.trace(n @ rho).real))
+    (ac, nc), (ae, ne) = vals
+    assert abs(ac) > 1e-2                       # the drive has moved the resonator
+    assert abs(ae - ac) <= 1e-7 * abs(ac), (ae, ac)
+    assert abs(ne - nc) <= 1e-7 * nc, (ne, nc)

@@ -247,6 +247,45 @@ def transmon_ground_state(Rt: int, ej_over_ec: float = 50.0, ng: float = 0.25) -
     return g * np.sign(g[np.argmax(np.abs(g))].real)
 
 
+def transmon_eigenbasis(n_keep: int, charges: np.ndarray, ej_over_ec: float = 50.0,
+                        ng: float = 0.25) -> tuple[np.ndarray, np.ndarray]:
+    """Lowest n_keep eigenstates Psi_a of H_t = 4 (n - ng)^2 - (E_J/2)(T_1 + T_-1)
+    on the given charge states (E_C = 1): their energies and the charge
+    operator in that basis, [n]_ab = sum_n Psi_a(n) n Psi_b(n) (paper Sec. 7.2)."""
+    n = np.asarray(charges, dtype=float)
+    H = np.diag(4.0 * (n - ng) ** 2) - 0.5 * ej_over_ec * (np.eye(len(n), k=1) + np.eye(len(n), k=-1))
+    w, v = np.linalg.eigh(H)
+    V = v[:, :n_keep]
+    return w[:n_keep], V.T @ (n[:, None] * V)
+
+
+def model_transmon_eigen(Rt: int = 5, Rr: int = 10, n_cut: int = 500, charges: np.ndarray | None = None,
+                         ej_over_ec: float = 50.0, ng: float = 0.25, omega_r: float = 30.0, g: float = 0.5,
+                         eps: float = 2.0, omega_d: float = 30.0, kappa: float = 0.05, dt: float = 2e-5,
+                         steps: int = 200, chi: int = 256, chi_mu: int = 32) -> Model:
+    """The driven transmon + resonator of model_transmon_resonator with the
+    transmon in its own eigenbasis (paper Sec. 7.2): the charge Hamiltonian is
+    diagonalised on |n| <= n_cut (or the given charges), the lowest 2^Rt
+    states are kept, and the transmon enters as explicit matrices: diag of the
+    energies (counted from the ground state) and the charge operator in that
+    basis.  Start: transmon ground state x resonator vacuum."""
+    if charges is None:
+        charges = np.arange(-n_cut, n_cut + 1)
+    e, nmat = transmon_eigenbasis(1 << Rt, charges, ej_over_ec, ng)
+    Ht = np.diag(e - e[0]).astype(complex)
+    nm = nmat.astype(complex)
+    H0 = [(1.0, {0: ("DENSE", Ht)}),
+          (omega_r, {1: ("NUM_POW", 1)}),
+          (1j * g, {0: ("DENSE", nm), 1: ("ADAG_POW", 1)}),
+          (-1j * g, {0: ("DENSE", nm), 1: ("A_POW", 1)})]
+    H1 = [(eps, {1: ("A_POW", 1)}), (eps, {1: ("ADAG_POW", 1)})]
+    jumps = [[(math.sqrt(kappa), {1: ("A_POW", 1)})]]
+    return Model(name="transmon-eigen-resonator", bits=[Rt, Rr], H0=H0, H1=H1,
+                 drive=[(1.0, omega_d, 0.0)], jumps=jumps,
+                 init=[fock_amplitudes(1 << Rt, 0), vacuum(1 << Rr)], dt=dt, steps=steps, chi=chi,
+                 chi_mu=chi_mu)
+
+
 # stable time steps of the three families (explicit-scheme bound, E_C = 1 units)
 SERVING_DT = {"two-photon-cat": 5e-5, "cat-buffer": 2.5e-5, "transmon-resonator": 1.5e-7}
 
