@@ -92,7 +92,7 @@ lb_status lindblad_kernel_heev(int32_t n, const double* G, double* w, double* U,
       if ((e = lbk::orthonormalize_columns((double*)dV.p, n, n, n, (double*)dG.p, (double*)dT.p, 2, nullptr, s)) != hipSuccess) { rc = hip_fail(e, "orthonormalize"); break; }
       if ((e = hipStreamSynchronize(s)) != hipSuccess) { rc = hip_fail(e, "sync"); break; }
     } else {
-      if ((e = lbk::heev_jacobi((double*)dG.p, n, 0, n, (double*)dw.p, 0, (double*)dV.p, 1, 1.5e-15, 40,
+      if ((e = lbk::heev_jacobi((double*)dG.p, n, 0, n, (double*)dw.p, 0, (double*)dV.p, 1, lbk::kJacobiRelTol, 40,
                                 (int*)di.p, s)) != hipSuccess) { rc = hip_fail(e, "heev"); break; }
     }
     int info = 0;

@@ -500,7 +500,7 @@ void mm(lb_solver* s, int M, int N, int K, const void* A, Prec pa, long long lda
 // Jacobi (relative accuracy; second pass of LB_FP64): eigenvectors in G.
 void eig_jacobi(lb_solver* s, double* G, int n, double* lam) {
   Timed tm(s, PC_JACOBI, 0.0, 32.0 * n * n);
-  HIPCHK(lbk::heev_jacobi(G, n, 0, n, lam, 0, s->V.d(), 1, 1.5e-15, 40, s->info.i(), s->stream));
+  HIPCHK(lbk::heev_jacobi(G, n, 0, n, lam, 0, s->V.d(), 1, lbk::kJacobiRelTol, 40, s->info.i(), s->stream));
 }
 
 // Tridiagonal route (absolute accuracy): G destroyed, all eigenvalues in

@@ -39,6 +39,13 @@ hipError_t gemm(const Gemm& g, hipStream_t stream);
 // V is scratch (batch * n * n complex).  rel_tol: rotate when
 // |g_pq| > rel_tol * sqrt(|g_pp g_qq|).  info[b] = sweeps used, or -1 if not
 // converged within max_sweeps.
+// Rotation threshold of the relative-accuracy Jacobi pass: a pair is rotated
+// while |g_pq| > t sqrt(g_pp g_qq).  Pairs whose diagonal entries are both
+// below kJacobiFloor times the largest diagonal entry are left alone: such
+// eigenvalues lie under the rounding of any explicitly formed Gram matrix
+// (sigma < 1e-14 sigma_1) and any orthonormal basis of them serves.
+constexpr double kJacobiRelTol = 1.5e-15;
+constexpr double kJacobiFloor = 1e-28;
 hipError_t heev_jacobi(double* G, int ldg, long long g_stride, int n, double* w, long long w_stride,
                        double* V, int batch, double rel_tol, int max_sweeps, int* info,
                        hipStream_t stream);

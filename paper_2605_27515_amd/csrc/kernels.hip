@@ -334,6 +334,13 @@ __global__ __launch_bounds__(HEEV_NT) void heev_kernel(double* Gall, int ldg, lo
     const int i = (int)(e / n), j = (int)(e % n);
     st(V, e, cplx{i == j ? 1.0 : 0.0, 0.0});
   }
+  __shared__ double gfloor;
+  if (tid == 0) {
+    double gmax = 0.0;
+    for (int j = 0; j < n; ++j) gmax = fmax(gmax, fabs(G[2 * ((long long)j * ldg + j)]));
+    gfloor = kJacobiFloor * gmax;
+  }
+  __syncthreads();
   int sweeps_used = -1;
   for (int sweep = 0; sweep < max_sweeps && n > 1; ++sweep) {
     if (tid == 0) nrot = 0;
@@ -349,7 +356,7 @@ __global__ __launch_bounds__(HEEV_NT) void heev_kernel(double* Gall, int ldg, lo
           const double a = G[2 * ((long long)p * ldg + p)], bb = G[2 * ((long long)q * ldg + q)];
           const cplx z = ld(G, (long long)p * ldg + q);
           const double az = sqrt(z.r * z.r + z.i * z.i);
-          if (az > rel_tol * sqrt(fabs(a * bb)) && az > 1e-300) {
+          if (az > rel_tol * sqrt(fabs(a * bb)) && az > 1e-300 && fmax(fabs(a), fabs(bb)) >= gfloor) {
             const double zeta = (bb - a) / (2.0 * az);
             const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
             c = 1.0 / sqrt(1.0 + tt * tt);
