@@ -181,3 +181,26 @@ def test_heev_tridiag_low_rank_unresolved_block(n, rank, negative):
     assert np.abs(w - ref).max() <= 1e-13 * scale
     assert np.abs(U.conj().T @ U - np.eye(n)).max() < 1e-13
     assert np.abs(G @ U - U * w).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("n,rank", [(64, 10), (128, 100), (256, 40)])
+def test_heev_jacobi_low_rank_second_pass(n, rank):
+    """The FP64 form's second pass on a Gram matrix of small rank: B = U0^H A
+    with U0 the eigenvectors of A A^H, G2 = B B^H nearly diagonal with most of
+    its diagonal at the rounding floor.  Pairs under 1e-28 of the largest
+    entry are left alone, so the sweeps stop after a few (10-12 when every
+    noise pair was rotated); the result stays orthonormal and accurate."""
+    api = _api()
+    rng = np.random.Generator(np.random.PCG64(wl.SEED + 17 * n + rank))
+    A = (rng.standard_normal((n, rank)) + 1j * rng.standard_normal((n, rank))) @ \
+        (rng.standard_normal((rank, 3 * n)) + 1j * rng.standard_normal((rank, 3 * n)))
+    _, U0 = np.linalg.eigh(A @ A.conj().T)
+    B = U0.conj().T @ A
+    G = B @ B.conj().T
+    w, U, sweeps = api.kernel_heev(G, "jacobi")
+    assert 0 < sweeps <= 5, sweeps
+    ref = np.linalg.eigvalsh(G)[::-1]
+    scale = np.abs(ref).max()
+    assert np.abs(w - ref).max() <= 1e-13 * scale
+    assert np.abs(U.conj().T @ U - np.eye(n)).max() < 1e-13
+    assert np.abs(G @ U - U * w).max() <= 1e-12 * scale
