@@ -320,6 +320,49 @@ def zgate_main(args) -> None:
     print(json.dumps(line), flush=True)
 
 
+def trajectory_main(args) -> None:
+    """The chi = 128 configuration run as physics: cat + buffer from vacuum x
+    vacuum, the same operators, caps and dt as the step benchmark, for
+    --trajectory-steps steps; bond profile, chi_mu and <n_a> every 500 steps."""
+    import torch
+    import workload as wl
+    from paper_2605_27515_amd import api
+    m = wl.model_cat_buffer(Ra=8, Rb=8, alpha2=8.0, dt=2.5e-5)
+    n_steps = args.trajectory_steps
+    print(f"bench: cat+buffer trajectory from vacuum, {n_steps} steps, {args.precision}", file=sys.stderr, flush=True)
+    s = api.solver_from_model(m, precision=args.precision, chi=128, chi_mu=16, device=0)
+    na = s.mpo([(1.0, {0: ("NUM_POW", 1)})])
+    history = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < n_steps:
+        n = min(500, n_steps - done)
+        s.step(n)
+        done += n
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        d = s.diagnostics()
+        history.append({"steps": done, "t": done * m.dt, "elapsed_s": el, "bonds": d["bonds"], "chi_mu": d["chi_mu"]})
+        print(f"bench: {done}/{n_steps} steps, {el:.1f} s, bonds {d['bonds']}, chi_mu {d['chi_mu']}",
+              file=sys.stderr, flush=True)
+    elapsed = time.perf_counter() - t0
+    n_a = s.observe(na).real
+    tr, pur = s.trace_purity()
+    s.close()
+    line = {
+        "metric": "purified-MPS steps/s of the physical chi=128 trajectory (vacuum start)",
+        "value": n_steps / elapsed, "unit": "steps/s", "n_gpus": 1, "steps": n_steps, "warmup": 0,
+        "ms_per_step": 1e3 * elapsed / n_steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": "cat+buffer 2x256 Fock (16 sites), alpha^2=8, 9 Kraus ops, chi=128, chi_mu=16, "
+                               "tol=1e-8, dt=2.5e-5, vacuum x vacuum start",
+                   "precision": args.precision, "parallelism": "single solve, one GPU"},
+        "final_n_a": n_a, "trace": tr, "purity": pur, "history": history,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -333,8 +376,10 @@ def main():
                     help="requests of the seeded serving stream (0: skip the serving leg)")
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
-    ap.add_argument("--workload", choices=["chi128", "cat-zgate"], default="chi128",
-                    help="chi128: the step benchmark (default); cat-zgate: the whole cat-qubit Z gate")
+    ap.add_argument("--workload", choices=["chi128", "cat-zgate", "chi128-trajectory"], default="chi128",
+                    help="chi128: the step benchmark (default); cat-zgate: the whole cat-qubit Z gate; "
+                         "chi128-trajectory: the same configuration run as physics from vacuum")
+    ap.add_argument("--trajectory-steps", type=int, default=5000)
     ap.add_argument("--zgate-dt", type=float, default=2e-4, help="largest time step of the Z-gate run")
     ap.add_argument("--zgate-chi", type=int, default=128, help="bond cap of the Z-gate run")
     ap.add_argument("--zgate-steps", type=int, default=0,
@@ -352,6 +397,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "cat-zgate":
         zgate_main(args)
+        return
+    if args.workload == "chi128-trajectory":
+        trajectory_main(args)
         return
     print(f"bench: {args.precision} steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
     if args.copy_calibration:
