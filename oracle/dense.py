@@ -89,7 +89,7 @@ def rk4_evolve(dm: DenseModel, rho: np.ndarray, h: float, n_steps: int,
 # ---------------------------------------------------------------------------
 
 def kraus_family(dm: DenseModel, t: float, h: float, order: int = 2) -> list[np.ndarray]:
-    """Kraus operators of one step, in the order used throughout this build:
+    """Kraus operators of one step, in the order the MPO stacking uses:
     [U1', sqrt(h/2) U1 L_k (k), sqrt(h/2) L_k U1 (k), (h/sqrt 2) L_k L_k' (k major)].
     order=1 gives [U1, sqrt(h) L_k]."""
     he = dm.H_eff(t + 0.5 * h)
