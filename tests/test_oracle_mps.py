@@ -111,3 +111,23 @@ def test_synthetic_saturated_state_keeps_caps():
     X = wl.synthetic_mps(L, chi_mu, chi)
     X, _ = mps.right_canonicalize(X)
     assert mps.bond_dims(X) + [X[-1].shape[2]] == wl.saturated_bonds(L, chi_mu, chi)[1:]
+
+
+def test_zgate_stored_prefix_is_the_oracles(golden_dir):
+    """tests/golden/zgate_mps.json's paper-size record (the first 300 steps of
+    the cat Z gate at memory 2^8, buffer 2^4, read by the GPU tests) is what
+    the oracle computes: recomputed here by the same committed script."""
+    import importlib.util
+    import json
+    import os
+    path = os.path.join(golden_dir, "make_zgate_mps.py")
+    spec = importlib.util.spec_from_file_location("make_zgate_mps", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    with open(os.path.join(golden_dir, "zgate_mps.json")) as f:
+        stored = json.load(f)["paper_prefix"]
+    fresh = mod.run(mod.PAPER, mod.PREFIX)
+    for k in ("parity", "n_a", "n_b", "tau"):
+        assert abs(fresh[k] - stored[k]) <= 1e-12 * max(1.0, abs(stored[k])), (k, fresh[k], stored[k])
+    assert abs(complex(*fresh["a"]) - complex(*stored["a"])) <= 1e-12
+    assert fresh["final_bonds"] == stored["final_bonds"]
