@@ -1955,7 +1955,8 @@ __device__ void unresolved_serial(int n, int k, const double* w, double floor_ab
 // the span of the resolved vectors (stein_unresolved_project_kernel, one
 // workgroup per column) and of the earlier unresolved chunks by block
 // Gram-Schmidt (two passes, UP earlier vectors at a time), then made
-// orthonormal within each chunk of UC columns by two Cholesky-QR passes.
+// orthonormal within each chunk of UC columns by Cholesky-QR (a second pass
+// when the first found the chunk less than well conditioned).
 // Random columns in a complement of dimension >= their count are well
 // conditioned; a chunk whose Gram matrix still loses a pivot (below 1e-12 of
 // its diagonal) is finished, with all later ones, one column at a time.
@@ -2009,8 +2010,10 @@ __device__ void ur_project_block(const int* cols, int p0, int pb, const int* uco
 }
 
 // One Cholesky-QR pass on the chunk: S = Y^T Y = L L^T, Y <- Y L^-T.
-// Returns false (Y untouched) when a pivot falls below 1e-12 of its diagonal.
-__device__ bool ur_cholqr(const int* ucols, int c0, int cb, int n, double* Z, int ldz, double* S, int* bad) {
+// Returns false (Y untouched) when a pivot falls below 1e-12 of its diagonal;
+// *minratio receives the smallest pivot / diagonal ratio.
+__device__ bool ur_cholqr(const int* ucols, int c0, int cb, int n, double* Z, int ldz, double* S, int* bad,
+                          double* minratio) {
   {
     const int a = threadIdx.x & 31, b0 = (threadIdx.x >> 5) * 4;   // 8 groups x 4 columns
     const long long ca = ucols[c0 + min(a, cb - 1)];
@@ -2031,11 +2034,12 @@ __device__ bool ur_cholqr(const int* ucols, int c0, int cb, int n, double* Z, in
       if (b0 + 3 < cb) sr[3] = s3;
     }
   }
-  if (threadIdx.x == 0) *bad = 0;
+  if (threadIdx.x == 0) { *bad = 0; *minratio = 1.0; }
   __syncthreads();
   // left-looking Cholesky by wave 0, lane i holding row i of L (in S's lower part)
   if (threadIdx.x < 64) {
     const int i = threadIdx.x;
+    double mr = 1.0;
     for (int j = 0; j < cb; ++j) {
       double v = 0.0;
       if (i >= j && i < cb) {
@@ -2049,11 +2053,13 @@ __device__ bool ur_cholqr(const int* ucols, int c0, int cb, int n, double* Z, in
         if (i == 0) *bad = 1;
         break;
       }
+      mr = fmin(mr, piv / diag);
       const double ljj = sqrt(piv);
       if (i == j) S[j * UC + j] = ljj;
       else if (i > j && i < cb) S[i * UC + j] = v / ljj;
       __builtin_amdgcn_wave_barrier();
     }
+    if (i == 0) *minratio = mr;
   }
   __syncthreads();
   if (*bad) return false;
@@ -2130,6 +2136,7 @@ __global__ __launch_bounds__(SG_NT) void stein_unresolved_kernel(int n, const do
   __shared__ double zl[512], dots[512];
   __shared__ double red[32];
   __shared__ int nres_s, bad;
+  __shared__ double minratio;
   const double tn = fmax(fmax(fabs(w[0]), fabs(w[n - 1])), 1e-300);
   const double floor_abs = 8.0 * n * 2.2e-16 * tn;
   if (threadIdx.x == 0) {
@@ -2159,8 +2166,11 @@ __global__ __launch_bounds__(SG_NT) void stein_unresolved_kernel(int n, const do
     const int cb = min(UC, nun - c0);
     for (int pass = 0; pass < 2; ++pass)
       for (int p0 = nres; p0 < nprev; p0 += UP) ur_project_block(cols, p0, min(UP, nprev - p0), ucols, c0, cb, n, Z, ldz, D);
-    bool ok = ur_cholqr(ucols, c0, cb, n, Z, ldz, S, &bad);
-    if (ok) ok = ur_cholqr(ucols, c0, cb, n, Z, ldz, S, &bad);
+    // a second pass only for a chunk that was not well conditioned: after one
+    // pass the columns are orthonormal to ~eps kappa^2 (kappa^2 <~ cb / ratio),
+    // and the Newton-Schulz step on all kept vectors removes the rest
+    bool ok = ur_cholqr(ucols, c0, cb, n, Z, ldz, S, &bad, &minratio);
+    if (ok && minratio < 0.1) ok = ur_cholqr(ucols, c0, cb, n, Z, ldz, S, &bad, &minratio);
     if (!ok) {
       unresolved_serial(n, k, w, floor_abs, ucols[c0], nprev, cols, Z, ldz, zl, dots, red);
       return;
