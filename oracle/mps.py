@@ -36,6 +36,9 @@ class StepInfo:
     bonds: list = field(default_factory=list)
     chi_mu: int = 1
     discarded: list = field(default_factory=list)
+    # relative discarded weight of each zip-up cut, sum_{j>k} s_j^2 / sum_j s_j^2
+    zip_discarded: list = field(default_factory=list)
+    zip_tail2: list = field(default_factory=list)   # the same, absolute: sum_{j>k} s_j^2
 
 
 def product_state(vectors, bits, site_order, tol: float = 1e-14) -> list[np.ndarray]:
@@ -85,6 +88,9 @@ def zipup(sites, W, tol_zip: float, chi_zip: int, tol: float, chi_mu: int, info:
             out.append(u[:, :k].reshape(ap, 2, k))
             C = (s[:k, None] * vh[:k]).reshape(k, b, v)
             info.zip_bonds.append(k)
+            total = float(np.sum(s ** 2))
+            info.zip_discarded.append(float(np.sum(s[k:] ** 2)) / total if total > 0 else 0.0)
+            info.zip_tail2.append(float(np.sum(s[k:] ** 2)))
         else:
             k = keep_rank(s, tol, chi_mu)
             out.append((u[:, :k] * s[None, :k]).reshape(ap, 2, k))
@@ -169,6 +175,37 @@ def rho_distance2(x1, x2) -> float:
     b = np.sum(np.abs(gram(x2)) ** 2)
     c = np.sum(np.abs(gram(x1, x2)) ** 2)
     return float(a + b - 2 * c)
+
+
+def rows(sites, idx) -> np.ndarray:
+    """Rows X[n, :] of the purification matrix (rho = X X^dag) at basis
+    indices n, each given as its digits in site order (sigma_1..sigma_L):
+    the product A_1[sigma_1] ... A_L[sigma_L] of one slice per site, a row
+    of length chi_mu.  rho_nm = X[n, :] . conj(X[m, :]) for any n, m, so
+    density-matrix entries can be compared one by one at any size."""
+    idx = np.asarray(idx, dtype=np.int64)
+    out = np.ones((idx.shape[0], 1), complex)
+    for i, A in enumerate(sites):
+        out = np.einsum('na,nab->nb', out, A[:, idx[:, i], :].transpose(1, 0, 2))
+    return out
+
+
+def sample_indices(sites, n: int, rng) -> np.ndarray:
+    """n basis indices (digits in site order) drawn from the diagonal of rho,
+    p(n) = rho_nn / Tr rho, by sequential conditional sampling.  Needs sites
+    2..L right-orthonormal (as between steps): the weight of a prefix is then
+    the squared norm of its partial row product."""
+    L = len(sites)
+    out = np.zeros((n, L), dtype=np.int64)
+    for j in range(n):
+        v = np.ones((1,), complex)
+        for i, A in enumerate(sites):
+            cand = np.stack([v @ A[:, 0, :], v @ A[:, 1, :]])      # [2, chi_i]
+            w = np.sum(np.abs(cand) ** 2, axis=1)
+            s = int(rng.random() * w.sum() >= w[0]) if w.sum() > 0 else 0
+            out[j, i] = s
+            v = cand[s]
+    return out
 
 
 def to_dense(sites, bits, site_order) -> np.ndarray:

@@ -65,7 +65,7 @@ def test_invariants_and_gauge():
     assert np.abs(Xd @ Xd.conj().T - Yd @ Yd.conj().T).max() < 1e-14
     # the overlap identity agrees within its rounding floor
     assert abs(mps.rho_distance2(X, Y)) < 1e-14
-    # dense cross-check of the rho distance identity
+    # the reconstructed density matrix is positive semidefinite (to rounding)
     Xa = mps.to_dense(X, m.bits, so)
     rho = Xa @ Xa.conj().T
     assert np.linalg.eigvalsh(0.5 * (rho + rho.conj().T)).min() > -1e-14
