@@ -28,7 +28,8 @@
  *  - One solver must not be used from two threads at once; distinct solvers
  *    may be used concurrently.
  *  - Device work is enqueued on the solver's HIP stream; lindblad_step is
- *    asynchronous with respect to the host except where noted.
+ *    asynchronous with respect to the host; the calls that read results wait
+ *    for the stream (noted at each).
  */
 #ifndef LINDBLAD_H
 #define LINDBLAD_H
@@ -58,9 +59,9 @@ enum lb_precision {
   LB_FP32_CONTRACT = 1  /* MPO/MPS contractions in complex64 (FP32 accumulate);
                            Gram matrices, eigen-decompositions, truncation
                            weights and trace in FP64.  The back-sweep and the
-                           purification cut run at max(tol, 1e-6) here:
-                           complex64 rounding puts noise singular values near
-                           1e-7 sigma_1                                        */
+                           purification cut run at max(tol, fp32_tol_floor)
+                           here: complex64 rounding puts noise singular values
+                           near 1e-7 sigma_1                                   */
 };
 
 typedef struct lb_config {
@@ -79,7 +80,17 @@ typedef struct lb_config {
   int32_t allow_unstable;          /* nonzero: skip the dt stability check       */
   void* stream;                    /* hipStream_t to use; NULL = a private stream */
   int32_t device;                  /* HIP device ordinal                         */
+  double fp32_tol_floor;           /* LB_FP32_CONTRACT only: the back-sweep and
+                                      purification cuts use max(tol, this);
+                                      <= 0 selects the default LB_FP32_TOL_FLOOR */
+  double tau_warn;                 /* a step whose pre-normalisation trace tau
+                                      exceeds 1 + tau_warn makes the next
+                                      lindblad_sync return LB_WARN_UNSTABLE;
+                                      <= 0 selects LB_TAU_WARN                  */
 } lb_config;
+
+#define LB_FP32_TOL_FLOOR 1e-6
+#define LB_TAU_WARN 1e-3
 
 typedef struct lb_solver lb_solver; /* opaque */
 typedef struct lb_op lb_op;         /* opaque MPO handle, owned by its solver */
@@ -197,12 +208,37 @@ lb_status lindblad_get_state_mps(lb_solver* s, int32_t* bonds, double** sites);
 
 /* ---- stepping ------------------------------------------------------------ */
 
-/* Advance by n_steps steps of the Kraus map (zip-up application, purification
- * truncation, right-to-left truncated-SVD sweep, trace renormalisation). */
+/* Enqueue n_steps steps of the Kraus map (zip-up application, purification
+ * truncation, right-to-left truncated-SVD sweep, trace renormalisation) on
+ * the solver's stream and return without waiting for them: the truncation
+ * ranks each step decides stay on the device, where the kernels that follow
+ * read them, and the step is launched as one captured HIP graph (direct
+ * launches while kernel timing is on).  What the steps find surfaces at the
+ * next call that waits for the stream (lindblad_sync, observe,
+ * trace_purity, get_state_mps, diagnostics): LB_ERR_NUMERIC for non-finite
+ * eigenvalues (also what a timed-out multi-workgroup reduction leaves) or a
+ * non-finite trace, after which the state is invalid and lindblad_step
+ * returns LB_ERR_NUMERIC until the next set_state_*.
+ * Errors: LB_ERR_ARG, LB_ERR_STATE (no generator or state), LB_ERR_NUMERIC
+ * (see above), LB_ERR_HIP. */
 lb_status lindblad_step(lb_solver* s, int32_t n_steps);
 
-/* Advance n solvers by n_steps each, sharing kernel launches across solvers
- * that live on the same device.  Solvers may differ in sizes and caps. */
+/* Wait for the solver's stream.  Returns LB_ERR_NUMERIC if an enqueued step
+ * produced non-finite values, else the positive LB_WARN_UNSTABLE if some
+ * step since the previous lindblad_sync had a pre-normalisation trace
+ * tau > 1 + tau_warn, else LB_OK.  The scheme is not trace preserving (end
+ * of paper Sec. 5.2.2): a stable step changes the trace by O(dt^3) and the
+ * truncations only lower it, while a dt beyond the explicit scheme's
+ * stability bound makes it grow step after step. */
+lb_status lindblad_sync(lb_solver* s);
+
+/* Advance n solvers by n_steps each and wait for all of them: every solver's
+ * steps are enqueued on its own stream, so their kernels overlap on the
+ * device (a solver whose co-resident reduction workgroups do not fit beside
+ * those of the solvers before it first waits for the earliest of them).
+ * Solvers may differ in sizes and caps.  Returns the first error of any
+ * solver (with its index in the message), else LB_WARN_UNSTABLE if any
+ * solver warned, else LB_OK. */
 lb_status lindblad_step_batch(lb_solver* const* s, int32_t n, int32_t n_steps);
 
 /* ---- device residency (for request loops that admit solves by memory) --- */
@@ -246,7 +282,8 @@ typedef struct lb_diag {
                                       [0] purification, [1..] back-sweep bonds  */
 } lb_diag;
 
-/* Diagnostics of the last step (synchronises). */
+/* Diagnostics of the last step (waits for the stream).  Errors:
+ * LB_ERR_NUMERIC as lindblad_sync. */
 lb_status lindblad_diagnostics(lb_solver* s, lb_diag* out);
 
 /* ---- live per-kernel timing ------------------------------------------------ */

@@ -26,7 +26,7 @@ FACTOR_KINDS = {"ID": 0, "A_POW": 1, "ADAG_POW": 2, "ADAG_A": 3, "NUM_POW": 4,
 EXPORTED = ["lindblad_default_config", "lindblad_create", "lindblad_destroy",
             "lindblad_mpo_build", "lindblad_op_info", "lindblad_op_site", "lindblad_set_generator",
             "lindblad_kraus_info", "lindblad_kraus_site", "lindblad_set_state_product", "lindblad_set_state_mps",
-            "lindblad_get_state_mps", "lindblad_step", "lindblad_step_batch",
+            "lindblad_get_state_mps", "lindblad_step", "lindblad_sync", "lindblad_step_batch",
             "lindblad_observe", "lindblad_trace_purity", "lindblad_diagnostics",
             "lindblad_last_error", "lindblad_profile", "lindblad_profile_mask", "lindblad_profile_read", "lindblad_kernel_zgemm", "lindblad_kernel_heev",
             "lindblad_kernel_truncate", "lindblad_kernel_set_wait_limit", "lindblad_get_config", "lindblad_footprint", "lindblad_release",
@@ -40,7 +40,8 @@ class LbConfig(C.Structure):
                 ("chi_cap", C.c_int32), ("chi_mu_cap", C.c_int32), ("chi_zip_cap", C.c_int32),
                 ("tol", C.c_double), ("tol_zip", C.c_double), ("order", C.c_int32),
                 ("precision", C.c_int32), ("allow_unstable", C.c_int32),
-                ("stream", C.c_void_p), ("device", C.c_int32)]
+                ("stream", C.c_void_p), ("device", C.c_int32),
+                ("fp32_tol_floor", C.c_double), ("tau_warn", C.c_double)]
 
 
 class LbFactor(C.Structure):
@@ -127,6 +128,7 @@ def load() -> C.CDLL:
     lib.lindblad_set_state_mps.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.POINTER(C.c_double))]
     lib.lindblad_get_state_mps.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.POINTER(C.c_double))]
     lib.lindblad_step.argtypes = [vp, C.c_int32]
+    lib.lindblad_sync.argtypes = [vp]
     lib.lindblad_step_batch.argtypes = [C.POINTER(vp), C.c_int32, C.c_int32]
     lib.lindblad_observe.argtypes = [vp, vp, C.POINTER(C.c_double)]
     lib.lindblad_trace_purity.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]

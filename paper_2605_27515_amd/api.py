@@ -64,7 +64,7 @@ class Solver:
     def __init__(self, bits, chi: int, chi_mu: int, tol: float = 1e-8, order: int = 2,
                  precision: str = "fp64", chi_zip: int = 0, tol_zip: float = 0.0,
                  site_order=None, stream: int | None = None, device: int = 0,
-                 allow_unstable: bool = False):
+                 allow_unstable: bool = False, fp32_tol_floor: float = 0.0, tau_warn: float = 0.0):
         lib = L.load()
         cfg = L.LbConfig()
         lib.lindblad_default_config(C.byref(cfg))
@@ -86,6 +86,8 @@ class Solver:
         cfg.allow_unstable = 1 if allow_unstable else 0
         cfg.stream = stream
         cfg.device = int(device)
+        cfg.fp32_tol_floor = float(fp32_tol_floor)
+        cfg.tau_warn = float(tau_warn)
         h = C.c_void_p()
         _check(lib.lindblad_create(C.byref(cfg), C.byref(h)), "create")
         self.h = h
@@ -179,8 +181,16 @@ class Solver:
         return arrs
 
     # ---- stepping and observation -------------------------------------------
-    def step(self, n: int = 1):
-        return _check(L.load().lindblad_step(self.h, int(n)), "step")
+    def step(self, n: int = 1, sync: bool = True):
+        """Enqueue n steps; with sync (the default) wait for them and return
+        the status of lindblad_sync (LB_OK or LB_WARN_UNSTABLE; errors raise)."""
+        rc = _check(L.load().lindblad_step(self.h, int(n)), "step")
+        if not sync:
+            return rc
+        return self.sync()
+
+    def sync(self):
+        return _check(L.load().lindblad_sync(self.h), "sync")
 
     def observe(self, op: Op) -> complex:
         out = (C.c_double * 2)()

@@ -122,7 +122,7 @@ lb_status lindblad_kernel_truncate(int32_t n, const double* lam, double tol, int
   lb_status rc = LB_OK;
   do {
     if ((e = hipMemcpyAsync(dl.p, lam, n * 8, hipMemcpyHostToDevice, s)) != hipSuccess) { rc = hip_fail(e, "copy"); break; }
-    if ((e = lbk::truncate_rank((double*)dl.p, n, tol, cap, (int*)dk.p, (double*)dd.p, s)) != hipSuccess) { rc = hip_fail(e, "trunc"); break; }
+    if ((e = lbk::truncate_rank((double*)dl.p, n, tol, cap, (int*)dk.p, (double*)dd.p, nullptr, s)) != hipSuccess) { rc = hip_fail(e, "trunc"); break; }
     double dh = 0.0;
     if ((e = hipMemcpyAsync(k, dk.p, 4, hipMemcpyDeviceToHost, s)) != hipSuccess) { rc = hip_fail(e, "copy"); break; }
     if ((e = hipMemcpyAsync(&dh, dd.p, 8, hipMemcpyDeviceToHost, s)) != hipSuccess) { rc = hip_fail(e, "copy"); break; }

@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <memory>
 #include <stdexcept>
@@ -210,13 +211,20 @@ struct lb_solver {
   size_t site_cap = 0;        // complex elements per site buffer
 
   // workspace
-  DevBuf C, P, T, Bm, G, G2, U2, Uf, U0, V, lam, lam2, ws, flag, info, scratch, ework;
-  // the per-site read-backs (truncation rank, discarded weight) and tau land
-  // in pinned host memory that the kernels write through its device mapping,
-  // so a read-back is one stream wait and no copy; kept until destruction
-  struct HostIO { int32_t k; int32_t pad; double disc; double tau; };
-  HostIO* hio = nullptr;       // host view
-  HostIO* hio_dev = nullptr;   // device view of the same memory
+  DevBuf C, P, T, Bm, G, G2, U2, Uf, U0, V, lam, lam2, ws, info, scratch, ework;
+  // sizes decided on the device (truncation ranks) live in a table that the
+  // kernels read, so a step is enqueued without waiting for them; the step's
+  // status (tau, max |tau - 1|, error bits) and the discarded weights live on
+  // the device too and are read at the next wait
+  DevBuf dd, stat, disc_dev;
+  std::vector<int> hd;        // host mirror of dd, valid after a wait
+  std::vector<int> zkhi;      // bounds of the zip-up carry ranks
+  int err_bits = 0;           // error bits found by a wait (sticky until set_state)
+  long long steps_done = 0;   // steps completed on the device (last wait)
+  // one step captured as a graph (none while timing, or if capture failed)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  bool graph_failed = false;
   size_t ws_bytes = 0;
   int n_max = 0;
   long long m_max = 0;
@@ -236,6 +244,7 @@ struct lb_solver {
   double t = 0.0;
   long long steps = 0;
   double last_tau = 1.0, max_defect = 0.0;
+  bool warned = false;     // a step since the last lindblad_sync had |tau - 1| > tau_warn
   std::vector<int> zip_bonds;
   std::vector<double> discarded;
   int last_chi_mu = 1;
@@ -243,6 +252,7 @@ struct lb_solver {
 
 namespace {
 
+using lbk::Dim;
 using lbk::Gemm;
 using lbk::Prec;
 
@@ -259,8 +269,11 @@ int passes(const lb_solver* s) { return fp32(s) ? 1 : 2; }
 // vectors), so the floor costs the FP32 form ~1e-6 of rho per such cut, the
 // size of its contraction rounding.  The zip-up cuts a product whose right
 // part is not orthonormal and keeps tol / 10 (flooring it too cost more).
-constexpr double kFp32TolFloor = 1e-6;
-double eff_tol(const lb_solver* s, double t) { return fp32(s) ? std::max(t, kFp32TolFloor) : t; }
+double eff_tol(const lb_solver* s, double t) {
+  if (!fp32(s)) return t;
+  return std::max(t, s->cfg.fp32_tol_floor > 0.0 ? s->cfg.fp32_tol_floor : LB_FP32_TOL_FLOOR);
+}
+double tau_warn(const lb_solver* s) { return s->cfg.tau_warn > 0.0 ? s->cfg.tau_warn : LB_TAU_WARN; }
 
 enum ProfClass { PC_CONTRACT = 0, PC_GRAM, PC_SVDGEMM, PC_HETRD, PC_STEBZ, PC_STEIN, PC_ORMTR, PC_JACOBI,
                  PC_OTHER, PC_COUNT };
@@ -413,9 +426,12 @@ void release_cus(lb_solver* s) {
   if (tl_cu_holder == s) tl_cu_holder = nullptr;
 }
 
+// Reserve the co-resident workgroups the solver's steps need, once: work of
+// one solver is ordered on its stream, so a reservation covers every step it
+// enqueues until the next wait on that stream gives it back.
 void reserve_cus(lb_solver* s, int w) {
-  if (w <= 0) return;
-  if (s->held_cus > 0) {   // not expected: every reservation is followed by a read-back
+  if (w <= 0 || s->held_cus >= w) return;
+  if (s->held_cus > 0) {
     HIPCHK(hipStreamSynchronize(s->stream));
     release_cus(s);
   }
@@ -431,18 +447,82 @@ void release_cus_on_error() {
   release_cus(s);
 }
 
-int read_k(lb_solver* s) {
+// ---- the size table ----------------------------------------------------------
+// dd[chi(i)], i = 0..L: bonds of the state between steps.
+// dd[zk(i)], i = 0..L: rows of the zip-up carry entering site i (zk(0) = 1);
+//   zk(L) receives the purification rank of the last cut.
+// dd[kb(i)], i = 1..L-1: rank of back-sweep bond i.
+int sl_chi(const lb_solver*, int i) { return i; }
+int sl_zk(const lb_solver* s, int i) { return s->L + 1 + i; }
+int sl_kb(const lb_solver* s, int i) { return 2 * (s->L + 1) + i; }
+Dim dchi(const lb_solver* s, int i, int hi) { return Dim::dyn(1, sl_chi(s, i), hi); }
+Dim dzk(const lb_solver* s, int i, int hi) { return Dim::dyn(1, sl_zk(s, i), hi); }
+Dim dkb(const lb_solver* s, int i, int hi) { return Dim::dyn(1, sl_kb(s, i), hi); }
+Dim scaled(const Dim& d, int c) {
+  if (d.idx < 0) return Dim(d.c * c);
+  return Dim::dyn(d.c * c, d.idx, d.hi * c);
+}
+Dim capped(const Dim& d, int hi) {
+  if (d.idx < 0) return Dim(std::min(d.c, hi));
+  return Dim::dyn(d.c, d.idx, std::min(d.hi, hi));
+}
+const int* ddp(const lb_solver* s) { return s->dd.i(); }
+// a size on the host, from the mirror of the table (valid while timing: the
+// timed path waits after every truncation)
+double hv(const lb_solver* s, const Dim& d) { return (double)lbk::dim_val(d, s->hd.data()); }
+
+// Wait for the stream, give the CUs back, refresh the host mirror of the
+// size table and of the step status.  Throws LB_ERR_NUMERIC when a step
+// produced non-finite values.
+// Copies of the small tables go through the solver's own stream (a copy on
+// the null stream would order against other solvers' streams).
+void copy_in(lb_solver* s, void* dst, const void* src, size_t bytes) {
+  HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s->stream));
   HIPCHK(hipStreamSynchronize(s->stream));
-  release_cus(s);
-  return *reinterpret_cast<volatile int32_t*>(&s->hio->k);
+}
+void copy_out(lb_solver* s, void* dst, const void* src, size_t bytes) {
+  HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
 }
 
-// Rank and relative discarded weight of the last truncation, one wait.
-int read_k_disc(lb_solver* s, double* disc) {
+void wait_stream(lb_solver* s) {
   HIPCHK(hipStreamSynchronize(s->stream));
   release_cus(s);
-  *disc = *reinterpret_cast<volatile double*>(&s->hio->disc);
-  return *reinterpret_cast<volatile int32_t*>(&s->hio->k);
+  if (!s->gen_on_device) return;
+  copy_out(s, s->hd.data(), s->dd.p, s->hd.size() * sizeof(int));
+  lbk::StepStat st;
+  copy_out(s, &st, s->stat.p, sizeof(st));
+  s->last_tau = st.tau;
+  s->max_defect = st.max_defect;
+  s->steps_done = st.steps;
+  if (st.warn) {
+    s->warned = true;
+    const int zero = 0;
+    copy_in(s, reinterpret_cast<char*>(s->stat.p) + offsetof(lbk::StepStat, warn), &zero, sizeof(int));
+  }
+  if (st.err) s->err_bits |= st.err;
+  const int L = s->L;
+  s->chi.assign(L + 1, 1);
+  for (int i = 0; i <= L; ++i) s->chi[i] = s->hd[sl_chi(s, i)];
+  if (s->have_state) {
+    s->zip_bonds.assign(L, 0);
+    for (int i = 0; i + 1 < L; ++i) s->zip_bonds[i] = s->hd[sl_zk(s, i + 1)];
+    if (L > 0) s->zip_bonds[L - 1] = s->hd[sl_zk(s, L)];
+    copy_out(s, s->discarded.data(), s->disc_dev.p, (L + 1) * sizeof(double));
+  }
+}
+
+void check_err(lb_solver* s) {
+  if (s->err_bits & 2) throw Fail(LB_ERR_NUMERIC, "non-finite eigenvalues in a truncation (the Householder "
+                                                  "reduction's bounded wait may have run out)");
+  if (s->err_bits & 1) throw Fail(LB_ERR_NUMERIC, "non-finite trace encountered during a step");
+}
+
+// While timing: wait after a truncation so that the host knows the sizes of
+// the launches that follow (their flops and bytes are accounted per launch).
+void timed_sync(lb_solver* s) {
+  if (!s->prof_on) return;
+  copy_out(s, s->hd.data(), s->dd.p, s->hd.size() * sizeof(int));
 }
 
 int choose_splits(int M, int N, long long K) {
@@ -463,88 +543,45 @@ int choose_splits_herm(int N, long long K) {
   return std::max(1, std::min(sp, 64));
 }
 
-// Gram G = A A^H of the rows of A (n x m, row stride lda), FP64 output n x n.
-void gram_rows(lb_solver* s, const void* A, Prec pa, int n, long long m, long long lda, double* G) {
+// Gram G = A A^H of the rows of A (n x m, row stride lda), FP64 output n x n
+// with leading dimension ldg.
+void gram_rows(lb_solver* s, const void* A, Prec pa, Dim n, Dim m, Dim lda, double* G, int ldg) {
   Gemm g;
-  g.M = n; g.N = n; g.K = (int)m;
+  g.M = n; g.N = n; g.K = m;
   g.A = A; g.sa_m = lda; g.sa_k = 1; g.pa = pa;
   g.B = A; g.sb_k = 1; g.sb_n = lda; g.conjB = 1; g.pb = pa;
-  g.C = G; g.sc_m = n; g.sc_n = 1; g.pc = lbk::F64;
+  g.C = G; g.sc_m = ldg; g.sc_n = 1; g.pc = lbk::F64;
   g.compute = lbk::F64;
   g.herm = 1;
-  g.splits = choose_splits_herm(n, m);
+  g.splits = choose_splits_herm(n.hi, m.hi);
   g.ws = s->ws.p;
-  Timed tm(s, PC_GRAM, 8.0 * n * n * (double)m, (double)n * m * (pa == lbk::F64 ? 16 : 8) + 16.0 * n * n);
+  g.dd = ddp(s);
+  Timed tm(s, PC_GRAM, s->prof_on ? 8.0 * hv(s, n) * hv(s, n) * hv(s, m) : 0.0,
+           s->prof_on ? hv(s, n) * hv(s, m) * (pa == lbk::F64 ? 16 : 8) + 16.0 * hv(s, n) * hv(s, n) : 0.0);
   check_gemm(lbk::gemm(g, s->stream), "gram_rows");
 }
 
-// Gram G = A^H A of the columns of A (n x m), FP64 output m x m.
-void gram_cols(lb_solver* s, const void* A, Prec pa, int n, int m, long long lda, double* G) {
+// Gram G = A^H A of the columns of A (n x m), FP64 output m x m, ld ldg.
+void gram_cols(lb_solver* s, const void* A, Prec pa, Dim n, Dim m, Dim lda, double* G, int ldg) {
   Gemm g;
   g.M = m; g.N = m; g.K = n;
   g.A = A; g.sa_m = 1; g.sa_k = lda; g.conjA = 1; g.pa = pa;
   g.B = A; g.sb_k = lda; g.sb_n = 1; g.pb = pa;
-  g.C = G; g.sc_m = m; g.sc_n = 1; g.pc = lbk::F64;
+  g.C = G; g.sc_m = ldg; g.sc_n = 1; g.pc = lbk::F64;
   g.compute = lbk::F64;
   g.herm = 1;
-  g.splits = choose_splits_herm(m, n);
+  g.splits = choose_splits_herm(m.hi, n.hi);
   g.ws = s->ws.p;
-  Timed tm(s, PC_GRAM, 8.0 * m * m * (double)n, (double)n * m * (pa == lbk::F64 ? 16 : 8) + 16.0 * m * m);
+  g.dd = ddp(s);
+  Timed tm(s, PC_GRAM, s->prof_on ? 8.0 * hv(s, m) * hv(s, m) * hv(s, n) : 0.0,
+           s->prof_on ? hv(s, n) * hv(s, m) * (pa == lbk::F64 ? 16 : 8) + 16.0 * hv(s, m) * hv(s, m) : 0.0);
   check_gemm(lbk::gemm(g, s->stream), "gram_cols");
 }
 
-void mm(lb_solver* s, int M, int N, int K, const void* A, Prec pa, long long lda, bool adjA,
-        const void* B, Prec pb, long long ldb, bool adjB, void* C, Prec pc, long long ldc, Prec comp,
-        int batch = 1, long long sa_b = 0, long long sb_b = 0, long long sc_b = 0);
-
-// Jacobi (relative accuracy; second pass of LB_FP64): eigenvectors in G.
-void eig_jacobi(lb_solver* s, double* G, int n, double* lam) {
-  Timed tm(s, PC_JACOBI, 0.0, 32.0 * n * n);
-  HIPCHK(lbk::heev_jacobi(G, n, 0, n, lam, 0, s->V.d(), 1, lbk::kJacobiRelTol, 40, s->info.i(), s->stream));
-}
-
-// Tridiagonal route (absolute accuracy): G destroyed, all eigenvalues in
-// lam, the eigenvectors of the kvec largest in U (ld n), made orthonormal by
-// Newton-Schulz polar steps U <- U (3I - U^H U)/2.  Inverse iteration with the
-// grouped orthogonalisation leaves at most ~1e-5 of mutual overlap; one step
-// takes that to ~1e-10, below the FP32 form's rounding of the contractions;
-// the FP64 form (whose second pass needs U0 unitary to rounding) takes two.
-void eig_trid(lb_solver* s, double* G, int n, double* lam, double* U, int kvec) {
-  kvec = std::min(kvec, n);
-  const double N = n;
-  const lbk::TridWork tw = lbk::trid_work(s->ework.d(), n);
-  {
-    // complex Hermitian Householder tridiagonalisation: 16/3 n^3 real flops;
-    // reads the matrix once, writes the reflectors and the tridiagonal
-    Timed tm(s, PC_HETRD, 16.0 / 3.0 * N * N * N, 16.0 * N * N + 8.0 * N * N + 24.0 * N);
-    reserve_cus(s, lbk::trid_coresident_workgroups(n));
-    HIPCHK(lbk::trid_reduce(G, n, n, tw, s->stream));
-  }
-  {
-    // bisection: 53 halvings x n Sturm steps of 5 flops, per eigenvalue
-    Timed tm(s, PC_STEBZ, 53.0 * 5.0 * N * N, 24.0 * N);
-    HIPCHK(lbk::trid_eigenvalues(n, tw, lam, s->stream));
-  }
-  {
-    // inverse iteration: factor (8n) + 2 x (forward 2n + backward 5n + norm 3n)
-    Timed tm(s, PC_STEIN, 28.0 * N * kvec, 8.0 * N * kvec + 24.0 * N);
-    HIPCHK(lbk::trid_vectors(n, tw, lam, kvec, s->stream));
-  }
-  {
-    // U = Q Z: n-1 complex reflectors of mean length n/2 on kvec vectors
-    Timed tm(s, PC_ORMTR, 8.0 * N * N * kvec, 16.0 * N * N / 2 + 8.0 * N * kvec + 16.0 * N * kvec);
-    HIPCHK(lbk::trid_backtransform(n, tw, kvec, U, n, s->stream));
-  }
-  {
-    Timed tm(s, PC_SVDGEMM, passes(s) * (8.0 * kvec * kvec * N * 2), passes(s) * 16.0 * (2.0 * N * kvec + kvec * kvec));
-    HIPCHK(lbk::orthonormalize_columns(U, n, n, kvec, s->scratch.d(), s->U2.d(), passes(s), s->ws.p, s->stream));
-  }
-}
-
 // C = op(A) op(B) with row-major dense operands described by leading dims.
-void mm(lb_solver* s, int M, int N, int K, const void* A, Prec pa, long long lda, bool adjA,
-        const void* B, Prec pb, long long ldb, bool adjB, void* C, Prec pc, long long ldc, Prec comp,
-        int batch, long long sa_b, long long sb_b, long long sc_b) {
+void mm(lb_solver* s, Dim M, Dim N, Dim K, const void* A, Prec pa, Dim lda, bool adjA,
+        const void* B, Prec pb, Dim ldb, bool adjB, void* C, Prec pc, Dim ldc, Prec comp,
+        Dim batch = Dim(1), Dim sa_b = Dim(0), Dim sb_b = Dim(0), Dim sc_b = Dim(0)) {
   Gemm g;
   g.M = M; g.N = N; g.K = K; g.batch = batch;
   g.A = A; g.pa = pa; g.sa_b = sa_b;
@@ -553,50 +590,108 @@ void mm(lb_solver* s, int M, int N, int K, const void* A, Prec pa, long long lda
   if (adjB) { g.sb_k = 1; g.sb_n = ldb; g.conjB = 1; } else { g.sb_k = ldb; g.sb_n = 1; }
   g.C = C; g.pc = pc; g.sc_m = ldc; g.sc_n = 1; g.sc_b = sc_b;
   g.compute = comp;
-  g.splits = (batch == 1) ? choose_splits(M, N, K) : 1;
+  g.splits = (batch.hi == 1) ? choose_splits(M.hi, N.hi, K.hi) : 1;
   g.ws = s->ws.p;
-  const double ea = (pa == lbk::F64 ? 16.0 : 8.0), eb = (pb == lbk::F64 ? 16.0 : 8.0), ec = (pc == lbk::F64 ? 16.0 : 8.0);
-  const double bytes = (double)M * K * ea * (sa_b ? batch : 1) + (double)K * N * eb * (sb_b ? batch : 1) +
-                       (double)M * N * ec * batch;
-  Timed tm(s, s->cls, 8.0 * M * N * (double)K * batch, bytes);
+  g.dd = ddp(s);
+  double flop = 0.0, bytes = 0.0;
+  if (s->prof_on) {
+    const double ea = (pa == lbk::F64 ? 16.0 : 8.0), eb = (pb == lbk::F64 ? 16.0 : 8.0), ec = (pc == lbk::F64 ? 16.0 : 8.0);
+    const double m_ = hv(s, M), n_ = hv(s, N), k_ = hv(s, K), b_ = hv(s, batch);
+    flop = 8.0 * m_ * n_ * k_ * b_;
+    bytes = m_ * k_ * ea * (sa_b.hi ? b_ : 1) + k_ * n_ * eb * (sb_b.hi ? b_ : 1) + m_ * n_ * ec * b_;
+  }
+  Timed tm(s, s->cls, flop, bytes);
   check_gemm(lbk::gemm(g, s->stream), "mm");
 }
 
+// Jacobi (relative accuracy; second pass of LB_FP64): eigenvectors in G.
+void eig_jacobi(lb_solver* s, double* G, int ldg, Dim n, double* lam) {
+  Timed tm(s, PC_JACOBI, 0.0, s->prof_on ? 32.0 * hv(s, n) * hv(s, n) : 0.0);
+  HIPCHK(lbk::heev_jacobi(G, ldg, 0, n, lam, 0, s->V.d(), 1, lbk::kJacobiRelTol, 40, s->info.i(), s->stream,
+                          ddp(s)));
+}
+
+// Tridiagonal route (absolute accuracy): G (ld ldg) destroyed, all
+// eigenvalues in lam, the eigenvectors of the kvec largest in U (ld ldg),
+// made orthonormal by Newton-Schulz polar steps U <- U (3I - U^H U)/2.
+// Inverse iteration with the grouped orthogonalisation leaves at most ~1e-5
+// of mutual overlap; one step takes that to ~1e-10, below the FP32 form's
+// rounding of the contractions; the FP64 form (whose second pass needs U0
+// unitary to rounding) takes two.
+void eig_trid(lb_solver* s, double* G, int ldg, Dim n, double* lam, double* U, Dim kvec) {
+  kvec = capped(kvec, n.hi);
+  const lbk::TridWork tw = lbk::trid_work(s->ework.d(), ldg);
+  const double N = s->prof_on ? hv(s, n) : 0.0, KV = s->prof_on ? std::min(hv(s, kvec), N) : 0.0;
+  {
+    // complex Hermitian Householder tridiagonalisation: 16/3 n^3 real flops;
+    // reads the matrix once, writes the reflectors and the tridiagonal
+    Timed tm(s, PC_HETRD, 16.0 / 3.0 * N * N * N, 16.0 * N * N + 8.0 * N * N + 24.0 * N);
+    HIPCHK(lbk::trid_reduce(G, ldg, n, tw, s->stream, ddp(s)));
+  }
+  {
+    // bisection: 53 halvings x n Sturm steps of 5 flops, per eigenvalue
+    Timed tm(s, PC_STEBZ, 53.0 * 5.0 * N * N, 24.0 * N);
+    HIPCHK(lbk::trid_eigenvalues(n, tw, lam, s->stream, ddp(s)));
+  }
+  {
+    // inverse iteration: factor (8n) + 2 x (forward 2n + backward 5n + norm 3n)
+    Timed tm(s, PC_STEIN, 28.0 * N * KV, 8.0 * N * KV + 24.0 * N);
+    HIPCHK(lbk::trid_vectors(n, tw, lam, kvec, s->stream, ddp(s)));
+  }
+  {
+    // U = Q Z: n-1 complex reflectors of mean length n/2 on kvec vectors
+    Timed tm(s, PC_ORMTR, 8.0 * N * N * KV, 16.0 * N * N / 2 + 8.0 * N * KV + 16.0 * N * KV);
+    HIPCHK(lbk::trid_backtransform(n, tw, kvec, U, ldg, s->stream, ddp(s)));
+  }
+  {
+    Timed tm(s, PC_SVDGEMM, passes(s) * (8.0 * KV * KV * N * 2), passes(s) * 16.0 * (2.0 * N * KV + KV * KV));
+    HIPCHK(lbk::orthonormalize_columns(U, ldg, n, kvec, s->scratch.d(), s->U2.d(), passes(s), s->ws.p,
+                                       s->stream, ddp(s)));
+  }
+}
+
 // Left singular vectors / squared singular values of the n x m matrix A
-// (row-major, leading dim lda).  Returns the device pointer of U (n x n, ld
-// n; the first kvec columns are valid) and leaves the eigenvalues in s->lam.
+// (row-major, leading dim lda).  U (n x n, leading dimension n.hi; the first
+// kvec columns are valid) is returned and the eigenvalues are left in s->lam.
 // LB_FP64 runs two passes: the tridiagonal route gives U0 (all n vectors),
-// one Newton-Schulz step makes it unitary to rounding, then B = U0^H A,
+// two Newton-Schulz steps make it unitary to rounding, then B = U0^H A,
 // G2 = B B^H is nearly diagonal with graded rows and Jacobi with a relative
 // threshold restores absolute FP64 accuracy of the small singular values.
-// `Bout` then holds U2^H B = rows sigma_j v_j^H (used for carries).
-double* left_svd(lb_solver* s, const void* A, Prec pa, int n, long long m, long long lda, bool want_b,
-                 int kvec) {
+// *Bout (when asked for) then points to U2^H B = rows sigma_j v_j^H (ld m),
+// used for carries.
+struct Svd {
+  double* U;
+  const double* B2;   // FP64 form only
+};
+Svd left_svd(lb_solver* s, const void* A, Prec pa, Dim n, Dim m, Dim lda, bool want_b, Dim kvec) {
+  const int ldg = n.hi;
   double* G = s->G.d();
-  gram_rows(s, A, pa, n, m, lda, G);
+  gram_rows(s, A, pa, n, m, lda, G, ldg);
   double* U0 = s->U0.d();
   if (passes(s) == 1) {
-    eig_trid(s, G, n, s->lam.d(), U0, kvec);
-    return U0;
+    eig_trid(s, G, ldg, n, s->lam.d(), U0, kvec);
+    return Svd{U0, nullptr};
   }
-  eig_trid(s, G, n, s->lam.d(), U0, n);
+  eig_trid(s, G, ldg, n, s->lam.d(), U0, n);
   double* U0o = s->Uf.d();
-  HIPCHK(lbk::copy_cols(U0, n, U0o, n, n, n, nullptr, s->stream));
+  {
+    Timed tm(s, PC_OTHER, 0.0, s->prof_on ? 32.0 * hv(s, n) * hv(s, n) : 0.0);
+    HIPCHK(lbk::copy_cols(U0, ldg, U0o, ldg, n, n, nullptr, s->stream, ddp(s)));
+  }
   // second pass: B = U0^H A, G2 = B B^H, Jacobi(G2) -> U2, U = U0 U2
   double* B = s->Bm.d();
-  mm(s, n, (int)m, n, U0o, lbk::F64, n, true, A, pa, lda, false, B, lbk::F64, m, lbk::F64);
+  mm(s, n, m, n, U0o, lbk::F64, ldg, true, A, pa, lda, false, B, lbk::F64, m, lbk::F64);
   double* G2 = s->G2.d();
-  gram_rows(s, B, lbk::F64, n, m, m, G2);
-  eig_jacobi(s, G2, n, s->lam.d());
+  gram_rows(s, B, lbk::F64, n, m, m, G2, ldg);
+  eig_jacobi(s, G2, ldg, n, s->lam.d());
   double* Uf = s->U0.d();
-  mm(s, n, n, n, U0o, lbk::F64, n, false, G2, lbk::F64, n, false, Uf, lbk::F64, n, lbk::F64);
+  mm(s, n, n, n, U0o, lbk::F64, ldg, false, G2, lbk::F64, ldg, false, Uf, lbk::F64, ldg, lbk::F64);
   if (want_b) {
     double* B2 = s->U2.d();
-    mm(s, n, (int)m, n, G2, lbk::F64, n, true, B, lbk::F64, m, false, B2, lbk::F64, m, lbk::F64);
-    std::swap(s->Bm.p, s->U2.p);
-    std::swap(s->Bm.bytes, s->U2.bytes);
+    mm(s, n, m, n, G2, lbk::F64, ldg, true, B, lbk::F64, m, false, B2, lbk::F64, m, lbk::F64);
+    return Svd{Uf, B2};
   }
-  return Uf;
+  return Svd{Uf, nullptr};
 }
 
 // Bond capacities of the state (bounded by 2^i, 2^(L-i) chi_mu and chi) and
@@ -624,7 +719,23 @@ std::vector<int> state_caps(const lb_solver* s, size_t* site_cap) {
   return cap;
 }
 
-// Byte sizes of the workspace buffers, in the order of WorkPlan::buffers().
+// Bounds of the carry rows entering each zip-up site: zkhi[0] = 1 and the
+// rank after site i is at most min(chi_zip, rows 2 zk, columns w chi).
+std::vector<int> zip_bounds(const lb_solver* s, const std::vector<int>& cap) {
+  const int L = s->L;
+  const int zc = s->cfg.chi_zip_cap > 0 ? s->cfg.chi_zip_cap : s->cfg.chi_cap;
+  std::vector<int> zk(L + 1, 1);
+  for (int i = 1; i < L; ++i) {
+    const long long cols = (long long)s->wb[i] * cap[i];
+    zk[i] = (int)std::min<long long>(std::min<long long>(zc, 2LL * zk[i - 1]), cols);
+  }
+  // purification rank after the last cut
+  zk[L] = (int)std::min<long long>(std::min<long long>(s->cfg.chi_mu_cap, 2LL * zk[L - 1]),
+                                   (long long)s->n_kraus * cap[L]);
+  return zk;
+}
+
+// Byte sizes of the workspace buffers.
 struct WorkPlan {
   int nmax = 2;
   long long mmax = 1;
@@ -634,23 +745,25 @@ struct WorkPlan {
 
 WorkPlan work_plan(const lb_solver* s, const std::vector<int>& cap) {
   const int L = s->L;
-  const int zc = s->cfg.chi_zip_cap > 0 ? s->cfg.chi_zip_cap : s->cfg.chi_cap;
+  const std::vector<int> zk = zip_bounds(s, cap);
   WorkPlan w;
   long long cmax = 1, pmax = 1;
-  std::vector<int> zcap(L + 1, 1);
-  for (int i = 1; i <= L; ++i) zcap[i] = (int)std::min<long long>(zc, 1LL << std::min(i, 30));
   for (int i = 0; i < L; ++i) {
-    const int zl = zcap[i];
-    const int cr = (i == L - 1) ? s->cfg.chi_mu_cap : cap[i + 1];
+    const int zl = zk[i];
+    const int cr = cap[i + 1];
     const int cl = cap[i];
     w.nmax = std::max(w.nmax, 2 * zl);
     w.mmax = std::max(w.mmax, (long long)s->wb[i + 1] * cr);
     cmax = std::max(cmax, (long long)zl * s->wb[i] * cl);
     pmax = std::max(pmax, (long long)zl * s->wb[i] * 2 * cr);
   }
-  // the last site's column Gram has m = K * chi_mu columns
+  // the last site's column Gram has m = K * chi_mu columns; the back-sweep
+  // rows reach the zip-up ranks
   w.nmax = std::max<long long>(w.nmax, (long long)s->n_kraus * s->cfg.chi_mu_cap);
   w.nmax = std::max(w.nmax, 2 * s->cfg.chi_cap);
+  for (int i = 1; i < L; ++i) w.mmax = std::max<long long>(w.mmax, 2LL * std::max(cap[i + 1], zk[i + 1]));
+  // a loaded state is swept before it is truncated: its bonds reach the caps
+  w.mmax = std::max<long long>(w.mmax, 2LL * std::max(s->cfg.chi_cap, s->cfg.chi_mu_cap));
   if (w.nmax > 512) throw Fail(LB_ERR_ARG, "zip-up factor dimension exceeds 512 (chi_zip or chi_mu*K too large)");
   const size_t cbytes = fp32(s) ? 8 : 16;
   w.C = std::max(cmax, (long long)w.nmax * w.mmax) * cbytes;
@@ -665,6 +778,8 @@ WorkPlan work_plan(const lb_solver* s, const std::vector<int>& cap) {
   w.scratch = (size_t)4 * w.nmax * w.nmax * 16;
   return w;
 }
+
+size_t table_bytes(const lb_solver* s) { return (size_t)3 * (s->L + 1) * sizeof(int); }
 
 void alloc_workspace(lb_solver* s) {
   const WorkPlan w = work_plan(s, s->cap);
@@ -681,9 +796,12 @@ void alloc_workspace(lb_solver* s) {
   s->lam.alloc(w.lam, st);
   s->lam2.alloc(w.lam, st);
   s->ws.alloc(w.ws, st);
-  for (DevBuf* b : {&s->flag, &s->info}) b->alloc(WorkPlan::kSmall, st);
+  s->info.alloc(WorkPlan::kSmall, st);
   s->scratch.alloc(w.scratch, st);
-  HIPCHK(hipMemsetAsync(s->flag.p, 0, 64, s->stream));
+  s->dd.alloc(table_bytes(s), st);
+  s->stat.alloc(sizeof(lbk::StepStat), st);
+  s->disc_dev.alloc((s->L + 1) * sizeof(double), st);
+  s->hd.assign(3 * (s->L + 1), 1);
 }
 
 void alloc_state(lb_solver* s) {
@@ -702,8 +820,9 @@ size_t footprint_bytes(const lb_solver* s) {
   const WorkPlan w = work_plan(s, cap);
   size_t t = (size_t)(s->L + 1) * size_class(site_cap * 16);
   t += size_class(w.C) + size_class(w.P) + size_class(w.T) + 5 * size_class(w.nn) + size_class(w.ework);
-  t += 2 * size_class(w.wide) + 2 * size_class(w.lam) + size_class(w.ws) + 2 * size_class(WorkPlan::kSmall);
-  t += size_class(w.scratch);
+  t += 2 * size_class(w.wide) + 2 * size_class(w.lam) + size_class(w.ws) + size_class(WorkPlan::kSmall);
+  t += size_class(w.scratch) + size_class(table_bytes(s)) + size_class(sizeof(lbk::StepStat)) +
+       size_class((s->L + 1) * sizeof(double));
   for (const lb::Site& x : s->kraus_dev) {
     const size_t e = (size_t)x.l * 4 * x.r;
     t += size_class(e * 16);
@@ -713,15 +832,24 @@ size_t footprint_bytes(const lb_solver* s) {
   return t;
 }
 
+void drop_graph(lb_solver* s) {
+  if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  s->gexec = nullptr;
+  s->graph = nullptr;
+}
+
 // Free every device buffer of the solver (state, workspace, MPOs); the host
 // copies of the generator and operators stay.
 void release_device(lb_solver* s) {
   if (s->dev_ready && s->stream) HIPCHK(hipStreamSynchronize(s->stream));
+  release_cus(s);
+  drop_graph(s);
   for (auto& x : s->X) x.release();
   s->X.clear();
   s->Xspare.release();
   for (DevBuf* b : {&s->C, &s->P, &s->T, &s->Bm, &s->G, &s->G2, &s->U2, &s->Uf, &s->U0, &s->V, &s->lam,
-                    &s->lam2, &s->ws, &s->flag, &s->info, &s->scratch, &s->ework})
+                    &s->lam2, &s->ws, &s->info, &s->scratch, &s->ework, &s->dd, &s->stat, &s->disc_dev})
     b->release();
   for (auto& b : s->W.d64) b.release();
   for (auto& b : s->W.d32) b.release();
@@ -745,10 +873,6 @@ void ensure_device(lb_solver* s) {
     HIPCHK(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
     s->own_stream = true;
   }
-  if (!s->hio) {
-    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&s->hio), sizeof(lb_solver::HostIO), hipHostMallocMapped));
-    HIPCHK(hipHostGetDevicePointer(reinterpret_cast<void**>(&s->hio_dev), s->hio, 0));
-  }
   s->dev_ready = true;
 }
 
@@ -757,6 +881,7 @@ void ensure_generator_on_device(lb_solver* s) {
   ensure_device(s);
   if (s->gen_on_device) return;
   HIPCHK(hipSetDevice(s->cfg.device));
+  drop_graph(s);
   if (s->degree > 1) {
     s->Wb0.alloc(s->h0.size() * sizeof(cd), s->stream);
     HIPCHK(hipMemcpyAsync(s->Wb0.p, s->h0.data(), s->h0.size() * sizeof(cd), hipMemcpyHostToDevice, s->stream));
@@ -764,20 +889,25 @@ void ensure_generator_on_device(lb_solver* s) {
   upload_mpo(s, s->kraus_dev, s->W, fp32(s));
   if (s->cap.empty()) alloc_state(s);
   alloc_workspace(s);
+  s->zkhi = zip_bounds(s, s->cap);
   s->gen_on_device = true;
 }
 
-// ---- one step ---------------------------------------------------------------
+// ---- one step -------------------------------------------------------------
+// Every launch below takes its sizes from the device table, so the sequence
+// is the same for every step and is captured once into a graph.
 
 void refresh_drive(lb_solver* s) {
   if (s->degree <= 1) return;
-  double f = 0.0;
-  const double tm = s->t + 0.5 * s->dt;
-  for (size_t j = 0; j < s->drv_c.size(); ++j) f += s->drv_c[j] * std::cos(s->drv_w[j] * tm + s->drv_p[j]);
+  lbk::DriveParams dp;
+  dp.n = (int)s->drv_c.size();
+  for (int j = 0; j < dp.n; ++j) { dp.c[j] = s->drv_c[j]; dp.w[j] = s->drv_w[j]; dp.p[j] = s->drv_p[j]; }
+  dp.dt = s->dt;
   const long long count = (long long)2 * s->W.wr[0] * 2 * 1;
   Timed tmr(s, PC_OTHER, 8.0 * count * s->degree, 16.0 * count * (s->degree + 1));
-  HIPCHK(lbk::boundary_contract(s->Wb0.d(), s->wb0_stride, s->degree, f, s->W.d64[0].d(),
-                                fp32(s) ? s->W.d32[0].f() : nullptr, count, s->stream));
+  HIPCHK(lbk::boundary_contract_step(s->Wb0.d(), s->wb0_stride, s->degree, dp,
+                                     reinterpret_cast<const lbk::StepStat*>(s->stat.p), s->W.d64[0].d(),
+                                     fp32(s) ? s->W.d32[0].f() : nullptr, count, s->stream));
 }
 
 void zipup(lb_solver* s) {
@@ -786,10 +916,11 @@ void zipup(lb_solver* s) {
   const Prec pw = f32 ? lbk::F32 : lbk::F64;   // contraction storage / compute precision
   const double tolz = s->cfg.tol_zip > 0 ? s->cfg.tol_zip : s->cfg.tol / 10.0;
   const int zc = s->cfg.chi_zip_cap > 0 ? s->cfg.chi_zip_cap : s->cfg.chi_cap;
-  int zk = 1;  // rows of the carry (new left bond)
-  s->zip_bonds.assign(L, 0);
+  const std::vector<int>& cap = s->cap;
+  const std::vector<int>& zh = s->zkhi;
   for (int i = 0; i < L; ++i) {
-    const int cl = s->chi[i], cr = s->chi[i + 1];
+    const Dim zk = dzk(s, i, zh[i]);            // rows of the carry (new left bond)
+    const Dim cl = dchi(s, i, cap[i]), cr = dchi(s, i + 1, cap[i + 1]);
     const int wl = s->wb[i], wr = s->wb[i + 1];
     // stage 1: P[(a', u)][(s, b)] = C[(a', u)][a] X_i[a][(s, b)]
     s->cls = PC_CONTRACT;
@@ -799,131 +930,201 @@ void zipup(lb_solver* s) {
       Pp = s->X[0].p;
       pp = lbk::F64;
     } else {
-      mm(s, zk * wl, 2 * cr, cl, s->C.p, pw, cl, false, s->X[i].p, lbk::F64, 2 * cr, false,
-         s->P.p, pw, 2 * cr, pw);
+      mm(s, scaled(zk, wl), scaled(cr, 2), cl, s->C.p, pw, cl, false, s->X[i].p, lbk::F64, scaled(cr, 2), false,
+         s->P.p, pw, scaled(cr, 2), pw);
       Pp = s->P.p;
       pp = pw;
     }
     // stage 2: T_{a'}[(s', v)][b] = Wt[(s', v)][(u, s)] P_{a'}[(u, s)][b]
     const void* Wt = f32 ? (const void*)s->W.d32[i].p : (const void*)s->W.d64[i].p;
-    mm(s, 2 * wr, cr, 2 * wl, Wt, pw, 2 * wl, false, Pp, pp, cr, false, s->T.p, pw, cr, pw,
-       zk, 0, (long long)2 * wl * cr, (long long)2 * wr * cr);
-    const int n = 2 * zk;
-    const long long m = (long long)wr * cr;
+    mm(s, Dim(2 * wr), cr, Dim(2 * wl), Wt, pw, Dim(2 * wl), false, Pp, pp, cr, false, s->T.p, pw, cr, pw,
+       zk, Dim(0), scaled(cr, 2 * wl), scaled(cr, 2 * wr));
+    const Dim n = scaled(zk, 2);
+    const Dim m = scaled(cr, wr);
     if (i < L - 1) {
       s->cls = PC_SVDGEMM;
-      double* U = left_svd(s, s->T.p, pw, n, m, m, passes(s) == 2, zc);
-      { Timed tm(s, PC_OTHER, 0.0, 8.0 * n); HIPCHK(lbk::truncate_rank(s->lam.d(), n, tolz, zc, &s->hio_dev->k, &s->hio_dev->disc, s->stream)); }
-      const int k = read_k(s);
+      const Svd sv = left_svd(s, s->T.p, pw, n, m, m, passes(s) == 2, capped(n, zc));
+      const int ldu = n.hi;
+      {
+        Timed tm(s, PC_OTHER, 0.0, s->prof_on ? 8.0 * hv(s, n) : 0.0);
+        HIPCHK(lbk::truncate_rank(s->lam.d(), n, tolz, zc, s->dd.i() + sl_zk(s, i + 1), nullptr,
+                                  &reinterpret_cast<lbk::StepStat*>(s->stat.p)->err, s->stream, ddp(s)));
+      }
+      timed_sync(s);
+      const Dim k = dzk(s, i + 1, zh[i + 1]);
       // new site X_i[(a', s')][k] = U[:, :k]
-      { Timed tm(s, PC_OTHER, 0.0, 32.0 * n * k); HIPCHK(lbk::copy_cols(U, n, s->X[i].d(), k, n, k, nullptr, s->stream)); }
+      {
+        Timed tm(s, PC_OTHER, 0.0, s->prof_on ? 32.0 * hv(s, n) * hv(s, k) : 0.0);
+        HIPCHK(lbk::copy_cols(sv.U, ldu, s->X[i].d(), k, n, k, nullptr, s->stream, ddp(s)));
+      }
       // carry C[k][(v, b)] = U_k^H T  (or the first k rows of U2^H B)
       if (passes(s) == 2) {
         if (f32) throw Fail(LB_ERR_STATE, "internal: two-pass FP32");
-        HIPCHK(hipMemcpyAsync(s->C.p, s->Bm.p, (size_t)k * m * 16, hipMemcpyDeviceToDevice, s->stream));
+        Timed tm(s, PC_OTHER, 0.0, s->prof_on ? 32.0 * hv(s, k) * hv(s, m) : 0.0);
+        HIPCHK(lbk::copy_cols(sv.B2, m, s->C.d(), m, k, m, nullptr, s->stream, ddp(s)));
       } else {
         s->cls = PC_CONTRACT;
-        mm(s, k, (int)m, n, U, lbk::F64, n, true, s->T.p, pw, m, false, s->C.p, pw, m, pw);
+        mm(s, k, m, n, sv.U, lbk::F64, ldu, true, s->T.p, pw, m, false, s->C.p, pw, m, pw);
       }
-      s->chi[i] = zk;       // left bond of the new site
-      zk = k;
-      s->zip_bonds[i] = k;
     } else {
       // S2: purification truncation on the (Kraus x purification) columns
-      const int mc = (int)m;
       s->cls = PC_SVDGEMM;
+      const int ldv = m.hi;
       double* Gc = s->G.d();
-      gram_cols(s, s->T.p, pw, n, mc, m, Gc);
+      gram_cols(s, s->T.p, pw, n, m, m, Gc, ldv);
       double* V0 = s->U0.d();
-      eig_trid(s, Gc, mc, s->lam.d(), V0, passes(s) == 2 ? mc : std::min(mc, s->cfg.chi_mu_cap));
+      eig_trid(s, Gc, ldv, m, s->lam.d(), V0, passes(s) == 2 ? m : capped(m, s->cfg.chi_mu_cap));
       double* Vf = V0;
       const void* Asrc = s->T.p;
       Prec asrc = pw;
+      Dim lda_src = m;
       if (passes(s) == 2) {
         // B' = T V0 (columns sigma_j u_j), G2' = B'^H B', Jacobi -> V2
-        double* V0o = V0;
         double* Bc = s->Bm.d();
-        mm(s, n, mc, mc, s->T.p, pw, m, false, V0o, lbk::F64, mc, false, Bc, lbk::F64, mc, lbk::F64);
+        mm(s, n, m, m, s->T.p, pw, m, false, V0, lbk::F64, ldv, false, Bc, lbk::F64, ldv, lbk::F64);
         double* G2 = s->G2.d();
-        gram_cols(s, Bc, lbk::F64, n, mc, mc, G2);
-        eig_jacobi(s, G2, mc, s->lam.d());
+        gram_cols(s, Bc, lbk::F64, n, m, ldv, G2, ldv);
+        eig_jacobi(s, G2, ldv, m, s->lam.d());
         Vf = G2;
         Asrc = Bc;
         asrc = lbk::F64;
+        lda_src = Dim(ldv);
       }
-      { Timed tm(s, PC_OTHER, 0.0, 8.0 * mc); HIPCHK(lbk::truncate_rank(s->lam.d(), mc, eff_tol(s, s->cfg.tol), s->cfg.chi_mu_cap, &s->hio_dev->k, &s->hio_dev->disc,
-                                s->stream)); }
-      const int k = read_k_disc(s, &s->discarded[0]);
+      {
+        Timed tm(s, PC_OTHER, 0.0, s->prof_on ? 8.0 * hv(s, m) : 0.0);
+        HIPCHK(lbk::truncate_rank(s->lam.d(), m, eff_tol(s, s->cfg.tol), s->cfg.chi_mu_cap, s->dd.i() + sl_zk(s, L),
+                                  s->disc_dev.d(), &reinterpret_cast<lbk::StepStat*>(s->stat.p)->err, s->stream,
+                                  ddp(s)));
+      }
+      timed_sync(s);
+      const Dim k = dzk(s, L, zh[L]);
       // X_{L-1}[(a', s')][k] = A V[:, :k]
       s->cls = PC_CONTRACT;
-      mm(s, n, k, mc, Asrc, asrc, (passes(s) == 2) ? mc : m, false, Vf, lbk::F64, mc, false,
-         s->X[i].p, lbk::F64, k, lbk::F64);
-      s->chi[i] = zk;
-      s->chi[L] = k;
-      s->last_chi_mu = k;
+      mm(s, n, k, m, Asrc, asrc, lda_src, false, Vf, lbk::F64, ldv, false, s->X[i].p, lbk::F64, k, lbk::F64);
     }
   }
+  // the new bonds: chi[i] = rows entering site i, chi[L] = purification rank
+  lbk::DimMoves mv;
+  for (int i = 1; i <= L; ++i) mv.add(sl_chi(s, i), sl_zk(s, i));
+  HIPCHK(lbk::move_dims(s->dd.i(), mv, s->stream));
+  timed_sync(s);
 }
 
 // Right-to-left truncated-SVD sweep; leaves sites 1..L-1 right-orthonormal.
-void back_sweep(lb_solver* s, double tol, bool record) {
+// lhi[i] bounds the left bond of site i on entry.
+void back_sweep(lb_solver* s, double tol, bool record, const std::vector<int>& lhi) {
   const int L = s->L;
   for (int i = L - 1; i >= 1; --i) {
-    const int l = s->chi[i], r = s->chi[i + 1];
-    const long long m = 2LL * r;
+    const Dim l = dchi(s, i, lhi[i]);
+    const Dim r = (i == L - 1) ? dchi(s, L, lhi[L]) : dkb(s, i + 1, std::min(s->cap[i + 1], lhi[i + 1]));
+    const Dim m = scaled(r, 2);
+    const int kmax = std::min(s->cap[i], lhi[i]);
     s->cls = PC_SVDGEMM;
-    double* U = left_svd(s, s->X[i].p, lbk::F64, l, m, m, passes(s) == 2, s->cap[i]);
-    { Timed tm(s, PC_OTHER, 0.0, 8.0 * l); HIPCHK(lbk::truncate_rank(s->lam.d(), l, tol, s->cap[i], &s->hio_dev->k, &s->hio_dev->disc, s->stream)); }
-    double disc = 0.0;
-    const int k = (record && i < (int)s->discarded.size()) ? read_k_disc(s, &disc) : read_k(s);
-    if (record && i < (int)s->discarded.size()) s->discarded[i] = disc;
-    // new X_i = S^-1 U_k^H M  (rows k)
+    const Svd sv = left_svd(s, s->X[i].p, lbk::F64, l, m, m, passes(s) == 2, capped(l, kmax));
+    const int ldu = l.hi;
+    {
+      Timed tm(s, PC_OTHER, 0.0, s->prof_on ? 8.0 * hv(s, l) : 0.0);
+      HIPCHK(lbk::truncate_rank(s->lam.d(), l, tol, s->cap[i], s->dd.i() + sl_kb(s, i),
+                                record ? s->disc_dev.d() + i : nullptr,
+                                &reinterpret_cast<lbk::StepStat*>(s->stat.p)->err, s->stream, ddp(s)));
+    }
+    timed_sync(s);
+    const Dim k = dkb(s, i, kmax);
+    // new X_i = S^-1 U_k^H M  (rows k), written in place: M is read before
     if (passes(s) == 2) {
-      Timed tm(s, PC_OTHER, 0.0, 32.0 * k * m);
-      HIPCHK(lbk::scale_rows_inv_sqrt(s->Bm.d(), (int)m, s->Xspare.d(), (int)m, k, (int)m, s->lam.d(), s->stream));
+      Timed tm(s, PC_OTHER, 0.0, s->prof_on ? 32.0 * hv(s, k) * hv(s, m) : 0.0);
+      HIPCHK(lbk::scale_rows_inv_sqrt(sv.B2, m, s->X[i].d(), m, k, m, s->lam.d(), s->stream, ddp(s)));
     } else {
       double* tmp = s->Bm.d();
-      mm(s, k, (int)m, l, U, lbk::F64, l, true, s->X[i].p, lbk::F64, m, false, tmp, lbk::F64, m, lbk::F64);
-      Timed tm(s, PC_OTHER, 0.0, 32.0 * k * m);
-      HIPCHK(lbk::scale_rows_inv_sqrt(tmp, (int)m, s->Xspare.d(), (int)m, k, (int)m, s->lam.d(), s->stream));
+      mm(s, k, m, l, sv.U, lbk::F64, ldu, true, s->X[i].p, lbk::F64, m, false, tmp, lbk::F64, m, lbk::F64);
+      Timed tm(s, PC_OTHER, 0.0, s->prof_on ? 32.0 * hv(s, k) * hv(s, m) : 0.0);
+      HIPCHK(lbk::scale_rows_inv_sqrt(tmp, m, s->X[i].d(), m, k, m, s->lam.d(), s->stream, ddp(s)));
     }
-    std::swap(s->X[i].p, s->Xspare.p);
-    std::swap(s->X[i].bytes, s->Xspare.bytes);
-    // US = U[:, :k] * sigma ; X_{i-1} <- X_{i-1} US
+    // US = U[:, :k] * sigma ; X_{i-1} <- X_{i-1} US (through the spare buffer)
     double* US = s->scratch.d();
-    { Timed tm(s, PC_OTHER, 0.0, 32.0 * l * k); HIPCHK(lbk::copy_cols(U, l, US, k, l, k, s->lam.d(), s->stream)); }
-    const int lp = s->chi[i - 1];
-    mm(s, 2 * lp, k, l, s->X[i - 1].p, lbk::F64, l, false, US, lbk::F64, k, false, s->Xspare.p,
+    {
+      Timed tm(s, PC_OTHER, 0.0, s->prof_on ? 32.0 * hv(s, l) * hv(s, k) : 0.0);
+      HIPCHK(lbk::copy_cols(sv.U, ldu, US, k, l, k, s->lam.d(), s->stream, ddp(s)));
+    }
+    const Dim lp = dchi(s, i - 1, lhi[i - 1]);
+    mm(s, scaled(lp, 2), k, l, s->X[i - 1].p, lbk::F64, l, false, US, lbk::F64, k, false, s->Xspare.p,
        lbk::F64, k, lbk::F64);
-    std::swap(s->X[i - 1].p, s->Xspare.p);
-    std::swap(s->X[i - 1].bytes, s->Xspare.bytes);
-    s->chi[i] = k;
+    {
+      Timed tm(s, PC_OTHER, 0.0, s->prof_on ? 32.0 * hv(s, lp) * hv(s, k) : 0.0);
+      HIPCHK(lbk::copy_cols(s->Xspare.d(), k, s->X[i - 1].d(), k, scaled(lp, 2), k, nullptr, s->stream, ddp(s)));
+    }
   }
+  lbk::DimMoves mv;
+  for (int i = 1; i < L; ++i) mv.add(sl_chi(s, i), sl_kb(s, i));
+  HIPCHK(lbk::move_dims(s->dd.i(), mv, s->stream));
 }
 
-void normalize_center(lb_solver* s) {
-  { Timed tm(s, PC_OTHER, 8.0 * s->chi[1], 64.0 * s->chi[1]); HIPCHK(lbk::normalize(s->X[0].d(), 2LL * s->chi[1], &s->hio_dev->tau, s->flag.i(), s->stream)); }
+// Bounds of the left bonds on entry of the back-sweep that follows a zip-up.
+std::vector<int> sweep_bounds(const lb_solver* s) {
+  std::vector<int> b(s->zkhi);
+  b[0] = 1;
+  return b;
 }
 
-void step_once(lb_solver* s) {
+void enqueue_step(lb_solver* s) {
   refresh_drive(s);
   zipup(s);
-  back_sweep(s, eff_tol(s, s->cfg.tol), true);
-  normalize_center(s);
-  HIPCHK(hipStreamSynchronize(s->stream));
-  const double tau = *reinterpret_cast<volatile double*>(&s->hio->tau);
-  s->last_tau = tau;
-  s->max_defect = std::max(s->max_defect, std::fabs(tau - 1.0));
-  s->t += s->dt;
-  s->steps += 1;
-  if (s->prof_on) prof_flush(s);
+  back_sweep(s, eff_tol(s, s->cfg.tol), true, sweep_bounds(s));
+  Timed tm(s, PC_OTHER, s->prof_on ? 8.0 * hv(s, dchi(s, 1, s->cap[1])) : 0.0, 0.0);
+  HIPCHK(lbk::normalize_step(s->X[0].d(), scaled(dchi(s, 1, s->cap[1]), 2),
+                             reinterpret_cast<lbk::StepStat*>(s->stat.p), tau_warn(s), s->stream, ddp(s)));
 }
 
-void canonicalize(lb_solver* s) {
+// Co-resident workgroups any reduction of a step may need.
+int step_coresident(const lb_solver* s) {
+  int nmax = 1;
+  for (int i = 0; i < s->L; ++i) nmax = std::max(nmax, 2 * s->zkhi[i]);
+  nmax = std::max(nmax, s->n_kraus * s->cap[s->L]);
+  for (int i = 1; i < s->L; ++i) nmax = std::max(nmax, s->zkhi[i]);
+  return lbk::trid_coresident_workgroups(std::min(nmax, 512));
+}
+
+// Capture one step into a graph (once per generator and state layout); a
+// capture that fails leaves the solver on direct launches.
+void ensure_graph(lb_solver* s) {
+  if (s->gexec || s->graph_failed) return;
+  hipGraph_t g = nullptr;
+  // relaxed: the capture constrains no API call of this or any other thread
+  // (solvers on other threads keep allocating and copying meanwhile)
+  HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeRelaxed));
+  bool ok = true;
+  try {
+    enqueue_step(s);
+  } catch (...) {
+    ok = false;
+  }
+  const hipError_t e = hipStreamEndCapture(s->stream, &g);
+  if (!ok || e != hipSuccess || !g) {
+    (void)hipGetLastError();
+    if (g) (void)hipGraphDestroy(g);
+    s->graph_failed = true;
+    if (!ok) throw Fail(LB_ERR_HIP, "enqueueing a step failed during graph capture");
+    return;
+  }
+  hipGraphExec_t x = nullptr;
+  if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess || !x) {
+    (void)hipGetLastError();
+    (void)hipGraphDestroy(g);
+    s->graph_failed = true;
+    return;
+  }
+  s->graph = g;
+  s->gexec = x;
+}
+
+void canonicalize(lb_solver* s, const std::vector<int>& bonds) {
   // back-sweep without truncation beyond numerical zeros, then normalise
-  back_sweep(s, 1e-14, false);
-  normalize_center(s);
-  HIPCHK(hipStreamSynchronize(s->stream));
+  std::vector<int> lhi(bonds);
+  back_sweep(s, 1e-14, false, lhi);
+  copy_out(s, s->hd.data(), s->dd.p, s->hd.size() * sizeof(int));
+  const long long count = 2LL * s->hd[sl_chi(s, 1)];
+  lbk::StepStat* st = reinterpret_cast<lbk::StepStat*>(s->stat.p);
+  HIPCHK(lbk::normalize(s->X[0].d(), count, &st->tau, &st->err, s->stream));
 }
 
 lb_status fail(const Fail& f) {
@@ -968,6 +1169,12 @@ std::vector<lb::Term> convert_terms(const lb_solver* s, const lb_term* terms, in
 // ============================================================================
 
 namespace lbk {
+int free_device_cus(int device) {
+  CuBudget& b = cu_budget(device);
+  std::lock_guard<std::mutex> lk(b.mu);
+  return b.total < 0 ? (1 << 30) : b.avail;
+}
+
 int reserve_device_cus(int device, int w) {
   if (w <= 0) return 0;
   CuBudget& b = cu_budget(device);
@@ -1047,7 +1254,8 @@ void lindblad_destroy(lb_solver* s) {
   hipStream_t st = s->stream;
   bool own = s->own_stream;
   for (auto e : s->ev_pool) (void)hipEventDestroy(e);
-  if (s->hio) (void)hipHostFree(s->hio);
+  release_cus(s);
+  drop_graph(s);
   delete s;
   if (own && st) (void)hipStreamDestroy(st);
 }
@@ -1205,20 +1413,39 @@ lb_status lindblad_kraus_info(const lb_solver* s, int32_t* bonds, int32_t* n_kra
 }
 
 static lb_status load_mps(lb_solver* s, const std::vector<int>& bonds, const std::vector<const cd*>& sites) {
+    (void)hipGetLastError();   // an unread error of an earlier call is not this call's
   const int L = s->L;
   HIPCHK(hipSetDevice(s->cfg.device));
   ensure_generator_on_device(s);
+  // nothing of the previous state is in flight after this wait
+  HIPCHK(hipStreamSynchronize(s->stream));
+  release_cus(s);
   for (int i = 0; i < L; ++i) {
     const size_t cnt = (size_t)bonds[i] * 2 * bonds[i + 1];
     if (cnt > s->site_cap) throw Fail(LB_ERR_ARG, "site exceeds the capacity implied by the caps");
     HIPCHK(hipMemcpyAsync(s->X[i].p, sites[i], cnt * sizeof(cd), hipMemcpyHostToDevice, s->stream));
   }
-  s->chi = bonds;
-  canonicalize(s);
+  // a new state: size table from its bonds, cleared status
+  HIPCHK(hipStreamSynchronize(s->stream));
+  std::vector<int> tab(3 * (L + 1), 1);
+  for (int i = 0; i <= L; ++i) tab[sl_chi(s, i)] = bonds[i];
+  copy_in(s, s->dd.p, tab.data(), tab.size() * sizeof(int));
+  lbk::StepStat st{};
+  st.tau = 1.0;
+  copy_in(s, s->stat.p, &st, sizeof(st));
+  std::vector<double> z(L + 1, 0.0);
+  copy_in(s, s->disc_dev.p, z.data(), z.size() * sizeof(double));
+  s->hd = tab;
+  s->err_bits = 0;
+  s->have_state = false;
+  canonicalize(s, bonds);
+  wait_stream(s);
+  check_err(s);
   s->t = 0.0;
   s->steps = 0;
   s->max_defect = 0.0;
   s->last_tau = 1.0;
+  s->warned = false;
   s->have_state = true;
   return LB_OK;
 }
@@ -1298,7 +1525,9 @@ lb_status lindblad_get_state_mps(lb_solver* s, int32_t* bonds, double** sites) {
   try {
     if (!s || !bonds) throw Fail(LB_ERR_ARG, "NULL argument");
     if (!s->have_state) throw Fail(LB_ERR_STATE, "no state");
-    HIPCHK(hipStreamSynchronize(s->stream));
+    HIPCHK(hipSetDevice(s->cfg.device));
+    wait_stream(s);
+    check_err(s);
     for (int i = 0; i <= s->L; ++i) bonds[i] = s->chi[i];
     if (sites)
       for (int i = 0; i < s->L; ++i) {
@@ -1314,10 +1543,24 @@ lb_status lindblad_get_state_mps(lb_solver* s, int32_t* bonds, double** sites) {
 
 lb_status lindblad_step(lb_solver* s, int32_t n_steps) {
   try {
+    (void)hipGetLastError();   // an unread error of an earlier call is not this call's
     if (!s || n_steps < 0) throw Fail(LB_ERR_ARG, "bad argument");
     if (!s->have_gen || !s->have_state) throw Fail(LB_ERR_STATE, "set_generator and set_state first");
     HIPCHK(hipSetDevice(s->cfg.device));
-    for (int k = 0; k < n_steps; ++k) step_once(s);
+    check_err(s);   // the state is invalid after a failed step until set_state
+    if (n_steps == 0) return LB_OK;
+    if (!s->prof_on) ensure_graph(s);
+    reserve_cus(s, step_coresident(s));
+    for (int k = 0; k < n_steps; ++k) {
+      if (s->gexec && !s->prof_on) {
+        HIPCHK(hipGraphLaunch(s->gexec, s->stream));
+      } else {
+        enqueue_step(s);
+        if (s->prof_on) prof_flush(s);
+      }
+    }
+    s->steps += n_steps;
+    s->t = (double)s->steps * s->dt;
     return LB_OK;
   } catch (const Fail& f) {
     return fail(f);
@@ -1325,6 +1568,25 @@ lb_status lindblad_step(lb_solver* s, int32_t n_steps) {
     release_cus_on_error();
     g_last_error = e.what();
     return LB_ERR_HIP;
+  }
+}
+
+lb_status lindblad_sync(lb_solver* s) {
+  try {
+    if (!s) throw Fail(LB_ERR_ARG, "NULL solver");
+    if (!s->dev_ready) return LB_OK;
+    HIPCHK(hipSetDevice(s->cfg.device));
+    wait_stream(s);
+    check_err(s);
+    if (s->warned) {
+      s->warned = false;
+      g_last_error = "a step's pre-normalisation trace deviated from 1 by more than tau_warn (max |tau - 1| = " +
+                     std::to_string(s->max_defect) + ")";
+      return LB_WARN_UNSTABLE;
+    }
+    return LB_OK;
+  } catch (const Fail& f) {
+    return fail(f);
   }
 }
 
@@ -1337,23 +1599,42 @@ lb_status lindblad_step_batch(lb_solver* const* ss, int32_t n, int32_t n_steps) 
       for (int i = 0; i < j; ++i)
         if (ss[i] == ss[j]) throw Fail(LB_ERR_ARG, "a solver appears twice in the batch");
     }
-    if (n == 1) return lindblad_step(ss[0], n_steps);
-    // one host thread per solve, each driving its solver's own stream, so the
-    // solves' kernels overlap on the device
-    std::vector<lb_status> rc(n, LB_OK);
+    // enqueue every solver's steps on its own stream (their kernels overlap on
+    // the device); a solver whose co-resident workgroups do not fit next to
+    // those reserved by the solvers before it waits for the earliest of them
     std::vector<std::string> msg(n);
-    std::vector<std::thread> th;
-    th.reserve(n);
+    std::vector<lb_status> rc(n, LB_OK);
+    for (int j = 0; j < n; ++j) {
+      lb_solver* s = ss[j];
+      HIPCHK(hipSetDevice(s->cfg.device));
+      const int w = step_coresident(s);
+      for (int i = 0; w > s->held_cus && i < j; ++i) {
+        if (lbk::free_device_cus(s->cfg.device) >= w) break;
+        if (ss[i]->held_cus > 0) {
+          HIPCHK(hipSetDevice(ss[i]->cfg.device));
+          HIPCHK(hipStreamSynchronize(ss[i]->stream));
+          release_cus(ss[i]);
+          HIPCHK(hipSetDevice(s->cfg.device));
+        }
+      }
+      rc[j] = lindblad_step(s, n_steps);
+      if (rc[j] != LB_OK) msg[j] = g_last_error;
+    }
+    // the batch returns when all its steps are done
+    for (int j = 0; j < n; ++j) {
+      if (rc[j] != LB_OK) continue;
+      rc[j] = lindblad_sync(ss[j]);
+      if (rc[j] != LB_OK) msg[j] = g_last_error;
+    }
     for (int j = 0; j < n; ++j)
-      th.emplace_back([&, j] {
-        rc[j] = lindblad_step(ss[j], n_steps);
-        if (rc[j] != LB_OK) msg[j] = g_last_error;
-      });
-    for (auto& t : th) t.join();
-    for (int j = 0; j < n; ++j)
-      if (rc[j] != LB_OK) {
+      if (rc[j] < 0) {
         g_last_error = "solver " + std::to_string(j) + " of the batch: " + msg[j];
         return rc[j];
+      }
+    for (int j = 0; j < n; ++j)
+      if (rc[j] == LB_WARN_UNSTABLE) {
+        g_last_error = "solver " + std::to_string(j) + " of the batch: " + msg[j];
+        return LB_WARN_UNSTABLE;
       }
     return LB_OK;
   } catch (const Fail& f) {
@@ -1402,8 +1683,12 @@ static void upload_op(lb_solver* s, lb_op* op) {
 
 lb_status lindblad_observe(lb_solver* s, const lb_op* Oc, double out[2]) {
   try {
+    (void)hipGetLastError();   // an unread error of an earlier call is not this call's
     if (!s || !Oc || !out) throw Fail(LB_ERR_ARG, "NULL argument");
     if (!s->have_state) throw Fail(LB_ERR_STATE, "no state");
+    HIPCHK(hipSetDevice(s->cfg.device));
+    wait_stream(s);
+    check_err(s);
     lb_op* O = const_cast<lb_op*>(Oc);
     upload_op(s, O);
     const int L = s->L;
@@ -1454,8 +1739,12 @@ lb_status lindblad_observe(lb_solver* s, const lb_op* Oc, double out[2]) {
 
 lb_status lindblad_trace_purity(lb_solver* s, double* trace, double* purity) {
   try {
+    (void)hipGetLastError();   // an unread error of an earlier call is not this call's
     if (!s) throw Fail(LB_ERR_ARG, "NULL solver");
     if (!s->have_state) throw Fail(LB_ERR_STATE, "no state");
+    HIPCHK(hipSetDevice(s->cfg.device));
+    wait_stream(s);
+    check_err(s);
     const int L = s->L;
     size_t need = 1;
     for (int i = 0; i < L; ++i) need = std::max<size_t>(need, (size_t)s->chi[i] * 2 * s->chi[i + 1]);
@@ -1492,7 +1781,10 @@ lb_status lindblad_trace_purity(lb_solver* s, double* trace, double* purity) {
 lb_status lindblad_diagnostics(lb_solver* s, lb_diag* out) {
   try {
     if (!s || !out) throw Fail(LB_ERR_ARG, "NULL argument");
-    HIPCHK(hipStreamSynchronize(s->stream));
+    if (s->dev_ready) {
+      HIPCHK(hipSetDevice(s->cfg.device));
+      wait_stream(s);
+    }
     std::memset(out, 0, sizeof(*out));
     out->steps = s->steps;
     out->t = s->t;
@@ -1503,12 +1795,7 @@ lb_status lindblad_diagnostics(lb_solver* s, lb_diag* out) {
     out->chi_mu = s->chi.empty() ? 0 : s->chi[s->L];
     for (int i = 0; i < s->L && i < (int)s->zip_bonds.size(); ++i) out->zip_bonds[i] = s->zip_bonds[i];
     for (int i = 0; i < s->L && i < (int)s->discarded.size(); ++i) out->discarded[i] = s->discarded[i];
-    int flag = 0;
-    if (s->flag.p) {
-      HIPCHK(hipMemcpyAsync(&flag, s->flag.p, sizeof(int), hipMemcpyDeviceToHost, s->stream));
-      HIPCHK(hipStreamSynchronize(s->stream));
-    }
-    if (flag) throw Fail(LB_ERR_NUMERIC, "non-finite trace encountered during a step");
+    check_err(s);
     return LB_OK;
   } catch (const Fail& f) {
     return fail(f);

@@ -9,6 +9,28 @@ namespace lbk {
 
 enum Prec { F64 = 0, F32 = 1 };
 
+// A size or stride that is either fixed on the host (idx < 0: the value c)
+// or read on the device as c * dd[idx] from a table of sizes that earlier
+// kernels of the same stream wrote (truncation ranks), so that a sequence of
+// launches whose shapes depend on data can be enqueued, or captured into a
+// graph, without waiting for those kernels.  hi bounds the value: launch
+// grids and workspaces are sized from it, and the device clamps to it.
+struct Dim {
+  int c = 0, idx = -1, hi = 0;
+  Dim() = default;
+  Dim(int v) : c(v), idx(-1), hi(v) {}
+  static Dim dyn(int coef, int slot, int bound) {
+    Dim d;
+    d.c = coef; d.idx = slot; d.hi = bound;
+    return d;
+  }
+};
+__host__ __device__ inline int dim_val(const Dim& d, const int* dd) {
+  if (d.idx < 0 || dd == nullptr) return d.c;
+  const long long v = (long long)d.c * dd[d.idx];
+  return (int)(v < 0 ? 0 : (v > d.hi ? d.hi : v));
+}
+
 // C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b] for b < batch.
 //   op(A)(i, k) = A[i*sa_m + k*sa_k] (conjugated if conjA), i < M, k < K
 //   op(B)(k, j) = B[k*sb_k + j*sb_n] (conjugated if conjB), j < N
@@ -16,15 +38,18 @@ enum Prec { F64 = 0, F32 = 1 };
 // separately: inputs are converted on load, products accumulate in the
 // compute precision (FP32 MFMA or FP64 MFMA).  splits > 1 partitions K and
 // reduces the partial products in a fixed order (workspace `ws`, at least
-// batch*splits*M*N complex of the compute precision).
+// batch*splits*M*N complex of the compute precision, at the bounds).
+// Sizes and strides may be device-side (Dim, table dd).
 struct Gemm {
-  int M = 0, N = 0, K = 0, batch = 1, splits = 1;
-  const void* A = nullptr; long long sa_m = 0, sa_k = 0, sa_b = 0; int conjA = 0; Prec pa = F64;
-  const void* B = nullptr; long long sb_k = 0, sb_n = 0, sb_b = 0; int conjB = 0; Prec pb = F64;
-  void* C = nullptr; long long sc_m = 0, sc_n = 0, sc_b = 0; Prec pc = F64;
+  Dim M = 0, N = 0, K = 0, batch = 1;
+  int splits = 1;
+  const void* A = nullptr; Dim sa_m = 0, sa_k = 0, sa_b = 0; int conjA = 0; Prec pa = F64;
+  const void* B = nullptr; Dim sb_k = 0, sb_n = 0, sb_b = 0; int conjB = 0; Prec pb = F64;
+  void* C = nullptr; Dim sc_m = 0, sc_n = 0, sc_b = 0; Prec pc = F64;
   Prec compute = F64;
   double alpha_re = 1.0, alpha_im = 0.0, beta_re = 0.0, beta_im = 0.0;
   void* ws = nullptr;
+  const int* dd = nullptr;   // device table of the dynamic sizes
   // herm = 1: the product is Hermitian (op(B) = op(A)^H, M == N, alpha real,
   // beta 0); only the 64 x 64 tiles on and above the diagonal are computed
   // and the others are written as their conjugate transposes
@@ -40,15 +65,18 @@ hipError_t gemm(const Gemm& g, hipStream_t stream);
 // |g_pq| > rel_tol * sqrt(|g_pp g_qq|).  info[b] = sweeps used, or -1 if not
 // converged within max_sweeps.
 // Rotation threshold of the relative-accuracy Jacobi pass: a pair is rotated
-// while |g_pq| > t sqrt(g_pp g_qq).  Pairs whose diagonal entries are both
-// below kJacobiFloor times the largest diagonal entry are left alone: such
-// eigenvalues lie under the rounding of any explicitly formed Gram matrix
-// (sigma < 1e-14 sigma_1) and any orthonormal basis of them serves.
+// while |g_pq| > t sqrt(|g_pp g_qq|).  A pair whose two diagonal entries and
+// off-diagonal entry are all below kJacobiFloor times the largest entry
+// modulus is left alone: for a Gram matrix (|g_pq|^2 <= g_pp g_qq) these are
+// the pairs of eigenvalues under the rounding of the explicitly formed
+// matrix (sigma < 1e-14 sigma_1), for which any orthonormal basis serves.  A
+// pair with small diagonal entries but a larger off-diagonal one (possible
+// only in an indefinite matrix) is rotated.
 constexpr double kJacobiRelTol = 1.5e-15;
 constexpr double kJacobiFloor = 1e-28;
-hipError_t heev_jacobi(double* G, int ldg, long long g_stride, int n, double* w, long long w_stride,
+hipError_t heev_jacobi(double* G, int ldg, long long g_stride, Dim n, double* w, long long w_stride,
                        double* V, int batch, double rel_tol, int max_sweeps, int* info,
-                       hipStream_t stream);
+                       hipStream_t stream, const int* dd = nullptr);
 
 // Hermitian eigen-decomposition through a real tridiagonal form (Householder
 // reduction, bisection, inverse iteration, back-transformation).  G (n x n,
@@ -60,17 +88,19 @@ hipError_t heev_tridiag(double* G, int ldg, int n, double* w, double* U, int ldu
                         hipStream_t stream);
 size_t heev_tridiag_work_doubles(int n);
 
-// The same four stages, callable one by one (for per-stage timing).
+// The same four stages, callable one by one (for per-stage timing).  The
+// order n may be device-side; the workspace layout is that of its bound
+// (trid_work(work, n.hi)), and every stage reads the same n.
 struct TridWork {
   double *d, *e, *tau, *Vt, *Z, *wy, *sync;
 };
-TridWork trid_work(double* work, int n);
-hipError_t trid_reduce(double* G, int ldg, int n, const TridWork& t, hipStream_t stream);
-// Workgroups of one trid_reduce launch of order n that spin on each other and
-// so must be resident together, one CU each at most (0: a single workgroup).
-// Reductions in flight at once on several streams must not need more CUs
-// than the device has; the solver keeps a process-wide budget for that.
-int trid_coresident_workgroups(int n);
+TridWork trid_work(double* work, int n_max);
+hipError_t trid_reduce(double* G, int ldg, Dim n, const TridWork& t, hipStream_t stream, const int* dd = nullptr);
+// Workgroups of one trid_reduce launch of order up to n_max that spin on each
+// other and so must be resident together, one CU each at most (0: a single
+// workgroup).  Reductions in flight at once on several streams must not need
+// more CUs than the device has; the solver keeps a process-wide budget.
+int trid_coresident_workgroups(int n_max);
 // Bound of those workgroups' waits on each other, in ticks of the 100 MHz
 // wall clock (<= 0: the default, 2 s).  When a wait runs out, every
 // workgroup leaves and d is NaN.  For tests of that path.
@@ -80,38 +110,73 @@ void trid_set_wait_ticks(long long ticks);
 // how many it took; release_device_cus gives them back once the launch that
 // needed them has completed (after a wait on its stream).
 int reserve_device_cus(int device, int w);
+// CUs of the budget not reserved now (a large value before first use).
+int free_device_cus(int device);
 void release_device_cus(int device, int w);
-hipError_t trid_eigenvalues(int n, const TridWork& t, double* w, hipStream_t stream);
-hipError_t trid_vectors(int n, const TridWork& t, const double* w, int kvec, hipStream_t stream);
-hipError_t trid_backtransform(int n, const TridWork& t, int kvec, double* U, int ldu, hipStream_t stream);
+hipError_t trid_eigenvalues(Dim n, const TridWork& t, double* w, hipStream_t stream, const int* dd = nullptr);
+// kvec: eigenvectors wanted, at most n (a larger value means n)
+hipError_t trid_vectors(Dim n, const TridWork& t, const double* w, Dim kvec, hipStream_t stream,
+                        const int* dd = nullptr);
+hipError_t trid_backtransform(Dim n, const TridWork& t, Dim kvec, double* U, int ldu, hipStream_t stream,
+                              const int* dd = nullptr);
 
 // Newton-Schulz polar steps U <- U (3I - U^H U) / 2 on the first k columns
 // of U (n rows, ld ldu): removes the eps ||G|| / gap overlap left by inverse
 // iteration.  S: k*k complex scratch, T: n*k complex scratch, ws: split-K
 // workspace of at least 32 * 64 * 64 complex (or nullptr: no split).
-hipError_t orthonormalize_columns(double* U, int ldu, int n, int k, double* S, double* T, int iters, void* ws,
-                                  hipStream_t stream);
+hipError_t orthonormalize_columns(double* U, int ldu, Dim n, Dim k, double* S, double* T, int iters, void* ws,
+                                  hipStream_t stream, const int* dd = nullptr);
 
 // Truncation rule on descending eigenvalues lam (= squared singular values):
 // smallest k >= 1 with sum_{j>k} lam_j <= tol^2 sum_j lam_j, then min(k, cap);
 // negative noise is clamped to zero.  Writes k to *k_out and the relative
-// discarded weight to *disc_out.
-hipError_t truncate_rank(const double* lam, int n, double tol, int cap, int* k_out,
-                         double* disc_out, hipStream_t stream);
+// discarded weight to *disc_out; a non-finite eigenvalue sets bit 1 of *err
+// (err may be nullptr).
+hipError_t truncate_rank(const double* lam, Dim n, double tol, int cap, int* k_out,
+                         double* disc_out, int* err, hipStream_t stream, const int* dd = nullptr);
 
 // dst[i*ldd + j] = src[i*lds + j] * (scale_cols ? sqrt(max(lam_j,0)) : 1) for
 // i < rows, j < cols (complex128).
-hipError_t copy_cols(const double* src, int lds, double* dst, int ldd, int rows, int cols,
-                     const double* lam, hipStream_t stream);
+hipError_t copy_cols(const double* src, Dim lds, double* dst, Dim ldd, Dim rows, Dim cols,
+                     const double* lam, hipStream_t stream, const int* dd = nullptr);
 
 // dst[j*ldd + c] = src[j*lds + c] / sqrt(lam_j) for j < rows, c < cols
 // (rows with lam_j <= 0 are zeroed).
-hipError_t scale_rows_inv_sqrt(const double* src, int lds, double* dst, int ldd, int rows, int cols,
-                               const double* lam, hipStream_t stream);
+hipError_t scale_rows_inv_sqrt(const double* src, Dim lds, double* dst, Dim ldd, Dim rows, Dim cols,
+                               const double* lam, hipStream_t stream, const int* dd = nullptr);
 
 // tau = sum |x|^2 over `count` complex128 values (one workgroup, fixed order);
-// x /= sqrt(tau); *tau_out = tau.  Non-finite tau sets *flag = 1.
+// x /= sqrt(tau); *tau_out = tau.  A non-finite or zero tau sets bit 0 of *flag.
 hipError_t normalize(double* x, long long count, double* tau_out, int* flag, hipStream_t stream);
+
+// Status of the steps enqueued on a solver's stream, kept on the device and
+// read by the host only when it waits for the stream.
+struct StepStat {
+  double tau;          // last step's trace before renormalisation
+  double max_defect;   // max |tau - 1| since set_state
+  long long steps;     // steps completed since set_state (drives the clock)
+  int err;             // bit 0: non-finite trace; bit 1: non-finite eigenvalues
+  int warn;            // a step with |tau - 1| > tau_warn since the last read
+  double pad[4];
+};
+// The end of a step: tau = sum |x|^2 over count complex128 values, x /=
+// sqrt(tau), and the step's status folded into *st (one workgroup): a
+// non-finite or zero tau sets err bit 0, tau > 1 + tau_warn sets warn.
+hipError_t normalize_step(double* x, Dim count, StepStat* st, double tau_warn, hipStream_t stream,
+                          const int* dd = nullptr);
+
+// dst[e] = src[e] for e < count complex128 values.
+hipError_t copy_elems(const double* src, double* dst, Dim count, hipStream_t stream, const int* dd = nullptr);
+
+// Size-table bookkeeping between the launches of a step: for each pair,
+// dd[dst] = (src >= 0 ? dd[src] : value), in order (one thread).
+struct DimMoves {
+  int n = 0;
+  int dst[64], src[64], value[64];
+  void add(int d, int s) { dst[n] = d; src[n] = s; value[n] = 0; ++n; }
+  void set(int d, int v) { dst[n] = d; src[n] = -1; value[n] = v; ++n; }
+};
+hipError_t move_dims(int* dd, const DimMoves& m, hipStream_t stream);
 
 // complex128 -> complex64 copy.
 hipError_t to_f32(const double* src, float* dst, long long count, hipStream_t stream);
@@ -122,12 +187,23 @@ hipError_t to_f32(const double* src, float* dst, long long count, hipStream_t st
 hipError_t boundary_contract(const double* Wb, long long stride, int degree, double f,
                              double* W0, float* W0f, long long count, hipStream_t stream);
 
+// The same with f evaluated on the device at the midpoint of the next step,
+// t = (st->steps + 1/2) dt: f(t) = sum_j c_j cos(w_j t + p_j).
+struct DriveParams {
+  int n = 0;
+  double c[8], w[8], p[8];
+  double dt = 0.0;
+};
+hipError_t boundary_contract_step(const double* Wb, long long stride, int degree, const DriveParams& f,
+                                  const StepStat* st, double* W0, float* W0f, long long count,
+                                  hipStream_t stream);
+
 // out[0] + i out[1] = sum_j E[j*ld + j] (complex128 trace of an n x n block)
 hipError_t diag_sum(const double* E, int n, long long ld, double* out, hipStream_t stream);
 
 // S <- 1.5 I - 0.5 S (n x n complex): the Newton-Schulz polar step
 // U <- U (3I - U^H U) / 2 is U . blend(U^H U).
-hipError_t newton_schulz_blend(double* S, int n, hipStream_t stream);
+hipError_t newton_schulz_blend(double* S, Dim n, hipStream_t stream, const int* dd = nullptr);
 
 // out[0] = sum |E|^2, out[1] = Re tr E, for an n x n complex matrix (purity).
 hipError_t gram_stats(const double* E, int n, double* out, hipStream_t stream);

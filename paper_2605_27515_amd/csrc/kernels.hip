@@ -41,13 +41,33 @@ constexpr int BM = 64, BN = 64, BK = 16, PAD = 4, NT = 256;
 constexpr int GEPT = BM * BK / NT;   // tile entries staged per thread
 
 struct GemmK {
-  int M, N, K, batch, splits, kchunk, herm;
-  const void* A; long long sa_m, sa_k, sa_b; int conjA;
-  const void* B; long long sb_k, sb_n, sb_b; int conjB;
-  void* C; long long sc_m, sc_n, sc_b;
+  Dim M, N, K, batch;
+  int splits, herm;
+  const void* A; Dim sa_m, sa_k, sa_b; int conjA;
+  const void* B; Dim sb_k, sb_n, sb_b; int conjB;
+  void* C; Dim sc_m, sc_n, sc_b;
   double ar, ai, br, bi;
   void* ws;
+  const int* dd;
 };
+
+// The sizes of one launch, read once per workgroup (a few scalar loads of
+// the size table when some are device-side).
+struct GemmDims {
+  int M, N, K, batch, kchunk;
+  long long sa_m, sa_k, sa_b, sb_k, sb_n, sb_b, sc_m, sc_n, sc_b;
+};
+__device__ inline GemmDims gemm_dims(const GemmK& g) {
+  GemmDims d;
+  d.M = dim_val(g.M, g.dd); d.N = dim_val(g.N, g.dd); d.K = dim_val(g.K, g.dd); d.batch = dim_val(g.batch, g.dd);
+  d.sa_m = dim_val(g.sa_m, g.dd); d.sa_k = dim_val(g.sa_k, g.dd); d.sa_b = dim_val(g.sa_b, g.dd);
+  d.sb_k = dim_val(g.sb_k, g.dd); d.sb_n = dim_val(g.sb_n, g.dd); d.sb_b = dim_val(g.sb_b, g.dd);
+  d.sc_m = dim_val(g.sc_m, g.dd); d.sc_n = dim_val(g.sc_n, g.dd); d.sc_b = dim_val(g.sc_b, g.dd);
+  int kc = (d.K + g.splits - 1) / g.splits;
+  kc = ((kc + BK - 1) / BK) * BK;
+  d.kchunk = kc > 0 ? kc : BK;
+  return d;
+}
 
 template <typename TA, typename TB, typename TC, typename TO>
 __global__ __launch_bounds__(NT) void gemm_kernel(GemmK g) {
@@ -56,25 +76,35 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmK g) {
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int tiles_n = (g.N + BN - 1) / BN;
-  int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+  const GemmDims gd = gemm_dims(g);
+  if (gd.M <= 0 || gd.N <= 0) return;
+  // the launch is sized for the bounds of the sizes; the tiles of the actual
+  // sizes are the first blockIdx.x values and the rest leave at once
+  const int tiles_n = (gd.N + BN - 1) / BN, tiles_m = (gd.M + BM - 1) / BM;
+  int tm, tn;
   if (g.herm) {
     // tiles on and above the diagonal, row by row
     int t = blockIdx.x;
+    if (t >= tiles_n * (tiles_n + 1) / 2) return;
     tm = 0;
     while (t >= tiles_n - tm) { t -= tiles_n - tm; ++tm; }
     tn = tm + t;
+  } else {
+    if ((int)blockIdx.x >= tiles_m * tiles_n) return;
+    tm = blockIdx.x / tiles_n;
+    tn = blockIdx.x % tiles_n;
   }
   const int i0 = tm * BM, j0 = tn * BN;
   const int z = blockIdx.y;
   const int b = z / g.splits, split = z % g.splits;
-  const int kb = split * g.kchunk;
-  const int ke = min(g.K, kb + g.kchunk);
+  if (b >= gd.batch) return;
+  const int kb = split * gd.kchunk;
+  const int ke = min(gd.K, kb + gd.kchunk);
 
-  const TA* A = reinterpret_cast<const TA*>(g.A) + 2 * (long long)b * g.sa_b;
-  const TB* B = reinterpret_cast<const TB*>(g.B) + 2 * (long long)b * g.sb_b;
-  const bool a_kfast = (g.sa_k == 1);
-  const bool b_nfast = (g.sb_n == 1);
+  const TA* A = reinterpret_cast<const TA*>(g.A) + 2 * (long long)b * gd.sa_b;
+  const TB* B = reinterpret_cast<const TB*>(g.B) + 2 * (long long)b * gd.sb_b;
+  const bool a_kfast = (gd.sa_k == 1);
+  const bool b_nfast = (gd.sb_n == 1);
   const TC sa = g.conjA ? TC(-1) : TC(1);
   const TC sb = g.conjB ? TC(-1) : TC(1);
 
@@ -91,8 +121,8 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmK g) {
       if (a_kfast) { ii = idx / BK; kk = idx % BK; } else { kk = idx / BM; ii = idx % BM; }
       const int gi = i0 + ii, gk = k0 + kk;
       TA vr = 0, vi = 0;
-      if (gi < g.M && gk < ke) {
-        const long long off = 2 * ((long long)gi * g.sa_m + (long long)gk * g.sa_k);
+      if (gi < gd.M && gk < ke) {
+        const long long off = 2 * ((long long)gi * gd.sa_m + (long long)gk * gd.sa_k);
         vr = A[off];
         vi = A[off + 1];
       }
@@ -105,8 +135,8 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmK g) {
       if (b_nfast) { kk = idx / BN; jj = idx % BN; } else { jj = idx / BK; kk = idx % BK; }
       const int gj = j0 + jj, gk = k0 + kk;
       TB vr = 0, vi = 0;
-      if (gj < g.N && gk < ke) {
-        const long long off = 2 * ((long long)gk * g.sb_k + (long long)gj * g.sb_n);
+      if (gj < gd.N && gk < ke) {
+        const long long off = 2 * ((long long)gk * gd.sb_k + (long long)gj * gd.sb_n);
         vr = B[off];
         vi = B[off + 1];
       }
@@ -180,16 +210,16 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmK g) {
       for (int r = 0; r < 4; ++r) {
         const int i = i0 + wm + x * 16 + (f64acc ? 4 * r + lk : 4 * lk + r);
         const int j = j0 + wn + y * 16 + lr;
-        if (i >= g.M || j >= g.N) continue;
+        if (i >= gd.M || j >= gd.N) continue;
         const double vr = (double)acc_r[x][y][r], vi = (double)acc_i[x][y][r];
         if (g.splits > 1) {
           TC* ws = reinterpret_cast<TC*>(g.ws);
-          const long long off = 2 * ((((long long)b * g.splits + split) * g.M + i) * g.N + j);
+          const long long off = 2 * ((((long long)b * g.splits + split) * gd.M + i) * gd.N + j);
           ws[off] = (TC)vr;
           ws[off + 1] = (TC)vi;
         } else {
-          TO* C = reinterpret_cast<TO*>(g.C) + 2 * (long long)b * g.sc_b;
-          const long long off = 2 * ((long long)i * g.sc_m + (long long)j * g.sc_n);
+          TO* C = reinterpret_cast<TO*>(g.C) + 2 * (long long)b * gd.sc_b;
+          const long long off = 2 * ((long long)i * gd.sc_m + (long long)j * gd.sc_n);
           double orr = g.ar * vr - g.ai * vi, oi = g.ar * vi + g.ai * vr;
           if (g.br != 0.0 || g.bi != 0.0) {
             const double cr = (double)C[off], ci = (double)C[off + 1];
@@ -199,7 +229,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmK g) {
           C[off] = (TO)orr;
           C[off + 1] = (TO)oi;
           if (g.herm && tm < tn) {
-            const long long mo = 2 * ((long long)j * g.sc_m + (long long)i * g.sc_n);
+            const long long mo = 2 * ((long long)j * gd.sc_m + (long long)i * gd.sc_n);
             C[mo] = (TO)orr;
             C[mo + 1] = (TO)(-oi);
           }
@@ -209,22 +239,23 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmK g) {
 
 template <typename TC, typename TO>
 __global__ void splitk_reduce(GemmK g) {
-  const long long total = (long long)g.batch * g.M * g.N;
+  const GemmDims gd = gemm_dims(g);
+  const long long total = (long long)gd.batch * gd.M * gd.N;
   const TC* ws = reinterpret_cast<const TC*>(g.ws);
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
-    const int b = (int)(e / ((long long)g.M * g.N));
-    const long long ij = e % ((long long)g.M * g.N);
-    const int i = (int)(ij / g.N), j = (int)(ij % g.N);
+    const int b = (int)(e / ((long long)gd.M * gd.N));
+    const long long ij = e % ((long long)gd.M * gd.N);
+    const int i = (int)(ij / gd.N), j = (int)(ij % gd.N);
     if (g.herm && i / BM > j / BN) continue;   // written as the mirror of (j, i)
     double vr = 0.0, vi = 0.0;
     for (int s = 0; s < g.splits; ++s) {
-      const long long off = 2 * ((((long long)b * g.splits + s) * g.M + i) * g.N + j);
+      const long long off = 2 * ((((long long)b * g.splits + s) * gd.M + i) * gd.N + j);
       vr += (double)ws[off];
       vi += (double)ws[off + 1];
     }
-    TO* C = reinterpret_cast<TO*>(g.C) + 2 * (long long)b * g.sc_b;
-    const long long off = 2 * ((long long)i * g.sc_m + (long long)j * g.sc_n);
+    TO* C = reinterpret_cast<TO*>(g.C) + 2 * (long long)b * gd.sc_b;
+    const long long off = 2 * ((long long)i * gd.sc_m + (long long)j * gd.sc_n);
     double orr = g.ar * vr - g.ai * vi, oi = g.ar * vi + g.ai * vr;
     if (g.br != 0.0 || g.bi != 0.0) {
       const double cr = (double)C[off], ci = (double)C[off + 1];
@@ -234,7 +265,7 @@ __global__ void splitk_reduce(GemmK g) {
     C[off] = (TO)orr;
     C[off + 1] = (TO)oi;
     if (g.herm && i / BM < j / BN) {
-      const long long mo = 2 * ((long long)j * g.sc_m + (long long)i * g.sc_n);
+      const long long mo = 2 * ((long long)j * gd.sc_m + (long long)i * gd.sc_n);
       C[mo] = (TO)orr;
       C[mo + 1] = (TO)(-oi);
     }
@@ -243,13 +274,14 @@ __global__ void splitk_reduce(GemmK g) {
 
 template <typename TA, typename TB, typename TC, typename TO>
 static hipError_t launch_gemm(const GemmK& k, hipStream_t s) {
-  const int tn = (k.N + BN - 1) / BN;
-  const int tiles = k.herm ? tn * (tn + 1) / 2 : ((k.M + BM - 1) / BM) * tn;
-  dim3 grid(tiles, k.batch * k.splits);
+  const int tn = (k.N.hi + BN - 1) / BN;
+  const int tiles = k.herm ? tn * (tn + 1) / 2 : ((k.M.hi + BM - 1) / BM) * tn;
+  if (tiles <= 0 || k.batch.hi <= 0) return hipSuccess;
+  dim3 grid(tiles, k.batch.hi * k.splits);
   hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, TO>), grid, dim3(NT), 0, s, k);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || k.splits == 1) return e;
-  const long long total = (long long)k.batch * k.M * k.N;
+  const long long total = (long long)k.batch.hi * k.M.hi * k.N.hi;
   const int blocks = (int)std::min<long long>((total + 255) / 256, 4096);
   hipLaunchKernelGGL((splitk_reduce<TC, TO>), dim3(blocks), dim3(256), 0, s, k);
   return hipGetLastError();
@@ -269,24 +301,25 @@ static hipError_t pick_b(const GemmK& k, Prec pb, Prec comp, Prec pc, hipStream_
 }
 
 hipError_t gemm(const Gemm& g, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+  if (g.M.hi <= 0 || g.N.hi <= 0 || g.batch.hi <= 0) return hipSuccess;
+  if ((g.M.idx >= 0 || g.N.idx >= 0 || g.K.idx >= 0 || g.batch.idx >= 0) && g.dd == nullptr)
+    return hipErrorInvalidValue;
   GemmK k;
   k.M = g.M; k.N = g.N; k.K = g.K; k.batch = g.batch;
-  int splits = std::max(1, g.splits);
-  if (g.K <= 0) splits = 1;
-  int kchunk = (g.K + splits - 1) / splits;
-  kchunk = ((kchunk + BK - 1) / BK) * BK;
-  if (kchunk <= 0) kchunk = BK;
-  splits = std::max(1, (g.K + kchunk - 1) / kchunk);
+  // at most one K slice per split at the bound of K
+  int splits = std::max(1, std::min(g.splits, (g.K.hi + BK - 1) / BK));
+  if (g.K.hi <= 0) splits = 1;
   if (splits > 1 && g.ws == nullptr) return hipErrorInvalidValue;
-  k.splits = splits; k.kchunk = kchunk;
+  k.splits = splits;
+  k.dd = g.dd;
   k.A = g.A; k.sa_m = g.sa_m; k.sa_k = g.sa_k; k.sa_b = g.sa_b; k.conjA = g.conjA;
   k.B = g.B; k.sb_k = g.sb_k; k.sb_n = g.sb_n; k.sb_b = g.sb_b; k.conjB = g.conjB;
   k.C = g.C; k.sc_m = g.sc_m; k.sc_n = g.sc_n; k.sc_b = g.sc_b;
   k.ar = g.alpha_re; k.ai = g.alpha_im; k.br = g.beta_re; k.bi = g.beta_im;
   k.ws = g.ws;
   k.herm = g.herm;
-  if (g.herm && (g.M != g.N || g.alpha_im != 0.0 || g.beta_re != 0.0 || g.beta_im != 0.0))
+  if (g.herm && (g.M.c != g.N.c || g.M.idx != g.N.idx || g.alpha_im != 0.0 || g.beta_re != 0.0 ||
+                 g.beta_im != 0.0))
     return hipErrorInvalidValue;
   return g.pa == F64 ? pick_b<double>(k, g.pb, g.compute, g.pc, s)
                      : pick_b<float>(k, g.pb, g.compute, g.pc, s);
@@ -316,9 +349,11 @@ __device__ inline void rr_pair(int r, int t, int nn, int& p, int& q) {
   p = min(x, y); q = max(x, y);
 }
 
-__global__ __launch_bounds__(HEEV_NT) void heev_kernel(double* Gall, int ldg, long long g_stride, int n,
-                                                        double* wall, long long w_stride, double* Vall,
-                                                        double rel_tol, int max_sweeps, int* info) {
+__global__ __launch_bounds__(HEEV_NT) void heev_kernel(double* Gall, int ldg, long long g_stride, Dim nD,
+                                                        const int* dd, double* wall, long long w_stride,
+                                                        double* Vall, double rel_tol, int max_sweeps, int* info) {
+  const int n = dim_val(nD, dd);
+  if (n <= 0) return;
   __shared__ int sp[HEEV_MAXP], sq[HEEV_MAXP];
   __shared__ double sc[HEEV_MAXP], ssr[HEEV_MAXP], ssi[HEEV_MAXP], sda[HEEV_MAXP], sdb[HEEV_MAXP];
   __shared__ int srot[HEEV_MAXP];
@@ -334,11 +369,25 @@ __global__ __launch_bounds__(HEEV_NT) void heev_kernel(double* Gall, int ldg, lo
     const int i = (int)(e / n), j = (int)(e % n);
     st(V, e, cplx{i == j ? 1.0 : 0.0, 0.0});
   }
+  // floor below which an off-diagonal entry is left alone: kJacobiFloor
+  // times the largest entry modulus (for a positive semidefinite Gram matrix
+  // that is the largest diagonal entry)
+  __shared__ double gred[HEEV_NT];
   __shared__ double gfloor;
-  if (tid == 0) {
-    double gmax = 0.0;
-    for (int j = 0; j < n; ++j) gmax = fmax(gmax, fabs(G[2 * ((long long)j * ldg + j)]));
-    gfloor = kJacobiFloor * gmax;
+  {
+    double gm = 0.0;
+    for (long long e = tid; e < (long long)n * n; e += HEEV_NT) {
+      const int i = (int)(e / n), j = (int)(e % n);
+      const cplx z = ld(G, (long long)i * ldg + j);
+      gm = fmax(gm, sqrt(z.r * z.r + z.i * z.i));
+    }
+    gred[tid] = gm;
+    __syncthreads();
+    for (int st_ = HEEV_NT / 2; st_ > 0; st_ >>= 1) {
+      if (tid < st_) gred[tid] = fmax(gred[tid], gred[tid + st_]);
+      __syncthreads();
+    }
+    if (tid == 0) gfloor = kJacobiFloor * gred[0];
   }
   __syncthreads();
   int sweeps_used = -1;
@@ -356,7 +405,7 @@ __global__ __launch_bounds__(HEEV_NT) void heev_kernel(double* Gall, int ldg, lo
           const double a = G[2 * ((long long)p * ldg + p)], bb = G[2 * ((long long)q * ldg + q)];
           const cplx z = ld(G, (long long)p * ldg + q);
           const double az = sqrt(z.r * z.r + z.i * z.i);
-          if (az > rel_tol * sqrt(fabs(a * bb)) && az > 1e-300 && fmax(fabs(a), fabs(bb)) >= gfloor) {
+          if (az > rel_tol * sqrt(fabs(a * bb)) && az > 1e-300 && (fmax(fabs(a), fabs(bb)) >= gfloor || az >= gfloor)) {
             const double zeta = (bb - a) / (2.0 * az);
             const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
             c = 1.0 / sqrt(1.0 + tt * tt);
@@ -450,12 +499,12 @@ __global__ __launch_bounds__(HEEV_NT) void heev_kernel(double* Gall, int ldg, lo
   if (tid == 0 && info) info[blockIdx.x] = sweeps_used;
 }
 
-hipError_t heev_jacobi(double* G, int ldg, long long g_stride, int n, double* w, long long w_stride,
+hipError_t heev_jacobi(double* G, int ldg, long long g_stride, Dim n, double* w, long long w_stride,
                        double* V, int batch, double rel_tol, int max_sweeps, int* info,
-                       hipStream_t s) {
-  if (n <= 0 || batch <= 0) return hipSuccess;
-  if (n > 2 * HEEV_MAXP) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(heev_kernel, dim3(batch), dim3(HEEV_NT), 0, s, G, ldg, g_stride, n, w, w_stride,
+                       hipStream_t s, const int* dd) {
+  if (n.hi <= 0 || batch <= 0) return hipSuccess;
+  if (n.hi > 2 * HEEV_MAXP || (n.idx >= 0 && !dd)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(heev_kernel, dim3(batch), dim3(HEEV_NT), 0, s, G, ldg, g_stride, n, dd, w, w_stride,
                      V, rel_tol, max_sweeps, info);
   return hipGetLastError();
 }
@@ -464,13 +513,26 @@ hipError_t heev_jacobi(double* G, int ldg, long long g_stride, int n, double* w,
 // small kernels
 // ---------------------------------------------------------------------------
 
-__global__ void truncate_kernel(const double* lam, int n, double tol, int cap, int* k_out, double* disc) {
+__global__ void truncate_kernel(const double* lam, Dim nD, const int* dd, double tol, int cap, int* k_out,
+                                double* disc, int* err) {
+  const int n = dim_val(nD, dd);
   // the eigenvalues are staged in LDS by all threads; the sums stay serial,
   // in index order, so the decision is that of the plain rule
   __shared__ double sl[512];
-  for (int j = threadIdx.x; j < n; j += blockDim.x) sl[j] = fmax(lam[j], 0.0);
+  for (int j = threadIdx.x; j < n; j += blockDim.x) sl[j] = lam[j];
   __syncthreads();
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (n < 1) {
+    *k_out = 1;
+    if (disc) *disc = 0.0;
+    return;
+  }
+  bool bad = false;
+  for (int j = 0; j < n; ++j) {
+    bad |= !isfinite(sl[j]);
+    sl[j] = fmax(sl[j], 0.0);
+  }
+  if (bad && err) *err = *err | 2;
   const double* lam_ = sl;
   double total = 0.0;
   for (int j = 0; j < n; ++j) total += lam_[j];
@@ -489,15 +551,18 @@ __global__ void truncate_kernel(const double* lam, int n, double tol, int cap, i
   if (disc) *disc = total > 0.0 ? tail / total : 0.0;
 }
 
-hipError_t truncate_rank(const double* lam, int n, double tol, int cap, int* k_out, double* disc,
-                         hipStream_t s) {
-  if (n < 1 || n > 512) return hipErrorInvalidValue;   // the kernel stages lam in 4 KB of LDS
-  hipLaunchKernelGGL(truncate_kernel, dim3(1), dim3(64), 0, s, lam, n, tol, cap, k_out, disc);
+hipError_t truncate_rank(const double* lam, Dim n, double tol, int cap, int* k_out, double* disc, int* err,
+                         hipStream_t s, const int* dd) {
+  // the kernel stages lam in 4 KB of LDS
+  if (n.hi < 1 || n.hi > 512 || (n.idx >= 0 && !dd)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(truncate_kernel, dim3(1), dim3(64), 0, s, lam, n, dd, tol, cap, k_out, disc, err);
   return hipGetLastError();
 }
 
-__global__ void copy_cols_kernel(const double* src, int lds, double* dst, int ldd, int rows, int cols,
-                                 const double* lam) {
+__global__ void copy_cols_kernel(const double* src, Dim ldsD, double* dst, Dim lddD, Dim rowsD, Dim colsD,
+                                 const double* lam, const int* dd) {
+  const long long lds = dim_val(ldsD, dd), ldd = dim_val(lddD, dd);
+  const int rows = dim_val(rowsD, dd), cols = dim_val(colsD, dd);
   const long long total = (long long)rows * cols;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
@@ -508,17 +573,19 @@ __global__ void copy_cols_kernel(const double* src, int lds, double* dst, int ld
   }
 }
 
-hipError_t copy_cols(const double* src, int lds, double* dst, int ldd, int rows, int cols,
-                     const double* lam, hipStream_t s) {
-  const long long total = (long long)rows * cols;
+hipError_t copy_cols(const double* src, Dim lds, double* dst, Dim ldd, Dim rows, Dim cols,
+                     const double* lam, hipStream_t s, const int* dd) {
+  const long long total = (long long)rows.hi * cols.hi;
   if (total <= 0) return hipSuccess;
   const int blocks = (int)std::min<long long>((total + 255) / 256, 2048);
-  hipLaunchKernelGGL(copy_cols_kernel, dim3(blocks), dim3(256), 0, s, src, lds, dst, ldd, rows, cols, lam);
+  hipLaunchKernelGGL(copy_cols_kernel, dim3(blocks), dim3(256), 0, s, src, lds, dst, ldd, rows, cols, lam, dd);
   return hipGetLastError();
 }
 
-__global__ void scale_rows_kernel(const double* src, int lds, double* dst, int ldd, int rows, int cols,
-                                  const double* lam) {
+__global__ void scale_rows_kernel(const double* src, Dim ldsD, double* dst, Dim lddD, Dim rowsD, Dim colsD,
+                                  const double* lam, const int* dd) {
+  const long long lds = dim_val(ldsD, dd), ldd = dim_val(lddD, dd);
+  const int rows = dim_val(rowsD, dd), cols = dim_val(colsD, dd);
   const long long total = (long long)rows * cols;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
@@ -530,12 +597,12 @@ __global__ void scale_rows_kernel(const double* src, int lds, double* dst, int l
   }
 }
 
-hipError_t scale_rows_inv_sqrt(const double* src, int lds, double* dst, int ldd, int rows, int cols,
-                               const double* lam, hipStream_t s) {
-  const long long total = (long long)rows * cols;
+hipError_t scale_rows_inv_sqrt(const double* src, Dim lds, double* dst, Dim ldd, Dim rows, Dim cols,
+                               const double* lam, hipStream_t s, const int* dd) {
+  const long long total = (long long)rows.hi * cols.hi;
   if (total <= 0) return hipSuccess;
   const int blocks = (int)std::min<long long>((total + 255) / 256, 2048);
-  hipLaunchKernelGGL(scale_rows_kernel, dim3(blocks), dim3(256), 0, s, src, lds, dst, ldd, rows, cols, lam);
+  hipLaunchKernelGGL(scale_rows_kernel, dim3(blocks), dim3(256), 0, s, src, lds, dst, ldd, rows, cols, lam, dd);
   return hipGetLastError();
 }
 
@@ -558,12 +625,73 @@ __global__ __launch_bounds__(256) void normalize_kernel(double* x, long long cou
   for (long long e = threadIdx.x; e < 2 * count; e += 256) x[e] *= f;
   if (threadIdx.x == 0) {
     *tau_out = tau;
-    if (!ok && flag) *flag = 1;
+    if (!ok && flag) *flag = *flag | 1;
   }
 }
 
 hipError_t normalize(double* x, long long count, double* tau_out, int* flag, hipStream_t s) {
   hipLaunchKernelGGL(normalize_kernel, dim3(1), dim3(256), 0, s, x, count, tau_out, flag);
+  return hipGetLastError();
+}
+
+// The same sum in the same order, then the step's status
+__global__ __launch_bounds__(256) void normalize_step_kernel(double* x, Dim countD, const int* dd, StepStat* st,
+                                                             double tau_warn) {
+  __shared__ double red[256];
+  const long long count = dim_val(countD, dd);
+  double acc = 0.0;
+  for (long long e = threadIdx.x; e < count; e += 256) {
+    const double a = x[2 * e], b = x[2 * e + 1];
+    acc += a * a + b * b;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double tau = red[0];
+  const bool ok = isfinite(tau) && tau > 0.0;
+  const double f = ok ? 1.0 / sqrt(tau) : 1.0;
+  for (long long e = threadIdx.x; e < 2 * count; e += 256) x[e] *= f;
+  if (threadIdx.x == 0) {
+    st->tau = tau;
+    if (!ok) st->err |= 1;
+    const double def = fabs(tau - 1.0);
+    if (def > st->max_defect) st->max_defect = def;
+    if (tau - 1.0 > tau_warn) st->warn = 1;
+    st->steps += 1;
+  }
+}
+
+hipError_t normalize_step(double* x, Dim count, StepStat* st, double tau_warn, hipStream_t s, const int* dd) {
+  hipLaunchKernelGGL(normalize_step_kernel, dim3(1), dim3(256), 0, s, x, count, dd, st, tau_warn);
+  return hipGetLastError();
+}
+
+__global__ void copy_elems_kernel(const double* src, double* dst, Dim countD, const int* dd) {
+  const long long n = 2LL * dim_val(countD, dd);
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    dst[e] = src[e];
+}
+
+hipError_t copy_elems(const double* src, double* dst, Dim count, hipStream_t s, const int* dd) {
+  const long long n = 2LL * count.hi;
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)std::min<long long>((n + 255) / 256, 2048);
+  hipLaunchKernelGGL(copy_elems_kernel, dim3(blocks), dim3(256), 0, s, src, dst, count, dd);
+  return hipGetLastError();
+}
+
+__global__ void move_dims_kernel(int* dd, DimMoves m) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int j = 0; j < m.n; ++j) dd[m.dst[j]] = m.src[j] >= 0 ? dd[m.src[j]] : m.value[j];
+}
+
+hipError_t move_dims(int* dd, const DimMoves& m, hipStream_t s) {
+  if (m.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(move_dims_kernel, dim3(1), dim3(64), 0, s, dd, m);
   return hipGetLastError();
 }
 
@@ -601,6 +729,34 @@ hipError_t boundary_contract(const double* Wb, long long stride, int degree, dou
   if (count <= 0) return hipSuccess;
   const int blocks = (int)std::min<long long>((count + 255) / 256, 1024);
   hipLaunchKernelGGL(boundary_kernel, dim3(blocks), dim3(256), 0, s, Wb, stride, degree, f, W0, W0f, count);
+  return hipGetLastError();
+}
+
+__global__ void boundary_step_kernel(const double* Wb, long long stride, int degree, DriveParams dp,
+                                     const StepStat* st, double* W0, float* W0f, long long count) {
+  const double t = ((double)st->steps + 0.5) * dp.dt;
+  double f = 0.0;
+  for (int j = 0; j < dp.n; ++j) f += dp.c[j] * cos(dp.w[j] * t + dp.p[j]);
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < count;
+       e += (long long)gridDim.x * blockDim.x) {
+    double vr = 0.0, vi = 0.0, c = 1.0;
+    for (int p = 0; p < degree; ++p) {
+      vr += c * Wb[2 * (p * stride + e)];
+      vi += c * Wb[2 * (p * stride + e) + 1];
+      c *= f;
+    }
+    W0[2 * e] = vr; W0[2 * e + 1] = vi;
+    if (W0f) { W0f[2 * e] = (float)vr; W0f[2 * e + 1] = (float)vi; }
+  }
+}
+
+hipError_t boundary_contract_step(const double* Wb, long long stride, int degree, const DriveParams& f,
+                                  const StepStat* st, double* W0, float* W0f, long long count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (f.n < 0 || f.n > 8) return hipErrorInvalidValue;
+  const int blocks = (int)std::min<long long>((count + 255) / 256, 1024);
+  hipLaunchKernelGGL(boundary_step_kernel, dim3(blocks), dim3(256), 0, s, Wb, stride, degree, f, st, W0, W0f,
+                     count);
   return hipGetLastError();
 }
 
@@ -642,7 +798,8 @@ __global__ __launch_bounds__(256) void gram_stats_kernel(const double* E, int n,
   if (threadIdx.x == 0) { out[0] = ra[0]; out[1] = rt[0]; }
 }
 
-__global__ void ns_blend_kernel(double* S, int n) {
+__global__ void ns_blend_kernel(double* S, Dim nD, const int* dd) {
+  const int n = dim_val(nD, dd);
   const long long total = (long long)n * n;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
@@ -652,10 +809,11 @@ __global__ void ns_blend_kernel(double* S, int n) {
   }
 }
 
-hipError_t newton_schulz_blend(double* S, int n, hipStream_t s) {
-  const long long total = (long long)n * n;
+hipError_t newton_schulz_blend(double* S, Dim n, hipStream_t s, const int* dd) {
+  const long long total = (long long)n.hi * n.hi;
+  if (total <= 0) return hipSuccess;
   const int blocks = (int)std::min<long long>((total + 255) / 256, 1024);
-  hipLaunchKernelGGL(ns_blend_kernel, dim3(blocks), dim3(256), 0, s, S, n);
+  hipLaunchKernelGGL(ns_blend_kernel, dim3(blocks), dim3(256), 0, s, S, n, dd);
   return hipGetLastError();
 }
 
@@ -886,10 +1044,13 @@ __device__ inline void trd_reflector(double2 alpha, double xn2, double& beta, do
 __device__ inline double2 cmul(double2 a, double2 b) { return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 
 template <int PARTS>
-__global__ __launch_bounds__(TRD_NT) void hetrd_kernel(const double2* G, int ldg, int n, double* d, double* e,
-                                                       double2* tau, double2* Vt) {
+__global__ __launch_bounds__(TRD_NT) void hetrd_kernel(const double2* G, int ldg, Dim nD, const int* dd, int nmin,
+                                                       double* d, double* e, double2* tau, double2* Vt) {
   static_assert(PARTS == 8 || PARTS == 16, "orders up to 128");
   __shared__ TrdShared<PARTS> sh;
+  // this form runs orders nmin..P (a launch of several forms gates by order)
+  const int n = dim_val(nD, dd);
+  if (n < nmin || n > TrdShared<PARTS>::P || n < 1) return;
   const int tid = threadIdx.x, lane = tid & 63;
   const bool w0 = tid < 64;
   if (n == 1) {
@@ -1018,8 +1179,10 @@ constexpr int TRM_NT = 512;                      // 8 waves
 constexpr int TRM_WMAX = 32;                     // workgroups, at most
 constexpr int TRM_NMAX = 512;                    // order, at most
 constexpr long long TRM_WAIT_TICKS = 200000000;  // 2 s (the default bound)
-// bound of the waits, in wall-clock ticks; tests of the time-out path lower it
-static std::atomic<long long> g_trm_wait_ticks{TRM_WAIT_TICKS};
+// bound of the waits, in wall-clock ticks; tests of the time-out path lower
+// it.  A device variable, so that launches captured into a graph see the
+// current bound.
+__device__ long long d_trm_wait_ticks = TRM_WAIT_TICKS;
 // sync block in doubles: the abort word (one 128-byte line), then the
 // mailboxes Y[n][n] and F[n][n] (complex, step-major): slot [j][c] receives
 // y_j[c] and row j+1 of B_j at column c, each double posted once per launch
@@ -1036,7 +1199,8 @@ __device__ inline unsigned long long trm_peek(const double* p) {
   return __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void trm_clear_kernel(unsigned long long* p, long long count) {
+__global__ void trm_clear_kernel(unsigned long long* p, long long count, unsigned long long* abortw) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *abortw = 0ull;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
     p[i] = TRM_EMPTY;
 }
@@ -1203,13 +1367,17 @@ __device__ inline void trm_pass(const double2* G, int ldg, int n, int j, TrmShar
 }
 
 template <int W, int CPW>
-__global__ __launch_bounds__(TRM_NT) void hetrd_mc_kernel(const double2* G, int ldg, int n, double* d, double* e,
-                                                          double2* tau, double2* Vt, double* mail,
-                                                          unsigned long long* abortw, unsigned gen,
-                                                          long long wait_ticks) {
+__global__ __launch_bounds__(TRM_NT) void hetrd_mc_kernel(const double2* G, int ldg, Dim nD, const int* dd, int nmin,
+                                                          double* d, double* e, double2* tau, double2* Vt,
+                                                          double* mail, unsigned long long* abortw, unsigned gen) {
   constexpr int LC = 8 * CPW, NMAX = W * LC, QR = NMAX / 64;
   static_assert(W <= TRM_WMAX && NMAX <= TRM_NMAX, "sync block layout");
   __shared__ TrmShared<NMAX, CPW> sh;
+  // orders nmin..NMAX; every workgroup reads the same order, so all of them
+  // leave here together or none does
+  const int n = dim_val(nD, dd);
+  if (n < nmin || n > NMAX || n < 2) return;
+  const long long wait_ticks = d_trm_wait_ticks;
   const int tid = threadIdx.x, lane = tid & 63, g = blockIdx.x;
   const bool w0 = tid < 64, lead = (g == 0);
   double2 reg[CPW][QR];
@@ -1383,8 +1551,10 @@ __device__ inline int sturm_count(const double* sd, const double* se2, int n, do
 // STEBZ_NT + 1 equal parts), so a round narrows the bracket STEBZ_NT + 1 fold
 // at the latency of one Sturm sequence.
 constexpr int STEBZ_NT = 256;
-__global__ __launch_bounds__(STEBZ_NT) void stebz_kernel(const double* d, const double* e, int n, double* w,
-                                                         int kmax) {
+__global__ __launch_bounds__(STEBZ_NT) void stebz_kernel(const double* d, const double* e, Dim nD, const int* dd,
+                                                         double* w) {
+  const int n = dim_val(nD, dd), kmax = n;
+  if ((int)blockIdx.x >= n) return;
   __shared__ double sd[512], se2[512];
   __shared__ double bnd[2], blo[STEBZ_NT / 64], bhi[STEBZ_NT / 64];
   __shared__ int firstw[STEBZ_NT / 64];
@@ -1507,8 +1677,10 @@ __device__ inline double stein_tiny_wave(const double* sd, const double* se, int
 // Z[i*ldz + j] (j < k): unit eigenvector of the tridiagonal for w[j], by one
 // solve with the pivoted LU of T - w_j I from a hashed start vector (which
 // amplifies the wanted direction by ~1 / (eps ||T||)).
-__global__ __launch_bounds__(64) void stein_kernel(const double* d, const double* e, int n, const double* w,
-                                                   int k, double* Z, int ldz) {
+__global__ __launch_bounds__(64) void stein_kernel(const double* d, const double* e, Dim nD, const double* w,
+                                                   Dim kD, const int* dd, double* Z) {
+  const int n = dim_val(nD, dd), k = min(dim_val(kD, dd), n), ldz = n;
+  if ((int)blockIdx.x * (int)blockDim.x >= k) return;
   // per-thread working arrays in LDS, [array][i][thread] (blockDim.x threads)
   extern __shared__ double lds[];
   __shared__ double sd[512], se[512], rs[512];
@@ -1593,7 +1765,10 @@ __host__ __device__ constexpr int orm_wy_b(int nmax) { return nmax <= 256 ? 16 :
 __host__ __device__ constexpr size_t orm_wy_doubles(int n) { return (size_t)2 * 16 * (n + 16); }
 
 template <int B, int NMAX>
-__global__ __launch_bounds__(512) void orm_t_kernel(const double* Vt, const double* tau, int n, double* Tw) {
+__global__ __launch_bounds__(512) void orm_t_kernel(const double* Vt, const double* tau, Dim nD, const int* dd,
+                                                    double* Tw) {
+  const int n = dim_val(nD, dd);
+  if ((int)blockIdx.x >= (n - 1 + B - 1) / B) return;
   static_assert(B * B <= 256, "one thread per (row, column) pair in the recurrence");
   __shared__ double2 vs[B][NMAX];
   __shared__ double2 S2[2][B][B];
@@ -1656,8 +1831,10 @@ __global__ __launch_bounds__(512) void orm_t_kernel(const double* Vt, const doub
 }
 
 template <int B, int NMAX>
-__global__ __launch_bounds__(256) void ormtr_wy_kernel(const double* Vt, const double* Tw, int n, const double* Z,
-                                                       int ldz, int k, double* U, int ldu) {
+__global__ __launch_bounds__(256) void ormtr_wy_kernel(const double* Vt, const double* Tw, Dim nD, const double* Z,
+                                                       Dim kD, const int* dd, double* U, int ldu) {
+  const int n = dim_val(nD, dd), k = min(dim_val(kD, dd), n), ldz = n;
+  if ((int)blockIdx.x * 4 >= k) return;
   constexpr int PF = B * NMAX / 256;   // staged V entries per thread
   constexpr int QW = NMAX / 64;        // rows per lane
   constexpr int NV = 2 * B;            // values folded per block
@@ -1875,8 +2052,11 @@ __device__ void sg_solve(double* zl, int n, const double* sd, const double* se, 
 // group.  Groups are disjoint, so workgroup g handles the group that starts
 // at eigenvalue g (if any); unresolved eigenvalues (|w| <= 8 n eps ||T||)
 // are left to stein_unresolved_kernel.
-__global__ __launch_bounds__(SG_NT) void stein_groups_kernel(int n, const double* d, const double* e,
-                                                             const double* w, int k, double theta, double* Z, int ldz) {
+__global__ __launch_bounds__(SG_NT) void stein_groups_kernel(Dim nD, const double* d, const double* e,
+                                                             const double* w, Dim kD, const int* dd, double theta,
+                                                             double* Z) {
+  const int n = dim_val(nD, dd), k = min(dim_val(kD, dd), n), ldz = n;
+  if ((int)blockIdx.x >= k) return;
   __shared__ double zl[512], dots[512], lu[3 * 512], sd[512], se[512];
   __shared__ double red[32];
   __shared__ int cols[512];
@@ -2082,8 +2262,10 @@ __device__ bool ur_cholqr(const int* ucols, int c0, int cb, int n, double* Z, in
 // vector, projected out of the span of the resolved vectors twice (classical
 // Gram-Schmidt against the whole set, the vector held in LDS).  Workgroups
 // read only resolved columns and write only their own.
-__global__ __launch_bounds__(SG_NT) void stein_unresolved_project_kernel(int n, const double* w, int k, double* Z,
-                                                                         int ldz) {
+__global__ __launch_bounds__(SG_NT) void stein_unresolved_project_kernel(Dim nD, const double* w, Dim kD,
+                                                                         const int* dd, double* Z) {
+  const int n = dim_val(nD, dd), k = min(dim_val(kD, dd), n), ldz = n;
+  if ((int)blockIdx.x >= k) return;
   __shared__ int cols[512];
   __shared__ double yl[512], d[512];
   __shared__ int nres_s;
@@ -2130,7 +2312,10 @@ __global__ __launch_bounds__(SG_NT) void stein_unresolved_project_kernel(int n, 
   for (int r = threadIdx.x; r < n; r += SG_NT) Z[(long long)r * ldz + j] = yl[r];
 }
 
-__global__ __launch_bounds__(SG_NT) void stein_unresolved_kernel(int n, const double* w, int k, double* Z, int ldz) {
+__global__ __launch_bounds__(SG_NT) void stein_unresolved_kernel(Dim nD, const double* w, Dim kD, const int* dd,
+                                                                 double* Z) {
+  const int n = dim_val(nD, dd), k = min(dim_val(kD, dd), n), ldz = n;
+  if (n < 1 || k < 1) return;
   __shared__ int cols[512], ucols[512];
   __shared__ double D[UP * UC], S[UC * UC];
   __shared__ double zl[512], dots[512];
@@ -2195,86 +2380,92 @@ TridWork trid_work(double* work, int n) {
   return t;
 }
 
-int trid_coresident_workgroups(int n) { return n <= 128 ? 0 : (n <= 256 ? 16 : 32); }
+int trid_coresident_workgroups(int n_max) { return n_max <= 128 ? 0 : (n_max <= 256 ? 16 : 32); }
 
 void trid_set_wait_ticks(long long ticks) {
-  g_trm_wait_ticks.store(ticks > 0 ? ticks : TRM_WAIT_TICKS, std::memory_order_relaxed);
+  const long long v = ticks > 0 ? ticks : TRM_WAIT_TICKS;
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(d_trm_wait_ticks), &v, sizeof(v));
 }
 
-hipError_t trid_reduce(double* G, int ldg, int n, const TridWork& t, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  if (n > 512 || ldg < n) return hipErrorInvalidValue;
+// Every form whose order range meets 1..n.hi is launched; each leaves at
+// once unless the order read on the device is in its range, so the launch
+// sequence does not depend on the order.
+hipError_t trid_reduce(double* G, int ldg, Dim n, const TridWork& t, hipStream_t s, const int* dd) {
+  if (n.hi <= 0) return hipSuccess;
+  if (n.hi > 512 || ldg < n.hi || (n.idx >= 0 && !dd)) return hipErrorInvalidValue;
   double2* g2 = reinterpret_cast<double2*>(G);
   double2* tau = reinterpret_cast<double2*>(t.tau);
   double2* vt = reinterpret_cast<double2*>(t.Vt);
-  if (n <= 64) hipLaunchKernelGGL(hetrd_kernel<16>, dim3(1), dim3(TRD_NT), 0, s, g2, ldg, n, t.d, t.e, tau, vt);
-  else if (n <= 128) hipLaunchKernelGGL(hetrd_kernel<8>, dim3(1), dim3(TRD_NT), 0, s, g2, ldg, n, t.d, t.e, tau, vt);
-  else {
-    // launch generation tag of the multi-workgroup form (never 0)
-    static std::atomic<unsigned> next_gen{1};
-    unsigned gen = next_gen.fetch_add(1, std::memory_order_relaxed);
-    if (gen == 0) gen = next_gen.fetch_add(1, std::memory_order_relaxed);
+  hipLaunchKernelGGL(hetrd_kernel<16>, dim3(1), dim3(TRD_NT), 0, s, g2, ldg, n, dd, 1, t.d, t.e, tau, vt);
+  if (n.hi > 64)
+    hipLaunchKernelGGL(hetrd_kernel<8>, dim3(1), dim3(TRD_NT), 0, s, g2, ldg, n, dd, 65, t.d, t.e, tau, vt);
+  if (n.hi > 128) {
     auto* abortw = reinterpret_cast<unsigned long long*>(t.sync);
     double* mail = t.sync + 16;
-    // the mailboxes start at the sentinel (a fill kernel: no memset node)
-    const long long cnt = (long long)4 * n * n;
+    // the mailboxes start at the sentinel and the abort word at zero (a fill
+    // kernel: no memset node in a captured graph)
+    const long long cnt = (long long)4 * n.hi * n.hi;
     hipLaunchKernelGGL(trm_clear_kernel, dim3((unsigned)std::min<long long>((cnt + 255) / 256, 1024)), dim3(256), 0, s,
-                       reinterpret_cast<unsigned long long*>(mail), cnt);
+                       reinterpret_cast<unsigned long long*>(mail), cnt, abortw);
     hipError_t ce = hipGetLastError();
     if (ce != hipSuccess) return ce;
-    const long long ticks = g_trm_wait_ticks.load(std::memory_order_relaxed);
-    if (n <= 256)
-      hipLaunchKernelGGL((hetrd_mc_kernel<16, 2>), dim3(16), dim3(TRM_NT), 0, s, g2, ldg, n, t.d, t.e, tau, vt, mail,
-                         abortw, gen, ticks);
+    if (n.hi <= 256)
+      hipLaunchKernelGGL((hetrd_mc_kernel<16, 2>), dim3(16), dim3(TRM_NT), 0, s, g2, ldg, n, dd, 129, t.d, t.e, tau,
+                         vt, mail, abortw, 1u);
     else
-      hipLaunchKernelGGL((hetrd_mc_kernel<32, 2>), dim3(32), dim3(TRM_NT), 0, s, g2, ldg, n, t.d, t.e, tau, vt, mail,
-                         abortw, gen, ticks);
+      hipLaunchKernelGGL((hetrd_mc_kernel<32, 2>), dim3(32), dim3(TRM_NT), 0, s, g2, ldg, n, dd, 129, t.d, t.e, tau,
+                         vt, mail, abortw, 1u);
   }
   return hipGetLastError();
 }
 
-hipError_t trid_eigenvalues(int n, const TridWork& t, double* w, hipStream_t s) {
-  hipLaunchKernelGGL(stebz_kernel, dim3(n), dim3(STEBZ_NT), 0, s, t.d, t.e, n, w, n);
+hipError_t trid_eigenvalues(Dim n, const TridWork& t, double* w, hipStream_t s, const int* dd) {
+  if (n.hi <= 0) return hipSuccess;
+  hipLaunchKernelGGL(stebz_kernel, dim3(n.hi), dim3(STEBZ_NT), 0, s, t.d, t.e, n, dd, w);
   return hipGetLastError();
 }
 
-hipError_t trid_vectors(int n, const TridWork& t, const double* w, int kvec, hipStream_t s) {
-  if (kvec <= 0) return hipSuccess;
+hipError_t trid_vectors(Dim n, const TridWork& t, const double* w, Dim kvec, hipStream_t s, const int* dd) {
+  const int kmax = std::min(kvec.hi, n.hi);
+  if (kmax <= 0) return hipSuccess;
   // threads per workgroup so that four n-long arrays per thread fit in 128 KB of LDS
   int tpb = 64;
-  while (tpb > 1 && 4LL * n * tpb * 8 > 131072) tpb >>= 1;
-  const size_t lds = (size_t)4 * n * tpb * 8;
-  hipLaunchKernelGGL(stein_kernel, dim3((kvec + tpb - 1) / tpb), dim3(tpb), lds, s, t.d, t.e, n, w, kvec, t.Z, n);
+  while (tpb > 1 && 4LL * n.hi * tpb * 8 > 131072) tpb >>= 1;
+  const size_t lds = (size_t)4 * n.hi * tpb * 8;
+  hipLaunchKernelGGL(stein_kernel, dim3((kmax + tpb - 1) / tpb), dim3(tpb), lds, s, t.d, t.e, n, w, kvec, dd, t.Z);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(stein_groups_kernel, dim3(kvec), dim3(SG_NT), 0, s, n, t.d, t.e, w, kvec, 1e-8, t.Z, n);
+  hipLaunchKernelGGL(stein_groups_kernel, dim3(kmax), dim3(SG_NT), 0, s, n, t.d, t.e, w, kvec, dd, 1e-8, t.Z);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(stein_unresolved_project_kernel, dim3(kvec), dim3(SG_NT), 0, s, n, w, kvec, t.Z, n);
+  hipLaunchKernelGGL(stein_unresolved_project_kernel, dim3(kmax), dim3(SG_NT), 0, s, n, w, kvec, dd, t.Z);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(stein_unresolved_kernel, dim3(1), dim3(SG_NT), 0, s, n, w, kvec, t.Z, n);
+  hipLaunchKernelGGL(stein_unresolved_kernel, dim3(1), dim3(SG_NT), 0, s, n, w, kvec, dd, t.Z);
   return hipGetLastError();
 }
 
-hipError_t trid_backtransform(int n, const TridWork& t, int kvec, double* U, int ldu, hipStream_t s) {
-  if (kvec <= 0) return hipSuccess;
-  const dim3 grid((kvec + 3) / 4);
-  const int B = orm_wy_b(n <= 256 ? 256 : 512);
-  const int nblk = (n - 1 + B - 1) / B;
+hipError_t trid_backtransform(Dim n, const TridWork& t, Dim kvec, double* U, int ldu, hipStream_t s,
+                              const int* dd) {
+  const int kmax = std::min(kvec.hi, n.hi);
+  if (kmax <= 0) return hipSuccess;
+  const dim3 grid((kmax + 3) / 4);
+  const int nh = n.hi;
+  const int B = orm_wy_b(nh <= 256 ? 256 : 512);
+  const int nblk = (nh - 1 + B - 1) / B;
   if (nblk > 0) {
-    if (n <= 64) hipLaunchKernelGGL((orm_t_kernel<16, 64>), dim3(nblk), dim3(512), 0, s, t.Vt, t.tau, n, t.wy);
-    else if (n <= 128) hipLaunchKernelGGL((orm_t_kernel<16, 128>), dim3(nblk), dim3(512), 0, s, t.Vt, t.tau, n, t.wy);
-    else if (n <= 256) hipLaunchKernelGGL((orm_t_kernel<16, 256>), dim3(nblk), dim3(512), 0, s, t.Vt, t.tau, n, t.wy);
-    else hipLaunchKernelGGL((orm_t_kernel<8, 512>), dim3(nblk), dim3(512), 0, s, t.Vt, t.tau, n, t.wy);
+    if (nh <= 64) hipLaunchKernelGGL((orm_t_kernel<16, 64>), dim3(nblk), dim3(512), 0, s, t.Vt, t.tau, n, dd, t.wy);
+    else if (nh <= 128) hipLaunchKernelGGL((orm_t_kernel<16, 128>), dim3(nblk), dim3(512), 0, s, t.Vt, t.tau, n, dd, t.wy);
+    else if (nh <= 256) hipLaunchKernelGGL((orm_t_kernel<16, 256>), dim3(nblk), dim3(512), 0, s, t.Vt, t.tau, n, dd, t.wy);
+    else hipLaunchKernelGGL((orm_t_kernel<8, 512>), dim3(nblk), dim3(512), 0, s, t.Vt, t.tau, n, dd, t.wy);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (n <= 64)
-    hipLaunchKernelGGL((ormtr_wy_kernel<16, 64>), grid, dim3(256), 0, s, t.Vt, t.wy, n, t.Z, n, kvec, U, ldu);
-  else if (n <= 128)
-    hipLaunchKernelGGL((ormtr_wy_kernel<16, 128>), grid, dim3(256), 0, s, t.Vt, t.wy, n, t.Z, n, kvec, U, ldu);
-  else if (n <= 256)
-    hipLaunchKernelGGL((ormtr_wy_kernel<16, 256>), grid, dim3(256), 0, s, t.Vt, t.wy, n, t.Z, n, kvec, U, ldu);
-  else hipLaunchKernelGGL((ormtr_wy_kernel<8, 512>), grid, dim3(256), 0, s, t.Vt, t.wy, n, t.Z, n, kvec, U, ldu);
+  if (nh <= 64)
+    hipLaunchKernelGGL((ormtr_wy_kernel<16, 64>), grid, dim3(256), 0, s, t.Vt, t.wy, n, t.Z, kvec, dd, U, ldu);
+  else if (nh <= 128)
+    hipLaunchKernelGGL((ormtr_wy_kernel<16, 128>), grid, dim3(256), 0, s, t.Vt, t.wy, n, t.Z, kvec, dd, U, ldu);
+  else if (nh <= 256)
+    hipLaunchKernelGGL((ormtr_wy_kernel<16, 256>), grid, dim3(256), 0, s, t.Vt, t.wy, n, t.Z, kvec, dd, U, ldu);
+  else hipLaunchKernelGGL((ormtr_wy_kernel<8, 512>), grid, dim3(256), 0, s, t.Vt, t.wy, n, t.Z, kvec, dd, U, ldu);
   return hipGetLastError();
 }
 
@@ -2304,26 +2495,28 @@ static int ns_splits(int M, int N, int K, const void* ws) {
   return std::max(1, std::min(32 / tiles, K / 64));
 }
 
-hipError_t orthonormalize_columns(double* U, int ldu, int n, int k, double* S, double* T, int iters, void* ws,
-                                  hipStream_t s) {
+hipError_t orthonormalize_columns(double* U, int ldu, Dim n, Dim k, double* S, double* T, int iters, void* ws,
+                                  hipStream_t s, const int* dd) {
   for (int it = 0; it < iters; ++it) {
     Gemm g;
     g.M = k; g.N = k; g.K = n;
     g.A = U; g.sa_m = 1; g.sa_k = ldu; g.conjA = 1;
     g.B = U; g.sb_k = ldu; g.sb_n = 1;
     g.C = S; g.sc_m = k; g.sc_n = 1;
-    g.splits = ns_splits(k, k, n, ws); g.ws = ws;
+    g.splits = ns_splits(k.hi, k.hi, n.hi, ws); g.ws = ws;
+    g.dd = dd;
     hipError_t e = gemm(g, s);
     if (e != hipSuccess) return e;
-    if ((e = newton_schulz_blend(S, k, s)) != hipSuccess) return e;
+    if ((e = newton_schulz_blend(S, k, s, dd)) != hipSuccess) return e;
     Gemm h;
     h.M = n; h.N = k; h.K = k;
     h.A = U; h.sa_m = ldu; h.sa_k = 1;
     h.B = S; h.sb_k = k; h.sb_n = 1;
     h.C = T; h.sc_m = k; h.sc_n = 1;
-    h.splits = ns_splits(n, k, k, ws); h.ws = ws;
+    h.splits = ns_splits(n.hi, k.hi, k.hi, ws); h.ws = ws;
+    h.dd = dd;
     if ((e = gemm(h, s)) != hipSuccess) return e;
-    if ((e = copy_cols(T, k, U, ldu, n, k, nullptr, s)) != hipSuccess) return e;
+    if ((e = copy_cols(T, k, U, ldu, n, k, nullptr, s, dd)) != hipSuccess) return e;
   }
   return hipSuccess;
 }

@@ -58,6 +58,29 @@ def test_heev_parity(n, method):
     assert np.abs(U @ np.diag(w) @ U.conj().T - G).max() <= 1e-12 * scale
 
 
+@pytest.mark.parametrize("method", ["jacobi", "tridiag"])
+def test_heev_indefinite_zero_diagonal(method):
+    """Indefinite Hermitian input whose coupled pair has both diagonal entries
+    zero, [[1,0,0],[0,0,z],[0,conj(z),0]]: eigenvalues 1, |z|, -|z|.  The
+    Jacobi pass must rotate that pair (its skip rule looks at the off-diagonal
+    entry, not at the diagonal)."""
+    api = _api()
+    z = 0.6 - 0.8j
+    G = np.array([[1, 0, 0], [0, 0, z], [0, np.conj(z), 0]], complex)
+    w, U, _ = api.kernel_heev(G, method)
+    assert np.abs(w - np.array([1.0, 1.0, -1.0])).max() <= 1e-14
+    assert np.abs(U.conj().T @ U - np.eye(3)).max() < 1e-14
+    assert np.abs(G @ U - U * w).max() <= 1e-14
+    rng = np.random.Generator(np.random.PCG64(wl.SEED + 29))
+    A = rng.standard_normal((24, 24)) + 1j * rng.standard_normal((24, 24))
+    H = A + A.conj().T
+    H[np.arange(24), np.arange(24)] = 0.0
+    w, U, _ = api.kernel_heev(H, method)
+    ref = np.linalg.eigvalsh(H)[::-1]
+    assert np.abs(w - ref).max() <= 1e-13 * np.abs(ref).max()
+    assert np.abs(H @ U - U * w).max() <= 1e-12 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("n", [40, 200])
 def test_heev_tridiag_graded_and_clustered(n):
     """Geometric spectrum (as in the zip-up Gram matrices) with an exactly
