@@ -16,14 +16,19 @@ FP32 accumulation) and every Gram matrix, factorisation, truncation weight
 and trace in FP64.  A few steps of the plain FP64 form are timed beside it,
 and the CPU oracle (NumPy/LAPACK) on a bounded sample of the same workload.
 
-The serving leg runs a seeded subsample of the parameter-sweep request
-stream (two-photon cat, cat + buffer, driven transmon; Fock sizes 64-4096,
+The serving leg runs the seeded parameter-sweep request stream (512
+requests: two-photon cat, cat + buffer, driven transmon; Fock sizes 64-4096,
 bond caps 32-256, 100 steps each) through the library's continuous-batching
 loop (include/lindblad_serve.h): a burst (every request at t = 0) gives
 solves/s, a Poisson stream at 0.7 x that rate gives the p50/p99 latency from
-arrival to completion, both against the same requests solved one at a time in
-plain FP64.  The host-side Kraus-MPO builds (once per request) are done
-before the timed runs and reported separately.
+arrival to completion; the plain-FP64 one-at-a-time baseline runs on a seeded
+subsample (its first --serve-baseline-requests requests) with the same
+arrivals.  The host-side Kraus-MPO builds (once per request) are done before
+the timed runs and reported separately.
+
+The chi = 256 leg steps the driven transmon + resonator (22 sites, chi_mu =
+32) from a seeded state saturated at the caps and checks that the bonds stay
+at the cap.  The CPU oracle runs on all host cores and on one core.
 
 Prints one JSON line.  --gpus above 1 is not supported (one GPU).
 """
@@ -172,13 +177,14 @@ def serve_once(built, slots: int, budget: int, arrivals):
     return res, st
 
 
-def serving(n_req: int, slots: int, budget_gb: float) -> dict:
+def serving(n_req: int, slots: int, budget_gb: float, n_base: int) -> dict:
     import numpy as np
     import workload as wl
     reqs = wl.serving_requests(512)[:n_req]
+    n_base = min(n_base, n_req)
     t0 = time.perf_counter()
     fast = build_requests(reqs, "fp32")
-    plain = build_requests(reqs, "fp64")
+    plain = build_requests(reqs[:n_base], "fp64")
     build_s = time.perf_counter() - t0
     budget = int(budget_gb * (1 << 30))
     # burst: every request at t = 0
@@ -189,13 +195,14 @@ def serving(n_req: int, slots: int, budget_gb: float) -> dict:
     arr = wl.poisson_arrivals(n_req, rate)
     res_p, st_p = serve_once(fast, slots, budget, arr)
     lat = np.array([r["done"] - r["arrival"] for r in res_p])
-    # the same requests one at a time in plain FP64, same arrivals
-    res_b, st_b = serve_once(plain, 1, 0, arr)
+    # the baseline subsample one at a time in plain FP64, same arrivals
+    res_b, st_b = serve_once(plain, 1, 0, arr[:n_base])
     lat_b = np.array([r["done"] - r["arrival"] for r in res_b])
     svc_b = np.array([r["done"] - r["admitted"] for r in res_b])
     # observables of the two forms (FP32 contractions vs plain FP64)
-    dev = max(abs(a - b) / max(1.0, abs(b)) for r1, r2 in zip(res_p, res_b)
+    dev = max(abs(a - b) / max(1.0, abs(b)) for r1, r2 in zip(res_p[:n_base], res_b)
               for a, b in zip(r1["observables"], r2["observables"]))
+    svc_f = np.array([r["done"] - r["admitted"] for r in res_p])
     for _, s, _ in fast + plain:
         s.close()
     fam = {}
@@ -208,36 +215,68 @@ def serving(n_req: int, slots: int, budget_gb: float) -> dict:
         "burst_peak_gb": st["peak_bytes"] / (1 << 30),
         "poisson_rate_per_s": rate, "poisson_solves_per_s": n_req / st_p["makespan"],
         "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+        "service_p50_s": float(np.percentile(svc_f, 50)), "service_p99_s": float(np.percentile(svc_f, 99)),
         "baseline_fp64_one_at_a_time": {
-            "solves_per_s": n_req / st_b["makespan"],
+            "requests": n_base, "sample": f"the first {n_base} requests of the stream, same arrival times",
+            "solves_per_s": n_base / st_b["makespan"],
             "p50_s": float(np.percentile(lat_b, 50)), "p99_s": float(np.percentile(lat_b, 99)),
             "service_p50_s": float(np.percentile(svc_b, 50)), "service_p99_s": float(np.percentile(svc_b, 99))},
-        "solves_per_s_vs_baseline": burst / (n_req / st_b["makespan"]),
+        "solves_per_s_vs_baseline": burst / (n_base / st_b["makespan"]),
         "max_rel_observable_diff_fp32_vs_fp64": dev,
     }
 
 
-def cpu_baseline(budget_s: float) -> dict:
-    """The oracle as it stands, on the same workload, for a bounded sample."""
-    import numpy as np
-    from threadpoolctl import threadpool_info
+def cpu_baseline(budget_s: float, one_core: bool = False) -> dict:
+    """The oracle as it stands, on the same workload, for a bounded sample;
+    on the host's BLAS threads, or on one core (BLAS limited to one thread)."""
+    import contextlib
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import mps, tt
     m, L, chi, chi_mu, raw = workload()
-    K = tt.KrausMPO(m, m.dt)
-    X, _ = mps.right_canonicalize(raw, tol=1e-14)
-    X, _ = mps.k2_step(X, K.at(0.0), m.tol, chi, chi_mu)       # warm-up step
-    n = 0
-    t0 = time.perf_counter()
-    while True:
-        X, _ = mps.k2_step(X, K.at(n * m.dt), m.tol, chi, chi_mu)
-        n += 1
-        if time.perf_counter() - t0 > budget_s or n >= 50:
-            break
-    dt = time.perf_counter() - t0
-    threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    ctx = threadpool_limits(limits=1) if one_core else contextlib.nullcontext()
+    with ctx:
+        K = tt.KrausMPO(m, m.dt)
+        X, _ = mps.right_canonicalize(raw, tol=1e-14)
+        X, _ = mps.k2_step(X, K.at(0.0), m.tol, chi, chi_mu)       # warm-up step
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            X, _ = mps.k2_step(X, K.at(n * m.dt), m.tol, chi, chi_mu)
+            n += 1
+            if time.perf_counter() - t0 > budget_s or n >= 50:
+                break
+        dt = time.perf_counter() - t0
+        threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
     return {"value": n / dt, "unit": "steps/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{n} steps of the same chi=128 cat+buffer workload (oracle NumPy/LAPACK FP64, "
                       f"{dt:.1f} s), after one warm-up step", "host_cpus": os.cpu_count()}
+
+
+def chi256_leg(steps: int, precision: str) -> dict:
+    """Driven transmon + resonator (charge states -512..511, resonator 4096
+    levels, 22 sites), chi = 256, chi_mu = 32, from a seeded state saturated
+    at the caps: steps/s, and whether the bonds stay at the cap."""
+    import torch
+    import workload as wl
+    from paper_2605_27515_amd import api
+    m = wl.model_transmon_resonator()
+    L, chi, chi_mu = 22, 256, 32
+    raw = wl.synthetic_mps(L, chi_mu, chi)
+    s = api.solver_from_model(m, precision=precision, chi=chi, chi_mu=chi_mu, state="none", device=0)
+    s.set_state_mps(raw)
+    s.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    d = s.diagnostics()
+    s.close()
+    cap = wl.saturated_bonds(L, chi_mu, chi)[1:-1]
+    return {"workload": "driven transmon + resonator, 2^10 charges x 2^12 Fock (22 sites), chi=256, chi_mu=32, "
+                        "tol=1e-8, dt=1.5e-7, seeded saturated MPS", "precision": precision,
+            "steps": steps, "steps_per_s": steps / el, "ms_per_step": 1e3 * el / steps,
+            "bonds": d["bonds"], "cap_bonds": cap, "bonds_at_cap": d["bonds"] == cap, "chi_mu": d["chi_mu"]}
 
 
 def zgate_main(args) -> None:
@@ -371,9 +410,12 @@ def main():
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--fp64-steps", type=int, default=3, help="steps of the plain FP64 form timed beside")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--serve-requests", type=int, default=64,
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests of the seeded serving stream (0: skip the serving leg)")
+    ap.add_argument("--serve-baseline-requests", type=int, default=64,
+                    help="requests of the plain-FP64 one-at-a-time baseline (the stream's first ones)")
+    ap.add_argument("--chi256-steps", type=int, default=3, help="steps of the chi=256 leg (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
     ap.add_argument("--workload", choices=["chi128", "cat-zgate", "chi128-trajectory"], default="chi128",
@@ -417,17 +459,24 @@ def main():
         e64 = gpu_run(args.fp64_steps, 1, "fp64")[0]
         fp64 = args.fp64_steps / e64
         print(f"bench: plain fp64 {fp64:.3f} steps/s", file=sys.stderr, flush=True)
+    c256 = None
+    if args.chi256_steps > 0:
+        c256 = chi256_leg(args.chi256_steps, args.precision)
+        print(f"bench: chi=256 {c256['steps_per_s']:.3f} steps/s, bonds at cap {c256['bonds_at_cap']}",
+              file=sys.stderr, flush=True)
     serve = None
     if args.serve_requests > 0:
-        serve = serving(args.serve_requests, args.serve_slots, args.serve_budget_gb)
+        serve = serving(args.serve_requests, args.serve_slots, args.serve_budget_gb, args.serve_baseline_requests)
         print(f"bench: serving {serve['burst_solves_per_s']:.2f} solves/s (burst), p50 {serve['p50_s']:.3f} s "
               f"p99 {serve['p99_s']:.3f} s; one-at-a-time FP64 "
               f"{serve['baseline_fp64_one_at_a_time']['solves_per_s']:.2f} solves/s", file=sys.stderr, flush=True)
-    cpu = None
+    cpu = cpu1 = None
     if not args.no_cpu:
         cpu = cpu_baseline(args.cpu_seconds)
         print(f"bench: cpu oracle {cpu['value']:.4f} steps/s on {cpu['cores']} threads", file=sys.stderr,
               flush=True)
+        cpu1 = cpu_baseline(args.cpu_seconds, one_core=True)
+        print(f"bench: cpu oracle {cpu1['value']:.4f} steps/s on one core", file=sys.stderr, flush=True)
     total_ms = sum(p["ms"] for p in prof.values())
     line = {
         "metric": METRIC,
@@ -448,7 +497,9 @@ def main():
         "roofline": roofline_entry({dominant: live[dominant]}, args.precision),
         "roofline_contractions": contraction_roofline(prof, args.precision),
         "cpu_baseline": cpu,
+        "cpu_baseline_one_core": cpu1,
         "fp64_plain_steps_per_s": fp64,
+        "chi256": c256,
         "kernel_ms_per_step": {k: v["ms"] / PROFILE_STEPS for k, v in prof.items() if v["launches"]},
         "kernel_share": {k: v["ms"] / total_ms for k, v in prof.items() if v["launches"]} if total_ms else {},
         "final_bonds": diag["bonds"],

@@ -56,12 +56,12 @@ typedef enum lb_status {
 
 enum lb_precision {
   LB_FP64 = 0,          /* every contraction in complex128                       */
-  LB_FP32_CONTRACT = 1  /* MPO/MPS contractions in complex64 (FP32 accumulate);
-                           Gram matrices, eigen-decompositions, truncation
-                           weights and trace in FP64.  The back-sweep and the
-                           purification cut run at max(tol, fp32_tol_floor)
-                           here: complex64 rounding puts noise singular values
-                           near 1e-7 sigma_1                                   */
+  LB_FP32_CONTRACT = 1  /* MPO/MPS contractions of the Kraus MPO's increment
+                           (U1' - 1 and the other members) in complex64 with
+                           FP32 accumulation; its identity channel, Gram
+                           matrices, eigen-decompositions, truncation weights
+                           and trace in FP64.  The complex64 rounding then
+                           sits on the per-step increment only             */
 };
 
 typedef struct lb_config {
@@ -82,14 +82,13 @@ typedef struct lb_config {
   int32_t device;                  /* HIP device ordinal                         */
   double fp32_tol_floor;           /* LB_FP32_CONTRACT only: the back-sweep and
                                       purification cuts use max(tol, this);
-                                      <= 0 selects the default LB_FP32_TOL_FLOOR */
+                                      <= 0: tol as given                        */
   double tau_warn;                 /* a step whose pre-normalisation trace tau
                                       exceeds 1 + tau_warn makes the next
                                       lindblad_sync return LB_WARN_UNSTABLE;
                                       <= 0 selects LB_TAU_WARN                  */
 } lb_config;
 
-#define LB_FP32_TOL_FLOOR 1e-6
 #define LB_TAU_WARN 1e-3
 
 typedef struct lb_solver lb_solver; /* opaque */

@@ -346,6 +346,16 @@ class KrausMPO:
     With a drive H(t) = H0 + f H1 every member is a polynomial of degree <= 2
     in f; the coefficient MPOs are stacked on a 3-dim left boundary index and
     the step contracts it with (1, f, f^2) at f = f(t + h/2).
+
+    The identity in U1' = 1 + Delta is kept as its own MPO channel: the family
+    is stacked with Delta in place of U1', compressed and brought to the
+    canonical gauge (``W``, the increment), and ``at(t)`` returns the sum of
+    the identity chain (last site into Kraus index 0) and W, formed as the
+    direct sum of Sec. 5.1 with the identity block not compressed into the
+    rest.  Compressing 1 + Delta as a whole rounds the increment, which is of
+    order h ||H|| per step, at the tolerance of the identity's norm.  The sum
+    is block diagonal, so sites 1..L-2 stay right-orthonormal; on the last
+    site the identity row and W's rows share Kraus index 0.
     """
 
     def __init__(self, model, dt: float, order: int = 2, tol: float = MPO_TOL):
@@ -354,6 +364,7 @@ class KrausMPO:
         self.dt = dt
         self.order = order
         self.model = model
+        self.n_sites = n
         h = dt
         L = [operator_mpo(j, bits, so, tol) for j in model.jumps]
         G = None
@@ -375,20 +386,22 @@ class KrausMPO:
                 acc = c(mpo_add(acc, x))
             return acc
 
-        # polynomial coefficients (in f) of U1 and U1'
+        # polynomial coefficients (in f) of U1 and of the increment of U1 or U1'
         u1 = [add(eye, mpo_scale(A, -1j * h))]
+        d1 = [c(mpo_scale(A, -1j * h))]
         if drive:
             u1.append(c(mpo_scale(B, -1j * h)))
+            d1.append(u1[1])
         if order == 1:
-            fam = [u1] + [[c(mpo_scale(l, np.sqrt(h)))] for l in L]
+            fam = [d1] + [[c(mpo_scale(l, np.sqrt(h)))] for l in L]
         else:
             A2 = c(mpo_mul(A, A))
-            u1p = [add(u1[0], mpo_scale(A2, -0.5 * h * h))]
+            dp = [add(d1[0], mpo_scale(A2, -0.5 * h * h))]
             if drive:
                 AB = add(c(mpo_mul(A, B)), c(mpo_mul(B, A)))
-                u1p.append(add(u1[1], mpo_scale(AB, -0.5 * h * h)))
-                u1p.append(c(mpo_scale(c(mpo_mul(B, B)), -0.5 * h * h)))
-            fam = [u1p]
+                dp.append(add(u1[1], mpo_scale(AB, -0.5 * h * h)))
+                dp.append(c(mpo_scale(c(mpo_mul(B, B)), -0.5 * h * h)))
+            fam = [dp]
             s = np.sqrt(h / 2)
             fam += [[c(mpo_scale(c(mpo_mul(p, l)), s)) for p in u1] for l in L]
             fam += [[c(mpo_scale(c(mpo_mul(l, p)), s)) for p in u1] for l in L]
@@ -406,16 +419,31 @@ class KrausMPO:
         else:
             self.W = c(boundary_stack(polys))
 
+    def identity_chain(self) -> list[np.ndarray]:
+        """The identity as an MPO whose last site feeds Kraus index 0, in the
+        canonical gauge of W: sites 1.. right-orthonormal (each 1/sqrt 2 times
+        the 2 x 2 identity), the norm 2^((L-1)/2) on site 0."""
+        n, K = self.n_sites, self.n_kraus
+        out = []
+        for i in range(n):
+            f = 2.0 ** ((n - 1) / 2.0) if i == 0 else 1.0 / np.sqrt(2.0)
+            w = np.zeros((1, 2, 2, K if i == n - 1 else 1), complex)
+            w[0, :, :, 0] = f * np.eye(2)
+            out.append(w)
+        return out
+
     def f(self, t: float) -> float:
         return sum(cc * np.cos(w * t + p) for (cc, w, p) in self.model.drive)
 
     def at(self, t: float) -> list[np.ndarray]:
-        """Kraus MPO for the step starting at t (drive at the midpoint)."""
-        if self.degree == 1:
-            return self.W
-        fm = self.f(t + 0.5 * self.dt)
-        return contract_boundary(self.W, [fm ** p for p in range(self.degree)])
+        """Kraus MPO for the step starting at t (drive at the midpoint): the
+        identity chain and the increment side by side (direct sum)."""
+        inc = self.W
+        if self.degree > 1:
+            fm = self.f(t + 0.5 * self.dt)
+            inc = contract_boundary(self.W, [fm ** p for p in range(self.degree)])
+        return mpo_add(self.identity_chain(), inc)
 
     @property
     def bonds(self) -> list[int]:
-        return mpo_bonds(self.W)
+        return mpo_bonds(self.at(0.0))

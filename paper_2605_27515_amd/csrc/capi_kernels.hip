@@ -8,8 +8,17 @@
 #include "../../include/lindblad_kernels.h"
 #include "kernels.h"
 
+// the engine keeps the thread's last error message (lindblad_last_error)
+void lb_set_last_error(const std::string& msg);
+
 namespace {
-thread_local std::string g_err;
+struct ErrSink {
+  ErrSink& operator=(const std::string& m) {
+    lb_set_last_error(m);
+    return *this;
+  }
+};
+thread_local ErrSink g_err;
 
 struct Dev {
   void* p = nullptr;

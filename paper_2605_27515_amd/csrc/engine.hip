@@ -194,7 +194,7 @@ struct lb_solver {
   double dt = 0.0;
   int n_kraus = 0, degree = 1;
   std::vector<double> drv_c, drv_w, drv_p;
-  lb::Mpo kraus;          // host copy (canonical gauge)
+  lb::Mpo kraus;          // host copy (canonical gauge): identity chain (+) increment
   lb::Mpo kraus_dev;      // as uploaded (site 0 zeroed when a drive refreshes it)
   std::vector<cd> h0;     // boundary coefficients of site 0 (Wt layout, per p)
   std::vector<int> wb;    // MPO bonds wb[0..L]; wb[0] = 1 after the boundary contraction
@@ -212,6 +212,9 @@ struct lb_solver {
 
   // workspace
   DevBuf C, P, T, Bm, G, G2, U2, Uf, U0, V, lam, lam2, ws, info, scratch, ework;
+  // FP32 form: the identity channel of the Kraus MPO, kept apart in FP64 --
+  // its carry C_I (rows x right bond), its P_I = T_I and a complex one
+  DevBuf CI, PI, one;
   // sizes decided on the device (truncation ranks) live in a table that the
   // kernels read, so a step is enqueued without waiting for them; the step's
   // status (tau, max |tau - 1|, error bits) and the discarded weights live on
@@ -259,19 +262,13 @@ using lbk::Prec;
 bool fp32(const lb_solver* s) { return s->cfg.precision == LB_FP32_CONTRACT; }
 int passes(const lb_solver* s) { return fp32(s) ? 1 : 2; }
 
-// Truncation tolerance of the back-sweep and the purification cut.  The FP32
-// form forms T in complex64, so singular values below ~1e-7 sigma_1 are
-// rounding noise there; keeping them (tol = 1e-8 would) grows the bonds to the
-// caps with noise, so these cuts run at no less than 1e-6.  At the
-// purification cut a truncation at t moves rho by ~t^2; at an internal bond
-// of the sweep it moves rho at first order (the partial trace over the
-// purification index keeps cross terms between kept and dropped Schmidt
-// vectors), so the floor costs the FP32 form ~1e-6 of rho per such cut, the
-// size of its contraction rounding.  The zip-up cuts a product whose right
-// part is not orthonormal and keeps tol / 10 (flooring it too cost more).
+// Truncation tolerance of the back-sweep and the purification cut: tol, or
+// for the FP32 form a floor under it when the caller sets one (a guard
+// against complex64 noise singular values; with the identity channel kept in
+// FP64 that noise is of the order of the per-step increment's rounding).
 double eff_tol(const lb_solver* s, double t) {
-  if (!fp32(s)) return t;
-  return std::max(t, s->cfg.fp32_tol_floor > 0.0 ? s->cfg.fp32_tol_floor : LB_FP32_TOL_FLOOR);
+  if (!fp32(s) || !(s->cfg.fp32_tol_floor > 0.0)) return t;
+  return std::max(t, s->cfg.fp32_tol_floor);
 }
 double tau_warn(const lb_solver* s) { return s->cfg.tau_warn > 0.0 ? s->cfg.tau_warn : LB_TAU_WARN; }
 
@@ -581,8 +578,11 @@ void gram_cols(lb_solver* s, const void* A, Prec pa, Dim n, Dim m, Dim lda, doub
 // C = op(A) op(B) with row-major dense operands described by leading dims.
 void mm(lb_solver* s, Dim M, Dim N, Dim K, const void* A, Prec pa, Dim lda, bool adjA,
         const void* B, Prec pb, Dim ldb, bool adjB, void* C, Prec pc, Dim ldc, Prec comp,
-        Dim batch = Dim(1), Dim sa_b = Dim(0), Dim sb_b = Dim(0), Dim sc_b = Dim(0)) {
+        Dim batch = Dim(1), Dim sa_b = Dim(0), Dim sb_b = Dim(0), Dim sc_b = Dim(0), double alpha = 1.0,
+        double beta = 0.0) {
   Gemm g;
+  g.alpha_re = alpha;
+  g.beta_re = beta;
   g.M = M; g.N = N; g.K = K; g.batch = batch;
   g.A = A; g.pa = pa; g.sa_b = sa_b;
   if (adjA) { g.sa_m = 1; g.sa_k = lda; g.conjA = 1; } else { g.sa_m = lda; g.sa_k = 1; }
@@ -798,6 +798,18 @@ void alloc_workspace(lb_solver* s) {
   s->ws.alloc(w.ws, st);
   s->info.alloc(WorkPlan::kSmall, st);
   s->scratch.alloc(w.scratch, st);
+  if (fp32(s)) {
+    // identity channel: C_I (rows x bond) and P_I (rows x 2 bond), FP64
+    int cmax = 1;
+    for (int i = 1; i <= s->L; ++i) cmax = std::max(cmax, s->cap[i]);
+    const size_t ib = (size_t)w.nmax * 2 * cmax * 16;
+    s->CI.alloc(ib, st);
+    s->PI.alloc(ib, st);
+    s->one.alloc(16, st);
+    const double one[2] = {1.0, 0.0};
+    HIPCHK(hipMemcpyAsync(s->one.p, one, sizeof(one), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
   s->dd.alloc(table_bytes(s), st);
   s->stat.alloc(sizeof(lbk::StepStat), st);
   s->disc_dev.alloc((s->L + 1) * sizeof(double), st);
@@ -823,6 +835,11 @@ size_t footprint_bytes(const lb_solver* s) {
   t += 2 * size_class(w.wide) + 2 * size_class(w.lam) + size_class(w.ws) + size_class(WorkPlan::kSmall);
   t += size_class(w.scratch) + size_class(table_bytes(s)) + size_class(sizeof(lbk::StepStat)) +
        size_class((s->L + 1) * sizeof(double));
+  if (fp32(s)) {
+    int cmax = 1;
+    for (int i = 1; i <= s->L; ++i) cmax = std::max(cmax, cap[i]);
+    t += 2 * size_class((size_t)w.nmax * 2 * cmax * 16) + size_class(16);
+  }
   for (const lb::Site& x : s->kraus_dev) {
     const size_t e = (size_t)x.l * 4 * x.r;
     t += size_class(e * 16);
@@ -849,7 +866,8 @@ void release_device(lb_solver* s) {
   s->X.clear();
   s->Xspare.release();
   for (DevBuf* b : {&s->C, &s->P, &s->T, &s->Bm, &s->G, &s->G2, &s->U2, &s->Uf, &s->U0, &s->V, &s->lam,
-                    &s->lam2, &s->ws, &s->info, &s->scratch, &s->ework, &s->dd, &s->stat, &s->disc_dev})
+                    &s->lam2, &s->ws, &s->info, &s->scratch, &s->ework, &s->dd, &s->stat, &s->disc_dev, &s->CI,
+                    &s->PI, &s->one})
     b->release();
   for (auto& b : s->W.d64) b.release();
   for (auto& b : s->W.d32) b.release();
@@ -910,9 +928,21 @@ void refresh_drive(lb_solver* s) {
                                      fp32(s) ? s->W.d32[0].f() : nullptr, count, s->stream));
 }
 
+// Factor of the identity chain's site i (its canonical gauge, see
+// with_identity): 2^((L-1)/2) on site 0, 1/sqrt 2 elsewhere.
+double identity_factor(const lb_solver* s, int i) {
+  if (s->L == 1) return 1.0;
+  return i == 0 ? std::pow(2.0, 0.5 * (s->L - 1)) : std::sqrt(0.5);
+}
+
 void zipup(lb_solver* s) {
   const int L = s->L;
   const bool f32 = fp32(s);
+  // FP32 form: the increment of the Kraus MPO is contracted in complex64, its
+  // identity channel apart in FP64 (T = [T_I | T_inc] by column blocks, the
+  // identity block holding the state itself); the FP64 form applies the
+  // direct sum as one MPO
+  const bool split = f32;
   const Prec pw = f32 ? lbk::F32 : lbk::F64;   // contraction storage / compute precision
   const double tolz = s->cfg.tol_zip > 0 ? s->cfg.tol_zip : s->cfg.tol / 10.0;
   const int zc = s->cfg.chi_zip_cap > 0 ? s->cfg.chi_zip_cap : s->cfg.chi_cap;
@@ -922,8 +952,15 @@ void zipup(lb_solver* s) {
     const Dim zk = dzk(s, i, zh[i]);            // rows of the carry (new left bond)
     const Dim cl = dchi(s, i, cap[i]), cr = dchi(s, i + 1, cap[i + 1]);
     const int wl = s->wb[i], wr = s->wb[i + 1];
-    // stage 1: P[(a', u)][(s, b)] = C[(a', u)][a] X_i[a][(s, b)]
+    const bool last = (i == L - 1);
     s->cls = PC_CONTRACT;
+    if (split) {
+      // identity channel: P_I = g_i C_I X_i, read as T_I[(a', s')][b] (2 zk x cr)
+      mm(s, zk, scaled(cr, 2), cl, i == 0 ? s->one.p : s->CI.p, lbk::F64, cl, false, s->X[i].p, lbk::F64,
+         scaled(cr, 2), false, s->PI.p, lbk::F64, scaled(cr, 2), lbk::F64, Dim(1), Dim(0), Dim(0), Dim(0),
+         identity_factor(s, i));
+    }
+    // stage 1: P[(a', u)][(s, b)] = C[(a', u)][a] X_i[a][(s, b)]
     const void* Pp;
     Prec pp;
     if (i == 0) {
@@ -935,15 +972,31 @@ void zipup(lb_solver* s) {
       Pp = s->P.p;
       pp = pw;
     }
-    // stage 2: T_{a'}[(s', v)][b] = Wt[(s', v)][(u, s)] P_{a'}[(u, s)][b]
+    // stage 2: T_{a'}[(s', v)][b] = Wt[(s', v)][(u, s)] P_{a'}[(u, s)][b]; the
+    // FP32 form's last site goes to an FP64 buffer, where T_I is added into
+    // Kraus index 0
     const void* Wt = f32 ? (const void*)s->W.d32[i].p : (const void*)s->W.d64[i].p;
-    mm(s, Dim(2 * wr), cr, Dim(2 * wl), Wt, pw, Dim(2 * wl), false, Pp, pp, cr, false, s->T.p, pw, cr, pw,
+    void* Tout = (split && last) ? s->Bm.p : s->T.p;
+    const Prec pt = (split && last) ? lbk::F64 : pw;
+    mm(s, Dim(2 * wr), cr, Dim(2 * wl), Wt, pw, Dim(2 * wl), false, Pp, pp, cr, false, Tout, pt, cr, pw,
        zk, Dim(0), scaled(cr, 2 * wl), scaled(cr, 2 * wr));
     const Dim n = scaled(zk, 2);
     const Dim m = scaled(cr, wr);
-    if (i < L - 1) {
+    if (!last) {
       s->cls = PC_SVDGEMM;
-      const Svd sv = left_svd(s, s->T.p, pw, n, m, m, passes(s) == 2, capped(n, zc));
+      Svd sv;
+      if (split) {
+        // G = T_inc T_inc^H + T_I T_I^H
+        const int ldg = n.hi;
+        double* G = s->G.d();
+        gram_rows(s, s->T.p, pw, n, m, m, G, ldg);
+        mm(s, n, n, cr, s->PI.p, lbk::F64, cr, false, s->PI.p, lbk::F64, cr, true, G, lbk::F64, ldg, lbk::F64,
+           Dim(1), Dim(0), Dim(0), Dim(0), 1.0, 1.0);
+        eig_trid(s, G, ldg, n, s->lam.d(), s->U0.d(), capped(n, zc));
+        sv = Svd{s->U0.d(), nullptr};
+      } else {
+        sv = left_svd(s, s->T.p, pw, n, m, m, passes(s) == 2, capped(n, zc));
+      }
       const int ldu = n.hi;
       {
         Timed tm(s, PC_OTHER, 0.0, s->prof_on ? 8.0 * hv(s, n) : 0.0);
@@ -965,18 +1018,27 @@ void zipup(lb_solver* s) {
       } else {
         s->cls = PC_CONTRACT;
         mm(s, k, m, n, sv.U, lbk::F64, ldu, true, s->T.p, pw, m, false, s->C.p, pw, m, pw);
+        if (split) mm(s, k, cr, n, sv.U, lbk::F64, ldu, true, s->PI.p, lbk::F64, cr, false, s->CI.p, lbk::F64, cr, lbk::F64);
       }
     } else {
       // S2: purification truncation on the (Kraus x purification) columns
+      const void* Tl = s->T.p;
+      Prec pl = pw;
+      if (split) {
+        Timed tm(s, PC_OTHER, 0.0, s->prof_on ? 48.0 * hv(s, n) * hv(s, cr) : 0.0);
+        HIPCHK(lbk::add_cols(s->PI.d(), cr, s->Bm.d(), m, n, cr, s->stream, ddp(s)));
+        Tl = s->Bm.p;
+        pl = lbk::F64;
+      }
       s->cls = PC_SVDGEMM;
       const int ldv = m.hi;
       double* Gc = s->G.d();
-      gram_cols(s, s->T.p, pw, n, m, m, Gc, ldv);
+      gram_cols(s, Tl, pl, n, m, m, Gc, ldv);
       double* V0 = s->U0.d();
       eig_trid(s, Gc, ldv, m, s->lam.d(), V0, passes(s) == 2 ? m : capped(m, s->cfg.chi_mu_cap));
       double* Vf = V0;
-      const void* Asrc = s->T.p;
-      Prec asrc = pw;
+      const void* Asrc = Tl;
+      Prec asrc = pl;
       Dim lda_src = m;
       if (passes(s) == 2) {
         // B' = T V0 (columns sigma_j u_j), G2' = B'^H B', Jacobi -> V2
@@ -1162,6 +1224,47 @@ std::vector<lb::Term> convert_terms(const lb_solver* s, const lb_term* terms, in
   return out;
 }
 
+// The Kraus MPO as the direct sum (MPO addition, block-diagonal bonds) of
+// the identity chain and the increment `inc`, the identity block first.  The
+// identity chain is in inc's canonical gauge: sites 1.. are the 2 x 2
+// identity over sqrt 2 (right-orthonormal), site 0 carries 2^((L-1)/2), and
+// its last site feeds Kraus index 0.  With a drive, site 0's left index is
+// the polynomial index p and the identity sits in p = 0.  One site: the sum.
+lb::Mpo with_identity(const lb::Mpo& inc, int K) {
+  const int n = (int)inc.size();
+  lb::Mpo out(n);
+  if (n == 1) {
+    out[0] = inc[0];
+    for (int o = 0; o < 2; ++o) out[0].at(0, o, o, 0) += cd(1.0, 0.0);
+    return out;
+  }
+  for (int i = 0; i < n; ++i) {
+    const lb::Site& x = inc[i];
+    const double f = (i == 0) ? std::pow(2.0, 0.5 * (n - 1)) : std::sqrt(0.5);
+    if (i == 0) {
+      lb::Site y(x.l, 1 + x.r);
+      for (int a = 0; a < x.l; ++a)
+        for (int o = 0; o < 2; ++o)
+          for (int ii = 0; ii < 2; ++ii) {
+            y.at(a, o, ii, 0) = (a == 0 && o == ii) ? cd(f, 0.0) : cd(0.0, 0.0);
+            for (int b = 0; b < x.r; ++b) y.at(a, o, ii, 1 + b) = x.at(a, o, ii, b);
+          }
+      out[i] = y;
+    } else {
+      const int r = (i == n - 1) ? x.r : 1 + x.r, ro = (i == n - 1) ? 0 : 1;
+      if (i == n - 1 && x.r != K) throw Fail(LB_ERR_STATE, "internal: Kraus index size");
+      lb::Site y(1 + x.l, r);
+      for (int o = 0; o < 2; ++o) y.at(0, o, o, 0) = cd(f, 0.0);
+      for (int a = 0; a < x.l; ++a)
+        for (int o = 0; o < 2; ++o)
+          for (int ii = 0; ii < 2; ++ii)
+            for (int b = 0; b < x.r; ++b) y.at(1 + a, o, ii, ro + b) = x.at(a, o, ii, b);
+      out[i] = y;
+    }
+  }
+  return out;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -1321,21 +1424,28 @@ lb_status lindblad_set_generator(lb_solver* s, const lb_op* H0, const lb_op* H1,
     Mpo eye = mpo_identity(L);
     auto c = [&](const Mpo& m) { return mpo_compress(m, tol); };
     auto add = [&](const Mpo& a, const Mpo& b) { return c(mpo_add(a, b)); };
+    // U1 and the increment of the first member (U1 - 1 or U1' - 1): the
+    // identity is kept as its own MPO channel beside the compressed rest, so
+    // the increment, of order h ||H||, is not rounded at the identity's scale
     std::vector<Mpo> u1{add(eye, mpo_scale(A, cd(0.0, -h)))};
-    if (drive) u1.push_back(c(mpo_scale(B, cd(0.0, -h))));
+    std::vector<Mpo> d1{c(mpo_scale(A, cd(0.0, -h)))};
+    if (drive) {
+      u1.push_back(c(mpo_scale(B, cd(0.0, -h))));
+      d1.push_back(u1[1]);
+    }
     std::vector<std::vector<Mpo>> fam;
     if (s->cfg.order == 1) {
-      fam.push_back(u1);
+      fam.push_back(d1);
       for (auto& l : Lm) fam.push_back({c(mpo_scale(l, std::sqrt(h)))});
     } else {
       Mpo A2 = c(mpo_mul(A, A));
-      std::vector<Mpo> u1p{add(u1[0], mpo_scale(A2, -0.5 * h * h))};
+      std::vector<Mpo> dp{add(d1[0], mpo_scale(A2, -0.5 * h * h))};
       if (drive) {
         Mpo AB = add(c(mpo_mul(A, B)), c(mpo_mul(B, A)));
-        u1p.push_back(add(u1[1], mpo_scale(AB, -0.5 * h * h)));
-        u1p.push_back(c(mpo_scale(c(mpo_mul(B, B)), -0.5 * h * h)));
+        dp.push_back(add(u1[1], mpo_scale(AB, -0.5 * h * h)));
+        dp.push_back(c(mpo_scale(c(mpo_mul(B, B)), -0.5 * h * h)));
       }
-      fam.push_back(u1p);
+      fam.push_back(dp);
       const double sq = std::sqrt(h / 2.0);
       for (auto& l : Lm) {
         std::vector<Mpo> v;
@@ -1358,9 +1468,12 @@ lb_status lindblad_set_generator(lb_solver* s, const lb_op* H0, const lb_op* H1,
       for (auto& f2 : fam) members.push_back(p < (int)f2.size() ? f2[p] : mpo_zero(L));
       polys.push_back(c(kraus_stack(members)));
     }
-    Mpo W = (degree == 1) ? polys[0] : c(boundary_stack(polys));
-    s->kraus = W;
+    Mpo inc = (degree == 1) ? polys[0] : c(boundary_stack(polys));
     s->n_kraus = (int)fam.size();
+    s->kraus = with_identity(inc, s->n_kraus);
+    // the FP64 form applies the direct sum as one MPO; the FP32 form applies
+    // the increment in complex64 and the identity channel apart in FP64
+    const Mpo W = fp32(s) ? inc : s->kraus;
     s->degree = degree;
     s->dt = dt;
     s->drv_c.clear(); s->drv_w.clear(); s->drv_p.clear();
@@ -1407,7 +1520,7 @@ lb_status lindblad_set_generator(lb_solver* s, const lb_op* H0, const lb_op* H1,
 lb_status lindblad_kraus_info(const lb_solver* s, int32_t* bonds, int32_t* n_kraus) {
   if (!s || !s->have_gen) { g_last_error = "no generator"; return LB_ERR_STATE; }
   if (bonds)
-    for (int k = 0; k + 1 < s->L; ++k) bonds[k] = s->wb[k + 1];
+    for (int k = 0; k + 1 < s->L; ++k) bonds[k] = s->kraus[k].r;
   if (n_kraus) *n_kraus = s->n_kraus;
   return LB_OK;
 }
@@ -1858,5 +1971,11 @@ lb_status lindblad_kraus_site(const lb_solver* s, int32_t site, int32_t* l, int3
 }
 
 const char* lindblad_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+void lb_set_last_error(const std::string& msg) { g_last_error = msg; }
+
+extern "C" {
 
 }  // extern "C"

@@ -140,6 +140,10 @@ hipError_t truncate_rank(const double* lam, Dim n, double tol, int cap, int* k_o
 hipError_t copy_cols(const double* src, Dim lds, double* dst, Dim ldd, Dim rows, Dim cols,
                      const double* lam, hipStream_t stream, const int* dd = nullptr);
 
+// dst[i*ldd + j] += src[i*lds + j] for i < rows, j < cols (complex128).
+hipError_t add_cols(const double* src, Dim lds, double* dst, Dim ldd, Dim rows, Dim cols, hipStream_t stream,
+                    const int* dd = nullptr);
+
 // dst[j*ldd + c] = src[j*lds + c] / sqrt(lam_j) for j < rows, c < cols
 // (rows with lam_j <= 0 are zeroed).
 hipError_t scale_rows_inv_sqrt(const double* src, Dim lds, double* dst, Dim ldd, Dim rows, Dim cols,

@@ -582,6 +582,28 @@ hipError_t copy_cols(const double* src, Dim lds, double* dst, Dim ldd, Dim rows,
   return hipGetLastError();
 }
 
+__global__ void add_cols_kernel(const double* src, Dim ldsD, double* dst, Dim lddD, Dim rowsD, Dim colsD,
+                                const int* dd) {
+  const long long lds = dim_val(ldsD, dd), ldd = dim_val(lddD, dd);
+  const int rows = dim_val(rowsD, dd), cols = dim_val(colsD, dd);
+  const long long total = (long long)rows * cols;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / cols), j = (int)(e % cols);
+    dst[2 * ((long long)i * ldd + j)] += src[2 * ((long long)i * lds + j)];
+    dst[2 * ((long long)i * ldd + j) + 1] += src[2 * ((long long)i * lds + j) + 1];
+  }
+}
+
+hipError_t add_cols(const double* src, Dim lds, double* dst, Dim ldd, Dim rows, Dim cols, hipStream_t s,
+                    const int* dd) {
+  const long long total = (long long)rows.hi * cols.hi;
+  if (total <= 0) return hipSuccess;
+  const int blocks = (int)std::min<long long>((total + 255) / 256, 2048);
+  hipLaunchKernelGGL(add_cols_kernel, dim3(blocks), dim3(256), 0, s, src, lds, dst, ldd, rows, cols, dd);
+  return hipGetLastError();
+}
+
 __global__ void scale_rows_kernel(const double* src, Dim ldsD, double* dst, Dim lddD, Dim rowsD, Dim colsD,
                                   const double* lam, const int* dd) {
   const long long lds = dim_val(ldsD, dd), ldd = dim_val(lddD, dd);
