@@ -35,6 +35,21 @@ lb_status lindblad_kernel_zgemm(int32_t M, int32_t N, int32_t K, const double* A
 lb_status lindblad_kernel_heev(int32_t n, const double* G, double* w, double* U, int32_t* sweeps,
                                int32_t method);
 
+/* The same eigen-decomposition for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): G, w and U are device pointers owned by the caller (G,
+ * n x n complex, is only read; w receives n doubles, U n x n complex), the
+ * work runs on `stream` (a hipStream_t; NULL is the null stream) and the call
+ * waits for it before returning.  Its scratch is a static device array of
+ * about 8 MB per GPU, kept until the process ends, so n is limited to
+ * LB_NOALLOC_MAX_N; the call makes no device allocation.  Calls that overlap
+ * on one GPU (from several threads) share that array and race: serialise
+ * them.  Results equal lindblad_kernel_heev's.  Errors: LB_ERR_ARG (n out of
+ * 1..LB_NOALLOC_MAX_N, NULL, bad method), LB_ERR_HIP. */
+#define LB_NOALLOC_MAX_N 256
+lb_status lindblad_kernel_heev_noalloc(int32_t n, const double* G, double* w, double* U, int32_t* sweeps,
+                                       int32_t method, void* stream);
+
 /* Bound of the waits of the multi-workgroup Householder reduction (orders
  * 129..512), whose workgroups wait on each other's posted values every step,
  * in ticks of the GPU's 100 MHz wall clock; ticks <= 0 restores the default

@@ -29,7 +29,7 @@ EXPORTED = ["lindblad_default_config", "lindblad_create", "lindblad_destroy",
             "lindblad_get_state_mps", "lindblad_step", "lindblad_sync", "lindblad_step_batch",
             "lindblad_observe", "lindblad_trace_purity", "lindblad_diagnostics",
             "lindblad_last_error", "lindblad_profile", "lindblad_profile_mask", "lindblad_profile_read", "lindblad_kernel_zgemm", "lindblad_kernel_heev",
-            "lindblad_kernel_truncate", "lindblad_kernel_set_wait_limit", "lindblad_get_config", "lindblad_footprint", "lindblad_release",
+            "lindblad_kernel_truncate", "lindblad_kernel_set_wait_limit", "lindblad_kernel_heev_noalloc", "lindblad_get_config", "lindblad_footprint", "lindblad_release",
             "lindblad_server_create", "lindblad_server_submit", "lindblad_server_run",
             "lindblad_server_result", "lindblad_server_stats", "lindblad_server_destroy"]
 
@@ -137,6 +137,7 @@ def load() -> C.CDLL:
     lib.lindblad_kernel_zgemm.argtypes = [C.c_int32, C.c_int32, C.c_int32, dp, C.c_int32, dp, C.c_int32,
                                           dp, C.c_int32, C.c_int32]
     lib.lindblad_kernel_heev.argtypes = [C.c_int32, dp, dp, dp, C.POINTER(C.c_int32), C.c_int32]
+    lib.lindblad_kernel_heev_noalloc.argtypes = [C.c_int32, vp, vp, vp, C.POINTER(C.c_int32), C.c_int32, vp]
     lib.lindblad_kernel_truncate.argtypes = [C.c_int32, dp, C.c_double, C.c_int32, C.POINTER(C.c_int32), dp]
     lib.lindblad_kernel_set_wait_limit.argtypes = [C.c_int64]
     lib.lindblad_profile.argtypes = [vp, C.c_int32]

@@ -357,6 +357,19 @@ def kernel_heev(G: np.ndarray, method: str = "jacobi"):
     return w, U, sw.value
 
 
+def kernel_heev_noalloc(n: int, g_ptr: int, w_ptr: int, u_ptr: int, method: str = "tridiag",
+                        stream: int = 0) -> int:
+    """lindblad_kernel_heev_noalloc on caller-owned device buffers (device
+    addresses, e.g. torch's data_ptr()): G (n x n complex, read), w (n
+    doubles) and U (n x n complex) written.  Returns the sweep count."""
+    sw = C.c_int32()
+    _check(L.load().lindblad_kernel_heev_noalloc(int(n), C.c_void_p(g_ptr), C.c_void_p(w_ptr), C.c_void_p(u_ptr),
+                                                 C.byref(sw), 1 if method == "tridiag" else 0,
+                                                 C.c_void_p(stream) if stream else None),
+           "kernel_heev_noalloc")
+    return sw.value
+
+
 def kernel_set_wait_limit(ticks: int):
     """Bound (100 MHz wall-clock ticks; <= 0: default 2 s) of the waits of the
     multi-workgroup Householder reduction (include/lindblad_kernels.h)."""

@@ -2,6 +2,7 @@
 // per call on host data, for isolated parity tests of the device kernels.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -113,6 +114,104 @@ lb_status lindblad_kernel_heev(int32_t n, const double* G, double* w, double* U,
   } while (0);
   (void)hipStreamSynchronize(s);
   (void)hipStreamDestroy(s);
+  return rc;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Scratch of lindblad_kernel_heev_noalloc: a file-scope device array (one
+// copy per GPU, held until the process ends) for orders up to
+// LB_NOALLOC_MAX_N.  Host code never passes the array's name to a kernel:
+// the device address of each GPU's copy is looked up once, with that device
+// current, and kept.  Layout in doubles: the tridiagonal workspace, then the
+// Newton-Schulz products S and T, the Jacobi copy of G and its rotation
+// accumulator V (each n^2 complex at the maximum order), then the Jacobi
+// sweep count.
+constexpr int kNaN = LB_NOALLOC_MAX_N;
+constexpr size_t kNaWork = 4 * kNaN + 3 * (size_t)kNaN * kNaN + 2 * 16 * (kNaN + 16) + 16 +
+                           (16 + 4 * (size_t)kNaN * kNaN) + 64;
+constexpr size_t kNaMat = 2 * (size_t)kNaN * kNaN;
+constexpr size_t kNaDoubles = kNaWork + 4 * kNaMat + 16;
+__device__ __align__(256) double scratch[kNaDoubles];
+
+double* scratch_ptr(int dev, hipError_t* err) {
+  static std::mutex mu;
+  static double* ptr[64] = {};
+  std::lock_guard<std::mutex> g(mu);
+  if (dev < 0 || dev >= 64) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      *err = (e != hipSuccess) ? e : hipErrorInvalidSymbol;
+      return nullptr;
+    }
+    ptr[dev] = static_cast<double*>(p);
+  }
+  return ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+lb_status lindblad_kernel_heev_noalloc(int32_t n, const double* G, double* w, double* U, int32_t* sweeps,
+                                       int32_t method, void* stream) {
+  if (n <= 0 || !G || !w || !U || (method != 0 && method != 1)) {
+    g_err = "bad argument";
+    return LB_ERR_ARG;
+  }
+  if (n > LB_NOALLOC_MAX_N) {
+    g_err = "order " + std::to_string(n) + " exceeds the static scratch limit " + std::to_string(LB_NOALLOC_MAX_N);
+    return LB_ERR_ARG;
+  }
+  if (lbk::heev_tridiag_work_doubles(kNaN) > kNaWork) {
+    g_err = "internal: tridiagonal workspace larger than its static share";
+    return LB_ERR_HIP;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "device");
+  double* base = scratch_ptr(dev, &e);
+  if (!base) return hip_fail(e, "scratch address");
+  double* work = base;
+  double* S = base + kNaWork;
+  double* T = S + kNaMat;
+  double* Gc = T + kNaMat;
+  double* V = Gc + kNaMat;
+  int* info = reinterpret_cast<int*>(V + kNaMat);
+  const size_t nn = (size_t)n * n;
+  lb_status rc = LB_OK;
+  do {
+    if (method == 1) {
+      // the reduction reads G only; its co-resident workgroups come from the
+      // device's budget until the stream has drained
+      const int held = lbk::reserve_device_cus(dev, lbk::trid_coresident_workgroups(n));
+      e = lbk::heev_tridiag(const_cast<double*>(G), n, n, w, U, n, n, work, s);
+      const hipError_t es = hipStreamSynchronize(s);
+      lbk::release_device_cus(dev, held);
+      if (e == hipSuccess) e = es;
+      if (e != hipSuccess) { rc = hip_fail(e, "heev_tridiag"); break; }
+      if ((e = lbk::orthonormalize_columns(U, n, n, n, S, T, 2, nullptr, s)) != hipSuccess) { rc = hip_fail(e, "orthonormalize"); break; }
+      if (sweeps) *sweeps = 0;
+    } else {
+      // Jacobi rotates its matrix in place: on a copy in the scratch
+      if ((e = hipMemcpyAsync(Gc, G, nn * 16, hipMemcpyDeviceToDevice, s)) != hipSuccess) { rc = hip_fail(e, "copy"); break; }
+      if ((e = lbk::heev_jacobi(Gc, n, 0, n, w, 0, V, 1, lbk::kJacobiRelTol, 40, info, s)) != hipSuccess) { rc = hip_fail(e, "heev"); break; }
+      if ((e = hipMemcpyAsync(U, Gc, nn * 16, hipMemcpyDeviceToDevice, s)) != hipSuccess) { rc = hip_fail(e, "copy"); break; }
+      int h = 0;
+      if ((e = hipMemcpyAsync(&h, info, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess) { rc = hip_fail(e, "copy"); break; }
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) { rc = hip_fail(e, "sync"); break; }
+      if (sweeps) *sweeps = h;
+    }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) { rc = hip_fail(e, "sync"); break; }
+  } while (0);
   return rc;
 }
 
