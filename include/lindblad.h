@@ -57,11 +57,19 @@ typedef enum lb_status {
 enum lb_precision {
   LB_FP64 = 0,          /* every contraction in complex128                       */
   LB_FP32_CONTRACT = 1  /* MPO/MPS contractions of the Kraus MPO's increment
-                           (U1' - 1 and the other members) in complex64 with
-                           FP32 accumulation; its identity channel, Gram
-                           matrices, eigen-decompositions, truncation weights
-                           and trace in FP64.  The complex64 rounding then
-                           sits on the per-step increment only             */
+                           (U1' - 1, the mixed members with U1 - 1 in place
+                           of U1, the L_k L_k' members) in complex64 with
+                           FP32 accumulation; its leading part (the identity
+                           and sqrt(h/2) L_k), Gram matrices,
+                           eigen-decompositions, truncation weights and trace
+                           in FP64, so the complex64 rounding sits on the
+                           O(h) increment only.  Each truncated factorisation
+                           is one tridiagonal eigen-decomposition of the Gram
+                           matrix plus a second one of its spectral tail
+                           (eigenvalues under 1e-6 of the largest), which
+                           resolves the singular values down to ~1e-10 of the
+                           largest that a single pass leaves at its ~1e-7
+                           rounding floor                                  */
 };
 
 typedef struct lb_config {
@@ -74,7 +82,8 @@ typedef struct lb_config {
   int32_t chi_mu_cap;              /* purification rank cap                      */
   int32_t chi_zip_cap;             /* zip-up intermediate cap; 0 = chi_cap       */
   double tol;                      /* relative Frobenius truncation tolerance    */
-  double tol_zip;                  /* zip-up tolerance; <= 0 means tol / 10      */
+  double tol_zip;                  /* zip-up tolerance; <= 0: tol / 10 (LB_FP64),
+                                      tol (LB_FP32_CONTRACT)                    */
   int32_t order;                   /* Kraus scheme order: 1 or 2                 */
   int32_t precision;               /* enum lb_precision                          */
   int32_t allow_unstable;          /* nonzero: skip the dt stability check       */
@@ -200,6 +209,16 @@ lb_status lindblad_set_state_product(lb_solver* s, const double* const* vectors)
  * checkpoints and synthetic states. */
 lb_status lindblad_set_state_mps(lb_solver* s, const int32_t* bonds,
                                  const double* const* sites);
+
+/* Resume from a checkpoint: the MPS that lindblad_get_state_mps exported
+ * (bonds and sites as there), loaded verbatim -- no re-canonicalisation --
+ * with the step counter set to `steps` (t = steps * dt, the drive's clock).
+ * Continuing from it gives, bit for bit, the states the exporting solver
+ * would have produced, when the solver has the same configuration and
+ * generator.  Errors: LB_ERR_ARG (a bond outside the caps, NULL, steps < 0),
+ * LB_ERR_STATE (no generator). */
+lb_status lindblad_restore_state(lb_solver* s, const int32_t* bonds, const double* const* sites,
+                                 int64_t steps);
 
 /* Export the current MPS (synchronises).  bonds: host int32[n_sites+1];
  * if sites != NULL, sites[i] must hold bonds[i]*2*bonds[i+1] complex. */

@@ -347,15 +347,17 @@ class KrausMPO:
     in f; the coefficient MPOs are stacked on a 3-dim left boundary index and
     the step contracts it with (1, f, f^2) at f = f(t + h/2).
 
-    The identity in U1' = 1 + Delta is kept as its own MPO channel: the family
-    is stacked with Delta in place of U1', compressed and brought to the
-    canonical gauge (``W``, the increment), and ``at(t)`` returns the sum of
-    the identity chain (last site into Kraus index 0) and W, formed as the
-    direct sum of Sec. 5.1 with the identity block not compressed into the
-    rest.  Compressing 1 + Delta as a whole rounds the increment, which is of
-    order h ||H|| per step, at the tolerance of the identity's norm.  The sum
-    is block diagonal, so sites 1..L-2 stay right-orthonormal; on the last
-    site the identity row and W's rows share Kraus index 0.
+    The family is split by order in h into a leading part -- the identity in
+    U1' (or U1) and sqrt(h/2) L_k in both mixed members -- and the increment
+    (U1' - 1, sqrt(h/2) (U1 - 1) L_k, sqrt(h/2) L_k (U1 - 1) and the (h/sqrt 2)
+    L_k L_k' members), each stacked on the Kraus index and compressed in its
+    own gauge (``lead``, ``W``).  ``at(t)`` returns their direct sum (the MPO
+    addition of Sec. 5.1 with the two blocks not compressed into each other),
+    which equals the family.  Compressing the family as a whole would round the
+    O(h) increment at the tolerance of the O(1) identity; kept apart, the
+    increment is held to its own relative tolerance.  The sum is block
+    diagonal, so its sites 1..L-2 stay right-orthonormal; on the last site both
+    blocks feed the Kraus index.
     """
 
     def __init__(self, model, dt: float, order: int = 2, tol: float = MPO_TOL):
@@ -386,30 +388,31 @@ class KrausMPO:
                 acc = c(mpo_add(acc, x))
             return acc
 
-        # polynomial coefficients (in f) of U1 and of the increment of U1 or U1'
-        u1 = [add(eye, mpo_scale(A, -1j * h))]
+        zero = [np.zeros((1, 2, 2, 1), complex) for _ in range(n)]
+        # increments (polynomial coefficients in f) of U1 - 1 and U1' - 1
         d1 = [c(mpo_scale(A, -1j * h))]
         if drive:
-            u1.append(c(mpo_scale(B, -1j * h)))
-            d1.append(u1[1])
+            d1.append(c(mpo_scale(B, -1j * h)))
         if order == 1:
-            fam = [d1] + [[c(mpo_scale(l, np.sqrt(h)))] for l in L]
+            lead = [eye] + [c(mpo_scale(l, np.sqrt(h))) for l in L]
+            fam = [d1] + [[zero] for _ in L]
         else:
             A2 = c(mpo_mul(A, A))
             dp = [add(d1[0], mpo_scale(A2, -0.5 * h * h))]
             if drive:
                 AB = add(c(mpo_mul(A, B)), c(mpo_mul(B, A)))
-                dp.append(add(u1[1], mpo_scale(AB, -0.5 * h * h)))
+                dp.append(add(d1[1], mpo_scale(AB, -0.5 * h * h)))
                 dp.append(c(mpo_scale(c(mpo_mul(B, B)), -0.5 * h * h)))
-            fam = [dp]
             s = np.sqrt(h / 2)
-            fam += [[c(mpo_scale(c(mpo_mul(p, l)), s)) for p in u1] for l in L]
-            fam += [[c(mpo_scale(c(mpo_mul(l, p)), s)) for p in u1] for l in L]
+            lead = [eye] + [c(mpo_scale(l, s)) for l in L] * 2 + [zero] * (len(L) ** 2)
+            fam = [dp]
+            fam += [[c(mpo_scale(c(mpo_mul(p, l)), s)) for p in d1] for l in L]
+            fam += [[c(mpo_scale(c(mpo_mul(l, p)), s)) for p in d1] for l in L]
             fam += [[c(mpo_scale(c(mpo_mul(l, lp)), h / np.sqrt(2.0)))]
                     for l in L for lp in L]
         self.n_kraus = len(fam)
         self.degree = max(len(f) for f in fam)
-        zero = [np.zeros((1, 2, 2, 1), complex) for _ in range(n)]
+        self.lead = c(kraus_stack(lead))
         polys = []
         for p in range(self.degree):
             members = [f[p] if p < len(f) else zero for f in fam]
@@ -418,19 +421,6 @@ class KrausMPO:
             self.W = polys[0]
         else:
             self.W = c(boundary_stack(polys))
-
-    def identity_chain(self) -> list[np.ndarray]:
-        """The identity as an MPO whose last site feeds Kraus index 0, in the
-        canonical gauge of W: sites 1.. right-orthonormal (each 1/sqrt 2 times
-        the 2 x 2 identity), the norm 2^((L-1)/2) on site 0."""
-        n, K = self.n_sites, self.n_kraus
-        out = []
-        for i in range(n):
-            f = 2.0 ** ((n - 1) / 2.0) if i == 0 else 1.0 / np.sqrt(2.0)
-            w = np.zeros((1, 2, 2, K if i == n - 1 else 1), complex)
-            w[0, :, :, 0] = f * np.eye(2)
-            out.append(w)
-        return out
 
     def f(self, t: float) -> float:
         return sum(cc * np.cos(w * t + p) for (cc, w, p) in self.model.drive)
@@ -442,7 +432,7 @@ class KrausMPO:
         if self.degree > 1:
             fm = self.f(t + 0.5 * self.dt)
             inc = contract_boundary(self.W, [fm ** p for p in range(self.degree)])
-        return mpo_add(self.identity_chain(), inc)
+        return mpo_add(self.lead, inc)
 
     @property
     def bonds(self) -> list[int]:

@@ -26,7 +26,7 @@ FACTOR_KINDS = {"ID": 0, "A_POW": 1, "ADAG_POW": 2, "ADAG_A": 3, "NUM_POW": 4,
 EXPORTED = ["lindblad_default_config", "lindblad_create", "lindblad_destroy",
             "lindblad_mpo_build", "lindblad_op_info", "lindblad_op_site", "lindblad_set_generator",
             "lindblad_kraus_info", "lindblad_kraus_site", "lindblad_set_state_product", "lindblad_set_state_mps",
-            "lindblad_get_state_mps", "lindblad_step", "lindblad_sync", "lindblad_step_batch",
+            "lindblad_get_state_mps", "lindblad_restore_state", "lindblad_step", "lindblad_sync", "lindblad_step_batch",
             "lindblad_observe", "lindblad_trace_purity", "lindblad_diagnostics",
             "lindblad_last_error", "lindblad_profile", "lindblad_profile_mask", "lindblad_profile_read", "lindblad_kernel_zgemm", "lindblad_kernel_heev",
             "lindblad_kernel_truncate", "lindblad_kernel_set_wait_limit", "lindblad_kernel_heev_noalloc", "lindblad_get_config", "lindblad_footprint", "lindblad_release",
@@ -127,6 +127,7 @@ def load() -> C.CDLL:
     lib.lindblad_set_state_product.argtypes = [vp, C.POINTER(C.POINTER(C.c_double))]
     lib.lindblad_set_state_mps.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.POINTER(C.c_double))]
     lib.lindblad_get_state_mps.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.POINTER(C.c_double))]
+    lib.lindblad_restore_state.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.POINTER(C.c_double)), C.c_int64]
     lib.lindblad_step.argtypes = [vp, C.c_int32]
     lib.lindblad_sync.argtypes = [vp]
     lib.lindblad_step_batch.argtypes = [C.POINTER(vp), C.c_int32, C.c_int32]

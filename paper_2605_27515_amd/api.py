@@ -170,6 +170,15 @@ class Solver:
         ptrs = (C.POINTER(C.c_double) * len(arrs))(*[_dptr(a.view(np.float64)) for a in arrs])
         _check(lib.lindblad_set_state_mps(self.h, b, ptrs), "set_state_mps")
 
+    def restore_state(self, sites, steps: int):
+        """Resume from a checkpoint taken with get_state_mps after `steps` steps."""
+        lib = L.load()
+        arrs = [np.ascontiguousarray(np.asarray(s, np.complex128)) for s in sites]
+        bonds = [1] + [a.shape[2] for a in arrs]
+        b = (C.c_int32 * len(bonds))(*bonds)
+        ptrs = (C.POINTER(C.c_double) * len(arrs))(*[_dptr(a.view(np.float64)) for a in arrs])
+        _check(lib.lindblad_restore_state(self.h, b, ptrs, int(steps)), "restore_state")
+
     def get_state_mps(self) -> list[np.ndarray]:
         lib = L.load()
         b = (C.c_int32 * (self.n_sites + 1))()

@@ -194,10 +194,13 @@ struct lb_solver {
   double dt = 0.0;
   int n_kraus = 0, degree = 1;
   std::vector<double> drv_c, drv_w, drv_p;
-  lb::Mpo kraus;          // host copy (canonical gauge): identity chain (+) increment
+  lb::Mpo kraus;          // host copy: leading part (+) increment (direct sum)
+  lb::Mpo lead;           // leading part (canonical gauge), the FP32 form's FP64 channel
   lb::Mpo kraus_dev;      // as uploaded (site 0 zeroed when a drive refreshes it)
   std::vector<cd> h0;     // boundary coefficients of site 0 (Wt layout, per p)
   std::vector<int> wb;    // MPO bonds wb[0..L]; wb[0] = 1 after the boundary contraction
+  std::vector<int> wlb;   // bonds of the leading part (FP32 form), wlb[0] = 1
+  DevMpo WL;              // device leading part (FP32 form, FP64)
   DevMpo W;               // device Kraus MPO (site 0 is refreshed per step for a drive)
   DevBuf Wb0;             // boundary polynomial coefficients of site 0 (FP64, Wt layout)
   long long wb0_stride = 0;
@@ -212,9 +215,9 @@ struct lb_solver {
 
   // workspace
   DevBuf C, P, T, Bm, G, G2, U2, Uf, U0, V, lam, lam2, ws, info, scratch, ework;
-  // FP32 form: the identity channel of the Kraus MPO, kept apart in FP64 --
-  // its carry C_I (rows x right bond), its P_I = T_I and a complex one
-  DevBuf CI, PI, one;
+  // FP32 form: the leading channel of the Kraus MPO, kept apart in FP64 --
+  // its carry C_L, stage-1 product P_L and stage-2 product T_L
+  DevBuf CL, PL, TL;
   // sizes decided on the device (truncation ranks) live in a table that the
   // kernels read, so a step is enqueued without waiting for them; the step's
   // status (tau, max |tau - 1|, error bits) and the discarded weights live on
@@ -260,6 +263,10 @@ using lbk::Gemm;
 using lbk::Prec;
 
 bool fp32(const lb_solver* s) { return s->cfg.precision == LB_FP32_CONTRACT; }
+
+// MPO bond i of the Kraus MPO as applied: the FP32 form applies its leading
+// part as a channel of its own beside the increment
+int mpo_bond(const lb_solver* s, int i) { return s->wb[i] + (fp32(s) ? s->wlb[i] : 0); }
 int passes(const lb_solver* s) { return fp32(s) ? 1 : 2; }
 
 // Truncation tolerance of the back-sweep and the purification cut: tol, or
@@ -452,6 +459,10 @@ void release_cus_on_error() {
 int sl_chi(const lb_solver*, int i) { return i; }
 int sl_zk(const lb_solver* s, int i) { return s->L + 1 + i; }
 int sl_kb(const lb_solver* s, int i) { return 2 * (s->L + 1) + i; }
+// start and size of the tail of the last decomposition re-resolved by refine_tail
+int sl_tail0(const lb_solver* s) { return 3 * (s->L + 1); }
+int sl_tailk(const lb_solver* s) { return 3 * (s->L + 1) + 1; }
+int table_len(const lb_solver* s) { return 3 * (s->L + 1) + 2; }
 Dim dchi(const lb_solver* s, int i, int hi) { return Dim::dyn(1, sl_chi(s, i), hi); }
 Dim dzk(const lb_solver* s, int i, int hi) { return Dim::dyn(1, sl_zk(s, i), hi); }
 Dim dkb(const lb_solver* s, int i, int hi) { return Dim::dyn(1, sl_kb(s, i), hi); }
@@ -650,6 +661,82 @@ void eig_trid(lb_solver* s, double* G, int ldg, Dim n, double* lam, double* U, D
   }
 }
 
+// One operand block of a Gram matrix: A is (order x len) for a row Gram
+// (G += A A^H), (len x order) for a column Gram (G += A^H A); ld its leading
+// dimension.
+struct GramOp {
+  const void* A;
+  Prec p;
+  Dim ld, len;
+};
+
+// The tail of the spectrum below this fraction of the largest eigenvalue is
+// decomposed a second time (refine_tail).
+constexpr double kTailFraction = 1e-6;
+
+// Re-resolves the tail of a one-pass eigen-decomposition of a Gram matrix G
+// (the FP32 form's single pass).  G = sum_b A_b A_b^H (rows) or
+// sum_b A_b^H A_b (!rows), of order n, was decomposed into lam (descending)
+// and U (n x n, ld ldu, all n columns) by the tridiagonal route, whose
+// absolute accuracy ~eps ||G|| leaves the eigenvalues under ~8 n eps lam_0
+// unresolved -- squared singular values, so singular values under ~1e-7 of
+// the largest, inside the range a truncation at tol = 1e-8 keeps.  The
+// columns of U past the eigenvalues >= kTailFraction lam_0 (at least the
+// last) span the tail; the Gram of the operands projected on it, of norm
+// ~kTailFraction lam_0, is decomposed again, with an accuracy relative to that
+// norm, and its vectors rotate U's tail columns and replace its eigenvalues.
+// The head keeps its vectors: they are all kept by any truncation, so only
+// their span matters, and that the second decomposition completes exactly.
+void refine_tail(lb_solver* s, bool rows, std::initializer_list<GramOp> ops, Dim n, double* U, int ldu,
+                 double* lam) {
+  const int js = sl_tail0(s), ks = sl_tailk(s);
+  const Dim kt = Dim::dyn(1, ks, n.hi);
+  const int ldt = n.hi;
+  {
+    Timed tm(s, PC_OTHER, 0.0, s->prof_on ? 8.0 * hv(s, n) : 0.0);
+    HIPCHK(lbk::tail_split(lam, n, kTailFraction, s->dd.i(), js, ks, s->stream));
+  }
+  // Ut = U[:, j0:]
+  double* Ut = s->Uf.d();
+  {
+    Timed tm(s, PC_OTHER, 0.0, s->prof_on ? 32.0 * hv(s, n) * hv(s, kt) : 0.0);
+    HIPCHK(lbk::copy_block(U, Dim(ldu), js, Ut, Dim(ldt), -1, n, kt, 2, s->stream, ddp(s)));
+  }
+  double* Gt = s->G2.d();
+  double* bufs[2] = {s->U2.d(), s->Bm.d()};
+  int b = 0;
+  for (const GramOp& o : ops) {
+    if (b >= 2) throw Fail(LB_ERR_STATE, "internal: Gram operands");
+    double* B = bufs[b];
+    if (rows) {
+      // B = Ut^H A (kt x len); Gt += B B^H
+      mm(s, kt, o.len, n, Ut, lbk::F64, Dim(ldt), true, o.A, o.p, o.ld, false, B, lbk::F64, o.len, lbk::F64);
+      if (b == 0)
+        gram_rows(s, B, lbk::F64, kt, o.len, o.len, Gt, ldt);
+      else
+        mm(s, kt, kt, o.len, B, lbk::F64, o.len, false, B, lbk::F64, o.len, true, Gt, lbk::F64, Dim(ldt),
+           lbk::F64, Dim(1), Dim(0), Dim(0), Dim(0), 1.0, 1.0);
+    } else {
+      // B = A Ut (len x kt); Gt += B^H B
+      mm(s, o.len, kt, n, o.A, o.p, o.ld, false, Ut, lbk::F64, Dim(ldt), false, B, lbk::F64, kt, lbk::F64);
+      if (b == 0)
+        gram_cols(s, B, lbk::F64, o.len, kt, kt, Gt, ldt);
+      else
+        mm(s, kt, kt, o.len, B, lbk::F64, kt, true, B, lbk::F64, kt, false, Gt, lbk::F64, Dim(ldt), lbk::F64,
+           Dim(1), Dim(0), Dim(0), Dim(0), 1.0, 1.0);
+    }
+    ++b;
+  }
+  double* V = s->V.d();
+  eig_trid(s, Gt, ldt, kt, s->lam2.d(), V, kt);
+  // U[:, j0:] = Ut V, lam[j0:] = the tail's eigenvalues
+  double* Un = s->G.d();
+  mm(s, n, kt, kt, Ut, lbk::F64, Dim(ldt), false, V, lbk::F64, Dim(ldt), false, Un, lbk::F64, Dim(ldt), lbk::F64);
+  Timed tm(s, PC_OTHER, 0.0, s->prof_on ? 32.0 * hv(s, n) * hv(s, kt) + 16.0 * hv(s, kt) : 0.0);
+  HIPCHK(lbk::copy_block(Un, Dim(ldt), -1, U, Dim(ldu), js, n, kt, 2, s->stream, ddp(s)));
+  HIPCHK(lbk::copy_block(s->lam2.d(), Dim(0), -1, lam, Dim(0), js, Dim(1), kt, 1, s->stream, ddp(s)));
+}
+
 // Left singular vectors / squared singular values of the n x m matrix A
 // (row-major, leading dim lda).  U (n x n, leading dimension n.hi; the first
 // kvec columns are valid) is returned and the eigenvalues are left in s->lam.
@@ -669,7 +756,8 @@ Svd left_svd(lb_solver* s, const void* A, Prec pa, Dim n, Dim m, Dim lda, bool w
   gram_rows(s, A, pa, n, m, lda, G, ldg);
   double* U0 = s->U0.d();
   if (passes(s) == 1) {
-    eig_trid(s, G, ldg, n, s->lam.d(), U0, kvec);
+    eig_trid(s, G, ldg, n, s->lam.d(), U0, n);
+    refine_tail(s, true, {GramOp{A, pa, lda, m}}, n, U0, ldg, s->lam.d());
     return Svd{U0, nullptr};
   }
   eig_trid(s, G, ldg, n, s->lam.d(), U0, n);
@@ -726,7 +814,7 @@ std::vector<int> zip_bounds(const lb_solver* s, const std::vector<int>& cap) {
   const int zc = s->cfg.chi_zip_cap > 0 ? s->cfg.chi_zip_cap : s->cfg.chi_cap;
   std::vector<int> zk(L + 1, 1);
   for (int i = 1; i < L; ++i) {
-    const long long cols = (long long)s->wb[i] * cap[i];
+    const long long cols = (long long)mpo_bond(s, i) * cap[i];
     zk[i] = (int)std::min<long long>(std::min<long long>(zc, 2LL * zk[i - 1]), cols);
   }
   // purification rank after the last cut
@@ -740,6 +828,7 @@ struct WorkPlan {
   int nmax = 2;
   long long mmax = 1;
   size_t C = 0, P = 0, T = 0, nn = 0, ework = 0, wide = 0, lam = 0, ws = 0, scratch = 0;
+  size_t CL = 0, PL = 0, TL = 0;  // leading channel (FP32 form)
   static constexpr size_t kSmall = 64;
 };
 
@@ -756,7 +845,19 @@ WorkPlan work_plan(const lb_solver* s, const std::vector<int>& cap) {
     w.mmax = std::max(w.mmax, (long long)s->wb[i + 1] * cr);
     cmax = std::max(cmax, (long long)zl * s->wb[i] * cl);
     pmax = std::max(pmax, (long long)zl * s->wb[i] * 2 * cr);
+    if (fp32(s)) {
+      // leading channel: carry zk x (wl cl) (also after the site, k <= zk[i+1]),
+      // stage 1 (zk wl) x 2 cr, stage 2 zk x 2 wr cr
+      w.CL = std::max<size_t>(w.CL, (size_t)zl * s->wlb[i] * cl);
+      w.CL = std::max<size_t>(w.CL, (size_t)zk[i + 1] * s->wlb[i + 1] * cr);
+      w.PL = std::max<size_t>(w.PL, (size_t)zl * s->wlb[i] * 2 * cr);
+      w.TL = std::max<size_t>(w.TL, (size_t)zl * 2 * s->wlb[i + 1] * cr);
+      w.mmax = std::max(w.mmax, (long long)s->wlb[i + 1] * cr);
+    }
   }
+  w.CL *= 16;
+  w.PL *= 16;
+  w.TL *= 16;
   // the last site's column Gram has m = K * chi_mu columns; the back-sweep
   // rows reach the zip-up ranks
   w.nmax = std::max<long long>(w.nmax, (long long)s->n_kraus * s->cfg.chi_mu_cap);
@@ -779,7 +880,7 @@ WorkPlan work_plan(const lb_solver* s, const std::vector<int>& cap) {
   return w;
 }
 
-size_t table_bytes(const lb_solver* s) { return (size_t)3 * (s->L + 1) * sizeof(int); }
+size_t table_bytes(const lb_solver* s) { return (size_t)table_len(s) * sizeof(int); }
 
 void alloc_workspace(lb_solver* s) {
   const WorkPlan w = work_plan(s, s->cap);
@@ -799,21 +900,14 @@ void alloc_workspace(lb_solver* s) {
   s->info.alloc(WorkPlan::kSmall, st);
   s->scratch.alloc(w.scratch, st);
   if (fp32(s)) {
-    // identity channel: C_I (rows x bond) and P_I (rows x 2 bond), FP64
-    int cmax = 1;
-    for (int i = 1; i <= s->L; ++i) cmax = std::max(cmax, s->cap[i]);
-    const size_t ib = (size_t)w.nmax * 2 * cmax * 16;
-    s->CI.alloc(ib, st);
-    s->PI.alloc(ib, st);
-    s->one.alloc(16, st);
-    const double one[2] = {1.0, 0.0};
-    HIPCHK(hipMemcpyAsync(s->one.p, one, sizeof(one), hipMemcpyHostToDevice, st));
-    HIPCHK(hipStreamSynchronize(st));
+    s->CL.alloc(w.CL, st);
+    s->PL.alloc(w.PL, st);
+    s->TL.alloc(w.TL, st);
   }
   s->dd.alloc(table_bytes(s), st);
   s->stat.alloc(sizeof(lbk::StepStat), st);
   s->disc_dev.alloc((s->L + 1) * sizeof(double), st);
-  s->hd.assign(3 * (s->L + 1), 1);
+  s->hd.assign(table_len(s), 1);
 }
 
 void alloc_state(lb_solver* s) {
@@ -836,9 +930,8 @@ size_t footprint_bytes(const lb_solver* s) {
   t += size_class(w.scratch) + size_class(table_bytes(s)) + size_class(sizeof(lbk::StepStat)) +
        size_class((s->L + 1) * sizeof(double));
   if (fp32(s)) {
-    int cmax = 1;
-    for (int i = 1; i <= s->L; ++i) cmax = std::max(cmax, cap[i]);
-    t += 2 * size_class((size_t)w.nmax * 2 * cmax * 16) + size_class(16);
+    t += size_class(w.CL) + size_class(w.PL) + size_class(w.TL);
+    for (const lb::Site& x : s->lead) t += size_class((size_t)x.l * 4 * x.r * 16);
   }
   for (const lb::Site& x : s->kraus_dev) {
     const size_t e = (size_t)x.l * 4 * x.r;
@@ -866,11 +959,12 @@ void release_device(lb_solver* s) {
   s->X.clear();
   s->Xspare.release();
   for (DevBuf* b : {&s->C, &s->P, &s->T, &s->Bm, &s->G, &s->G2, &s->U2, &s->Uf, &s->U0, &s->V, &s->lam,
-                    &s->lam2, &s->ws, &s->info, &s->scratch, &s->ework, &s->dd, &s->stat, &s->disc_dev, &s->CI,
-                    &s->PI, &s->one})
+                    &s->lam2, &s->ws, &s->info, &s->scratch, &s->ework, &s->dd, &s->stat, &s->disc_dev, &s->CL,
+                    &s->PL, &s->TL})
     b->release();
   for (auto& b : s->W.d64) b.release();
   for (auto& b : s->W.d32) b.release();
+  for (auto& b : s->WL.d64) b.release();
   s->Wb0.release();
   for (auto& op : s->ops) {
     for (auto& b : op->dev.d64) b.release();
@@ -905,6 +999,7 @@ void ensure_generator_on_device(lb_solver* s) {
     HIPCHK(hipMemcpyAsync(s->Wb0.p, s->h0.data(), s->h0.size() * sizeof(cd), hipMemcpyHostToDevice, s->stream));
   }
   upload_mpo(s, s->kraus_dev, s->W, fp32(s));
+  if (fp32(s)) upload_mpo(s, s->lead, s->WL, false);
   if (s->cap.empty()) alloc_state(s);
   alloc_workspace(s);
   s->zkhi = zip_bounds(s, s->cap);
@@ -928,23 +1023,19 @@ void refresh_drive(lb_solver* s) {
                                      fp32(s) ? s->W.d32[0].f() : nullptr, count, s->stream));
 }
 
-// Factor of the identity chain's site i (its canonical gauge, see
-// with_identity): 2^((L-1)/2) on site 0, 1/sqrt 2 elsewhere.
-double identity_factor(const lb_solver* s, int i) {
-  if (s->L == 1) return 1.0;
-  return i == 0 ? std::pow(2.0, 0.5 * (s->L - 1)) : std::sqrt(0.5);
-}
-
 void zipup(lb_solver* s) {
   const int L = s->L;
   const bool f32 = fp32(s);
   // FP32 form: the increment of the Kraus MPO is contracted in complex64, its
-  // identity channel apart in FP64 (T = [T_I | T_inc] by column blocks, the
-  // identity block holding the state itself); the FP64 form applies the
-  // direct sum as one MPO
+  // leading part (identity and sqrt(h/2) L_k) apart in FP64; the two blocks of
+  // the direct sum give T = [T_L | T_inc] by column blocks.  The FP64 form
+  // applies the direct sum as one MPO.
   const bool split = f32;
   const Prec pw = f32 ? lbk::F32 : lbk::F64;   // contraction storage / compute precision
-  const double tolz = s->cfg.tol_zip > 0 ? s->cfg.tol_zip : s->cfg.tol / 10.0;
+  // zip-up tolerance: tol / 10 (FP64), tol in the FP32 form, whose complex64
+  // rounding of the O(sqrt h) jump members puts noise singular values near
+  // 1e-9 of the largest, which a zip-up at tol / 10 would keep
+  const double tolz = s->cfg.tol_zip > 0 ? s->cfg.tol_zip : (f32 ? s->cfg.tol : s->cfg.tol / 10.0);
   const int zc = s->cfg.chi_zip_cap > 0 ? s->cfg.chi_zip_cap : s->cfg.chi_cap;
   const std::vector<int>& cap = s->cap;
   const std::vector<int>& zh = s->zkhi;
@@ -955,10 +1046,17 @@ void zipup(lb_solver* s) {
     const bool last = (i == L - 1);
     s->cls = PC_CONTRACT;
     if (split) {
-      // identity channel: P_I = g_i C_I X_i, read as T_I[(a', s')][b] (2 zk x cr)
-      mm(s, zk, scaled(cr, 2), cl, i == 0 ? s->one.p : s->CI.p, lbk::F64, cl, false, s->X[i].p, lbk::F64,
-         scaled(cr, 2), false, s->PI.p, lbk::F64, scaled(cr, 2), lbk::F64, Dim(1), Dim(0), Dim(0), Dim(0),
-         identity_factor(s, i));
+      // leading channel, both stages in FP64: P_L = C_L X_i, then
+      // T_L{a'}[(s', v)][b] = WLt[(s', v)][(u, s)] P_L{a'}[(u, s)][b]
+      const int ll = s->wlb[i], lr = s->wlb[i + 1];
+      const void* PLp = s->X[0].p;
+      if (i > 0) {
+        mm(s, scaled(zk, ll), scaled(cr, 2), cl, s->CL.p, lbk::F64, cl, false, s->X[i].p, lbk::F64,
+           scaled(cr, 2), false, s->PL.p, lbk::F64, scaled(cr, 2), lbk::F64);
+        PLp = s->PL.p;
+      }
+      mm(s, Dim(2 * lr), cr, Dim(2 * ll), s->WL.d64[i].p, lbk::F64, Dim(2 * ll), false, PLp, lbk::F64, cr,
+         false, s->TL.p, lbk::F64, cr, lbk::F64, zk, Dim(0), scaled(cr, 2 * ll), scaled(cr, 2 * lr));
     }
     // stage 1: P[(a', u)][(s, b)] = C[(a', u)][a] X_i[a][(s, b)]
     const void* Pp;
@@ -973,8 +1071,8 @@ void zipup(lb_solver* s) {
       pp = pw;
     }
     // stage 2: T_{a'}[(s', v)][b] = Wt[(s', v)][(u, s)] P_{a'}[(u, s)][b]; the
-    // FP32 form's last site goes to an FP64 buffer, where T_I is added into
-    // Kraus index 0
+    // FP32 form's last site goes to an FP64 buffer, where T_L is added (both
+    // blocks feed the Kraus index)
     const void* Wt = f32 ? (const void*)s->W.d32[i].p : (const void*)s->W.d64[i].p;
     void* Tout = (split && last) ? s->Bm.p : s->T.p;
     const Prec pt = (split && last) ? lbk::F64 : pw;
@@ -982,17 +1080,20 @@ void zipup(lb_solver* s) {
        zk, Dim(0), scaled(cr, 2 * wl), scaled(cr, 2 * wr));
     const Dim n = scaled(zk, 2);
     const Dim m = scaled(cr, wr);
+    const Dim mL = scaled(cr, split ? s->wlb[i + 1] : 1);
     if (!last) {
       s->cls = PC_SVDGEMM;
       Svd sv;
       if (split) {
-        // G = T_inc T_inc^H + T_I T_I^H
+        // G = T_inc T_inc^H + T_L T_L^H
         const int ldg = n.hi;
         double* G = s->G.d();
         gram_rows(s, s->T.p, pw, n, m, m, G, ldg);
-        mm(s, n, n, cr, s->PI.p, lbk::F64, cr, false, s->PI.p, lbk::F64, cr, true, G, lbk::F64, ldg, lbk::F64,
+        mm(s, n, n, mL, s->TL.p, lbk::F64, mL, false, s->TL.p, lbk::F64, mL, true, G, lbk::F64, ldg, lbk::F64,
            Dim(1), Dim(0), Dim(0), Dim(0), 1.0, 1.0);
-        eig_trid(s, G, ldg, n, s->lam.d(), s->U0.d(), capped(n, zc));
+        eig_trid(s, G, ldg, n, s->lam.d(), s->U0.d(), n);
+        refine_tail(s, true, {GramOp{s->T.p, pw, m, m}, GramOp{s->TL.p, lbk::F64, mL, mL}}, n, s->U0.d(), ldg,
+                    s->lam.d());
         sv = Svd{s->U0.d(), nullptr};
       } else {
         sv = left_svd(s, s->T.p, pw, n, m, m, passes(s) == 2, capped(n, zc));
@@ -1018,15 +1119,16 @@ void zipup(lb_solver* s) {
       } else {
         s->cls = PC_CONTRACT;
         mm(s, k, m, n, sv.U, lbk::F64, ldu, true, s->T.p, pw, m, false, s->C.p, pw, m, pw);
-        if (split) mm(s, k, cr, n, sv.U, lbk::F64, ldu, true, s->PI.p, lbk::F64, cr, false, s->CI.p, lbk::F64, cr, lbk::F64);
+        if (split) mm(s, k, mL, n, sv.U, lbk::F64, ldu, true, s->TL.p, lbk::F64, mL, false, s->CL.p, lbk::F64, mL, lbk::F64);
       }
     } else {
       // S2: purification truncation on the (Kraus x purification) columns
       const void* Tl = s->T.p;
       Prec pl = pw;
       if (split) {
-        Timed tm(s, PC_OTHER, 0.0, s->prof_on ? 48.0 * hv(s, n) * hv(s, cr) : 0.0);
-        HIPCHK(lbk::add_cols(s->PI.d(), cr, s->Bm.d(), m, n, cr, s->stream, ddp(s)));
+        Timed tm(s, PC_OTHER, 0.0, s->prof_on ? 48.0 * hv(s, n) * hv(s, m) : 0.0);
+        if (s->wlb[L] != wr) throw Fail(LB_ERR_STATE, "internal: Kraus index of the leading part");
+        HIPCHK(lbk::add_cols(s->TL.d(), m, s->Bm.d(), m, n, m, s->stream, ddp(s)));
         Tl = s->Bm.p;
         pl = lbk::F64;
       }
@@ -1035,7 +1137,8 @@ void zipup(lb_solver* s) {
       double* Gc = s->G.d();
       gram_cols(s, Tl, pl, n, m, m, Gc, ldv);
       double* V0 = s->U0.d();
-      eig_trid(s, Gc, ldv, m, s->lam.d(), V0, passes(s) == 2 ? m : capped(m, s->cfg.chi_mu_cap));
+      eig_trid(s, Gc, ldv, m, s->lam.d(), V0, m);
+      if (passes(s) == 1) refine_tail(s, false, {GramOp{Tl, pl, m, n}}, m, V0, ldv, s->lam.d());
       double* Vf = V0;
       const void* Asrc = Tl;
       Prec asrc = pl;
@@ -1224,43 +1327,31 @@ std::vector<lb::Term> convert_terms(const lb_solver* s, const lb_term* terms, in
   return out;
 }
 
-// The Kraus MPO as the direct sum (MPO addition, block-diagonal bonds) of
-// the identity chain and the increment `inc`, the identity block first.  The
-// identity chain is in inc's canonical gauge: sites 1.. are the 2 x 2
-// identity over sqrt 2 (right-orthonormal), site 0 carries 2^((L-1)/2), and
-// its last site feeds Kraus index 0.  With a drive, site 0's left index is
-// the polynomial index p and the identity sits in p = 0.  One site: the sum.
-lb::Mpo with_identity(const lb::Mpo& inc, int K) {
+// The Kraus MPO as the direct sum (MPO addition with block-diagonal bonds)
+// of its leading part `lead` and the increment `inc`, the leading block
+// first.  Both carry the K Kraus indices on their last site, where the two
+// blocks meet; with a drive, site 0's left index is inc's polynomial index p
+// and the leading part sits in p = 0.  One site: the plain sum.
+lb::Mpo direct_sum(const lb::Mpo& lead, const lb::Mpo& inc, int K) {
   const int n = (int)inc.size();
+  if ((int)lead.size() != n || n < 1) throw Fail(LB_ERR_STATE, "internal: Kraus MPO parts");
   lb::Mpo out(n);
-  if (n == 1) {
-    out[0] = inc[0];
-    for (int o = 0; o < 2; ++o) out[0].at(0, o, o, 0) += cd(1.0, 0.0);
-    return out;
-  }
   for (int i = 0; i < n; ++i) {
+    const lb::Site& a = lead[i];
     const lb::Site& x = inc[i];
-    const double f = (i == 0) ? std::pow(2.0, 0.5 * (n - 1)) : std::sqrt(0.5);
-    if (i == 0) {
-      lb::Site y(x.l, 1 + x.r);
-      for (int a = 0; a < x.l; ++a)
-        for (int o = 0; o < 2; ++o)
-          for (int ii = 0; ii < 2; ++ii) {
-            y.at(a, o, ii, 0) = (a == 0 && o == ii) ? cd(f, 0.0) : cd(0.0, 0.0);
-            for (int b = 0; b < x.r; ++b) y.at(a, o, ii, 1 + b) = x.at(a, o, ii, b);
-          }
-      out[i] = y;
-    } else {
-      const int r = (i == n - 1) ? x.r : 1 + x.r, ro = (i == n - 1) ? 0 : 1;
-      if (i == n - 1 && x.r != K) throw Fail(LB_ERR_STATE, "internal: Kraus index size");
-      lb::Site y(1 + x.l, r);
-      for (int o = 0; o < 2; ++o) y.at(0, o, o, 0) = cd(f, 0.0);
-      for (int a = 0; a < x.l; ++a)
-        for (int o = 0; o < 2; ++o)
-          for (int ii = 0; ii < 2; ++ii)
-            for (int b = 0; b < x.r; ++b) y.at(1 + a, o, ii, ro + b) = x.at(a, o, ii, b);
-      out[i] = y;
-    }
+    const bool first = (i == 0), fin = (i == n - 1);
+    if ((first && a.l != 1) || (fin && (a.r != K || x.r != K))) throw Fail(LB_ERR_STATE, "internal: Kraus index size");
+    const int lo = first ? 0 : a.l;  // offsets of inc's block
+    const int ro = fin ? 0 : a.r;
+    lb::Site y(first ? x.l : a.l + x.l, fin ? K : a.r + x.r);
+    for (int o = 0; o < 2; ++o)
+      for (int ii = 0; ii < 2; ++ii) {
+        for (int p = 0; p < a.l; ++p)
+          for (int b = 0; b < a.r; ++b) y.at(p, o, ii, b) += a.at(p, o, ii, b);
+        for (int p = 0; p < x.l; ++p)
+          for (int b = 0; b < x.r; ++b) y.at(lo + p, o, ii, ro + b) += x.at(p, o, ii, b);
+      }
+    out[i] = y;
   }
   return out;
 }
@@ -1424,55 +1515,63 @@ lb_status lindblad_set_generator(lb_solver* s, const lb_op* H0, const lb_op* H1,
     Mpo eye = mpo_identity(L);
     auto c = [&](const Mpo& m) { return mpo_compress(m, tol); };
     auto add = [&](const Mpo& a, const Mpo& b) { return c(mpo_add(a, b)); };
-    // U1 and the increment of the first member (U1 - 1 or U1' - 1): the
-    // identity is kept as its own MPO channel beside the compressed rest, so
-    // the increment, of order h ||H||, is not rounded at the identity's scale
-    std::vector<Mpo> u1{add(eye, mpo_scale(A, cd(0.0, -h)))};
+    // The family split by order in h: the leading part (the identity of the
+    // first member, sqrt(h/2) L_k of the mixed members; sqrt(h) L_k at first
+    // order) and the increment (U1 - 1 or U1' - 1, and the mixed members with
+    // U1 - 1 in place of U1), each compressed on its own, so the increment is
+    // not rounded at the scale of the identity.  d1: polynomial coefficients
+    // (in the drive f) of U1 - 1.
     std::vector<Mpo> d1{c(mpo_scale(A, cd(0.0, -h)))};
-    if (drive) {
-      u1.push_back(c(mpo_scale(B, cd(0.0, -h))));
-      d1.push_back(u1[1]);
-    }
+    if (drive) d1.push_back(c(mpo_scale(B, cd(0.0, -h))));
+    const Mpo zero = mpo_zero(L);
+    std::vector<Mpo> leadm{eye};
     std::vector<std::vector<Mpo>> fam;
     if (s->cfg.order == 1) {
       fam.push_back(d1);
-      for (auto& l : Lm) fam.push_back({c(mpo_scale(l, std::sqrt(h)))});
+      for (auto& l : Lm) {
+        leadm.push_back(c(mpo_scale(l, std::sqrt(h))));
+        fam.push_back({zero});
+      }
     } else {
       Mpo A2 = c(mpo_mul(A, A));
       std::vector<Mpo> dp{add(d1[0], mpo_scale(A2, -0.5 * h * h))};
       if (drive) {
         Mpo AB = add(c(mpo_mul(A, B)), c(mpo_mul(B, A)));
-        dp.push_back(add(u1[1], mpo_scale(AB, -0.5 * h * h)));
+        dp.push_back(add(d1[1], mpo_scale(AB, -0.5 * h * h)));
         dp.push_back(c(mpo_scale(c(mpo_mul(B, B)), -0.5 * h * h)));
       }
       fam.push_back(dp);
       const double sq = std::sqrt(h / 2.0);
       for (auto& l : Lm) {
         std::vector<Mpo> v;
-        for (auto& p : u1) v.push_back(c(mpo_scale(c(mpo_mul(p, l)), sq)));
+        for (auto& p : d1) v.push_back(c(mpo_scale(c(mpo_mul(p, l)), sq)));
         fam.push_back(v);
       }
       for (auto& l : Lm) {
         std::vector<Mpo> v;
-        for (auto& p : u1) v.push_back(c(mpo_scale(c(mpo_mul(l, p)), sq)));
+        for (auto& p : d1) v.push_back(c(mpo_scale(c(mpo_mul(l, p)), sq)));
         fam.push_back(v);
       }
       for (auto& l : Lm)
         for (auto& lp : Lm) fam.push_back({c(mpo_scale(c(mpo_mul(l, lp)), h / std::sqrt(2.0)))});
+      for (int rep = 0; rep < 2; ++rep)
+        for (auto& l : Lm) leadm.push_back(c(mpo_scale(l, sq)));
+      for (size_t j = 0; j < Lm.size() * Lm.size(); ++j) leadm.push_back(zero);
     }
     int degree = 1;
     for (auto& f2 : fam) degree = std::max(degree, (int)f2.size());
     std::vector<Mpo> polys;
     for (int p = 0; p < degree; ++p) {
       std::vector<Mpo> members;
-      for (auto& f2 : fam) members.push_back(p < (int)f2.size() ? f2[p] : mpo_zero(L));
+      for (auto& f2 : fam) members.push_back(p < (int)f2.size() ? f2[p] : zero);
       polys.push_back(c(kraus_stack(members)));
     }
     Mpo inc = (degree == 1) ? polys[0] : c(boundary_stack(polys));
     s->n_kraus = (int)fam.size();
-    s->kraus = with_identity(inc, s->n_kraus);
+    s->lead = c(kraus_stack(leadm));
+    s->kraus = direct_sum(s->lead, inc, s->n_kraus);
     // the FP64 form applies the direct sum as one MPO; the FP32 form applies
-    // the increment in complex64 and the identity channel apart in FP64
+    // the increment in complex64 and the leading part apart in FP64
     const Mpo W = fp32(s) ? inc : s->kraus;
     s->degree = degree;
     s->dt = dt;
@@ -1487,6 +1586,8 @@ lb_status lindblad_set_generator(lb_solver* s, const lb_op* H0, const lb_op* H1,
     s->wb.assign(L + 1, 1);
     for (int k = 0; k < L; ++k) s->wb[k + 1] = W[k].r;
     s->wb[0] = 1;
+    s->wlb.assign(L + 1, 1);
+    for (int k = 0; k < L; ++k) s->wlb[k + 1] = s->lead[k].r;
     Mpo Wdev = W;
     std::vector<cd> h0;
     if (degree > 1) {
@@ -1525,7 +1626,11 @@ lb_status lindblad_kraus_info(const lb_solver* s, int32_t* bonds, int32_t* n_kra
   return LB_OK;
 }
 
-static lb_status load_mps(lb_solver* s, const std::vector<int>& bonds, const std::vector<const cd*>& sites) {
+// verbatim: the sites come from get_state_mps (right-canonical, normalised)
+// and are loaded as they are, with the clock at `steps`, so that stepping on
+// continues exactly as the solver that exported them would have.
+static lb_status load_mps(lb_solver* s, const std::vector<int>& bonds, const std::vector<const cd*>& sites,
+                          bool verbatim = false, long long steps = 0) {
     (void)hipGetLastError();   // an unread error of an earlier call is not this call's
   const int L = s->L;
   HIPCHK(hipSetDevice(s->cfg.device));
@@ -1540,22 +1645,23 @@ static lb_status load_mps(lb_solver* s, const std::vector<int>& bonds, const std
   }
   // a new state: size table from its bonds, cleared status
   HIPCHK(hipStreamSynchronize(s->stream));
-  std::vector<int> tab(3 * (L + 1), 1);
+  std::vector<int> tab(table_len(s), 1);
   for (int i = 0; i <= L; ++i) tab[sl_chi(s, i)] = bonds[i];
   copy_in(s, s->dd.p, tab.data(), tab.size() * sizeof(int));
   lbk::StepStat st{};
   st.tau = 1.0;
+  st.steps = verbatim ? steps : 0;
   copy_in(s, s->stat.p, &st, sizeof(st));
   std::vector<double> z(L + 1, 0.0);
   copy_in(s, s->disc_dev.p, z.data(), z.size() * sizeof(double));
   s->hd = tab;
   s->err_bits = 0;
   s->have_state = false;
-  canonicalize(s, bonds);
+  if (!verbatim) canonicalize(s, bonds);
   wait_stream(s);
   check_err(s);
-  s->t = 0.0;
-  s->steps = 0;
+  s->steps = verbatim ? steps : 0;
+  s->t = (double)s->steps * s->dt;
   s->max_defect = 0.0;
   s->last_tau = 1.0;
   s->warned = false;
@@ -1625,6 +1731,31 @@ lb_status lindblad_set_state_mps(lb_solver* s, const int32_t* bonds, const doubl
       ptrs[i] = (const cd*)sites[i];
     }
     return load_mps(s, b, ptrs);
+  } catch (const Fail& f) {
+    return fail(f);
+  } catch (const std::exception& e) {
+    release_cus_on_error();
+    g_last_error = e.what();
+    return LB_ERR_ARG;
+  }
+}
+
+lb_status lindblad_restore_state(lb_solver* s, const int32_t* bonds, const double* const* sites, int64_t steps) {
+  try {
+    if (!s || !bonds || !sites || steps < 0) throw Fail(LB_ERR_ARG, "bad argument");
+    const int L = s->L;
+    std::vector<int> b(bonds, bonds + L + 1);
+    if (b[0] != 1) throw Fail(LB_ERR_ARG, "bonds[0] must be 1");
+    ensure_generator_on_device(s);
+    for (int i = 1; i <= L; ++i)
+      if (b[i] < 1 || b[i] > (i == L ? s->cfg.chi_mu_cap : s->cap[i]))
+        throw Fail(LB_ERR_ARG, "bond out of range for a state this solver exported");
+    std::vector<const cd*> ptrs(L);
+    for (int i = 0; i < L; ++i) {
+      if (!sites[i]) throw Fail(LB_ERR_ARG, "NULL site");
+      ptrs[i] = (const cd*)sites[i];
+    }
+    return load_mps(s, b, ptrs, true, steps);
   } catch (const Fail& f) {
     return fail(f);
   } catch (const std::exception& e) {

@@ -140,6 +140,17 @@ hipError_t truncate_rank(const double* lam, Dim n, double tol, int cap, int* k_o
 hipError_t copy_cols(const double* src, Dim lds, double* dst, Dim ldd, Dim rows, Dim cols,
                      const double* lam, hipStream_t stream, const int* dd = nullptr);
 
+// Tail of a descending spectrum lam (n values): j0 = the number of eigenvalues
+// >= c lam_0, at most n - 1, so the tail [j0, n) holds at least the last one;
+// writes dd[j0_slot] = j0 and dd[k_slot] = n - j0 (one thread).
+hipError_t tail_split(const double* lam, Dim n, double c, int* dd, int j0_slot, int k_slot, hipStream_t stream);
+
+// dst[i*ldd + doff + j] = src[i*lds + soff + j] for i < rows, j < cols, in
+// units of `elem` doubles (2: complex128, 1: real); soff = dd[soff_slot] and
+// doff = dd[doff_slot] (a slot < 0 stands for 0).
+hipError_t copy_block(const double* src, Dim lds, int soff_slot, double* dst, Dim ldd, int doff_slot, Dim rows,
+                      Dim cols, int elem, hipStream_t stream, const int* dd);
+
 // dst[i*ldd + j] += src[i*lds + j] for i < rows, j < cols (complex128).
 hipError_t add_cols(const double* src, Dim lds, double* dst, Dim ldd, Dim rows, Dim cols, hipStream_t stream,
                     const int* dd = nullptr);

@@ -582,6 +582,51 @@ hipError_t copy_cols(const double* src, Dim lds, double* dst, Dim ldd, Dim rows,
   return hipGetLastError();
 }
 
+__global__ void tail_split_kernel(const double* lam, Dim nD, double c, int* dd, int j0_slot, int k_slot) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int n = dim_val(nD, dd);
+  int j0 = 0;
+  if (n > 0) {
+    const double t = c * lam[0];
+    while (j0 < n && lam[j0] >= t) ++j0;
+    if (j0 > n - 1) j0 = n - 1;
+  }
+  dd[j0_slot] = j0;
+  dd[k_slot] = n - j0;
+}
+
+hipError_t tail_split(const double* lam, Dim n, double c, int* dd, int j0_slot, int k_slot, hipStream_t s) {
+  if (!dd || j0_slot < 0 || k_slot < 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(tail_split_kernel, dim3(1), dim3(64), 0, s, lam, n, c, dd, j0_slot, k_slot);
+  return hipGetLastError();
+}
+
+__global__ void copy_block_kernel(const double* src, Dim ldsD, int soff_slot, double* dst, Dim lddD,
+                                  int doff_slot, Dim rowsD, Dim colsD, int elem, const int* dd) {
+  const long long lds = dim_val(ldsD, dd), ldd = dim_val(lddD, dd);
+  const int rows = dim_val(rowsD, dd), cols = dim_val(colsD, dd);
+  const long long so = soff_slot >= 0 ? dd[soff_slot] : 0, dof = doff_slot >= 0 ? dd[doff_slot] : 0;
+  const long long total = (long long)rows * cols;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long i = e / cols, j = e % cols;
+    const long long si = elem * (i * lds + so + j), di = elem * (i * ldd + dof + j);
+    dst[di] = src[si];
+    if (elem == 2) dst[di + 1] = src[si + 1];
+  }
+}
+
+hipError_t copy_block(const double* src, Dim lds, int soff_slot, double* dst, Dim ldd, int doff_slot, Dim rows,
+                      Dim cols, int elem, hipStream_t s, const int* dd) {
+  const long long total = (long long)rows.hi * cols.hi;
+  if (total <= 0) return hipSuccess;
+  if ((elem != 1 && elem != 2) || ((soff_slot >= 0 || doff_slot >= 0) && !dd)) return hipErrorInvalidValue;
+  const int blocks = (int)std::min<long long>((total + 255) / 256, 2048);
+  hipLaunchKernelGGL(copy_block_kernel, dim3(blocks), dim3(256), 0, s, src, lds, soff_slot, dst, ldd, doff_slot,
+                     rows, cols, elem, dd);
+  return hipGetLastError();
+}
+
 __global__ void add_cols_kernel(const double* src, Dim ldsD, double* dst, Dim lddD, Dim rowsD, Dim colsD,
                                 const int* dd) {
   const long long lds = dim_val(ldsD, dd), ldd = dim_val(lddD, dd);

@@ -6,6 +6,8 @@ the even cat, in two records:
   2^4, |alpha|^2 = 256/3, dt <= 2e-4, caps chi 128 / chi_mu 16, for the first
   PREFIX steps of the gate (the whole gate, 10628 steps, takes the oracle
   hours);
+* "paper_check": the same scan point over its first CHECK steps (the record
+  the CPU tests recompute in seconds);
 * "small_whole_gate": memory 2^5, buffer 2^2, |alpha|^2 = 32/3, dt <= 1e-3,
   caps chi 64 / chi_mu 16, over the whole gate (6012 steps).
 
@@ -26,6 +28,7 @@ from oracle import mps, tt     # noqa: E402
 
 PAPER = dict(Ra=8, Rb=4, dt_max=2e-4, chi=128, chi_mu=16)
 PREFIX = 300
+CHECK = 12
 SMALL = dict(Ra=5, Rb=2, alpha2=32.0 / 3.0, dt_max=1e-3, chi=64, chi_mu=16)
 
 
@@ -57,7 +60,7 @@ def run(case, n_steps=None):
 
 
 def main():
-    out = {"paper_prefix": run(PAPER, PREFIX), "small_whole_gate": run(SMALL)}
+    out = {"paper_prefix": run(PAPER, PREFIX), "paper_check": run(PAPER, CHECK), "small_whole_gate": run(SMALL)}
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "zgate_mps.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)

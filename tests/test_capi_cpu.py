@@ -91,16 +91,17 @@ def test_host_kraus_mpo_matches_dense_family(which):
     assert nk == len(fam)
     assert bonds == K.bonds
     # canonical gauge: sites 1..L-2 right-orthonormal; at the last site the
-    # identity row and the increment rows share Kraus index 0, so only the
-    # increment rows are orthonormal there and every row has unit norm
+    # leading block's rows and the increment's rows feed the same Kraus
+    # indices, so each block's rows are orthonormal among themselves
     for w in W[1:-1]:
         M = w.reshape(w.shape[0], -1)
         assert np.abs(M @ M.conj().T - np.eye(w.shape[0])).max() < 1e-12
     M = W[-1].reshape(W[-1].shape[0], -1)
     if len(W) > 1:
         G = M @ M.conj().T
-        assert np.abs(np.diag(G) - 1.0).max() < 1e-12
-        assert np.abs(G[1:, 1:] - np.eye(G.shape[0] - 1)).max() < 1e-12
+        r = K.lead[-1].shape[0]
+        assert np.abs(G[:r, :r] - np.eye(r)).max() < 1e-12
+        assert np.abs(G[r:, r:] - np.eye(G.shape[0] - r)).max() < 1e-12
     s.close()
 
 

@@ -132,16 +132,17 @@ def test_driven_kraus_mpo_polynomial_in_drive():
 
 
 def test_kraus_mpo_canonical_gauge():
-    """The increment W has sites 1.. right-orthonormal; the direct sum with the
-    identity chain is block diagonal, so it keeps that on sites 1..L-2, and on
-    the last site (where both feed Kraus index 0) every row has unit norm and
-    the increment's rows stay orthonormal."""
+    """The leading part and the increment each have sites 1.. right-
+    orthonormal; their direct sum is block diagonal, so it keeps that on sites
+    1..L-2, and on the last site (where both feed the Kraus index) each
+    block's rows stay orthonormal."""
     m = wl.model_cat_buffer(Ra=3, Rb=3, alpha2=2.0, dt=1e-3)
     K = tt.KrausMPO(m, m.dt)
-    for w in K.W[1:]:
-        l = w.shape[0]
-        M = w.reshape(l, -1)
-        assert np.abs(M @ M.conj().T - np.eye(l)).max() < 1e-13
+    for W in (K.lead, K.W):
+        for w in W[1:]:
+            l = w.shape[0]
+            M = w.reshape(l, -1)
+            assert np.abs(M @ M.conj().T - np.eye(l)).max() < 1e-13
     F = K.at(0.0)
     for w in F[1:-1]:
         l = w.shape[0]
@@ -149,15 +150,17 @@ def test_kraus_mpo_canonical_gauge():
         assert np.abs(M @ M.conj().T - np.eye(l)).max() < 1e-13
     M = F[-1].reshape(F[-1].shape[0], -1)
     G = M @ M.conj().T
-    assert np.abs(np.diag(G) - 1.0).max() < 1e-13
-    assert np.abs(G[1:, 1:] - np.eye(G.shape[0] - 1)).max() < 1e-13
-    assert [b - 1 for b in K.bonds] == tt.mpo_bonds(K.W)
+    r = K.lead[-1].shape[0]
+    assert np.abs(G[:r, :r] - np.eye(r)).max() < 1e-13
+    assert np.abs(G[r:, r:] - np.eye(G.shape[0] - r)).max() < 1e-13
+    assert K.bonds == [a + b for a, b in zip(tt.mpo_bonds(K.lead), tt.mpo_bonds(K.W))]
 
 
 def test_identity_split_keeps_the_increment():
-    """With the identity kept apart, the MPO's increment (first Kraus member
-    minus the identity) is -i h H_eff - (h^2/2) H_eff^2 to 1e-12 of its own
-    size at a step of 1e-6, where the increment is ~1e-4 of the identity."""
+    """With the leading part kept apart, the increment of the first member
+    (U1' - 1) is -i h H_eff - (h^2/2) H_eff^2 to 1e-12 of its own size at a
+    step of 1e-6, where it is ~1e-4 of the identity; the leading part of a
+    mixed member is sqrt(h/2) L_k exactly."""
     m = wl.model_cat_buffer(Ra=3, Rb=2, alpha2=2.0, dt=1e-6)
     K = tt.KrausMPO(m, m.dt)
     dm = dense.DenseModel(m)
@@ -167,3 +170,6 @@ def test_identity_split_keeps_the_increment():
     got = _member(K.W, 0, m.bits, m.site_order())
     assert 1e-6 < np.abs(inc).max() < 1e-3
     assert np.abs(got - inc).max() <= 1e-12 * np.abs(inc).max()
+    lead1 = _member(K.lead, 1, m.bits, m.site_order())
+    ref = np.sqrt(h / 2) * dm.L[0]
+    assert np.abs(lead1 - ref).max() <= 1e-13 * np.abs(ref).max()
