@@ -462,7 +462,8 @@ int sl_kb(const lb_solver* s, int i) { return 2 * (s->L + 1) + i; }
 // start and size of the tail of the last decomposition re-resolved by refine_tail
 int sl_tail0(const lb_solver* s) { return 3 * (s->L + 1); }
 int sl_tailk(const lb_solver* s) { return 3 * (s->L + 1) + 1; }
-int table_len(const lb_solver* s) { return 3 * (s->L + 1) + 2; }
+int sl_tailv(const lb_solver* s) { return 3 * (s->L + 1) + 2; }
+int table_len(const lb_solver* s) { return 3 * (s->L + 1) + 3; }
 Dim dchi(const lb_solver* s, int i, int hi) { return Dim::dyn(1, sl_chi(s, i), hi); }
 Dim dzk(const lb_solver* s, int i, int hi) { return Dim::dyn(1, sl_zk(s, i), hi); }
 Dim dkb(const lb_solver* s, int i, int hi) { return Dim::dyn(1, sl_kb(s, i), hi); }
@@ -622,6 +623,21 @@ void eig_jacobi(lb_solver* s, double* G, int ldg, Dim n, double* lam) {
                           ddp(s)));
 }
 
+// One operand block of a Gram matrix: A is (order x len) for a row Gram
+// (G += A A^H), (len x order) for a column Gram (G += A^H A); ld its leading
+// dimension.
+struct GramOp {
+  const void* A;
+  Prec p;
+  Dim ld, len;
+};
+
+// The tail of the spectrum below this fraction of the largest eigenvalue is
+// decomposed a second time (refine_tail): well above the one-pass floor
+// (~8 n eps lam_0 for the orders up to 512), and low enough that a saturated
+// state's truncations at the bond caps rarely reach it.
+constexpr double kTailFraction = 1e-9;
+
 // Tridiagonal route (absolute accuracy): G (ld ldg) destroyed, all
 // eigenvalues in lam, the eigenvectors of the kvec largest in U (ld ldg),
 // made orthonormal by Newton-Schulz polar steps U <- U (3I - U^H U)/2.
@@ -629,10 +645,11 @@ void eig_jacobi(lb_solver* s, double* G, int ldg, Dim n, double* lam) {
 // of mutual overlap; one step takes that to ~1e-10, below the FP32 form's
 // rounding of the contractions; the FP64 form (whose second pass needs U0
 // unitary to rounding) takes two.
-void eig_trid(lb_solver* s, double* G, int ldg, Dim n, double* lam, double* U, Dim kvec) {
+void eig_trid(lb_solver* s, double* G, int ldg, Dim n, double* lam, double* U, Dim kvec, int tail_cap = 0) {
   kvec = capped(kvec, n.hi);
   const lbk::TridWork tw = lbk::trid_work(s->ework.d(), ldg);
-  const double N = s->prof_on ? hv(s, n) : 0.0, KV = s->prof_on ? std::min(hv(s, kvec), N) : 0.0;
+  const double N = s->prof_on ? hv(s, n) : 0.0;
+  double KV = s->prof_on ? std::min(hv(s, kvec), N) : 0.0;
   {
     // complex Hermitian Householder tridiagonalisation: 16/3 n^3 real flops;
     // reads the matrix once, writes the reflectors and the tridiagonal
@@ -643,6 +660,16 @@ void eig_trid(lb_solver* s, double* G, int ldg, Dim n, double* lam, double* U, D
     // bisection: 53 halvings x n Sturm steps of 5 flops, per eigenvalue
     Timed tm(s, PC_STEBZ, 53.0 * 5.0 * N * N, 24.0 * N);
     HIPCHK(lbk::trid_eigenvalues(n, tw, lam, s->stream, ddp(s)));
+  }
+  if (tail_cap > 0) {
+    // the spectrum's tail for refine_tail; the vectors computed are all n
+    // when a truncation at tail_cap reaches into the tail, else tail_cap
+    Timed tm(s, PC_OTHER, 0.0, s->prof_on ? 8.0 * N : 0.0);
+    HIPCHK(lbk::tail_split(lam, n, kTailFraction, tail_cap, s->dd.i(), sl_tail0(s), sl_tailk(s), sl_tailv(s),
+                           s->stream));
+    kvec = Dim::dyn(1, sl_tailv(s), n.hi);
+    timed_sync(s);
+    KV = s->prof_on ? std::min(hv(s, kvec), N) : 0.0;
   }
   {
     // inverse iteration: factor (8n) + 2 x (forward 2n + backward 5n + norm 3n)
@@ -661,41 +688,27 @@ void eig_trid(lb_solver* s, double* G, int ldg, Dim n, double* lam, double* U, D
   }
 }
 
-// One operand block of a Gram matrix: A is (order x len) for a row Gram
-// (G += A A^H), (len x order) for a column Gram (G += A^H A); ld its leading
-// dimension.
-struct GramOp {
-  const void* A;
-  Prec p;
-  Dim ld, len;
-};
-
-// The tail of the spectrum below this fraction of the largest eigenvalue is
-// decomposed a second time (refine_tail).
-constexpr double kTailFraction = 1e-6;
-
 // Re-resolves the tail of a one-pass eigen-decomposition of a Gram matrix G
 // (the FP32 form's single pass).  G = sum_b A_b A_b^H (rows) or
 // sum_b A_b^H A_b (!rows), of order n, was decomposed into lam (descending)
-// and U (n x n, ld ldu, all n columns) by the tridiagonal route, whose
-// absolute accuracy ~eps ||G|| leaves the eigenvalues under ~8 n eps lam_0
-// unresolved -- squared singular values, so singular values under ~1e-7 of
-// the largest, inside the range a truncation at tol = 1e-8 keeps.  The
-// columns of U past the eigenvalues >= kTailFraction lam_0 (at least the
-// last) span the tail; the Gram of the operands projected on it, of norm
-// ~kTailFraction lam_0, is decomposed again, with an accuracy relative to that
-// norm, and its vectors rotate U's tail columns and replace its eigenvalues.
-// The head keeps its vectors: they are all kept by any truncation, so only
-// their span matters, and that the second decomposition completes exactly.
+// and U (n x n, ld ldu) by eig_trid with a tail_cap, which set the tail's
+// start j0 and size in the size table (size 0 when the truncation that
+// follows keeps no tail value: then every launch here is empty) and computed
+// all n vectors when the size is not 0.  The tridiagonal route's absolute
+// accuracy ~eps ||G|| leaves the eigenvalues under ~8 n eps lam_0 unresolved
+// -- squared singular values, so singular values under ~1e-7 of the largest,
+// inside the range a truncation at tol = 1e-8 keeps.  The columns of U past
+// the eigenvalues >= kTailFraction lam_0 (at least the last) span the tail;
+// the Gram of the operands projected on it, of norm ~kTailFraction lam_0, is
+// decomposed again, with an accuracy relative to that norm, and its vectors
+// rotate U's tail columns and replace its eigenvalues.  The head keeps its
+// vectors: a truncation keeps them all, so only their span matters, and the
+// second decomposition completes that span exactly.
 void refine_tail(lb_solver* s, bool rows, std::initializer_list<GramOp> ops, Dim n, double* U, int ldu,
                  double* lam) {
   const int js = sl_tail0(s), ks = sl_tailk(s);
   const Dim kt = Dim::dyn(1, ks, n.hi);
   const int ldt = n.hi;
-  {
-    Timed tm(s, PC_OTHER, 0.0, s->prof_on ? 8.0 * hv(s, n) : 0.0);
-    HIPCHK(lbk::tail_split(lam, n, kTailFraction, s->dd.i(), js, ks, s->stream));
-  }
   // Ut = U[:, j0:]
   double* Ut = s->Uf.d();
   {
@@ -756,7 +769,7 @@ Svd left_svd(lb_solver* s, const void* A, Prec pa, Dim n, Dim m, Dim lda, bool w
   gram_rows(s, A, pa, n, m, lda, G, ldg);
   double* U0 = s->U0.d();
   if (passes(s) == 1) {
-    eig_trid(s, G, ldg, n, s->lam.d(), U0, n);
+    eig_trid(s, G, ldg, n, s->lam.d(), U0, n, kvec.hi);
     refine_tail(s, true, {GramOp{A, pa, lda, m}}, n, U0, ldg, s->lam.d());
     return Svd{U0, nullptr};
   }
@@ -1091,7 +1104,7 @@ void zipup(lb_solver* s) {
         gram_rows(s, s->T.p, pw, n, m, m, G, ldg);
         mm(s, n, n, mL, s->TL.p, lbk::F64, mL, false, s->TL.p, lbk::F64, mL, true, G, lbk::F64, ldg, lbk::F64,
            Dim(1), Dim(0), Dim(0), Dim(0), 1.0, 1.0);
-        eig_trid(s, G, ldg, n, s->lam.d(), s->U0.d(), n);
+        eig_trid(s, G, ldg, n, s->lam.d(), s->U0.d(), n, zc);
         refine_tail(s, true, {GramOp{s->T.p, pw, m, m}, GramOp{s->TL.p, lbk::F64, mL, mL}}, n, s->U0.d(), ldg,
                     s->lam.d());
         sv = Svd{s->U0.d(), nullptr};
@@ -1137,7 +1150,7 @@ void zipup(lb_solver* s) {
       double* Gc = s->G.d();
       gram_cols(s, Tl, pl, n, m, m, Gc, ldv);
       double* V0 = s->U0.d();
-      eig_trid(s, Gc, ldv, m, s->lam.d(), V0, m);
+      eig_trid(s, Gc, ldv, m, s->lam.d(), V0, m, passes(s) == 1 ? s->cfg.chi_mu_cap : 0);
       if (passes(s) == 1) refine_tail(s, false, {GramOp{Tl, pl, m, n}}, m, V0, ldv, s->lam.d());
       double* Vf = V0;
       const void* Asrc = Tl;

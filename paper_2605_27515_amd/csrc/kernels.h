@@ -141,9 +141,13 @@ hipError_t copy_cols(const double* src, Dim lds, double* dst, Dim ldd, Dim rows,
                      const double* lam, hipStream_t stream, const int* dd = nullptr);
 
 // Tail of a descending spectrum lam (n values): j0 = the number of eigenvalues
-// >= c lam_0, at most n - 1, so the tail [j0, n) holds at least the last one;
-// writes dd[j0_slot] = j0 and dd[k_slot] = n - j0 (one thread).
-hipError_t tail_split(const double* lam, Dim n, double c, int* dd, int j0_slot, int k_slot, hipStream_t stream);
+// >= c lam_0, at most n - 1, so the tail [j0, n) holds at least the last one.
+// A truncation that keeps at most `cap` values then reaches into the tail only
+// if j0 < cap.  Writes dd[j0_slot] = j0, dd[k_slot] = n - j0 if j0 < cap else
+// 0, and dd[kv_slot] = n if j0 < cap else min(n, cap), the eigenvectors the
+// decomposition needs (one thread).
+hipError_t tail_split(const double* lam, Dim n, double c, int cap, int* dd, int j0_slot, int k_slot, int kv_slot,
+                      hipStream_t stream);
 
 // dst[i*ldd + doff + j] = src[i*lds + soff + j] for i < rows, j < cols, in
 // units of `elem` doubles (2: complex128, 1: real); soff = dd[soff_slot] and

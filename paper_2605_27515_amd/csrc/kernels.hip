@@ -582,7 +582,8 @@ hipError_t copy_cols(const double* src, Dim lds, double* dst, Dim ldd, Dim rows,
   return hipGetLastError();
 }
 
-__global__ void tail_split_kernel(const double* lam, Dim nD, double c, int* dd, int j0_slot, int k_slot) {
+__global__ void tail_split_kernel(const double* lam, Dim nD, double c, int cap, int* dd, int j0_slot, int k_slot,
+                                  int kv_slot) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const int n = dim_val(nD, dd);
   int j0 = 0;
@@ -591,13 +592,16 @@ __global__ void tail_split_kernel(const double* lam, Dim nD, double c, int* dd, 
     while (j0 < n && lam[j0] >= t) ++j0;
     if (j0 > n - 1) j0 = n - 1;
   }
+  const bool tail = j0 < cap;
   dd[j0_slot] = j0;
-  dd[k_slot] = n - j0;
+  dd[k_slot] = tail ? n - j0 : 0;
+  dd[kv_slot] = tail ? n : min(n, cap);
 }
 
-hipError_t tail_split(const double* lam, Dim n, double c, int* dd, int j0_slot, int k_slot, hipStream_t s) {
-  if (!dd || j0_slot < 0 || k_slot < 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(tail_split_kernel, dim3(1), dim3(64), 0, s, lam, n, c, dd, j0_slot, k_slot);
+hipError_t tail_split(const double* lam, Dim n, double c, int cap, int* dd, int j0_slot, int k_slot, int kv_slot,
+                      hipStream_t s) {
+  if (!dd || j0_slot < 0 || k_slot < 0 || kv_slot < 0 || cap < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(tail_split_kernel, dim3(1), dim3(64), 0, s, lam, n, c, cap, dd, j0_slot, k_slot, kv_slot);
   return hipGetLastError();
 }
 
