@@ -65,11 +65,10 @@ enum lb_precision {
                            in FP64, so the complex64 rounding sits on the
                            O(h) increment only.  Each truncated factorisation
                            is one tridiagonal eigen-decomposition of the Gram
-                           matrix plus a second one of its spectral tail
-                           (eigenvalues under 1e-6 of the largest), which
-                           resolves the singular values down to ~1e-10 of the
-                           largest that a single pass leaves at its ~1e-7
-                           rounding floor                                  */
+                           matrix; when its truncation keeps eigenvalues under
+                           1e-9 of the largest, that tail is decomposed a
+                           second time, resolving the singular values a
+                           single pass leaves at its ~1e-7 rounding floor  */
 };
 
 typedef struct lb_config {
@@ -96,6 +95,18 @@ typedef struct lb_config {
                                       exceeds 1 + tau_warn makes the next
                                       lindblad_sync return LB_WARN_UNSTABLE;
                                       <= 0 selects LB_TAU_WARN                  */
+  void* arena;                     /* NULL, or caller-owned device memory on
+                                      `device` from which the solver carves
+                                      every device buffer it holds (256-byte
+                                      aligned, no hipMalloc): state, Kraus MPO,
+                                      workspace, uploaded operators.  It must
+                                      outlive the solver's device use (until
+                                      lindblad_release or lindblad_destroy);
+                                      lindblad_footprint gives the bytes one
+                                      generator and state need.  A buffer that
+                                      does not fit fails its call with
+                                      LB_ERR_OOM                                */
+  int64_t arena_bytes;             /* size of the arena (> 0 when it is set)   */
 } lb_config;
 
 #define LB_TAU_WARN 1e-3

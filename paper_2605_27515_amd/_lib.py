@@ -41,7 +41,8 @@ class LbConfig(C.Structure):
                 ("tol", C.c_double), ("tol_zip", C.c_double), ("order", C.c_int32),
                 ("precision", C.c_int32), ("allow_unstable", C.c_int32),
                 ("stream", C.c_void_p), ("device", C.c_int32),
-                ("fp32_tol_floor", C.c_double), ("tau_warn", C.c_double)]
+                ("fp32_tol_floor", C.c_double), ("tau_warn", C.c_double),
+                ("arena", C.c_void_p), ("arena_bytes", C.c_int64)]
 
 
 class LbFactor(C.Structure):

@@ -64,7 +64,8 @@ class Solver:
     def __init__(self, bits, chi: int, chi_mu: int, tol: float = 1e-8, order: int = 2,
                  precision: str = "fp64", chi_zip: int = 0, tol_zip: float = 0.0,
                  site_order=None, stream: int | None = None, device: int = 0,
-                 allow_unstable: bool = False, fp32_tol_floor: float = 0.0, tau_warn: float = 0.0):
+                 allow_unstable: bool = False, fp32_tol_floor: float = 0.0, tau_warn: float = 0.0,
+                 arena: int | None = None, arena_bytes: int = 0):
         lib = L.load()
         cfg = L.LbConfig()
         lib.lindblad_default_config(C.byref(cfg))
@@ -88,6 +89,8 @@ class Solver:
         cfg.device = int(device)
         cfg.fp32_tol_floor = float(fp32_tol_floor)
         cfg.tau_warn = float(tau_warn)
+        cfg.arena = arena
+        cfg.arena_bytes = int(arena_bytes)
         h = C.c_void_p()
         _check(lib.lindblad_create(C.byref(cfg), C.byref(h)), "create")
         self.h = h

@@ -118,35 +118,79 @@ void* cache_get(int d, size_t cls) {
   return q;
 }
 
+// Caller-owned device memory a solver carves its buffers from (bump
+// allocation, 256-byte aligned).  Space comes back only when the solver
+// releases all of its device buffers, or at a mark taken before temporaries.
+struct Arena {
+  char* base = nullptr;
+  size_t size = 0, used = 0;
+  void* take(size_t b) {
+    const size_t a = (used + 255) & ~(size_t)255;
+    if (a > size || b > size - a)
+      throw Fail(LB_ERR_OOM, "arena of " + std::to_string(size) + " bytes exhausted (" + std::to_string(a + b) +
+                                 " needed)");
+    used = a + b;
+    return base + a;
+  }
+};
+
+// Temporaries of one call carved from an arena: the space taken after the
+// mark comes back when the mark goes out of scope, once the stream has
+// drained (declare it before the temporaries).
+struct ArenaMark {
+  Arena& a;
+  size_t used;
+  hipStream_t st;
+  ArenaMark(Arena& ar, hipStream_t s) : a(ar), used(ar.used), st(s) {}
+  ~ArenaMark() {
+    if (a.used != used && st) (void)hipStreamSynchronize(st);
+    a.used = used;
+  }
+};
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;             // size class actually held
   int dev = 0;
   hipStream_t st = nullptr;     // the stream the block is used on
+  bool in_arena = false;        // carved from a caller's arena (never cached)
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), dev(o.dev), st(o.st) { o.p = nullptr; o.bytes = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), dev(o.dev), st(o.st), in_arena(o.in_arena) {
+    o.p = nullptr; o.bytes = 0; o.in_arena = false;
+  }
   DevBuf& operator=(DevBuf&& o) noexcept {
     if (this != &o) {
       release();
-      p = o.p; bytes = o.bytes; dev = o.dev; st = o.st;
-      o.p = nullptr; o.bytes = 0;
+      p = o.p; bytes = o.bytes; dev = o.dev; st = o.st; in_arena = o.in_arena;
+      o.p = nullptr; o.bytes = 0; o.in_arena = false;
     }
     return *this;
   }
-  void alloc(size_t b, hipStream_t stream) {
+  // b bytes for use on `stream`, from the arena when one is given
+  void alloc(size_t b, hipStream_t stream, Arena* ar) {
     if (b <= bytes && p) { st = stream; return; }
     release();
-    const size_t cls = size_class(b);
     int d = 0;
     (void)hipGetDevice(&d);
+    if (ar && ar->base) {
+      p = ar->take(b);
+      bytes = b; dev = d; st = stream; in_arena = true;
+      return;
+    }
+    const size_t cls = size_class(b);
     void* q = cache_get(d, cls);
     if (!q) throw Fail(LB_ERR_OOM, "device allocation of " + std::to_string(cls) + " bytes failed");
     p = q; bytes = cls; dev = d; st = stream;
   }
   void release() {
     if (!p) return;
+    if (in_arena) {
+      // the space returns with the arena's next reset
+      p = nullptr; bytes = 0; in_arena = false;
+      return;
+    }
     if (st) (void)hipStreamSynchronize(st);
     BlockCache& c = block_cache();
     {
@@ -180,6 +224,7 @@ struct lb_op {
 
 struct lb_solver {
   lb_config cfg;
+  Arena arena;                  // the caller's device memory, when cfg.arena is set
   int held_cus = 0;             // CUs reserved for a multi-workgroup reduction in flight
   lb::Layout lay;
   int L = 0;
@@ -389,10 +434,10 @@ void upload_mpo(lb_solver* s, const lb::Mpo& m, DevMpo& d, bool want32) {
         for (int i = 0; i < 2; ++i)
           for (int r = 0; r < x.r; ++r)
             h[((size_t)o * x.r + r) * (2 * x.l) + (size_t)l * 2 + i] = x.at(l, o, i, r);
-    d.d64[k].alloc(h.size() * sizeof(cd), s->stream);
+    d.d64[k].alloc(h.size() * sizeof(cd), s->stream, &s->arena);
     HIPCHK(hipMemcpyAsync(d.d64[k].p, h.data(), h.size() * sizeof(cd), hipMemcpyHostToDevice, s->stream));
     if (want32) {
-      d.d32[k].alloc(h.size() * 2 * sizeof(float), s->stream);
+      d.d32[k].alloc(h.size() * 2 * sizeof(float), s->stream, &s->arena);
       HIPCHK(lbk::to_f32(d.d64[k].d(), d.d32[k].f(), (long long)h.size(), s->stream));
     }
   }
@@ -900,26 +945,26 @@ void alloc_workspace(lb_solver* s) {
   hipStream_t st = s->stream;
   s->n_max = w.nmax;
   s->m_max = w.mmax;
-  s->C.alloc(w.C, st);
-  s->P.alloc(w.P, st);
-  s->T.alloc(w.T, st);
-  for (DevBuf* b : {&s->G, &s->G2, &s->Uf, &s->U0, &s->V}) b->alloc(w.nn, st);
-  s->ework.alloc(w.ework, st);
-  s->Bm.alloc(w.wide, st);
-  s->U2.alloc(w.wide, st);
-  s->lam.alloc(w.lam, st);
-  s->lam2.alloc(w.lam, st);
-  s->ws.alloc(w.ws, st);
-  s->info.alloc(WorkPlan::kSmall, st);
-  s->scratch.alloc(w.scratch, st);
+  s->C.alloc(w.C, st, &s->arena);
+  s->P.alloc(w.P, st, &s->arena);
+  s->T.alloc(w.T, st, &s->arena);
+  for (DevBuf* b : {&s->G, &s->G2, &s->Uf, &s->U0, &s->V}) b->alloc(w.nn, st, &s->arena);
+  s->ework.alloc(w.ework, st, &s->arena);
+  s->Bm.alloc(w.wide, st, &s->arena);
+  s->U2.alloc(w.wide, st, &s->arena);
+  s->lam.alloc(w.lam, st, &s->arena);
+  s->lam2.alloc(w.lam, st, &s->arena);
+  s->ws.alloc(w.ws, st, &s->arena);
+  s->info.alloc(WorkPlan::kSmall, st, &s->arena);
+  s->scratch.alloc(w.scratch, st, &s->arena);
   if (fp32(s)) {
-    s->CL.alloc(w.CL, st);
-    s->PL.alloc(w.PL, st);
-    s->TL.alloc(w.TL, st);
+    s->CL.alloc(w.CL, st, &s->arena);
+    s->PL.alloc(w.PL, st, &s->arena);
+    s->TL.alloc(w.TL, st, &s->arena);
   }
-  s->dd.alloc(table_bytes(s), st);
-  s->stat.alloc(sizeof(lbk::StepStat), st);
-  s->disc_dev.alloc((s->L + 1) * sizeof(double), st);
+  s->dd.alloc(table_bytes(s), st, &s->arena);
+  s->stat.alloc(sizeof(lbk::StepStat), st, &s->arena);
+  s->disc_dev.alloc((s->L + 1) * sizeof(double), st, &s->arena);
   s->hd.assign(table_len(s), 1);
 }
 
@@ -927,8 +972,8 @@ void alloc_state(lb_solver* s) {
   const int L = s->L;
   s->cap = state_caps(s, &s->site_cap);
   s->X.resize(L);
-  for (int i = 0; i < L; ++i) s->X[i].alloc(s->site_cap * 16, s->stream);
-  s->Xspare.alloc(s->site_cap * 16, s->stream);
+  for (int i = 0; i < L; ++i) s->X[i].alloc(s->site_cap * 16, s->stream, &s->arena);
+  s->Xspare.alloc(s->site_cap * 16, s->stream, &s->arena);
 }
 
 // Device bytes a solver holds once its generator and state are on the device
@@ -987,6 +1032,7 @@ void release_device(lb_solver* s) {
   s->cap.clear();
   s->gen_on_device = false;
   s->have_state = false;
+  s->arena.used = 0;   // every buffer carved from it is gone
 }
 
 void ensure_device(lb_solver* s) {
@@ -1008,7 +1054,7 @@ void ensure_generator_on_device(lb_solver* s) {
   HIPCHK(hipSetDevice(s->cfg.device));
   drop_graph(s);
   if (s->degree > 1) {
-    s->Wb0.alloc(s->h0.size() * sizeof(cd), s->stream);
+    s->Wb0.alloc(s->h0.size() * sizeof(cd), s->stream, &s->arena);
     HIPCHK(hipMemcpyAsync(s->Wb0.p, s->h0.data(), s->h0.size() * sizeof(cd), hipMemcpyHostToDevice, s->stream));
   }
   upload_mpo(s, s->kraus_dev, s->W, fp32(s));
@@ -1439,8 +1485,14 @@ lb_status lindblad_create(const lb_config* cfg, lb_solver** out) {
     if (!(cfg->tol >= 0.0) || cfg->tol >= 1.0) throw Fail(LB_ERR_ARG, "tol out of range");
     if (cfg->order != 1 && cfg->order != 2) throw Fail(LB_ERR_ARG, "order must be 1 or 2");
     if (cfg->precision != LB_FP64 && cfg->precision != LB_FP32_CONTRACT) throw Fail(LB_ERR_ARG, "bad precision");
+    if (cfg->arena && cfg->arena_bytes <= 0) throw Fail(LB_ERR_ARG, "arena without a size");
+    if (cfg->arena && ((uintptr_t)cfg->arena & 255)) throw Fail(LB_ERR_ARG, "arena not 256-byte aligned");
     auto s = std::make_unique<lb_solver>();
     s->cfg = *cfg;
+    if (cfg->arena) {
+      s->arena.base = static_cast<char*>(cfg->arena);
+      s->arena.size = (size_t)cfg->arena_bytes;
+    }
     s->lay = make_layout(*cfg);
     s->L = s->lay.n_sites;
     s->discarded.assign(s->L + 1, 0.0);
@@ -1959,12 +2011,13 @@ lb_status lindblad_observe(lb_solver* s, const lb_op* Oc, double out[2]) {
       need = std::max<size_t>(need, (size_t)s->chi[i] * 2 * wo[i + 1] * s->chi[i + 1]);
       need = std::max<size_t>(need, (size_t)s->chi[i + 1] * wo[i + 1] * s->chi[i + 1]);
     }
+    ArenaMark mark(s->arena, s->stream);
     DevBuf E, T1, T2;
-    E.alloc(need * 16, s->stream);
-    T1.alloc(need * 16, s->stream);
-    T2.alloc(need * 16, s->stream);
+    E.alloc(need * 16, s->stream, &s->arena);
+    T1.alloc(need * 16, s->stream, &s->arena);
+    T2.alloc(need * 16, s->stream, &s->arena);
     DevBuf res;
-    res.alloc(64, s->stream);
+    res.alloc(64, s->stream, &s->arena);
     for (int i = 0; i < L; ++i) {
       const int cl = s->chi[i], cr = s->chi[i + 1], ul = wo[i], vr = wo[i + 1];
       const void* Tin;
@@ -2005,10 +2058,11 @@ lb_status lindblad_trace_purity(lb_solver* s, double* trace, double* purity) {
     const int L = s->L;
     size_t need = 1;
     for (int i = 0; i < L; ++i) need = std::max<size_t>(need, (size_t)s->chi[i] * 2 * s->chi[i + 1]);
+    ArenaMark mark(s->arena, s->stream);
     DevBuf E, T1, res;
-    E.alloc(need * 16, s->stream);
-    T1.alloc(need * 16, s->stream);
-    res.alloc(64, s->stream);
+    E.alloc(need * 16, s->stream, &s->arena);
+    T1.alloc(need * 16, s->stream, &s->arena);
+    res.alloc(64, s->stream, &s->arena);
     for (int i = 0; i < L; ++i) {
       const int cl = s->chi[i], cr = s->chi[i + 1];
       const void* Tin;

@@ -170,3 +170,17 @@ def test_server_argument_errors_host_only():
         sv.result(0)
     s.close()
     sv.close()
+
+
+def test_arena_rejects_bad_arguments():
+    """An arena without a size, or not 256-byte aligned, is refused at create
+    (host-side validation, no device touched)."""
+    _lib_or_skip()
+    from paper_2605_27515_amd import api
+    from paper_2605_27515_amd._lib import LB_ERR_ARG
+    with pytest.raises(api.LindbladError) as e:
+        api.Solver([4], 8, 2, arena=4096, arena_bytes=0)
+    assert e.value.code == LB_ERR_ARG
+    with pytest.raises(api.LindbladError) as e:
+        api.Solver([4], 8, 2, arena=4096 + 8, arena_bytes=1 << 20)
+    assert e.value.code == LB_ERR_ARG
