@@ -40,6 +40,10 @@ import os
 import sys
 import time
 
+# one hardware queue per serving slot (HIP's default of 4 would funnel the
+# 16 slots' streams through 4 queues); read when the runtime starts
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+
 # hardware queues for the overlapping solves of the serving leg (HIP reads
 # this when it initialises, so it is set before torch is imported): at least
 # 16, one per slot (HIP's default is 4, which serialises the slots' streams)
@@ -106,7 +110,8 @@ def contraction_roofline(prof: dict, precision: str) -> dict:
     carries) and of the Gram GEMMs, the kernels the dense-contraction roofline
     applies to."""
     out = {}
-    for name, dt in (("gemm_contract", "f32" if precision == "fp32" else "f64"), ("gemm_gram", "f64")):
+    for name, dt in (("gemm_contract", "f32" if precision == "fp32" else "f64"), ("gemm_gram", "f64"),
+                     ("gemm_lead_f64", "f64")):
         p = prof.get(name)
         if not p or not p["ms"]:
             continue
@@ -167,7 +172,29 @@ def serve_once(built, slots: int, budget: int, arrivals):
     sv = api.Server(n_slots=slots, hbm_budget=budget)
     for (m, s, obs), t in zip(built, arrivals):
         sv.submit(s, m.init, m.steps, obs, arrival=float(t))
-    sv.run()
+    # the run blocks in the library (the GIL released); this thread reports
+    # each further eighth of the requests as it completes
+    import threading
+    err = []
+
+    def go():
+        try:
+            sv.run()
+        except Exception as e:   # noqa: BLE001 - re-raised below
+            err.append(e)
+
+    th = threading.Thread(target=go)
+    th.start()
+    step = max(1, len(built) // 8)
+    mark = step
+    while th.is_alive():
+        th.join(timeout=1.0)
+        done = sv.stats()["completed"]
+        if done >= mark:
+            print(f"bench: serving: {done} of {len(built)} requests done", file=sys.stderr, flush=True)
+            mark = (done // step + 1) * step
+    if err:
+        raise err[0]
     res = [sv.result(k) for k in range(len(built))]
     st = sv.stats()
     sv.close()
@@ -186,18 +213,24 @@ def serving(n_req: int, slots: int, budget_gb: float, n_base: int) -> dict:
     fast = build_requests(reqs, "fp32")
     plain = build_requests(reqs[:n_base], "fp64")
     build_s = time.perf_counter() - t0
+    print(f"bench: serving: {n_req} + {n_base} solvers built on the host in {build_s:.1f} s", file=sys.stderr,
+          flush=True)
     budget = int(budget_gb * (1 << 30))
     # burst: every request at t = 0
     res, st = serve_once(fast, slots, budget, [0.0] * n_req)
     burst = n_req / st["makespan"]
+    print(f"bench: serving: burst of {n_req} done in {st['makespan']:.1f} s", file=sys.stderr, flush=True)
     # Poisson stream at 0.7 x the burst rate
     rate = 0.7 * burst
     arr = wl.poisson_arrivals(n_req, rate)
     res_p, st_p = serve_once(fast, slots, budget, arr)
     lat = np.array([r["done"] - r["arrival"] for r in res_p])
+    print(f"bench: serving: Poisson stream done in {st_p['makespan']:.1f} s", file=sys.stderr, flush=True)
     # the baseline subsample one at a time in plain FP64, same arrivals
     res_b, st_b = serve_once(plain, 1, 0, arr[:n_base])
     lat_b = np.array([r["done"] - r["arrival"] for r in res_b])
+    print(f"bench: serving: FP64 one-at-a-time baseline done in {st_b['makespan']:.1f} s", file=sys.stderr,
+          flush=True)
     svc_b = np.array([r["done"] - r["admitted"] for r in res_b])
     # observables of the two forms (FP32 contractions vs plain FP64)
     dev = max(abs(a - b) / max(1.0, abs(b)) for r1, r2 in zip(res_p[:n_base], res_b)
@@ -411,8 +444,9 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=3, help="steps of the plain FP64 form timed beside")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--serve-requests", type=int, default=512,
-                    help="requests of the seeded serving stream (0: skip the serving leg)")
+    ap.add_argument("--serve-requests", type=int, default=256,
+                    help="requests of the seeded serving stream (its first N of 512; 512 runs the whole "
+                         "stream, ~7 min; 0: skip the serving leg)")
     ap.add_argument("--serve-baseline-requests", type=int, default=64,
                     help="requests of the plain-FP64 one-at-a-time baseline (the stream's first ones)")
     ap.add_argument("--chi256-steps", type=int, default=3, help="steps of the chi=256 leg (0: skip)")

@@ -89,7 +89,9 @@ lb_status lindblad_server_run(lb_server* sv);
  * LB_ERR_ARG (bad ticket), LB_ERR_STATE (not run yet). */
 lb_status lindblad_server_result(const lb_server* sv, int32_t ticket, lb_result* res, double* obs_out);
 
-/* Aggregate figures of the last run. */
+/* Aggregate figures of the last run, or of the run in progress when called
+ * from another thread while lindblad_server_run blocks (completed counts the
+ * requests finished so far). */
 lb_status lindblad_server_stats(const lb_server* sv, lb_server_stats* out);
 
 /* Destroy the server (not while it runs).  NULL is a no-op. */

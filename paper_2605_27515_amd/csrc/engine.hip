@@ -324,10 +324,11 @@ double eff_tol(const lb_solver* s, double t) {
 }
 double tau_warn(const lb_solver* s) { return s->cfg.tau_warn > 0.0 ? s->cfg.tau_warn : LB_TAU_WARN; }
 
+// PC_LEAD: the FP32 form's FP64 contractions of the Kraus MPO's leading part
 enum ProfClass { PC_CONTRACT = 0, PC_GRAM, PC_SVDGEMM, PC_HETRD, PC_STEBZ, PC_STEIN, PC_ORMTR, PC_JACOBI,
-                 PC_OTHER, PC_COUNT };
+                 PC_LEAD, PC_OTHER, PC_COUNT };
 const char* kProfNames[PC_COUNT] = {"gemm_contract", "gemm_gram", "gemm_svd", "hetrd", "stebz", "stein",
-                                    "ormtr", "jacobi", "other"};
+                                    "ormtr", "jacobi", "gemm_lead_f64", "other"};
 
 size_t prof_event(lb_solver* s) {
   if (s->ev_used == s->ev_pool.size()) {
@@ -1108,6 +1109,7 @@ void zipup(lb_solver* s) {
       // leading channel, both stages in FP64: P_L = C_L X_i, then
       // T_L{a'}[(s', v)][b] = WLt[(s', v)][(u, s)] P_L{a'}[(u, s)][b]
       const int ll = s->wlb[i], lr = s->wlb[i + 1];
+      s->cls = PC_LEAD;
       const void* PLp = s->X[0].p;
       if (i > 0) {
         mm(s, scaled(zk, ll), scaled(cr, 2), cl, s->CL.p, lbk::F64, cl, false, s->X[i].p, lbk::F64,
@@ -1116,6 +1118,7 @@ void zipup(lb_solver* s) {
       }
       mm(s, Dim(2 * lr), cr, Dim(2 * ll), s->WL.d64[i].p, lbk::F64, Dim(2 * ll), false, PLp, lbk::F64, cr,
          false, s->TL.p, lbk::F64, cr, lbk::F64, zk, Dim(0), scaled(cr, 2 * ll), scaled(cr, 2 * lr));
+      s->cls = PC_CONTRACT;
     }
     // stage 1: P[(a', u)][(s, b)] = C[(a', u)][a] X_i[a][(s, b)]
     const void* Pp;
@@ -1148,8 +1151,10 @@ void zipup(lb_solver* s) {
         const int ldg = n.hi;
         double* G = s->G.d();
         gram_rows(s, s->T.p, pw, n, m, m, G, ldg);
+        s->cls = PC_LEAD;
         mm(s, n, n, mL, s->TL.p, lbk::F64, mL, false, s->TL.p, lbk::F64, mL, true, G, lbk::F64, ldg, lbk::F64,
            Dim(1), Dim(0), Dim(0), Dim(0), 1.0, 1.0);
+        s->cls = PC_SVDGEMM;
         eig_trid(s, G, ldg, n, s->lam.d(), s->U0.d(), n, zc);
         refine_tail(s, true, {GramOp{s->T.p, pw, m, m}, GramOp{s->TL.p, lbk::F64, mL, mL}}, n, s->U0.d(), ldg,
                     s->lam.d());
@@ -1178,7 +1183,10 @@ void zipup(lb_solver* s) {
       } else {
         s->cls = PC_CONTRACT;
         mm(s, k, m, n, sv.U, lbk::F64, ldu, true, s->T.p, pw, m, false, s->C.p, pw, m, pw);
-        if (split) mm(s, k, mL, n, sv.U, lbk::F64, ldu, true, s->TL.p, lbk::F64, mL, false, s->CL.p, lbk::F64, mL, lbk::F64);
+        if (split) {
+          s->cls = PC_LEAD;
+          mm(s, k, mL, n, sv.U, lbk::F64, ldu, true, s->TL.p, lbk::F64, mL, false, s->CL.p, lbk::F64, mL, lbk::F64);
+        }
       }
     } else {
       // S2: purification truncation on the (Kraus x purification) columns

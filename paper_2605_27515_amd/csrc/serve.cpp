@@ -209,6 +209,8 @@ lb_status lindblad_server_result(const lb_server* sv, int32_t ticket, lb_result*
 
 lb_status lindblad_server_stats(const lb_server* sv, lb_server_stats* out) {
   if (!sv || !out) return LB_ERR_ARG;
+  lb_server* m = const_cast<lb_server*>(sv);   // the lock only
+  std::lock_guard<std::mutex> g(m->mu);
   *out = sv->stats;
   return LB_OK;
 }
