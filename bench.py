@@ -69,10 +69,11 @@ PEAKS = {  # MI355X published dense peaks
 ALU_CLASSES = {"hetrd", "stebz", "stein", "ormtr", "jacobi"}
 # HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this
 # workload, scaled by a plain 256 MiB copy (profiles/step_catbuffer_chi128_fp32_kernels.md);
-# hetrd is the dispatch-weighted mean over its instantiations (the
-# multi-workgroup form polls its mailboxes with agent-scope atomic loads,
-# which go to memory).  A kernel absent here reports traffic null
-PMC_TRAFFIC_BYTES = {"hetrd": 4.688e6}
+# hetrd is per reduction call (all instantiations a call launches, summed
+# over the run, divided by the calls; the multi-workgroup form polls its
+# mailboxes with agent-scope atomic loads, which go to memory).  A kernel
+# absent here reports traffic null
+PMC_TRAFFIC_BYTES = {"hetrd": 2.421e6}
 
 
 def workload():
