@@ -12,6 +12,7 @@ Oracle-K is the paper's second-order Kraus scheme (Sec. 5.2.2):
                                         + L_k U1 rho U1^dag L_k^dag)
            + (h^2/2) sum_{k,k'} L_k L_k' rho L_k'^dag L_k^dag
 followed by rho -> rho / Tr rho (trace renormalisation, end of Sec. 5.2.2).
+For pure states, rk4_pure_step is the global RK4 of Sec. 3.1.1 on Psi.
 The first-order scheme K = U + h L is also provided.  A time-dependent
 Hamiltonian is evaluated at the midpoint t + h/2 inside U1 and U1'.
 The purified form applies the same Kraus operators to a dense purification
@@ -156,3 +157,33 @@ def stability_factor(dm: DenseModel, h: float) -> dict:
     hn = float(np.linalg.norm(dm.H(0.0), 2))
     x = 0.5 * h * gmax
     return dict(x=x, damping=abs(1 - x + 0.5 * x * x) ** 2, h_norm=h * hn)
+
+
+# ---------------------------------------------------------------------------
+# Pure-state integrator: the global RK4 of the Schroedinger equation
+# ---------------------------------------------------------------------------
+
+def rk4_pure_step(dm: DenseModel, psi: np.ndarray, t: float, h: float) -> np.ndarray:
+    """One step of the explicit fourth-order Runge-Kutta scheme for
+    i dPsi/dt = H(t) Psi in the stage form of paper Sec. 3.1.1: stages with
+    H at t, t + h/2, t + h/2 and t + h, combined with weights 1, 2, 2, 1 over 6.
+    No renormalisation (the scheme conserves the norm to O(h^5))."""
+    p1 = -1j * (dm.H(t) @ psi)
+    p2 = -1j * (dm.H(t + 0.5 * h) @ (psi + 0.5 * h * p1))
+    p3 = -1j * (dm.H(t + 0.5 * h) @ (psi + 0.5 * h * p2))
+    p4 = -1j * (dm.H(t + h) @ (psi + h * p3))
+    return psi + (h / 6.0) * (p1 + 2.0 * p2 + 2.0 * p3 + p4)
+
+
+def rk4_pure_evolve(dm: DenseModel, psi: np.ndarray, h: float, n_steps: int, t0: float = 0.0):
+    t = t0
+    for _ in range(n_steps):
+        psi = rk4_pure_step(dm, psi, t, h)
+        t += h
+    return psi
+
+
+def rk4_pure_operator(dm: DenseModel, t: float, h: float) -> np.ndarray:
+    """The linear map of one RK4 step as a matrix (its action on the basis)."""
+    n = dm.H0.shape[0]
+    return rk4_pure_step(dm, np.eye(n, dtype=complex), t, h)

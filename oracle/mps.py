@@ -19,6 +19,10 @@ One step (paper Sec. 5.2 with the compression of Sec. 5.1):
   S4  tau = ||A_1||_F^2 (= Tr of the step's output); A_1 /= sqrt(tau).
 Truncation rule: keep the smallest k >= 1 whose discarded squared singular
 values sum to at most tol^2 times the total, then cap.
+
+Pure states (purification bond 1) also have the global RK4 of the
+Schroedinger equation (Sec. 3.1.1), built from exact MPO.MPS products and MPS
+sums, each compressed (rk4_pure_step).
 """
 from __future__ import annotations
 
@@ -222,3 +226,86 @@ def to_dense(sites, bits, site_order) -> np.ndarray:
 
 def bond_dims(sites) -> list[int]:
     return [A.shape[2] for A in sites[:-1]]
+
+
+# ---------------------------------------------------------------------------
+# Pure states: the global RK4 on an MPS (paper Sec. 3.1.1)
+# ---------------------------------------------------------------------------
+# A pure state is the same chain with a purification bond of size 1.
+
+def mpo_apply(sites, W) -> list[np.ndarray]:
+    """Exact MPO.MPS product: new site [(u, a), s', (v, b)] =
+    sum_s W[u, s', s, v] A[a, s, b] (bonds multiply; no truncation)."""
+    out = []
+    for A, w in zip(sites, W):
+        t = np.einsum('uxsv,asb->uaxvb', w, A)
+        u, a, x, v, b = t.shape
+        out.append(t.reshape(u * a, x, v * b))
+    return out
+
+
+def mps_add(x, y, cx: complex = 1.0, cy: complex = 1.0) -> list[np.ndarray]:
+    """cx X + cy Y as one MPS: the bonds side by side (block diagonal inside
+    the chain, concatenated on the two open ends; the last site's right bond,
+    the purification index, is shared)."""
+    n = len(x)
+    if n == 1:
+        return [cx * x[0] + cy * y[0]]
+    out = []
+    for i in range(n):
+        a, b = x[i], y[i]
+        if i == 0:
+            out.append(np.concatenate([cx * a, cy * b], axis=2))
+        elif i == n - 1:
+            out.append(np.concatenate([a, b], axis=0))
+        else:
+            la, d, ra = a.shape
+            lb, _, rb = b.shape
+            z = np.zeros((la + lb, d, ra + rb), complex)
+            z[:la, :, :ra] = a
+            z[la:, :, ra:] = b
+            out.append(z)
+    return out
+
+
+def compress(sites, tol: float, chi: int | None = None) -> list[np.ndarray]:
+    """Left-to-right QR sweep (exact), then a right-to-left truncated-SVD
+    sweep with the tolerance rule and the cap; the norm stays in site 1 (no
+    renormalisation)."""
+    s = [x.copy() for x in sites]
+    for i in range(len(s) - 1):
+        l, d, r = s[i].shape
+        q, rr = np.linalg.qr(s[i].reshape(l * d, r))
+        s[i] = q.reshape(l, d, q.shape[1])
+        s[i + 1] = np.einsum('kb,bsc->ksc', rr, s[i + 1])
+    for i in range(len(s) - 1, 0, -1):
+        l, d, r = s[i].shape
+        u, sv, vh = svd(s[i].reshape(l, d * r))
+        k = keep_rank(sv, tol, chi)
+        s[i] = vh[:k].reshape(k, d, r)
+        s[i - 1] = np.einsum('asb,bk->ask', s[i - 1], u[:, :k] * sv[None, :k])
+    return s
+
+
+def rk4_pure_step(sites, H, t: float, h: float, tol: float, chi: int | None = None):
+    """One global RK4 step on an MPS, in the paper's stage order (Sec. 3.1.1):
+    Psi1 = -iH(t)Psi0, Psi2 = -iH(t+h/2)(Psi0 + h/2 Psi1),
+    Psi3 = -iH(t+h/2)(Psi0 + h/2 Psi2), Psi4 = -iH(t+h)(Psi0 + h Psi3),
+    Psi(t+h) = Psi0 + h/6 (Psi1 + 2 Psi2 + 2 Psi3 + Psi4).  Every MPO.MPS
+    product and every sum is compressed at (tol, chi); no renormalisation.
+    H(t) returns the MPO of the Hamiltonian at time t."""
+    def app(tt, x):
+        return compress(mpo_apply(x, H(tt)), tol, chi)
+
+    def add(x, y, cy):
+        return compress(mps_add(x, y, 1.0, cy), tol, chi)
+
+    p0 = sites
+    p1 = [-1j * a if i == 0 else a for i, a in enumerate(app(t, p0))]
+    p2 = [-1j * a if i == 0 else a for i, a in enumerate(app(t + 0.5 * h, add(p0, p1, 0.5 * h)))]
+    p3 = [-1j * a if i == 0 else a for i, a in enumerate(app(t + 0.5 * h, add(p0, p2, 0.5 * h)))]
+    p4 = [-1j * a if i == 0 else a for i, a in enumerate(app(t + h, add(p0, p3, h)))]
+    acc = add(p1, p2, 2.0)
+    acc = add(acc, p3, 2.0)
+    acc = add(acc, p4, 1.0)
+    return add(p0, acc, h / 6.0)

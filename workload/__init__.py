@@ -135,6 +135,24 @@ def model_two_photon_cat(R: int = 8, alpha2: float = 8.0, kappa2: float = 1.0,
                  init=[vacuum(1 << R)], dt=dt, steps=steps, chi=chi, chi_mu=chi_mu)
 
 
+def model_driven_kerr(R: int = 8, omega0: float = 1.0, kerr: float = 1.0 / 25.0, alpha0: complex = 4.0,
+                      drive: bool = True, dt: float = 1e-3, steps: int = 1000, chi: int = 64,
+                      tol: float = 1e-8) -> Model:
+    """Driven Kerr oscillator of the pure-state benchmark (paper Sec. 3.2):
+    H(t) = w0 a^dag a + (K/2) a^dag^2 a^2 + f(t)(a^2 + a^dag^2),
+    f(t) = (2/100) cos(sqrt(2) t) + (2 pi/100) cos(sqrt(3) t), coherent start
+    |alpha0>, no jumps; a pure state (purification rank 1)."""
+    H0 = [(omega0, {0: ("NUM_POW", 1)})]
+    if kerr != 0.0:
+        H0.append((0.5 * kerr, {0: ("ADAG_A", 2, 2)}))
+    H1, drv = [], []
+    if drive:
+        H1 = [(1.0, {0: ("A_POW", 2)}), (1.0, {0: ("ADAG_POW", 2)})]
+        drv = [(2.0 / 100.0, math.sqrt(2.0), 0.0), (2.0 * math.pi / 100.0, math.sqrt(3.0), 0.0)]
+    return Model(name="driven-kerr", bits=[R], H0=H0, H1=H1, drive=drv, jumps=[],
+                 init=[coherent_amplitudes(1 << R, alpha0)], dt=dt, steps=steps, chi=chi, chi_mu=1, tol=tol)
+
+
 def model_cat_buffer(Ra: int = 8, Rb: int = 8, alpha2: float = 8.0, g2: float = 1.0,
                      kappa_b: float = 10.0, kappa_a: float = 1e-3, dt: float = 2.5e-5,
                      steps: int = 200, chi: int = 128, chi_mu: int = 16) -> Model:
