@@ -83,7 +83,11 @@ typedef struct lb_config {
   double tol;                      /* relative Frobenius truncation tolerance    */
   double tol_zip;                  /* zip-up tolerance; <= 0: tol / 10 (LB_FP64),
                                       tol (LB_FP32_CONTRACT)                    */
-  int32_t order;                   /* Kraus scheme order: 1 or 2                 */
+  int32_t order;                   /* 1 or 2: the Kraus scheme of that order
+                                      (Sec. 5.2.2); 4: the global RK4 of the
+                                      Schroedinger equation on a pure state
+                                      (Sec. 3.1.1; no jumps, chi_mu_cap 1, the
+                                      norm not renormalised)                   */
   int32_t precision;               /* enum lb_precision                          */
   int32_t allow_unstable;          /* nonzero: skip the dt stability check       */
   void* stream;                    /* hipStream_t to use; NULL = a private stream */
@@ -191,7 +195,15 @@ typedef struct lb_drive {          /* f(t) = sum_j coef_j cos(omega_j t + phase_
  * Errors: LB_ERR_ARG, LB_ERR_UNSTABLE (|1 - x + x^2/2| > 1 with
  * x = dt * G/2 and G = sum_k ||L_k||^2 bounded by the triangle inequality
  * over each jump's terms, unless cfg.allow_unstable), LB_ERR_OOM,
- * LB_ERR_HIP. */
+ * LB_ERR_HIP.
+ * With cfg.order == 4 the step is one step of RK4 (paper Sec. 3.1.1), its
+ * four stages multiplied out into one MPO P(t) = 1 + a sum of the words in
+ * H0 and H1 of length 1..4 (one channel of site 0's left index per word with
+ * a drive, combined on the device with f at t, t + dt/2 and t + dt; the
+ * degree-4 Taylor polynomial of exp(-i dt H0) without one), applied to the
+ * pure state by the same zip-up and compressed; n_jumps must be 0
+ * (LB_ERR_ARG) and dt * (||H0|| + max|f| ||H1||) must be at most 2.8, inside
+ * RK4's stability interval (LB_ERR_UNSTABLE unless cfg.allow_unstable). */
 lb_status lindblad_set_generator(lb_solver* s, const lb_op* H0, const lb_op* H1,
                                  const lb_drive* f, const lb_op* const* L,
                                  int32_t n_jumps, double dt);

@@ -239,6 +239,7 @@ struct lb_solver {
   double dt = 0.0;
   int n_kraus = 0, degree = 1;
   std::vector<double> drv_c, drv_w, drv_p;
+  lbk::Rk4Words rk4w;     // order 4 with a drive: the words of the boundary index
   lb::Mpo kraus;          // host copy: leading part (+) increment (direct sum)
   lb::Mpo lead;           // leading part (canonical gauge), the FP32 form's FP64 channel
   lb::Mpo kraus_dev;      // as uploaded (site 0 zeroed when a drive refreshes it)
@@ -1078,6 +1079,12 @@ void refresh_drive(lb_solver* s) {
   dp.dt = s->dt;
   const long long count = (long long)2 * s->W.wr[0] * 2 * 1;
   Timed tmr(s, PC_OTHER, 8.0 * count * s->degree, 16.0 * count * (s->degree + 1));
+  if (s->cfg.order == 4) {
+    HIPCHK(lbk::rk4_boundary_step(s->Wb0.d(), s->wb0_stride, s->rk4w, dp,
+                                  reinterpret_cast<const lbk::StepStat*>(s->stat.p), s->W.d64[0].d(),
+                                  fp32(s) ? s->W.d32[0].f() : nullptr, count, s->stream));
+    return;
+  }
   HIPCHK(lbk::boundary_contract_step(s->Wb0.d(), s->wb0_stride, s->degree, dp,
                                      reinterpret_cast<const lbk::StepStat*>(s->stat.p), s->W.d64[0].d(),
                                      fp32(s) ? s->W.d32[0].f() : nullptr, count, s->stream));
@@ -1303,8 +1310,10 @@ void enqueue_step(lb_solver* s) {
   zipup(s);
   back_sweep(s, eff_tol(s, s->cfg.tol), true, sweep_bounds(s));
   Timed tm(s, PC_OTHER, s->prof_on ? 8.0 * hv(s, dchi(s, 1, s->cap[1])) : 0.0, 0.0);
+  // the Kraus maps renormalise the trace; the pure-state RK4 keeps the norm
   HIPCHK(lbk::normalize_step(s->X[0].d(), scaled(dchi(s, 1, s->cap[1]), 2),
-                             reinterpret_cast<lbk::StepStat*>(s->stat.p), tau_warn(s), s->stream, ddp(s)));
+                             reinterpret_cast<lbk::StepStat*>(s->stat.p), tau_warn(s), s->stream, ddp(s),
+                             s->cfg.order != 4));
 }
 
 // Co-resident workgroups any reduction of a step may need.
@@ -1491,7 +1500,7 @@ lb_status lindblad_create(const lb_config* cfg, lb_solver** out) {
     if (cfg->chi_mu_cap < 1 || cfg->chi_mu_cap > 256) throw Fail(LB_ERR_ARG, "chi_mu_cap out of range");
     if (cfg->chi_zip_cap < 0 || cfg->chi_zip_cap > 256) throw Fail(LB_ERR_ARG, "chi_zip_cap out of range");
     if (!(cfg->tol >= 0.0) || cfg->tol >= 1.0) throw Fail(LB_ERR_ARG, "tol out of range");
-    if (cfg->order != 1 && cfg->order != 2) throw Fail(LB_ERR_ARG, "order must be 1 or 2");
+    if (cfg->order != 1 && cfg->order != 2 && cfg->order != 4) throw Fail(LB_ERR_ARG, "order must be 1, 2 or 4");
     if (cfg->precision != LB_FP64 && cfg->precision != LB_FP32_CONTRACT) throw Fail(LB_ERR_ARG, "bad precision");
     if (cfg->arena && cfg->arena_bytes <= 0) throw Fail(LB_ERR_ARG, "arena without a size");
     if (cfg->arena && ((uintptr_t)cfg->arena & 255)) throw Fail(LB_ERR_ARG, "arena not 256-byte aligned");
@@ -1588,48 +1597,103 @@ lb_status lindblad_set_generator(lb_solver* s, const lb_op* H0, const lb_op* H1,
     Mpo eye = mpo_identity(L);
     auto c = [&](const Mpo& m) { return mpo_compress(m, tol); };
     auto add = [&](const Mpo& a, const Mpo& b) { return c(mpo_add(a, b)); };
-    // The family split by order in h: the leading part (the identity of the
-    // first member, sqrt(h/2) L_k of the mixed members; sqrt(h) L_k at first
-    // order) and the increment (U1 - 1 or U1' - 1, and the mixed members with
-    // U1 - 1 in place of U1), each compressed on its own, so the increment is
-    // not rounded at the scale of the identity.  d1: polynomial coefficients
-    // (in the drive f) of U1 - 1.
-    std::vector<Mpo> d1{c(mpo_scale(A, cd(0.0, -h)))};
-    if (drive) d1.push_back(c(mpo_scale(B, cd(0.0, -h))));
     const Mpo zero = mpo_zero(L);
     std::vector<Mpo> leadm{eye};
     std::vector<std::vector<Mpo>> fam;
-    if (s->cfg.order == 1) {
-      fam.push_back(d1);
-      for (auto& l : Lm) {
-        leadm.push_back(c(mpo_scale(l, std::sqrt(h))));
-        fam.push_back({zero});
-      }
-    } else {
-      Mpo A2 = c(mpo_mul(A, A));
-      std::vector<Mpo> dp{add(d1[0], mpo_scale(A2, -0.5 * h * h))};
+    if (s->cfg.order == 4) {
+      // Pure-state global RK4 (one member, K = 1): P = 1 + sum of words in
+      // H0, H1 of length 1..4 with the coefficients of rk4_word_coef; the
+      // identity is the leading part.  Without a drive the words are the
+      // powers of H0 and P is one MPO (the degree-4 Taylor polynomial);
+      // with one, each word is a channel of site 0's left index (31 with the
+      // empty word) and the step combines them with coefficients from f at
+      // t, t + h/2, t + h.
+      if (n_jumps != 0) throw Fail(LB_ERR_ARG, "order 4 (pure-state RK4) takes no jump operators");
+      double hn = lb::norm_bound(H0->terms, s->lay);
       if (drive) {
-        Mpo AB = add(c(mpo_mul(A, B)), c(mpo_mul(B, A)));
-        dp.push_back(add(d1[1], mpo_scale(AB, -0.5 * h * h)));
-        dp.push_back(c(mpo_scale(c(mpo_mul(B, B)), -0.5 * h * h)));
+        double fmax = 0.0;
+        for (int j = 0; j < f->n; ++j) fmax += std::fabs(f->coef[j]);
+        hn += fmax * lb::norm_bound(H1->terms, s->lay);
       }
-      fam.push_back(dp);
-      const double sq = std::sqrt(h / 2.0);
-      for (auto& l : Lm) {
-        std::vector<Mpo> v;
-        for (auto& p : d1) v.push_back(c(mpo_scale(c(mpo_mul(p, l)), sq)));
-        fam.push_back(v);
+      // RK4's stability interval on the imaginary axis is |h lambda| <= 2 sqrt 2
+      if (h * hn > 2.8 && !s->cfg.allow_unstable)
+        throw Fail(LB_ERR_UNSTABLE, "dt too large for the explicit RK4: h ||H|| <= " + std::to_string(h * hn));
+      std::vector<Mpo> words;
+      s->rk4w = lbk::Rk4Words{};
+      if (!drive) {
+        Mpo pw = H0->mpo, sum;
+        for (int len = 1; len <= 4; ++len) {
+          double cr, ci;
+          lbk::rk4_word_coef(len, 0u, h, 0.0, 0.0, 0.0, &cr, &ci);
+          Mpo t = c(mpo_scale(pw, cd(cr, ci)));
+          sum = (len == 1) ? t : add(sum, t);
+          if (len < 4) pw = c(mpo_mul(pw, H0->mpo));
+        }
+        words.push_back(sum);
+      } else {
+        // channel 0 is the empty word: the leading part (the identity) sits in
+        // channel 0 of the direct sum, so its coefficient must be 1; the
+        // increment has the zero MPO there
+        words.push_back(zero);
+        s->rk4w.len[0] = 0;
+        s->rk4w.bits[0] = 0u;
+        s->rk4w.n = 1;
+        for (int len = 1; len <= 4; ++len)
+          for (unsigned bits = 0; bits < (1u << len); ++bits) {
+            Mpo w = ((bits >> (len - 1)) & 1u) ? B : H0->mpo;
+            for (int k = len - 2; k >= 0; --k) w = c(mpo_mul(((bits >> k) & 1u) ? B : H0->mpo, w));
+            // channel p holds h^L times its word, so that the channels are of
+            // comparable size (~(h ||H||)^L) when they are stacked and
+            // compressed together: unscaled, H0^4 would set the tolerance of
+            // the joint compression ~1e12 times above the size of H1 alone
+            words.push_back(c(mpo_scale(w, cd(std::pow(h, len), 0.0))));
+            s->rk4w.len[s->rk4w.n] = len;
+            s->rk4w.bits[s->rk4w.n] = bits;
+            s->rk4w.n++;
+          }
       }
-      for (auto& l : Lm) {
-        std::vector<Mpo> v;
-        for (auto& p : d1) v.push_back(c(mpo_scale(c(mpo_mul(l, p)), sq)));
-        fam.push_back(v);
+      fam.push_back(words);
+    } else {
+      // The family split by order in h: the leading part (the identity of the
+      // first member, sqrt(h/2) L_k of the mixed members; sqrt(h) L_k at first
+      // order) and the increment (U1 - 1 or U1' - 1, and the mixed members with
+      // U1 - 1 in place of U1), each compressed on its own, so the increment is
+      // not rounded at the scale of the identity.  d1: polynomial coefficients
+      // (in the drive f) of U1 - 1.
+      std::vector<Mpo> d1{c(mpo_scale(A, cd(0.0, -h)))};
+      if (drive) d1.push_back(c(mpo_scale(B, cd(0.0, -h))));
+      if (s->cfg.order == 1) {
+        fam.push_back(d1);
+        for (auto& l : Lm) {
+          leadm.push_back(c(mpo_scale(l, std::sqrt(h))));
+          fam.push_back({zero});
+        }
+      } else {
+        Mpo A2 = c(mpo_mul(A, A));
+        std::vector<Mpo> dp{add(d1[0], mpo_scale(A2, -0.5 * h * h))};
+        if (drive) {
+          Mpo AB = add(c(mpo_mul(A, B)), c(mpo_mul(B, A)));
+          dp.push_back(add(d1[1], mpo_scale(AB, -0.5 * h * h)));
+          dp.push_back(c(mpo_scale(c(mpo_mul(B, B)), -0.5 * h * h)));
+        }
+        fam.push_back(dp);
+        const double sq = std::sqrt(h / 2.0);
+        for (auto& l : Lm) {
+          std::vector<Mpo> v;
+          for (auto& p : d1) v.push_back(c(mpo_scale(c(mpo_mul(p, l)), sq)));
+          fam.push_back(v);
+        }
+        for (auto& l : Lm) {
+          std::vector<Mpo> v;
+          for (auto& p : d1) v.push_back(c(mpo_scale(c(mpo_mul(l, p)), sq)));
+          fam.push_back(v);
+        }
+        for (auto& l : Lm)
+          for (auto& lp : Lm) fam.push_back({c(mpo_scale(c(mpo_mul(l, lp)), h / std::sqrt(2.0)))});
+        for (int rep = 0; rep < 2; ++rep)
+          for (auto& l : Lm) leadm.push_back(c(mpo_scale(l, sq)));
+        for (size_t j = 0; j < Lm.size() * Lm.size(); ++j) leadm.push_back(zero);
       }
-      for (auto& l : Lm)
-        for (auto& lp : Lm) fam.push_back({c(mpo_scale(c(mpo_mul(l, lp)), h / std::sqrt(2.0)))});
-      for (int rep = 0; rep < 2; ++rep)
-        for (auto& l : Lm) leadm.push_back(c(mpo_scale(l, sq)));
-      for (size_t j = 0; j < Lm.size() * Lm.size(); ++j) leadm.push_back(zero);
     }
     int degree = 1;
     for (auto& f2 : fam) degree = std::max(degree, (int)f2.size());

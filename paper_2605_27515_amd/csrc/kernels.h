@@ -181,8 +181,10 @@ struct StepStat {
 // The end of a step: tau = sum |x|^2 over count complex128 values, x /=
 // sqrt(tau), and the step's status folded into *st (one workgroup): a
 // non-finite or zero tau sets err bit 0, tau > 1 + tau_warn sets warn.
+// rescale = false keeps x (the pure-state RK4 does not renormalise) and only
+// records tau.
 hipError_t normalize_step(double* x, Dim count, StepStat* st, double tau_warn, hipStream_t stream,
-                          const int* dd = nullptr);
+                          const int* dd = nullptr, bool rescale = true);
 
 // dst[e] = src[e] for e < count complex128 values.
 hipError_t copy_elems(const double* src, double* dst, Dim count, hipStream_t stream, const int* dd = nullptr);
@@ -216,6 +218,57 @@ struct DriveParams {
 hipError_t boundary_contract_step(const double* Wb, long long stride, int degree, const DriveParams& f,
                                   const StepStat* st, double* W0, float* W0f, long long count,
                                   hipStream_t stream);
+
+// One step of the global RK4 for i dPsi/dt = H(t) Psi (paper Sec. 3.1.1) is
+// the operator P = 1 + h/6 A1 + 2h/3 A2 + h/6 A3 + h^2/6 (A2 A1 + A2 A2 + A3 A2)
+// + h^3/12 (A2 A2 A1 + A3 A2 A2) + h^4/24 A3 A2 A2 A1 with A_j = -i H(t_j),
+// t_1 = t, t_2 = t + h/2, t_3 = t + h (the stages multiplied out).  With
+// H(t) = H0 + f(t) H1 it is a sum over the words X_{b_1} ... X_{b_L} (X_0 = H0,
+// X_1 = H1, L <= 4); rk4_word_coef gives the word's coefficient: letter k
+// (leftmost first) is bit k of `bits`, f_j = f(t_j); the empty word (L = 0)
+// is the identity with coefficient 1.
+__host__ __device__ inline void rk4_word_coef(int L, unsigned bits, double h, double f1, double f2, double f3,
+                                              double* re, double* im) {
+  if (L == 0) {   // the empty word: the identity, coefficient 1
+    *re = 1.0;
+    *im = 0.0;
+    return;
+  }
+  // the terms of P by length: weight (in units of h^L) and stage of each factor
+  const double f[4] = {0.0, f1, f2, f3};
+  double sum = 0.0;
+  auto term = [&](double wgt, int a, int b, int c, int d) {
+    const int st[4] = {a, b, c, d};
+    double v = wgt;
+    for (int k = 0; k < L; ++k) v *= ((bits >> k) & 1u) ? f[st[k]] : 1.0;
+    sum += v;
+  };
+  if (L == 1) { term(1.0 / 6.0, 1, 0, 0, 0); term(2.0 / 3.0, 2, 0, 0, 0); term(1.0 / 6.0, 3, 0, 0, 0); }
+  if (L == 2) { term(1.0 / 6.0, 2, 1, 0, 0); term(1.0 / 6.0, 2, 2, 0, 0); term(1.0 / 6.0, 3, 2, 0, 0); }
+  if (L == 3) { term(1.0 / 12.0, 2, 2, 1, 0); term(1.0 / 12.0, 3, 2, 2, 0); }
+  if (L == 4) { term(1.0 / 24.0, 3, 2, 2, 1); }
+  double hl = 1.0;
+  for (int k = 0; k < L; ++k) hl *= h;
+  sum *= hl;
+  // times (-i)^L
+  const int m = L & 3;
+  *re = (m == 0) ? sum : (m == 2) ? -sum : 0.0;
+  *im = (m == 1) ? -sum : (m == 3) ? sum : 0.0;
+}
+
+// The words of an RK4 boundary index: word p has length len[p] and letters
+// bits[p] (as rk4_word_coef).
+struct Rk4Words {
+  int n = 0;
+  int len[32];
+  unsigned bits[32];
+};
+// W0[e] = sum_p c_p(t) Wb[p*stride + e] with c_p the RK4 coefficient of word p
+// at t = steps * dt (the step about to run), f from the drive parameters,
+// without its factor dt^L, which channel p carries (complex128 and an
+// optional complex64 copy).
+hipError_t rk4_boundary_step(const double* Wb, long long stride, const Rk4Words& words, const DriveParams& f,
+                             const StepStat* st, double* W0, float* W0f, long long count, hipStream_t stream);
 
 // out[0] + i out[1] = sum_j E[j*ld + j] (complex128 trace of an n x n block)
 hipError_t diag_sum(const double* E, int n, long long ld, double* out, hipStream_t stream);

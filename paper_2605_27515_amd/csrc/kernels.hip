@@ -707,7 +707,7 @@ hipError_t normalize(double* x, long long count, double* tau_out, int* flag, hip
 
 // The same sum in the same order, then the step's status
 __global__ __launch_bounds__(256) void normalize_step_kernel(double* x, Dim countD, const int* dd, StepStat* st,
-                                                             double tau_warn) {
+                                                             double tau_warn, int rescale) {
   __shared__ double red[256];
   const long long count = dim_val(countD, dd);
   double acc = 0.0;
@@ -724,7 +724,8 @@ __global__ __launch_bounds__(256) void normalize_step_kernel(double* x, Dim coun
   const double tau = red[0];
   const bool ok = isfinite(tau) && tau > 0.0;
   const double f = ok ? 1.0 / sqrt(tau) : 1.0;
-  for (long long e = threadIdx.x; e < 2 * count; e += 256) x[e] *= f;
+  if (rescale)
+    for (long long e = threadIdx.x; e < 2 * count; e += 256) x[e] *= f;
   if (threadIdx.x == 0) {
     st->tau = tau;
     if (!ok) st->err |= 1;
@@ -735,8 +736,9 @@ __global__ __launch_bounds__(256) void normalize_step_kernel(double* x, Dim coun
   }
 }
 
-hipError_t normalize_step(double* x, Dim count, StepStat* st, double tau_warn, hipStream_t s, const int* dd) {
-  hipLaunchKernelGGL(normalize_step_kernel, dim3(1), dim3(256), 0, s, x, count, dd, st, tau_warn);
+hipError_t normalize_step(double* x, Dim count, StepStat* st, double tau_warn, hipStream_t s, const int* dd,
+                          bool rescale) {
+  hipLaunchKernelGGL(normalize_step_kernel, dim3(1), dim3(256), 0, s, x, count, dd, st, tau_warn, rescale ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -828,6 +830,45 @@ hipError_t boundary_contract_step(const double* Wb, long long stride, int degree
   const int blocks = (int)std::min<long long>((count + 255) / 256, 1024);
   hipLaunchKernelGGL(boundary_step_kernel, dim3(blocks), dim3(256), 0, s, Wb, stride, degree, f, st, W0, W0f,
                      count);
+  return hipGetLastError();
+}
+
+__global__ void rk4_boundary_kernel(const double* Wb, long long stride, Rk4Words wd, DriveParams dp,
+                                    const StepStat* st, double* W0, float* W0f, long long count) {
+  __shared__ double cr[32], ci[32];
+  const double h = dp.dt, t = (double)st->steps * h;
+  if (threadIdx.x < (unsigned)wd.n) {
+    double fv[3];
+    for (int q = 0; q < 3; ++q) {
+      const double tq = t + 0.5 * h * q;
+      double f = 0.0;
+      for (int j = 0; j < dp.n; ++j) f += dp.c[j] * cos(dp.w[j] * tq + dp.p[j]);
+      fv[q] = f;
+    }
+    // the channels carry the factor h^L themselves (unit h here)
+    rk4_word_coef(wd.len[threadIdx.x], wd.bits[threadIdx.x], 1.0, fv[0], fv[1], fv[2], &cr[threadIdx.x],
+                  &ci[threadIdx.x]);
+  }
+  __syncthreads();
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < count;
+       e += (long long)gridDim.x * blockDim.x) {
+    double vr = 0.0, vi = 0.0;
+    for (int p = 0; p < wd.n; ++p) {
+      const double ar = Wb[2 * (p * stride + e)], ai = Wb[2 * (p * stride + e) + 1];
+      vr += cr[p] * ar - ci[p] * ai;
+      vi += cr[p] * ai + ci[p] * ar;
+    }
+    W0[2 * e] = vr; W0[2 * e + 1] = vi;
+    if (W0f) { W0f[2 * e] = (float)vr; W0f[2 * e + 1] = (float)vi; }
+  }
+}
+
+hipError_t rk4_boundary_step(const double* Wb, long long stride, const Rk4Words& words, const DriveParams& f,
+                             const StepStat* st, double* W0, float* W0f, long long count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (f.n < 0 || f.n > 8 || words.n < 1 || words.n > 32) return hipErrorInvalidValue;
+  const int blocks = (int)std::min<long long>((count + 255) / 256, 1024);
+  hipLaunchKernelGGL(rk4_boundary_kernel, dim3(blocks), dim3(256), 0, s, Wb, stride, words, f, st, W0, W0f, count);
   return hipGetLastError();
 }
 

@@ -184,3 +184,57 @@ def test_arena_rejects_bad_arguments():
     with pytest.raises(api.LindbladError) as e:
         api.Solver([4], 8, 2, arena=4096 + 8, arena_bytes=1 << 20)
     assert e.value.code == LB_ERR_ARG
+
+
+@pytest.mark.parametrize("drive", [False, True])
+def test_host_rk4_mpo_matches_dense_step(drive):
+    """order = 4 (pure-state global RK4, paper Sec. 3.1.1): without a drive the
+    host MPO is the dense RK4 step operator of the oracle; with one, the dense
+    step operator at several t lies in the span of the 31 channels (the empty word and the 30 words) of
+    site 0's boundary index plus the identity (the coefficients are the device's, checked by
+    the GPU parity tests)."""
+    _lib_or_skip()
+    from paper_2605_27515_amd import api
+    m = wl.model_driven_kerr(R=4, alpha0=1.5, drive=drive, dt=1e-2)
+    s = api.solver_from_model(m, order=4, chi=16, chi_mu=1, state="none")
+    W = s.kraus_sites()
+    so = m.site_order()
+    dm = dense.DenseModel(m)
+    bonds, nk = s.kraus_info()
+    assert nk == 1
+    if not drive:
+        assert W[0].shape[0] == 1
+        P = tt.mpo_to_dense(W, m.bits, so)
+        assert np.abs(P - dense.rk4_pure_operator(dm, 0.0, m.dt)).max() < 1e-12
+    else:
+        D = W[0].shape[0]
+        assert D == 31
+        chans = []
+        for p in range(D):
+            e = np.zeros(D)
+            e[p] = 1.0
+            chans.append(tt.mpo_to_dense(tt.contract_boundary(W, list(e)), m.bits, so).ravel())
+        # the leading part (the identity) sits in channel 0 beside its word
+        eye = np.eye(16, dtype=complex).ravel()
+        chans[0] = chans[0] - eye
+        A = np.array([eye] + chans).T
+        for t in (0.0, 0.37, 1.9):
+            P = dense.rk4_pure_operator(dm, t, m.dt).ravel()
+            c, *_ = np.linalg.lstsq(A, P, rcond=None)
+            assert np.abs(A @ c - P).max() < 1e-11
+            assert abs(c[0] - 1.0) < 1e-9
+    s.close()
+
+
+def test_rk4_order_refuses_jumps_and_unstable_dt():
+    _lib_or_skip()
+    from paper_2605_27515_amd import api
+    from paper_2605_27515_amd._lib import LB_ERR_ARG, LB_ERR_UNSTABLE
+    m = wl.model_driven_kerr(R=8, dt=1e-2)
+    with pytest.raises(api.LindbladError) as e:
+        api.solver_from_model(m, order=4, chi=16, chi_mu=1, state="none")
+    assert e.value.code == LB_ERR_UNSTABLE
+    m = wl.model_coherent_loss()
+    with pytest.raises(api.LindbladError) as e:
+        api.solver_from_model(m, order=4, chi=16, chi_mu=1, state="none")
+    assert e.value.code == LB_ERR_ARG
