@@ -313,6 +313,55 @@ def chi256_leg(steps: int, precision: str) -> dict:
             "bonds": d["bonds"], "cap_bonds": cap, "bonds_at_cap": d["bonds"] == cap, "chi_mu": d["chi_mu"]}
 
 
+def kerr_rk4_main(args) -> None:
+    """Pure-state global RK4 (paper Sec. 3.1.1) on the driven Kerr oscillator
+    at the paper's parameters (Sec. 3.2: R = 8, w0 = 1, K = 1/25, alpha0 = 4,
+    the two-frequency drive, tol 1e-8): steps/s of both forms and their
+    distance to the dense scheme."""
+    import numpy as np
+    import torch
+    import workload as wl
+    from oracle import dense, mps
+    from paper_2605_27515_amd import api
+    m = wl.model_driven_kerr(R=8, dt=args.kerr_dt)
+    n_run = args.kerr_steps
+    dm = dense.DenseModel(m)
+    ref = dense.rk4_pure_evolve(dm, dm.psi0, m.dt, n_run)
+    rr = np.outer(ref, ref.conj())
+    aop = np.diag(np.sqrt(np.arange(1, 256)), 1)
+    a_ref = np.vdot(ref, aop @ ref)
+    out = {}
+    for prec in ("fp32", "fp64"):
+        s = api.solver_from_model(m, precision=prec, order=4, chi=64, chi_mu=1, device=0)
+        if args.warmup:
+            s.step(args.warmup)
+            s.close()
+            s = api.solver_from_model(m, precision=prec, order=4, chi=64, chi_mu=1, device=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(n_run)
+        s.sync()
+        elapsed = time.perf_counter() - t0
+        X = s.get_state_mps()
+        a = s.observe(s.mpo([(1.0, {0: ("A_POW", 1)})]))
+        bonds = s.diagnostics()["bonds"]
+        s.close()
+        psi = mps.to_dense(X, m.bits, m.site_order())[:, 0]
+        err = float(np.abs(np.outer(psi, psi.conj()) - rr).max() / np.abs(rr).max())
+        out[prec] = {"steps_per_s": n_run / elapsed, "rho_max_rel_error_vs_dense": err,
+                     "a_abs_error_vs_dense": float(abs(a - a_ref)), "bonds": bonds}
+        print(f"bench: kerr RK4 {prec}: {n_run / elapsed:.1f} steps/s, rho error {err:.2e}, bonds {bonds}",
+              file=sys.stderr, flush=True)
+    line = {"metric": "pure-state global RK4 steps/s, driven Kerr oscillator", "value": out[args.precision]["steps_per_s"],
+            "unit": "steps/s", "n_gpus": 1, "steps": n_run, "warmup": args.warmup,
+            "ms_per_step": 1e3 / out[args.precision]["steps_per_s"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32+f64" if args.precision == "fp32" else "f64", "data": "synthetic",
+            "config": {"workload": f"driven Kerr oscillator, 2^8 Fock levels (8 sites), K=1/25, alpha0=4, "
+                                   f"two-frequency drive, dt={m.dt}, tol=1e-8, chi=64", "precision": args.precision},
+            "forms": out, "a_dense": [a_ref.real, a_ref.imag]}
+    print(json.dumps(line), flush=True)
+
+
 def zgate_main(args) -> None:
     """Cat-qubit Z gate at the paper's scan point N_a = 2^8, N_b = 2^4,
     |alpha|^2 = N_a / 3 (paper Sec. 6.2): the whole gate, timed, and its
@@ -453,9 +502,12 @@ def main():
     ap.add_argument("--chi256-steps", type=int, default=3, help="steps of the chi=256 leg (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
-    ap.add_argument("--workload", choices=["chi128", "cat-zgate", "chi128-trajectory"], default="chi128",
+    ap.add_argument("--kerr-steps", type=int, default=1000, help="steps of the kerr-rk4 workload")
+    ap.add_argument("--kerr-dt", type=float, default=1e-3, help="time step of the kerr-rk4 workload")
+    ap.add_argument("--workload", choices=["chi128", "cat-zgate", "chi128-trajectory", "kerr-rk4"], default="chi128",
                     help="chi128: the step benchmark (default); cat-zgate: the whole cat-qubit Z gate; "
-                         "chi128-trajectory: the same configuration run as physics from vacuum")
+                         "chi128-trajectory: the same configuration run as physics from vacuum; "
+                         "kerr-rk4: the pure-state RK4 on the driven Kerr oscillator")
     ap.add_argument("--trajectory-steps", type=int, default=5000)
     ap.add_argument("--zgate-dt", type=float, default=2e-4, help="largest time step of the Z-gate run")
     ap.add_argument("--zgate-chi", type=int, default=128, help="bond cap of the Z-gate run")
@@ -477,6 +529,9 @@ def main():
         return
     if args.workload == "chi128-trajectory":
         trajectory_main(args)
+        return
+    if args.workload == "kerr-rk4":
+        kerr_rk4_main(args)
         return
     print(f"bench: {args.precision} steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
     if args.copy_calibration:
