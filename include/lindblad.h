@@ -111,6 +111,19 @@ typedef struct lb_config {
                                       does not fit fails its call with
                                       LB_ERR_OOM                                */
   int64_t arena_bytes;             /* size of the arena (> 0 when it is set)   */
+  int32_t fixed_bounds;            /* nonzero: every launch of a step is sized
+                                      for the caps.  0 (default): while the
+                                      bonds stay far below the caps, steps
+                                      run under launch bounds of a power of
+                                      two, at least 16 and at least twice the
+                                      largest bond (a "tier"), in checked
+                                      runs; a run in which a truncation was
+                                      capped by the tier below what the caps
+                                      allow is undone and run again under a
+                                      larger tier, so results are those of
+                                      the caps up to rounding.  The undo keeps
+                                      a second copy of the state (counted by
+                                      lindblad_footprint)                      */
 } lb_config;
 
 #define LB_TAU_WARN 1e-3
@@ -251,10 +264,15 @@ lb_status lindblad_get_state_mps(lb_solver* s, int32_t* bonds, double** sites);
 
 /* Enqueue n_steps steps of the Kraus map (zip-up application, purification
  * truncation, right-to-left truncated-SVD sweep, trace renormalisation) on
- * the solver's stream and return without waiting for them: the truncation
- * ranks each step decides stay on the device, where the kernels that follow
- * read them, and the step is launched as one captured HIP graph (direct
- * launches while kernel timing is on).  What the steps find surfaces at the
+ * the solver's stream: the truncation ranks each step decides stay on the
+ * device, where the kernels that follow read them, and the step is launched
+ * as one captured HIP graph per launch tier (direct launches while kernel
+ * timing is on).  With cfg.fixed_bounds, or from lindblad_step_batch, every
+ * step is bounded by the caps and the call returns without waiting.
+ * Otherwise the steps go in runs of up to 32, each under the tier of the
+ * bonds it starts from (see lb_config.fixed_bounds), with a wait between
+ * runs; a run under a tier below the caps is also waited for and checked
+ * before the call goes on, a run at the caps is not.  What the steps find surfaces at the
  * next call that waits for the stream (lindblad_sync, observe,
  * trace_purity, get_state_mps, diagnostics): LB_ERR_NUMERIC for non-finite
  * eigenvalues (also what a timed-out multi-workgroup reduction leaves) or a
@@ -321,6 +339,9 @@ typedef struct lb_diag {
   int32_t zip_bonds[LB_MAX_SITES]; /* last step's zip-up ranks                   */
   double discarded[LB_MAX_SITES];  /* last step's relative discarded weights:
                                       [0] purification, [1..] back-sweep bonds  */
+  int32_t tier;                    /* launch tier of the last step; 0: caps    */
+  int64_t bound_redos;             /* steps undone and run again under a larger
+                                      tier since the solver was created        */
 } lb_diag;
 
 /* Diagnostics of the last step (waits for the stream).  Errors:

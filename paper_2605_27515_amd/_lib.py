@@ -42,7 +42,8 @@ class LbConfig(C.Structure):
                 ("precision", C.c_int32), ("allow_unstable", C.c_int32),
                 ("stream", C.c_void_p), ("device", C.c_int32),
                 ("fp32_tol_floor", C.c_double), ("tau_warn", C.c_double),
-                ("arena", C.c_void_p), ("arena_bytes", C.c_int64)]
+                ("arena", C.c_void_p), ("arena_bytes", C.c_int64),
+                ("fixed_bounds", C.c_int32)]
 
 
 class LbFactor(C.Structure):
@@ -65,7 +66,8 @@ class LbDiag(C.Structure):
                 ("max_tau_defect", C.c_double), ("n_sites", C.c_int32),
                 ("bonds", C.c_int32 * LB_MAX_SITES), ("chi_mu", C.c_int32),
                 ("zip_bonds", C.c_int32 * LB_MAX_SITES),
-                ("discarded", C.c_double * LB_MAX_SITES)]
+                ("discarded", C.c_double * LB_MAX_SITES), ("tier", C.c_int32),
+                ("bound_redos", C.c_int64)]
 
 
 class LbProfile(C.Structure):

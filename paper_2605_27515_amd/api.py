@@ -65,7 +65,7 @@ class Solver:
                  precision: str = "fp64", chi_zip: int = 0, tol_zip: float = 0.0,
                  site_order=None, stream: int | None = None, device: int = 0,
                  allow_unstable: bool = False, fp32_tol_floor: float = 0.0, tau_warn: float = 0.0,
-                 arena: int | None = None, arena_bytes: int = 0):
+                 arena: int | None = None, arena_bytes: int = 0, fixed_bounds: bool = False):
         lib = L.load()
         cfg = L.LbConfig()
         lib.lindblad_default_config(C.byref(cfg))
@@ -91,6 +91,7 @@ class Solver:
         cfg.tau_warn = float(tau_warn)
         cfg.arena = arena
         cfg.arena_bytes = int(arena_bytes)
+        cfg.fixed_bounds = 1 if fixed_bounds else 0
         h = C.c_void_p()
         _check(lib.lindblad_create(C.byref(cfg), C.byref(h)), "create")
         self.h = h
@@ -221,7 +222,8 @@ class Solver:
         return dict(steps=d.steps, t=d.t, tau=d.tau, max_tau_defect=d.max_tau_defect,
                     bonds=[d.bonds[i] for i in range(n - 1)], chi_mu=d.chi_mu,
                     zip_bonds=[d.zip_bonds[i] for i in range(n)],
-                    discarded=[d.discarded[i] for i in range(n)])
+                    discarded=[d.discarded[i] for i in range(n)], tier=d.tier,
+                    bound_redos=d.bound_redos)
 
     def profile(self, enable: bool = True, classes=None):
         """Reset and switch live kernel timing on or off; `classes` limits it to

@@ -273,10 +273,25 @@ struct lb_solver {
   std::vector<int> zkhi;      // bounds of the zip-up carry ranks
   int err_bits = 0;           // error bits found by a wait (sticky until set_state)
   long long steps_done = 0;   // steps completed on the device (last wait)
-  // one step captured as a graph (none while timing, or if capture failed)
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  bool graph_failed = false;
+  // one step captured as a graph per launch-bound tier (none while timing,
+  // or if capture failed)
+  struct StepGraph {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    bool failed = false;
+  };
+  std::map<int, StepGraph> graphs;
+  // launch bounds of the step: tier 0 sizes every launch for the caps; tier
+  // b > 0 bounds every bond, zip-up rank and purification rank by b as well,
+  // for states far below the caps (a truncation that the tier caps is
+  // detected, the step undone and run again with a larger tier)
+  int tier = 0;
+  std::vector<int> bnd;        // bond bounds of the current tier (min(cap, tier))
+  bool unsynced = false;       // steps enqueued since the last wait
+  long long tier_redos = 0;    // steps run again with a larger tier
+  bool in_batch = false;       // stepping as part of lindblad_step_batch
+  DevBuf bk;                   // the state before a tiered step: sites, size
+                               // table, status and discards
   size_t ws_bytes = 0;
   int n_max = 0;
   long long m_max = 0;
@@ -314,6 +329,12 @@ bool fp32(const lb_solver* s) { return s->cfg.precision == LB_FP32_CONTRACT; }
 // part as a channel of its own beside the increment
 int mpo_bond(const lb_solver* s, int i) { return s->wb[i] + (fp32(s) ? s->wlb[i] : 0); }
 int passes(const lb_solver* s) { return fp32(s) ? 1 : 2; }
+
+// Caps of the zip-up and purification truncations: the configured ones, and
+// those of the current launch-bound tier
+int zcap_full(const lb_solver* s) { return s->cfg.chi_zip_cap > 0 ? s->cfg.chi_zip_cap : s->cfg.chi_cap; }
+int zcap(const lb_solver* s) { return s->tier > 0 ? std::min(zcap_full(s), s->tier) : zcap_full(s); }
+int mucap(const lb_solver* s) { return s->tier > 0 ? std::min(s->cfg.chi_mu_cap, s->tier) : s->cfg.chi_mu_cap; }
 
 // Truncation tolerance of the back-sweep and the purification cut: tol, or
 // for the FP32 form a floor under it when the caller sets one (a guard
@@ -544,6 +565,7 @@ void copy_out(lb_solver* s, void* dst, const void* src, size_t bytes) {
 void wait_stream(lb_solver* s) {
   HIPCHK(hipStreamSynchronize(s->stream));
   release_cus(s);
+  s->unsynced = false;
   if (!s->gen_on_device) return;
   copy_out(s, s->hd.data(), s->dd.p, s->hd.size() * sizeof(int));
   lbk::StepStat st;
@@ -869,18 +891,29 @@ std::vector<int> state_caps(const lb_solver* s, size_t* site_cap) {
 
 // Bounds of the carry rows entering each zip-up site: zkhi[0] = 1 and the
 // rank after site i is at most min(chi_zip, rows 2 zk, columns w chi).
-std::vector<int> zip_bounds(const lb_solver* s, const std::vector<int>& cap) {
+std::vector<int> zip_bounds(const lb_solver* s, const std::vector<int>& cap, int tierb = 0) {
   const int L = s->L;
-  const int zc = s->cfg.chi_zip_cap > 0 ? s->cfg.chi_zip_cap : s->cfg.chi_cap;
+  const int zc = tierb > 0 ? std::min(zcap_full(s), tierb) : zcap_full(s);
+  const int mu = tierb > 0 ? std::min(s->cfg.chi_mu_cap, tierb) : s->cfg.chi_mu_cap;
   std::vector<int> zk(L + 1, 1);
   for (int i = 1; i < L; ++i) {
     const long long cols = (long long)mpo_bond(s, i) * cap[i];
     zk[i] = (int)std::min<long long>(std::min<long long>(zc, 2LL * zk[i - 1]), cols);
   }
   // purification rank after the last cut
-  zk[L] = (int)std::min<long long>(std::min<long long>(s->cfg.chi_mu_cap, 2LL * zk[L - 1]),
+  zk[L] = (int)std::min<long long>(std::min<long long>(mu, 2LL * zk[L - 1]),
                                    (long long)s->n_kraus * cap[L]);
   return zk;
+}
+
+// Launch bounds for tier b (0: the caps): bonds min(cap, b), zip-up ranks
+// and purification rank under the tier's caps.
+void set_tier(lb_solver* s, int b) {
+  s->tier = b;
+  s->bnd = s->cap;
+  if (b > 0)
+    for (int i = 1; i <= s->L; ++i) s->bnd[i] = std::min(s->cap[i], b);
+  s->zkhi = zip_bounds(s, s->bnd, b);
 }
 
 // Byte sizes of the workspace buffers.
@@ -942,6 +975,14 @@ WorkPlan work_plan(const lb_solver* s, const std::vector<int>& cap) {
 
 size_t table_bytes(const lb_solver* s) { return (size_t)table_len(s) * sizeof(int); }
 
+// Bytes of the backup that lets a tiered step be undone: every site at its
+// capacity, the size table, the step status and the discarded weights.
+size_t backup_bytes(const lb_solver* s, size_t site_cap) {
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  return (size_t)s->L * al(site_cap * 16) + al(table_bytes(s)) + al(sizeof(lbk::StepStat)) +
+         al((size_t)(s->L + 1) * sizeof(double));
+}
+
 void alloc_workspace(lb_solver* s) {
   const WorkPlan w = work_plan(s, s->cap);
   hipStream_t st = s->stream;
@@ -976,6 +1017,7 @@ void alloc_state(lb_solver* s) {
   s->X.resize(L);
   for (int i = 0; i < L; ++i) s->X[i].alloc(s->site_cap * 16, s->stream, &s->arena);
   s->Xspare.alloc(s->site_cap * 16, s->stream, &s->arena);
+  if (!s->cfg.fixed_bounds) s->bk.alloc(backup_bytes(s, s->site_cap), s->stream, &s->arena);
 }
 
 // Device bytes a solver holds once its generator and state are on the device
@@ -999,14 +1041,16 @@ size_t footprint_bytes(const lb_solver* s) {
     if (fp32(s)) t += size_class(e * 8);
   }
   if (s->degree > 1) t += size_class(s->h0.size() * sizeof(cd));
+  if (!s->cfg.fixed_bounds) t += size_class(backup_bytes(s, site_cap));
   return t;
 }
 
 void drop_graph(lb_solver* s) {
-  if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
-  if (s->graph) (void)hipGraphDestroy(s->graph);
-  s->gexec = nullptr;
-  s->graph = nullptr;
+  for (auto& kv : s->graphs) {
+    if (kv.second.x) (void)hipGraphExecDestroy(kv.second.x);
+    if (kv.second.g) (void)hipGraphDestroy(kv.second.g);
+  }
+  s->graphs.clear();
 }
 
 // Free every device buffer of the solver (state, workspace, MPOs); the host
@@ -1018,6 +1062,7 @@ void release_device(lb_solver* s) {
   for (auto& x : s->X) x.release();
   s->X.clear();
   s->Xspare.release();
+  s->bk.release();
   for (DevBuf* b : {&s->C, &s->P, &s->T, &s->Bm, &s->G, &s->G2, &s->U2, &s->Uf, &s->U0, &s->V, &s->lam,
                     &s->lam2, &s->ws, &s->info, &s->scratch, &s->ework, &s->dd, &s->stat, &s->disc_dev, &s->CL,
                     &s->PL, &s->TL})
@@ -1063,7 +1108,7 @@ void ensure_generator_on_device(lb_solver* s) {
   if (fp32(s)) upload_mpo(s, s->lead, s->WL, false);
   if (s->cap.empty()) alloc_state(s);
   alloc_workspace(s);
-  s->zkhi = zip_bounds(s, s->cap);
+  set_tier(s, 0);
   s->gen_on_device = true;
 }
 
@@ -1103,8 +1148,9 @@ void zipup(lb_solver* s) {
   // rounding of the O(sqrt h) jump members puts noise singular values near
   // 1e-9 of the largest, which a zip-up at tol / 10 would keep
   const double tolz = s->cfg.tol_zip > 0 ? s->cfg.tol_zip : (f32 ? s->cfg.tol : s->cfg.tol / 10.0);
-  const int zc = s->cfg.chi_zip_cap > 0 ? s->cfg.chi_zip_cap : s->cfg.chi_cap;
-  const std::vector<int>& cap = s->cap;
+  const int zc = zcap(s), mu = mucap(s);
+  const std::vector<int>& cap = s->bnd;
+  int* over = &reinterpret_cast<lbk::StepStat*>(s->stat.p)->over;
   const std::vector<int>& zh = s->zkhi;
   for (int i = 0; i < L; ++i) {
     const Dim zk = dzk(s, i, zh[i]);            // rows of the carry (new left bond)
@@ -1173,7 +1219,8 @@ void zipup(lb_solver* s) {
       {
         Timed tm(s, PC_OTHER, 0.0, s->prof_on ? 8.0 * hv(s, n) : 0.0);
         HIPCHK(lbk::truncate_rank(s->lam.d(), n, tolz, zc, s->dd.i() + sl_zk(s, i + 1), nullptr,
-                                  &reinterpret_cast<lbk::StepStat*>(s->stat.p)->err, s->stream, ddp(s)));
+                                  &reinterpret_cast<lbk::StepStat*>(s->stat.p)->err, s->stream, ddp(s),
+                                  zcap_full(s), over));
       }
       timed_sync(s);
       const Dim k = dzk(s, i + 1, zh[i + 1]);
@@ -1211,7 +1258,7 @@ void zipup(lb_solver* s) {
       double* Gc = s->G.d();
       gram_cols(s, Tl, pl, n, m, m, Gc, ldv);
       double* V0 = s->U0.d();
-      eig_trid(s, Gc, ldv, m, s->lam.d(), V0, m, passes(s) == 1 ? s->cfg.chi_mu_cap : 0);
+      eig_trid(s, Gc, ldv, m, s->lam.d(), V0, m, passes(s) == 1 ? mu : 0);
       if (passes(s) == 1) refine_tail(s, false, {GramOp{Tl, pl, m, n}}, m, V0, ldv, s->lam.d());
       double* Vf = V0;
       const void* Asrc = Tl;
@@ -1231,9 +1278,9 @@ void zipup(lb_solver* s) {
       }
       {
         Timed tm(s, PC_OTHER, 0.0, s->prof_on ? 8.0 * hv(s, m) : 0.0);
-        HIPCHK(lbk::truncate_rank(s->lam.d(), m, eff_tol(s, s->cfg.tol), s->cfg.chi_mu_cap, s->dd.i() + sl_zk(s, L),
+        HIPCHK(lbk::truncate_rank(s->lam.d(), m, eff_tol(s, s->cfg.tol), mu, s->dd.i() + sl_zk(s, L),
                                   s->disc_dev.d(), &reinterpret_cast<lbk::StepStat*>(s->stat.p)->err, s->stream,
-                                  ddp(s)));
+                                  ddp(s), s->cfg.chi_mu_cap, over));
       }
       timed_sync(s);
       const Dim k = dzk(s, L, zh[L]);
@@ -1255,17 +1302,18 @@ void back_sweep(lb_solver* s, double tol, bool record, const std::vector<int>& l
   const int L = s->L;
   for (int i = L - 1; i >= 1; --i) {
     const Dim l = dchi(s, i, lhi[i]);
-    const Dim r = (i == L - 1) ? dchi(s, L, lhi[L]) : dkb(s, i + 1, std::min(s->cap[i + 1], lhi[i + 1]));
+    const Dim r = (i == L - 1) ? dchi(s, L, lhi[L]) : dkb(s, i + 1, std::min(s->bnd[i + 1], lhi[i + 1]));
     const Dim m = scaled(r, 2);
-    const int kmax = std::min(s->cap[i], lhi[i]);
+    const int kmax = std::min(s->bnd[i], lhi[i]);
     s->cls = PC_SVDGEMM;
     const Svd sv = left_svd(s, s->X[i].p, lbk::F64, l, m, m, passes(s) == 2, capped(l, kmax));
     const int ldu = l.hi;
     {
       Timed tm(s, PC_OTHER, 0.0, s->prof_on ? 8.0 * hv(s, l) : 0.0);
-      HIPCHK(lbk::truncate_rank(s->lam.d(), l, tol, s->cap[i], s->dd.i() + sl_kb(s, i),
+      HIPCHK(lbk::truncate_rank(s->lam.d(), l, tol, s->bnd[i], s->dd.i() + sl_kb(s, i),
                                 record ? s->disc_dev.d() + i : nullptr,
-                                &reinterpret_cast<lbk::StepStat*>(s->stat.p)->err, s->stream, ddp(s)));
+                                &reinterpret_cast<lbk::StepStat*>(s->stat.p)->err, s->stream, ddp(s), s->cap[i],
+                                &reinterpret_cast<lbk::StepStat*>(s->stat.p)->over));
     }
     timed_sync(s);
     const Dim k = dkb(s, i, kmax);
@@ -1309,9 +1357,9 @@ void enqueue_step(lb_solver* s) {
   refresh_drive(s);
   zipup(s);
   back_sweep(s, eff_tol(s, s->cfg.tol), true, sweep_bounds(s));
-  Timed tm(s, PC_OTHER, s->prof_on ? 8.0 * hv(s, dchi(s, 1, s->cap[1])) : 0.0, 0.0);
+  Timed tm(s, PC_OTHER, s->prof_on ? 8.0 * hv(s, dchi(s, 1, s->bnd[1])) : 0.0, 0.0);
   // the Kraus maps renormalise the trace; the pure-state RK4 keeps the norm
-  HIPCHK(lbk::normalize_step(s->X[0].d(), scaled(dchi(s, 1, s->cap[1]), 2),
+  HIPCHK(lbk::normalize_step(s->X[0].d(), scaled(dchi(s, 1, s->bnd[1]), 2),
                              reinterpret_cast<lbk::StepStat*>(s->stat.p), tau_warn(s), s->stream, ddp(s),
                              s->cfg.order != 4));
 }
@@ -1320,7 +1368,7 @@ void enqueue_step(lb_solver* s) {
 int step_coresident(const lb_solver* s) {
   int nmax = 1;
   for (int i = 0; i < s->L; ++i) nmax = std::max(nmax, 2 * s->zkhi[i]);
-  nmax = std::max(nmax, s->n_kraus * s->cap[s->L]);
+  nmax = std::max(nmax, s->n_kraus * s->bnd[s->L]);
   for (int i = 1; i < s->L; ++i) nmax = std::max(nmax, s->zkhi[i]);
   return lbk::trid_coresident_workgroups(std::min(nmax, 512));
 }
@@ -1328,7 +1376,8 @@ int step_coresident(const lb_solver* s) {
 // Capture one step into a graph (once per generator and state layout); a
 // capture that fails leaves the solver on direct launches.
 void ensure_graph(lb_solver* s) {
-  if (s->gexec || s->graph_failed) return;
+  lb_solver::StepGraph& sg = s->graphs[s->tier];
+  if (sg.x || sg.failed) return;
   hipGraph_t g = nullptr;
   // relaxed: the capture constrains no API call of this or any other thread
   // (solvers on other threads keep allocating and copying meanwhile)
@@ -1343,7 +1392,7 @@ void ensure_graph(lb_solver* s) {
   if (!ok || e != hipSuccess || !g) {
     (void)hipGetLastError();
     if (g) (void)hipGraphDestroy(g);
-    s->graph_failed = true;
+    sg.failed = true;
     if (!ok) throw Fail(LB_ERR_HIP, "enqueueing a step failed during graph capture");
     return;
   }
@@ -1351,11 +1400,97 @@ void ensure_graph(lb_solver* s) {
   if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess || !x) {
     (void)hipGetLastError();
     (void)hipGraphDestroy(g);
-    s->graph_failed = true;
+    sg.failed = true;
     return;
   }
-  s->graph = g;
-  s->gexec = x;
+  sg.g = g;
+  sg.x = x;
+}
+
+// Enqueue one step under the current tier: its graph when there is one,
+// else the launches themselves (always while timing).
+void launch_step(lb_solver* s) {
+  if (!s->prof_on) {
+    ensure_graph(s);
+    const lb_solver::StepGraph& sg = s->graphs[s->tier];
+    if (sg.x) {
+      HIPCHK(hipGraphLaunch(sg.x, s->stream));
+      return;
+    }
+  }
+  enqueue_step(s);
+  if (s->prof_on) prof_flush(s);
+}
+
+// The largest bound any launch of a step takes at tier 0.
+int top_bound(const lb_solver* s) {
+  int t = std::max(zcap_full(s), s->cfg.chi_mu_cap);
+  for (int i = 1; i <= s->L; ++i) t = std::max(t, s->cap[i]);
+  return t;
+}
+
+// Tier for a state with bonds s->chi: the smallest power of two, at least 16,
+// that is no less than twice the largest bond (a step grows a bond by less
+// than that in all but rare steps); 0 once that reaches every cap.
+int pick_tier(const lb_solver* s) {
+  int m = 1;
+  for (int i = 1; i <= s->L; ++i) m = std::max(m, s->chi[i]);
+  int b = 16;
+  while (b < 2 * m) b *= 2;
+  return b >= top_bound(s) ? 0 : b;
+}
+
+// Copy the live state (sites at the bonds s->chi, size table, status,
+// discarded weights) into the backup, or the backup back into it.
+void backup_state(lb_solver* s, bool save) {
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  char* bk = static_cast<char*>(s->bk.p);
+  lbk::CopyList cl;
+  auto add = [&](void* live, size_t off, size_t bytes) {
+    if (cl.n == 48) {
+      HIPCHK(lbk::copy_list(cl, s->stream));
+      cl.n = 0;
+    }
+    cl.src[cl.n] = save ? live : static_cast<void*>(bk + off);
+    cl.dst[cl.n] = save ? static_cast<void*>(bk + off) : live;
+    cl.words[cl.n] = (long long)(bytes / 4);
+    ++cl.n;
+  };
+  size_t off = 0;
+  for (int i = 0; i < s->L; ++i) {
+    add(s->X[i].p, off, (size_t)s->chi[i] * 2 * s->chi[i + 1] * sizeof(cd));
+    off += al(s->site_cap * 16);
+  }
+  add(s->dd.p, off, table_bytes(s));
+  off += al(table_bytes(s));
+  add(s->stat.p, off, sizeof(lbk::StepStat));
+  off += al(sizeof(lbk::StepStat));
+  add(s->disc_dev.p, off, (size_t)(s->L + 1) * sizeof(double));
+  HIPCHK(lbk::copy_list(cl, s->stream));
+}
+
+// A run of steps under tier b (0: the caps), enqueued behind the call.  For
+// b > 0 the state is kept first and the run is checked once enqueued: when
+// a truncation of any of its steps was capped by the tier's bounds below what
+// the caps allow, the run is undone and enqueued again under the next tier
+// (twice b, or the caps), so the result is the one the caps give.
+void step_run(lb_solver* s, int b, int run) {
+  if (b > 0 && !s->bk.p) throw Fail(LB_ERR_STATE, "no backup for a tiered step");
+  if (b > 0) backup_state(s, true);
+  for (;;) {
+    if (s->tier != b) set_tier(s, b);
+    reserve_cus(s, step_coresident(s));
+    for (int j = 0; j < run; ++j) launch_step(s);
+    s->unsynced = true;
+    if (b == 0) return;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    lbk::StepStat st;
+    copy_out(s, &st, s->stat.p, sizeof(st));
+    if (!st.over) return;
+    backup_state(s, false);
+    ++s->tier_redos;
+    b = 2 * b >= top_bound(s) ? 0 : 2 * b;
+  }
 }
 
 void canonicalize(lb_solver* s, const std::vector<int>& bonds) {
@@ -1775,6 +1910,7 @@ static lb_status load_mps(lb_solver* s, const std::vector<int>& bonds, const std
   // nothing of the previous state is in flight after this wait
   HIPCHK(hipStreamSynchronize(s->stream));
   release_cus(s);
+  if (s->tier != 0) set_tier(s, 0);
   for (int i = 0; i < L; ++i) {
     const size_t cnt = (size_t)bonds[i] * 2 * bonds[i + 1];
     if (cnt > s->site_cap) throw Fail(LB_ERR_ARG, "site exceeds the capacity implied by the caps");
@@ -1930,14 +2066,22 @@ lb_status lindblad_step(lb_solver* s, int32_t n_steps) {
     HIPCHK(hipSetDevice(s->cfg.device));
     check_err(s);   // the state is invalid after a failed step until set_state
     if (n_steps == 0) return LB_OK;
-    if (!s->prof_on) ensure_graph(s);
-    reserve_cus(s, step_coresident(s));
-    for (int k = 0; k < n_steps; ++k) {
-      if (s->gexec && !s->prof_on) {
-        HIPCHK(hipGraphLaunch(s->gexec, s->stream));
-      } else {
-        enqueue_step(s);
-        if (s->prof_on) prof_flush(s);
+    if (s->cfg.fixed_bounds || s->prof_on || s->in_batch || !s->bk.p) {
+      // every launch bounded by the caps; the steps run behind the call
+      if (s->tier != 0) set_tier(s, 0);
+      reserve_cus(s, step_coresident(s));
+      for (int k = 0; k < n_steps; ++k) launch_step(s);
+      s->unsynced = true;
+    } else {
+      // bounds follow the state: runs of up to kRun steps, each under the
+      // tier of the bonds it starts from, with a wait between runs
+      constexpr int kRun = 32;
+      if (s->unsynced) wait_stream(s);
+      for (int k = 0; k < n_steps && !s->err_bits;) {
+        const int run = std::min(n_steps - k, kRun);
+        step_run(s, pick_tier(s), run);
+        k += run;
+        if (k < n_steps) wait_stream(s);
       }
     }
     s->steps += n_steps;
@@ -1998,7 +2142,9 @@ lb_status lindblad_step_batch(lb_solver* const* ss, int32_t n, int32_t n_steps) 
           HIPCHK(hipSetDevice(s->cfg.device));
         }
       }
+      s->in_batch = true;
       rc[j] = lindblad_step(s, n_steps);
+      s->in_batch = false;
       if (rc[j] != LB_OK) msg[j] = g_last_error;
     }
     // the batch returns when all its steps are done
@@ -2178,6 +2324,8 @@ lb_status lindblad_diagnostics(lb_solver* s, lb_diag* out) {
     out->chi_mu = s->chi.empty() ? 0 : s->chi[s->L];
     for (int i = 0; i < s->L && i < (int)s->zip_bonds.size(); ++i) out->zip_bonds[i] = s->zip_bonds[i];
     for (int i = 0; i < s->L && i < (int)s->discarded.size(); ++i) out->discarded[i] = s->discarded[i];
+    out->tier = s->tier;
+    out->bound_redos = s->tier_redos;
     check_err(s);
     return LB_OK;
   } catch (const Fail& f) {

@@ -131,9 +131,12 @@ hipError_t orthonormalize_columns(double* U, int ldu, Dim n, Dim k, double* S, d
 // smallest k >= 1 with sum_{j>k} lam_j <= tol^2 sum_j lam_j, then min(k, cap);
 // negative noise is clamped to zero.  Writes k to *k_out and the relative
 // discarded weight to *disc_out; a non-finite eigenvalue sets bit 1 of *err
-// (err may be nullptr).
+// (err may be nullptr).  When cap is a tighter launch bound than the real cap
+// full_cap (> cap) and the rule keeps more than cap, *over is set to 1 (over
+// may be nullptr): the result then differs from one under the real cap.
 hipError_t truncate_rank(const double* lam, Dim n, double tol, int cap, int* k_out,
-                         double* disc_out, int* err, hipStream_t stream, const int* dd = nullptr);
+                         double* disc_out, int* err, hipStream_t stream, const int* dd = nullptr,
+                         int full_cap = 0, int* over = nullptr);
 
 // dst[i*ldd + j] = src[i*lds + j] * (scale_cols ? sqrt(max(lam_j,0)) : 1) for
 // i < rows, j < cols (complex128).
@@ -176,7 +179,10 @@ struct StepStat {
   long long steps;     // steps completed since set_state (drives the clock)
   int err;             // bit 0: non-finite trace; bit 1: non-finite eigenvalues
   int warn;            // a step with |tau - 1| > tau_warn since the last read
-  double pad[4];
+  int over;            // a truncation kept fewer values than the rule and the
+                       // real cap allow because a tighter launch bound capped it
+  int pad0;
+  double pad[3];
 };
 // The end of a step: tau = sum |x|^2 over count complex128 values, x /=
 // sqrt(tau), and the step's status folded into *st (one workgroup): a
@@ -185,6 +191,16 @@ struct StepStat {
 // records tau.
 hipError_t normalize_step(double* x, Dim count, StepStat* st, double tau_warn, hipStream_t stream,
                           const int* dd = nullptr, bool rescale = true);
+
+// Several device-to-device copies in one launch: entry j copies words[j]
+// 32-bit words from src[j] to dst[j] (disjoint ranges).
+struct CopyList {
+  int n = 0;
+  const void* src[48];
+  void* dst[48];
+  long long words[48];
+};
+hipError_t copy_list(const CopyList& cl, hipStream_t stream);
 
 // dst[e] = src[e] for e < count complex128 values.
 hipError_t copy_elems(const double* src, double* dst, Dim count, hipStream_t stream, const int* dd = nullptr);

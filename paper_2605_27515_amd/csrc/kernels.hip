@@ -514,7 +514,7 @@ hipError_t heev_jacobi(double* G, int ldg, long long g_stride, Dim n, double* w,
 // ---------------------------------------------------------------------------
 
 __global__ void truncate_kernel(const double* lam, Dim nD, const int* dd, double tol, int cap, int* k_out,
-                                double* disc, int* err) {
+                                double* disc, int* err, int full_cap, int* over) {
   const int n = dim_val(nD, dd);
   // the eigenvalues are staged in LDS by all threads; the sums stay serial,
   // in index order, so the decision is that of the plain rule
@@ -543,6 +543,7 @@ __global__ void truncate_kernel(const double* lam, Dim nD, const int* dd, double
     --k;
   }
   if (cap > 0 && k > cap) {
+    if (over && full_cap > cap) *over = 1;
     for (int j = cap; j < k; ++j) tail += lam_[j];
     k = cap;
   }
@@ -552,10 +553,11 @@ __global__ void truncate_kernel(const double* lam, Dim nD, const int* dd, double
 }
 
 hipError_t truncate_rank(const double* lam, Dim n, double tol, int cap, int* k_out, double* disc, int* err,
-                         hipStream_t s, const int* dd) {
+                         hipStream_t s, const int* dd, int full_cap, int* over) {
   // the kernel stages lam in 4 KB of LDS
   if (n.hi < 1 || n.hi > 512 || (n.idx >= 0 && !dd)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(truncate_kernel, dim3(1), dim3(64), 0, s, lam, n, dd, tol, cap, k_out, disc, err);
+  hipLaunchKernelGGL(truncate_kernel, dim3(1), dim3(64), 0, s, lam, n, dd, tol, cap, k_out, disc, err, full_cap,
+                     over);
   return hipGetLastError();
 }
 
@@ -739,6 +741,26 @@ __global__ __launch_bounds__(256) void normalize_step_kernel(double* x, Dim coun
 hipError_t normalize_step(double* x, Dim count, StepStat* st, double tau_warn, hipStream_t s, const int* dd,
                           bool rescale) {
   hipLaunchKernelGGL(normalize_step_kernel, dim3(1), dim3(256), 0, s, x, count, dd, st, tau_warn, rescale ? 1 : 0);
+  return hipGetLastError();
+}
+
+__global__ void copy_list_kernel(CopyList cl) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long t0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  for (int j = 0; j < cl.n; ++j) {
+    const unsigned* src = static_cast<const unsigned*>(cl.src[j]);
+    unsigned* dst = static_cast<unsigned*>(cl.dst[j]);
+    for (long long e = t0; e < cl.words[j]; e += stride) dst[e] = src[e];
+  }
+}
+
+hipError_t copy_list(const CopyList& cl, hipStream_t s) {
+  if (cl.n < 0 || cl.n > 48) return hipErrorInvalidValue;
+  long long total = 0;
+  for (int j = 0; j < cl.n; ++j) total += cl.words[j];
+  if (total <= 0) return hipSuccess;
+  const int blocks = (int)std::min<long long>((total + 255) / 256, 1024);
+  hipLaunchKernelGGL(copy_list_kernel, dim3(blocks), dim3(256), 0, s, cl);
   return hipGetLastError();
 }
 
