@@ -124,6 +124,15 @@ typedef struct lb_config {
                                       the caps up to rounding.  The undo keeps
                                       a second copy of the state (counted by
                                       lindblad_footprint)                      */
+  int32_t fp64_jacobi_pass;        /* LB_FP64 only, nonzero: every truncated
+                                      factorisation takes a second pass, cyclic
+                                      Jacobi on the Gram of the operand
+                                      projected on the first pass's vectors
+                                      (all singular values to FP64 accuracy
+                                      relative to the largest; one workgroup,
+                                      far slower).  0 (default): one pass, its
+                                      spectral tail decomposed again as in
+                                      LB_FP32_CONTRACT                         */
 } lb_config;
 
 #define LB_TAU_WARN 1e-3

@@ -65,7 +65,8 @@ class Solver:
                  precision: str = "fp64", chi_zip: int = 0, tol_zip: float = 0.0,
                  site_order=None, stream: int | None = None, device: int = 0,
                  allow_unstable: bool = False, fp32_tol_floor: float = 0.0, tau_warn: float = 0.0,
-                 arena: int | None = None, arena_bytes: int = 0, fixed_bounds: bool = False):
+                 arena: int | None = None, arena_bytes: int = 0, fixed_bounds: bool = False,
+                 fp64_jacobi_pass: bool = False):
         lib = L.load()
         cfg = L.LbConfig()
         lib.lindblad_default_config(C.byref(cfg))
@@ -92,6 +93,7 @@ class Solver:
         cfg.arena = arena
         cfg.arena_bytes = int(arena_bytes)
         cfg.fixed_bounds = 1 if fixed_bounds else 0
+        cfg.fp64_jacobi_pass = 1 if fp64_jacobi_pass else 0
         h = C.c_void_p()
         _check(lib.lindblad_create(C.byref(cfg), C.byref(h)), "create")
         self.h = h

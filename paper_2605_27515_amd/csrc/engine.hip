@@ -328,7 +328,14 @@ bool fp32(const lb_solver* s) { return s->cfg.precision == LB_FP32_CONTRACT; }
 // MPO bond i of the Kraus MPO as applied: the FP32 form applies its leading
 // part as a channel of its own beside the increment
 int mpo_bond(const lb_solver* s, int i) { return s->wb[i] + (fp32(s) ? s->wlb[i] : 0); }
-int passes(const lb_solver* s) { return fp32(s) ? 1 : 2; }
+// Passes of a truncated factorisation: 2 only for the FP64 form with the
+// Jacobi second pass asked for; otherwise one pass whose spectral tail is
+// decomposed again where a truncation reaches it (refine_tail)
+int passes(const lb_solver* s) { return !fp32(s) && s->cfg.fp64_jacobi_pass ? 2 : 1; }
+// Newton-Schulz steps after the tridiagonal route's vectors: one leaves the
+// FP32 form's bases orthonormal to its complex64 rounding, two the FP64 form's
+// to FP64 rounding
+int ns_iters(const lb_solver* s) { return fp32(s) ? 1 : 2; }
 
 // Caps of the zip-up and purification truncations: the configured ones, and
 // those of the current launch-bound tier
@@ -751,8 +758,8 @@ void eig_trid(lb_solver* s, double* G, int ldg, Dim n, double* lam, double* U, D
     HIPCHK(lbk::trid_backtransform(n, tw, kvec, U, ldg, s->stream, ddp(s)));
   }
   {
-    Timed tm(s, PC_SVDGEMM, passes(s) * (8.0 * KV * KV * N * 2), passes(s) * 16.0 * (2.0 * N * KV + KV * KV));
-    HIPCHK(lbk::orthonormalize_columns(U, ldg, n, kvec, s->scratch.d(), s->U2.d(), passes(s), s->ws.p,
+    Timed tm(s, PC_SVDGEMM, ns_iters(s) * (8.0 * KV * KV * N * 2), ns_iters(s) * 16.0 * (2.0 * N * KV + KV * KV));
+    HIPCHK(lbk::orthonormalize_columns(U, ldg, n, kvec, s->scratch.d(), s->U2.d(), ns_iters(s), s->ws.p,
                                        s->stream, ddp(s)));
   }
 }
@@ -819,10 +826,30 @@ void refine_tail(lb_solver* s, bool rows, std::initializer_list<GramOp> ops, Dim
   HIPCHK(lbk::copy_block(s->lam2.d(), Dim(0), -1, lam, Dim(0), js, Dim(1), kt, 1, s->stream, ddp(s)));
 }
 
+// The tail refinement after eig_trid(..., cap): one level resolves the
+// singular values down to ~kTailFraction sqrt(8 n eps) of the largest, enough
+// for the FP32 form's tolerances; the FP64 form, whose tolerances reach
+// 1e-12, splits the refined spectrum again at kTailFraction^2 lam_0 and
+// decomposes that deeper tail once more (empty when no truncation reaches it).
+void refine(lb_solver* s, bool rows, std::initializer_list<GramOp> ops, Dim n, double* U, int ldu, double* lam,
+            int cap) {
+  refine_tail(s, rows, ops, n, U, ldu, lam);
+  if (fp32(s)) return;
+  {
+    Timed tm(s, PC_OTHER, 0.0, s->prof_on ? 8.0 * hv(s, n) : 0.0);
+    HIPCHK(lbk::tail_split(lam, n, kTailFraction * kTailFraction, cap, s->dd.i(), sl_tail0(s), sl_tailk(s),
+                           sl_tailv(s), s->stream));
+  }
+  timed_sync(s);
+  refine_tail(s, rows, ops, n, U, ldu, lam);
+}
+
 // Left singular vectors / squared singular values of the n x m matrix A
 // (row-major, leading dim lda).  U (n x n, leading dimension n.hi; the first
 // kvec columns are valid) is returned and the eigenvalues are left in s->lam.
-// LB_FP64 runs two passes: the tridiagonal route gives U0 (all n vectors),
+// One pass: the tridiagonal route, then the spectral tail decomposed again
+// where the truncation reaches it (refine_tail).  LB_FP64 with
+// fp64_jacobi_pass runs two passes: the tridiagonal route gives U0 (all n vectors),
 // two Newton-Schulz steps make it unitary to rounding, then B = U0^H A,
 // G2 = B B^H is nearly diagonal with graded rows and Jacobi with a relative
 // threshold restores absolute FP64 accuracy of the small singular values.
@@ -839,7 +866,7 @@ Svd left_svd(lb_solver* s, const void* A, Prec pa, Dim n, Dim m, Dim lda, bool w
   double* U0 = s->U0.d();
   if (passes(s) == 1) {
     eig_trid(s, G, ldg, n, s->lam.d(), U0, n, kvec.hi);
-    refine_tail(s, true, {GramOp{A, pa, lda, m}}, n, U0, ldg, s->lam.d());
+    refine(s, true, {GramOp{A, pa, lda, m}}, n, U0, ldg, s->lam.d(), kvec.hi);
     return Svd{U0, nullptr};
   }
   eig_trid(s, G, ldg, n, s->lam.d(), U0, n);
@@ -1209,8 +1236,8 @@ void zipup(lb_solver* s) {
            Dim(1), Dim(0), Dim(0), Dim(0), 1.0, 1.0);
         s->cls = PC_SVDGEMM;
         eig_trid(s, G, ldg, n, s->lam.d(), s->U0.d(), n, zc);
-        refine_tail(s, true, {GramOp{s->T.p, pw, m, m}, GramOp{s->TL.p, lbk::F64, mL, mL}}, n, s->U0.d(), ldg,
-                    s->lam.d());
+        refine(s, true, {GramOp{s->T.p, pw, m, m}, GramOp{s->TL.p, lbk::F64, mL, mL}}, n, s->U0.d(), ldg,
+               s->lam.d(), zc);
         sv = Svd{s->U0.d(), nullptr};
       } else {
         sv = left_svd(s, s->T.p, pw, n, m, m, passes(s) == 2, capped(n, zc));
@@ -1259,7 +1286,7 @@ void zipup(lb_solver* s) {
       gram_cols(s, Tl, pl, n, m, m, Gc, ldv);
       double* V0 = s->U0.d();
       eig_trid(s, Gc, ldv, m, s->lam.d(), V0, m, passes(s) == 1 ? mu : 0);
-      if (passes(s) == 1) refine_tail(s, false, {GramOp{Tl, pl, m, n}}, m, V0, ldv, s->lam.d());
+      if (passes(s) == 1) refine(s, false, {GramOp{Tl, pl, m, n}}, m, V0, ldv, s->lam.d(), mu);
       double* Vf = V0;
       const void* Asrc = Tl;
       Prec asrc = pl;
