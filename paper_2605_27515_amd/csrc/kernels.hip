@@ -1177,14 +1177,34 @@ __device__ inline void trd_reflector(double2 alpha, double xn2, double& beta, do
 
 __device__ inline double2 cmul(double2 a, double2 b) { return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 
-template <int PARTS>
+// TAIL: the same reduction continued on the trailing block of order P that
+// hetrd_mc_kernel (launched with tail_order = P) leaves for orders n > P
+// after its first n - P steps, in the mailbox rows of the steps it did not
+// take (mail + 2 (n - P) n, P x P complex, full storage): its reflectors,
+// d, e and tau go to positions n - P.. of the whole reduction's.
+template <int PARTS, bool TAIL>
 __global__ __launch_bounds__(TRD_NT) void hetrd_kernel(const double2* G, int ldg, Dim nD, const int* dd, int nmin,
-                                                       double* d, double* e, double2* tau, double2* Vt) {
+                                                       double* d, double* e, double2* tau, double2* Vt,
+                                                       const double* mail) {
   static_assert(PARTS == 8 || PARTS == 16, "orders up to 128");
+  constexpr int P = TrdShared<PARTS>::P;
   __shared__ TrdShared<PARTS> sh;
   // this form runs orders nmin..P (a launch of several forms gates by order)
-  const int n = dim_val(nD, dd);
-  if (n < nmin || n > TrdShared<PARTS>::P || n < 1) return;
+  int n = dim_val(nD, dd);
+  long long ldv = n;   // row stride of Vt
+  if constexpr (TAIL) {
+    if (n <= P) return;
+    const int off = n - P;
+    G = reinterpret_cast<const double2*>(mail + 2LL * off * n);
+    ldg = P;
+    d += off;
+    e += off;
+    tau += off;
+    Vt += (long long)off * n + off;
+    n = P;
+  } else {
+    if (n < nmin || n > P || n < 1) return;
+  }
   const int tid = threadIdx.x, lane = tid & 63;
   const bool w0 = tid < 64;
   if (n == 1) {
@@ -1280,7 +1300,7 @@ __global__ __launch_bounds__(TRD_NT) void hetrd_kernel(const double2* G, int ldg
     }
     if (j == n - 2) break;
     lds_barrier();
-    trd_pass<PARTS, false>(G, ldg, n, j, sh, vc, vn, reg, Vt + (long long)(j + 1) * n);
+    trd_pass<PARTS, false>(G, ldg, n, j, sh, vc, vn, reg, Vt + (long long)(j + 1) * ldv);
     lds_barrier();
   }
 }
@@ -1503,7 +1523,8 @@ __device__ inline void trm_pass(const double2* G, int ldg, int n, int j, TrmShar
 template <int W, int CPW>
 __global__ __launch_bounds__(TRM_NT) void hetrd_mc_kernel(const double2* G, int ldg, Dim nD, const int* dd, int nmin,
                                                           double* d, double* e, double2* tau, double2* Vt,
-                                                          double* mail, unsigned long long* abortw, unsigned gen) {
+                                                          double* mail, unsigned long long* abortw, unsigned gen,
+                                                          int tail_order) {
   constexpr int LC = 8 * CPW, NMAX = W * LC, QR = NMAX / 64;
   static_assert(W <= TRM_WMAX && NMAX <= TRM_NMAX, "sync block layout");
   __shared__ TrmShared<NMAX, CPW> sh;
@@ -1511,6 +1532,12 @@ __global__ __launch_bounds__(TRM_NT) void hetrd_mc_kernel(const double2* G, int 
   // leave here together or none does
   const int n = dim_val(nD, dd);
   if (n < nmin || n > NMAX || n < 2) return;
+  // with tail_order > 0 and n > tail_order the workgroups stop after step
+  // kstop - 1, kstop = n - tail_order, and leave the trailing block B_kstop
+  // (order tail_order, full storage) in the mailbox rows of steps kstop..,
+  // which no step of this launch touches, for the one-workgroup form
+  const int kstop = (tail_order > 0 && n > tail_order) ? n - tail_order : -1;
+  double2* dump = kstop > 0 ? reinterpret_cast<double2*>(mail + 2LL * kstop * n) : nullptr;
   const long long wait_ticks = d_trm_wait_ticks;
   const int tid = threadIdx.x, lane = tid & 63, g = blockIdx.x;
   const bool w0 = tid < 64, lead = (g == 0);
@@ -1546,6 +1573,24 @@ __global__ __launch_bounds__(TRM_NT) void hetrd_mc_kernel(const double2* G, int 
   trm_pass<W, CPW, true>(G, ldg, n, -1, sh, nullptr, sh.v[0], reg, Vt);
   __syncthreads();
   for (int j = 0;; ++j) {
+    if (j == kstop) {
+      // columns c > kstop of B_kstop at rows R > kstop (the pass of step
+      // kstop - 1 applied its update); row and column kstop came from the
+      // lead workgroup's wave 0 in that step
+      const int k = tid >> 6;
+#pragma unroll
+      for (int u = 0; u < CPW; ++u) {
+        const int c = (k + 8 * u) * W + g;
+        if (c > kstop && c < n) {
+#pragma unroll
+          for (int q = 0; q < QR; ++q) {
+            const int R = q * 64 + lane;
+            if (R > kstop && R < n) dump[(long long)(R - kstop) * tail_order + (c - kstop)] = reg[u][q];
+          }
+        }
+      }
+      return;
+    }
     const double2* vc = sh.v[j & 1];
     double2* vn = sh.v[(j & 1) ^ 1];
     if (w0) {
@@ -1628,6 +1673,17 @@ __global__ __launch_bounds__(TRM_NT) void hetrd_mc_kernel(const double2* G, int 
         }
         const double xn2 = wave_sum(tail);
         const double dg = read_lane(yv[0].x, 0);
+        if (lead && j + 1 == kstop) {
+          // column kstop of B_kstop (and, conjugated, its row kstop)
+#pragma unroll
+          for (int q = 0; q < QR; ++q) {
+            const int R = j + 1 + lane + 64 * q;
+            if (R < n) {
+              dump[(long long)(R - kstop) * tail_order] = yv[q];
+              if (R > kstop) dump[R - kstop] = double2{yv[q].x, -yv[q].y};
+            }
+          }
+        }
         if (j == n - 2) {
           if (lead && lane == 0) d[j + 1] = dg;
         } else {
@@ -2530,9 +2586,11 @@ hipError_t trid_reduce(double* G, int ldg, Dim n, const TridWork& t, hipStream_t
   double2* g2 = reinterpret_cast<double2*>(G);
   double2* tau = reinterpret_cast<double2*>(t.tau);
   double2* vt = reinterpret_cast<double2*>(t.Vt);
-  hipLaunchKernelGGL(hetrd_kernel<16>, dim3(1), dim3(TRD_NT), 0, s, g2, ldg, n, dd, 1, t.d, t.e, tau, vt);
+  hipLaunchKernelGGL((hetrd_kernel<16, false>), dim3(1), dim3(TRD_NT), 0, s, g2, ldg, n, dd, 1, t.d, t.e, tau, vt,
+                     nullptr);
   if (n.hi > 64)
-    hipLaunchKernelGGL(hetrd_kernel<8>, dim3(1), dim3(TRD_NT), 0, s, g2, ldg, n, dd, 65, t.d, t.e, tau, vt);
+    hipLaunchKernelGGL((hetrd_kernel<8, false>), dim3(1), dim3(TRD_NT), 0, s, g2, ldg, n, dd, 65, t.d, t.e, tau, vt,
+                       nullptr);
   if (n.hi > 128) {
     auto* abortw = reinterpret_cast<unsigned long long*>(t.sync);
     double* mail = t.sync + 16;
@@ -2543,12 +2601,21 @@ hipError_t trid_reduce(double* G, int ldg, Dim n, const TridWork& t, hipStream_t
                        reinterpret_cast<unsigned long long*>(mail), cnt, abortw);
     hipError_t ce = hipGetLastError();
     if (ce != hipSuccess) return ce;
+    // the multi-workgroup form takes the first n - 128 steps, where the
+    // trailing block does not fit one CU; the one-workgroup form the last
+    // 128, at about half the multi-workgroup form's exchange-bound step time
+    // (order 256: 0.60 + 0.31 ms against 1.03 ms for all steps on 16 CUs)
+    constexpr int kTail = TrdShared<8>::P;
     if (n.hi <= 256)
       hipLaunchKernelGGL((hetrd_mc_kernel<16, 2>), dim3(16), dim3(TRM_NT), 0, s, g2, ldg, n, dd, 129, t.d, t.e, tau,
-                         vt, mail, abortw, 1u);
+                         vt, mail, abortw, 1u, kTail);
     else
       hipLaunchKernelGGL((hetrd_mc_kernel<32, 2>), dim3(32), dim3(TRM_NT), 0, s, g2, ldg, n, dd, 129, t.d, t.e, tau,
-                         vt, mail, abortw, 1u);
+                         vt, mail, abortw, 1u, kTail);
+    ce = hipGetLastError();
+    if (ce != hipSuccess) return ce;
+    hipLaunchKernelGGL((hetrd_kernel<8, true>), dim3(1), dim3(TRD_NT), 0, s, g2, ldg, n, dd, 0, t.d, t.e, tau, vt,
+                       mail);
   }
   return hipGetLastError();
 }

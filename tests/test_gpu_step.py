@@ -69,11 +69,12 @@ def _assert_same_rho(Xo, Xg, m, rtol, samples=192):
     assert d2 <= max(rtol ** 2, 1e-14) * norm2, d2 / norm2
 
 
-def _compare(m, steps, chi, chi_mu, precision, rtol, tol=1e-8):
+def _compare(m, steps, chi, chi_mu, precision, rtol, tol=1e-8, **solver_kw):
     api = _api()
-    print(f"case {m.name} bits={m.bits} steps={steps} chi={chi} chi_mu={chi_mu} {precision}", flush=True)
+    print(f"case {m.name} bits={m.bits} steps={steps} chi={chi} chi_mu={chi_mu} {precision} {solver_kw}",
+          flush=True)
     Xo, taus = _oracle_run(m, steps, chi, chi_mu, tol)
-    s = api.solver_from_model(m, precision=precision, chi=chi, chi_mu=chi_mu, tol=tol)
+    s = api.solver_from_model(m, precision=precision, chi=chi, chi_mu=chi_mu, tol=tol, **solver_kw)
     s.step(steps)
     Xg = s.get_state_mps()
     so = m.site_order()
@@ -104,6 +105,17 @@ def test_step_coherent_loss(precision, rtol, tol):
 @pytest.mark.parametrize("precision,rtol,tol", FORMS)
 def test_step_two_photon_cat(precision, rtol, tol):
     _compare(wl.model_two_photon_cat(R=5, alpha2=2.0, dt=1e-3), 60, 16, 8, precision, rtol, tol)
+
+
+@pytest.mark.parametrize("case", ["coherent_loss", "two_photon_cat"])
+def test_step_fp64_jacobi_pass(case):
+    """The FP64 form with the Jacobi second pass instead of the tail
+    refinement (lb_config.fp64_jacobi_pass), at 1e-10 and tol 1e-12."""
+    if case == "coherent_loss":
+        _compare(wl.model_coherent_loss(), 100, 16, 4, "fp64", 1e-10, 1e-12, fp64_jacobi_pass=True)
+    else:
+        _compare(wl.model_two_photon_cat(R=5, alpha2=2.0, dt=1e-3), 60, 16, 8, "fp64", 1e-10, 1e-12,
+                 fp64_jacobi_pass=True)
 
 
 @pytest.mark.parametrize("precision,rtol,tol", FORMS)
