@@ -73,7 +73,7 @@ ALU_CLASSES = {"hetrd", "stebz", "stein", "ormtr", "jacobi"}
 # over the run, divided by the calls; the multi-workgroup form polls its
 # mailboxes with agent-scope atomic loads, which go to memory).  A kernel
 # absent here reports traffic null
-PMC_TRAFFIC_BYTES = {}
+PMC_TRAFFIC_BYTES = {"hetrd": 1.817e6}
 
 
 def workload():
@@ -127,7 +127,10 @@ def gpu_run(steps: int, warmup: int, precision: str):
     import torch
     from paper_2605_27515_amd import api
     m, L, chi, chi_mu, raw = workload()
-    s = api.solver_from_model(m, precision=precision, chi=chi, chi_mu=chi_mu, state="none", device=0)
+    # autotune: the first step times the split-K count of each GEMM on its
+    # operands (include/lindblad.h, lb_config.autotune); it is a warm-up step
+    s = api.solver_from_model(m, precision=precision, chi=chi, chi_mu=chi_mu, state="none", device=0,
+                              autotune=True)
     s.set_state_mps(raw)
     if warmup:
         s.step(warmup)
@@ -305,7 +308,8 @@ def chi256_leg(steps: int, precision: str) -> dict:
     m = wl.model_transmon_resonator()
     L, chi, chi_mu = 22, 256, 32
     raw = wl.synthetic_mps(L, chi_mu, chi)
-    s = api.solver_from_model(m, precision=precision, chi=chi, chi_mu=chi_mu, state="none", device=0)
+    s = api.solver_from_model(m, precision=precision, chi=chi, chi_mu=chi_mu, state="none", device=0,
+                              autotune=True)
     s.set_state_mps(raw)
     s.step(1)
     torch.cuda.synchronize()
@@ -592,7 +596,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "cat+buffer 2x256 Fock (16 sites), alpha^2=8, 9 Kraus ops, chi=128, "
                                "chi_mu=16, tol=1e-8, dt=2.5e-5, seeded saturated MPS",
-                   "precision": args.precision, "parallelism": "single solve, one GPU"},
+                   "precision": args.precision, "parallelism": "single solve, one GPU",
+                   "gemm_splits": "autotuned on the warm-up step"},
         "roofline": dict(roofline_entry({dominant: live[dominant]}, args.precision),
                          timing="HIP events on the solver's stream around every launch of the class, over a "
                                 "second pass of the timed steps (direct launches); the timed pass replays the "

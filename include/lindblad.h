@@ -133,6 +133,18 @@ typedef struct lb_config {
                                       far slower).  0 (default): one pass, its
                                       spectral tail decomposed again as in
                                       LB_FP32_CONTRACT                         */
+  int32_t autotune;                /* nonzero: the first step of each launch
+                                      tier runs eagerly and times every
+                                      admissible split-K count of each GEMM
+                                      that overwrites its output, on its own
+                                      operands; the fastest is kept for that
+                                      GEMM's bounds and precisions for the
+                                      rest of the process (every solver).  The
+                                      split count changes the summation order,
+                                      so results may differ from an untuned
+                                      run at rounding level.  0: heuristic
+                                      split counts (or ones another solver of
+                                      the process tuned)                       */
 } lb_config;
 
 #define LB_TAU_WARN 1e-3

@@ -43,7 +43,8 @@ class LbConfig(C.Structure):
                 ("stream", C.c_void_p), ("device", C.c_int32),
                 ("fp32_tol_floor", C.c_double), ("tau_warn", C.c_double),
                 ("arena", C.c_void_p), ("arena_bytes", C.c_int64),
-                ("fixed_bounds", C.c_int32), ("fp64_jacobi_pass", C.c_int32)]
+                ("fixed_bounds", C.c_int32), ("fp64_jacobi_pass", C.c_int32),
+                ("autotune", C.c_int32)]
 
 
 class LbFactor(C.Structure):

@@ -66,7 +66,7 @@ class Solver:
                  site_order=None, stream: int | None = None, device: int = 0,
                  allow_unstable: bool = False, fp32_tol_floor: float = 0.0, tau_warn: float = 0.0,
                  arena: int | None = None, arena_bytes: int = 0, fixed_bounds: bool = False,
-                 fp64_jacobi_pass: bool = False):
+                 fp64_jacobi_pass: bool = False, autotune: bool = False):
         lib = L.load()
         cfg = L.LbConfig()
         lib.lindblad_default_config(C.byref(cfg))
@@ -94,6 +94,7 @@ class Solver:
         cfg.arena_bytes = int(arena_bytes)
         cfg.fixed_bounds = 1 if fixed_bounds else 0
         cfg.fp64_jacobi_pass = 1 if fp64_jacobi_pass else 0
+        cfg.autotune = 1 if autotune else 0
         h = C.c_void_p()
         _check(lib.lindblad_create(C.byref(cfg), C.byref(h)), "create")
         self.h = h

@@ -290,6 +290,9 @@ struct lb_solver {
   bool unsynced = false;       // steps enqueued since the last wait
   long long tier_redos = 0;    // steps run again with a larger tier
   bool in_batch = false;       // stepping as part of lindblad_step_batch
+  bool tuning = false;         // an eager step that times GEMM split counts
+  std::map<int, bool> tuned;   // tiers whose first step has been tuned
+  hipEvent_t tune_ev[2] = {nullptr, nullptr};
   DevBuf bk;                   // the state before a tiered step: sites, size
                                // table, status and discards
   size_t ws_bytes = 0;
@@ -478,6 +481,84 @@ void check_gemm(hipError_t e, const char* what) {
   if (e != hipSuccess) throw Fail(LB_ERR_HIP, std::string("gemm ") + what + ": " + hipGetErrorString(e));
 }
 
+// ---- split-K autotuner ----------------------------------------------------------
+// The split count of a GEMM launch, keyed by its bounds, operand precisions and
+// layout, process-wide.  With lb_config.autotune a solver runs the first step
+// of each launch tier eagerly and times every admissible split count of each
+// GEMM that overwrites its output (beta = 0, one batch), on its actual
+// operands; later launches of the same key (this solver's graph, other
+// solvers) take the fastest.  Without an entry the split comes from the
+// heuristics choose_splits / choose_splits_herm.
+struct GemmKey {
+  int M, N, K, batch, pa, pb, pc, comp, herm, conjA, conjB, akf, bnf;
+  bool operator<(const GemmKey& o) const {
+    const int a[13] = {M, N, K, batch, pa, pb, pc, comp, herm, conjA, conjB, akf, bnf};
+    const int b[13] = {o.M, o.N, o.K, o.batch, o.pa, o.pb, o.pc, o.comp, o.herm, o.conjA, o.conjB, o.akf, o.bnf};
+    return std::lexicographical_compare(a, a + 13, b, b + 13);
+  }
+};
+std::mutex g_tune_mu;
+std::map<GemmKey, int> g_tune;
+
+GemmKey gemm_key(const lbk::Gemm& g) {
+  return GemmKey{g.M.hi, g.N.hi, g.K.hi, g.batch.hi, (int)g.pa, (int)g.pb, (int)g.pc, (int)g.compute, g.herm,
+                 g.conjA, g.conjB, g.sa_k.idx < 0 && g.sa_k.c == 1, g.sb_n.idx < 0 && g.sb_n.c == 1};
+}
+
+void run_gemm(lb_solver* s, lbk::Gemm& g, const char* what) {
+  const GemmKey key = gemm_key(g);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      g.splits = it->second;
+      check_gemm(lbk::gemm(g, s->stream), what);
+      return;
+    }
+  }
+  if (!s->tuning || s->prof_on || g.beta_re != 0.0 || g.beta_im != 0.0 || g.batch.hi != 1) {
+    check_gemm(lbk::gemm(g, s->stream), what);
+    return;
+  }
+  for (hipEvent_t& e : s->tune_ev)
+    if (!e) HIPCHK(hipEventCreate(&e));
+  // admissible: at least one 16-deep K slice per split, partial sums within
+  // the split-K workspace
+  const int heur = g.splits;
+  const long long part = (long long)g.M.hi * g.N.hi * 16;
+  std::vector<int> cand;
+  for (int sp : {1, 2, 4, 8, 16, 32, 64, heur}) {
+    if (sp > 1 && (sp > (g.K.hi + 15) / 16 || (size_t)(sp * part) > s->ws.bytes)) continue;
+    if (std::find(cand.begin(), cand.end(), sp) == cand.end()) cand.push_back(sp);
+  }
+  int best = heur;
+  float best_ms = 1e30f;
+  for (int sp : cand) {
+    g.splits = sp;
+    float t = 1e30f;
+    for (int rep = 0; rep < 2; ++rep) {
+      HIPCHK(hipEventRecord(s->tune_ev[0], s->stream));
+      check_gemm(lbk::gemm(g, s->stream), what);
+      HIPCHK(hipEventRecord(s->tune_ev[1], s->stream));
+      HIPCHK(hipEventSynchronize(s->tune_ev[1]));
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, s->tune_ev[0], s->tune_ev[1]));
+      t = std::min(t, ms);
+    }
+    // the heuristic's choice wins ties within 3 %
+    if (t < best_ms * (sp == heur ? 1.03f : 0.97f) || best_ms >= 1e29f) {
+      best = sp;
+      best_ms = t;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.emplace(key, best);
+  }
+  g.splits = best;
+  check_gemm(lbk::gemm(g, s->stream), what);
+}
+
 // Process-wide budget of CUs per device for the multi-workgroup reduction,
 // whose workgroups spin on each other and so must all be resident at once.
 // A solver reserves a launch's workgroups (one CU each at most) before
@@ -643,7 +724,7 @@ void gram_rows(lb_solver* s, const void* A, Prec pa, Dim n, Dim m, Dim lda, doub
   g.dd = ddp(s);
   Timed tm(s, PC_GRAM, s->prof_on ? 8.0 * hv(s, n) * hv(s, n) * hv(s, m) : 0.0,
            s->prof_on ? hv(s, n) * hv(s, m) * (pa == lbk::F64 ? 16 : 8) + 16.0 * hv(s, n) * hv(s, n) : 0.0);
-  check_gemm(lbk::gemm(g, s->stream), "gram_rows");
+  run_gemm(s, g, "gram_rows");
 }
 
 // Gram G = A^H A of the columns of A (n x m), FP64 output m x m, ld ldg.
@@ -660,7 +741,7 @@ void gram_cols(lb_solver* s, const void* A, Prec pa, Dim n, Dim m, Dim lda, doub
   g.dd = ddp(s);
   Timed tm(s, PC_GRAM, s->prof_on ? 8.0 * hv(s, m) * hv(s, m) * hv(s, n) : 0.0,
            s->prof_on ? hv(s, n) * hv(s, m) * (pa == lbk::F64 ? 16 : 8) + 16.0 * hv(s, m) * hv(s, m) : 0.0);
-  check_gemm(lbk::gemm(g, s->stream), "gram_cols");
+  run_gemm(s, g, "gram_cols");
 }
 
 // C = op(A) op(B) with row-major dense operands described by leading dims.
@@ -689,7 +770,7 @@ void mm(lb_solver* s, Dim M, Dim N, Dim K, const void* A, Prec pa, Dim lda, bool
     bytes = m_ * k_ * ea * (sa_b.hi ? b_ : 1) + k_ * n_ * eb * (sb_b.hi ? b_ : 1) + m_ * n_ * ec * b_;
   }
   Timed tm(s, s->cls, flop, bytes);
-  check_gemm(lbk::gemm(g, s->stream), "mm");
+  run_gemm(s, g, "mm");
 }
 
 // Jacobi (relative accuracy; second pass of LB_FP64): eigenvectors in G.
@@ -827,14 +908,21 @@ void refine_tail(lb_solver* s, bool rows, std::initializer_list<GramOp> ops, Dim
 }
 
 // The tail refinement after eig_trid(..., cap): one level resolves the
-// singular values down to ~kTailFraction sqrt(8 n eps) of the largest, enough
-// for the FP32 form's tolerances; the FP64 form, whose tolerances reach
-// 1e-12, splits the refined spectrum again at kTailFraction^2 lam_0 and
-// decomposes that deeper tail once more (empty when no truncation reaches it).
+// eigenvalues of the Gram matrix down to ~kTailFraction 8 n eps lam_0 (~1e-23
+// lam_0), so the singular values to ~3e-12 of the largest: enough for every
+// truncation at tol >= 1e-10, whose cut lies at weights ~tol^2.  The FP64
+// form at a smaller tolerance (down to 1e-12 in the parity tests) splits the
+// refined spectrum again at kTailFraction^2 lam_0 and decomposes that deeper
+// tail once more (empty when no truncation reaches it).
+bool deep_tail(const lb_solver* s) {
+  const double tz = s->cfg.tol_zip > 0 ? s->cfg.tol_zip : s->cfg.tol / 10.0;
+  return !fp32(s) && std::min(tz, s->cfg.tol) < 1e-10;
+}
+
 void refine(lb_solver* s, bool rows, std::initializer_list<GramOp> ops, Dim n, double* U, int ldu, double* lam,
             int cap) {
   refine_tail(s, rows, ops, n, U, ldu, lam);
-  if (fp32(s)) return;
+  if (!deep_tail(s)) return;
   {
     Timed tm(s, PC_OTHER, 0.0, s->prof_on ? 8.0 * hv(s, n) : 0.0);
     HIPCHK(lbk::tail_split(lam, n, kTailFraction * kTailFraction, cap, s->dd.i(), sl_tail0(s), sl_tailk(s),
@@ -1437,6 +1525,19 @@ void ensure_graph(lb_solver* s) {
 // Enqueue one step under the current tier: its graph when there is one,
 // else the launches themselves (always while timing).
 void launch_step(lb_solver* s) {
+  if (s->cfg.autotune && !s->prof_on && !s->tuned[s->tier]) {
+    // the tier's first step, eager, timing the GEMM split counts it meets
+    s->tuning = true;
+    try {
+      enqueue_step(s);
+    } catch (...) {
+      s->tuning = false;
+      throw;
+    }
+    s->tuning = false;
+    s->tuned[s->tier] = true;
+    return;
+  }
   if (!s->prof_on) {
     ensure_graph(s);
     const lb_solver::StepGraph& sg = s->graphs[s->tier];
@@ -1692,6 +1793,8 @@ void lindblad_destroy(lb_solver* s) {
   hipStream_t st = s->stream;
   bool own = s->own_stream;
   for (auto e : s->ev_pool) (void)hipEventDestroy(e);
+  for (auto e : s->tune_ev)
+    if (e) (void)hipEventDestroy(e);
   release_cus(s);
   drop_graph(s);
   delete s;

@@ -118,6 +118,14 @@ def test_step_fp64_jacobi_pass(case):
                  fp64_jacobi_pass=True)
 
 
+@pytest.mark.parametrize("precision,rtol,tol", [("fp64", 1e-10, 1e-12), ("fp32", 1e-5, 1e-8)])
+def test_step_autotuned(precision, rtol, tol):
+    """lb_config.autotune: the first step times the split-K counts of its
+    GEMMs; the results still meet the oracle at the form's tolerance."""
+    _compare(wl.model_cat_buffer(Ra=4, Rb=3, alpha2=4.0, dt=2.5e-5), 40, 32, 8, precision, rtol, tol,
+             autotune=True)
+
+
 @pytest.mark.parametrize("precision,rtol,tol", FORMS)
 def test_step_cat_buffer(precision, rtol, tol):
     _compare(wl.model_cat_buffer(Ra=4, Rb=3, alpha2=2.0, dt=1e-3), 30, 16, 8, precision, rtol, tol)
