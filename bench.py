@@ -73,7 +73,7 @@ ALU_CLASSES = {"hetrd", "stebz", "stein", "ormtr", "jacobi"}
 # over the run, divided by the calls; the multi-workgroup form polls its
 # mailboxes with agent-scope atomic loads, which go to memory).  A kernel
 # absent here reports traffic null
-PMC_TRAFFIC_BYTES = {"hetrd": 1.817e6}
+PMC_TRAFFIC_BYTES = {"hetrd": 1.814e6}
 
 
 def workload():
@@ -161,6 +161,33 @@ def gpu_run(steps: int, warmup: int, precision: str):
     d = s.diagnostics()
     s.close()
     return (t1 - t0), breakdown, live, dominant, d
+
+
+def copy_calibration() -> None:
+    """One plain 256 MiB device copy: its counter readings scale the HBM
+    counters of the other kernels."""
+    import torch
+    src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")   # 256 MiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def counter_run(steps: int, precision: str) -> None:
+    """The step workload's solver (as gpu_run builds it) for a few steps, a line
+    after each: a short program for rocprofv3 counter passes, which serialise
+    every dispatch."""
+    from paper_2605_27515_amd import api
+    m, L, chi, chi_mu, raw = workload()
+    s = api.solver_from_model(m, precision=precision, chi=chi, chi_mu=chi_mu, state="none", device=0,
+                              autotune=True)
+    s.set_state_mps(raw)
+    print("bench: counter run, state set", file=sys.stderr, flush=True)
+    for k in range(steps):
+        s.step(1)
+        print(f"bench: counter run, step {k + 1} of {steps} done", file=sys.stderr, flush=True)
+    s.close()
 
 
 def build_requests(reqs, precision: str, threads: int = 16):
@@ -526,6 +553,9 @@ def main():
     ap.add_argument("--zgate-chi", type=int, default=128, help="bond cap of the Z-gate run")
     ap.add_argument("--zgate-steps", type=int, default=0,
                     help="time only the first N steps of the gate (0: the whole gate, with its phase-flip probability)")
+    ap.add_argument("--counter-run", type=int, default=0,
+                    help="only take N steps of the step workload, a line after each, and exit (for rocprofv3 "
+                         "counter passes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -537,6 +567,11 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.counter_run > 0:
+        if args.copy_calibration:
+            copy_calibration()
+        counter_run(args.counter_run, args.precision)
+        return
     if args.workload == "cat-zgate":
         zgate_main(args)
         return
@@ -548,11 +583,7 @@ def main():
         return
     print(f"bench: {args.precision} steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
     if args.copy_calibration:
-        src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")   # 256 MiB
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_calibration()
     elapsed, prof, live, dominant, diag = gpu_run(args.steps, args.warmup, args.precision)
     value = args.steps / elapsed
     print(f"bench: {value:.3f} steps/s, bonds {diag['bonds']}, chi_mu {diag['chi_mu']}",
