@@ -396,6 +396,22 @@ lb_status lindblad_profile_mask(lb_solver* s, uint32_t mask);
 /* Read the counters accumulated since lindblad_profile (synchronises). */
 lb_status lindblad_profile_read(lb_solver* s, lb_profile* out);
 
+/* ---- GEMM split-count table (lb_config.autotune) -------------------------- */
+
+/* The process-wide table of tuned split-K counts, keyed by a GEMM's bounds
+ * (M, N, K, batch), operand/output/compute precisions, Hermitian flag,
+ * conjugations and unit-stride layout.  Save writes it to the file at path
+ * (UTF-8 text, one JSON object per line with the integer fields M, N, K,
+ * batch, pa, pb, pc, comp, herm, conjA, conjB, akf, bnf, splits); load
+ * merges such a file into the table (entries already present keep their
+ * value), so that later processes launch the same split counts without
+ * tuning.  Host only.  Errors: LB_ERR_ARG (NULL path, unreadable or
+ * unwritable file, a line without every field, splits outside 1..64). */
+lb_status lindblad_gemm_tune_save(const char* path);
+lb_status lindblad_gemm_tune_load(const char* path);
+/* Number of entries in the table. */
+int64_t lindblad_gemm_tune_entries(void);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* lindblad_last_error(void);
 

@@ -31,7 +31,8 @@ EXPORTED = ["lindblad_default_config", "lindblad_create", "lindblad_destroy",
             "lindblad_last_error", "lindblad_profile", "lindblad_profile_mask", "lindblad_profile_read", "lindblad_kernel_zgemm", "lindblad_kernel_heev",
             "lindblad_kernel_truncate", "lindblad_kernel_set_wait_limit", "lindblad_kernel_heev_noalloc", "lindblad_get_config", "lindblad_footprint", "lindblad_release",
             "lindblad_server_create", "lindblad_server_submit", "lindblad_server_run",
-            "lindblad_server_result", "lindblad_server_stats", "lindblad_server_destroy"]
+            "lindblad_server_result", "lindblad_server_stats", "lindblad_server_destroy",
+            "lindblad_gemm_tune_save", "lindblad_gemm_tune_load", "lindblad_gemm_tune_entries"]
 
 
 class LbConfig(C.Structure):
@@ -138,6 +139,10 @@ def load() -> C.CDLL:
     lib.lindblad_observe.argtypes = [vp, vp, C.POINTER(C.c_double)]
     lib.lindblad_trace_purity.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.lindblad_diagnostics.argtypes = [vp, C.POINTER(LbDiag)]
+    lib.lindblad_gemm_tune_save.argtypes = [C.c_char_p]
+    lib.lindblad_gemm_tune_load.argtypes = [C.c_char_p]
+    lib.lindblad_gemm_tune_entries.argtypes = []
+    lib.lindblad_gemm_tune_entries.restype = C.c_int64
     dp = C.POINTER(C.c_double)
     lib.lindblad_kernel_zgemm.argtypes = [C.c_int32, C.c_int32, C.c_int32, dp, C.c_int32, dp, C.c_int32,
                                           dp, C.c_int32, C.c_int32]
@@ -163,7 +168,7 @@ def load() -> C.CDLL:
     for name in EXPORTED:
         fn = getattr(lib, name)
         if name not in ("lindblad_default_config", "lindblad_destroy", "lindblad_last_error",
-                        "lindblad_server_destroy"):
+                        "lindblad_server_destroy", "lindblad_gemm_tune_entries"):
             fn.restype = C.c_int
     _lib = lib
     return lib

@@ -268,6 +268,20 @@ class Solver:
             pass
 
 
+def gemm_tune_save(path: str) -> None:
+    """Write the process-wide table of tuned GEMM split counts (lb_config.autotune)."""
+    _check(L.load().lindblad_gemm_tune_save(str(path).encode()), "gemm_tune_save")
+
+
+def gemm_tune_load(path: str) -> None:
+    """Merge a saved split-count table into the process-wide one."""
+    _check(L.load().lindblad_gemm_tune_load(str(path).encode()), "gemm_tune_load")
+
+
+def gemm_tune_entries() -> int:
+    return int(L.load().lindblad_gemm_tune_entries())
+
+
 def step_batch(solvers, n_steps: int = 1):
     arr = (C.c_void_p * len(solvers))(*[s.h.value for s in solvers])
     return _check(L.load().lindblad_step_batch(arr, len(solvers), int(n_steps)), "step_batch")

@@ -27,6 +27,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstddef>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <stdexcept>
@@ -2516,6 +2517,75 @@ lb_status lindblad_op_site(const lb_op* op, int32_t site, int32_t* l, int32_t* r
 lb_status lindblad_kraus_site(const lb_solver* s, int32_t site, int32_t* l, int32_t* r, double* w) {
   if (!s || !s->have_gen) { g_last_error = "no generator"; return LB_ERR_STATE; }
   return export_site(s->kraus, site, l, r, w);
+}
+
+lb_status lindblad_gemm_tune_save(const char* path) {
+  try {
+    if (!path) throw Fail(LB_ERR_ARG, "NULL path");
+    std::vector<std::pair<GemmKey, int>> rows;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      rows.assign(g_tune.begin(), g_tune.end());
+    }
+    FILE* f = std::fopen(path, "w");
+    if (!f) throw Fail(LB_ERR_ARG, std::string("cannot write ") + path);
+    for (const auto& r : rows) {
+      const GemmKey& k = r.first;
+      std::fprintf(f,
+                   "{\"M\": %d, \"N\": %d, \"K\": %d, \"batch\": %d, \"pa\": %d, \"pb\": %d, \"pc\": %d, "
+                   "\"comp\": %d, \"herm\": %d, \"conjA\": %d, \"conjB\": %d, \"akf\": %d, \"bnf\": %d, "
+                   "\"splits\": %d}\n",
+                   k.M, k.N, k.K, k.batch, k.pa, k.pb, k.pc, k.comp, k.herm, k.conjA, k.conjB, k.akf, k.bnf, r.second);
+    }
+    const bool ok = std::fclose(f) == 0;
+    if (!ok) throw Fail(LB_ERR_ARG, std::string("cannot write ") + path);
+    return LB_OK;
+  } catch (const Fail& f) {
+    return fail(f);
+  }
+}
+
+lb_status lindblad_gemm_tune_load(const char* path) {
+  try {
+    if (!path) throw Fail(LB_ERR_ARG, "NULL path");
+    FILE* f = std::fopen(path, "r");
+    if (!f) throw Fail(LB_ERR_ARG, std::string("cannot read ") + path);
+    std::vector<std::pair<GemmKey, int>> rows;
+    char line[1024];
+    int ln = 0;
+    std::string err;
+    while (std::fgets(line, sizeof(line), f)) {
+      ++ln;
+      const std::string t(line);
+      if (t.find_first_not_of(" \t\r\n") == std::string::npos) continue;
+      // "name": integer, for every field
+      static const char* names[14] = {"M", "N", "K", "batch", "pa", "pb", "pc", "comp", "herm", "conjA", "conjB",
+                                      "akf", "bnf", "splits"};
+      int v[14];
+      for (int q = 0; q < 14 && err.empty(); ++q) {
+        const std::string key = std::string("\"") + names[q] + "\":";
+        const size_t at = t.find(key);
+        if (at == std::string::npos || std::sscanf(t.c_str() + at + key.size(), " %d", &v[q]) != 1)
+          err = "line " + std::to_string(ln) + ": no integer field " + names[q];
+      }
+      if (err.empty() && (v[13] < 1 || v[13] > 64)) err = "line " + std::to_string(ln) + ": splits outside 1..64";
+      if (!err.empty()) break;
+      rows.push_back({GemmKey{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8], v[9], v[10], v[11], v[12]},
+                      v[13]});
+    }
+    std::fclose(f);
+    if (!err.empty()) throw Fail(LB_ERR_ARG, std::string(path) + ", " + err);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& r : rows) g_tune.emplace(r.first, r.second);
+    return LB_OK;
+  } catch (const Fail& f) {
+    return fail(f);
+  }
+}
+
+int64_t lindblad_gemm_tune_entries(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return (int64_t)g_tune.size();
 }
 
 const char* lindblad_last_error(void) { return g_last_error.c_str(); }

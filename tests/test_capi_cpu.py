@@ -25,7 +25,7 @@ def _declared_symbols():
     names = set()
     for h in ("lindblad.h", "lindblad_kernels.h", "lindblad_serve.h"):
         text = open(os.path.join(ROOT, "include", h)).read()
-        names |= set(re.findall(r"^\s*(?:lb_status|void|const char\*)\s+(lindblad_\w+)\s*\(", text, re.M))
+        names |= set(re.findall(r"^\s*(?:lb_status|void|const char\*|int64_t)\s+(lindblad_\w+)\s*\(", text, re.M))
     return sorted(names)
 
 
@@ -238,3 +238,38 @@ def test_rk4_order_refuses_jumps_and_unstable_dt():
     with pytest.raises(api.LindbladError) as e:
         api.solver_from_model(m, order=4, chi=16, chi_mu=1, state="none")
     assert e.value.code == LB_ERR_ARG
+
+
+def test_gemm_tune_table_round_trip(tmp_path):
+    """The split-count table (lb_config.autotune) saved and loaded as JSON
+    lines: entries merge, a saved file reloads to the same entries, and a
+    line missing a field or with splits outside 1..64 is refused."""
+    import json
+    from paper_2605_27515_amd import api
+    n0 = api.gemm_tune_entries()
+    rows = [dict(M=256, N=256, K=11648, batch=1, pa=1, pb=1, pc=0, comp=0, herm=1, conjA=0, conjB=1, akf=1,
+                 bnf=0, splits=8),
+            dict(M=64, N=64, K=4093, batch=1, pa=0, pb=0, pc=0, comp=0, herm=0, conjA=1, conjB=0, akf=0,
+                 bnf=1, splits=16)]
+    src = tmp_path / "tune.jsonl"
+    src.write_text("".join(json.dumps(r) + "\n" for r in rows) + "\n")
+    api.gemm_tune_load(src)
+    assert api.gemm_tune_entries() == n0 + 2
+    out = tmp_path / "out.jsonl"
+    api.gemm_tune_save(out)
+    saved = [json.loads(line) for line in out.read_text().splitlines()]
+    for r in rows:
+        assert r in saved
+    # a second load of the same entries adds nothing
+    api.gemm_tune_load(out)
+    assert api.gemm_tune_entries() == n0 + 2
+    bad = tmp_path / "bad.jsonl"
+    bad.write_text(json.dumps({k: v for k, v in rows[0].items() if k != "herm"}) + "\n")
+    with pytest.raises(api.LindbladError):
+        api.gemm_tune_load(bad)
+    bad.write_text(json.dumps(dict(rows[0], splits=0)) + "\n")
+    with pytest.raises(api.LindbladError):
+        api.gemm_tune_load(bad)
+    with pytest.raises(api.LindbladError):
+        api.gemm_tune_load(tmp_path / "missing.jsonl")
+    assert api.gemm_tune_entries() == n0 + 2

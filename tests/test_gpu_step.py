@@ -124,6 +124,18 @@ def test_step_autotuned(precision, rtol, tol):
     GEMMs; the results still meet the oracle at the form's tolerance."""
     _compare(wl.model_cat_buffer(Ra=4, Rb=3, alpha2=4.0, dt=2.5e-5), 40, 32, 8, precision, rtol, tol,
              autotune=True)
+    # the tuned split counts are in the process-wide table, which saves as
+    # JSON lines with splits in 1..64
+    import json
+    import tempfile
+    api = _api()
+    assert api.gemm_tune_entries() > 0
+    with tempfile.TemporaryDirectory() as d:
+        path = f"{d}/tune.jsonl"
+        api.gemm_tune_save(path)
+        rows = [json.loads(line) for line in open(path)]
+    assert len(rows) == api.gemm_tune_entries()
+    assert all(1 <= r["splits"] <= 64 for r in rows)
 
 
 @pytest.mark.parametrize("precision,rtol,tol", FORMS)
