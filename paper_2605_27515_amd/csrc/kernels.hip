@@ -160,12 +160,18 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmK g) {
     }
   };
 
+  // complex products by three real ones (Gauss): p = ar br, q = ai bi,
+  // t = (ar + ai)(br + bi); Re = p - q, Im = t - p - q
   typedef typename Acc<TC>::type AV;
-  AV acc_r[2][2], acc_i[2][2];
+  AV acc_p[2][2], acc_q[2][2], acc_t[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y) { acc_r[x][y] = AV{0, 0, 0, 0}; acc_i[x][y] = AV{0, 0, 0, 0}; }
+    for (int y = 0; y < 2; ++y) {
+      acc_p[x][y] = AV{0, 0, 0, 0};
+      acc_q[x][y] = AV{0, 0, 0, 0};
+      acc_t[x][y] = AV{0, 0, 0, 0};
+    }
 
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int lr = lane & 15, lk = lane >> 4;
@@ -186,14 +192,16 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmK g) {
         b_r[x] = Bs_r[kk + lk][wn + x * 16 + lr];
         b_i[x] = Bs_i[kk + lk][wn + x * 16 + lr];
       }
+      TC a_s[2], b_s[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) { a_s[x] = a_r[x] + a_i[x]; b_s[x] = b_r[x] + b_i[x]; }
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y) {
-          acc_r[x][y] = mfma(a_r[x], b_r[y], acc_r[x][y]);
-          acc_r[x][y] = mfma(-a_i[x], b_i[y], acc_r[x][y]);
-          acc_i[x][y] = mfma(a_r[x], b_i[y], acc_i[x][y]);
-          acc_i[x][y] = mfma(a_i[x], b_r[y], acc_i[x][y]);
+          acc_p[x][y] = mfma(a_r[x], b_r[y], acc_p[x][y]);
+          acc_q[x][y] = mfma(a_i[x], b_i[y], acc_q[x][y]);
+          acc_t[x][y] = mfma(a_s[x], b_s[y], acc_t[x][y]);
         }
     }
   }
@@ -211,7 +219,8 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmK g) {
         const int i = i0 + wm + x * 16 + (f64acc ? 4 * r + lk : 4 * lk + r);
         const int j = j0 + wn + y * 16 + lr;
         if (i >= gd.M || j >= gd.N) continue;
-        const double vr = (double)acc_r[x][y][r], vi = (double)acc_i[x][y][r];
+        const TC p = acc_p[x][y][r], q = acc_q[x][y][r];
+        const double vr = (double)(p - q), vi = (double)(acc_t[x][y][r] - p - q);
         if (g.splits > 1) {
           TC* ws = reinterpret_cast<TC*>(g.ws);
           const long long off = 2 * ((((long long)b * g.splits + split) * gd.M + i) * gd.N + j);
@@ -586,14 +595,21 @@ hipError_t copy_cols(const double* src, Dim lds, double* dst, Dim ldd, Dim rows,
 
 __global__ void tail_split_kernel(const double* lam, Dim nD, double c, int cap, int* dd, int j0_slot, int k_slot,
                                   int kv_slot) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  // j0 = the first index whose eigenvalue is not >= c lam[0] (n if none),
+  // found by all threads at once (the values are descending), at most n - 1
+  __shared__ int first;
   const int n = dim_val(nD, dd);
-  int j0 = 0;
+  if (threadIdx.x == 0) first = n;
+  __syncthreads();
   if (n > 0) {
     const double t = c * lam[0];
-    while (j0 < n && lam[j0] >= t) ++j0;
-    if (j0 > n - 1) j0 = n - 1;
+    for (int j = threadIdx.x; j < n; j += blockDim.x)
+      if (!(lam[j] >= t)) atomicMin(&first, j);
   }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  int j0 = 0;
+  if (n > 0) j0 = min(first, n - 1);
   const bool tail = j0 < cap;
   dd[j0_slot] = j0;
   dd[k_slot] = tail ? n - j0 : 0;
