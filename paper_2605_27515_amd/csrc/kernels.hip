@@ -524,41 +524,67 @@ hipError_t heev_jacobi(double* G, int ldg, long long g_stride, Dim n, double* w,
 
 __global__ void truncate_kernel(const double* lam, Dim nD, const int* dd, double tol, int cap, int* k_out,
                                 double* disc, int* err, int full_cap, int* over) {
-  const int n = dim_val(nD, dd);
-  // the eigenvalues are staged in LDS by all threads; the sums stay serial,
-  // in index order, so the decision is that of the plain rule
-  __shared__ double sl[512];
-  for (int j = threadIdx.x; j < n; j += blockDim.x) sl[j] = lam[j];
-  __syncthreads();
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  // one wave: lane l holds the eigenvalues of its chunk [l c, (l + 1) c);
+  // suf[j] = sum of lam_i over i >= j (negative noise clamped to zero), from
+  // the chunk sums and a suffix scan over the lanes
+  const int n = min(dim_val(nD, dd), 512);
+  const int lane = threadIdx.x;
+  __shared__ double suf[513];
   if (n < 1) {
-    *k_out = 1;
-    if (disc) *disc = 0.0;
+    if (lane == 0) {
+      *k_out = 1;
+      if (disc) *disc = 0.0;
+    }
     return;
   }
+  const int c = (n + 63) / 64, j0 = lane * c, j1 = min(j0 + c, n);
+  double v[8];
   bool bad = false;
-  for (int j = 0; j < n; ++j) {
-    bad |= !isfinite(sl[j]);
-    sl[j] = fmax(sl[j], 0.0);
+  double cs = 0.0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    double x = 0.0;
+    if (i < c && j0 + i < j1) {
+      x = lam[j0 + i];
+      bad |= !isfinite(x);
+      x = fmax(x, 0.0);
+    }
+    v[i] = x;
   }
-  if (bad && err) *err = *err | 2;
-  const double* lam_ = sl;
-  double total = 0.0;
-  for (int j = 0; j < n; ++j) total += lam_[j];
+#pragma unroll
+  for (int i = 7; i >= 0; --i) cs += v[i];
+  double after = cs;   // inclusive suffix scan of the chunk sums over the lanes
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const double o = __shfl_down(after, d, 64);
+    if (lane + d < 64) after += o;
+  }
+  double run = after - cs;   // the chunks after this lane's
+#pragma unroll
+  for (int i = 7; i >= 0; --i) {
+    run += v[i];
+    if (i < c && j0 + i < j1) suf[j0 + i] = run;
+  }
+  if (lane == 0) suf[n] = 0.0;
+  const bool any_bad = __ballot(bad) != 0ull;
+  __syncthreads();
+  // the smallest k >= 1 whose tail sum_{j >= k} lam_j is within tol^2 of the
+  // total (the tail sums fall with k, and the tail past n is zero)
+  const double total = suf[0], thr = tol * tol * total;
   int k = n;
-  double tail = 0.0;
-  while (k > 1 && tail + lam_[k - 1] <= tol * tol * total) {
-    tail += lam_[k - 1];
-    --k;
-  }
+  for (int j = lane + 1; j <= n; j += 64)
+    if (suf[j] <= thr) k = min(k, j);
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) k = min(k, __shfl_xor(k, d, 64));
+  if (lane != 0) return;
+  if (any_bad && err) *err = *err | 2;
   if (cap > 0 && k > cap) {
     if (over && full_cap > cap) *over = 1;
-    for (int j = cap; j < k; ++j) tail += lam_[j];
     k = cap;
   }
   if (k < 1) k = 1;
   *k_out = k;
-  if (disc) *disc = total > 0.0 ? tail / total : 0.0;
+  if (disc) *disc = total > 0.0 ? suf[k] / total : 0.0;
 }
 
 hipError_t truncate_rank(const double* lam, Dim n, double tol, int cap, int* k_out, double* disc, int* err,
