@@ -1167,6 +1167,8 @@ void drop_graph(lb_solver* s) {
     if (kv.second.g) (void)hipGraphDestroy(kv.second.g);
   }
   s->graphs.clear();
+  // a new generator or layout brings new GEMM bounds: tune its first steps
+  s->tuned.clear();
 }
 
 // Free every device buffer of the solver (state, workspace, MPOs); the host
