@@ -26,8 +26,10 @@ positivity invariants, exact polynomial MPO ranks (paper Table I, exact row),
 and brute-force agreement of the MPS step with the dense Kraus map on small
 Hilbert spaces.
 
-Parity unpinned: the zip-up truncation inside Oracle-M is not compared to
-any closed form when it is active (it is an approximation with no exact
-target); it is pinned only in the regime where it is inactive (brute force)
-and by the invariants.
+The zip-up truncation inside Oracle-M, an approximation with no exact
+target when it is active, is pinned by its error bound: with a cap below the
+exact zip-up ranks, its product stays within the telescoped sum of the
+discarded weights times the exact continuations to their right
+(``tests/test_oracle_pins.py``), and without the cap it equals the exact
+product; where it is inactive, the brute-force step tests pin it as well.
 """
