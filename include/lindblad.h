@@ -55,7 +55,10 @@ typedef enum lb_status {
 } lb_status;
 
 enum lb_precision {
-  LB_FP64 = 0,          /* every contraction in complex128                       */
+  LB_FP64 = 0,          /* every contraction in complex128; the factorisations
+                           as below (the tail decomposed again, twice below
+                           tol 1e-10), or with a Jacobi second pass
+                           (lb_config.fp64_jacobi_pass)                       */
   LB_FP32_CONTRACT = 1  /* MPO/MPS contractions of the Kraus MPO's increment
                            (U1' - 1, the mixed members with U1 - 1 in place
                            of U1, the L_k L_k' members) in complex64 with
