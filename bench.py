@@ -325,6 +325,29 @@ def cpu_baseline(budget_s: float, one_core: bool = False) -> dict:
                       f"{dt:.1f} s), after one warm-up step", "host_cpus": os.cpu_count()}
 
 
+def trajectory_leg(steps: int, precision: str) -> dict:
+    """The chi = 128 configuration from vacuum x vacuum for a short stretch:
+    the small-bond regime, where a step is bound by its launches, not by
+    flops (launch tiers follow the bonds)."""
+    import torch
+    import workload as wl
+    from paper_2605_27515_amd import api
+    m = wl.model_cat_buffer(Ra=8, Rb=8, alpha2=8.0, dt=2.5e-5)
+    s = api.solver_from_model(m, precision=precision, chi=128, chi_mu=16, device=0)
+    s.step(32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    d = s.diagnostics()
+    s.close()
+    return {"workload": "cat+buffer 2x256 Fock (16 sites), chi=128, chi_mu=16, tol=1e-8, dt=2.5e-5, "
+                        "vacuum x vacuum start, after 32 steps", "precision": precision, "steps": steps,
+            "steps_per_s": steps / el, "ms_per_step": 1e3 * el / steps, "max_bond": max(d["bonds"]),
+            "chi_mu": d["chi_mu"], "tier": d["tier"]}
+
+
 def chi256_leg(steps: int, precision: str) -> dict:
     """Driven transmon + resonator (charge states -512..511, resonator 4096
     levels, 22 sites), chi = 256, chi_mu = 32, from a seeded state saturated
@@ -540,6 +563,8 @@ def main():
     ap.add_argument("--serve-baseline-requests", type=int, default=64,
                     help="requests of the plain-FP64 one-at-a-time baseline (the stream's first ones)")
     ap.add_argument("--chi256-steps", type=int, default=3, help="steps of the chi=256 leg (0: skip)")
+    ap.add_argument("--trajectory-leg-steps", type=int, default=960,
+                    help="steps of the small-bond trajectory leg (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
     ap.add_argument("--kerr-steps", type=int, default=1000, help="steps of the kerr-rk4 workload")
@@ -593,6 +618,11 @@ def main():
         e64 = gpu_run(args.fp64_steps, 1, "fp64")[0]
         fp64 = args.fp64_steps / e64
         print(f"bench: plain fp64 {fp64:.3f} steps/s", file=sys.stderr, flush=True)
+    traj = None
+    if args.trajectory_leg_steps > 0:
+        traj = trajectory_leg(args.trajectory_leg_steps, args.precision)
+        print(f"bench: trajectory from vacuum {traj['steps_per_s']:.1f} steps/s (max bond {traj['max_bond']})",
+              file=sys.stderr, flush=True)
     c256 = None
     if args.chi256_steps > 0:
         c256 = chi256_leg(args.chi256_steps, args.precision)
@@ -638,6 +668,7 @@ def main():
         "cpu_baseline_one_core": cpu1,
         "fp64_plain_steps_per_s": fp64,
         "chi256": c256,
+        "trajectory": traj,
         "kernel_ms_per_step": {k: v["ms"] / PROFILE_STEPS for k, v in prof.items() if v["launches"]},
         "kernel_share": {k: v["ms"] / total_ms for k, v in prof.items() if v["launches"]} if total_ms else {},
         "final_bonds": diag["bonds"],
