@@ -436,11 +436,12 @@ def zgate_main(args) -> None:
     m, z = wl.model_cat_zgate(Ra=8, Rb=4, dt_max=args.zgate_dt, chi=args.zgate_chi, chi_mu=16)
     print(f"bench: cat Z gate, {m.steps} steps of dt={m.dt:.3e}, {args.precision}; building the Kraus MPO",
           file=sys.stderr, flush=True)
-    w = api.solver_from_model(m, precision=args.precision, device=0)
+    floor = args.zgate_fp32_floor if args.precision == "fp32" else 0.0
+    w = api.solver_from_model(m, precision=args.precision, device=0, fp32_tol_floor=floor)
     if args.warmup:
         w.step(args.warmup)
     w.close()
-    s = api.solver_from_model(m, precision=args.precision, device=0)
+    s = api.solver_from_model(m, precision=args.precision, device=0, fp32_tol_floor=floor)
     parity = s.mpo(wl.parity_operator(0, m.dims[0]))
     n_run = m.steps if args.zgate_steps <= 0 else min(args.zgate_steps, m.steps)
     chunk = 250
@@ -493,7 +494,8 @@ def zgate_main(args) -> None:
         "config": {"workload": f"cat Z gate: memory 2^8 Fock, buffer 2^4 (12 sites), |alpha|^2={z.alpha2:.3f}, "
                                f"g2=1, kappa_b=10, eps_Z={z.eps_z}, theta=pi, T_Z={z.t_gate:.4f}, dt={m.dt:.4e}, "
                                f"4 Kraus ops, chi cap {m.chi}, chi_mu cap {m.chi_mu}, tol {m.tol}, even-cat start",
-                   "precision": args.precision, "parallelism": "single solve, one GPU"},
+                   "precision": args.precision, "parallelism": "single solve, one GPU",
+                   "fp32_tol_floor": floor},
         "gate_seconds": elapsed,
         "p_z": p_z, "p_z_law": law, "p_z_over_law": p_z / law if whole else None, "final_parity": p,
         "trace": tr, "purity": pur, "final_bonds": diag["bonds"], "final_chi_mu": diag["chi_mu"],
@@ -576,6 +578,10 @@ def main():
     ap.add_argument("--trajectory-steps", type=int, default=5000)
     ap.add_argument("--zgate-dt", type=float, default=2e-4, help="largest time step of the Z-gate run")
     ap.add_argument("--zgate-chi", type=int, default=128, help="bond cap of the Z-gate run")
+    ap.add_argument("--zgate-fp32-floor", type=float, default=1e-7,
+                    help="FP32 form of the Z-gate run: floor of the back-sweep and purification tolerance "
+                         "(lb_config.fp32_tol_floor; 0: the paper's tol 1e-8, whose cuts keep the complex64 "
+                         "noise of the 10628 steps until it fills the caps)")
     ap.add_argument("--zgate-steps", type=int, default=0,
                     help="time only the first N steps of the gate (0: the whole gate, with its phase-flip probability)")
     ap.add_argument("--counter-run", type=int, default=0,
