@@ -9,8 +9,10 @@
 //   S1   zip-up, site i = 0..L-2:
 //          P = C_i . X_i                         (stage 1 GEMM)
 //          T = W_i^t . P, batched over C's rows   (stage 2 GEMM)
-//          G = T T^H (FP64), eigen(G) -> U, lambda (FP64 two-pass refinement
-//          in LB_FP64: B = U^H T, G2 = B B^H, eigen(G2))
+//          G = T T^H (FP64), eigen(G) -> U, lambda, the spectral tail
+//          decomposed again where the cut reaches it (B = U_t^H T,
+//          G_t = B B^H, eigen(G_t)); with fp64_jacobi_pass a full second
+//          pass instead (B = U^H T, G2 = B B^H, Jacobi(G2))
 //          k = rule(lambda, tol_zip, chi_zip); X_i <- U[:, :k];
 //          C_{i+1} = U[:, :k]^H T
 //   S2   last site: G' = T^H T over (Kraus x purification) columns,
@@ -19,9 +21,16 @@
 //        eigen, k = rule(tol, chi); X_i <- S^-1 U_k^H M; X_{i-1} <- X_{i-1} U_k S
 //   S4   tau = ||X_0||^2, X_0 /= sqrt(tau)
 // The singular values and left singular vectors of each unfolding come from
-// the eigen-decomposition of its Gram matrix; in LB_FP64 a second pass on
-// the rotated matrix restores absolute FP64 accuracy of the small singular
-// values (the first pass alone resolves them only to sqrt(eps) relative).
+// the eigen-decomposition of its Gram matrix; the first pass resolves the
+// small singular values only to ~sqrt(eps) of the largest, so the tail below
+// 1e-9 of the largest eigenvalue is decomposed again from the operand
+// projected on it (twice in LB_FP64 below tol 1e-10).
+//
+// Launches are sized for bounds and read the actual sizes from a device
+// table; a step is one captured HIP graph per launch tier (bounds of a power
+// of two above the bonds while those are far below the caps, the caps
+// otherwise), and the first step of a tier may time the GEMM split counts
+// (autotune).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

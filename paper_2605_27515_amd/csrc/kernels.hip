@@ -3,8 +3,9 @@
 //  * gemm_kernel   complex GEMM on MFMA (v_mfma_f64_16x16x4f64 or
 //                  v_mfma_f32_16x16x4f32), 64x64 output tile per 256-thread
 //                  workgroup (4 waves x 32x32), K staged through LDS in
-//                  slices of 16, one-slice register prefetch, optional
-//                  split-K with a fixed-order reduction.
+//                  slices of 16, one-slice register prefetch, three real
+//                  MFMAs per complex product, optional split-K with a
+//                  fixed-order reduction.
 //  * heev_kernel   Hermitian eigen-decomposition by cyclic Jacobi with the
 //                  round-robin parallel ordering (one workgroup per matrix).
 //  * tridiagonal route (hetrd_kernel / hetrd_mc_kernel, stebz_kernel, stein_kernel,
