@@ -2545,8 +2545,75 @@ __global__ __launch_bounds__(SG_NT) void stein_unresolved_project_kernel(Dim nD,
   for (int r = threadIdx.x; r < n; r += SG_NT) Z[(long long)r * ldz + j] = yl[r];
 }
 
+// Few resolved vectors, many unresolved: an orthonormal basis of the
+// complement of the resolved span is Q[:, nres..] of the Householder QR of
+// the resolved columns, Q = H_0 H_1 ... H_{nres-1}.  V (n x nres, column
+// major) and tau (nres) are workspace; the QR takes O(n nres^2) and each
+// unresolved column O(n nres), against O(n nun^2) for orthonormalising random
+// columns chunk by chunk.  Q is orthogonal to rounding, so the columns need
+// no further orthonormalisation here.
+constexpr int UR_QR_MAX = 64;   // resolved columns, at most, for this form
+__device__ void unresolved_qr(int n, int nres, int nun, const int* cols, const int* ucols, double* Z, int ldz,
+                              double* V, double* tau, double* red, double* ql) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NW = SG_NT / 64;
+  for (long long idx = tid; idx < (long long)n * nres; idx += SG_NT) {
+    const int c = (int)(idx / n), i = (int)(idx % n);
+    V[idx] = Z[(long long)i * ldz + cols[c]];
+  }
+  __syncthreads();
+  for (int kk = 0; kk < nres; ++kk) {
+    double* x = V + (long long)kk * n;
+    double part = 0.0;
+    for (int i = kk + 1 + tid; i < n; i += SG_NT) part += x[i] * x[i];
+    part = wave_sum(part);
+    if (lane == 0) red[wave] = part;
+    __syncthreads();
+    double xn2 = 0.0;
+    for (int q = 0; q < NW; ++q) xn2 += red[q];
+    const double alpha = x[kk];
+    double tk = 0.0, scale = 0.0;
+    if (xn2 > 0.0) {
+      const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+      tk = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    __syncthreads();   // every thread has read alpha and red
+    for (int i = kk + 1 + tid; i < n; i += SG_NT) x[i] *= scale;
+    if (tid == 0) {
+      x[kk] = 1.0;
+      tau[kk] = tk;
+    }
+    __syncthreads();
+    // H_kk = I - tk v v^T on the remaining columns, one wave per column
+    for (int j = kk + 1 + wave; j < nres; j += NW) {
+      double* y = V + (long long)j * n;
+      double d = 0.0;
+      for (int i = kk + lane; i < n; i += 64) d += x[i] * y[i];
+      d = wave_sum(d) * tk;
+      for (int i = kk + lane; i < n; i += 64) y[i] -= d * x[i];
+    }
+    __syncthreads();
+  }
+  // unresolved column m: Q e_{nres+m}, built in LDS by the reflectors from
+  // the last to the first, then written to its column of Z
+  double* q = ql + wave * 512;
+  for (int m = wave; m < nun; m += NW) {
+    for (int i = lane; i < n; i += 64) q[i] = (i == nres + m) ? 1.0 : 0.0;
+    for (int kk = nres - 1; kk >= 0; --kk) {
+      const double* v = V + (long long)kk * n;
+      double d = 0.0;
+      for (int i = kk + lane; i < n; i += 64) d += v[i] * q[i];
+      d = wave_sum(d) * tau[kk];
+      for (int i = kk + lane; i < n; i += 64) q[i] -= d * v[i];
+    }
+    const long long col = ucols[m];
+    for (int i = lane; i < n; i += 64) Z[(long long)i * ldz + col] = q[i];
+  }
+}
+
 __global__ __launch_bounds__(SG_NT) void stein_unresolved_kernel(Dim nD, const double* w, Dim kD, const int* dd,
-                                                                 double* Z) {
+                                                                 double* Z, double* qrw) {
   const int n = dim_val(nD, dd), k = min(dim_val(kD, dd), n), ldz = n;
   if (n < 1 || k < 1) return;
   __shared__ int cols[512], ucols[512];
@@ -2574,6 +2641,13 @@ __global__ __launch_bounds__(SG_NT) void stein_unresolved_kernel(Dim nD, const d
   // are completed one at a time
   if (k < n && fabs(w[n - 1]) > floor_abs) {
     unresolved_serial(n, k, w, floor_abs, 0, nres, cols, Z, ldz, zl, dots, red);
+    return;
+  }
+  // (a single chunk of random columns is cheap: the QR form only from one
+  // full chunk of unresolved columns on)
+  if (qrw && nres >= 1 && nres <= UR_QR_MAX && nun > nres && nun >= UC) {
+    __shared__ double ql[(SG_NT / 64) * 512];
+    unresolved_qr(n, nres, nun, cols, ucols, Z, ldz, qrw, qrw + (long long)n * nres, red, ql);
     return;
   }
   // stein_unresolved_project_kernel has filled the unresolved columns and
@@ -2683,7 +2757,9 @@ hipError_t trid_vectors(Dim n, const TridWork& t, const double* w, Dim kvec, hip
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(stein_unresolved_project_kernel, dim3(kmax), dim3(SG_NT), 0, s, n, w, kvec, dd, t.Z);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(stein_unresolved_kernel, dim3(1), dim3(SG_NT), 0, s, n, w, kvec, dd, t.Z);
+  // the QR completion's workspace: the reduction's mailboxes, free after it
+  // (n x 64 + 64 doubles at most, within their 4 n^2)
+  hipLaunchKernelGGL(stein_unresolved_kernel, dim3(1), dim3(SG_NT), 0, s, n, w, kvec, dd, t.Z, t.sync + 16);
   return hipGetLastError();
 }
 
