@@ -16,7 +16,9 @@ Three levels, each a plain NumPy/LAPACK implementation in float64/complex128:
   stacked Kraus-family MPO (paper Sec. 2.1-2.2, Sec. 5.1 matrix addition).
 * ``oracle.mps``    -- Oracle-M: the purified-MPS step (zip-up apply,
   purification truncation, truncated-SVD back-sweep, renormalisation) and
-  observables by transfer matrices.
+  observables by transfer matrices; the pure-state global RK4 (Sec. 3.1.1).
+* ``oracle.tdvp``   -- one-site TDVP with the fourth-order Magnus Hamiltonian
+  for a pure state (Sec. 3.1.3), dense local exponentials.
 
 Pins (``tests/test_oracle_*.py``, marked ``not gpu``): closed forms for a
 coherent state and a Fock state under loss, RK4 order 4 / Kraus order 2
