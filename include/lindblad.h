@@ -401,7 +401,9 @@ lb_status lindblad_profile_read(lb_solver* s, lb_profile* out);
 
 /* ---- GEMM split-count table (lb_config.autotune) -------------------------- */
 
-/* The process-wide table of tuned split-K counts, keyed by a GEMM's bounds
+/* Not an operation of the paper: the GEMMs are its MPO/MPS contractions
+ * (Sec. 3.1.1 zip-up, Sec. 5.1), and the split count only orders their sums.
+ * The process-wide table of tuned split-K counts, keyed by a GEMM's bounds
  * (M, N, K, batch), operand/output/compute precisions, Hermitian flag,
  * conjugations and unit-stride layout.  Save writes it to the file at path
  * (UTF-8 text, one JSON object per line with the integer fields M, N, K,
@@ -412,7 +414,7 @@ lb_status lindblad_profile_read(lb_solver* s, lb_profile* out);
  * unwritable file, a line without every field, splits outside 1..64). */
 lb_status lindblad_gemm_tune_save(const char* path);
 lb_status lindblad_gemm_tune_load(const char* path);
-/* Number of entries in the table. */
+/* Number of entries in the table (host only, never fails). */
 int64_t lindblad_gemm_tune_entries(void);
 
 /* Message of the last failing call on this thread ("" if none). */
