@@ -154,6 +154,30 @@ def test_footprint_host_only():
     assert 1 << 20 < f["fp64", 16] < 1 << 30
 
 
+def test_footprint_counts_the_tier_backup():
+    """Launch tiers keep a device copy of the state to undo a run: the
+    footprint with them exceeds the one with fixed bounds by that copy (every
+    site at its capacity, the size table, status and discarded weights, in
+    the block cache's size classes), and the other config fields change
+    nothing on the device."""
+    _lib_or_skip()
+    from paper_2605_27515_amd import api
+    m = wl.model_cat_buffer(Ra=5, Rb=5, alpha2=4.0, dt=2.5e-5)
+    f = {}
+    for kw in ({}, {"fixed_bounds": True}, {"autotune": True}, {"fp64_jacobi_pass": True}):
+        s = api.solver_from_model(m, precision="fp64", chi=32, chi_mu=8, state="none", **kw)
+        f[tuple(kw)] = s.footprint()
+        s.close()
+    backup = f[()] - f[("fixed_bounds",)]
+    L = sum(m.bits)
+    site_bytes = 32 * 2 * 32 * 16                 # the largest site at chi = 32
+    # at least every site at chi = 32; a site's capacity also covers the
+    # zip-up's wider bonds, and the block is rounded up to a power of two
+    assert L * site_bytes <= backup <= 16 * L * site_bytes, (backup, f)
+    assert f[("autotune",)] == f[()]
+    assert f[("fp64_jacobi_pass",)] == f[()]
+
+
 def test_server_argument_errors_host_only():
     _lib_or_skip()
     from paper_2605_27515_amd import api
