@@ -90,7 +90,10 @@ typedef struct lb_config {
                                       (Sec. 5.2.2); 4: the global RK4 of the
                                       Schroedinger equation on a pure state
                                       (Sec. 3.1.1; no jumps, chi_mu_cap 1, the
-                                      norm not renormalised)                   */
+                                      norm not renormalised); 5: one-site TDVP
+                                      with the fourth-order Magnus Hamiltonian
+                                      (Sec. 3.1.3; pure state, LB_FP64 only,
+                                      bonds fixed by the state)                 */
   int32_t precision;               /* enum lb_precision                          */
   int32_t allow_unstable;          /* nonzero: skip the dt stability check       */
   void* stream;                    /* hipStream_t to use; NULL = a private stream */
@@ -240,7 +243,20 @@ typedef struct lb_drive {          /* f(t) = sum_j coef_j cos(omega_j t + phase_
  * degree-4 Taylor polynomial of exp(-i dt H0) without one), applied to the
  * pure state by the same zip-up and compressed; n_jumps must be 0
  * (LB_ERR_ARG) and dt * (||H0|| + max|f| ||H1||) must be at most 2.8, inside
- * RK4's stability interval (LB_ERR_UNSTABLE unless cfg.allow_unstable). */
+ * RK4's stability interval (LB_ERR_UNSTABLE unless cfg.allow_unstable).
+ * With cfg.order == 5 the step is one symmetric sweep of one-site TDVP
+ * (paper Sec. 3.1.3) under the fourth-order Magnus Hamiltonian of
+ * [t, t + dt], H_Omega = H0 + c1 H1 + c2 [H0, H1] with c1 = (f(t1) +
+ * f(t2))/2, c2 = i sqrt(3) dt (f(t2) - f(t1))/12 and t1,2 = t + (3 -+
+ * sqrt 3) dt / 6: H0, H1 and their commutator are stacked on site 0's left
+ * index once, and every step combines them with the two weights on the
+ * device.  H0 and H1 must be Hermitian and f real; n_jumps must be 0
+ * (LB_ERR_ARG).  Each local exponential is exact (dense eigen-decomposition),
+ * so the bonds of the loaded state are kept (a redundant bond direction is
+ * dropped by the first sweep) and the norm is conserved up to rounding.
+ * lindblad_step returns LB_ERR_ARG when a site has 2 l r > 512, an inner bond
+ * has chi^2 > 512 (the dense local problems' largest order), or the
+ * purification rank is not 1. */
 lb_status lindblad_set_generator(lb_solver* s, const lb_op* H0, const lb_op* H1,
                                  const lb_drive* f, const lb_op* const* L,
                                  int32_t n_jumps, double dt);

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblindblad.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["engine.hip", "kernels.hip", "capi_kernels.hip", "mpo.cpp", "hostla.cpp", "serve.cpp"]
+SOURCES = ["engine.hip", "kernels.hip", "tdvp.hip", "capi_kernels.hip", "mpo.cpp", "hostla.cpp", "serve.cpp"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-pthread",
              # packed FP32 instructions stay off: some of their forms have given
              # wrong results with no error

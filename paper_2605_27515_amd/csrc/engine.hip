@@ -50,6 +50,7 @@
 #include "../../include/lindblad.h"
 #include "kernels.h"
 #include "mpo.h"
+#include "tdvp.h"
 
 using lb::cd;
 
@@ -319,6 +320,19 @@ struct lb_solver {
   std::vector<Pending> pending;
   double p_ms[LB_PROF_CLASSES] = {0}, p_flop[LB_PROF_CLASSES] = {0}, p_bytes[LB_PROF_CLASSES] = {0};
   long long p_n[LB_PROF_CLASSES] = {0};
+
+  // order 5, one-site TDVP with the fourth-order Magnus Hamiltonian (Sec.
+  // 3.1.3): the MPO of H0, or of H0, H1 and [H0, H1] stacked on site 0's left
+  // index (channel weights 1, c1, c2 per step), and its device work
+  lb::Mpo tdvp_W;
+  int tdvp_np = 1;
+  struct Tdvp {
+    DevBuf W, B0, env, e1, e2, H, U, S, Tn, w, work, qrw, C, Xt;
+    std::vector<long long> woff;        // complex offset of site i in W
+    std::vector<int> wl, wr;            // MPO bonds of site i as applied (wl[0] = 1)
+    std::vector<long long> loff, roff;  // complex offsets of L[i], R[i] in env
+    bool ready = false;
+  } td;
 
   // diagnostics
   double t = 0.0;
@@ -1145,6 +1159,235 @@ void alloc_state(lb_solver* s) {
   if (!s->cfg.fixed_bounds) s->bk.alloc(backup_bytes(s, s->site_cap), s->stream, &s->arena);
 }
 
+// ---- order 5: one-site TDVP of a pure state (Sec. 3.1.3) -----------------------
+// Environments L[i] (left of site i) and R[i] (right of site i - 1) at bond
+// i, of size cap_i x D_i x cap_i, D_i the MPO bond as applied (D_0 = D_L =
+// 1); the local effective Hamiltonians are dense matrices of order 2 l r
+// (a site) and l r (a bond), at most lbt::kMaxLocal.
+
+struct TdvpPlan {
+  std::vector<int> D;
+  std::vector<long long> woff, loff, roff;
+  long long wtot = 0, etot = 0, e1 = 1, e2 = 1, b0 = 0;
+};
+
+TdvpPlan tdvp_plan(const lb_solver* s, const std::vector<int>& cap) {
+  const int L = s->L;
+  TdvpPlan p;
+  p.D.assign(L + 1, 1);
+  for (int i = 1; i < L; ++i) p.D[i] = s->tdvp_W[i].l;
+  p.woff.resize(L);
+  for (int i = 0; i < L; ++i) {
+    p.woff[i] = p.wtot;
+    p.wtot += (long long)p.D[i] * 4 * p.D[i + 1];
+  }
+  p.loff.resize(L + 1);
+  p.roff.resize(L + 1);
+  for (int i = 0; i <= L; ++i) {
+    const long long e = (long long)cap[i] * cap[i] * p.D[i];
+    p.loff[i] = p.etot;
+    p.etot += e;
+    p.roff[i] = p.etot;
+    p.etot += e;
+  }
+  for (int i = 0; i < L; ++i) {
+    p.e1 = std::max(p.e1, (long long)cap[i] * p.D[i] * 2 * cap[i + 1]);
+    p.e2 = std::max(p.e2, (long long)cap[i] * 2 * p.D[i + 1] * cap[i + 1]);
+  }
+  p.b0 = (long long)s->tdvp_np * 4 * p.D[1];
+  return p;
+}
+
+constexpr size_t kTdvpQrDoubles = 8 * (size_t)lbt::kMaxLocal + 64;   // >= qr_work_doubles(m, n), m n <= kMaxLocal
+
+size_t tdvp_bytes(const lb_solver* s, const std::vector<int>& cap, size_t site_cap) {
+  const TdvpPlan p = tdvp_plan(s, cap);
+  const size_t nn = (size_t)lbt::kMaxLocal * lbt::kMaxLocal * 16;
+  return size_class(p.wtot * 16) + size_class(p.b0 * 16) + size_class(p.etot * 16) + size_class(p.e1 * 16) +
+         size_class(p.e2 * 16) + 4 * size_class(nn) + size_class(lbt::kMaxLocal * 8) +
+         size_class(lbk::heev_tridiag_work_doubles(lbt::kMaxLocal) * 8) + size_class(kTdvpQrDoubles * 8) +
+         size_class(lbt::kMaxLocal * 16) + size_class(site_cap * 16);
+}
+
+void tdvp_alloc(lb_solver* s) {
+  const TdvpPlan p = tdvp_plan(s, s->cap);
+  hipStream_t st = s->stream;
+  Arena* ar = &s->arena;
+  auto& t = s->td;
+  const size_t nn = (size_t)lbt::kMaxLocal * lbt::kMaxLocal * 16;
+  t.W.alloc(p.wtot * 16, st, ar);
+  t.B0.alloc(p.b0 * 16, st, ar);
+  t.env.alloc(p.etot * 16, st, ar);
+  t.e1.alloc(p.e1 * 16, st, ar);
+  t.e2.alloc(p.e2 * 16, st, ar);
+  for (DevBuf* b : {&t.H, &t.U, &t.S, &t.Tn}) b->alloc(nn, st, ar);
+  t.w.alloc(lbt::kMaxLocal * 8, st, ar);
+  t.work.alloc(lbk::heev_tridiag_work_doubles(lbt::kMaxLocal) * 8, st, ar);
+  t.qrw.alloc(kTdvpQrDoubles * 8, st, ar);
+  t.C.alloc(lbt::kMaxLocal * 16, st, ar);
+  t.Xt.alloc(s->site_cap * 16, st, ar);
+  // sites 1.. as built; site 0 is combined from its stacked channels per step
+  std::vector<cd> buf(p.wtot, cd(0.0, 0.0));
+  for (int i = 1; i < s->L; ++i) std::copy(s->tdvp_W[i].w.begin(), s->tdvp_W[i].w.end(), buf.begin() + p.woff[i]);
+  copy_in(s, t.W.p, buf.data(), buf.size() * sizeof(cd));
+  copy_in(s, t.B0.p, s->tdvp_W[0].w.data(), (size_t)p.b0 * sizeof(cd));
+  // the boundary environments L[0] = R[L] = 1
+  const cd one(1.0, 0.0);
+  copy_in(s, static_cast<cd*>(t.env.p) + p.loff[0], &one, sizeof(cd));
+  copy_in(s, static_cast<cd*>(t.env.p) + p.roff[s->L], &one, sizeof(cd));
+  t.woff = p.woff;
+  t.wl.assign(p.D.begin(), p.D.end() - 1);
+  t.wr.assign(p.D.begin() + 1, p.D.end());
+  t.loff = p.loff;
+  t.roff = p.roff;
+  t.ready = true;
+}
+
+void tdvp_release(lb_solver* s) {
+  auto& t = s->td;
+  for (DevBuf* b : {&t.W, &t.B0, &t.env, &t.e1, &t.e2, &t.H, &t.U, &t.S, &t.Tn, &t.w, &t.work, &t.qrw, &t.C, &t.Xt})
+    b->release();
+  t.ready = false;
+}
+
+double drive_at(const lb_solver* s, double t) {
+  double f = 0.0;
+  for (size_t j = 0; j < s->drv_c.size(); ++j) f += s->drv_c[j] * std::cos(s->drv_w[j] * t + s->drv_p[j]);
+  return f;
+}
+
+// Site 0 of H_Omega for the step [t0, t0 + h]: the channels H0, H1, [H0, H1]
+// weighted by 1, (f(t1) + f(t2)) / 2 and i (sqrt 3 h / 12)(f(t2) - f(t1)),
+// t1,2 = t0 + (3 -+ sqrt 3) h / 6 (Sec. 3.1.3, the fourth-order Magnus
+// Hamiltonian of H0 + f(t) H1).
+void tdvp_site0(lb_solver* s, double t0) {
+  auto& t = s->td;
+  const double h = s->dt;
+  double cre[3] = {1.0, 0.0, 0.0}, cim[3] = {0.0, 0.0, 0.0};
+  if (s->tdvp_np == 3) {
+    const double r3 = std::sqrt(3.0);
+    const double f1 = drive_at(s, t0 + (3.0 - r3) / 6.0 * h), f2 = drive_at(s, t0 + (3.0 + r3) / 6.0 * h);
+    cre[1] = 0.5 * (f1 + f2);
+    cim[2] = r3 * h / 12.0 * (f2 - f1);
+  }
+  HIPCHK(lbt::combine(static_cast<const double*>(t.B0.p), 4LL * t.wr[0], s->tdvp_np, cre, cim,
+                      static_cast<double*>(t.W.p) + 2 * t.woff[0], s->stream));
+}
+
+// x <- exp(-i tau H) x for the dense Hermitian H of order n in td.H
+// (destroyed): tridiagonal eigen-decomposition, two Newton-Schulz steps on
+// its vectors, then the exponential through them.
+void tdvp_expm(lb_solver* s, int n, double* x, double tau) {
+  auto& t = s->td;
+  double* U = static_cast<double*>(t.U.p);
+  double* w = static_cast<double*>(t.w.p);
+  HIPCHK(lbk::heev_tridiag(static_cast<double*>(t.H.p), n, n, w, U, n, n, static_cast<double*>(t.work.p), s->stream));
+  HIPCHK(lbk::orthonormalize_columns(U, n, Dim(n), Dim(n), static_cast<double*>(t.S.p), static_cast<double*>(t.Tn.p),
+                                     2, nullptr, s->stream));
+  lbk::StepStat* stp = reinterpret_cast<lbk::StepStat*>(s->stat.p);
+  HIPCHK(lbt::expv(U, n, w, n, tau, x, &stp->err, s->stream));
+}
+
+// One symmetric one-site TDVP step over h: left to right, each site forward
+// over h/2 under its one-site effective Hamiltonian, its QR, the bond matrix
+// backward over h/2 under the zero-site one and absorbed into the next site;
+// then the same right to left.  On entry sites 1.. are right-orthonormal;
+// so they are on exit.  chi (host) follows the bonds: a QR of a 2l x r site
+// with r > 2l leaves 2l (only a state with redundant bonds has one).
+void tdvp_sweep(lb_solver* s, std::vector<int>& chi, double h) {
+  auto& t = s->td;
+  const int L = s->L;
+  hipStream_t st = s->stream;
+  double* env = static_cast<double*>(t.env.p);
+  auto Lp = [&](int i) { return env + 2 * t.loff[i]; };
+  auto Rp = [&](int i) { return env + 2 * t.roff[i]; };
+  auto Wp = [&](int i) { return static_cast<double*>(t.W.p) + 2 * t.woff[i]; };
+  auto Xp = [&](int i) { return static_cast<double*>(s->X[i].p); };
+  double* e1 = static_cast<double*>(t.e1.p);
+  double* e2 = static_cast<double*>(t.e2.p);
+  double* H = static_cast<double*>(t.H.p);
+  double* C = static_cast<double*>(t.C.p);
+  double* Xt = static_cast<double*>(t.Xt.p);
+  double* qw = static_cast<double*>(t.qrw.p);
+  for (int i = L - 1; i >= 1; --i)
+    HIPCHK(lbt::env_right(Rp(i + 1), Xp(i), Wp(i), chi[i], chi[i + 1], t.wl[i], t.wr[i], e2, e1, Rp(i), st));
+  const double tau = 0.5 * h;
+  for (int i = 0; i < L; ++i) {
+    const int l = chi[i], r = chi[i + 1];
+    HIPCHK(lbt::heff_site(Lp(i), Wp(i), Rp(i + 1), l, r, t.wl[i], t.wr[i], H, st));
+    tdvp_expm(s, 2 * l * r, Xp(i), tau);
+    if (i == L - 1) break;
+    // X_i (2l x r) = Q C: Q is the new site (l x 2 x k), C (k x r) the bond
+    const int k = std::min(2 * l, r);
+    HIPCHK(lbt::qr(Xp(i), r, 1, 2 * l, r, Xp(i), k, 1, C, r, 1, qw, st));
+    chi[i + 1] = k;
+    HIPCHK(lbt::env_left(Lp(i), Xp(i), Wp(i), l, k, t.wl[i], t.wr[i], e1, e2, Lp(i + 1), st));
+    HIPCHK(lbt::heff_bond(Lp(i + 1), Rp(i + 1), k, r, t.wr[i], H, st));
+    tdvp_expm(s, k * r, C, -tau);
+    const int r2 = chi[i + 2];
+    HIPCHK(lbt::absorb_left(C, Xp(i + 1), k, r, r2, Xt, st));
+    HIPCHK(hipMemcpyAsync(Xp(i + 1), Xt, (size_t)k * 2 * r2 * sizeof(cd), hipMemcpyDeviceToDevice, st));
+  }
+  for (int i = L - 1; i >= 0; --i) {
+    const int l = chi[i], r = chi[i + 1];
+    HIPCHK(lbt::heff_site(Lp(i), Wp(i), Rp(i + 1), l, r, t.wl[i], t.wr[i], H, st));
+    tdvp_expm(s, 2 * l * r, Xp(i), tau);
+    if (i == 0) break;
+    // X_i^T (2r x l) = Q C: Q^T is the new site (k x 2 x r), C^T (l x k) the bond
+    const int k = std::min(2 * r, l);
+    HIPCHK(lbt::qr(Xp(i), 1, 2 * r, 2 * r, l, Xp(i), 1, 2 * r, C, 1, k, qw, st));
+    chi[i] = k;
+    HIPCHK(lbt::env_right(Rp(i + 1), Xp(i), Wp(i), k, r, t.wl[i], t.wr[i], e2, e1, Rp(i), st));
+    HIPCHK(lbt::heff_bond(Lp(i), Rp(i), l, k, t.wl[i], H, st));
+    tdvp_expm(s, l * k, C, -tau);
+    const int l2 = chi[i - 1];
+    HIPCHK(lbt::absorb_right(Xp(i - 1), C, l2, l, k, Xt, st));
+    HIPCHK(hipMemcpyAsync(Xp(i - 1), Xt, (size_t)l2 * 2 * k * sizeof(cd), hipMemcpyDeviceToDevice, st));
+  }
+}
+
+void tdvp_run(lb_solver* s, int n_steps) {
+  if (!s->td.ready) throw Fail(LB_ERR_STATE, "internal: TDVP work not allocated");
+  if (s->unsynced) wait_stream(s);
+  check_err(s);
+  const int L = s->L;
+  std::vector<int> chi = s->chi;
+  if (chi[L] != 1) throw Fail(LB_ERR_ARG, "order 5 (TDVP) evolves a pure state: purification rank must be 1");
+  for (int i = 1; i < L; ++i)
+    if (chi[i] > s->cap[i])
+      throw Fail(LB_ERR_ARG, "order 5 (TDVP): bond " + std::to_string(i) + " = " + std::to_string(chi[i]) +
+                                 " exceeds what the sites on either side can carry (" + std::to_string(s->cap[i]) +
+                                 ")");
+  long long nmax = 1;
+  for (int i = 0; i < L; ++i) {
+    const long long d = 2LL * chi[i] * chi[i + 1];
+    if (d > lbt::kMaxLocal)
+      throw Fail(LB_ERR_ARG, "order 5 (TDVP): site " + std::to_string(i) + " has 2 l r = " + std::to_string(d) +
+                                 " > " + std::to_string(lbt::kMaxLocal));
+    nmax = std::max(nmax, d);
+  }
+  for (int i = 1; i < L; ++i) {
+    const long long d = (long long)chi[i] * chi[i];
+    if (d > lbt::kMaxLocal)
+      throw Fail(LB_ERR_ARG, "order 5 (TDVP): bond " + std::to_string(i) + " has chi^2 = " + std::to_string(d) +
+                                 " > " + std::to_string(lbt::kMaxLocal));
+    nmax = std::max(nmax, d);
+  }
+  reserve_cus(s, lbk::trid_coresident_workgroups((int)nmax));
+  const std::vector<int> before = chi;
+  for (int k = 0; k < n_steps; ++k) {
+    tdvp_site0(s, (double)(s->steps + k) * s->dt);
+    tdvp_sweep(s, chi, s->dt);
+  }
+  if (chi != before) {
+    // the first sweep removed redundant bond directions: the size table follows
+    copy_in(s, static_cast<int*>(s->dd.p) + sl_chi(s, 0), chi.data(), (size_t)(L + 1) * sizeof(int));
+    for (int i = 0; i <= L; ++i) s->hd[sl_chi(s, i)] = chi[i];
+    s->chi = chi;
+  }
+  s->unsynced = true;
+}
+
 // Device bytes a solver holds once its generator and state are on the device
 // (the size classes the block cache hands out).
 size_t footprint_bytes(const lb_solver* s) {
@@ -1167,6 +1410,7 @@ size_t footprint_bytes(const lb_solver* s) {
   }
   if (s->degree > 1) t += size_class(s->h0.size() * sizeof(cd));
   if (!s->cfg.fixed_bounds) t += size_class(backup_bytes(s, site_cap));
+  if (s->cfg.order == 5) t += tdvp_bytes(s, cap, site_cap);
   return t;
 }
 
@@ -1198,6 +1442,7 @@ void release_device(lb_solver* s) {
   for (auto& b : s->W.d32) b.release();
   for (auto& b : s->WL.d64) b.release();
   s->Wb0.release();
+  tdvp_release(s);
   for (auto& op : s->ops) {
     for (auto& b : op->dev.d64) b.release();
     for (auto& b : op->dev.d32) b.release();
@@ -1235,6 +1480,7 @@ void ensure_generator_on_device(lb_solver* s) {
   if (fp32(s)) upload_mpo(s, s->lead, s->WL, false);
   if (s->cap.empty()) alloc_state(s);
   alloc_workspace(s);
+  if (s->cfg.order == 5) tdvp_alloc(s);
   set_tier(s, 0);
   s->gen_on_device = true;
 }
@@ -1775,7 +2021,9 @@ lb_status lindblad_create(const lb_config* cfg, lb_solver** out) {
     if (cfg->chi_mu_cap < 1 || cfg->chi_mu_cap > 256) throw Fail(LB_ERR_ARG, "chi_mu_cap out of range");
     if (cfg->chi_zip_cap < 0 || cfg->chi_zip_cap > 256) throw Fail(LB_ERR_ARG, "chi_zip_cap out of range");
     if (!(cfg->tol >= 0.0) || cfg->tol >= 1.0) throw Fail(LB_ERR_ARG, "tol out of range");
-    if (cfg->order != 1 && cfg->order != 2 && cfg->order != 4) throw Fail(LB_ERR_ARG, "order must be 1, 2 or 4");
+    if (cfg->order != 1 && cfg->order != 2 && cfg->order != 4 && cfg->order != 5)
+      throw Fail(LB_ERR_ARG, "order must be 1, 2, 4 or 5");
+    if (cfg->order == 5 && cfg->precision != LB_FP64) throw Fail(LB_ERR_ARG, "order 5 (TDVP) runs in LB_FP64 only");
     if (cfg->precision != LB_FP64 && cfg->precision != LB_FP32_CONTRACT) throw Fail(LB_ERR_ARG, "bad precision");
     if (cfg->arena && cfg->arena_bytes <= 0) throw Fail(LB_ERR_ARG, "arena without a size");
     if (cfg->arena && ((uintptr_t)cfg->arena & 255)) throw Fail(LB_ERR_ARG, "arena not 256-byte aligned");
@@ -1930,6 +2178,22 @@ lb_status lindblad_set_generator(lb_solver* s, const lb_op* H0, const lb_op* H1,
           }
       }
       fam.push_back(words);
+    } else if (s->cfg.order == 5) {
+      // One-site TDVP of a pure state with the fourth-order Magnus
+      // Hamiltonian (Sec. 3.1.3): H_Omega = H0 + c1 H1 + c2 [H0, H1] per step,
+      // the three MPOs stacked on site 0's left index and the commutator
+      // formed once.  The Kraus family is the identity (this order does not
+      // apply it).
+      if (n_jumps != 0) throw Fail(LB_ERR_ARG, "order 5 (TDVP) takes no jump operators");
+      if (drive) {
+        const Mpo comm = add(c(mpo_mul(H0->mpo, B)), mpo_scale(c(mpo_mul(B, H0->mpo)), cd(-1.0, 0.0)));
+        s->tdvp_W = c(boundary_stack({H0->mpo, B, comm}));
+        s->tdvp_np = 3;
+      } else {
+        s->tdvp_W = c(H0->mpo);
+        s->tdvp_np = 1;
+      }
+      fam.push_back({zero});
     } else {
       // The family split by order in h: the leading part (the identity of the
       // first member, sqrt(h/2) L_k of the mixed members; sqrt(h) L_k at first
@@ -2208,7 +2472,9 @@ lb_status lindblad_step(lb_solver* s, int32_t n_steps) {
     HIPCHK(hipSetDevice(s->cfg.device));
     check_err(s);   // the state is invalid after a failed step until set_state
     if (n_steps == 0) return LB_OK;
-    if (s->cfg.fixed_bounds || s->prof_on || s->in_batch || !s->bk.p) {
+    if (s->cfg.order == 5) {
+      tdvp_run(s, n_steps);
+    } else if (s->cfg.fixed_bounds || s->prof_on || s->in_batch || !s->bk.p) {
       // every launch bounded by the caps; the steps run behind the call
       if (s->tier != 0) set_tier(s, 0);
       reserve_cus(s, step_coresident(s));

@@ -264,6 +264,28 @@ def test_rk4_order_refuses_jumps_and_unstable_dt():
     assert e.value.code == LB_ERR_ARG
 
 
+def test_tdvp_order_refuses_fp32_jumps_and_counts_its_work():
+    """order = 5 (one-site TDVP with the Magnus-4 Hamiltonian, paper Sec.
+    3.1.3): the FP32 form is refused at create, jump operators at
+    set_generator, and the footprint counts the dense local work (four
+    512 x 512 complex matrices at least) beside the state."""
+    _lib_or_skip()
+    from paper_2605_27515_amd import api
+    from paper_2605_27515_amd._lib import LB_ERR_ARG
+    m = wl.model_driven_kerr(R=6, dt=1e-3)
+    with pytest.raises(api.LindbladError) as e:
+        api.solver_from_model(m, order=5, precision="fp32", chi=16, chi_mu=1, state="none")
+    assert e.value.code == LB_ERR_ARG
+    with pytest.raises(api.LindbladError) as e:
+        api.solver_from_model(wl.model_coherent_loss(), order=5, chi=16, chi_mu=1, state="none")
+    assert e.value.code == LB_ERR_ARG
+    s5 = api.solver_from_model(m, order=5, chi=16, chi_mu=1, state="none")
+    s4 = api.solver_from_model(m, order=4, chi=16, chi_mu=1, state="none")
+    assert s5.footprint() >= s4.footprint() // 4 + 4 * 512 * 512 * 16
+    s5.close()
+    s4.close()
+
+
 def test_gemm_tune_table_round_trip(tmp_path):
     """The split-count table (lb_config.autotune) saved and loaded as JSON
     lines: entries merge, a saved file reloads to the same entries, and a
