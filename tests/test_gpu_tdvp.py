@@ -130,3 +130,81 @@ def test_tdvp_refuses_local_problems_above_512():
         s.step(1)
     assert "512" in str(e.value)
     s.close()
+
+
+class _Mem:
+    """hipMalloc / hipFree of the library's runtime (test plumbing)."""
+
+    def __init__(self):
+        import ctypes as C
+        from paper_2605_27515_amd import _lib
+        _lib.load()
+        self.C = C
+        self.h = C.CDLL("libamdhip64.so.7", mode=C.RTLD_GLOBAL)
+        self.h.hipMalloc.argtypes = [C.POINTER(C.c_void_p), C.c_size_t]
+        self.h.hipFree.argtypes = [C.c_void_p]
+        self.h.hipSetDevice.argtypes = [C.c_int]
+        assert self.h.hipSetDevice(0) == 0
+
+    def alloc(self, nbytes):
+        p = self.C.c_void_p()
+        assert self.h.hipMalloc(self.C.byref(p), nbytes) == 0
+        return p.value
+
+    def free(self, p):
+        self.h.hipFree(p)
+
+
+def _same(Xa, Xb):
+    assert len(Xa) == len(Xb)
+    for a, b in zip(Xa, Xb):
+        assert a.shape == b.shape
+        assert np.array_equal(a, b)
+
+
+def test_tdvp_resume_batch_and_arena_are_bitwise():
+    """A checkpoint taken after 5 of 10 steps and restored continues bit for
+    bit (the drive's clock included); two solvers stepped together by
+    step_batch each equal one stepped alone; a solver whose buffers come from
+    an arena of lindblad_footprint bytes gives the same state."""
+    api = _api()
+    m = wl.model_driven_kerr(R=6, alpha0=2.0, dt=2e-3)
+    X0 = tdvp.right_orthonormal(mps.product_state(m.init, m.bits, m.site_order(), tol=1e-10))
+    X0[0] = X0[0] / np.linalg.norm(_vec(X0, m))
+    print(f"case tdvp resume/batch/arena R=6, bonds {mps.bond_dims(X0)}", flush=True)
+
+    def mk(**kw):
+        s = api.solver_from_model(m, order=5, chi=32, chi_mu=1, state="none", **kw)
+        s.set_state_mps(X0)
+        return s
+    a = mk()
+    a.step(10)
+    Xa = a.get_state_mps()
+    need = a.footprint()
+    a.close()
+    b = mk()
+    b.step(5)
+    ck = b.get_state_mps()
+    b.close()
+    c = api.solver_from_model(m, order=5, chi=32, chi_mu=1, state="none")
+    c.restore_state(ck, 5)
+    c.step(5)
+    _same(c.get_state_mps(), Xa)
+    assert c.diagnostics()["steps"] == 10
+    c.close()
+    d, e = mk(), mk()
+    api.step_batch([d, e], 10)
+    _same(d.get_state_mps(), Xa)
+    _same(e.get_state_mps(), Xa)
+    d.close()
+    e.close()
+    mem = _Mem()
+    size = need + (8 << 20)
+    arena = mem.alloc(size)
+    try:
+        f = mk(arena=arena, arena_bytes=size)
+        f.step(10)
+        _same(f.get_state_mps(), Xa)
+        f.close()
+    finally:
+        mem.free(arena)
