@@ -19,6 +19,9 @@ Three levels, each a plain NumPy/LAPACK implementation in float64/complex128:
   observables by transfer matrices; the pure-state global RK4 (Sec. 3.1.1).
 * ``oracle.tdvp``   -- one-site TDVP with the fourth-order Magnus Hamiltonian
   for a pure state (Sec. 3.1.3), dense local exponentials.
+* ``oracle.comb``   -- the quantics comb for M modes (Sec. 4.2-4.3: backbone
+  tensors with one quantics tooth per mode) and the purified Kraus step on
+  it, operators as sums of products of single-mode matrices.
 
 Pins (``tests/test_oracle_*.py``, marked ``not gpu``): closed forms for a
 coherent state and a Fock state under loss, RK4 order 4 / Kraus order 2

@@ -1,0 +1,394 @@
+"""Oracle: the quantics comb for M modes (paper Sec. 4.2-4.3) and the purified
+second-order Kraus step on it.
+
+TEST INFRASTRUCTURE ONLY (see the package header).
+
+Format.  The purification Psi[n_1, ..., n_M, mu] is an inter-mode MPS
+  Psi = P_1(n_1) P_2(n_2) ... P_M(n_M),  P_a(n) an e_a x e_{a+1} matrix,
+with e_1 = 1 and e_{M+1} = chi_mu: the purification index mu is the open
+right bond of the last mode (the paper lets it sit anywhere; the chain layout
+of this package puts it at the end too).  Each local tensor is in turn a
+quantics chain hanging from a backbone tensor (Sec. 4.3):
+  P_a(n)_{e e'} = sum_q B_a[e, q, e'] Q_a(n)_q,
+  Q_a(n) = T_1(s_1) T_2(s_2) ... T_R(s_R),  n = sum_i 2^(R-i) s_i,
+with the most significant digit s_1 next to the backbone (the ordering the
+paper found to compress slightly better).  A tooth core is T[q, s, q'], the
+last one with q' = 1.
+
+Operators act on the comb as sums of products of single-mode matrices
+(`terms`: a list of (coef, {mode: N x N matrix})), the form in which every
+Hamiltonian, jump operator and Kraus operator of the paper is written.  A
+product term multiplies each local tensor P_a by its factor (exact); sums
+and the stacking of Kraus images over mu are the block-diagonal additions of
+Sec. 5.1 (vector addition keeps mu, matrix addition concatenates it).
+
+One Kraus step:
+  1. the local tensors P_a of the comb;
+  2. the images K_k Psi (each a sum over K_k's product terms, its partial
+     sums compressed at 1e-14), stacked along mu (the matrix addition rho = sum_k K_k rho
+     K_k^dag, Sec. 5.2.1);
+  3. compression of the inter-mode MPS: a left-to-right QR sweep, the
+     purification cut of the last mode's (e, n) x mu matrix at (tol, chi_mu),
+     then a right-to-left truncated-SVD sweep at (tol, chi_e) that leaves the
+     orthogonality centre on mode 1;
+  4. tau = ||Psi||^2, Psi /= sqrt(tau) (Sec. 5.2.2);
+  5. each P_a re-split into backbone tensor and quantics tooth by truncated
+     SVDs at (tol, chi_q).
+Truncation rule everywhere: the smallest rank whose discarded squared
+singular values sum to at most tol^2 of the total (tt.keep_rank).  The local
+tensors are dense in n (N = 2^R states per mode), which is what makes this a
+reference for small modes only.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .operators import factor_matrix
+from .tt import keep_rank, svd
+
+
+@dataclass
+class Comb:
+    B: list            # B[a]: (e_a, q_a, e_{a+1})
+    T: list            # T[a]: list of R_a tooth cores (q, 2, q'), most significant digit first
+    bits: list
+
+
+@dataclass
+class CombStepInfo:
+    tau: float = 1.0
+    chi_mu: int = 1
+    backbone: list = field(default_factory=list)     # e_2 .. e_M after the step
+    teeth: list = field(default_factory=list)        # per mode, the tooth bonds q_a, q_{a,1}, ...
+    # bound on ||Psi_kept - Psi|| from each truncation, in units of the
+    # normalised state (step 3's cuts sit at the orthogonality centre; step
+    # 5's act on right-orthonormal tensors or the centre)
+    psi_bounds: list = field(default_factory=list)
+
+
+# ---- teeth and local tensors ------------------------------------------------------
+
+def _chain_svd(mat: np.ndarray, R: int, tol: float, cap: int | None = None):
+    """Quantics chain of the rows of mat (left x 2^R), most significant digit
+    first: cores (left, 2, k) ... (k', 2, 1); returns (cores, discarded
+    absolute squared weights per cut)."""
+    cores, disc = [], []
+    left = mat.shape[0]
+    rest = mat
+    for i in range(R - 1):
+        m = rest.reshape(left * 2, -1)
+        u, s, vh = svd(m)
+        k = 1 if s[0] == 0.0 else keep_rank(s, tol, cap)
+        disc.append(float(np.sum(s[k:] ** 2)))
+        cores.append(u[:, :k].reshape(left, 2, k))
+        rest = s[:k, None] * vh[:k]
+        left = k
+    cores.append(rest.reshape(left, 2, 1))
+    return cores, disc
+
+
+def tooth_matrix(cores) -> np.ndarray:
+    """Q[q, n] of a tooth (n over the mode's 2^R states, MSB first)."""
+    acc = cores[0]                                   # (q, 2, r)
+    for c in cores[1:]:
+        acc = np.einsum('qnr,rsk->qnsk', acc, c).reshape(acc.shape[0], -1, c.shape[2])
+    return acc[:, :, 0]
+
+
+def local_tensor(comb: Comb, a: int) -> np.ndarray:
+    """P_a[e, n, e'] = sum_q B_a[e, q, e'] Q_a[q, n]."""
+    return np.einsum('eqf,qn->enf', comb.B[a], tooth_matrix(comb.T[a]))
+
+
+def split_local(P: np.ndarray, R: int, tol: float, cap: int | None = None):
+    """Backbone tensor and tooth of one local tensor P[e, n, e'] (Sec. 4.3):
+    the SVD of the (e e') x n matrix gives B = U (isometric) and the tooth is
+    the quantics chain of S V^dag.  Returns (B, cores, discarded squared
+    weights: the backbone cut first, then the tooth's)."""
+    e, N, f = P.shape
+    M = P.transpose(0, 2, 1).reshape(e * f, N)
+    u, s, vh = svd(M)
+    k = 1 if s[0] == 0.0 else keep_rank(s, tol, cap)
+    B = u[:, :k].reshape(e, f, k).transpose(0, 2, 1)
+    cores, disc = _chain_svd(s[:k, None] * vh[:k], R, tol, cap)
+    return np.ascontiguousarray(B), cores, [float(np.sum(s[k:] ** 2))] + disc
+
+
+def from_locals(Ps, bits, tol: float = 0.0, cap: int | None = None) -> Comb:
+    B, T = [], []
+    for a, P in enumerate(Ps):
+        b, cores, _ = split_local(P, bits[a], tol, cap)
+        B.append(b)
+        T.append(cores)
+    return Comb(B=B, T=T, bits=list(bits))
+
+
+def locals_of(comb: Comb) -> list[np.ndarray]:
+    return [local_tensor(comb, a) for a in range(len(comb.B))]
+
+
+# ---- dense conversions ------------------------------------------------------------
+
+def inter_to_tensor(Ps) -> np.ndarray:
+    """Psi[n_1, ..., n_M, mu] of an inter-mode MPS."""
+    acc = Ps[0][0]                                   # (N_1, e_2)
+    for P in Ps[1:]:
+        acc = (acc @ P.reshape(P.shape[0], -1)).reshape(-1, P.shape[2])
+    return acc.reshape([P.shape[1] for P in Ps] + [Ps[-1].shape[2]])
+
+
+def to_tensor(comb: Comb) -> np.ndarray:
+    return inter_to_tensor(locals_of(comb))
+
+
+def to_matrix(comb: Comb) -> np.ndarray:
+    """X[(n_1 ... n_M), mu], mode 0 the most significant (the dense oracle's order)."""
+    t = to_tensor(comb)
+    return t.reshape(-1, t.shape[-1])
+
+
+def from_tensor(psi: np.ndarray, bits, tol: float = 0.0) -> Comb:
+    """Comb of Psi[n_1, ..., n_M, mu]: a left-to-right TT-SVD over the modes
+    (the backbone), then each local tensor split into backbone tensor and
+    tooth, every cut at relative tolerance tol."""
+    dims = [1 << r for r in bits]
+    mu = psi.shape[-1]
+    Ps = []
+    left = 1
+    rest = psi.reshape(1, -1)
+    for a in range(len(dims) - 1):
+        m = rest.reshape(left * dims[a], -1)
+        u, s, vh = svd(m)
+        k = 1 if s[0] == 0.0 else keep_rank(s, tol)
+        Ps.append(u[:, :k].reshape(left, dims[a], k))
+        rest = s[:k, None] * vh[:k]
+        left = k
+    Ps.append(rest.reshape(left, dims[-1], mu))
+    return from_locals(Ps, bits, tol)
+
+
+def product_comb(vectors, bits) -> Comb:
+    """Comb of a product state (backbone bonds 1, purification rank 1)."""
+    Ps = [np.asarray(v, complex).reshape(1, -1, 1) for v in vectors]
+    return from_locals(Ps, bits, 1e-14)
+
+
+def n_params(comb: Comb) -> int:
+    return sum(b.size for b in comb.B) + sum(c.size for t in comb.T for c in t)
+
+
+# ---- operators as sums of products ---------------------------------------------------
+
+def op_terms(terms, dims) -> list:
+    """(coef, {mode: matrix}) from the workload's term descriptions."""
+    out = []
+    for coef, factors in terms:
+        out.append((complex(coef), {m: factor_matrix(f, dims[m]) for m, f in factors.items()}))
+    return out
+
+
+def op_identity() -> list:
+    return [(1.0 + 0.0j, {})]
+
+
+def op_scale(A, c) -> list:
+    return [(c * x, f) for (x, f) in A]
+
+
+def op_add(*ops) -> list:
+    return [t for A in ops for t in A]
+
+
+def op_mul(A, B) -> list:
+    """The product A B, term by term (factors on one mode multiply)."""
+    out = []
+    for ca, fa in A:
+        for cb, fb in B:
+            f = dict(fa)
+            for m, mat in fb.items():
+                f[m] = f[m] @ mat if m in f else mat
+            out.append((ca * cb, f))
+    return out
+
+
+def op_dagger(A) -> list:
+    return [(np.conj(c), {m: mat.conj().T for m, mat in f.items()}) for (c, f) in A]
+
+
+def op_dense(A, dims) -> np.ndarray:
+    """Dense matrix of a sum of products (mode 0 most significant)."""
+    D = int(np.prod(dims))
+    out = np.zeros((D, D), complex)
+    for c, f in A:
+        m = np.eye(1, dtype=complex)
+        for a, n in enumerate(dims):
+            m = np.kron(m, f.get(a, np.eye(n, dtype=complex)))
+        out += c * m
+    return out
+
+
+def kraus_ops(H, Ls, h: float) -> list:
+    """The second-order Kraus family (Sec. 5.2.2) as sums of products, in the
+    stacking order of the chain oracle: U1', sqrt(h/2) U1 L_k, sqrt(h/2) L_k U1,
+    (h / sqrt 2) L_k L_k'.  H_eff = H - (i/2) sum_k L_k^dag L_k,
+    U1 = 1 - i h H_eff, U1' = U1 - (h^2/2) H_eff^2."""
+    G = op_add(*[op_mul(op_dagger(L), L) for L in Ls]) if Ls else []
+    He = op_add(H, op_scale(G, -0.5j))
+    U1 = op_add(op_identity(), op_scale(He, -1j * h))
+    U1p = op_add(U1, op_scale(op_mul(He, He), -0.5 * h * h))
+    fam = [U1p]
+    fam += [op_scale(op_mul(U1, L), np.sqrt(h / 2)) for L in Ls]
+    fam += [op_scale(op_mul(L, U1), np.sqrt(h / 2)) for L in Ls]
+    fam += [op_scale(op_mul(L, Lp), h / np.sqrt(2.0)) for L in Ls for Lp in Ls]
+    return fam
+
+
+# ---- inter-mode MPS algebra ---------------------------------------------------------
+
+def apply_term(Ps, coef, factors) -> list[np.ndarray]:
+    """(coef prod_a F_a) Psi on the local tensors: P_a(n) -> sum_n' F_a[n, n'] P_a(n')."""
+    out = []
+    for a, P in enumerate(Ps):
+        Q = np.tensordot(factors[a], P, axes=([1], [1])).transpose(1, 0, 2) if a in factors else P.copy()
+        out.append(Q)
+    out[0] = coef * out[0]
+    return out
+
+
+def inter_add(terms) -> list[np.ndarray]:
+    """Vector addition of inter-mode MPS with the same mu dimension: the
+    first site concatenated along its right bond, the inner ones block
+    diagonal, the last one concatenated along its left bond (Sec. 5.1)."""
+    if len(terms) == 1:
+        return [P.copy() for P in terms[0]]
+    M = len(terms[0])
+    if M == 1:
+        return [sum(t[0] for t in terms)]
+    out = []
+    for a in range(M):
+        if a == 0:
+            out.append(np.concatenate([t[0] for t in terms], axis=2))
+        elif a == M - 1:
+            out.append(np.concatenate([t[a] for t in terms], axis=0))
+        else:
+            l = sum(t[a].shape[0] for t in terms)
+            r = sum(t[a].shape[2] for t in terms)
+            P = np.zeros((l, terms[0][a].shape[1], r), complex)
+            i = j = 0
+            for t in terms:
+                x = t[a]
+                P[i:i + x.shape[0], :, j:j + x.shape[2]] = x
+                i += x.shape[0]
+                j += x.shape[2]
+            out.append(P)
+    return out
+
+
+def inter_stack_mu(images) -> list[np.ndarray]:
+    """Matrix addition: the images side by side along mu, [Psi_1 | Psi_2 | ...]
+    (block diagonal everywhere, the last site's mu concatenated)."""
+    if len(images) == 1:
+        return [P.copy() for P in images[0]]
+    M = len(images[0])
+    if M == 1:
+        return [np.concatenate([im[0] for im in images], axis=2)]
+    out = []
+    for a in range(M):
+        if a == 0:
+            out.append(np.concatenate([im[0] for im in images], axis=2))
+            continue
+        l = sum(im[a].shape[0] for im in images)
+        r = sum(im[a].shape[2] for im in images)
+        P = np.zeros((l, images[0][a].shape[1], r), complex)
+        i = j = 0
+        for im in images:
+            x = im[a]
+            P[i:i + x.shape[0], :, j:j + x.shape[2]] = x
+            i += x.shape[0]
+            j += x.shape[2]
+        out.append(P)
+    return out
+
+
+def apply_op(Ps, A) -> list[np.ndarray]:
+    """A Psi for A a sum of products: the terms' images added eight at a time,
+    each partial sum compressed at 1e-14 (numerical zeros only; the sum's
+    bond is otherwise the number of terms times the state's)."""
+    parts = [apply_term(Ps, c, f) for (c, f) in A]
+    while True:
+        parts = [compress(inter_add(parts[i:i + 8]), 1e-14, None, None, mu_cut=False)
+                 for i in range(0, len(parts), 8)]
+        if len(parts) == 1:
+            return parts[0]
+
+
+def compress(Ps, tol: float, chi_e: int | None, chi_mu: int | None, bounds: list | None = None,
+             mu_cut: bool = True):
+    """Step 3: left-to-right QR sweep, the purification cut at (tol, chi_mu)
+    (skipped with mu_cut False: Psi itself is then kept, not only Psi Psi^dag),
+    right-to-left truncated SVDs at (tol, chi_e); the centre ends on mode 1.
+    Appends each cut's discarded norm (sqrt of its squared weight, taken at
+    the orthogonality centre) to bounds."""
+    Ps = [P.copy() for P in Ps]
+    M = len(Ps)
+    for a in range(M - 1):
+        e, n, f = Ps[a].shape
+        q, r = np.linalg.qr(Ps[a].reshape(e * n, f))
+        Ps[a] = q.reshape(e, n, q.shape[1])
+        nxt = Ps[a + 1]
+        Ps[a + 1] = (r @ nxt.reshape(nxt.shape[0], -1)).reshape(r.shape[0], nxt.shape[1], nxt.shape[2])
+    if mu_cut:
+        e, n, mu = Ps[-1].shape
+        u, s, _ = svd(Ps[-1].reshape(e * n, mu))
+        k = 1 if s[0] == 0.0 else keep_rank(s, tol, chi_mu)
+        # dropping V^dag is a unitary on mu: rho is unchanged by it
+        Ps[-1] = (u[:, :k] * s[None, :k]).reshape(e, n, k)
+        if bounds is not None:
+            bounds.append(float(np.sqrt(np.sum(s[k:] ** 2))))
+    for a in range(M - 1, 0, -1):
+        e, n, f = Ps[a].shape
+        u, s, vh = svd(Ps[a].reshape(e, n * f))
+        k = 1 if s[0] == 0.0 else keep_rank(s, tol, chi_e)
+        Ps[a] = vh[:k].reshape(k, n, f)
+        prv = Ps[a - 1]
+        Ps[a - 1] = (prv.reshape(-1, prv.shape[2]) @ (u[:, :k] * s[None, :k])).reshape(prv.shape[0], prv.shape[1], k)
+        if bounds is not None:
+            bounds.append(float(np.sqrt(np.sum(s[k:] ** 2))))
+    return Ps
+
+
+# ---- the step --------------------------------------------------------------------------
+
+def kraus_step(comb: Comb, fam, tol: float, chi_e: int | None = None, chi_q: int | None = None,
+               chi_mu: int | None = None) -> tuple[Comb, CombStepInfo]:
+    """One purified Kraus step on the comb (steps 1-5 of the module header)."""
+    info = CombStepInfo()
+    Ps = locals_of(comb)
+    images = [apply_op(Ps, K) for K in fam]
+    Y = inter_stack_mu(images)
+    bounds = []
+    Y = compress(Y, tol, chi_e, chi_mu, bounds)
+    tau = float(np.sum(np.abs(Y[0]) ** 2))
+    nrm = np.sqrt(tau)
+    Y[0] = Y[0] / nrm
+    info.tau = tau
+    info.chi_mu = Y[-1].shape[2]
+    info.backbone = [P.shape[2] for P in Y[:-1]]
+    info.psi_bounds = [b / nrm for b in bounds]
+    B, T = [], []
+    for a, P in enumerate(Y):
+        b, cores, disc = split_local(P, comb.bits[a], tol, chi_q)
+        # mode 1 holds the centre (its discarded norm is one of Psi); the
+        # others are right-orthonormal, so ||dPsi|| <= ||Psi|| ||dP_a||
+        info.psi_bounds += [float(np.sqrt(d)) for d in disc]
+        B.append(b)
+        T.append(cores)
+        info.teeth.append([b.shape[1]] + [c.shape[2] for c in cores[:-1]])
+    return Comb(B=B, T=T, bits=list(comb.bits)), info
+
+
+def rho(comb: Comb) -> np.ndarray:
+    X = to_matrix(comb)
+    return X @ X.conj().T

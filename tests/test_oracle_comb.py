@@ -1,0 +1,139 @@
+"""Pins of the quantics-comb oracle (paper Sec. 4.2-4.3, three modes): the
+format against dense tensors, the tooth's digit order, the sum-of-products
+operators against the dense oracle's matrices, and the purified Kraus step
+against the dense Kraus map (exact at tol 0, within the truncation bound at
+tol 1e-4)."""
+import numpy as np
+import pytest
+
+import workload as wl
+from oracle import comb, dense
+from oracle.operators import dense_operator
+
+
+def _model():
+    return wl.model_coupled_cavities(bits=(3, 3, 3), dt=0.02)
+
+
+def _random_tensor(dims, mu, seed):
+    rng = np.random.Generator(np.random.PCG64(wl.SEED + seed))
+    t = rng.standard_normal(list(dims) + [mu]) + 1j * rng.standard_normal(list(dims) + [mu])
+    return t / np.linalg.norm(t)
+
+
+def test_comb_round_trip_and_product_state():
+    m = _model()
+    psi = _random_tensor(m.dims, 3, 51)
+    C = comb.from_tensor(psi, m.bits, 0.0)
+    assert np.abs(comb.to_tensor(C) - psi).max() < 1e-13
+    # full ranks: backbone bonds 8 and 24 (from 8 x 8 x 8 x 3), teeth of 8 states
+    assert [b.shape[2] for b in C.B[:-1]] == [8, 24]
+    P = comb.product_comb(m.init, m.bits)
+    assert [b.shape for b in P.B] == [(1, 1, 1)] * 3
+    ref = np.kron(np.kron(m.init[0], m.init[1]), m.init[2])
+    assert np.abs(comb.to_matrix(P)[:, 0] - ref).max() < 1e-14
+
+
+def test_tooth_carries_the_most_significant_digit_next_to_the_backbone():
+    """A basis state |n = 6> = |110> of one mode: the first tooth core selects
+    s_1 = 1 and the last one s_3 = 0 (paper Sec. 4.3, sigma_1 at the backbone)."""
+    v = np.zeros(8, complex)
+    v[6] = 1.0
+    C = comb.product_comb([v, v, v], [3, 3, 3])
+    for a in range(3):
+        T = C.T[a]
+        assert np.abs(T[0][:, 0, :]).max() == 0.0 and np.abs(T[0][:, 1, :]).max() > 0.5
+        assert np.abs(T[1][:, 0, :]).max() == 0.0
+        assert np.abs(T[2][:, 1, :]).max() == 0.0
+    assert np.abs(comb.tooth_matrix(C.T[0])[0] * C.B[0][0, 0, 0] - v).max() < 1e-15
+
+
+def test_sum_of_products_match_the_dense_operators():
+    m = _model()
+    dm = dense.DenseModel(m)
+    H = comb.op_terms(m.H0, m.dims)
+    assert np.abs(comb.op_dense(H, m.dims) - dm.H0).max() < 1e-13
+    Ls = [comb.op_terms(j, m.dims) for j in m.jumps]
+    for L, Ld in zip(Ls, dm.L):
+        assert np.abs(comb.op_dense(L, m.dims) - Ld).max() < 1e-13
+    # the family against the dense oracle's (pinned on its own in test_oracle_dense)
+    fam = comb.kraus_ops(H, Ls, m.dt)
+    famd = dense.kraus_family(dm, 0.0, m.dt)
+    assert len(fam) == len(famd) == 1 + 2 * 3 + 9
+    for a, b in zip(fam, famd):
+        assert np.abs(comb.op_dense(a, m.dims) - b).max() < 1e-13
+    # adjoint and product of complex factors against the dense matrices
+    rng = np.random.Generator(np.random.PCG64(wl.SEED + 57))
+    F = rng.standard_normal((8, 8)) + 1j * rng.standard_normal((8, 8))
+    A = [(0.3 - 0.2j, {0: F, 2: F @ F}), (1j, {1: F.T})]
+    B = [(0.5 + 0.1j, {1: F.conj()}), (2.0, {0: F, 1: F})]
+    Ad, Bd = comb.op_dense(A, m.dims), comb.op_dense(B, m.dims)
+    assert np.abs(comb.op_dense(comb.op_dagger(A), m.dims) - Ad.conj().T).max() < 1e-12
+    assert np.abs(comb.op_dense(comb.op_mul(A, B), m.dims) - Ad @ Bd).max() < 1e-10 * np.abs(Ad @ Bd).max()
+
+
+def test_operator_application_and_the_two_additions():
+    """A Psi term by term (vector addition) against the dense product, and the
+    stacking along mu (matrix addition) against [X1 | X2]."""
+    m = _model()
+    psi = _random_tensor(m.dims, 2, 53)
+    Ps = comb.locals_of(comb.from_tensor(psi, m.bits, 0.0))
+    X = psi.reshape(-1, 2)
+    for terms in (m.H0, m.jumps[1], [(0.3 - 0.2j, {0: ("A_POW", 1), 2: ("ADAG_POW", 2)})]):
+        A = comb.op_terms(terms, m.dims)
+        Y = comb.inter_to_tensor(comb.apply_op(Ps, A)).reshape(-1, 2)
+        assert np.abs(Y - dense_operator(terms, m.dims) @ X).max() < 1e-12
+    A = comb.op_terms(m.jumps[0], m.dims)
+    B = comb.op_terms(m.jumps[2], m.dims)
+    S = comb.inter_to_tensor(comb.inter_stack_mu([comb.apply_op(Ps, A), comb.apply_op(Ps, B)])).reshape(-1, 4)
+    ref = np.concatenate([comb.op_dense(A, m.dims) @ X, comb.op_dense(B, m.dims) @ X], axis=1)
+    assert np.abs(S - ref).max() < 1e-12
+
+
+def test_comb_kraus_step_is_the_dense_kraus_map_without_truncation():
+    """tol 0: one step from the product start, then 9 more at 1e-12, against
+    rho <- sum_k K_k rho K_k^dag / tau on the dense matrices; tau agrees."""
+    m = _model()
+    dm = dense.DenseModel(m)
+    fam = comb.kraus_ops(comb.op_terms(m.H0, m.dims), [comb.op_terms(j, m.dims) for j in m.jumps], m.dt)
+    C = comb.product_comb(m.init, m.bits)
+    rho = np.outer(dm.psi0, dm.psi0.conj())
+    C, info = comb.kraus_step(C, fam, 0.0)
+    rho, tau = dense.k2_step_rho(dm, rho, 0.0, m.dt)
+    assert abs(info.tau - tau) < 1e-13
+    assert np.abs(comb.rho(C) - rho).max() < 1e-13
+    for k in range(9):
+        C, info = comb.kraus_step(C, fam, 1e-12)
+        rho, tau = dense.k2_step_rho(dm, rho, 0.0, m.dt)
+    assert np.abs(comb.rho(C) - rho).max() < 1e-11
+    assert abs(np.trace(comb.rho(C)).real - 1.0) < 1e-13
+    assert info.backbone[0] > 1 and info.chi_mu > 1      # entangled and mixed by then
+
+
+@pytest.fixture(scope="module")
+def entangled():
+    """An entangled mixed state: 12 steps at 1e-12 from the product start."""
+    m = _model()
+    fam = comb.kraus_ops(comb.op_terms(m.H0, m.dims), [comb.op_terms(j, m.dims) for j in m.jumps], m.dt)
+    C = comb.product_comb(m.init, m.bits)
+    for k in range(12):
+        C, _ = comb.kraus_step(C, fam, 1e-12)
+    return m, fam, C
+
+
+@pytest.mark.parametrize("tol", [1e-3, 1e-4])
+def test_comb_truncated_step_within_its_discarded_weight(tol, entangled):
+    """From an entangled mixed state, one step at tol: the state moves by at
+    most the sum of the cuts' discarded norms, so rho by at most twice that
+    (plus the renormalisation, which at most doubles it)."""
+    m, fam, C = entangled
+    dm = dense.DenseModel(m)
+    rho = comb.rho(C)
+    Ct, info = comb.kraus_step(C, fam, tol)
+    ref, _ = dense.k2_step_rho(dm, rho, 0.0, m.dt)
+    err = np.linalg.norm(comb.rho(Ct) - ref)
+    bound = 4.0 * sum(info.psi_bounds)
+    assert 0.0 < err <= bound + 1e-12, (err, bound)
+    assert sum(info.psi_bounds) <= 20 * tol
+    exact, _ = comb.kraus_step(C, fam, 1e-12)
+    assert comb.n_params(Ct) < comb.n_params(exact)

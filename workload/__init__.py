@@ -123,6 +123,27 @@ def model_coherent_loss(R: int = 4, delta: float = 1.0, kappa: float = 1.0,
         dt=dt, steps=steps, chi=chi, chi_mu=chi_mu)
 
 
+def model_coupled_cavities(bits=(3, 3, 3), omega=(1.0, 1.3, 0.8), g: float = 0.4, kerr: float = 0.2,
+                           kappa: float = 0.3, alpha: complex = 1.5, dt: float = 0.01, steps: int = 100,
+                           chi: int = 32, chi_mu: int = 8) -> Model:
+    """M lossy cavities in a row, each coupled to the next by a beam splitter,
+    with a Kerr term on the second one (a multi-mode test system for the
+    quantics comb of paper Sec. 4.3):
+    H = sum_a w_a n_a + g sum_a (a_a^dag a_{a+1} + h.c.) + (K/2) a_1^dag^2 a_1^2,
+    L_a = sqrt(kappa) a_a, coherent |alpha> in mode 0 and vacuum elsewhere."""
+    M = len(bits)
+    H0 = [(float(omega[a]), {a: ("NUM_POW", 1)}) for a in range(M)]
+    for a in range(M - 1):
+        H0.append((g, {a: ("ADAG_POW", 1), a + 1: ("A_POW", 1)}))
+        H0.append((g, {a: ("A_POW", 1), a + 1: ("ADAG_POW", 1)}))
+    if kerr != 0.0 and M > 1:
+        H0.append((0.5 * kerr, {1: ("ADAG_A", 2, 2)}))
+    jumps = [[(math.sqrt(kappa), {a: ("A_POW", 1)})] for a in range(M)]
+    init = [coherent_amplitudes(1 << bits[0], alpha)] + [vacuum(1 << bits[a]) for a in range(1, M)]
+    return Model(name="coupled-cavities", bits=list(bits), H0=H0, jumps=jumps, init=init,
+                 dt=dt, steps=steps, chi=chi, chi_mu=chi_mu)
+
+
 def model_two_photon_cat(R: int = 8, alpha2: float = 8.0, kappa2: float = 1.0,
                          kappa1: float = 1e-3, dt: float = 5e-5, steps: int = 5000,
                          chi: int = 64, chi_mu: int = 8) -> Model:
