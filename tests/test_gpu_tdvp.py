@@ -208,3 +208,44 @@ def test_tdvp_resume_batch_and_arena_are_bitwise():
         f.close()
     finally:
         mem.free(arena)
+
+
+def test_tdvp_two_modes_undriven_and_single_site():
+    """Two beam-splitter-coupled Kerr cavities (2^3 levels each, no loss, so a
+    pure state; H0 only, the unstacked path) from a random full-bond state
+    against the oracle, 5 steps of h = 0.02; and a chain of one site (a
+    two-level mode), where each step is two exponentials of h/2 of its 2 x 2
+    Hamiltonian, against the exact propagator."""
+    from scipy.linalg import expm
+    api = _api()
+    m = wl.model_coupled_cavities(bits=(3, 3), kappa=0.0, dt=0.02, chi_mu=1)
+    m.jumps = []
+    rng = np.random.Generator(np.random.PCG64(wl.SEED + 59))
+    v = rng.standard_normal(64) + 1j * rng.standard_normal(64)
+    v /= np.linalg.norm(v)
+    # the state on the model's own site order: a TT-SVD of the 64-vector, mode 0 first
+    sites = tdvp.right_orthonormal(_two_mode_mps(v, m))
+    print(f"case tdvp two modes 2^3 x 2^3, bonds {mps.bond_dims(sites)}", flush=True)
+    ref = _vec(_oracle(m, sites, 5), m)
+    pg, b0, d = _gpu(m, sites, [5])
+    err = np.linalg.norm(pg - ref)
+    print(f"  state error {err:.2e}", flush=True)
+    assert err < 1e-10
+    m1 = wl.model_driven_kerr(R=1, kerr=0.0, alpha0=0.5, dt=0.1)
+    psi0 = np.array([0.6, 0.8j])
+    X1 = [psi0.reshape(1, 2, 1)]
+    pg1, _, _ = _gpu(m1, X1, [7])
+    H = dense.DenseModel(m1).H0
+    exact = expm(-1j * 0.7 * H) @ psi0
+    print(f"  single site error {np.linalg.norm(pg1 - exact):.2e}", flush=True)
+    assert np.linalg.norm(pg1 - exact) < 1e-12
+
+
+def _two_mode_mps(v, m):
+    """MPS of the 64-vector v (mode 0 the most significant index) in the
+    model's site order, by the oracle's TT-SVD at tol 0."""
+    so = m.site_order()
+    t = v.reshape([2] * 6)             # bits of mode 0 (MSB first), then of mode 1
+    perm = [b if md == 0 else 3 + b for (md, b) in so]
+    cores = tt.tt_svd(t.transpose(perm).reshape(-1), 2, 6, 0.0)
+    return cores
