@@ -376,18 +376,17 @@ def chi256_leg(steps: int, precision: str) -> dict:
             "bonds": d["bonds"], "cap_bonds": cap, "bonds_at_cap": d["bonds"] == cap, "chi_mu": d["chi_mu"]}
 
 
-def kerr_rk4_main(args) -> None:
+def kerr_rk4_leg(n_run: int, dt: float, warmup: int) -> dict:
     """Pure-state global RK4 (paper Sec. 3.1.1) on the driven Kerr oscillator
     at the paper's parameters (Sec. 3.2: R = 8, w0 = 1, K = 1/25, alpha0 = 4,
     the two-frequency drive, tol 1e-8): steps/s of both forms and their
-    distance to the dense scheme."""
+    distance to the dense scheme (computed after the timed region)."""
     import numpy as np
     import torch
     import workload as wl
     from oracle import dense, mps
     from paper_2605_27515_amd import api
-    m = wl.model_driven_kerr(R=8, dt=args.kerr_dt)
-    n_run = args.kerr_steps
+    m = wl.model_driven_kerr(R=8, dt=dt)
     dm = dense.DenseModel(m)
     ref = dense.rk4_pure_evolve(dm, dm.psi0, m.dt, n_run)
     rr = np.outer(ref, ref.conj())
@@ -396,8 +395,8 @@ def kerr_rk4_main(args) -> None:
     out = {}
     for prec in ("fp32", "fp64"):
         s = api.solver_from_model(m, precision=prec, order=4, chi=64, chi_mu=1, device=0)
-        if args.warmup:
-            s.step(args.warmup)
+        if warmup:
+            s.step(warmup)
             s.close()
             s = api.solver_from_model(m, precision=prec, order=4, chi=64, chi_mu=1, device=0)
         torch.cuda.synchronize()
@@ -415,33 +414,44 @@ def kerr_rk4_main(args) -> None:
                      "a_abs_error_vs_dense": float(abs(a - a_ref)), "bonds": bonds}
         print(f"bench: kerr RK4 {prec}: {n_run / elapsed:.1f} steps/s, rho error {err:.2e}, bonds {bonds}",
               file=sys.stderr, flush=True)
+    out["steps"] = n_run
+    out["dt"] = dt
+    out["a_dense"] = [a_ref.real, a_ref.imag]
+    return out
+
+
+def kerr_rk4_main(args) -> None:
+    out = kerr_rk4_leg(args.kerr_steps, args.kerr_dt, args.warmup)
+    n_run = args.kerr_steps
+    forms = {k: out[k] for k in ("fp32", "fp64")}
     line = {"metric": "pure-state global RK4 steps/s, driven Kerr oscillator", "value": out[args.precision]["steps_per_s"],
             "unit": "steps/s", "n_gpus": 1, "steps": n_run, "warmup": args.warmup,
             "ms_per_step": 1e3 / out[args.precision]["steps_per_s"], "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32+f64" if args.precision == "fp32" else "f64", "data": "synthetic",
             "config": {"workload": f"driven Kerr oscillator, 2^8 Fock levels (8 sites), K=1/25, alpha0=4, "
-                                   f"two-frequency drive, dt={m.dt}, tol=1e-8, chi=64", "precision": args.precision},
-            "forms": out, "a_dense": [a_ref.real, a_ref.imag]}
+                                   f"two-frequency drive, dt={args.kerr_dt}, tol=1e-8, chi=64", "precision": args.precision},
+            "forms": forms, "a_dense": out["a_dense"]}
     print(json.dumps(line), flush=True)
 
 
-def kerr_tdvp_main(args) -> None:
+def kerr_tdvp_leg(n_run: int, dt: float, warmup: int, cpu_seconds: float | None) -> dict:
     """One-site TDVP with the fourth-order Magnus Hamiltonian (order 5, paper
     Sec. 3.1.3) on the driven Kerr oscillator at the paper's parameters (Sec.
     3.2: R = 8, w0 = 1, K = 1/25, alpha0 = 4, the two-frequency drive), FP64,
     from the coherent state as the library compresses it: steps/s, the bonds
     the state keeps, and its distance to the dense Magnus-4 steps (the exact
-    propagator up to O(h^5) per step; the rest is TDVP's projection)."""
+    propagator up to O(h^5) per step; the rest is TDVP's projection),
+    computed after the timed region; with cpu_seconds, the oracle's TDVP
+    timed on a few steps."""
     import numpy as np
     import torch
     import workload as wl
     from oracle import dense, mps, tdvp, tt
     from paper_2605_27515_amd import api
-    m = wl.model_driven_kerr(R=8, dt=args.kerr_dt)
-    n_run = args.kerr_steps
+    m = wl.model_driven_kerr(R=8, dt=dt)
     s = api.solver_from_model(m, order=5, chi=64, chi_mu=1, device=0)
-    if args.warmup:
-        s.step(args.warmup)
+    if warmup:
+        s.step(warmup)
         s.close()
         s = api.solver_from_model(m, order=5, chi=64, chi_mu=1, device=0)
     bonds0 = s.diagnostics()["bonds"]
@@ -463,26 +473,34 @@ def kerr_tdvp_main(args) -> None:
     print(f"bench: kerr TDVP fp64: {n_run / elapsed:.1f} steps/s, state error {err:.2e}, "
           f"|<a> - dense| {abs(a - a_ref):.2e}", file=sys.stderr, flush=True)
     cpu = None
-    if not args.no_cpu:
+    if cpu_seconds:
         # the oracle's TDVP from its own compression of the same start, a few steps
         so = m.site_order()
         X0 = tdvp.right_orthonormal(mps.product_state(m.init, m.bits, so, tol=1e-14))
         H0m, H1m = tt.operator_mpo(m.H0, m.bits, so), tt.operator_mpo(m.H1, m.bits, so)
         n_cpu, t_cpu = 0, 0.0
-        while t_cpu < args.cpu_seconds and n_cpu < n_run:
+        while t_cpu < cpu_seconds and n_cpu < n_run:
             c0 = time.perf_counter()
             X0 = tdvp.magnus4_tdvp_evolve(X0, H0m, H1m, dm.f, m.dt, 1, t0=n_cpu * m.dt)
             t_cpu += time.perf_counter() - c0
             n_cpu += 1
         cpu = {"value": n_cpu / t_cpu, "unit": "steps/s", "cores": torch.get_num_threads(), "kind": "oracle",
                "sample": f"the first {n_cpu} steps of the same run (oracle.tdvp, dense local exponentials)"}
-    line = {"metric": "Magnus-4 one-site TDVP steps/s, driven Kerr oscillator", "value": n_run / elapsed,
-            "unit": "steps/s", "n_gpus": 1, "steps": n_run, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / n_run,
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": f"driven Kerr oscillator, 2^8 Fock levels (8 sites), K=1/25, alpha0=4, "
-                                   f"two-frequency drive, dt={m.dt}, coherent start compressed at 1e-14, chi=64"},
+    return {"steps_per_s": n_run / elapsed, "ms_per_step": 1e3 * elapsed / n_run, "steps": n_run, "dt": dt,
             "bonds": bonds0, "state_error_vs_dense_magnus4": err,
             "a_abs_error_vs_dense_magnus4": float(abs(a - a_ref)), "cpu_baseline": cpu}
+
+
+def kerr_tdvp_main(args) -> None:
+    out = kerr_tdvp_leg(args.kerr_steps, args.kerr_dt, args.warmup, None if args.no_cpu else args.cpu_seconds)
+    line = {"metric": "Magnus-4 one-site TDVP steps/s, driven Kerr oscillator", "value": out["steps_per_s"],
+            "unit": "steps/s", "n_gpus": 1, "steps": out["steps"], "warmup": args.warmup,
+            "ms_per_step": out["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"driven Kerr oscillator, 2^8 Fock levels (8 sites), K=1/25, alpha0=4, "
+                                   f"two-frequency drive, dt={out['dt']}, coherent start compressed at 1e-14, chi=64"},
+            "bonds": out["bonds"], "state_error_vs_dense_magnus4": out["state_error_vs_dense_magnus4"],
+            "a_abs_error_vs_dense_magnus4": out["a_abs_error_vs_dense_magnus4"], "cpu_baseline": out["cpu_baseline"]}
     print(json.dumps(line), flush=True)
 
 
@@ -631,6 +649,9 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
     ap.add_argument("--kerr-steps", type=int, default=1000, help="steps of the kerr-rk4 and kerr-tdvp workloads")
+    ap.add_argument("--pure-steps", type=int, default=200,
+                    help="steps of the pure-state legs (RK4 and Magnus-4 TDVP on the Kerr oscillator) of the "
+                         "default run (0: skip)")
     ap.add_argument("--kerr-dt", type=float, default=1e-3, help="time step of the kerr-rk4 and kerr-tdvp workloads")
     ap.add_argument("--workload", choices=["chi128", "cat-zgate", "chi128-trajectory", "kerr-rk4", "kerr-tdvp"],
                     default="chi128",
@@ -706,6 +727,18 @@ def main():
         print(f"bench: serving {serve['burst_solves_per_s']:.2f} solves/s (burst), p50 {serve['p50_s']:.3f} s "
               f"p99 {serve['p99_s']:.3f} s; one-at-a-time FP64 "
               f"{serve['baseline_fp64_one_at_a_time']['solves_per_s']:.2f} solves/s", file=sys.stderr, flush=True)
+    pure = None
+    if args.pure_steps > 0:
+        # the pure-state integrators on the paper's Kerr oscillator; a failure
+        # here is reported in the line and does not cost the headline
+        pure = {}
+        for name, fn in (("kerr_rk4", lambda: kerr_rk4_leg(args.pure_steps, args.kerr_dt, 5)),
+                         ("kerr_tdvp", lambda: kerr_tdvp_leg(args.pure_steps, args.kerr_dt, 5, None))):
+            try:
+                pure[name] = fn()
+            except Exception as e:   # noqa: BLE001 - recorded, not hidden
+                pure[name] = {"error": f"{type(e).__name__}: {e}"}
+                print(f"bench: {name} leg failed: {e}", file=sys.stderr, flush=True)
     cpu = cpu1 = None
     if not args.no_cpu:
         cpu = cpu_baseline(args.cpu_seconds)
@@ -745,6 +778,7 @@ def main():
         "kernel_share": {k: v["ms"] / total_ms for k, v in prof.items() if v["launches"]} if total_ms else {},
         "final_bonds": diag["bonds"],
         "serving": serve,
+        "pure_state": pure,
     }
     print(json.dumps(line), flush=True)
 
