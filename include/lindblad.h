@@ -267,6 +267,9 @@ lb_status lindblad_kraus_info(const lb_solver* s, int32_t* bonds, int32_t* n_kra
 
 /* Site tensor of the stacked Kraus MPO, layout as lindblad_op_site.  With a
  * drive, site 0's left bond is the polynomial index p (coefficient of f^p).
+ * With cfg.order == 5 (TDVP) this call and lindblad_kraus_info describe the
+ * MPO the step combines instead: H0, or with a drive H0, H1 and [H0, H1] as
+ * the channels 0, 1, 2 of site 0's left index (one "Kraus" index).
  * Host only.  Errors: LB_ERR_STATE before set_generator, LB_ERR_ARG. */
 lb_status lindblad_kraus_site(const lb_solver* s, int32_t site, int32_t* l, int32_t* r, double* w);
 

@@ -2300,9 +2300,10 @@ lb_status lindblad_set_generator(lb_solver* s, const lb_op* H0, const lb_op* H1,
 
 lb_status lindblad_kraus_info(const lb_solver* s, int32_t* bonds, int32_t* n_kraus) {
   if (!s || !s->have_gen) { g_last_error = "no generator"; return LB_ERR_STATE; }
+  const lb::Mpo& m = s->cfg.order == 5 ? s->tdvp_W : s->kraus;
   if (bonds)
-    for (int k = 0; k + 1 < s->L; ++k) bonds[k] = s->kraus[k].r;
-  if (n_kraus) *n_kraus = s->n_kraus;
+    for (int k = 0; k + 1 < s->L; ++k) bonds[k] = m[k].r;
+  if (n_kraus) *n_kraus = s->cfg.order == 5 ? 1 : s->n_kraus;
   return LB_OK;
 }
 
@@ -2795,7 +2796,7 @@ lb_status lindblad_op_site(const lb_op* op, int32_t site, int32_t* l, int32_t* r
 
 lb_status lindblad_kraus_site(const lb_solver* s, int32_t site, int32_t* l, int32_t* r, double* w) {
   if (!s || !s->have_gen) { g_last_error = "no generator"; return LB_ERR_STATE; }
-  return export_site(s->kraus, site, l, r, w);
+  return export_site(s->cfg.order == 5 ? s->tdvp_W : s->kraus, site, l, r, w);
 }
 
 lb_status lindblad_gemm_tune_save(const char* path) {

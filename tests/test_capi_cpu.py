@@ -286,6 +286,30 @@ def test_tdvp_order_refuses_fp32_jumps_and_counts_its_work():
     s4.close()
 
 
+@pytest.mark.parametrize("drive", [False, True])
+def test_host_tdvp_mpo_channels_are_h0_h1_and_their_commutator(drive):
+    """order = 5: the MPO the TDVP step combines, exported, is H0 (no drive) or
+    H0, H1 and [H0, H1] on the channels of site 0's left index, each equal to
+    the dense operator (paper Sec. 3.1.3: the commutator formed once)."""
+    _lib_or_skip()
+    from paper_2605_27515_amd import api
+    m = wl.model_driven_kerr(R=4, alpha0=1.5, drive=drive, dt=1e-2)
+    s = api.solver_from_model(m, order=5, chi=16, chi_mu=1, state="none")
+    W = s.kraus_sites()
+    so = m.site_order()
+    dm = dense.DenseModel(m)
+    bonds, nk = s.kraus_info()
+    assert nk == 1
+    want = [dm.H0] if not drive else [dm.H0, dm.H1, dm.H0 @ dm.H1 - dm.H1 @ dm.H0]
+    assert W[0].shape[0] == len(want)
+    for p, ref in enumerate(want):
+        e = np.zeros(len(want))
+        e[p] = 1.0
+        got = tt.mpo_to_dense(tt.contract_boundary(W, list(e)), m.bits, so)
+        assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max()), p
+    s.close()
+
+
 def test_gemm_tune_table_round_trip(tmp_path):
     """The split-count table (lb_config.autotune) saved and loaded as JSON
     lines: entries merge, a saved file reloads to the same entries, and a
