@@ -137,3 +137,26 @@ def test_comb_truncated_step_within_its_discarded_weight(tol, entangled):
     assert sum(info.psi_bounds) <= 20 * tol
     exact, _ = comb.kraus_step(C, fam, 1e-12)
     assert comb.n_params(Ct) < comb.n_params(exact)
+
+
+def test_two_mode_comb_step_equals_the_chain_step():
+    """M = 2, where the chain of this package and the comb hold the same state
+    (the chain orders each mode's digits so that its most significant digit
+    faces the other mode, the comb hangs each tooth MSB-first from its
+    backbone tensor): five steps of both oracles without active truncation
+    give the same rho."""
+    from oracle import mps, tt
+    m = wl.model_coupled_cavities(bits=(3, 3), dt=0.02, chi=64, chi_mu=64)
+    so = m.site_order()
+    K = tt.KrausMPO(m, m.dt)
+    X = mps.product_state(m.init, m.bits, so)
+    X, _ = mps.right_canonicalize(X)
+    fam = comb.kraus_ops(comb.op_terms(m.H0, m.dims), [comb.op_terms(j, m.dims) for j in m.jumps], m.dt)
+    C = comb.product_comb(m.init, m.bits)
+    for s in range(5):
+        X, info = mps.k2_step(X, K.at(s * m.dt), 1e-12, 64, 64)
+        C, cinfo = comb.kraus_step(C, fam, 1e-12)
+        assert abs(info.tau - cinfo.tau) < 1e-12
+    Xd = mps.to_dense(X, m.bits, so)
+    rc = comb.rho(C)
+    assert np.abs(Xd @ Xd.conj().T - rc).max() < 1e-11
