@@ -155,6 +155,13 @@ def test_step_transmon_eigenbasis(precision, rtol, tol):
     _compare(wl.model_transmon_eigen(Rt=4, Rr=3, n_cut=40, dt=2e-4), 20, 16, 8, precision, rtol, tol)
 
 
+@pytest.mark.parametrize("precision,rtol,tol", [("fp64", 1e-10, 1e-12), ("fp32", 1e-5, 1e-8)])
+def test_step_transmon_eigenbasis_paper_size(precision, rtol, tol):
+    """The eigenbasis model at the paper's size (paper Sec. 7.2: 2^5 transmon
+    eigenstates, resonator 2^10, 15 sites), 40 steps of dt = 2e-5."""
+    _compare(wl.model_transmon_eigen(Rt=5, Rr=10, dt=2e-5), 40, 64, 8, precision, rtol, tol)
+
+
 def test_step_caps_bind_ragged():
     """Caps below the exact ranks (truncation by cap at every bond), odd sizes."""
     _compare(wl.model_cat_buffer(Ra=4, Rb=3, alpha2=3.0, dt=1e-3), 15, 6, 3, "fp64", 1e-10, 1e-12)
