@@ -38,6 +38,12 @@ Truncation rule everywhere: the smallest rank whose discarded squared
 singular values sum to at most tol^2 of the total (tt.keep_rank).  The local
 tensors are dense in n (N = 2^R states per mode), which is what makes this a
 reference for small modes only.
+
+`kraus_step_tree` takes the same step on the tree itself (single-mode factors
+as quantics MPOs on the teeth, tree additions, a compression that sweeps the
+backbone and then each tooth with the orthogonality centre at the node it
+cuts), the form a device implementation would take; at tolerances below
+the rounding of either, the two steps give the same rho.
 """
 from __future__ import annotations
 
@@ -392,3 +398,199 @@ def kraus_step(comb: Comb, fam, tol: float, chi_e: int | None = None, chi_q: int
 def rho(comb: Comb) -> np.ndarray:
     X = to_matrix(comb)
     return X @ X.conj().T
+
+
+# ---- the comb as a tree: operators on the teeth, tree addition and compression ------
+#
+# The step above works on dense local tensors P_a (N entries per mode).  Below
+# is the same step on the tree itself, as a device implementation would run
+# it: single-mode factors act on the teeth as quantics MPOs, sums are tree
+# additions (block diagonal in every bond), and the compression sweeps the
+# backbone and then each tooth with the orthogonality centre at the node it
+# cuts.  Nothing is formed with N entries except the factors' own MPOs.
+
+def factor_mpo(F: np.ndarray, tol: float = 1e-14) -> list[np.ndarray]:
+    """Quantics MPO of an N x N single-mode factor, most significant digit
+    first (the tooth's order): cores W[w, s_out, s_in, w']."""
+    from .tt import matrix_to_mpo
+    return matrix_to_mpo(np.asarray(F, complex), tol)
+
+
+def qtt_terms(A, bits, tol: float = 1e-14) -> list:
+    """A sum of products with every dense factor replaced by its quantics MPO."""
+    return [(c, {m: factor_mpo(F, tol) for m, F in f.items()}) for (c, f) in A]
+
+
+def tooth_apply(cores, W) -> list[np.ndarray]:
+    """F applied to a tooth through its MPO: T'_j[(q w), s, (q' w')] =
+    sum_s' T_j[q, s', q'] W_j[w, s, s', w'].  W's outer bonds are 1, so the
+    tooth keeps its bond q to the backbone and its unit bond at the tip."""
+    out = []
+    for T, Wj in zip(cores, W):
+        q, _, r = T.shape
+        u, _, _, v = Wj.shape
+        out.append(np.einsum('aib,usiv->ausbv', T, Wj).reshape(q * u, 2, r * v))
+    return out
+
+
+def apply_term_tree(C: Comb, coef, factors) -> Comb:
+    T = [tooth_apply(C.T[a], factors[a]) if a in factors else [c.copy() for c in C.T[a]] for a in range(len(C.B))]
+    B = [b.copy() for b in C.B]
+    B[0] = coef * B[0]
+    return Comb(B=B, T=T, bits=list(C.bits))
+
+
+def _block_diag3(blocks, shared_left: bool, shared_right: bool) -> np.ndarray:
+    """Direct sum of three-index tensors (l, s, r): block diagonal in l and r,
+    except that a shared bond (size equal in every block) is not enlarged."""
+    l = blocks[0].shape[0] if shared_left else sum(b.shape[0] for b in blocks)
+    r = blocks[0].shape[2] if shared_right else sum(b.shape[2] for b in blocks)
+    out = np.zeros((l, blocks[0].shape[1], r), complex)
+    i = j = 0
+    for b in blocks:
+        li, ri = b.shape[0], b.shape[2]
+        out[(0 if shared_left else i):(li if shared_left else i + li), :,
+            (0 if shared_right else j):(ri if shared_right else j + ri)] += b
+        i += li
+        j += ri
+    return out
+
+
+def tree_add(combs, stack_mu: bool = False) -> Comb:
+    """Tree addition (Sec. 5.1: the standard rule for tree networks, every
+    tensor block diagonal): vector addition sums the states (mu shared);
+    with stack_mu the images are set side by side along mu (matrix
+    addition)."""
+    M = len(combs[0].B)
+    B, T = [], []
+    for a in range(M):
+        first, last = a == 0, a == M - 1
+        blocks = [c.B[a] for c in combs]
+        e = blocks[0].shape[0] if first else sum(b.shape[0] for b in blocks)
+        q = sum(b.shape[1] for b in blocks)
+        share_r = last and not stack_mu
+        f = blocks[0].shape[2] if share_r else sum(b.shape[2] for b in blocks)
+        out = np.zeros((e, q, f), complex)
+        i = k = j = 0
+        for b in blocks:
+            ei, qi, fi = b.shape
+            rs = slice(0, ei) if first else slice(i, i + ei)
+            cs = slice(0, fi) if share_r else slice(j, j + fi)
+            out[rs, k:k + qi, cs] += b
+            i += ei
+            k += qi
+            j += fi
+        B.append(out)
+        R = len(combs[0].T[a])
+        teeth = []
+        for jj in range(R):
+            cores = [c.T[a][jj] for c in combs]
+            teeth.append(_block_diag3(cores, shared_left=False, shared_right=(jj == R - 1)))
+        T.append(teeth)
+    return Comb(B=B, T=T, bits=list(combs[0].bits))
+
+
+def _lq(m: np.ndarray):
+    """m = L Q with Q having orthonormal rows."""
+    q, r = np.linalg.qr(m.conj().T)
+    return r.conj().T, q.conj().T
+
+
+def tree_compress(C: Comb, tol: float, chi_e: int | None, chi_q: int | None, chi_mu: int | None,
+                  mu_cut: bool = True, normalise: bool = False):
+    """Compression of a comb on the tree.  (1) Each tooth is made an isometry
+    from its backbone bond by LQ sweeps from the tip, the factors absorbed
+    into the backbone tensor's q index.  (2) The backbone, an MPS whose
+    physical index is q, gets the step-3 compression of the dense-mode step
+    (QR sweep, purification cut, right-to-left truncated SVDs at (tol,
+    chi_e)), which leaves the centre on mode 1; with normalise, the state is
+    divided by its norm there.  (3) Each mode in turn, with the centre moved
+    to its backbone tensor: the q bond is cut by an SVD at (tol, chi_q) and
+    the tooth's bonds by truncated SVDs down to the tip, then the centre goes
+    back up the tooth and on to the next mode.  Returns (comb, norm^2 before
+    normalisation, discarded norms of every cut, each taken at the centre)."""
+    M = len(C.B)
+    B = [b.copy() for b in C.B]
+    T = [[c.copy() for c in t] for t in C.T]
+    bounds = []
+    # (1) teeth isometric towards the backbone
+    for a in range(M):
+        t = T[a]
+        for j in range(len(t) - 1, -1, -1):
+            q, _, r = t[j].shape
+            L, Q = _lq(t[j].reshape(q, 2 * r))
+            t[j] = Q.reshape(Q.shape[0], 2, r)
+            if j > 0:
+                p = t[j - 1]
+                t[j - 1] = (p.reshape(-1, q) @ L).reshape(p.shape[0], 2, L.shape[1])
+            else:
+                e, _, f = B[a].shape
+                B[a] = np.einsum('eqf,qk->ekf', B[a], L)
+    # (2) the backbone
+    B = compress(B, tol, chi_e, chi_mu, bounds, mu_cut=mu_cut)
+    tau = float(np.sum(np.abs(B[0]) ** 2))
+    if normalise and tau > 0.0:
+        B[0] = B[0] / np.sqrt(tau)
+        bounds = [x / np.sqrt(tau) for x in bounds]
+    # (3) teeth, the centre at each mode's backbone tensor in turn
+    for a in range(M):
+        e, q, f = B[a].shape
+        u, s, vh = svd(B[a].transpose(0, 2, 1).reshape(e * f, q))
+        k = 1 if s[0] == 0.0 else keep_rank(s, tol, chi_q)
+        bounds.append(float(np.sqrt(np.sum(s[k:] ** 2))))
+        B[a] = u[:, :k].reshape(e, f, k).transpose(0, 2, 1)
+        t = T[a]
+        c0 = t[0]
+        t[0] = ((s[:k, None] * vh[:k]) @ c0.reshape(q, -1)).reshape(k, 2, c0.shape[2])
+        for j in range(len(t) - 1):
+            l, _, r = t[j].shape
+            u, s, vh = svd(t[j].reshape(l * 2, r))
+            k = 1 if s[0] == 0.0 else keep_rank(s, tol, chi_q)
+            bounds.append(float(np.sqrt(np.sum(s[k:] ** 2))))
+            t[j] = u[:, :k].reshape(l, 2, k)
+            n = t[j + 1]
+            t[j + 1] = ((s[:k, None] * vh[:k]) @ n.reshape(r, -1)).reshape(k, 2, n.shape[2])
+        # the centre back up the tooth and into the backbone tensor
+        for j in range(len(t) - 1, -1, -1):
+            l, _, r = t[j].shape
+            L, Q = _lq(t[j].reshape(l, 2 * r))
+            t[j] = Q.reshape(Q.shape[0], 2, r)
+            if j > 0:
+                p = t[j - 1]
+                t[j - 1] = (p.reshape(-1, l) @ L).reshape(p.shape[0], 2, L.shape[1])
+            else:
+                B[a] = np.einsum('eqf,qk->ekf', B[a], L)
+        if a + 1 < M:
+            e, q, f = B[a].shape
+            Qm, Rm = np.linalg.qr(B[a].reshape(e * q, f))
+            B[a] = Qm.reshape(e, q, Qm.shape[1])
+            nb = B[a + 1]
+            B[a + 1] = (Rm @ nb.reshape(nb.shape[0], -1)).reshape(Rm.shape[0], nb.shape[1], nb.shape[2])
+    return Comb(B=B, T=T, bits=list(C.bits)), tau, bounds
+
+
+def apply_op_tree(C: Comb, A) -> Comb:
+    """A Psi on the tree (A with quantics-MPO factors): the terms' images added
+    eight at a time, each partial sum compressed at 1e-14 without the
+    purification cut (Psi itself is kept)."""
+    parts = [apply_term_tree(C, c, f) for (c, f) in A]
+    while True:
+        parts = [tree_compress(tree_add(parts[i:i + 8]), 1e-14, None, None, None, mu_cut=False)[0]
+                 for i in range(0, len(parts), 8)]
+        if len(parts) == 1:
+            return parts[0]
+
+
+def kraus_step_tree(C: Comb, fam_qtt, tol: float, chi_e: int | None = None, chi_q: int | None = None,
+                    chi_mu: int | None = None) -> tuple[Comb, CombStepInfo]:
+    """The purified Kraus step on the tree: the images K_k Psi (quantics-MPO
+    factors on the teeth), stacked along mu, compressed on the tree at
+    (tol, chi_e, chi_q, chi_mu) with the trace taken and divided out after
+    the backbone sweep (Sec. 5.2.2)."""
+    images = [apply_op_tree(C, K) for K in fam_qtt]
+    Y = tree_add(images, stack_mu=True)
+    out, tau, bounds = tree_compress(Y, tol, chi_e, chi_q, chi_mu, mu_cut=True, normalise=True)
+    info = CombStepInfo(tau=tau, chi_mu=out.B[-1].shape[2], backbone=[b.shape[2] for b in out.B[:-1]],
+                        teeth=[[b.shape[1]] + [c.shape[2] for c in t[:-1]] for b, t in zip(out.B, out.T)],
+                        psi_bounds=bounds)
+    return out, info

@@ -160,3 +160,63 @@ def test_two_mode_comb_step_equals_the_chain_step():
     Xd = mps.to_dense(X, m.bits, so)
     rc = comb.rho(C)
     assert np.abs(Xd @ Xd.conj().T - rc).max() < 1e-11
+
+
+# ---- the same step on the tree (quantics-MPO factors on the teeth) ------------------
+
+def test_tree_operator_application_and_additions():
+    """Factors applied to the teeth as quantics MPOs, the terms summed by tree
+    addition, against the dense products; the tree's matrix addition against
+    [X1 | X2]; the tree compression at tol 0 keeps Psi, and with the
+    purification cut keeps rho."""
+    m = _model()
+    psi = _random_tensor(m.dims, 2, 61)
+    C = comb.from_tensor(psi, m.bits, 0.0)
+    X = psi.reshape(-1, 2)
+    for terms in (m.H0, m.jumps[1], [(0.3 - 0.2j, {0: ("A_POW", 1), 2: ("ADAG_POW", 2)})]):
+        A = comb.op_terms(terms, m.dims)
+        Y = comb.to_matrix(comb.apply_op_tree(C, comb.qtt_terms(A, m.bits)))
+        assert np.abs(Y - dense_operator(terms, m.dims) @ X).max() < 1e-12
+    A = comb.qtt_terms(comb.op_terms(m.jumps[0], m.dims), m.bits)
+    B = comb.qtt_terms(comb.op_terms(m.jumps[2], m.dims), m.bits)
+    S = comb.to_matrix(comb.tree_add([comb.apply_op_tree(C, A), comb.apply_op_tree(C, B)], stack_mu=True))
+    ref = np.concatenate([dense_operator(m.jumps[0], m.dims) @ X, dense_operator(m.jumps[2], m.dims) @ X], axis=1)
+    assert np.abs(S - ref).max() < 1e-12
+    V = comb.to_matrix(comb.tree_add([C, comb.apply_op_tree(C, A)]))
+    assert np.abs(V - (X + dense_operator(m.jumps[0], m.dims) @ X)).max() < 1e-12
+    C2, tau, bounds = comb.tree_compress(C, 0.0, None, None, None, mu_cut=False)
+    assert np.abs(comb.to_matrix(C2) - X).max() < 1e-13 and abs(tau - 1.0) < 1e-13
+    C3, _, _ = comb.tree_compress(C, 0.0, None, None, None)
+    assert np.abs(comb.rho(C3) - X @ X.conj().T).max() < 1e-13
+    assert max(bounds) < 1e-13
+
+
+def test_tree_step_equals_dense_kraus_map_and_the_dense_mode_step():
+    """Four tree steps at 1e-12 from the product start: tau and rho of the
+    dense Kraus map, and the dense-mode step's rho."""
+    m = _model()
+    dm = dense.DenseModel(m)
+    fam = comb.kraus_ops(comb.op_terms(m.H0, m.dims), [comb.op_terms(j, m.dims) for j in m.jumps], m.dt)
+    famq = [comb.qtt_terms(K, m.bits) for K in fam]
+    Ct = Cd = comb.product_comb(m.init, m.bits)
+    rho = np.outer(dm.psi0, dm.psi0.conj())
+    for k in range(4):
+        Ct, info = comb.kraus_step_tree(Ct, famq, 1e-12)
+        Cd, _ = comb.kraus_step(Cd, fam, 1e-12)
+        rho, tau = dense.k2_step_rho(dm, rho, 0.0, m.dt)
+        assert abs(info.tau - tau) < 1e-13
+    assert np.abs(comb.rho(Ct) - rho).max() < 1e-11
+    assert np.abs(comb.rho(Ct) - comb.rho(Cd)).max() < 1e-11
+    assert info.chi_mu > 1 and info.backbone[1] > 1
+
+
+@pytest.mark.parametrize("tol", [1e-3, 1e-4])
+def test_tree_truncated_step_within_its_discarded_weight(tol, entangled):
+    m, fam, C = entangled
+    famq = [comb.qtt_terms(K, m.bits) for K in fam]
+    Ct, info = comb.kraus_step_tree(C, famq, tol)
+    ref, _ = dense.k2_step_rho(dense.DenseModel(m), comb.rho(C), 0.0, m.dt)
+    err = np.linalg.norm(comb.rho(Ct) - ref)
+    bound = 4.0 * sum(info.psi_bounds)
+    assert 0.0 < err <= bound + 1e-12, (err, bound)
+    assert sum(info.psi_bounds) <= 30 * tol
