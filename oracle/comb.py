@@ -594,3 +594,41 @@ def kraus_step_tree(C: Comb, fam_qtt, tol: float, chi_e: int | None = None, chi_
                         teeth=[[b.shape[1]] + [c.shape[2] for c in t[:-1]] for b, t in zip(out.B, out.T)],
                         psi_bounds=bounds)
     return out, info
+
+
+# ---- observables on the tree (step S5) -----------------------------------------------
+
+def _tooth_transfer(cores, W=None) -> np.ndarray:
+    """G[q, q'] = sum conj(Q(n))_q F[n, n'] Q(n')_q' for a tooth, contracted
+    from the tip to the backbone with F as a quantics MPO (identity if None)."""
+    E = np.ones((1, 1, 1), complex)                              # E[y*, v, b]
+    for j in range(len(cores) - 1, -1, -1):
+        T = cores[j]
+        Wj = W[j] if W is not None else np.eye(2, dtype=complex).reshape(1, 2, 2, 1)
+        F = np.tensordot(T, E, axes=([2], [2]))                  # [a, s, y*, v]
+        F = np.tensordot(Wj, F, axes=([2, 3], [1, 3]))           # [u, s', a, y*]
+        E = np.tensordot(T.conj(), F, axes=([1, 2], [1, 3]))     # [x*, u, a]
+    return E[:, 0, :]
+
+
+def gram_tree(C: Comb, factors=None) -> np.ndarray:
+    """(X^dag F X)[mu, nu] over the physical indices, F a product of
+    single-mode quantics MPOs ({mode: cores}; identity where absent), by
+    transfer matrices along the backbone with each tooth's transfer."""
+    L = np.ones((1, 1), complex)                                 # L[e*, e]
+    for a, B in enumerate(C.B):
+        G = _tooth_transfer(C.T[a], None if factors is None else factors.get(a))
+        X = np.tensordot(L, B, axes=([1], [0]))                  # [e*, q, f]
+        X = np.tensordot(G, X, axes=([1], [1]))                  # [q*, e*, f]
+        L = np.tensordot(B.conj(), X, axes=([0, 1], [1, 0]))     # [f*, f]
+    return L
+
+
+def expect_tree(C: Comb, A_qtt) -> complex:
+    """Tr(A rho) = sum over A's terms of c Tr(X^dag F X) (Sec. 4.1, purified)."""
+    return complex(sum(c * np.trace(gram_tree(C, f)) for (c, f) in A_qtt))
+
+
+def purity_tree(C: Comb) -> float:
+    g = gram_tree(C)
+    return float(np.sum(np.abs(g) ** 2) / np.trace(g).real ** 2)

@@ -220,3 +220,23 @@ def test_tree_truncated_step_within_its_discarded_weight(tol, entangled):
     bound = 4.0 * sum(info.psi_bounds)
     assert 0.0 < err <= bound + 1e-12, (err, bound)
     assert sum(info.psi_bounds) <= 30 * tol
+
+
+def test_tree_observables_against_dense_traces():
+    """Tr(O rho) by transfer matrices on the tree for non-Hermitian, complex,
+    single- and two-mode operators, and the purity, against the dense traces
+    on a random mixed state (purification rank 3)."""
+    m = _model()
+    psi = _random_tensor(m.dims, 3, 63)
+    C = comb.from_tensor(psi, m.bits, 0.0)
+    X = psi.reshape(-1, 3)
+    rho = X @ X.conj().T
+    ops = [[(1.0, {0: ("A_POW", 1)})], [(0.5 + 0.25j, {0: ("ADAG_POW", 1), 1: ("A_POW", 1)})],
+           [(1.0, {2: ("A_POW", 2)}), (-0.3j, {1: ("NUM_POW", 2)})], m.H0]
+    for terms in ops:
+        A = comb.qtt_terms(comb.op_terms(terms, m.dims), m.bits)
+        ref = np.trace(dense_operator(terms, m.dims) @ rho)
+        assert abs(comb.expect_tree(C, A) - ref) <= 1e-12 * max(1.0, abs(ref)), terms
+    pur = np.trace(rho @ rho).real / np.trace(rho).real ** 2
+    assert abs(comb.purity_tree(C) - pur) < 1e-13
+    assert abs(np.trace(comb.gram_tree(C)).real - np.trace(rho).real) < 1e-13
