@@ -1311,12 +1311,16 @@ void tdvp_sweep(lb_solver* s, std::vector<int>& chi, double h) {
   double* C = static_cast<double*>(t.C.p);
   double* Xt = static_cast<double*>(t.Xt.p);
   double* qw = static_cast<double*>(t.qrw.p);
+  // the eigenvector buffer is free while an effective Hamiltonian is formed:
+  // it holds the intermediate of the two-contraction form
+  double* Ux = static_cast<double*>(t.U.p);
+  const long long ux_cap = (long long)lbt::kMaxLocal * lbt::kMaxLocal;
   for (int i = L - 1; i >= 1; --i)
     HIPCHK(lbt::env_right(Rp(i + 1), Xp(i), Wp(i), chi[i], chi[i + 1], t.wl[i], t.wr[i], e2, e1, Rp(i), st));
   const double tau = 0.5 * h;
   for (int i = 0; i < L; ++i) {
     const int l = chi[i], r = chi[i + 1];
-    HIPCHK(lbt::heff_site(Lp(i), Wp(i), Rp(i + 1), l, r, t.wl[i], t.wr[i], H, st));
+    HIPCHK(lbt::heff_site(Lp(i), Wp(i), Rp(i + 1), l, r, t.wl[i], t.wr[i], H, st, Ux, ux_cap));
     tdvp_expm(s, 2 * l * r, Xp(i), tau);
     if (i == L - 1) break;
     // X_i (2l x r) = Q C: Q is the new site (l x 2 x k), C (k x r) the bond
@@ -1332,7 +1336,7 @@ void tdvp_sweep(lb_solver* s, std::vector<int>& chi, double h) {
   }
   for (int i = L - 1; i >= 0; --i) {
     const int l = chi[i], r = chi[i + 1];
-    HIPCHK(lbt::heff_site(Lp(i), Wp(i), Rp(i + 1), l, r, t.wl[i], t.wr[i], H, st));
+    HIPCHK(lbt::heff_site(Lp(i), Wp(i), Rp(i + 1), l, r, t.wl[i], t.wr[i], H, st, Ux, ux_cap));
     tdvp_expm(s, 2 * l * r, Xp(i), tau);
     if (i == 0) break;
     // X_i^T (2r x l) = Q C: Q^T is the new site (k x 2 x r), C^T (l x k) the bond

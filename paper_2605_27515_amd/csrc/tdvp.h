@@ -28,8 +28,10 @@ hipError_t env_right(const double* R, const double* A, const double* W, int l, i
                      double* S1, double* S2, double* Rout, hipStream_t stream);
 // One-site effective Hamiltonian as a dense d x d matrix, d = 2 l r:
 // H[(x,p,y)][(a,s,b)] = sum_{u,v} L[x][u][a] W[u][p][s][v] R[y][v][b].
+// With scratch X of at least 4 r^2 Du complex (x_cap), in two contractions
+// through X[y][u][p][s][b] = sum_v W R; otherwise in one.
 hipError_t heff_site(const double* L, const double* W, const double* R, int l, int r, int Du, int Dv, double* H,
-                     hipStream_t stream);
+                     hipStream_t stream, double* X = nullptr, long long x_cap = 0);
 // Zero-site (bond) effective Hamiltonian, d = l r:
 // H[(x,y)][(a,b)] = sum_w L[x][w][a] R[y][w][b].
 hipError_t heff_bond(const double* L, const double* R, int l, int r, int D, double* H, hipStream_t stream);

@@ -161,6 +161,40 @@ __global__ __launch_bounds__(NT) void heff_site_kernel(const double* L, const do
   }
 }
 
+// The same matrix in two contractions: X[y][u][p][s][b] = sum_v W[u][p][s][v]
+// R[y][v][b], then H = sum_u L[x][u][a] X[y][u][p][s][b] (d^2 Du + 4 r^2 Du Dv
+// products against d^2 Du Dv).
+__global__ __launch_bounds__(NT) void heff_site_x_kernel(const double* W, const double* R, int r, int Du, int Dv,
+                                                         double* X) {
+  const long long n = (long long)r * Du * 4 * r;
+  for (long long idx = blockIdx.x * (long long)NT + threadIdx.x; idx < n; idx += (long long)gridDim.x * NT) {
+    long long t = idx;
+    const int b = (int)(t % r); t /= r;
+    const int s = (int)(t % 2); t /= 2;
+    const int p = (int)(t % 2); t /= 2;
+    const int u = (int)(t % Du);
+    const int y = (int)(t / Du);
+    cplx acc{0.0, 0.0};
+    for (int v = 0; v < Dv; ++v)
+      mac(acc, ld(W, (((long long)u * 2 + p) * 2 + s) * Dv + v), ld(R, ((long long)y * Dv + v) * r + b));
+    st(X, idx, acc);
+  }
+}
+
+__global__ __launch_bounds__(NT) void heff_site_h_kernel(const double* L, const double* X, int l, int r, int Du,
+                                                         double* H) {
+  const long long d = 2LL * l * r, n = d * d;
+  for (long long idx = blockIdx.x * (long long)NT + threadIdx.x; idx < n; idx += (long long)gridDim.x * NT) {
+    const long long row = idx / d, col = idx % d;
+    const int y = (int)(row % r), p = (int)((row / r) % 2), x = (int)(row / (2LL * r));
+    const int b = (int)(col % r), s = (int)((col / r) % 2), a = (int)(col / (2LL * r));
+    cplx acc{0.0, 0.0};
+    for (int u = 0; u < Du; ++u)
+      mac(acc, ld(L, ((long long)x * Du + u) * l + a), ld(X, ((((long long)y * Du + u) * 2 + p) * 2 + s) * r + b));
+    st(H, idx, acc);
+  }
+}
+
 __global__ __launch_bounds__(NT) void heff_bond_kernel(const double* L, const double* R, int l, int r, int D,
                                                        double* H) {
   const long long d = (long long)l * r, n = d * d;
@@ -351,9 +385,15 @@ hipError_t env_right(const double* R, const double* A, const double* W, int l, i
 }
 
 hipError_t heff_site(const double* L, const double* W, const double* R, int l, int r, int Du, int Dv, double* H,
-                     hipStream_t stream) {
+                     hipStream_t stream, double* X, long long x_cap) {
   const long long d = 2LL * l * r;
-  hipLaunchKernelGGL(heff_site_kernel, dim3(grid_for(d * d)), dim3(NT), 0, stream, L, W, R, l, r, Du, Dv, H);
+  const long long nx = 4LL * r * Du * r;
+  if (X && nx <= x_cap) {
+    hipLaunchKernelGGL(heff_site_x_kernel, dim3(grid_for(nx)), dim3(NT), 0, stream, W, R, r, Du, Dv, X);
+    hipLaunchKernelGGL(heff_site_h_kernel, dim3(grid_for(d * d)), dim3(NT), 0, stream, L, X, l, r, Du, H);
+  } else {
+    hipLaunchKernelGGL(heff_site_kernel, dim3(grid_for(d * d)), dim3(NT), 0, stream, L, W, R, l, r, Du, Dv, H);
+  }
   return hipGetLastError();
 }
 
