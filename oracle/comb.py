@@ -43,7 +43,11 @@ reference for small modes only.
 as quantics MPOs on the teeth, tree additions, a compression that sweeps the
 backbone and then each tooth with the orthogonality centre at the node it
 cuts), the form a device implementation would take; at tolerances below
-the rounding of either, the two steps give the same rho.
+the rounding of either, the two steps give the same rho.  `kraus_comb_mpo`
+builds the whole stacked family as one comb MPO (backbone tensors with
+quantics-MPO teeth, the Kraus index on the last right bond) and
+`kraus_step_comb_mpo` applies it exactly before the same compression: the
+step a device zip-up on the tree would approximate cut by cut.
 """
 from __future__ import annotations
 
@@ -517,14 +521,13 @@ def tree_compress(C: Comb, tol: float, chi_e: int | None, chi_q: int | None, chi
     for a in range(M):
         t = T[a]
         for j in range(len(t) - 1, -1, -1):
-            q, _, r = t[j].shape
-            L, Q = _lq(t[j].reshape(q, 2 * r))
-            t[j] = Q.reshape(Q.shape[0], 2, r)
+            q, d, r = t[j].shape
+            L, Q = _lq(t[j].reshape(q, d * r))
+            t[j] = Q.reshape(Q.shape[0], d, r)
             if j > 0:
                 p = t[j - 1]
-                t[j - 1] = (p.reshape(-1, q) @ L).reshape(p.shape[0], 2, L.shape[1])
+                t[j - 1] = (p.reshape(-1, q) @ L).reshape(p.shape[0], p.shape[1], L.shape[1])
             else:
-                e, _, f = B[a].shape
                 B[a] = np.einsum('eqf,qk->ekf', B[a], L)
     # (2) the backbone
     B = compress(B, tol, chi_e, chi_mu, bounds, mu_cut=mu_cut)
@@ -541,23 +544,23 @@ def tree_compress(C: Comb, tol: float, chi_e: int | None, chi_q: int | None, chi
         B[a] = u[:, :k].reshape(e, f, k).transpose(0, 2, 1)
         t = T[a]
         c0 = t[0]
-        t[0] = ((s[:k, None] * vh[:k]) @ c0.reshape(q, -1)).reshape(k, 2, c0.shape[2])
+        t[0] = ((s[:k, None] * vh[:k]) @ c0.reshape(q, -1)).reshape(k, c0.shape[1], c0.shape[2])
         for j in range(len(t) - 1):
-            l, _, r = t[j].shape
-            u, s, vh = svd(t[j].reshape(l * 2, r))
+            l, d, r = t[j].shape
+            u, s, vh = svd(t[j].reshape(l * d, r))
             k = 1 if s[0] == 0.0 else keep_rank(s, tol, chi_q)
             bounds.append(float(np.sqrt(np.sum(s[k:] ** 2))))
-            t[j] = u[:, :k].reshape(l, 2, k)
+            t[j] = u[:, :k].reshape(l, d, k)
             n = t[j + 1]
-            t[j + 1] = ((s[:k, None] * vh[:k]) @ n.reshape(r, -1)).reshape(k, 2, n.shape[2])
+            t[j + 1] = ((s[:k, None] * vh[:k]) @ n.reshape(r, -1)).reshape(k, n.shape[1], n.shape[2])
         # the centre back up the tooth and into the backbone tensor
         for j in range(len(t) - 1, -1, -1):
-            l, _, r = t[j].shape
-            L, Q = _lq(t[j].reshape(l, 2 * r))
-            t[j] = Q.reshape(Q.shape[0], 2, r)
+            l, d, r = t[j].shape
+            L, Q = _lq(t[j].reshape(l, d * r))
+            t[j] = Q.reshape(Q.shape[0], d, r)
             if j > 0:
                 p = t[j - 1]
-                t[j - 1] = (p.reshape(-1, l) @ L).reshape(p.shape[0], 2, L.shape[1])
+                t[j - 1] = (p.reshape(-1, l) @ L).reshape(p.shape[0], p.shape[1], L.shape[1])
             else:
                 B[a] = np.einsum('eqf,qk->ekf', B[a], L)
         if a + 1 < M:
@@ -632,3 +635,106 @@ def expect_tree(C: Comb, A_qtt) -> complex:
 def purity_tree(C: Comb) -> float:
     g = gram_tree(C)
     return float(np.sum(np.abs(g) ** 2) / np.trace(g).real ** 2)
+
+
+# ---- operators as trees (the Kraus family as one comb MPO) ---------------------------
+#
+# A comb MPO has the comb's shape: backbone tensors V_a[u, p, u'] and teeth of
+# MPO cores, stored flattened as W[p, 4, p'] with the digit pair (s_out, s_in)
+# as s_out * 2 + s_in.  For the stacked Kraus family the last backbone
+# tensor's right bond is the Kraus index (the chain's convention).  Built
+# from sums of products (each product a tree with unit backbone bonds) by tree
+# addition, and compressed on the tree as states are.
+
+def _identity_tooth(R: int) -> list[np.ndarray]:
+    return [np.eye(2, dtype=complex).reshape(1, 4, 1) for _ in range(R)]
+
+
+def term_comb_mpo(coef, factors_qtt, bits) -> Comb:
+    """c prod_a F_a as a comb MPO: scalar backbone tensors, the factors'
+    quantics MPOs as teeth (identity teeth where a mode has no factor)."""
+    M = len(bits)
+    B = [np.ones((1, 1, 1), complex) for _ in range(M)]
+    B[0] = B[0] * coef
+    T = []
+    for a in range(M):
+        if a in factors_qtt:
+            T.append([w.reshape(w.shape[0], 4, w.shape[3]).astype(complex) for w in factors_qtt[a]])
+        else:
+            T.append(_identity_tooth(bits[a]))
+    return Comb(B=B, T=T, bits=list(bits))
+
+
+def comb_mpo(A_qtt, bits, tol: float = 1e-14) -> Comb:
+    """The comb MPO of a sum of products, the terms added eight at a time and
+    each partial sum compressed at tol (no cut on the last right bond)."""
+    parts = [term_comb_mpo(c, f, bits) for (c, f) in A_qtt]
+    while True:
+        parts = [tree_compress(tree_add(parts[i:i + 8]), tol, None, None, None, mu_cut=False)[0]
+                 for i in range(0, len(parts), 8)]
+        if len(parts) == 1:
+            return parts[0]
+
+
+def kraus_comb_mpo(fam_qtt, bits, tol: float = 1e-14) -> Comb:
+    """The stacked Kraus family: each member's comb MPO, set side by side on
+    the last backbone tensor's right bond (the Kraus index)."""
+    return tree_add([comb_mpo(K, bits, tol) for K in fam_qtt], stack_mu=True)
+
+
+def _tooth_operator(cores) -> np.ndarray:
+    """Q[p, n_out, n_in] of an MPO tooth (digits MSB first)."""
+    acc = cores[0].reshape(cores[0].shape[0], 2, 2, cores[0].shape[2])
+    for c in cores[1:]:
+        cc = c.reshape(c.shape[0], 2, 2, c.shape[2])
+        p, no, ni, _ = acc.shape
+        acc = np.einsum('pxyr,rabk->pxaybk', acc, cc).reshape(p, no * 2, ni * 2, cc.shape[3])
+    return acc[..., 0]
+
+
+def comb_mpo_dense(W: Comb, k: int = 0) -> np.ndarray:
+    """Dense matrix of channel k of a comb MPO (k indexes the last backbone
+    tensor's right bond), mode 0 the most significant."""
+    acc = None
+    for a, V in enumerate(W.B):
+        Q = _tooth_operator(W.T[a])                              # [p, n, n']
+        P = np.einsum('upv,pxy->uxyv', V, Q)                     # [u, n, n', v]
+        if acc is None:
+            acc = P[0]                                           # [n, n', v]
+        else:
+            rows, cols, _ = acc.shape
+            acc = np.einsum('abu,uxyv->axbyv', acc, P).reshape(rows * P.shape[1], cols * P.shape[2], P.shape[3])
+    return acc[:, :, k]
+
+
+def apply_comb_mpo(C: Comb, W: Comb) -> Comb:
+    """W Psi exactly: backbone tensors multiply as outer products (the state's
+    purification bond and the Kraus index combine into the new purification
+    bond, mu' = (mu, k)), teeth as MPO on MPS."""
+    B = []
+    for b, v in zip(C.B, W.B):
+        e, q, f = b.shape
+        u, p, g = v.shape
+        B.append(np.einsum('eqf,upg->euqpfg', b, v).reshape(e * u, q * p, f * g))
+    T = []
+    for ts, tw in zip(C.T, W.T):
+        teeth = []
+        for t, w in zip(ts, tw):
+            q, _, r = t.shape
+            p, _, s2 = w.shape
+            w4 = w.reshape(p, 2, 2, s2)
+            teeth.append(np.einsum('aib,usiv->ausbv', t, w4).reshape(q * p, 2, r * s2))
+        T.append(teeth)
+    return Comb(B=B, T=T, bits=list(C.bits))
+
+
+def kraus_step_comb_mpo(C: Comb, W: Comb, tol: float, chi_e: int | None = None, chi_q: int | None = None,
+                        chi_mu: int | None = None) -> tuple[Comb, CombStepInfo]:
+    """The step with the family as one comb MPO: the exact product W Psi (bonds
+    multiplied, the Kraus images already side by side on mu), then the tree
+    compression with the purification cut and the trace divided out."""
+    out, tau, bounds = tree_compress(apply_comb_mpo(C, W), tol, chi_e, chi_q, chi_mu, mu_cut=True, normalise=True)
+    info = CombStepInfo(tau=tau, chi_mu=out.B[-1].shape[2], backbone=[b.shape[2] for b in out.B[:-1]],
+                        teeth=[[b.shape[1]] + [c.shape[2] for c in t[:-1]] for b, t in zip(out.B, out.T)],
+                        psi_bounds=bounds)
+    return out, info

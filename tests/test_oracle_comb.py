@@ -240,3 +240,32 @@ def test_tree_observables_against_dense_traces():
     pur = np.trace(rho @ rho).real / np.trace(rho).real ** 2
     assert abs(comb.purity_tree(C) - pur) < 1e-13
     assert abs(np.trace(comb.gram_tree(C)).real - np.trace(rho).real) < 1e-13
+
+
+def test_comb_mpo_of_the_hamiltonian_and_the_kraus_family():
+    """The Hamiltonian and the stacked Kraus family as comb MPOs (backbone
+    tensors with quantics-MPO teeth, channel k on the last right bond) against
+    the dense matrices; two steps with the family applied as one comb MPO
+    against the dense Kraus map and the term-by-term tree step."""
+    m = _model()
+    dm = dense.DenseModel(m)
+    H = comb.op_terms(m.H0, m.dims)
+    WH = comb.comb_mpo(comb.qtt_terms(H, m.bits), m.bits)
+    assert np.abs(comb.comb_mpo_dense(WH) - dm.H0).max() <= 1e-13 * np.abs(dm.H0).max()
+    assert max(b.shape[2] for b in WH.B[:-1]) <= 4       # w0 n + hopping on each side: bond 4
+    fam = comb.kraus_ops(H, [comb.op_terms(j, m.dims) for j in m.jumps], m.dt)
+    famq = [comb.qtt_terms(K, m.bits) for K in fam]
+    WK = comb.kraus_comb_mpo(famq, m.bits)
+    famd = dense.kraus_family(dm, 0.0, m.dt)
+    assert WK.B[-1].shape[2] == len(famd)
+    for k, Kd in enumerate(famd):
+        assert np.abs(comb.comb_mpo_dense(WK, k) - Kd).max() < 1e-13
+    C1 = C2 = comb.product_comb(m.init, m.bits)
+    rho = np.outer(dm.psi0, dm.psi0.conj())
+    for k in range(2):
+        C1, info = comb.kraus_step_comb_mpo(C1, WK, 1e-12)
+        C2, _ = comb.kraus_step_tree(C2, famq, 1e-12)
+        rho, tau = dense.k2_step_rho(dm, rho, 0.0, m.dt)
+        assert abs(info.tau - tau) < 1e-12
+    assert np.abs(comb.rho(C1) - rho).max() < 1e-12
+    assert np.abs(comb.rho(C1) - comb.rho(C2)).max() < 1e-12
