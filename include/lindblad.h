@@ -14,7 +14,10 @@
  *     H_eff = H - (i/2) sum_k L_k^dag L_k,
  * as one MPO applied to X, recompresses it by truncated SVDs that cap the
  * bond dimension and the purification rank, and renormalises the trace
- * (end of paper Sec. 5.2.2).
+ * (end of paper Sec. 5.2.2).  For a pure state (purification rank 1) the
+ * same solver also integrates the Schroedinger equation: the global RK4 of
+ * paper Sec. 3.1.1 (lb_config.order 4) and the one-site TDVP under the
+ * fourth-order Magnus Hamiltonian of Sec. 3.1.3 (order 5).
  *
  * Conventions shared by every call.
  *  - Complex numbers are interleaved (re, im) pairs of double.
