@@ -286,14 +286,20 @@ def test_tdvp_order_refuses_fp32_jumps_and_counts_its_work():
     s4.close()
 
 
-@pytest.mark.parametrize("drive", [False, True])
+@pytest.mark.parametrize("drive", [False, True, "two-modes"])
 def test_host_tdvp_mpo_channels_are_h0_h1_and_their_commutator(drive):
     """order = 5: the MPO the TDVP step combines, exported, is H0 (no drive) or
     H0, H1 and [H0, H1] on the channels of site 0's left index, each equal to
-    the dense operator (paper Sec. 3.1.3: the commutator formed once)."""
+    the dense operator (paper Sec. 3.1.3: the commutator formed once); also
+    for two coupled modes (H0 only, bonds across the mode boundary)."""
     _lib_or_skip()
     from paper_2605_27515_amd import api
-    m = wl.model_driven_kerr(R=4, alpha0=1.5, drive=drive, dt=1e-2)
+    if drive == "two-modes":
+        m = wl.model_coupled_cavities(bits=(2, 3), kappa=0.0, chi_mu=1)
+        m.jumps = []
+        drive = False
+    else:
+        m = wl.model_driven_kerr(R=4, alpha0=1.5, drive=drive, dt=1e-2)
     s = api.solver_from_model(m, order=5, chi=16, chi_mu=1, state="none")
     W = s.kraus_sites()
     so = m.site_order()
