@@ -253,8 +253,9 @@ typedef struct lb_drive {          /* f(t) = sum_j coef_j cos(omega_j t + phase_
  * f(t2))/2, c2 = i sqrt(3) dt (f(t2) - f(t1))/12 and t1,2 = t + (3 -+
  * sqrt 3) dt / 6: H0, H1 and their commutator are stacked on site 0's left
  * index once, and every step combines them with the two weights on the
- * device.  H0 and H1 must be Hermitian and f real; n_jumps must be 0
- * (LB_ERR_ARG).  Each local exponential is exact (dense eigen-decomposition),
+ * device.  H0 and H1 must be Hermitian (a relative Frobenius defect
+ * ||H - H^dag|| / ||H|| above 1e-10 is LB_ERR_ARG; f is real by its form);
+ * n_jumps must be 0 (LB_ERR_ARG).  Each local exponential is exact (dense eigen-decomposition),
  * so the bonds of the loaded state are kept (a redundant bond direction is
  * dropped by the first sweep) and the norm is conserved up to rounding.
  * lindblad_step returns LB_ERR_ARG when a site has 2 l r > 512, an inner bond

@@ -2191,6 +2191,19 @@ lb_status lindblad_set_generator(lb_solver* s, const lb_op* H0, const lb_op* H1,
       // formed once.  The Kraus family is the identity (this order does not
       // apply it).
       if (n_jumps != 0) throw Fail(LB_ERR_ARG, "order 5 (TDVP) takes no jump operators");
+      // the local problems are Hermitian eigen-decompositions: H0 and H1 must
+      // be Hermitian (relative Frobenius defect; sites 1.. of a compressed
+      // MPO are right-orthonormal, so its norm is that of site 0)
+      auto herm_defect = [&](const Mpo& a) {
+        const Mpo d = c(mpo_add(a, mpo_scale(mpo_dagger(a), cd(-1.0, 0.0))));
+        const Mpo n = c(a);
+        double dn = 0.0, nn = 0.0;
+        for (const cd& x : d[0].w) dn += std::norm(x);
+        for (const cd& x : n[0].w) nn += std::norm(x);
+        return std::sqrt(dn / std::max(nn, 1e-300));
+      };
+      if (herm_defect(H0->mpo) > 1e-10) throw Fail(LB_ERR_ARG, "order 5 (TDVP) needs a Hermitian H0");
+      if (drive && herm_defect(B) > 1e-10) throw Fail(LB_ERR_ARG, "order 5 (TDVP) needs a Hermitian H1");
       if (drive) {
         const Mpo comm = add(c(mpo_mul(H0->mpo, B)), mpo_scale(c(mpo_mul(B, H0->mpo)), cd(-1.0, 0.0)));
         s->tdvp_W = c(boundary_stack({H0->mpo, B, comm}));

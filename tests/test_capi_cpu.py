@@ -266,8 +266,9 @@ def test_rk4_order_refuses_jumps_and_unstable_dt():
 
 def test_tdvp_order_refuses_fp32_jumps_and_counts_its_work():
     """order = 5 (one-site TDVP with the Magnus-4 Hamiltonian, paper Sec.
-    3.1.3): the FP32 form is refused at create, jump operators at
-    set_generator, and the footprint counts the dense local work (four
+    3.1.3): the FP32 form is refused at create, jump operators and a
+    non-Hermitian H0 at set_generator (a Hermitian one with complex
+    coefficients passes), and the footprint counts the dense local work (four
     512 x 512 complex matrices at least) beside the state."""
     _lib_or_skip()
     from paper_2605_27515_amd import api
@@ -279,6 +280,14 @@ def test_tdvp_order_refuses_fp32_jumps_and_counts_its_work():
     with pytest.raises(api.LindbladError) as e:
         api.solver_from_model(wl.model_coherent_loss(), order=5, chi=16, chi_mu=1, state="none")
     assert e.value.code == LB_ERR_ARG
+    # a non-Hermitian H0 (the local problems are Hermitian eigen-decompositions)
+    bad = wl.Model(name="a", bits=[3], H0=[(1.0, {0: ("A_POW", 1)})], jumps=[], init=[wl.vacuum(8)], dt=0.01)
+    with pytest.raises(api.LindbladError) as e:
+        api.solver_from_model(bad, order=5, chi=8, chi_mu=1, state="none")
+    assert e.value.code == LB_ERR_ARG and "Hermitian" in str(e.value)
+    ok = wl.Model(name="p", bits=[3], H0=[(1j, {0: ("A_POW", 1)}), (-1j, {0: ("ADAG_POW", 1)})], jumps=[],
+                  init=[wl.vacuum(8)], dt=0.01)
+    api.solver_from_model(ok, order=5, chi=8, chi_mu=1, state="none").close()
     s5 = api.solver_from_model(m, order=5, chi=16, chi_mu=1, state="none")
     s4 = api.solver_from_model(m, order=4, chi=16, chi_mu=1, state="none")
     assert s5.footprint() >= s4.footprint() // 4 + 4 * 512 * 512 * 16
