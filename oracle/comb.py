@@ -255,6 +255,19 @@ def kraus_ops(H, Ls, h: float) -> list:
     return fam
 
 
+def kraus_ops_at(model, t: float, h: float) -> list:
+    """The family of the step [t, t + h] for a workload model: the drive
+    f(t) = sum_j c_j cos(w_j t + phi_j) taken at the midpoint t + h/2, as the
+    chain's step takes it, H = H0 + f H1."""
+    dims = model.dims
+    H = op_terms(model.H0, dims) if model.H0 else []
+    if model.H1:
+        tm = t + 0.5 * h
+        f = sum(c * np.cos(w * tm + p) for (c, w, p) in model.drive)
+        H = op_add(H, op_scale(op_terms(model.H1, dims), f))
+    return kraus_ops(H, [op_terms(j, dims) for j in model.jumps], h)
+
+
 # ---- inter-mode MPS algebra ---------------------------------------------------------
 
 def apply_term(Ps, coef, factors) -> list[np.ndarray]:

@@ -269,3 +269,18 @@ def test_comb_mpo_of_the_hamiltonian_and_the_kraus_family():
         assert abs(info.tau - tau) < 1e-12
     assert np.abs(comb.rho(C1) - rho).max() < 1e-12
     assert np.abs(comb.rho(C1) - comb.rho(C2)).max() < 1e-12
+
+
+def test_driven_family_at_the_midpoint():
+    """A driven two-mode model (the Kerr oscillator's two-photon drive on the
+    first of two coupled cavities): the family of the step [t, t + h] equals
+    the dense oracle's, which takes the drive at t + h/2."""
+    m = wl.model_coupled_cavities(bits=(3, 2), dt=0.05)
+    m.H1 = [(1.0, {0: ("A_POW", 2)}), (1.0, {0: ("ADAG_POW", 2)})]
+    m.drive = [(0.02, 2 ** 0.5, 0.0), (0.06, 3 ** 0.5, 0.3)]
+    dm = dense.DenseModel(m)
+    for t in (0.0, 0.7):
+        fam = comb.kraus_ops_at(m, t, m.dt)
+        famd = dense.kraus_family(dm, t, m.dt)
+        for a, b in zip(fam, famd):
+            assert np.abs(comb.op_dense(a, m.dims) - b).max() < 1e-13
