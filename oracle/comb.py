@@ -434,7 +434,12 @@ def factor_mpo(F: np.ndarray, tol: float = 1e-14) -> list[np.ndarray]:
 
 
 def qtt_terms(A, bits, tol: float = 1e-14) -> list:
-    """A sum of products with every dense factor replaced by its quantics MPO."""
+    """A sum of products with every dense factor replaced by its quantics MPO
+    (each factor of mode m must be 2^bits[m] square)."""
+    for _, f in A:
+        for m, F in f.items():
+            if F.shape != (1 << bits[m], 1 << bits[m]):
+                raise ValueError(f"factor on mode {m} is {F.shape}, not {1 << bits[m]} square")
     return [(c, {m: factor_mpo(F, tol) for m, F in f.items()}) for (c, f) in A]
 
 
